@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: demagnetization-curve time-to-solution on one MI355X.
+
+One step = one whole demagnetization curve (every field value, each
+minimization run to max |m x h_eff| < 1e-6) of the hard-magnetic cube: edge
+80 nm, 20^3 cells x 6 tets, 3x air box for the scalar potential, mu0 Ms =
+1.61 T, K1 = 4.3 MJ/m^3, A = 7.7 pJ/m, easy axis z tilted 1 degree toward x,
+field along -z from 0 to -8 T in 0.05 T steps (161 values), jmax = 10, in the
+FP32-bulk mode (FP32 operators and Poisson CG, FP64 reductions, FP64
+magnetization). Inputs (mesh operators, the start state) are resident in HBM
+before the timed region; assembly is untimed, as in the paper.
+
+Printed (one JSON line): time per curve, the dominant kernel's measured
+bandwidth against the HBM roofline (HIP events around its launches inside the
+timed region), the plain FP64 form's time for the same curve, and the CPU FP64
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fields", type=int, default=0, help="truncate the schedule (0 = all 161)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison curve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1801_03690_amd import binding, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.hard_cube()
+    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
+    prec = binding.MM_FP32_BULK if args.precision == "fp32" else binding.MM_FP64
+
+    ctx = binding.Context(0)
+    t0 = time.time()
+    ctx.upload(w.mesh)
+    t_setup = time.time() - t0
+    info = ctx.info()
+    print(f"# setup {t_setup:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}",
+          file=sys.stderr, flush=True)
+    m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
+    m = torch.empty_like(m0)
+    opts = binding.default_opts(jmax=w.jmax, precision=prec)
+    ctx.set_opts(opts)
+
+    def one_curve(o):
+        m.copy_(m0)
+        ctx.reset_warm_start()
+        return ctx.curve(m, fields, opts=o)
+
+    for i in range(args.warmup):
+        r = one_curve(opts)
+        print(f"# warmup {i} done rc={r['rc']}", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    ctx.profile(-1)
+    ctx.profile(1)
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(one_curve(opts))
+        print(f"# step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(0)
+    sec_per_curve = (t1 - t0) / args.steps
+    r = results[-1]
+    st = r["stats"]
+    tot = {k: int(sum(s[k] for s in st)) for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks")}
+    worst = max(s["status"] for s in st)
+
+    avg_launch = prof["seconds"] / max(prof["launches"], 1)
+    achieved = prof["bytes_per_launch"] / avg_launch / 1e9 if prof["launches"] else None
+
+    out = {
+        "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
+        "value": round(sec_per_curve, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec_per_curve, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
+        "data": "synthetic (seeded Kuhn mesh, tilted +z start)",
+        "config": {"workload": f"hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {len(fields)} fields "
+                               f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6",
+                   "precision": args.precision, "n_mag": info["n_mag"], "n_pot": info["n_pot"],
+                   "nnz_K": info["nnz_K"]},
+        "counters": dict(tot, worst_status=worst),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_cg32_spmv_dot" if prec == binding.MM_FP32_BULK else "k_cg_spmv_dot",
+            "achieved": None if achieved is None else round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(1e6 * avg_launch, 3),
+            "launches": prof["launches"],
+            "bytes_per_launch": prof["bytes_per_launch"],
+        },
+    }
+
+    if not args.no_plain and prec != binding.MM_FP64:
+        o64 = binding.default_opts(jmax=w.jmax, precision=binding.MM_FP64)
+        ctx.set_opts(o64)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rp = one_curve(o64)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ctx.set_opts(opts)
+        dE = float(np.max(np.abs(rp["E"] - r["E"]) / np.maximum(np.abs(rp["E"]), 1.0)))
+        dmav = float(np.max(np.abs(rp["m_avg"] - r["m_avg"])))
+        out["plain_fp64"] = {"seconds": round(tb - ta, 4),
+                             "evals": int(sum(s["evals"] for s in rp["stats"])),
+                             "nli": int(sum(s["nli"] for s in rp["stats"])),
+                             "max_rel_dE_vs_fp32": dE, "max_dmavg_vs_fp32": dmav}
+        print(f"# plain fp64 curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(w.mesh)
+        ns = max(1, min(args.cpu_fields, len(fields)))
+        ta = time.perf_counter()
+        ro = o.curve(w.m0, fields[:ns], jmax=w.jmax)
+        tb = time.perf_counter()
+        t_sample = tb - ta
+        # extrapolate with the GPU's own distribution of work over the fields
+        gpu_all = sum(s["t_nl"] for s in st)
+        gpu_sample = sum(s["t_nl"] for s in st[:ns])
+        est = t_sample * gpu_all / max(gpu_sample, 1e-12)
+        out["cpu_baseline"] = {
+            "value": round(est, 2), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ns} of {len(fields)} field steps timed ({t_sample:.2f} s, "
+                      f"{sum(s['evals'] for s in ro['stats'])} evals); scaled to the whole curve by the "
+                      f"GPU's per-field time distribution",
+            "sample_seconds": round(t_sample, 3),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

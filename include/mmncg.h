@@ -1,0 +1,207 @@
+/*
+ * mmncg.h - C ABI of the MI355X (gfx950) library for micromagnetic energy
+ * minimization with the preconditioned projected nonlinear conjugate gradient
+ * method of Exl, Fischbacher, Kovacs, Oezelt, Gusenbauer and Schrefl
+ * ("Preconditioned nonlinear conjugate gradient method for micromagnetic
+ * energy minimization").
+ *
+ * The problem (Sec. 2.2, eq. (opt)): minimize the P1 finite-element energy
+ *   F(m) = 1/2 m^T C m - 1/2 h_d^T M m - h_ext^T M m      (eq. (energy))
+ * subject to |m_i| = 1 at every magnet node, for a sequence of applied fields
+ * (Sec. 3.1: one minimization per field value, each started from the previous
+ * minimizer). The minimizer is Alg. 4 with the restarted Hestenes-Stiefel
+ * beta*ZA; the preconditioner is the sparse local-field approximation of the
+ * Hessian of the Lagrangian, eq. (precond) without its last term, solved with a
+ * few steps of Alg. 1 with the exchange diagonal as Jacobi preconditioner.
+ * The stray field comes from a scalar potential on the magnet plus an air box
+ * with zero Dirichlet values on the outer boundary (Sec. 3.1).
+ *
+ * Units. Coordinates in nm. Materials in SI (Ms in A/m, A in J/m, K1 in
+ * J/m^3). Applied fields in Tesla (mu0 H). Internally the library works in
+ * reduced units: length 1 nm, magnetization Ms_ref = max Ms, energy
+ * mu0 Ms_ref^2 nm^3, fields in units of Ms_ref. Energies and gradients
+ * returned by the ABI are in these reduced units; torques |m x h_eff| are in
+ * units of Ms_ref.
+ *
+ * Vectors. A magnetization or gradient is n_mag x 3 doubles, node-major
+ * (x, y, z of node 0, then node 1, ...), ordered by ascending mesh-node index
+ * of the magnet nodes (nodes touched by a tet with region > 0).
+ *
+ * Host or device pointers. Every double* vector argument may point to host
+ * memory or to device memory of the context's GPU; the library detects which.
+ * Device vectors are read/written on the context's stream.
+ *
+ * Ownership. The caller owns every pointer it passes; the library copies what
+ * it needs during the call and keeps no caller pointer after return. Device
+ * buffers belong to the context and come from the allocator callbacks given to
+ * mm_create (hipMalloc/hipFree when NULL).
+ *
+ * Errors. Negative return codes mean failure and that no output was written;
+ * mm_last_error() then holds a message. Positive codes mean the outputs were
+ * written with a warning (not converged within max_nli, or the line search
+ * stalled). The library never aborts the process; HIP failures map to
+ * MM_EDEVICE.
+ *
+ * Concurrency. One context per host thread; contexts share no state. Calls on
+ * one context are serialized by the caller. Every call that returns host
+ * results synchronizes the context's stream before returning.
+ */
+#ifndef MMNCG_H
+#define MMNCG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+
+enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,        /* bad argument (NULL, size, NaN, non-unit m) */
+    MM_ENOMEM = -2,        /* device or host allocation failed */
+    MM_EDEVICE = -3,       /* a HIP call failed */
+    MM_EMESH = -4,         /* degenerate tet, no magnet, inconsistent mesh */
+    MM_ESTATE = -5,        /* call out of order (e.g. no mesh/material yet) */
+    MM_NOT_CONVERGED = 1,  /* max_nli reached; outputs hold the last iterate */
+    MM_STALLED = 2         /* line search failed twice (also along -g) */
+};
+
+enum { MM_FP64 = 0, MM_FP32_BULK = 1 };
+enum { MM_STOP_TORQUE = 0, MM_STOP_PAPER = 1 };
+enum { MM_T_EXCH = 1, MM_T_ANIS = 2, MM_T_ZEE = 4, MM_T_DEMAG = 8, MM_T_ALL = 15 };
+
+typedef struct {
+    int jmax;              /* (li1) inner PCG iteration cap; 0 = unpreconditioned NCG */
+    double tol_torque;     /* MM_STOP_TORQUE: stop when max_i |m_i x h_eff,i| < tol */
+    int stop_mode;         /* MM_STOP_TORQUE or MM_STOP_PAPER ((t1)-(t3) of Sec. 3.1) */
+    double tau_F;          /* function tolerance for (t1)-(t3) */
+    double theta_max;      /* line search: largest nodal rotation per step (rad) */
+    double theta_init;     /* first trial rotation when jmax = 0 (rad) */
+    double c1, c2;         /* sufficient-decrease and curvature constants */
+    double poisson_rtol;   /* scalar-potential CG: stop at |r| <= rtol |b| */
+    long max_nli;          /* nonlinear iteration cap per field value */
+    int precision;         /* MM_FP64 or MM_FP32_BULK */
+    int terms;             /* energy terms, MM_T_* bitmask */
+    int ls_max_halvings;   /* line-search backtracking cap */
+    long poisson_maxit;    /* scalar-potential CG iteration cap per solve */
+} mm_opts;
+
+typedef struct {
+    long evals;            /* energy+gradient evaluations */
+    long nli;              /* nonlinear (outer) iterations */
+    long li;               /* inner preconditioner CG iterations */
+    long mi;               /* scalar-potential CG iterations */
+    long restarts;         /* steepest-descent restarts after a failed line search */
+    long fallbacks;        /* descent safeguard activations */
+    double t_nl, t_lin, t_mag; /* seconds: total, preconditioner, magnetostatics */
+    double F;              /* final total energy (reduced units) */
+    double torque_max;     /* final max |m x h_eff| */
+    int status;            /* MM_OK, MM_NOT_CONVERGED or MM_STALLED */
+} mm_stats;
+
+typedef struct {
+    long n_nodes, n_tets, n_mag, n_pot;   /* mesh nodes, tets, magnet nodes, free potential nodes */
+    long nnz_C_blocks, nnz_K, nnz_B;      /* stored nonzeros (padding excluded) */
+    double Ms_ref;                        /* A/m */
+    size_t device_bytes;                  /* device memory held by the context */
+} mm_info;
+
+/* Fill o with the defaults: jmax 4, tol_torque 1e-6, torque stopping,
+   tau_F 1e-10, theta_max 0.2, theta_init 0.01, c1 1e-4, c2 0.1,
+   poisson_rtol 1e-10, max_nli 20000, FP64, all terms, 20 halvings,
+   poisson_maxit 100000. */
+int mm_opts_default(mm_opts *o);
+
+typedef void *(*mm_alloc_fn)(size_t bytes, void *user);
+typedef void (*mm_free_fn)(void *ptr, void *user);
+
+/* Create a context on HIP device `device`. `hip_stream` (a hipStream_t, may be
+   NULL) is borrowed: all work is enqueued on it; NULL makes the context create
+   its own stream. dev_alloc/dev_free (both NULL or both set) provide device
+   memory; `alloc_user` is passed through to them. */
+int mm_create(mm_ctx **out, int device, void *hip_stream, mm_alloc_fn dev_alloc, mm_free_fn dev_free,
+              void *alloc_user);
+int mm_destroy(mm_ctx *c);
+const char *mm_last_error(const mm_ctx *c);
+int mm_get_info(const mm_ctx *c, mm_info *info);
+
+/* Tetrahedral mesh (Sec. 2.2: P1 finite elements). xyz: n_nodes x 3 (nm);
+   tets: n_tets x 4 node indices (0-based); region[t] = 0 for air, > 0 for
+   magnetic material. Nodes on faces that belong to exactly one tet form the
+   outer boundary, where the scalar potential is zero. Host pointers only. */
+int mm_mesh_upload(mm_ctx *c, const double *xyz, long n_nodes, const int *tets, long n_tets,
+                   const int *region);
+
+/* Per-tet SI materials (Sec. 2.2: C = C_A + C_K and M carrying local Ms):
+   Ms, A, K1 (n_tets each) and the easy axis (n_tets x 3, normalized here; may
+   be NULL when every K1 is 0). Air tets are ignored. Assembles the device
+   operators (the matrices C, K, B, B^T, the nodal weights of M and the
+   exchange diagonal). Host pointers only. */
+int mm_material_set(mm_ctx *c, const double *Ms, const double *A, const double *K1, const double *axis);
+
+/* Number of magnet nodes and (when node_ids != NULL) their mesh-node ids. */
+int mm_magnet_nodes(const mm_ctx *c, long *n_mag, int *node_ids);
+
+/* Options used by mm_energy_grad / mm_precondition (minimize and curve take
+   their own). */
+int mm_set_opts(mm_ctx *c, const mm_opts *o);
+
+/* Zero the scalar-potential warm start (the potential of the previous
+   evaluation is the starting guess of the next Poisson CG). */
+int mm_reset_warm_start(mm_ctx *c);
+
+/* Energy and gradient (eq. (energy)) at unit vectors m for the applied field
+   h_ext (Tesla). E_parts = {exchange, anisotropy, Zeeman, demag, total};
+   grad = dF/dm (n_mag x 3); gproj = Pi_{m-perp}(grad) (eq. (nablaLF));
+   torque_max = max_i |gproj_i| / L_i = max_i |m_i x h_eff,i| (eq. (optcond)).
+   Every output may be NULL. */
+int mm_energy_grad(mm_ctx *c, const double *m, const double h_ext[3], double E_parts[5], double *grad,
+                   double *gproj, double *torque_max);
+
+/* Approximately solve P y = gproj with at most jmax steps of Alg. 1 from
+   y = 0, P v = C v - (m.(C v)) m - lambda v (eq. (precond) without its last
+   term), lambda_i = m_i . grad_i, Jacobi = exchange diagonal (times dscale_i
+   when dscale != NULL), exits (li1)-(li3). jmax = 0 returns y = gproj. */
+int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax,
+                    const double *dscale, double *y, int *inner_iters);
+
+/* Alg. 4 for one field (Tesla), m_inout updated in place. Returns MM_OK,
+   MM_NOT_CONVERGED or MM_STALLED (outputs written in all three cases). */
+int mm_ncg_minimize(mm_ctx *c, double *m_inout, const double h_ext[3], const mm_opts *o, mm_stats *st,
+                    double E_parts[5]);
+
+/* Demagnetization curve (Sec. 3.1): for k = 0..n-1 minimize at h_list[k]
+   (Tesla, n x 3) from the previous minimizer. m_avg (n x 3) = sum_i L_i m_i /
+   sum_i L_i, E_tot (n), st (n), m_hist (n x n_mag x 3) may each be NULL.
+   m_inout ends at the last minimizer. Returns the worst per-step status. */
+int mm_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, const mm_opts *o,
+                   double *m_avg, double *E_tot, mm_stats *st, double *m_hist);
+
+/* Single operators for checking (same kernels as the solver):
+   MM_OP_C   : out = C in            (n_mag x 3 -> n_mag x 3; exchange + anisotropy)
+   MM_OP_B   : out = b(in)           (n_mag x 3 -> n_pot; divergence right-hand side)
+   MM_OP_BT  : out = B^T in          (n_pot -> n_mag x 3; stray-field gradient from a potential)
+   MM_OP_K   : out = K in            (n_pot -> n_pot; Poisson matrix, Dirichlet rows removed) */
+enum { MM_OP_C = 0, MM_OP_B = 1, MM_OP_BT = 2, MM_OP_K = 3 };
+int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out);
+
+/* Scalar-potential solve K u = b by Jacobi-preconditioned CG, warm-started
+   from u_inout (n_pot), until |r| <= rtol |b|. iters may be NULL. */
+int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters);
+
+/* Measurement hook. enable = 1 brackets every launch of the scalar-potential
+   CG matrix-vector kernel (the dominant kernel of an evaluation) with HIP
+   events on the context's stream and accumulates their durations; enable = 0
+   stops; enable = -1 resets the counters. out (may be NULL) receives
+   {launches timed, total seconds, algorithmic bytes per launch, rows}, where
+   the algorithmic bytes are the stored matrix (values + column indices, no
+   padding) plus one read of the input vector and one write of the output
+   vector, at the precision of the active mode (FP32-bulk: 4-byte values). */
+int mm_profile(mm_ctx *c, int enable, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMNCG_H */

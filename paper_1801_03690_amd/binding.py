@@ -1,0 +1,301 @@
+"""ctypes binding of libmmncg.so (the C ABI declared in include/mmncg.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Vectors may be numpy arrays (host) or torch tensors on the context's GPU
+(device pointers are passed straight through). PyTorch supplies device memory
+(its caching allocator, through the ABI's allocator callbacks) and the stream.
+If the shared library is missing this module raises at import time: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmmncg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mmncg.h")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_EMESH, MM_ESTATE = 0, -1, -2, -3, -4, -5
+MM_NOT_CONVERGED, MM_STALLED = 1, 2
+MM_FP64, MM_FP32_BULK = 0, 1
+MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
+MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
+MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
+
+
+class MMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mmncg error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("jmax", C.c_int), ("tol_torque", C.c_double), ("stop_mode", C.c_int), ("tau_F", C.c_double),
+                ("theta_max", C.c_double), ("theta_init", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
+                ("poisson_rtol", C.c_double), ("max_nli", C.c_long), ("precision", C.c_int), ("terms", C.c_int),
+                ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("evals", C.c_long), ("nli", C.c_long), ("li", C.c_long), ("mi", C.c_long),
+                ("restarts", C.c_long), ("fallbacks", C.c_long), ("t_nl", C.c_double), ("t_lin", C.c_double),
+                ("t_mag", C.c_double), ("F", C.c_double), ("torque_max", C.c_double), ("status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_long), ("n_tets", C.c_long), ("n_mag", C.c_long), ("n_pot", C.c_long),
+                ("nnz_C_blocks", C.c_long), ("nnz_K", C.c_long), ("nnz_B", C.c_long), ("Ms_ref", C.c_double),
+                ("device_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_vp = C.c_void_p
+
+
+def header_symbols():
+    """Names of the functions the public header declares."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(mm_\w+)\s*\(", txt, re.M)))
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libmmncg.so not built ({path}); run __graft_entry__.build()")
+    L = C.CDLL(path)
+    L.mm_opts_default.argtypes = [C.POINTER(Opts)]
+    L.mm_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, ALLOC_FN, FREE_FN, _vp]
+    L.mm_destroy.argtypes = [_vp]
+    L.mm_last_error.restype = C.c_char_p
+    L.mm_last_error.argtypes = [_vp]
+    L.mm_get_info.argtypes = [_vp, C.POINTER(Info)]
+    L.mm_mesh_upload.argtypes = [_vp, _dp, C.c_long, _ip, C.c_long, _ip]
+    L.mm_material_set.argtypes = [_vp, _dp, _dp, _dp, _dp]
+    L.mm_magnet_nodes.argtypes = [_vp, C.POINTER(C.c_long), _ip]
+    L.mm_set_opts.argtypes = [_vp, C.POINTER(Opts)]
+    L.mm_reset_warm_start.argtypes = [_vp]
+    L.mm_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
+    L.mm_precondition.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _ip]
+    L.mm_ncg_minimize.argtypes = [_vp, _vp, _dp, C.POINTER(Opts), C.POINTER(Stats), _dp]
+    L.mm_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats), _vp]
+    L.mm_operator_apply.argtypes = [_vp, C.c_int, _vp, _vp]
+    L.mm_poisson_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.POINTER(C.c_long)]
+    L.mm_profile.argtypes = [_vp, C.c_int, _dp]
+    for name in header_symbols():
+        if getattr(L, name).restype is C.c_int or name != "mm_last_error":
+            if name != "mm_last_error":
+                getattr(L, name).restype = C.c_int
+    return L
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib().mm_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _host_f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def _vec_ptr(x):
+    """Pointer for a vector argument: torch CUDA tensor -> its device pointer,
+    anything else -> contiguous float64 numpy array on the host."""
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            if x.dtype != torch.float64 or not x.is_contiguous():
+                raise TypeError("device vectors must be contiguous float64 tensors")
+            return C.c_void_p(x.data_ptr()), x
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    return C.c_void_p(a.ctypes.data), a
+
+
+class Context:
+    """One mmncg context (device memory, stream, discretized problem)."""
+
+    def __init__(self, device=0, stream=None, torch_allocator=True):
+        self._L = lib()
+        self.device = device
+        self._alloc_cb = ALLOC_FN()
+        self._free_cb = FREE_FN()
+        sp = None
+        if torch_allocator or stream is not None:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            sp = C.c_void_p(stream.cuda_stream)
+            self._torch_stream = stream
+            if torch_allocator:
+                dev = device
+
+                def _alloc(nbytes, user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+                    except Exception:
+                        return None
+
+                def _free(ptr, user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                self._alloc_cb = ALLOC_FN(_alloc)
+                self._free_cb = FREE_FN(_free)
+        h = C.c_void_p()
+        rc = self._L.mm_create(C.byref(h), device, sp, self._alloc_cb, self._free_cb, None)
+        if rc != MM_OK:
+            raise MMError(rc, "mm_create failed")
+        self.h = h
+        self.n_mag = 0
+        self.n_pot = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_warn=True):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise MMError(rc, self._L.mm_last_error(self.h).decode())
+        return rc
+
+    # ----------------------------------------------------------------
+    def upload(self, mesh):
+        xyz = _host_f64(mesh.xyz)
+        tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+        reg = np.ascontiguousarray(mesh.region, dtype=np.int32)
+        self._check(self._L.mm_mesh_upload(self.h, xyz.ctypes.data_as(_dp), xyz.shape[0],
+                                           tets.ctypes.data_as(_ip), tets.shape[0], reg.ctypes.data_as(_ip)))
+        Ms, A, K1 = _host_f64(mesh.Ms), _host_f64(mesh.A), _host_f64(mesh.K1)
+        ax = _host_f64(mesh.axis)
+        self._check(self._L.mm_material_set(self.h, Ms.ctypes.data_as(_dp), A.ctypes.data_as(_dp),
+                                            K1.ctypes.data_as(_dp), ax.ctypes.data_as(_dp)))
+        inf = self.info()
+        self.n_mag, self.n_pot = inf["n_mag"], inf["n_pot"]
+        return self
+
+    def info(self):
+        i = Info()
+        self._check(self._L.mm_get_info(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def magnet_nodes(self):
+        n = C.c_long()
+        ids = np.zeros(self.n_mag, dtype=np.int32)
+        self._check(self._L.mm_magnet_nodes(self.h, C.byref(n), ids.ctypes.data_as(_ip)))
+        return ids
+
+    def set_opts(self, opts=None, **kw):
+        o = opts or default_opts(**kw)
+        self._check(self._L.mm_set_opts(self.h, C.byref(o)))
+
+    def reset_warm_start(self):
+        self._check(self._L.mm_reset_warm_start(self.h))
+
+    def energy_grad(self, m, h_T):
+        mp, keep = _vec_ptr(m)
+        h = _host_f64(h_T, (3,))
+        E = np.zeros(5)
+        G = np.zeros((self.n_mag, 3))
+        g = np.zeros((self.n_mag, 3))
+        t = C.c_double()
+        self._check(self._L.mm_energy_grad(self.h, mp, h.ctypes.data_as(_dp), E.ctypes.data_as(_dp),
+                                           C.c_void_p(G.ctypes.data), C.c_void_p(g.ctypes.data), C.byref(t)))
+        return dict(E=E, G=G, g=g, tmax=t.value)
+
+    def precondition(self, m, G, g, jmax, dscale=None):
+        mp, k1 = _vec_ptr(m)
+        Gp, k2 = _vec_ptr(G)
+        gp, k3 = _vec_ptr(g)
+        dsp = None
+        if dscale is not None:
+            dsp, k4 = _vec_ptr(dscale)
+        y = np.zeros((self.n_mag, 3))
+        it = C.c_int()
+        self._check(self._L.mm_precondition(self.h, mp, Gp, gp, int(jmax), dsp, C.c_void_p(y.ctypes.data),
+                                            C.byref(it)))
+        return y, it.value
+
+    def minimize(self, m, h_T, opts=None, **kw):
+        o = opts or default_opts(**kw)
+        mp, keep = _vec_ptr(m)
+        if keep is m and isinstance(m, np.ndarray):
+            keep = m.copy()
+            mp = C.c_void_p(keep.ctypes.data)
+        h = _host_f64(h_T, (3,))
+        st = Stats()
+        E = np.zeros(5)
+        rc = self._check(self._L.mm_ncg_minimize(self.h, mp, h.ctypes.data_as(_dp), C.byref(o), C.byref(st),
+                                                 E.ctypes.data_as(_dp)))
+        return keep, E, st.as_dict(), rc
+
+    def curve(self, m, fields_T, opts=None, keep_hist=False, **kw):
+        o = opts or default_opts(**kw)
+        mp, keep = _vec_ptr(m)
+        if isinstance(keep, np.ndarray):
+            keep = keep.copy()
+            mp = C.c_void_p(keep.ctypes.data)
+        F = _host_f64(fields_T, (-1, 3))
+        nf = F.shape[0]
+        mavg = np.zeros((nf, 3))
+        Et = np.zeros(nf)
+        st = (Stats * nf)()
+        hist = np.zeros((nf, self.n_mag, 3)) if keep_hist else None
+        rc = self._check(self._L.mm_demag_curve(self.h, mp, F.ctypes.data_as(_dp), nf, C.byref(o),
+                                                mavg.ctypes.data_as(_dp), Et.ctypes.data_as(_dp), st,
+                                                None if hist is None else C.c_void_p(hist.ctypes.data)))
+        return dict(m=keep, m_avg=mavg, E=Et, stats=[s.as_dict() for s in st], rc=rc, hist=hist)
+
+    def apply(self, op, x):
+        xp, keep = _vec_ptr(x)
+        n_out = {MM_OP_C: 3 * self.n_mag, MM_OP_B: self.n_pot, MM_OP_BT: 3 * self.n_mag, MM_OP_K: self.n_pot}[op]
+        out = np.zeros(n_out)
+        self._check(self._L.mm_operator_apply(self.h, op, xp, C.c_void_p(out.ctypes.data)))
+        return out.reshape(-1, 3) if op in (MM_OP_C, MM_OP_BT) else out
+
+    def profile(self, enable):
+        out = np.zeros(4)
+        self._check(self._L.mm_profile(self.h, int(enable), out.ctypes.data_as(_dp)))
+        return dict(launches=int(out[0]), seconds=float(out[1]), bytes_per_launch=float(out[2]), rows=int(out[3]))
+
+    def poisson(self, b, u0=None, rtol=1e-10):
+        bp, k1 = _vec_ptr(b)
+        u = np.zeros(self.n_pot) if u0 is None else _host_f64(u0).copy()
+        it = C.c_long()
+        self._check(self._L.mm_poisson_solve(self.h, bp, C.c_void_p(u.ctypes.data), rtol, C.byref(it)))
+        return u, it.value

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU FP64 oracle.
+
+Tolerances (FP64 path): operators and single evaluations to round-off
+(1e-12 relative); minimizations to a relative energy error of 1e-8 and a
+largest nodal |dm| of 1e-5 (the target stated for the method); iteration
+counts identical across repeated GPU runs. Every input is seeded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1801_03690_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MU0 = 4e-7 * math.pi
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not _gpu_available():
+        pytest.skip("no GPU")
+    from paper_1801_03690_amd import binding
+    return binding
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def e_tol(E_or):
+    return 1e-8 * max(abs(E_or[4]), float(np.abs(E_or[:4]).sum()))
+
+
+MESHES = {
+    # several SELL slices and a ragged last slice on the potential side
+    "soft_3x2x2": lambda: inputs.small_box((3, 2, 2), 4.0),
+    "hard_5x4x3": lambda: inputs.small_box((5, 4, 3), 3.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6,
+                                           axis=(0.2, 0.1, 0.97)),
+    "soft_noair_4x3x2": lambda: inputs.small_box((4, 3, 2), 4.0, air=False),
+}
+
+
+def _ctx(B, mesh, **opts):
+    ctx = B.Context(0)
+    ctx.upload(mesh)
+    if opts:
+        ctx.set_opts(**opts)
+    return ctx
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_operators_match_oracle(B, oracle_mod, name):
+    mesh = MESHES[name]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    assert ctx.n_mag == o.nm and ctx.n_pot == o.np
+    np.testing.assert_array_equal(ctx.magnet_nodes(), o.magnet_nodes())
+    v = inputs.random_vec(o.nm, 1)
+    assert rel(ctx.apply(B.MM_OP_C, v), o.apply_C(v)) < 1e-13
+    if o.np > 0:
+        assert rel(ctx.apply(B.MM_OP_B, v), o.bmul(v)) < 1e-13
+        u = np.random.default_rng(2).standard_normal(o.np)
+        assert rel(ctx.apply(B.MM_OP_BT, u), o.btmul(u)) < 1e-13
+        assert rel(ctx.apply(B.MM_OP_K, u), o.kmul(u)) < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["soft_3x2x2", "hard_5x4x3"])
+def test_poisson_matches_oracle(B, oracle_mod, name):
+    mesh = MESHES[name]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    b = o.bmul(inputs.random_unit(o.nm, 3))
+    ug, itg = ctx.poisson(b, rtol=1e-12)
+    uo, ito = o.poisson(b, rtol=1e-12)
+    assert rel(ug, uo) < 1e-10
+    assert abs(itg - ito) <= 1
+    # warm start at the solution: no iterations
+    ug2, it2 = ctx.poisson(b, u0=ug, rtol=1e-10)
+    assert it2 == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("terms", [15, 1, 2, 4, 8, 7])
+def test_energy_gradient_matches_oracle(B, oracle_mod, name, terms):
+    mesh = MESHES[name]()
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13, terms=terms)
+    m = inputs.random_unit(o.nm, 4)
+    hT = np.array([0.1, 0.2, 0.5])
+    rg = ctx.energy_grad(m, hT)
+    ro = o.eval_T(m, hT, terms=terms)
+    # scales of the full problem (a single term may vanish, e.g. anisotropy at K1 = 0)
+    full = o.eval_T(m, hT)
+    escale = max(np.abs(full["E"]).max(), 1.0)
+    gscale = np.abs(full["G"]).max()
+    assert np.abs(rg["E"] - ro["E"]).max() < 1e-11 * escale
+    assert np.abs(rg["G"] - ro["G"]).max() < 1e-10 * gscale
+    assert np.abs(rg["g"] - ro["g"]).max() < 1e-9 * gscale
+    assert abs(rg["tmax"] - ro["tmax"]) < 1e-9 * max(ro["tmax"], gscale / o.lumped().min())
+    ctx.close()
+
+
+def _near_state(o, seed, tilt=0.3):
+    return inputs.tilted_state(o.nm, (0, 0, 1), tilt, np.random.Generator(np.random.PCG64(seed)))
+
+
+@pytest.mark.parametrize("jmax", [0, 1, 3, 10])
+def test_precondition_matches_oracle(B, oracle_mod, jmax):
+    mesh = MESHES["hard_5x4x3"]()
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13)
+    m = _near_state(o, 5)
+    hT = np.array([0.0, 0.0, 0.5])
+    ro = o.eval_T(m, hT)
+    y, it = ctx.precondition(m, ro["G"], ro["g"], jmax)
+    yo, ito = o.precond(m, ro["lam"], ro["g"], jmax)
+    assert it == ito
+    assert rel(y, yo) < 1e-10
+    # learned per-node scaling of the Jacobi diagonal
+    s = np.linspace(0.5, 2.0, o.nm)
+    y2, it2 = ctx.precondition(m, ro["G"], ro["g"], jmax, dscale=s)
+    yo2, ito2 = o.precond(m, ro["lam"], ro["g"], jmax, dscale=s)
+    assert it2 == ito2 and rel(y2, yo2) < 1e-10
+    ctx.close()
+
+
+def test_precondition_negative_curvature_exit(B, oracle_mod):
+    mesh = MESHES["hard_5x4x3"]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m = _near_state(o, 6, 0.05)
+    ro = o.eval_T(m, [0.0, 0.0, -60.0])
+    y, it = ctx.precondition(m, ro["G"], ro["g"], 10)
+    yo, ito = o.precond(m, ro["lam"], ro["g"], 10)
+    assert it == ito == 0
+    np.testing.assert_array_equal(y, ro["g"])
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,field,jmax", [("soft_3x2x2", [0.0, 0.0, 0.3], 4),
+                                             ("hard_5x4x3", [0.0, 0.0, -1.0], 10),
+                                             ("hard_5x4x3", [0.3, 0.0, -2.0], 0)])
+def test_minimize_matches_oracle(B, oracle_mod, name, field, jmax):
+    mesh = MESHES[name]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m0 = _near_state(o, 1, 0.01)
+    mg, Eg, sg, rcg = ctx.minimize(m0, field, jmax=jmax)
+    mo, Eo, so, rco = o.minimize(m0, field, jmax=jmax)
+    assert rcg == 0 and rco == 0
+    assert sg["torque_max"] < 1e-6
+    assert abs(Eg[4] - Eo[4]) <= e_tol(Eo)
+    assert np.abs(mg - mo).max() <= 1e-5
+    assert np.abs(np.linalg.norm(mg, axis=1) - 1).max() < 1e-14
+    ctx.close()
+
+
+def test_minimize_deterministic(B):
+    mesh = MESHES["hard_5x4x3"]()
+    m0 = inputs.tilted_state(mesh.magnet_nodes().size, (0, 0, 1), 0.01, np.random.Generator(np.random.PCG64(1)))
+    out = []
+    for _ in range(2):
+        ctx = _ctx(B, mesh)
+        assert ctx.n_mag == m0.shape[0]
+        mg, Eg, sg, rc = ctx.minimize(m0, [0.0, 0.0, -1.5], jmax=10)
+        out.append((mg, Eg, sg))
+        ctx.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks"):
+        assert out[0][2][k] == out[1][2][k]
+
+
+def test_paper_stopping_rule_and_not_converged(B, oracle_mod):
+    mesh = MESHES["soft_3x2x2"]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m0 = _near_state(o, 2, 0.01)
+    mg, Eg, sg, rc = ctx.minimize(m0, [0.0, 0.0, 0.2], jmax=4, stop_mode=1, tau_F=1e-10)
+    mo, Eo, so, rco = o.minimize(m0, [0.0, 0.0, 0.2], jmax=4, stop_mode=1, tau_F=1e-10)
+    assert rc == 0 and rco == 0
+    assert abs(Eg[4] - Eo[4]) <= 1e-7 * abs(Eo[4])
+    mg, Eg, sg, rc = ctx.minimize(m0, [0.0, 0.0, 0.2], jmax=4, max_nli=1)
+    assert rc == 1 and sg["nli"] == 1
+    ctx.close()
+
+
+def test_invalid_inputs_rejected(B):
+    mesh = MESHES["soft_3x2x2"]()
+    ctx = _ctx(B, mesh)
+    m = np.tile([0.0, 0.0, 1.0], (ctx.n_mag, 1))
+    bad = m.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(B.MMError) as e:
+        ctx.energy_grad(bad, [0, 0, 1.0])
+    assert e.value.code == B.MM_EINVAL
+    with pytest.raises(B.MMError) as e:
+        ctx.minimize(2.0 * m, [0, 0, 1.0])
+    assert e.value.code == B.MM_EINVAL
+    with pytest.raises(B.MMError):
+        ctx.set_opts(jmax=-1)
+    ctx.close()
+
+
+def test_device_pointers(B, oracle_mod):
+    import torch
+    mesh = MESHES["soft_3x2x2"]()
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m0 = _near_state(o, 3, 0.01)
+    md = torch.tensor(m0, dtype=torch.float64, device="cuda")
+    ctx.reset_warm_start()
+    mg, Eg, sg, rc = ctx.minimize(md, [0.0, 0.0, 0.4], jmax=4)
+    torch.cuda.synchronize()
+    ctx.reset_warm_start()
+    mh, Eh, sh, rch = ctx.minimize(m0, [0.0, 0.0, 0.4], jmax=4)
+    np.testing.assert_array_equal(md.cpu().numpy(), mh)
+    ctx.close()
+
+
+def test_curve_matches_oracle_small(B, oracle_mod):
+    """Whole demagnetization curve of a small soft cube (21 fields)."""
+    w = inputs.soft_cube(n=4, h=4.0)
+    o = oracle_mod.Oracle(w.mesh)
+    ctx = _ctx(B, w.mesh)
+    rg = ctx.curve(w.m0, w.fields, jmax=4)
+    ro = o.curve(w.m0, w.fields, jmax=4)
+    assert rg["rc"] == 0 and ro["rc"] == 0
+    for k in range(len(w.fields)):
+        tol = 1e-8 * max(abs(ro["E"][k]), 1.0)
+        assert abs(rg["E"][k] - ro["E"][k]) <= tol * 10, k
+    assert np.abs(rg["m_avg"] - ro["m_avg"]).max() < 1e-5
+    assert np.abs(rg["m"] - ro["m"]).max() <= 1e-5
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# full-size meshes of the soft cube (10^3 cells) and the hard cube (20^3)
+# ---------------------------------------------------------------------------
+
+def test_soft_cube_full_size_step(B, oracle_mod):
+    w = inputs.soft_cube()
+    o = oracle_mod.Oracle(w.mesh)
+    ctx = _ctx(B, w.mesh)
+    assert ctx.n_mag == 1331 and ctx.n_pot == o.np
+    mg, Eg, sg, rcg = ctx.minimize(w.m0, w.fields[0], jmax=4)
+    mo, Eo, so, rco = o.minimize(w.m0, w.fields[0], jmax=4)
+    assert rcg == 0 and rco == 0
+    assert abs(Eg[4] - Eo[4]) <= e_tol(Eo)
+    assert np.abs(mg - mo).max() <= 1e-5
+    ctx.close()
+
+
+def test_hard_cube_full_size_eval(B, oracle_mod):
+    w = inputs.hard_cube()
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_poisson(1e-12)
+    ctx = _ctx(B, w.mesh, poisson_rtol=1e-12)
+    assert ctx.n_mag == 9261
+    m = w.m0
+    rg = ctx.energy_grad(m, w.fields[3])
+    ro = o.eval_T(m, w.fields[3])
+    assert np.abs(rg["E"] - ro["E"]).max() <= 1e-10 * np.abs(ro["E"]).sum()
+    assert rel(rg["G"], ro["G"]) < 1e-8
+    # preconditioner at the same state (every node compared)
+    y, it = ctx.precondition(m, ro["G"], ro["g"], 10)
+    yo, ito = o.precond(m, ro["lam"], ro["g"], 10)
+    assert it == ito and rel(y, yo) < 1e-8
+    ctx.close()
+
+
+def test_fp32_bulk_error_is_small(B, oracle_mod):
+    """FP32 operators with FP64 reductions: the error against the FP64 oracle
+    is reported, and must stay near the FP32 rounding of the operators."""
+    mesh = MESHES["hard_5x4x3"]()
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-12)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-12, precision=B.MM_FP32_BULK)
+    m = inputs.random_unit(o.nm, 4)
+    hT = np.array([0.1, 0.2, 0.5])
+    rg = ctx.energy_grad(m, hT)
+    ro = o.eval_T(m, hT)
+    assert abs(rg["E"][4] - ro["E"][4]) < 1e-6 * np.abs(ro["E"][:4]).sum()
+    assert rel(rg["G"], ro["G"]) < 1e-5
+    m0 = _near_state(o, 1, 0.01)
+    mg, Eg, sg, rcg = ctx.minimize(m0, [0.0, 0.0, -1.0], jmax=10, precision=B.MM_FP32_BULK)
+    mo, Eo, so, rco = o.minimize(m0, [0.0, 0.0, -1.0], jmax=10)
+    assert rcg == 0
+    assert abs(Eg[4] - Eo[4]) <= 1e-6 * abs(Eo[4])
+    assert np.abs(mg - mo).max() <= 1e-4
+    ctx.close()
