@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison curve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run a plain copy kernel of known size (for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -52,6 +54,17 @@ def main():
     from paper_1801_03690_amd import binding, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate:
+        # elementwise copy kernel: reads and writes exactly `nbytes` per launch
+        nbytes = 256 << 20
+        a = torch.rand(nbytes // 4, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "torch.mul(a, 1.0, out=b)", "bytes_read_per_launch": nbytes,
+                          "bytes_written_per_launch": nbytes, "launches": 5}), flush=True)
+        return
     w = inputs.hard_cube()
     fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
     prec = binding.MM_FP32_BULK if args.precision == "fp32" else binding.MM_FP64

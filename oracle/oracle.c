@@ -639,16 +639,24 @@ static void ls_eval(or_ctx *c, const or_state *s0, const double *d, double alpha
     }
     or_eval(c, st->x, h, terms, st->E, st->G, st->g, st->lam, &st->tmax);
     stats->evals++;
-    /* exact energy difference for the quadratic F (reading S26) */
+    /* Exact energy difference of the quadratic F between unit vectors (reading
+       S26 written in tangential form): with G = g + lambda x and |x| = |x+| = 1,
+       F(x+) - F(x) = 1/2 sum_a [ dx.(g + g+) + 1/2 (lambda+ - lambda) |dx|^2 ],
+       dx = x+ - x. It equals 1/2 dx.(G + G+) in exact arithmetic, and it keeps
+       the large radial part of G (|lambda| >> |g| near a minimum) out of the sum. */
     ksum t = {0, 0}, p = {0, 0};
     for (long a = 0; a < nm; a++) {
-        double w[3];
+        double w[3], dx[3];
         for (int k = 0; k < 3; k++) w[k] = s0->x[3 * a + k] + alpha * d[3 * a + k];
         double n = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        double dx2 = 0.0, dg = 0.0;
         for (int k = 0; k < 3; k++) {
-            ks_add(&t, 0.5 * (st->x[3 * a + k] - s0->x[3 * a + k]) * (st->G[3 * a + k] + s0->G[3 * a + k]));
+            dx[k] = st->x[3 * a + k] - s0->x[3 * a + k];
+            dx2 += dx[k] * dx[k];
+            dg += dx[k] * (st->g[3 * a + k] + s0->g[3 * a + k]);
             ks_add(&p, st->g[3 * a + k] * d[3 * a + k] / n);
         }
+        ks_add(&t, 0.5 * (dg + 0.5 * (st->lam[a] - s0->lam[a]) * dx2));
     }
     *dF = ks_val(&t);
     *dphi = ks_val(&p);

@@ -9,9 +9,11 @@ no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -102,6 +104,17 @@ def load_library(path=LIB_PATH):
 
 
 _LIB = None
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device memory through the allocator callbacks while torch is alive
+    for ctx in list(_LIVE):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -166,7 +179,10 @@ class Context:
                         return None
 
                 def _free(ptr, user):
-                    torch.cuda.caching_allocator_delete(ptr)
+                    try:
+                        torch.cuda.caching_allocator_delete(ptr)
+                    except Exception:
+                        pass
 
                 self._alloc_cb = ALLOC_FN(_alloc)
                 self._free_cb = FREE_FN(_free)
@@ -177,6 +193,7 @@ class Context:
         self.h = h
         self.n_mag = 0
         self.n_pot = 0
+        _LIVE.add(self)
 
     def close(self):
         if getattr(self, "h", None):

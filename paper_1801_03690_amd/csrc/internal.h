@@ -101,8 +101,8 @@ void launch_add_correction(int n, double *u, const float *x, double scale, hipSt
 
 void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,
                           const double *u, const double *L, const double h[3], double *G, double *g, double *lam,
-                          const double *x0, const double *G0, const double *d, double alpha, double *part, bool fp32,
-                          hipStream_t s);
+                          const double *x0, const double *g0, const double *lam0, const double *d, double alpha,
+                          double *part, bool fp32, hipStream_t s);
 void launch_trial(int n, const double *x0, const double *d, double alpha, double *xt, hipStream_t s);
 void launch_finalize(const double *part, int nblk, int nslot, unsigned is_max, double *out, hipStream_t s);
 

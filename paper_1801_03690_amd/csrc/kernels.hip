@@ -547,8 +547,8 @@ template <class V>
 __global__ __launch_bounds__(kBlock) void k_eval_epilogue(
     SV<V> C, SV<V> S, SV<V> Bt, int cmode, int use_demag, const double *__restrict__ m, const double *__restrict__ u,
     const double *__restrict__ L, double hx, double hy, double hz, double *__restrict__ G, double *__restrict__ g,
-    double *__restrict__ lam, const double *__restrict__ x0, const double *__restrict__ G0,
-    const double *__restrict__ d, double alpha, double *__restrict__ part) {
+    double *__restrict__ lam, const double *__restrict__ x0, const double *__restrict__ g0v,
+    const double *__restrict__ lam0, const double *__restrict__ d, double alpha, double *__restrict__ part) {
     __shared__ double sh[kWaves * 10];
     int s0, s1;
     slice_range(C.nslices, s0, s1);
@@ -602,8 +602,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_epilogue(
                 double da = d[a3], db = d[a3 + 1], dc = d[a3 + 2];
                 double wa = xa + alpha * da, wb = xb + alpha * db, wc = xc + alpha * dc;
                 double wn = sqrt(wa * wa + wb * wb + wc * wc);
-                acc[3] += 0.5 * ((m0 - xa) * (G0v + G0[a3]) + (m1 - xb) * (G1v + G0[a3 + 1]) +
-                                 (m2 - xc) * (G2v + G0[a3 + 2]));
+                // energy difference between unit vectors in tangential form:
+                // 1/2 [dx.(g + g0) + 1/2 (lambda - lambda0) |dx|^2]  (= 1/2 dx.(G + G0))
+                double e0 = m0 - xa, e1 = m1 - xb, e2 = m2 - xc;
+                double dx2 = e0 * e0 + e1 * e1 + e2 * e2;
+                acc[3] += 0.5 * (e0 * (g0 + g0v[a3]) + e1 * (g1 + g0v[a3 + 1]) + e2 * (g2 + g0v[a3 + 2]) +
+                                 0.5 * (l - lam0[a]) * dx2);
                 acc[4] += (g0 * da + g1 * db + g2 * dc) / wn;
                 acc[8] = fmax(acc[8], fmax(fabs(m0 - xa), fmax(fabs(m1 - xb), fabs(m2 - xc))));
             }
@@ -1054,17 +1058,17 @@ void launch_add_correction(int n, double *u, const float *x, double scale, hipSt
 
 void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,
                           const double *u, const double *L, const double h[3], double *G, double *g, double *lam,
-                          const double *x0, const double *G0, const double *d, double alpha, double *part, bool fp32,
-                          hipStream_t s) {
+                          const double *x0, const double *g0, const double *lam0, const double *d, double alpha,
+                          double *part, bool fp32, hipStream_t s) {
     int gr = grid_for_rows(C.nrows);
     if (fp32)
         hipLaunchKernelGGL(k_eval_epilogue<float>, dim3(gr), dim3(kBlock), 0, s, view<float>(C), view<float>(S),
-                           view<float>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, G0, d, alpha,
-                           part);
+                           view<float>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, g0, lam0, d,
+                           alpha, part);
     else
         hipLaunchKernelGGL(k_eval_epilogue<double>, dim3(gr), dim3(kBlock), 0, s, view<double>(C), view<double>(S),
-                           view<double>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, G0, d, alpha,
-                           part);
+                           view<double>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, g0, lam0, d,
+                           alpha, part);
 }
 unsigned eval_max_mask() { return kEvalMaxMask; }
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -449,8 +450,8 @@ void eval(mm_ctx *c, State &st, const double h[3], const mm_opts &o, const State
     if (o.terms & MM_T_ZEE)
         for (int k = 0; k < 3; ++k) hz[k] = h[k];
     launch_eval_epilogue(c->C, c->S, c->Bt, cmode_of(o.terms), demag ? 1 : 0, st.x, c->u, c->L, hz, st.G, st.g,
-                         st.lam, x0 ? x0->x : nullptr, x0 ? x0->G : nullptr, x0 ? c->d : nullptr, alpha,
-                         partp(c, PS_EVAL), fp32, s);
+                         st.lam, x0 ? x0->x : nullptr, x0 ? x0->g : nullptr, x0 ? x0->lam : nullptr,
+                         x0 ? c->d : nullptr, alpha, partp(c, PS_EVAL), fp32, s);
     launch_finalize(partp(c, PS_EVAL), grid_for_rows(nm), kEvalParts, eval_max_mask(), c->dsc + SC_EVAL, s);
     pull(c, SC_EVAL, kEvalParts);
     const double *r = c->hsc + SC_EVAL;
@@ -622,6 +623,14 @@ LsResult line_search(mm_ctx *c, const mm_opts &o, const double h[3], int i0, dou
 // Alg. 4 for one reduced field; the start point is in st[*cur].x; on return
 // *cur indexes the final state
 // ---------------------------------------------------------------------------
+int trace_level() {
+    static int lvl = [] {
+        const char *e = std::getenv("MMNCG_TRACE");
+        return e ? std::atoi(e) : 0;
+    }();
+    return lvl;
+}
+
 int minimize(mm_ctx *c, int *cur, const double h[3], const mm_opts &o, mm_stats *stats) {
     auto t0 = std::chrono::steady_clock::now();
     c->c_evals = c->c_mi = c->c_li = 0;
@@ -667,6 +676,12 @@ int minimize(mm_ctx *c, int *cur, const double h[3], const mm_opts &o, mm_stats 
             nli++;
             State &s1 = c->st[ls.idx];
             State &s0 = c->st[i0];
+            if (trace_level() > 0 && (nli <= 40 || nli % 100 == 0))
+                std::fprintf(stderr,
+                             "[mmncg] nli %ld alpha %.4e amax %.4e a0 %.4e dp0 %.4e dF %.4e dE %.4e tmax %.4e "
+                             "E %.12e evals %ld\n",
+                             nli, ls.alpha, o.theta_max / dmax, a0, dp0, ls.dF, s1.E - s0.E, s1.tmax, s1.E,
+                             c->c_evals);
             bool conv;
             if (o.stop_mode == MM_STOP_TORQUE) {
                 conv = s1.tmax < o.tol_torque;

@@ -176,7 +176,9 @@ def cap_directions(k, centre, half_angle_rad, rng):
 
 
 def field_schedule(start_T, stop_T, step_T, direction):
-    """Fields in Tesla (mu0*H) along `direction`, both endpoints included."""
+    """Fields in Tesla (mu0*H): value * direction for values from start_T to
+    stop_T (both included). A field "along -z from 0 to -8 T" is direction +z
+    with values 0 .. -8."""
     n = int(round(abs(stop_T - start_T) / step_T)) + 1
     vals = np.linspace(start_T, stop_T, n)
     d = np.asarray(direction, dtype=np.float64)
@@ -221,7 +223,8 @@ def hard_cube(n=20, h=4.0, seed=1, step_T=0.05, stop_T=-8.0):
     mesh = make_box_magnet((n, n, n), h, axis=u, **HARD)
     rng = np.random.Generator(np.random.PCG64(seed))
     m0 = tilted_state(mesh.magnet_nodes().size, (0.0, 0.0, 1.0), 0.01, rng)
-    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, -1.0))
+    # field along -z: h = (0, 0, B) with B from 0 down to stop_T
+    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, 1.0))
     return Workload(f"hard_cube_{n}", mesh, m0, fields, jmax=10,
                     meta=dict(seed=seed, edge_nm=n * h))
 
@@ -233,7 +236,7 @@ def batch_cubes(n_inst=64, seed=2, nmin=8, nmax=24, h=4.0, step_T=0.1, stop_T=-8
     K1s = rng.uniform(3.0e6, 4.9e6, size=n_inst)
     axes = cap_directions(n_inst, (0.0, 0.0, 1.0), math.radians(15.0), rng)
     out = []
-    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, -1.0))
+    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, 1.0))
     for i in range(n_inst):
         mat = dict(HARD)
         mat["K1"] = float(K1s[i])
@@ -302,7 +305,7 @@ def polycrystal(n=96, edge=200.0, n_grains=27, seed=4, gb_width=2.0, step_T=0.05
                 meta=dict(seeds=seeds, axes=axes))
     m0 = tilted_state(mesh.magnet_nodes().size, (0.0, 0.0, 1.0), 0.01,
                       np.random.Generator(np.random.PCG64(seed + 1000)))
-    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, -1.0))
+    fields = field_schedule(0.0, stop_T, step_T, (0.0, 0.0, 1.0))
     return Workload(f"polycrystal_{n}", mesh, m0, fields, jmax=10, meta=dict(seed=seed))
 
 
