@@ -27,6 +27,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_hard_cube_20_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "poisson.hip")
+
+
+def measured_traffic(precision):
+    """Counter-measured bytes per CG iteration, if taken on the current kernel source."""
+    import hashlib
+    try:
+        kv = dict(line.split(None, 1) for line in open(TRAFFIC_FILE) if line.strip() and not line.startswith("#"))
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if kv.get("source_sha256_prefix", "").strip() != h or kv.get("precision", "").strip() != precision:
+        return None
+    return float(kv["traffic_bytes_per_iteration"])
 
 
 def main():
@@ -107,8 +122,8 @@ def main():
     tot = {k: int(sum(s[k] for s in st)) for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks")}
     worst = max(s["status"] for s in st)
 
-    avg_launch = prof["seconds"] / max(prof["launches"], 1)
-    achieved = prof["bytes_per_launch"] / avg_launch / 1e9 if prof["launches"] else None
+    avg_iter = prof["seconds"] / max(prof["iterations"], 1)
+    achieved = prof["bytes_per_iteration"] / avg_iter / 1e9 if prof["iterations"] else None
 
     out = {
         "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
@@ -130,15 +145,16 @@ def main():
         "counters": dict(tot, worst_status=worst),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cg32_spmv_dot" if prec == binding.MM_FP32_BULK else "k_cg_spmv_dot",
+            "kernel": ("scalar-potential CG iteration: k_pcg_a + k_pcg_b "
+                       + ("<float>" if prec == binding.MM_FP32_BULK else "<double>")),
             "achieved": None if achieved is None else round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "avg_launch_us": round(1e6 * avg_launch, 3),
-            "launches": prof["launches"],
-            "bytes_per_launch": prof["bytes_per_launch"],
+            "traffic": measured_traffic(args.precision),
+            "avg_iteration_us": round(1e6 * avg_iter, 3),
+            "iterations": prof["iterations"],
+            "bytes_per_iteration": prof["bytes_per_iteration"],
         },
     }
 

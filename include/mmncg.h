@@ -191,14 +191,17 @@ int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out);
    from u_inout (n_pot), until |r| <= rtol |b|. iters may be NULL. */
 int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters);
 
-/* Measurement hook. enable = 1 brackets every launch of the scalar-potential
-   CG matrix-vector kernel (the dominant kernel of an evaluation) with HIP
-   events on the context's stream and accumulates their durations; enable = 0
-   stops; enable = -1 resets the counters. out (may be NULL) receives
-   {launches timed, total seconds, algorithmic bytes per launch, rows}, where
-   the algorithmic bytes are the stored matrix (values + column indices, no
-   padding) plus one read of the input vector and one write of the output
-   vector, at the precision of the active mode (FP32-bulk: 4-byte values). */
+/* Measurement hook. enable = 1 times the scalar-potential CG iterations (the
+   dominant work of an evaluation: kernel A, q = K p with the direction update,
+   and kernel B, the solution/residual update) with HIP events on the
+   context's stream around every batch of iterations (the iterations run as
+   replays of a captured graph); enable = 0 stops; enable = -1 resets the
+   counters. out (may be NULL) receives {iterations executed, seconds,
+   algorithmic bytes per iteration, rows}: the stored matrix (values + column
+   indices, no padding) plus the vector traffic of the two kernels (kernel A:
+   read r, D^-1, old direction, write new direction and K p; kernel B: read x,
+   r, p, q, D^-1, write x and r), at the precision of the options last set
+   with mm_set_opts (FP32-bulk: 4-byte values). */
 int mm_profile(mm_ctx *c, int enable, double out[4]);
 
 #ifdef __cplusplus

@@ -141,12 +141,16 @@ def _host_f64(a, shape=None):
 
 def _vec_ptr(x):
     """Pointer for a vector argument: torch CUDA tensor -> its device pointer,
-    anything else -> contiguous float64 numpy array on the host."""
+    anything else -> contiguous float64 numpy array on the host. Work queued by
+    torch on its current stream is waited for first (the library may run on
+    a stream of its own)."""
     try:
         import torch
         if isinstance(x, torch.Tensor):
             if x.dtype != torch.float64 or not x.is_contiguous():
                 raise TypeError("device vectors must be contiguous float64 tensors")
+            if x.is_cuda:
+                torch.cuda.current_stream(x.device).synchronize()
             return C.c_void_p(x.data_ptr()), x
     except ImportError:
         pass
@@ -308,7 +312,8 @@ class Context:
     def profile(self, enable):
         out = np.zeros(4)
         self._check(self._L.mm_profile(self.h, int(enable), out.ctypes.data_as(_dp)))
-        return dict(launches=int(out[0]), seconds=float(out[1]), bytes_per_launch=float(out[2]), rows=int(out[3]))
+        return dict(iterations=int(out[0]), seconds=float(out[1]), bytes_per_iteration=float(out[2]),
+                    rows=int(out[3]))
 
     def poisson(self, b, u0=None, rtol=1e-10):
         bp, k1 = _vec_ptr(b)

@@ -77,26 +77,25 @@ void launch_spmv_scalar3(const Sell &A, const double *x, double *y, bool fp32, h
 void launch_bmul(const Sell &B, const double *m, double *b, bool fp32, hipStream_t s);
 void launch_btmul(const Sell &Bt, const double *u, double *gout, bool fp32, hipStream_t s);
 
-void launch_cg_init(const Sell &K, const double *b, const double *u, double *r, double *p, const double *invD,
-                    double *part, bool fp32, hipStream_t s);
-void launch_cg_spmv_dot(const Sell &K, const double *p, double *q, double *part, const int *done, int phase,
-                        hipStream_t s);
-void launch_cg_update(int n, double *u, double *r, const double *p, const double *q, const double *invD,
-                      const double *part_pq, const double *part_rz_prev, double *part_out, int *done, int *iters,
-                      int phase, hipStream_t s);
-void launch_cg_pupdate(int n, double *p, const double *r, const double *invD, const double *part_new,
-                       const double *part_old, double tol2, int *done, int phase, hipStream_t s);
+// Poisson CG state (device memory): start scalars, tolerance, stop flag and
+// iteration count
+struct PcgState {
+    double rz, beta, alpha, tol2, bb, rr;
+    int done, iters, zero_u, pad;
+};
+// partial buffer of the Poisson kernels (8 slots of kMaxPartials doubles)
+constexpr int kPcgPartDoubles = 8 * kMaxPartials;
 
-void launch_residual64(const Sell &K, const double *b, const double *u, double *r, double *part, hipStream_t s);
-void launch_cg32_init(int n, const double *r64, double inv_scale, float *x, float *r, float *p, const float *invD,
-                      double *part, hipStream_t s);
-void launch_cg32_spmv_dot(const Sell &K, const float *p, float *q, double *part, const int *done, int phase,
-                          hipStream_t s);
-void launch_cg32_update(int n, float *x, float *r, const float *p, const float *q, const float *invD,
-                        const double *part_pq, const double *part_rz_prev, double *part_out, int *done, int *iters,
-                        int phase, hipStream_t s);
-void launch_cg32_pupdate(int n, float *p, const float *r, const float *invD, const double *part_new,
-                         const double *part_old, double tol2, int *done, int phase, hipStream_t s);
+void launch_pcg_init64(const Sell &K, const double *b, const double *u, double *r, const double *invD, double rtol2,
+                       PcgState *st, double *part, bool fp32, hipStream_t s);
+void launch_residual64(const Sell &K, const double *b, const double *u, double *r, PcgState *st, double *part,
+                       hipStream_t s);
+void launch_pcg_init32(int n, const double *r64, double scale, float *x, float *r, const float *invD, double inner2,
+                       PcgState *st, double *part, hipStream_t s);
+void launch_pcg_iter64(const Sell &K, double *u, double *r, double *p_old, double *p_new, double *q,
+                       const double *invD, PcgState *st, int phase_a, int odd, double *part, hipStream_t s);
+void launch_pcg_iter32(const Sell &K, float *x, float *r, float *p_old, float *p_new, float *q, const float *invD,
+                       PcgState *st, int phase_a, int odd, double *part, hipStream_t s);
 void launch_add_correction(int n, double *u, const float *x, double scale, hipStream_t s);
 
 void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,

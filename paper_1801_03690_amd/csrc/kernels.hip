@@ -21,193 +21,14 @@
 // accumulated in FP64.
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace mmncg {
 
+using namespace dev;
+
 namespace {
-
-template <class V>
-struct SV {
-    const int64_t *sptr;
-    const int *col;
-    const V *val;
-    const int *row_out;
-    int nrows, nslices;
-};
-
-template <class V>
-SV<V> view(const Sell &A);
-template <>
-SV<double> view<double>(const Sell &A) {
-    return SV<double>{A.sptr, A.col, A.val, A.row_out, A.nrows, A.nslices};
-}
-template <>
-SV<float> view<float>(const Sell &A) {
-    return SV<float>{A.sptr, A.col, A.val32, A.row_out, A.nrows, A.nslices};
-}
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
-constexpr int kWaves = kBlock / 64;
-
-__device__ __forceinline__ int logical_block() {
-    int G = gridDim.x, b = blockIdx.x;
-    if (G >= 8 && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
-    return b;
-}
-
-// contiguous slice range of this block
-__device__ __forceinline__ void slice_range(int nslices, int &s0, int &s1) {
-    int G = gridDim.x;
-    int per = (nslices + G - 1) / G;
-    s0 = logical_block() * per;
-    s1 = min(nslices, s0 + per);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Block reduction of NQ quantities (sum, or max where is_max bit set). Result
-// valid in every thread. Uses `sh` (kWaves * NQ doubles of shared memory).
-template <int NQ>
-__device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max, double *sh) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = ((is_max >> q) & 1) ? wave_max(v[q]) : wave_sum(v[q]);
-    if (lane_id() == 0)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) sh[wave_id() * NQ + q] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double t = sh[q];
-        for (int w = 1; w < kWaves; ++w) t = ((is_max >> q) & 1) ? fmax(t, sh[w * NQ + q]) : t + sh[w * NQ + q];
-        v[q] = t;
-    }
-    __syncthreads();
-}
-
-template <int NQ>
-__device__ __forceinline__ void write_partials(double (&v)[NQ], unsigned is_max, double *part, double *sh) {
-    block_reduce<NQ>(v, is_max, sh);
-    if (threadIdx.x == 0) {
-        int lb = logical_block();
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) part[q * kMaxPartials + lb] = v[q];
-    }
-}
-
-// every block re-reduces partial slots (fixed order): out[q] = sum/max over nblk
-template <int NQ>
-__device__ __forceinline__ void read_partials(const double *part, int nblk, unsigned is_max, double (&out)[NQ],
-                                              double *sh) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) out[q] = ((is_max >> q) & 1) ? 0.0 : 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kBlock)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            double x = part[q * kMaxPartials + i];
-            out[q] = ((is_max >> q) & 1) ? fmax(out[q], x) : out[q] + x;
-        }
-    block_reduce<NQ>(out, is_max, sh);
-}
-
-// Stop flags carry the phase of the kernel that raised them. Every launch of
-// an iterative loop has a phase number increasing along the stream; a kernel
-// of phase P skips its work only when a kernel of an earlier phase stopped the
-// loop (0 < flag < P). A kernel never reacts to a flag raised by its own
-// launch, so all blocks of one launch take the same branch.
-__device__ __forceinline__ bool stopped_before(const int *flag, int phase) {
-    int f = *flag;
-    return f != 0 && f < phase;
-}
-
-// ---------------------------------------------------------------------------
-// row kernels: symmetric 3x3 block row (xx yy zz xy xz yz), scalar row, vec3 rows
-// ---------------------------------------------------------------------------
-template <class V>
-__device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const double *__restrict__ x,
-                                           double &o0, double &o1, double &o2) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
-    o0 = o1 = o2 = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        int c = A.col[e + ln];
-        const V *v = A.val + e * 6 + ln;
-        double vxx = (double)v[0], vyy = (double)v[64], vzz = (double)v[128];
-        double vxy = (double)v[192], vxz = (double)v[256], vyz = (double)v[320];
-        double x0 = x[3 * (int64_t)c], x1 = x[3 * (int64_t)c + 1], x2 = x[3 * (int64_t)c + 2];
-        o0 += vxx * x0 + vxy * x1 + vxz * x2;
-        o1 += vxy * x0 + vyy * x1 + vyz * x2;
-        o2 += vxz * x0 + vyz * x1 + vzz * x2;
-    }
-}
-
-template <class V, class X>
-__device__ __forceinline__ double row_scalar(const SV<V> &A, int s, int ln, const X *__restrict__ x) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
-    double acc = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k + ln;
-        acc += (double)A.val[e] * (double)x[A.col[e]];
-    }
-    return acc;
-}
-
-template <class V>
-__device__ __forceinline__ float row_scalar_f32(const SV<V> &A, int s, int ln, const float *__restrict__ x) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
-    float acc = 0.0f;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k + ln;
-        acc = fmaf((float)A.val[e], x[A.col[e]], acc);
-    }
-    return acc;
-}
-
-// sum_k vec3_k . x[col_k] (x node-major 3-vectors)
-template <class V>
-__device__ __forceinline__ double row_vec3_dot(const SV<V> &A, int s, int ln, const double *__restrict__ x) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
-    double acc = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        int c = A.col[e + ln];
-        const V *v = A.val + e * 3 + ln;
-        acc += (double)v[0] * x[3 * (int64_t)c] + (double)v[64] * x[3 * (int64_t)c + 1] +
-               (double)v[128] * x[3 * (int64_t)c + 2];
-    }
-    return acc;
-}
-
-// sum_k vec3_k * u[col_k]
-template <class V>
-__device__ __forceinline__ void row_vec3_scale(const SV<V> &A, int s, int ln, const double *__restrict__ u,
-                                               double &o0, double &o1, double &o2) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
-    o0 = o1 = o2 = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        double uc = u[A.col[e + ln]];
-        const V *v = A.val + e * 3 + ln;
-        o0 += (double)v[0] * uc;
-        o1 += (double)v[64] * uc;
-        o2 += (double)v[128] * uc;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // plain operator kernels (used by the checking ABI and as building blocks)
@@ -297,242 +118,6 @@ __global__ __launch_bounds__(kBlock) void k_btmul(SV<V> Bt, const double *__rest
             g[3 * (int64_t)row + 2] = o2;
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Poisson CG (FP64): K u = b, Jacobi preconditioner
-// partial slots: rz ring RZ[j%2] = 2 slots (rz, rr); PQ = 1 slot; INIT = 3 slots (bb, rz, rr)
-// ---------------------------------------------------------------------------
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_cg_init(SV<V> K, const double *__restrict__ b, const double *__restrict__ u,
-                                                    double *__restrict__ r, double *__restrict__ p,
-                                                    const double *__restrict__ invD, double *__restrict__ part) {
-    __shared__ double sh[kWaves * 3];
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
-    double acc[3] = {0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        double ku = row_scalar(K, s, ln, u);
-        int row = s * 64 + ln;
-        if (row < K.nrows) {
-            double bi = b[row];
-            double ri = bi - ku;
-            double zi = ri * invD[row];
-            r[row] = ri;
-            p[row] = zi;
-            acc[0] += bi * bi;
-            acc[1] += ri * zi;
-            acc[2] += ri * ri;
-        }
-    }
-    write_partials<3>(acc, 0u, part, sh);
-}
-
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(SV<V> K, const double *__restrict__ p, double *__restrict__ q,
-                                                        double *__restrict__ part, const int *__restrict__ done,
-                                                        int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves];
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
-    double acc[1] = {0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        double kp = row_scalar(K, s, ln, p);
-        int row = s * 64 + ln;
-        if (row < K.nrows) {
-            q[row] = kp;
-            acc[0] += p[row] * kp;
-        }
-    }
-    write_partials<1>(acc, 0u, part, sh);
-}
-
-// alpha = rz / pq; u += alpha p; r -= alpha q; partials (r.z, r.r) with z = D^-1 r
-__global__ __launch_bounds__(kBlock) void k_cg_update(int n, int nslices, double *__restrict__ u, double *__restrict__ r,
-                                                      const double *__restrict__ p, const double *__restrict__ q,
-                                                      const double *__restrict__ invD, const double *__restrict__ part_pq,
-                                                      const double *__restrict__ part_rz_prev,
-                                                      double *__restrict__ part_out, int nblk, int *__restrict__ done,
-                                                      int *__restrict__ iters, int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double pq[1], rz[1];
-    read_partials<1>(part_pq, nblk, 0u, pq, sh);
-    read_partials<1>(part_rz_prev, nblk, 0u, rz, sh);
-    double alpha = rz[0] / pq[0];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n) {
-            u[i] += alpha * p[i];
-            double ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            acc[0] += ri * (ri * invD[i]);
-            acc[1] += ri * ri;
-        }
-    }
-    write_partials<2>(acc, 0u, part_out, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *iters += 1;
-}
-
-// convergence test |r|^2 <= tol2; else beta = rz_new / rz_old, p = D^-1 r + beta p
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int n, int nslices, double *__restrict__ p,
-                                                       const double *__restrict__ r, const double *__restrict__ invD,
-                                                       const double *__restrict__ part_new,
-                                                       const double *__restrict__ part_old, int nblk, double tol2,
-                                                       int *__restrict__ done, int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double nw[2], od[1];
-    read_partials<2>(part_new, nblk, 0u, nw, sh);
-    if (nw[1] <= tol2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *done = phase;
-        return;
-    }
-    read_partials<1>(part_old, nblk, 0u, od, sh);
-    double beta = nw[0] / od[0];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n) p[i] = r[i] * invD[i] + beta * p[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// FP32 inner CG for the defect-correction Poisson solve (FP32-bulk mode)
-// ---------------------------------------------------------------------------
-// r64 = b - K u (FP64 accumulation of FP32-stored K), r32 = r64 * (1/|r|) later;
-// partials (bb, rr)
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_residual64(SV<V> K, const double *__restrict__ b, const double *__restrict__ u,
-                                                       double *__restrict__ r, double *__restrict__ part) {
-    __shared__ double sh[kWaves * 2];
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
-    double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        double ku = row_scalar(K, s, ln, u);
-        int row = s * 64 + ln;
-        if (row < K.nrows) {
-            double bi = b[row];
-            double ri = bi - ku;
-            r[row] = ri;
-            acc[0] += bi * bi;
-            acc[1] += ri * ri;
-        }
-    }
-    write_partials<2>(acc, 0u, part, sh);
-}
-
-// start of an inner FP32 solve of K x = r / scale: x = 0, r32 = r / scale,
-// p = z = D^-1 r32; partials (r.z, r.r)
-__global__ __launch_bounds__(kBlock) void k_cg32_init(int n, int nslices, const double *__restrict__ r64, double inv_scale,
-                                                      float *__restrict__ x, float *__restrict__ r,
-                                                      float *__restrict__ p, const float *__restrict__ invD,
-                                                      double *__restrict__ part) {
-    __shared__ double sh[kWaves * 2];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n) {
-            float ri = (float)(r64[i] * inv_scale);
-            float zi = ri * invD[i];
-            x[i] = 0.0f;
-            r[i] = ri;
-            p[i] = zi;
-            acc[0] += (double)ri * (double)zi;
-            acc[1] += (double)ri * (double)ri;
-        }
-    }
-    write_partials<2>(acc, 0u, part, sh);
-}
-
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_cg32_spmv_dot(SV<V> K, const float *__restrict__ p, float *__restrict__ q,
-                                                          double *__restrict__ part, const int *__restrict__ done,
-                                                          int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves];
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
-    double acc[1] = {0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        float kp = row_scalar_f32(K, s, ln, p);
-        int row = s * 64 + ln;
-        if (row < K.nrows) {
-            q[row] = kp;
-            acc[0] += (double)p[row] * (double)kp;
-        }
-    }
-    write_partials<1>(acc, 0u, part, sh);
-}
-
-__global__ __launch_bounds__(kBlock) void k_cg32_update(int n, int nslices, float *__restrict__ x, float *__restrict__ r,
-                                                        const float *__restrict__ p, const float *__restrict__ q,
-                                                        const float *__restrict__ invD, const double *__restrict__ part_pq,
-                                                        const double *__restrict__ part_rz_prev,
-                                                        double *__restrict__ part_out, int nblk, int *__restrict__ done,
-                                                        int *__restrict__ iters, int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double pq[1], rz[1];
-    read_partials<1>(part_pq, nblk, 0u, pq, sh);
-    read_partials<1>(part_rz_prev, nblk, 0u, rz, sh);
-    float alpha = (float)(rz[0] / pq[0]);
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n) {
-            x[i] = fmaf(alpha, p[i], x[i]);
-            float ri = fmaf(-alpha, q[i], r[i]);
-            r[i] = ri;
-            acc[0] += (double)ri * (double)(ri * invD[i]);
-            acc[1] += (double)ri * (double)ri;
-        }
-    }
-    write_partials<2>(acc, 0u, part_out, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *iters += 1;
-}
-
-__global__ __launch_bounds__(kBlock) void k_cg32_pupdate(int n, int nslices, float *__restrict__ p,
-                                                         const float *__restrict__ r, const float *__restrict__ invD,
-                                                         const double *__restrict__ part_new,
-                                                         const double *__restrict__ part_old, int nblk, double tol2,
-                                                         int *__restrict__ done, int phase) {
-    if (stopped_before(done, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double nw[2], od[1];
-    read_partials<2>(part_new, nblk, 0u, nw, sh);
-    if (nw[1] <= tol2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *done = phase;
-        return;
-    }
-    read_partials<1>(part_old, nblk, 0u, od, sh);
-    float beta = (float)(nw[0] / od[0]);
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n) p[i] = fmaf(beta, p[i], r[i] * invD[i]);
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *__restrict__ u, const float *__restrict__ x,
-                                                           double scale) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) u[i] += scale * (double)x[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -997,63 +582,6 @@ void launch_btmul(const Sell &Bt, const double *u, double *gout, bool fp32, hipS
     int g = grid_for_rows(Bt.nrows);
     if (fp32) hipLaunchKernelGGL(k_btmul<float>, dim3(g), dim3(kBlock), 0, s, view<float>(Bt), u, gout);
     else hipLaunchKernelGGL(k_btmul<double>, dim3(g), dim3(kBlock), 0, s, view<double>(Bt), u, gout);
-}
-
-void launch_cg_init(const Sell &K, const double *b, const double *u, double *r, double *p, const double *invD,
-                    double *part, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(K.nrows);
-    if (fp32) hipLaunchKernelGGL(k_cg_init<float>, dim3(g), dim3(kBlock), 0, s, view<float>(K), b, u, r, p, invD, part);
-    else hipLaunchKernelGGL(k_cg_init<double>, dim3(g), dim3(kBlock), 0, s, view<double>(K), b, u, r, p, invD, part);
-}
-void launch_cg_spmv_dot(const Sell &K, const double *p, double *q, double *part, const int *done, int phase,
-                        hipStream_t s) {
-    int g = grid_for_rows(K.nrows);
-    hipLaunchKernelGGL(k_cg_spmv_dot<double>, dim3(g), dim3(kBlock), 0, s, view<double>(K), p, q, part, done, phase);
-}
-void launch_cg_update(int n, double *u, double *r, const double *p, const double *q, const double *invD,
-                      const double *part_pq, const double *part_rz_prev, double *part_out, int *done, int *iters,
-                      int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), u, r, p, q, invD, part_pq,
-                       part_rz_prev, part_out, g, done, iters, phase);
-}
-void launch_cg_pupdate(int n, double *p, const double *r, const double *invD, const double *part_new,
-                       const double *part_old, double tol2, int *done, int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_cg_pupdate, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), p, r, invD, part_new, part_old, g,
-                       tol2, done, phase);
-}
-
-void launch_residual64(const Sell &K, const double *b, const double *u, double *r, double *part, hipStream_t s) {
-    int g = grid_for_rows(K.nrows);
-    hipLaunchKernelGGL(k_residual64<float>, dim3(g), dim3(kBlock), 0, s, view<float>(K), b, u, r, part);
-}
-void launch_cg32_init(int n, const double *r64, double inv_scale, float *x, float *r, float *p, const float *invD,
-                      double *part, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_cg32_init, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), r64, inv_scale, x, r, p, invD, part);
-}
-void launch_cg32_spmv_dot(const Sell &K, const float *p, float *q, double *part, const int *done, int phase,
-                          hipStream_t s) {
-    int g = grid_for_rows(K.nrows);
-    hipLaunchKernelGGL(k_cg32_spmv_dot<float>, dim3(g), dim3(kBlock), 0, s, view<float>(K), p, q, part, done, phase);
-}
-void launch_cg32_update(int n, float *x, float *r, const float *p, const float *q, const float *invD,
-                        const double *part_pq, const double *part_rz_prev, double *part_out, int *done, int *iters,
-                        int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_cg32_update, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), x, r, p, q, invD, part_pq,
-                       part_rz_prev, part_out, g, done, iters, phase);
-}
-void launch_cg32_pupdate(int n, float *p, const float *r, const float *invD, const double *part_new,
-                         const double *part_old, double tol2, int *done, int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_cg32_pupdate, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), p, r, invD, part_new, part_old,
-                       g, tol2, done, phase);
-}
-void launch_add_correction(int n, double *u, const float *x, double scale, hipStream_t s) {
-    int g = (n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_add_correction, dim3(g), dim3(kBlock), 0, s, n, u, x, scale);
 }
 
 void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,

@@ -100,8 +100,12 @@ struct mm_ctx {
     double *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr, *dscale = nullptr,
            *tmp3 = nullptr;
     // vectors on potential nodes
-    double *u = nullptr, *b = nullptr, *cr = nullptr, *cp = nullptr, *cq = nullptr, *usave = nullptr;
-    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    double *u = nullptr, *b = nullptr, *cr = nullptr, *cp = nullptr, *cp2 = nullptr, *cq = nullptr, *usave = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;
+    PcgState *pst = nullptr;     // device
+    PcgState *hpst = nullptr;    // pinned host mirror
+    double *ppart = nullptr;     // partials of the Poisson kernels
+    hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
     double *part = nullptr;
     double *dsc = nullptr, *hsc = nullptr;
     int *dflags = nullptr, *hflags = nullptr;
@@ -113,7 +117,7 @@ struct mm_ctx {
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
     size_t prof_used = 0;
-    double prof_launches = 0, prof_seconds = 0, prof_bytes = 0;
+    double prof_launches = 0, prof_seconds = 0, prof_units = 0;
     // counters of the current minimization
     long c_evals = 0, c_mi = 0, c_li = 0;
     double t_mag = 0, t_lin = 0;
@@ -158,6 +162,10 @@ T *dalloc_n(mm_ctx *c, size_t n) {
 
 void free_all(mm_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
     for (void *p : c->allocs) {
         if (c->ufree) c->ufree(p, c->user);
         else (void)hipFree(p);
@@ -304,8 +312,12 @@ void setup_device(mm_ctx *c) {
     c->b = dalloc_n<double>(c, np);
     c->cr = dalloc_n<double>(c, np);
     c->cp = dalloc_n<double>(c, np);
+    c->cp2 = dalloc_n<double>(c, np);
     c->cq = dalloc_n<double>(c, np);
     c->usave = dalloc_n<double>(c, np);
+    c->p32b = dalloc_n<float>(c, np);
+    c->pst = dalloc_n<PcgState>(c, 1);
+    c->ppart = dalloc_n<double>(c, kPcgPartDoubles);
     c->x32 = dalloc_n<float>(c, np);
     c->r32 = dalloc_n<float>(c, np);
     c->p32 = dalloc_n<float>(c, np);
@@ -317,6 +329,8 @@ void setup_device(mm_ctx *c) {
     HIPCHK(hipMemsetAsync(c->b, 0, np * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->part, 0, (size_t)PS_TOTAL * kMaxPartials * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->dflags, 0, FL_TOTAL * sizeof(int), c->stream));
+    HIPCHK(hipMemsetAsync(c->pst, 0, sizeof(PcgState), c->stream));
+    HIPCHK(hipMemsetAsync(c->ppart, 0, kPcgPartDoubles * sizeof(double), c->stream));
     sync(c);
     c->last_poisson_iters = 16;
 }
@@ -324,43 +338,98 @@ void setup_device(mm_ctx *c) {
 // ---------------------------------------------------------------------------
 // Poisson: K u = b (warm start u), Jacobi-PCG; FP64 or FP32 defect correction
 // ---------------------------------------------------------------------------
+constexpr int kPcgChunk = 8;  // CG iterations per captured graph (even: the p double buffer returns)
+
+// capture kPcgChunk iterations (2 kernels each) once per context and mode
+hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32) {
+    hipGraphExec_t &ge = fp32 ? c->graph32 : c->graph64;
+    if (ge) return ge;
+    hipStream_t s = c->stream;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < kPcgChunk; ++j) {
+        const int ph = 2 * j + 2;
+        if (fp32) {
+            float *po = (j & 1) ? c->p32b : c->p32, *pn = (j & 1) ? c->p32 : c->p32b;
+            launch_pcg_iter32(c->K, c->x32, c->r32, po, pn, c->q32, c->invDK32, c->pst, ph, j & 1, c->ppart, s);
+        } else {
+            double *po = (j & 1) ? c->cp2 : c->cp, *pn = (j & 1) ? c->cp : c->cp2;
+            launch_pcg_iter64(c->K, c->u, c->cr, po, pn, c->cq, c->invDK, c->pst, ph, j & 1, c->ppart, s);
+        }
+    }
+    HIPCHK(hipStreamEndCapture(s, &g));
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return ge;
+}
+
+void pull_pcg(mm_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->hpst, c->pst, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+// replay graph chunks until the device flag reports convergence; returns
+// iterations. With timing on, HIP events bracket every batch of replays and
+// the executed iterations of the batch are counted (speculative replays after
+// convergence return at once; their time stays in the measurement).
+bool use_graphs() {
+    static bool on = [] {
+        const char *e = std::getenv("MMNCG_NO_GRAPH");
+        return !(e && std::atoi(e) != 0);
+    }();
+    return on;
+}
+
+void pcg_chunk_eager(mm_ctx *c, bool fp32) {
+    hipStream_t s = c->stream;
+    for (int j = 0; j < kPcgChunk; ++j) {
+        const int ph = 2 * j + 2;
+        if (fp32) {
+            float *po = (j & 1) ? c->p32b : c->p32, *pn = (j & 1) ? c->p32 : c->p32b;
+            launch_pcg_iter32(c->K, c->x32, c->r32, po, pn, c->q32, c->invDK32, c->pst, ph, j & 1, c->ppart, s);
+        } else {
+            double *po = (j & 1) ? c->cp2 : c->cp, *pn = (j & 1) ? c->cp : c->cp2;
+            launch_pcg_iter64(c->K, c->u, c->cr, po, pn, c->cq, c->invDK, c->pst, ph, j & 1, c->ppart, s);
+        }
+    }
+}
+
+long pcg_replay(mm_ctx *c, bool fp32, long maxit) {
+    hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32) : nullptr;
+    long expect = std::max<long>(kPcgChunk, c->last_poisson_iters);
+    long nrep = (expect + kPcgChunk - 1) / kPcgChunk;
+    long launched = 0, seen = 0;
+    for (;;) {
+        prof_mark(c);
+        for (long k = 0; k < nrep; ++k) {
+            if (ge) HIPCHK(hipGraphLaunch(ge, c->stream));
+            else pcg_chunk_eager(c, fp32);
+        }
+        prof_mark(c);
+        launched += nrep * kPcgChunk;
+        pull_pcg(c);
+        if (c->prof_on) {
+            prof_harvest(c);
+            c->prof_units += c->hpst->iters - seen;
+            seen = c->hpst->iters;
+        }
+        if (c->hpst->done || c->hpst->zero_u) break;
+        if (launched >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
+        nrep = std::max<long>(1, (expect / 8 + kPcgChunk - 1) / kPcgChunk);
+    }
+    return c->hpst->iters;
+}
+
 long poisson_fp64(mm_ctx *c, double rtol, long maxit) {
     const int n = c->n_pot();
     if (n == 0) return 0;
-    hipStream_t s = c->stream;
-    launch_cg_init(c->K, c->b, c->u, c->cr, c->cp, c->invDK, partp(c, PS_CG_INIT), false, s);
-    launch_finalize(partp(c, PS_CG_INIT), grid_for_rows(n), 3, 0u, c->dsc + SC_CG, s);
-    pull(c, SC_CG, 3);
-    double bb = c->hsc[SC_CG], rr = c->hsc[SC_CG + 2];
-    if (bb == 0.0) {
-        HIPCHK(hipMemsetAsync(c->u, 0, n * sizeof(double), s));
+    launch_pcg_init64(c->K, c->b, c->u, c->cr, c->invDK, rtol * rtol, c->pst, c->ppart, false, c->stream);
+    long it = pcg_replay(c, false, maxit);
+    if (c->hpst->zero_u) {
+        HIPCHK(hipMemsetAsync(c->u, 0, n * sizeof(double), c->stream));
         return 0;
     }
-    double tol2 = rtol * rtol * bb;
-    if (rr <= tol2) return 0;
-    HIPCHK(hipMemsetAsync(c->dflags + FL_CG_DONE, 0, 2 * sizeof(int), s));
-    long j = 0;
-    long chunk = std::max<long>(4, c->last_poisson_iters);
-    for (;;) {
-        for (long k = 0; k < chunk && j < maxit; ++k, ++j) {
-            const double *prev = (j == 0) ? partp(c, PS_CG_INIT + 1) : partp(c, (j & 1) ? PS_CG_RZ1 : PS_CG_RZ0);
-            double *nw = partp(c, ((j + 1) & 1) ? PS_CG_RZ1 : PS_CG_RZ0);
-            const int ph = 3 * (int)j;
-            prof_mark(c);
-            launch_cg_spmv_dot(c->K, c->cp, c->cq, partp(c, PS_CG_PQ), c->dflags + FL_CG_DONE, ph + 1, s);
-            prof_mark(c);
-            launch_cg_update(n, c->u, c->cr, c->cp, c->cq, c->invDK, partp(c, PS_CG_PQ), prev, nw,
-                             c->dflags + FL_CG_DONE, c->dflags + FL_CG_ITERS, ph + 2, s);
-            launch_cg_pupdate(n, c->cp, c->cr, c->invDK, nw, prev, tol2, c->dflags + FL_CG_DONE, ph + 3, s);
-        }
-        HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-        sync(c);
-        prof_harvest(c);
-        if (c->hflags[FL_CG_DONE]) break;
-        if (j >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
-        chunk = std::max<long>(4, c->last_poisson_iters / 8);
-    }
-    long it = c->hflags[FL_CG_ITERS];
     c->last_poisson_iters = std::max<long>(4, it);
     return it;
 }
@@ -371,45 +440,20 @@ long poisson_fp32(mm_ctx *c, double rtol, long maxit) {
     hipStream_t s = c->stream;
     long total = 0;
     for (int outer = 0; outer < 50; ++outer) {
-        launch_residual64(c->K, c->b, c->u, c->cr, partp(c, PS_CG_INIT), s);
-        launch_finalize(partp(c, PS_CG_INIT), grid_for_rows(n), 2, 0u, c->dsc + SC_CG, s);
-        pull(c, SC_CG, 2);
-        double bb = c->hsc[SC_CG], rr = c->hsc[SC_CG + 1];
+        launch_residual64(c->K, c->b, c->u, c->cr, c->pst, c->ppart, s);
+        pull_pcg(c);
+        double bb = c->hpst->bb, rr = c->hpst->rr;
         if (bb == 0.0) {
             HIPCHK(hipMemsetAsync(c->u, 0, n * sizeof(double), s));
             return total;
         }
         if (rr <= rtol * rtol * bb) return total;
         double rn = std::sqrt(rr);
-        // inner relative target: stop early enough to not over-solve the last correction
+        // relative target of the inner FP32 solve: not beyond what the last correction needs
         double inner = std::max(1e-5, 0.5 * rtol * std::sqrt(bb) / rn);
         inner = std::min(inner, 1e-1);
-        double tol2 = inner * inner;  // the inner rhs is r / |r|, so |r32_0| = 1
-        launch_cg32_init(n, c->cr, 1.0 / rn, c->x32, c->r32, c->p32, c->invDK32, partp(c, PS_CG_INIT), s);
-        HIPCHK(hipMemsetAsync(c->dflags + FL_CG_DONE, 0, 2 * sizeof(int), s));
-        long j = 0;
-        long chunk = std::max<long>(4, c->last_poisson_iters);
-        for (;;) {
-            for (long k = 0; k < chunk && total + j < maxit; ++k, ++j) {
-                const double *prev = (j == 0) ? partp(c, PS_CG_INIT) : partp(c, (j & 1) ? PS_CG_RZ1 : PS_CG_RZ0);
-                double *nw = partp(c, ((j + 1) & 1) ? PS_CG_RZ1 : PS_CG_RZ0);
-                const int ph = 3 * (int)j;
-                prof_mark(c);
-                launch_cg32_spmv_dot(c->K, c->p32, c->q32, partp(c, PS_CG_PQ), c->dflags + FL_CG_DONE, ph + 1, s);
-                prof_mark(c);
-                launch_cg32_update(n, c->x32, c->r32, c->p32, c->q32, c->invDK32, partp(c, PS_CG_PQ), prev, nw,
-                                   c->dflags + FL_CG_DONE, c->dflags + FL_CG_ITERS, ph + 2, s);
-                launch_cg32_pupdate(n, c->p32, c->r32, c->invDK32, nw, prev, tol2, c->dflags + FL_CG_DONE, ph + 3,
-                                    s);
-            }
-            HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            sync(c);
-            prof_harvest(c);
-            if (c->hflags[FL_CG_DONE]) break;
-            if (total + j >= maxit) break;
-            chunk = std::max<long>(4, c->last_poisson_iters / 8);
-        }
-        long it = c->hflags[FL_CG_ITERS];
+        launch_pcg_init32(n, c->cr, 1.0 / rn, c->x32, c->r32, c->invDK32, inner * inner, c->pst, c->ppart, s);
+        long it = pcg_replay(c, true, maxit - total);
         total += it;
         c->last_poisson_iters = std::max<long>(4, it);
         launch_add_correction(n, c->u, c->x32, rn, s);
@@ -842,6 +886,8 @@ int mm_create(mm_ctx **out, int device, void *hip_stream, mm_alloc_fn dev_alloc,
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
         HIPCHK(hipHostMalloc((void **)&c->hsc, SC_TOTAL * sizeof(double), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&c->hflags, FL_TOTAL * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&c->hpst, sizeof(PcgState), hipHostMallocDefault));
+        std::memset(c->hpst, 0, sizeof(PcgState));
         std::memset(c->hsc, 0, SC_TOTAL * sizeof(double));
         std::memset(c->hflags, 0, FL_TOTAL * sizeof(int));
         return MM_OK;
@@ -863,6 +909,7 @@ int mm_destroy(mm_ctx *c) {
     for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hflags) (void)hipHostFree(c->hflags);
+    if (c->hpst) (void)hipHostFree(c->hpst);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return MM_OK;
@@ -1128,16 +1175,18 @@ int mm_profile(mm_ctx *c, int enable, double out[4]) {
         sync(c);
         prof_harvest(c);
         if (enable < 0) {
-            c->prof_launches = c->prof_seconds = 0;
+            c->prof_launches = c->prof_seconds = c->prof_units = 0;
         } else {
             c->prof_on = enable != 0;
         }
         if (out) {
             const bool fp32 = c->opts.precision == MM_FP32_BULK;
             const double vb = fp32 ? 4.0 : 8.0;
-            out[0] = c->prof_launches;
+            out[0] = c->prof_units;
             out[1] = c->prof_seconds;
-            out[2] = c->have_mat ? (double)c->K.nnz * (vb + 4.0) + 2.0 * vb * c->K.nrows : 0.0;
+            // kernel A: matrix + r, D^-1, p_old read + p_new, q written;
+            // kernel B: x, r, p, q, D^-1 read + x, r written (x is FP64 in the FP64 mode only)
+            out[2] = c->have_mat ? (double)c->K.nnz * (vb + 4.0) + 12.0 * vb * c->K.nrows : 0.0;
             out[3] = c->have_mat ? (double)c->K.nrows : 0.0;
         }
         return MM_OK;
