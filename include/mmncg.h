@@ -196,13 +196,67 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
    and kernel B, the solution/residual update) with HIP events on the
    context's stream around every batch of iterations (the iterations run as
    replays of a captured graph); enable = 0 stops; enable = -1 resets the
-   counters. out (may be NULL) receives {iterations executed, seconds,
-   algorithmic bytes per iteration, rows}: the stored matrix (values + column
-   indices, no padding) plus the vector traffic of the two kernels (kernel A:
-   read r, D^-1, old direction, write new direction and K p; kernel B: read x,
-   r, p, q, D^-1, write x and r), at the precision of the options last set
-   with mm_set_opts (FP32-bulk: 4-byte values). */
+   counters. out (may be NULL) receives {instance-iterations executed,
+   seconds, algorithmic bytes of those iterations, potential rows of all
+   instances}. Algorithmic bytes of one iteration of an instance: its stored
+   matrix (values + column indices, no padding) plus the vector traffic of the
+   two kernels (kernel A: read r, D^-1, old direction, write new direction and
+   K p; kernel B: read x, r, p, q, D^-1, write x and r), 8-byte values in the
+   FP64 mode and 4-byte values in the FP32 inner solves. */
 int mm_profile(mm_ctx *c, int enable, double out[4]);
+
+/* ---------------------------------------------------------------------------
+   Batches of independent instances (parameter studies, Sec. 3.1 curves of
+   many grains). A context may hold n_inst independent problems, each with
+   its own mesh, materials, air box, Dirichlet boundary and reduced units
+   (Ms_ref = max Ms of that instance). Every kernel launch serves all
+   instances; each instance runs its own minimizer (Alg. 4) and walks its own
+   field list. Results per instance equal those of a context holding that
+   instance alone, up to the order of floating-point sums.
+
+   Caller layout: per-instance arrays are concatenated in instance order.
+   Magnetizations (and gradients) are sum_i n_mag_i x 3 doubles, instance i
+   occupying the rows after those of instances 0..i-1, each ordered like
+   mm_magnet_nodes. The single-instance calls above (mm_energy_grad,
+   mm_precondition, mm_ncg_minimize, mm_demag_curve, mm_operator_apply,
+   mm_poisson_solve, mm_magnet_nodes) need a context with one instance and
+   return MM_ESTATE otherwise.
+   --------------------------------------------------------------------------- */
+
+/* Upload n_inst meshes with their materials (replaces mm_mesh_upload +
+   mm_material_set). n_nodes, n_tets: per instance. xyz (sum n_nodes x 3),
+   tets (sum n_tets x 4, node indices local to the instance), region, Ms, A,
+   K1 (sum n_tets each) and axis (sum n_tets x 3, may be NULL when every K1 is
+   0) are concatenated in instance order; meaning and units as in
+   mm_mesh_upload / mm_material_set. Host pointers only. On failure the
+   context holds no problem (MM_ESTATE until the next successful upload). */
+int mm_batch_upload(mm_ctx *c, int n_inst, const long *n_nodes, const long *n_tets, const double *xyz,
+                    const int *tets, const int *region, const double *Ms, const double *A, const double *K1,
+                    const double *axis);
+
+/* Number of instances of the context (0 before any problem is set). */
+int mm_batch_size(const mm_ctx *c, int *n_inst);
+
+/* Sizes and Ms_ref of instance inst (device_bytes: the whole context). */
+int mm_batch_info(const mm_ctx *c, int inst, mm_info *info);
+
+/* Magnet nodes of instance inst (local mesh-node ids, ascending). */
+int mm_batch_magnet_nodes(const mm_ctx *c, int inst, long *n_mag, int *node_ids);
+
+/* Energy and gradient of every instance at once (eq. (energy)), options of
+   mm_set_opts. m: concatenated unit vectors; h_ext: n_inst x 3 (Tesla).
+   E_tot, torque_max: n_inst; grad, gproj: concatenated like m. Every output
+   may be NULL. */
+int mm_batch_energy_grad(mm_ctx *c, const double *m, const double *h_ext, double *E_tot, double *grad,
+                         double *gproj, double *torque_max);
+
+/* Demagnetization curves of every instance (Sec. 3.1): instance i minimizes
+   at h_list[i][k] (Tesla; h_list is n_inst x n x 3) for k = 0..n-1, each
+   from its previous minimizer. m_inout: concatenated start / final states.
+   m_avg (n_inst x n x 3), E_tot (n_inst x n) and st (n_inst x n) may be NULL.
+   Returns the worst status over all instances and fields. */
+int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, const mm_opts *o,
+                         double *m_avg, double *E_tot, mm_stats *st);
 
 #ifdef __cplusplus
 }

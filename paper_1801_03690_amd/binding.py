@@ -96,6 +96,13 @@ def load_library(path=LIB_PATH):
     L.mm_operator_apply.argtypes = [_vp, C.c_int, _vp, _vp]
     L.mm_poisson_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.POINTER(C.c_long)]
     L.mm_profile.argtypes = [_vp, C.c_int, _dp]
+    _lp = C.POINTER(C.c_long)
+    L.mm_batch_upload.argtypes = [_vp, C.c_int, _lp, _lp, _dp, _ip, _ip, _dp, _dp, _dp, _dp]
+    L.mm_batch_size.argtypes = [_vp, _ip]
+    L.mm_batch_info.argtypes = [_vp, C.c_int, C.POINTER(Info)]
+    L.mm_batch_magnet_nodes.argtypes = [_vp, C.c_int, _lp, _ip]
+    L.mm_batch_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
+    L.mm_batch_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats)]
     for name in header_symbols():
         if getattr(L, name).restype is C.c_int or name != "mm_last_error":
             if name != "mm_last_error":
@@ -312,8 +319,9 @@ class Context:
     def profile(self, enable):
         out = np.zeros(4)
         self._check(self._L.mm_profile(self.h, int(enable), out.ctypes.data_as(_dp)))
-        return dict(iterations=int(out[0]), seconds=float(out[1]), bytes_per_iteration=float(out[2]),
-                    rows=int(out[3]))
+        it = int(out[0])
+        return dict(iterations=it, seconds=float(out[1]), bytes=float(out[2]),
+                    bytes_per_iteration=float(out[2]) / it if it else 0.0, rows=int(out[3]))
 
     def poisson(self, b, u0=None, rtol=1e-10):
         bp, k1 = _vec_ptr(b)
@@ -321,3 +329,86 @@ class Context:
         it = C.c_long()
         self._check(self._L.mm_poisson_solve(self.h, bp, C.c_void_p(u.ctypes.data), rtol, C.byref(it)))
         return u, it.value
+
+    # ----------------------------------------------------------------
+    # batches of independent instances
+    def upload_batch(self, meshes):
+        """Upload several meshes (with materials) as one batch."""
+        meshes = list(meshes)
+        nn = np.array([m.xyz.shape[0] for m in meshes], dtype=np.int64)
+        nt = np.array([m.tets.shape[0] for m in meshes], dtype=np.int64)
+        xyz = _host_f64(np.concatenate([m.xyz for m in meshes]))
+        tets = np.ascontiguousarray(np.concatenate([m.tets for m in meshes]), dtype=np.int32)
+        reg = np.ascontiguousarray(np.concatenate([m.region for m in meshes]), dtype=np.int32)
+        Ms = _host_f64(np.concatenate([m.Ms for m in meshes]))
+        A = _host_f64(np.concatenate([m.A for m in meshes]))
+        K1 = _host_f64(np.concatenate([m.K1 for m in meshes]))
+        ax = _host_f64(np.concatenate([m.axis for m in meshes]))
+        self._check(self._L.mm_batch_upload(self.h, len(meshes), nn.ctypes.data_as(C.POINTER(C.c_long)),
+                                            nt.ctypes.data_as(C.POINTER(C.c_long)), xyz.ctypes.data_as(_dp),
+                                            tets.ctypes.data_as(_ip), reg.ctypes.data_as(_ip),
+                                            Ms.ctypes.data_as(_dp), A.ctypes.data_as(_dp),
+                                            K1.ctypes.data_as(_dp), ax.ctypes.data_as(_dp)))
+        self.n_inst = len(meshes)
+        self.inst_info = [self.batch_info(i) for i in range(self.n_inst)]
+        self.n_mag_list = [d["n_mag"] for d in self.inst_info]
+        self.n_mag = int(sum(self.n_mag_list))
+        self.n_pot = int(sum(d["n_pot"] for d in self.inst_info))
+        return self
+
+    def batch_size(self):
+        n = C.c_int()
+        self._check(self._L.mm_batch_size(self.h, C.byref(n)))
+        return n.value
+
+    def batch_info(self, i):
+        inf = Info()
+        self._check(self._L.mm_batch_info(self.h, int(i), C.byref(inf)))
+        return inf.as_dict()
+
+    def batch_magnet_nodes(self, i):
+        n = C.c_long()
+        self._check(self._L.mm_batch_magnet_nodes(self.h, int(i), C.byref(n), None))
+        ids = np.zeros(n.value, dtype=np.int32)
+        self._check(self._L.mm_batch_magnet_nodes(self.h, int(i), C.byref(n), ids.ctypes.data_as(_ip)))
+        return ids
+
+    def split(self, v):
+        """Split a concatenated (sum n_mag, ...) array into per-instance arrays."""
+        out, o = [], 0
+        for n in self.n_mag_list:
+            out.append(v[o:o + n])
+            o += n
+        return out
+
+    def batch_energy_grad(self, m, h_T):
+        mp, keep = _vec_ptr(m)
+        h = _host_f64(h_T, (-1, 3))
+        ni = self.n_inst
+        E = np.zeros(ni)
+        t = np.zeros(ni)
+        G = np.zeros((self.n_mag, 3))
+        g = np.zeros((self.n_mag, 3))
+        self._check(self._L.mm_batch_energy_grad(self.h, mp, h.ctypes.data_as(_dp), E.ctypes.data_as(_dp),
+                                                 C.c_void_p(G.ctypes.data), C.c_void_p(g.ctypes.data),
+                                                 t.ctypes.data_as(_dp)))
+        return dict(E=E, G=G, g=g, tmax=t)
+
+    def batch_curve(self, m, fields_T, opts=None, **kw):
+        """fields_T: (n_inst, n, 3) Tesla. Returns per-instance curves."""
+        o = opts or default_opts(**kw)
+        mp, keep = _vec_ptr(m)
+        if isinstance(keep, np.ndarray):
+            keep = keep.copy()
+            mp = C.c_void_p(keep.ctypes.data)
+        F = _host_f64(fields_T)
+        ni = self.n_inst
+        F = F.reshape(ni, -1, 3)
+        nf = F.shape[1]
+        mavg = np.zeros((ni, nf, 3))
+        Et = np.zeros((ni, nf))
+        st = (Stats * (ni * nf))()
+        rc = self._check(self._L.mm_batch_demag_curve(self.h, mp, F.ctypes.data_as(_dp), nf, C.byref(o),
+                                                      mavg.ctypes.data_as(_dp), Et.ctypes.data_as(_dp), st))
+        stats = [[st[i * nf + k].as_dict() for k in range(nf)] for i in range(ni)]
+        return dict(m=keep, m_avg=mavg, E=Et, stats=stats, rc=rc)

@@ -1,6 +1,6 @@
 // Device-side helpers shared by the HIP translation units: the SELL-64 row
-// view, XCD-aware block numbering, deterministic wave/block reductions, the
-// phase-stamped stop flags.
+// view, instance tiles of a RowMap with XCD-aware block numbering,
+// deterministic wave/block reductions and the phase-stamped stop flags.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,20 +32,24 @@ inline SV<float> view<float>(const Sell &A) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
-constexpr int kWaves = kBlock / 64;
 
+// Hardware blocks are dealt round-robin to the 8 XCDs; renumber them so that
+// each XCD runs one contiguous eighth of the logical blocks (the tables of a
+// RowMap hold a multiple of 8 blocks).
 __device__ __forceinline__ int logical_block() {
     int G = gridDim.x, b = blockIdx.x;
     if (G >= 8 && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
     return b;
 }
 
-// contiguous slice range of this block
-__device__ __forceinline__ void slice_range(int nslices, int &s0, int &s1) {  // NOLINT
-    int G = gridDim.x;
-    int per = (nslices + G - 1) / G;
-    s0 = logical_block() * per;
-    s1 = min(nslices, s0 + per);
+struct Tile {
+    int inst, s0, s1, b;
+};
+// the tile of this block; inst < 0 marks padding blocks (no work, no partials)
+__device__ __forceinline__ Tile tile_of(const RowMap &M) {
+    int b = logical_block();
+    int4 t = M.tab[b];
+    return Tile{t.x, t.y, t.z, b};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -59,9 +63,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block reduction of NQ quantities (sum, or max where is_max bit set). Result
-// valid in every thread. Uses `sh` (kWaves * NQ doubles of shared memory).
-template <int NQ, int NW = kWaves>
+// Block reduction of NQ quantities (sum, or max where is_max bit set); result
+// valid in every thread; `sh` holds NW * NQ doubles of shared memory.
+template <int NQ, int NW>
 __device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max, double *sh) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = ((is_max >> q) & 1) ? wave_max(v[q]) : wave_sum(v[q]);
@@ -78,26 +82,26 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ], unsigned is_max, d
     __syncthreads();
 }
 
-template <int NQ, int NW = kWaves>
-__device__ __forceinline__ void write_partials(double (&v)[NQ], unsigned is_max, double *part, double *sh) {
+// this block's partials -> part[q * stride + b]
+template <int NQ, int NW>
+__device__ __forceinline__ void write_part(double (&v)[NQ], unsigned is_max, double *part, int stride, int b,
+                                           double *sh) {
     block_reduce<NQ, NW>(v, is_max, sh);
-    if (threadIdx.x == 0) {
-        int lb = logical_block();
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) part[q * kMaxPartials + lb] = v[q];
-    }
+        for (int q = 0; q < NQ; ++q) part[(size_t)q * stride + b] = v[q];
 }
 
-// every block re-reduces partial slots (fixed order): out[q] = sum/max over nblk
-template <int NQ, int NW = kWaves>
-__device__ __forceinline__ void read_partials(const double *part, int nblk, unsigned is_max, double (&out)[NQ],
-                                              double *sh) {
+// fixed-order reduction of the partials of blocks [b0, b1); result in every thread
+template <int NQ, int NW>
+__device__ __forceinline__ void read_part(const double *part, int stride, int b0, int b1, unsigned is_max,
+                                          double (&out)[NQ], double *sh) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) out[q] = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += NW * 64)
+    for (int i = b0 + (int)threadIdx.x; i < b1; i += NW * 64)
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            double x = part[q * kMaxPartials + i];
+            double x = part[(size_t)q * stride + i];
             out[q] = ((is_max >> q) & 1) ? fmax(out[q], x) : out[q] + x;
         }
     block_reduce<NQ, NW>(out, is_max, sh);
@@ -114,11 +118,12 @@ __device__ __forceinline__ bool stopped_before(const int *flag, int phase) {
 }
 
 // ---------------------------------------------------------------------------
-// row kernels: symmetric 3x3 block row (xx yy zz xy xz yz), scalar row, vec3 rows
+// SELL-64 rows
 // ---------------------------------------------------------------------------
+// symmetric 3x3 block row (xx yy zz xy xz yz) times node-major 3-vectors
 template <class V>
-__device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const double *__restrict__ x,
-                                           double &o0, double &o1, double &o2) {
+__device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const double *__restrict__ x, double &o0,
+                                           double &o1, double &o2) {
     int64_t base = A.sptr[s];
     int w = (int)((A.sptr[s + 1] - base) >> 6);
     o0 = o1 = o2 = 0.0;
@@ -135,6 +140,7 @@ __device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const 
     }
 }
 
+// scalar row times a plain vector
 template <class V, class X>
 __device__ __forceinline__ double row_scalar(const SV<V> &A, int s, int ln, const X *__restrict__ x) {
     int64_t base = A.sptr[s];
@@ -147,19 +153,24 @@ __device__ __forceinline__ double row_scalar(const SV<V> &A, int s, int ln, cons
     return acc;
 }
 
+// scalar row applied to each component of node-major 3-vectors
 template <class V>
-__device__ __forceinline__ float row_scalar_f32(const SV<V> &A, int s, int ln, const float *__restrict__ x) {
+__device__ __forceinline__ void row_scalar3(const SV<V> &A, int s, int ln, const double *__restrict__ x, double &o0,
+                                            double &o1, double &o2) {
     int64_t base = A.sptr[s];
     int w = (int)((A.sptr[s + 1] - base) >> 6);
-    float acc = 0.0f;
+    o0 = o1 = o2 = 0.0;
     for (int k = 0; k < w; ++k) {
         int64_t e = base + 64 * k + ln;
-        acc = fmaf((float)A.val[e], x[A.col[e]], acc);
+        double a = (double)A.val[e];
+        int64_t c = A.col[e];
+        o0 += a * x[3 * c];
+        o1 += a * x[3 * c + 1];
+        o2 += a * x[3 * c + 2];
     }
-    return acc;
 }
 
-// sum_k vec3_k . x[col_k] (x node-major 3-vectors)
+// sum_k vec3_k . x[col_k]
 template <class V>
 __device__ __forceinline__ double row_vec3_dot(const SV<V> &A, int s, int ln, const double *__restrict__ x) {
     int64_t base = A.sptr[s];
@@ -191,7 +202,6 @@ __device__ __forceinline__ void row_vec3_scale(const SV<V> &A, int s, int ln, co
         o2 += (double)v[128] * uc;
     }
 }
-
 
 }  // namespace dev
 }  // namespace mmncg

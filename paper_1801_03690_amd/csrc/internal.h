@@ -12,7 +12,8 @@ namespace mmncg {
 
 constexpr int kSlice = 64;      // rows per SELL slice = one wavefront
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
-constexpr int kMaxPartials = 1024;  // upper bound on blocks of a reducing kernel
+constexpr int kMaxBlocksPerInst = 256;  // per instance and row space
+constexpr int kPoissonBlock = 1024;     // threads per block of the scalar-potential kernels
 
 // ---------------------------------------------------------------------------
 // host-side CSR produced by the assembly (row-major, sorted columns)
@@ -64,67 +65,106 @@ std::string assemble(const double *xyz, long n_nodes, const int *tets, long n_te
                      Assembly &out);
 
 // ---------------------------------------------------------------------------
-// kernel launchers (defined in kernels.hip); all enqueue on `s`. Partial
-// buffers hold NQ slots of kMaxPartials doubles (slot q at q * kMaxPartials).
+// Instance batching. Several independent problems ("instances") share every
+// launch: their rows are concatenated, each instance padded to whole SELL
+// slices. A RowMap partitions one row space (magnet rows, potential rows or
+// divergence rows) into logical blocks that never straddle two instances:
+// block b covers slices [tab[b].y, tab[b].z) of instance tab[b].x, the blocks
+// of instance i are [ipb[i], ipb[i+1]), and its real rows end at rend[i].
+// Per-block partial sums are stored at part[q * nblk + b]; the reductions of
+// instance i read only its own blocks.
 // ---------------------------------------------------------------------------
-int grid_for_rows(int nrows);   // blocks of a row kernel (multiple of 8 when >= 8, <= kMaxPartials)
-unsigned eval_max_mask();
-constexpr int kEvalParts = 10;  // Eloc, Ezee, Edemag, dF, dphi, |g|^2, max torque, max|g|_inf, max|m-x0|_inf, max|m|_inf
-
-void launch_spmv_block6(const Sell &C, const double *x, double *y, bool fp32, hipStream_t s);
-void launch_spmv_scalar(const Sell &A, const double *x, double *y, bool fp32, hipStream_t s);
-void launch_spmv_scalar3(const Sell &A, const double *x, double *y, bool fp32, hipStream_t s);
-void launch_bmul(const Sell &B, const double *m, double *b, bool fp32, hipStream_t s);
-void launch_btmul(const Sell &Bt, const double *u, double *gout, bool fp32, hipStream_t s);
-
-// Poisson CG state (device memory): start scalars, tolerance, stop flag and
-// iteration count
-struct PcgState {
-    double rz, beta, alpha, tol2, bb, rr;
-    int done, iters, zero_u, pad;
+struct RowMap {
+    const int4 *tab = nullptr;
+    const int *ipb = nullptr;
+    const int *rend = nullptr;
+    int nblk = 0;
+    int ninst = 0;
 };
-// partial buffer of the Poisson kernels (8 slots of kMaxPartials doubles)
-constexpr int kPcgPartDoubles = 8 * kMaxPartials;
 
-void launch_pcg_init64(const Sell &K, const double *b, const double *u, double *r, const double *invD, double rtol2,
-                       PcgState *st, double *part, bool fp32, hipStream_t s);
-void launch_residual64(const Sell &K, const double *b, const double *u, double *r, PcgState *st, double *part,
-                       hipStream_t s);
-void launch_pcg_init32(int n, const double *r64, double scale, float *x, float *r, const float *invD, double inner2,
-                       PcgState *st, double *part, hipStream_t s);
-void launch_pcg_iter64(const Sell &K, double *u, double *r, double *p_old, double *p_new, double *q,
-                       const double *invD, PcgState *st, int phase_a, int odd, double *part, hipStream_t s);
-void launch_pcg_iter32(const Sell &K, float *x, float *r, float *p_old, float *p_new, float *q, const float *invD,
-                       PcgState *st, int phase_a, int odd, double *part, hipStream_t s);
-void launch_add_correction(int n, double *u, const float *x, double scale, hipStream_t s);
+// state vectors of one evaluation point (magnet rows)
+struct StateV {
+    double *x = nullptr, *G = nullptr, *g = nullptr, *lam = nullptr;
+};
 
-void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,
-                          const double *u, const double *L, const double h[3], double *G, double *g, double *lam,
-                          const double *x0, const double *g0, const double *lam0, const double *d, double alpha,
-                          double *part, bool fp32, hipStream_t s);
-void launch_trial(int n, const double *x0, const double *d, double alpha, double *xt, hipStream_t s);
-void launch_finalize(const double *part, int nblk, int nslot, unsigned is_max, double *out, hipStream_t s);
+// per-instance scalar-potential CG state (device memory)
+struct PcgState {
+    double tol2, bb, rr, scale;
+    int done, iters, zero_u, active;
+};
 
-void launch_prec_init(int n, const double *gv, const double *invDex, const double *dscale, double *y, double *r,
-                      double *p, double *part, int *flags, hipStream_t s);
-void launch_prec_apply(const Sell &C, const double *m, const double *lam, const double *p, double *q, double *part,
-                       const int *flags, int phase, bool fp32, hipStream_t s);
-void launch_prec_update(int n, int j, const double *gv, const double *invDex, const double *dscale, double *y,
-                        double *r, const double *p, const double *q, const double *part_pq, const double *part_rz_prev,
-                        int rz_slot, double *part_out, int *flags, int phase, hipStream_t s);
-void launch_prec_pupdate(int n, const double *invDex, const double *dscale, double *p, const double *r,
-                         const double *part_init, const double *part_new, const double *part_old, int old_slot,
-                         int *flags, int phase, hipStream_t s);
-
+constexpr int kEvalParts = 10;  // Eloc, Ezee, Edemag, dF, dphi, |g|^2, max torque, max|g|_inf, max|m-x0|_inf, max|m|_inf
+unsigned eval_max_mask();
 constexpr int kDirParts = 6;
-void launch_dir_dots(int n, const double *g1, const double *g0, const double *y1, const double *d, double *part,
-                     int *nblk_out, hipStream_t s);
-void launch_dir_update(int n, const double *g1, const double *y1, double *d, const double *part_dots, int nblk_dots,
-                       int first, double *part_out, int *info, hipStream_t s);
+constexpr int kPcgSlots = 8;    // partial slots of the scalar-potential CG
 
-void launch_energy_split(const Sell &S, const double *m, double *part, bool fp32, hipStream_t s);
-void launch_mavg(int n, const double *m, const double *L, double *part, hipStream_t s);
-void launch_lambda(int n, const double *m, const double *G, double *lam, hipStream_t s);
+// --- operators (kernels.hip) ---
+void launch_spmv_block6(const Sell &C, const RowMap &M, const double *x, double *y, bool fp32, hipStream_t s);
+void launch_spmv_scalar(const Sell &A, const RowMap &M, const double *x, double *y, bool fp32, hipStream_t s);
+void launch_bmul(const Sell &B, const RowMap &MB, const int *act, const StateV *sv, const int *role, double *b,
+                 bool fp32, hipStream_t s);
+void launch_btmul(const Sell &Bt, const RowMap &M, const double *u, double *gout, bool fp32, hipStream_t s);
+
+// --- evaluation (kernels.hip) ---
+struct EvalLaunch {
+    const Sell *C, *S, *Bt;
+    const RowMap *M;
+    int cmode, use_demag;
+    const int *act, *role;     // per instance: active, which state (0 cur, 1 T, 2 C)
+    StateV st[3];              // cur, T, C
+    const double *u, *L, *h3, *d, *alpha;
+    double *part;
+    bool fp32;
+};
+void launch_trial(const RowMap &M, const int *act, const int *role, const StateV st[3], const double *d,
+                  const double *alpha, hipStream_t s);
+void launch_eval_epilogue(const EvalLaunch &e, hipStream_t s);
+void launch_finalize_inst(const RowMap &M, const double *part, int nslot, unsigned is_max, double *out,
+                          hipStream_t s);
+void launch_copy_state(const RowMap &M, const int *from, const StateV st[3], double *gprev, hipStream_t s);
+
+// --- preconditioner (kernels.hip) ---
+struct PrecLaunch {
+    const Sell *C;
+    const RowMap *M;
+    const int *act;
+    const double *m, *lam, *g, *invDex, *dscale;
+    double *y, *r, *p, *q;
+    double *part;              // 7 slots: INIT(2), PQ(1), RZ0(2), RZ1(2)
+    int *flags;                // per instance: {stop phase, iterations, exit reason, -}
+    bool fp32;
+};
+void launch_prec_init(const PrecLaunch &a, hipStream_t s);
+void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s);
+
+// --- direction (kernels.hip) ---
+void launch_dir(const RowMap &M, const int *act, const int *first, const double *g1, const double *g0,
+                const double *y1, double *d, double *part_dots, double *part_out, int *info, hipStream_t s);
+
+// --- misc (kernels.hip) ---
+void launch_energy_split(const Sell &S, const RowMap &M, const double *m, double *part, bool fp32, hipStream_t s);
+void launch_mavg(const RowMap &M, const double *m, const double *L, double *part, hipStream_t s);
+void launch_lambda(const RowMap &M, const double *m, const double *G, double *lam, hipStream_t s);
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
+void launch_fill(int64_t n, double *x, double v, hipStream_t s);
+
+// --- scalar-potential CG (poisson.hip) ---
+struct PcgLaunch {
+    const Sell *K;
+    const RowMap *M;
+    PcgState *st;              // per instance
+    double *part;              // kPcgSlots slots of M->nblk
+    double *u, *b, *r, *p0, *p1, *q;   // FP64 vectors
+    const double *invD;
+    float *x32, *r32, *p32a, *p32b, *q32;
+    const float *invD32;
+    const double *pin;         // per instance 4 doubles: FP32 rhs scale, inner tol^2 (<= 0: inactive), rn, -
+};
+void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, bool fp32_matrix, hipStream_t s);
+void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s);
+void launch_pcg_init32(const PcgLaunch &a, hipStream_t s);
+void launch_pcg_iter64(const PcgLaunch &a, int phase_a, int odd, hipStream_t s);
+void launch_pcg_iter32(const PcgLaunch &a, int phase_a, int odd, hipStream_t s);
+void launch_add_correction(const PcgLaunch &a, hipStream_t s);
 
 }  // namespace mmncg

@@ -1,24 +1,22 @@
-// HIP kernels (gfx950) of the micromagnetic PNCG hot path.
+// HIP kernels (gfx950) of the micromagnetic PNCG hot path, batched over
+// independent problem instances.
 //
 // Layout. Every sparse operator is stored SELL-64: a wavefront owns a slice of
 // 64 consecutive rows, one row per lane, and walks the slice's entries
 // column-major, so the k-th load of the wave reads 64 consecutive values and
-// 64 consecutive column indices (one 512 B / 256 B coalesced transaction).
-// Vectors on magnet nodes are node-major AoS doubles (x, y, z); vectors on
-// potential nodes are plain arrays. A block of 256 threads (4 waves) owns a
-// contiguous range of slices; blocks are renumbered so that each of the 8 XCDs
-// (blocks are dealt round-robin to XCDs) gets one contiguous eighth of the
-// rows, keeping the neighbour gathers of a row range inside one L2.
+// 64 consecutive column indices. Vectors on magnet nodes are node-major AoS
+// doubles (x, y, z); vectors on potential nodes are plain arrays. Instances
+// are concatenated, each padded to whole slices; a RowMap gives every block
+// one instance and a contiguous slice range of it (internal.h), so one launch
+// serves every instance and each instance's reductions read only its blocks.
 //
 // Reductions are deterministic: each block writes one partial per quantity
-// into a fixed slot, and the consumer (the next kernel, every block of it, or
-// a one-block finalize kernel) re-reduces the partials in a fixed order. No
-// floating-point atomics anywhere, so repeated runs are bitwise identical.
+// into a fixed slot and the consumer (a later kernel, every block of it, or a
+// one-block-per-instance finalize kernel) re-reduces them in a fixed order.
+// No floating-point atomics anywhere.
 //
 // Operator values may be stored in FP32 (template parameter V) for the
-// FP32-bulk mode; products and sums are always formed in FP64 except in the
-// FP32 inner Poisson CG, whose vectors are FP32 and whose dot products are
-// accumulated in FP64.
+// FP32-bulk mode; products and sums are formed in FP64.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -30,19 +28,26 @@ using namespace dev;
 
 namespace {
 
+constexpr int NW = kBlock / 64;  // waves per block of the magnet-row kernels
+
+__device__ __forceinline__ StateV pick(const StateV &a, const StateV &b, const StateV &c, int role) {
+    return role == 1 ? b : (role == 2 ? c : a);
+}
+
 // ---------------------------------------------------------------------------
-// plain operator kernels (used by the checking ABI and as building blocks)
+// plain operators (checking ABI and building blocks)
 // ---------------------------------------------------------------------------
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_spmv_block6(SV<V> A, const double *__restrict__ x, double *__restrict__ y) {
-    int s0, s1;
-    slice_range(A.nslices, s0, s1);
-    int ln = lane_id();
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+__global__ __launch_bounds__(kBlock) void k_spmv_block6(SV<V> A, RowMap M, const double *__restrict__ x,
+                                                        double *__restrict__ y) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int rend = M.rend[t.inst], ln = lane_id();
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o0, o1, o2;
         row_block6(A, s, ln, x, o0, o1, o2);
         int row = s * 64 + ln;
-        if (row < A.nrows) {
+        if (row < rend) {
             y[3 * (int64_t)row] = o0;
             y[3 * (int64_t)row + 1] = o1;
             y[3 * (int64_t)row + 2] = o2;
@@ -51,68 +56,46 @@ __global__ __launch_bounds__(kBlock) void k_spmv_block6(SV<V> A, const double *_
 }
 
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_spmv_scalar(SV<V> A, const double *__restrict__ x, double *__restrict__ y) {
-    int s0, s1;
-    slice_range(A.nslices, s0, s1);
-    int ln = lane_id();
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+__global__ __launch_bounds__(kBlock) void k_spmv_scalar(SV<V> A, RowMap M, const double *__restrict__ x,
+                                                        double *__restrict__ y) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int rend = M.rend[t.inst], ln = lane_id();
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o = row_scalar(A, s, ln, x);
         int row = s * 64 + ln;
-        if (row < A.nrows) y[row] = o;
+        if (row < rend) y[row] = o;
     }
 }
 
-// scalar rows applied to node-major 3-vectors: y_i = sum_k a_k x_{c_k} (each component)
+// b[row_out[r]] = sum_k B_k . m[col_k] over the free magnet nodes; every
+// other entry of b stays zero. m is the state the instance evaluates.
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_spmv_scalar3(SV<V> A, const double *__restrict__ x, double *__restrict__ y) {
-    int s0, s1;
-    slice_range(A.nslices, s0, s1);
-    int ln = lane_id();
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int64_t base = A.sptr[s];
-        int w = (int)((A.sptr[s + 1] - base) >> 6);
-        double o0 = 0, o1 = 0, o2 = 0;
-        for (int k = 0; k < w; ++k) {
-            int64_t e = base + 64 * k + ln;
-            double a = (double)A.val[e];
-            int64_t c = A.col[e];
-            o0 += a * x[3 * c];
-            o1 += a * x[3 * c + 1];
-            o2 += a * x[3 * c + 2];
-        }
-        int row = s * 64 + ln;
-        if (row < A.nrows) {
-            y[3 * (int64_t)row] = o0;
-            y[3 * (int64_t)row + 1] = o1;
-            y[3 * (int64_t)row + 2] = o2;
-        }
-    }
-}
-
-// b[row_out[r]] = sum_k B_k . m[col_k]  (divergence right-hand side; rows are
-// the free magnet nodes, every other entry of b stays zero)
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_bmul(SV<V> B, const double *__restrict__ m, double *__restrict__ b) {
-    int s0, s1;
-    slice_range(B.nslices, s0, s1);
-    int ln = lane_id();
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+__global__ __launch_bounds__(kBlock) void k_bmul(SV<V> B, RowMap MB, const int *__restrict__ act, StateV s0v,
+                                                 StateV s1v, StateV s2v, const int *__restrict__ role,
+                                                 double *__restrict__ b) {
+    Tile t = tile_of(MB);
+    if (t.inst < 0 || (act && !act[t.inst])) return;
+    const double *m = pick(s0v, s1v, s2v, role ? role[t.inst] : 0).x;
+    const int rend = MB.rend[t.inst], ln = lane_id();
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o = row_vec3_dot(B, s, ln, m);
         int row = s * 64 + ln;
-        if (row < B.nrows) b[B.row_out[row]] = o;
+        if (row < rend) b[B.row_out[row]] = o;
     }
 }
 
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_btmul(SV<V> Bt, const double *__restrict__ u, double *__restrict__ g) {
-    int s0, s1;
-    slice_range(Bt.nslices, s0, s1);
-    int ln = lane_id();
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+__global__ __launch_bounds__(kBlock) void k_btmul(SV<V> Bt, RowMap M, const double *__restrict__ u,
+                                                  double *__restrict__ g) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int rend = M.rend[t.inst], ln = lane_id();
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o0, o1, o2;
         row_vec3_scale(Bt, s, ln, u, o0, o1, o2);
         int row = s * 64 + ln;
-        if (row < Bt.nrows) {
+        if (row < rend) {
             g[3 * (int64_t)row] = o0;
             g[3 * (int64_t)row + 1] = o1;
             g[3 * (int64_t)row + 2] = o2;
@@ -121,40 +104,64 @@ __global__ __launch_bounds__(kBlock) void k_btmul(SV<V> Bt, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// eval epilogue: G = C m + B^T u - L h; lambda = m.G; g = G - lambda m;
-// torque = |g| / L; reductions for energies and the line search
-// partial slots: 0 Eloc, 1 Ezee, 2 Edemag, 3 dF, 4 dphi, 5 |g|^2, 6 max torque, 7 max |g|_inf,
-// 8 max |m-x0|_inf, 9 max |m|_inf
+// evaluation
 // ---------------------------------------------------------------------------
+// x_role = N(x_cur + alpha_i d) for the active instances
+__global__ __launch_bounds__(kBlock) void k_trial(RowMap M, const int *__restrict__ act, const int *__restrict__ role,
+                                                  StateV s0v, StateV s1v, StateV s2v, const double *__restrict__ d,
+                                                  const double *__restrict__ alpha) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst]) return;
+    const int rl = role[t.inst];
+    if (rl == 0) return;
+    double *xt = pick(s0v, s1v, s2v, rl).x;
+    const double *x0 = s0v.x;
+    const double a = alpha[t.inst];
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        int r = s * 64 + lane_id();
+        if (r < rend) {
+            int64_t r3 = 3 * (int64_t)r;
+            double w0 = x0[r3] + a * d[r3], w1 = x0[r3 + 1] + a * d[r3 + 1], w2 = x0[r3 + 2] + a * d[r3 + 2];
+            double nn = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+            xt[r3] = w0 / nn;
+            xt[r3 + 1] = w1 / nn;
+            xt[r3 + 2] = w2 / nn;
+        }
+    }
+}
+
+// G = C m + B^T u - L h; lambda = m.G; g = G - lambda m; torque |g| / L;
+// partials: 0 Eloc, 1 Ezee, 2 Edemag, 3 dF, 4 dphi, 5 |g|^2, 6 max torque,
+// 7 max |g|_inf, 8 max |m-x0|_inf, 9 max |m|_inf. With role != 0 the point is
+// a line-search trial relative to the current state (role 0) along d.
 constexpr unsigned kEvalMaxMask = (1u << 6) | (1u << 7) | (1u << 8) | (1u << 9);
 
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_eval_epilogue(
-    SV<V> C, SV<V> S, SV<V> Bt, int cmode, int use_demag, const double *__restrict__ m, const double *__restrict__ u,
-    const double *__restrict__ L, double hx, double hy, double hz, double *__restrict__ G, double *__restrict__ g,
-    double *__restrict__ lam, const double *__restrict__ x0, const double *__restrict__ g0v,
-    const double *__restrict__ lam0, const double *__restrict__ d, double alpha, double *__restrict__ part) {
-    __shared__ double sh[kWaves * 10];
-    int s0, s1;
-    slice_range(C.nslices, s0, s1);
-    int ln = lane_id();
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+__global__ __launch_bounds__(kBlock) void k_eval_epilogue(SV<V> C, SV<V> S, SV<V> Bt, RowMap M, int cmode,
+                                                          int use_demag, const int *__restrict__ act,
+                                                          const int *__restrict__ role, StateV s0v, StateV s1v,
+                                                          StateV s2v, const double *__restrict__ u,
+                                                          const double *__restrict__ L, const double *__restrict__ h3,
+                                                          const double *__restrict__ d,
+                                                          const double *__restrict__ alpha, double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || (act && !act[t.inst])) return;
+    __shared__ double sh[NW * kEvalParts];
+    const int rl = role ? role[t.inst] : 0;
+    const StateV sv = pick(s0v, s1v, s2v, rl);
+    const double *__restrict__ m = sv.x;
+    const double hx = h3[3 * t.inst], hy = h3[3 * t.inst + 1], hz = h3[3 * t.inst + 2];
+    const double a = (rl != 0) ? alpha[t.inst] : 0.0;
+    const int rend = M.rend[t.inst], ln = lane_id();
+    double acc[kEvalParts] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double c0 = 0, c1 = 0, c2 = 0;
         // cmode: 0 none, 1 exchange only (S), 2 anisotropy only (C - S), 3 both (C)
         if (cmode & 2) row_block6(C, s, ln, m, c0, c1, c2);
         if (cmode == 1 || cmode == 2) {
-            int64_t base = S.sptr[s];
-            int w = (int)((S.sptr[s + 1] - base) >> 6);
-            double e0 = 0, e1 = 0, e2 = 0;
-            for (int k = 0; k < w; ++k) {
-                int64_t e = base + 64 * k + ln;
-                double a = (double)S.val[e];
-                int64_t c = S.col[e];
-                e0 += a * m[3 * c];
-                e1 += a * m[3 * c + 1];
-                e2 += a * m[3 * c + 2];
-            }
+            double e0, e1, e2;
+            row_scalar3(S, s, ln, m, e0, e1, e2);
             if (cmode == 1) {
                 c0 = e0; c1 = e1; c2 = e2;
             } else {
@@ -163,18 +170,18 @@ __global__ __launch_bounds__(kBlock) void k_eval_epilogue(
         }
         double d0 = 0, d1 = 0, d2 = 0;
         if (use_demag) row_vec3_scale(Bt, s, ln, u, d0, d1, d2);
-        int a = s * 64 + ln;
-        if (a < C.nrows) {
-            int64_t a3 = 3 * (int64_t)a;
-            double m0 = m[a3], m1 = m[a3 + 1], m2 = m[a3 + 2];
-            double La = L[a];
-            double G0v = c0 + d0 - La * hx, G1v = c1 + d1 - La * hy, G2v = c2 + d2 - La * hz;
-            double l = m0 * G0v + m1 * G1v + m2 * G2v;
-            double g0 = G0v - l * m0, g1 = G1v - l * m1, g2 = G2v - l * m2;
+        int r = s * 64 + ln;
+        if (r < rend) {
+            int64_t r3 = 3 * (int64_t)r;
+            double m0 = m[r3], m1 = m[r3 + 1], m2 = m[r3 + 2];
+            double La = L[r];
+            double Gx = c0 + d0 - La * hx, Gy = c1 + d1 - La * hy, Gz = c2 + d2 - La * hz;
+            double l = m0 * Gx + m1 * Gy + m2 * Gz;
+            double g0 = Gx - l * m0, g1 = Gy - l * m1, g2 = Gz - l * m2;
             double gg = g0 * g0 + g1 * g1 + g2 * g2;
-            G[a3] = G0v; G[a3 + 1] = G1v; G[a3 + 2] = G2v;
-            g[a3] = g0; g[a3 + 1] = g1; g[a3 + 2] = g2;
-            lam[a] = l;
+            sv.G[r3] = Gx; sv.G[r3 + 1] = Gy; sv.G[r3 + 2] = Gz;
+            sv.g[r3] = g0; sv.g[r3 + 1] = g1; sv.g[r3 + 2] = g2;
+            sv.lam[r] = l;
             acc[0] += 0.5 * (m0 * c0 + m1 * c1 + m2 * c2);
             acc[1] += -La * (hx * m0 + hy * m1 + hz * m2);
             acc[2] += 0.5 * (m0 * d0 + m1 * d1 + m2 * d2);
@@ -182,82 +189,90 @@ __global__ __launch_bounds__(kBlock) void k_eval_epilogue(
             acc[6] = fmax(acc[6], sqrt(gg) / La);
             acc[7] = fmax(acc[7], fmax(fabs(g0), fmax(fabs(g1), fabs(g2))));
             acc[9] = fmax(acc[9], fmax(fabs(m0), fmax(fabs(m1), fabs(m2))));
-            if (x0) {
-                double xa = x0[a3], xb = x0[a3 + 1], xc = x0[a3 + 2];
-                double da = d[a3], db = d[a3 + 1], dc = d[a3 + 2];
-                double wa = xa + alpha * da, wb = xb + alpha * db, wc = xc + alpha * dc;
+            if (rl != 0) {
+                const double *x0 = s0v.x, *g0v = s0v.g, *lam0 = s0v.lam;
+                double xa = x0[r3], xb = x0[r3 + 1], xc = x0[r3 + 2];
+                double da = d[r3], db = d[r3 + 1], dc = d[r3 + 2];
+                double wa = xa + a * da, wb = xb + a * db, wc = xc + a * dc;
                 double wn = sqrt(wa * wa + wb * wb + wc * wc);
                 // energy difference between unit vectors in tangential form:
                 // 1/2 [dx.(g + g0) + 1/2 (lambda - lambda0) |dx|^2]  (= 1/2 dx.(G + G0))
                 double e0 = m0 - xa, e1 = m1 - xb, e2 = m2 - xc;
                 double dx2 = e0 * e0 + e1 * e1 + e2 * e2;
-                acc[3] += 0.5 * (e0 * (g0 + g0v[a3]) + e1 * (g1 + g0v[a3 + 1]) + e2 * (g2 + g0v[a3 + 2]) +
-                                 0.5 * (l - lam0[a]) * dx2);
+                acc[3] += 0.5 * (e0 * (g0 + g0v[r3]) + e1 * (g1 + g0v[r3 + 1]) + e2 * (g2 + g0v[r3 + 2]) +
+                                 0.5 * (l - lam0[r]) * dx2);
                 acc[4] += (g0 * da + g1 * db + g2 * dc) / wn;
-                acc[8] = fmax(acc[8], fmax(fabs(m0 - xa), fmax(fabs(m1 - xb), fabs(m2 - xc))));
+                acc[8] = fmax(acc[8], fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
             }
         }
     }
-    write_partials<10>(acc, kEvalMaxMask, part, sh);
+    write_part<kEvalParts, NW>(acc, kEvalMaxMask, part, M.nblk, t.b, sh);
 }
 
-// x_t = N(x0 + alpha d)
-__global__ __launch_bounds__(kBlock) void k_trial(int n, const double *__restrict__ x0, const double *__restrict__ d,
-                                                  double alpha, double *__restrict__ xt) {
-    int a = blockIdx.x * kBlock + threadIdx.x;
-    if (a >= n) return;
-    int64_t a3 = 3 * (int64_t)a;
-    double w0 = x0[a3] + alpha * d[a3], w1 = x0[a3 + 1] + alpha * d[a3 + 1], w2 = x0[a3 + 2] + alpha * d[a3 + 2];
-    double nn = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    xt[a3] = w0 / nn;
-    xt[a3 + 1] = w1 / nn;
-    xt[a3 + 2] = w2 / nn;
-}
-
-// one block: out[q] = sum/max of partial slot q over nblk
-__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ part, int nblk, int nslot, unsigned is_max,
-                                                     double *__restrict__ out) {
-    __shared__ double sh[kWaves];
+// one block per instance: out[i * nslot + q] = reduction of slot q over the instance's blocks
+__global__ __launch_bounds__(kBlock) void k_finalize_inst(const double *__restrict__ part, int stride,
+                                                          const int *__restrict__ ipb, int nslot, unsigned is_max,
+                                                          double *__restrict__ out) {
+    __shared__ double sh[NW];
+    const int i = blockIdx.x;
+    const int b0 = ipb[i], b1 = ipb[i + 1];
     for (int q = 0; q < nslot; ++q) {
-        bool mx = (is_max >> q) & 1;
-        double v = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += kBlock) {
-            double x = part[q * kMaxPartials + i];
-            v = mx ? fmax(v, x) : v + x;
+        double v[1];
+        read_part<1, NW>(part + (size_t)q * stride, stride, b0, b1, (is_max >> q) & 1, v, sh);
+        if (threadIdx.x == 0) out[(size_t)i * nslot + q] = v[0];
+    }
+}
+
+// state 0 <- state from[i] (1 or 2) for the instances that accepted a trial;
+// the projected gradient of the replaced state is kept in gprev (beta*ZA needs
+// g of both iterates)
+__global__ __launch_bounds__(kBlock) void k_copy_state(RowMap M, const int *__restrict__ from, StateV s0v, StateV s1v,
+                                                       StateV s2v, double *__restrict__ gprev) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int f = from[t.inst];
+    if (f == 0) return;
+    const StateV src = pick(s0v, s1v, s2v, f);
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        int r = s * 64 + lane_id();
+        if (r < rend) {
+            int64_t r3 = 3 * (int64_t)r;
+            for (int c = 0; c < 3; ++c) {
+                gprev[r3 + c] = s0v.g[r3 + c];
+                s0v.x[r3 + c] = src.x[r3 + c];
+                s0v.G[r3 + c] = src.G[r3 + c];
+                s0v.g[r3 + c] = src.g[r3 + c];
+            }
+            s0v.lam[r] = src.lam[r];
         }
-        v = mx ? wave_max(v) : wave_sum(v);
-        if (lane_id() == 0) sh[wave_id()] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = sh[0];
-            for (int w = 1; w < kWaves; ++w) t = mx ? fmax(t, sh[w]) : t + sh[w];
-            out[q] = t;
-        }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // inner PCG on the preconditioner: P v = C v - (m.(C v)) m - lambda v
-// partial slots: INIT (rz, gg); PQ (1); RZ ring (rz, rr) x 2
-// flags: [0] stop, [1] iterations, [2] exit reason (1 li1, 2 li2, 3 li3)
+// partial slots: INIT 0-1 (r.z, g.g), PQ 2, RZ0 3-4, RZ1 5-6 (r.z, r.r)
+// flags per instance (4 ints): stop phase, iterations, exit reason (1 li1, 2 li2, 3 li3)
 // ---------------------------------------------------------------------------
+constexpr int kPrINIT = 0, kPrPQ = 2, kPrRZ0 = 3, kPrRZ1 = 5;
+
 __device__ __forceinline__ double jacobi_inv(const double *invDex, const double *dscale, int a) {
     return dscale ? invDex[a] / dscale[a] : invDex[a];
 }
 
-__global__ __launch_bounds__(kBlock) void k_prec_init(int n, int nslices, const double *__restrict__ gv,
-                                                      const double *__restrict__ invDex,
+__global__ __launch_bounds__(kBlock) void k_prec_init(RowMap M, const int *__restrict__ act,
+                                                      const double *__restrict__ gv, const double *__restrict__ invDex,
                                                       const double *__restrict__ dscale, double *__restrict__ y,
                                                       double *__restrict__ r, double *__restrict__ p,
                                                       double *__restrict__ part, int *__restrict__ flags) {
-    __shared__ double sh[kWaves * 2];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst]) return;
+    __shared__ double sh[NW * 2];
+    const int rend = M.rend[t.inst];
     double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int a = s * 64 + lane_id();
-        if (a < n) {
+        if (a < rend) {
             double iD = jacobi_inv(invDex, dscale, a);
             for (int c = 0; c < 3; ++c) {
                 int64_t i = 3 * (int64_t)a + c;
@@ -270,30 +285,30 @@ __global__ __launch_bounds__(kBlock) void k_prec_init(int n, int nslices, const 
             }
         }
     }
-    write_partials<2>(acc, 0u, part, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        flags[0] = 0;
-        flags[1] = 0;
-        flags[2] = 1;
+    write_part<2, NW>(acc, 0u, part + (size_t)kPrINIT * M.nblk, M.nblk, t.b, sh);
+    if (t.b == M.ipb[t.inst] && threadIdx.x == 0) {
+        flags[4 * t.inst] = 0;
+        flags[4 * t.inst + 1] = 0;
+        flags[4 * t.inst + 2] = 1;
     }
 }
 
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, const double *__restrict__ m,
-                                                       const double *__restrict__ lam, const double *__restrict__ p,
-                                                       double *__restrict__ q, double *__restrict__ part,
-                                                       const int *__restrict__ flags, int phase) {
-    if (stopped_before(flags, phase)) return;
-    __shared__ double sh[kWaves];
-    int s0, s1;
-    slice_range(C.nslices, s0, s1);
-    int ln = lane_id();
+__global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, RowMap M, const int *__restrict__ act,
+                                                       const double *__restrict__ m, const double *__restrict__ lam,
+                                                       const double *__restrict__ p, double *__restrict__ q,
+                                                       double *__restrict__ part, const int *__restrict__ flags,
+                                                       int phase) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst] || stopped_before(flags + 4 * t.inst, phase)) return;
+    __shared__ double sh[NW];
+    const int rend = M.rend[t.inst], ln = lane_id();
     double acc[1] = {0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double c0, c1, c2;
         row_block6(C, s, ln, p, c0, c1, c2);
         int a = s * 64 + ln;
-        if (a < C.nrows) {
+        if (a < rend) {
             int64_t a3 = 3 * (int64_t)a;
             double m0 = m[a3], m1 = m[a3 + 1], m2 = m[a3 + 2];
             double mc = m0 * c0 + m1 * c1 + m2 * c2;
@@ -306,45 +321,45 @@ __global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, const double *__
             acc[0] += p0 * q0 + p1 * q1 + p2 * q2;
         }
     }
-    write_partials<1>(acc, 0u, part, sh);
+    write_part<1, NW>(acc, 0u, part + (size_t)kPrPQ * M.nblk, M.nblk, t.b, sh);
 }
 
 // (li2) if p.Pp <= 0: stop (y = g when j == 0); else alpha step; partials (r.z, r.r)
-__global__ __launch_bounds__(kBlock) void k_prec_update(int n, int nslices, int j, const double *__restrict__ gv,
+__global__ __launch_bounds__(kBlock) void k_prec_update(RowMap M, const int *__restrict__ act, int j,
+                                                        const double *__restrict__ gv,
                                                         const double *__restrict__ invDex,
                                                         const double *__restrict__ dscale, double *__restrict__ y,
                                                         double *__restrict__ r, const double *__restrict__ p,
-                                                        const double *__restrict__ q,
-                                                        const double *__restrict__ part_pq,
-                                                        const double *__restrict__ part_rz_prev, int rz_slot,
-                                                        double *__restrict__ part_out, int nblk,
+                                                        const double *__restrict__ q, double *__restrict__ part,
                                                         int *__restrict__ flags, int phase) {
-    if (stopped_before(flags, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double pq[1], rz[2];
-    read_partials<1>(part_pq, nblk, 0u, pq, sh);
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst] || stopped_before(flags + 4 * t.inst, phase)) return;
+    __shared__ double sh[NW * 2];
+    const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
+    double pq[1], rz[1];
+    read_part<1, NW>(part + (size_t)kPrPQ * S, S, b0, b1, 0u, pq, sh);
+    const int rend = M.rend[t.inst];
     if (!(pq[0] > 0.0)) {
         if (j == 0)
-            for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+            for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
                 int a = s * 64 + lane_id();
-                if (a < n)
+                if (a < rend)
                     for (int c = 0; c < 3; ++c) y[3 * (int64_t)a + c] = gv[3 * (int64_t)a + c];
             }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            flags[0] = phase;
-            flags[2] = 2;
+        if (t.b == b0 && threadIdx.x == 0) {
+            flags[4 * t.inst] = phase;
+            flags[4 * t.inst + 2] = 2;
         }
         return;
     }
-    // rz of the previous step: slot rz_slot of part_rz_prev (the INIT layout has rz in slot 0 too)
-    read_partials<2>(part_rz_prev, nblk, 0u, rz, sh);
-    double alpha = rz[rz_slot] / pq[0];
+    const int prev = (j == 0) ? kPrINIT : ((j & 1) ? kPrRZ1 : kPrRZ0);
+    const int next = ((j + 1) & 1) ? kPrRZ1 : kPrRZ0;
+    read_part<1, NW>(part + (size_t)prev * S, S, b0, b1, 0u, rz, sh);
+    const double alpha = rz[0] / pq[0];
     double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int a = s * 64 + lane_id();
-        if (a < n) {
+        if (a < rend) {
             double iD = jacobi_inv(invDex, dscale, a);
             for (int c = 0; c < 3; ++c) {
                 int64_t i = 3 * (int64_t)a + c;
@@ -356,39 +371,40 @@ __global__ __launch_bounds__(kBlock) void k_prec_update(int n, int nslices, int 
             }
         }
     }
-    write_partials<2>(acc, 0u, part_out, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) flags[1] = j + 1;
+    write_part<2, NW>(acc, 0u, part + (size_t)next * S, S, t.b, sh);
+    if (t.b == b0 && threadIdx.x == 0) flags[4 * t.inst + 1] = j + 1;
 }
 
 // (li3) |r| < min(0.5, sqrt(|g|)) |g|: stop; else p = D^-1 r + beta p
-__global__ __launch_bounds__(kBlock) void k_prec_pupdate(int n, int nslices, const double *__restrict__ invDex,
+__global__ __launch_bounds__(kBlock) void k_prec_pupdate(RowMap M, const int *__restrict__ act, int j,
+                                                         const double *__restrict__ invDex,
                                                          const double *__restrict__ dscale, double *__restrict__ p,
-                                                         const double *__restrict__ r,
-                                                         const double *__restrict__ part_init,
-                                                         const double *__restrict__ part_new,
-                                                         const double *__restrict__ part_old, int old_slot, int nblk,
+                                                         const double *__restrict__ r, const double *__restrict__ part,
                                                          int *__restrict__ flags, int phase) {
-    if (stopped_before(flags, phase)) return;
-    __shared__ double sh[kWaves * 2];
-    double ini[2], nw[2], od[2];
-    read_partials<2>(part_init, nblk, 0u, ini, sh);
-    read_partials<2>(part_new, nblk, 0u, nw, sh);
-    double gn = sqrt(ini[1]);
-    double eta = fmin(0.5, sqrt(gn));
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst] || stopped_before(flags + 4 * t.inst, phase)) return;
+    __shared__ double sh[NW * 2];
+    const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
+    const int prev = (j == 0) ? kPrINIT : ((j & 1) ? kPrRZ1 : kPrRZ0);
+    const int next = ((j + 1) & 1) ? kPrRZ1 : kPrRZ0;
+    double ini[2], nw[2], od[1];
+    read_part<2, NW>(part + (size_t)kPrINIT * S, S, b0, b1, 0u, ini, sh);
+    read_part<2, NW>(part + (size_t)next * S, S, b0, b1, 0u, nw, sh);
+    const double gn = sqrt(ini[1]);
+    const double eta = fmin(0.5, sqrt(gn));
     if (sqrt(nw[1]) < eta * gn) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            flags[0] = phase;
-            flags[2] = 3;
+        if (t.b == b0 && threadIdx.x == 0) {
+            flags[4 * t.inst] = phase;
+            flags[4 * t.inst + 2] = 3;
         }
         return;
     }
-    read_partials<2>(part_old, nblk, 0u, od, sh);
-    double beta = nw[0] / od[old_slot];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    read_part<1, NW>(part + (size_t)prev * S, S, b0, b1, 0u, od, sh);
+    const double beta = nw[0] / od[0];
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int a = s * 64 + lane_id();
-        if (a < n) {
+        if (a < rend) {
             double iD = jacobi_inv(invDex, dscale, a);
             for (int c = 0; c < 3; ++c) {
                 int64_t i = 3 * (int64_t)a + c;
@@ -399,71 +415,81 @@ __global__ __launch_bounds__(kBlock) void k_prec_pupdate(int n, int nslices, con
 }
 
 // ---------------------------------------------------------------------------
-// direction: dots then update with beta*ZA and the descent safeguard
+// direction: dots, then beta*ZA with the descent safeguard. first[i] bits:
+// 1 = first direction of a field or a restart (no beta term), 2 = take g in
+// place of the preconditioned y (no preconditioner, or steepest descent)
 // dot slots: 0 <g1-g0,y1>, 1 <g1-g0,d>, 2 <g1,y1>, 3 <g1,d>, 4 <g1-g0,g1>, 5 <g1,g1>
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_dir_dots(int n3, int nslices3, const double *__restrict__ g1,
+__global__ __launch_bounds__(kBlock) void k_dir_dots(RowMap M, const int *__restrict__ act,
+                                                     const int *__restrict__ first, const double *__restrict__ g1,
                                                      const double *__restrict__ g0, const double *__restrict__ y1,
                                                      const double *__restrict__ d, double *__restrict__ part) {
-    __shared__ double sh[kWaves * 6];
-    int s0, s1;
-    slice_range(nslices3, s0, s1);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int i = s * 64 + lane_id();
-        if (i < n3) {
-            double a = g1[i], b = g0 ? g0[i] : 0.0, y = y1[i], dd = d ? d[i] : 0.0;
-            double dg = a - b;
-            acc[0] += dg * y;
-            acc[1] += dg * dd;
-            acc[2] += a * y;
-            acc[3] += a * dd;
-            acc[4] += dg * a;
-            acc[5] += a * a;
-        }
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst]) return;
+    __shared__ double sh[NW * kDirParts];
+    const int fm = first[t.inst];
+    const bool fst = (fm & 1) != 0;
+    const double *__restrict__ yv = (fm & 2) ? g1 : y1;
+    const int rend = M.rend[t.inst];
+    double acc[kDirParts] = {0, 0, 0, 0, 0, 0};
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        int a = s * 64 + lane_id();
+        if (a < rend)
+            for (int c = 0; c < 3; ++c) {
+                int64_t i = 3 * (int64_t)a + c;
+                double gn = g1[i], go = fst ? 0.0 : g0[i], yy = yv[i], dd = fst ? 0.0 : d[i];
+                double dg = gn - go;
+                acc[0] += dg * yy;
+                acc[1] += dg * dd;
+                acc[2] += gn * yy;
+                acc[3] += gn * dd;
+                acc[4] += dg * gn;
+                acc[5] += gn * gn;
+            }
     }
-    write_partials<6>(acc, 0u, part, sh);
+    write_part<kDirParts, NW>(acc, 0u, part, M.nblk, t.b, sh);
 }
 
-// mode written to info[0]: 0 -y+beta d, 1 fallback -g+beta2 d, 2 -g
-// partial slots out: 0 <g1,dnew>, 1 max |dnew_a| (per node norm) -- per node needs the 3 components,
-// so this kernel runs over nodes
-__global__ __launch_bounds__(kBlock) void k_dir_update(int n, int nslices, const double *__restrict__ g1,
+// info[i] = mode: 0 -y + beta d, 1 fallback -g + beta2 d, 2 -g; partials out: <g1,dnew>, max |dnew_a|
+__global__ __launch_bounds__(kBlock) void k_dir_update(RowMap M, const int *__restrict__ act,
+                                                       const int *__restrict__ first, const double *__restrict__ g1,
                                                        const double *__restrict__ y1, double *__restrict__ d,
-                                                       const double *__restrict__ part_dots, int nblk_dots, int first,
+                                                       const double *__restrict__ part_dots,
                                                        double *__restrict__ part_out, int *__restrict__ info) {
-    __shared__ double sh[kWaves * 6];
-    double t[6];
-    read_partials<6>(part_dots, nblk_dots, 0u, t, sh);
-    double cy, cd, cg;  // d_new = cy * y1 + cd * d + cg * g1
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !act[t.inst]) return;
+    __shared__ double sh[NW * kDirParts];
+    double tt[kDirParts];
+    read_part<kDirParts, NW>(part_dots, M.nblk, M.ipb[t.inst], M.ipb[t.inst + 1], 0u, tt, sh);
+    const int fm = first[t.inst];
+    const double *__restrict__ yv = (fm & 2) ? g1 : y1;
+    double cy, cd, cg;  // d_new = cy y + cd d + cg g1
     int mode;
-    if (first) {
-        // initial direction -y; if not descent, -g
-        if (-t[2] < 0.0) { cy = -1; cd = 0; cg = 0; mode = 0; }
+    if (fm & 1) {
+        if (-tt[2] < 0.0) { cy = -1; cd = 0; cg = 0; mode = 0; }
         else { cy = 0; cd = 0; cg = -1; mode = 2; }
     } else {
-        double num = t[0], den = t[1];
+        double num = tt[0], den = tt[1];
         double beta = (num > 0.0 && den > 0.0) ? num / den : 0.0;
-        double dpn = -t[2] + beta * t[3];
+        double dpn = -tt[2] + beta * tt[3];
         if (dpn < 0.0) { cy = -1; cd = beta; cg = 0; mode = 0; }
         else {
-            double num2 = t[4];
+            double num2 = tt[4];
             double beta2 = (num2 > 0.0 && den > 0.0) ? num2 / den : 0.0;
-            double dpn2 = -t[5] + beta2 * t[3];
+            double dpn2 = -tt[5] + beta2 * tt[3];
             if (dpn2 < 0.0) { cy = 0; cd = beta2; cg = -1; mode = 1; }
             else { cy = 0; cd = 0; cg = -1; mode = 2; }
         }
     }
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+    const int rend = M.rend[t.inst];
     double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int a = s * 64 + lane_id();
-        if (a < n) {
+        if (a < rend) {
             double nn = 0.0;
             for (int c = 0; c < 3; ++c) {
                 int64_t i = 3 * (int64_t)a + c;
-                double dv = (cd != 0.0 ? cd * d[i] : 0.0) + cy * y1[i] + cg * g1[i];
+                double dv = (cd != 0.0 ? cd * d[i] : 0.0) + cy * yv[i] + cg * g1[i];
                 d[i] = dv;
                 acc[0] += g1[i] * dv;
                 nn += dv * dv;
@@ -471,46 +497,40 @@ __global__ __launch_bounds__(kBlock) void k_dir_update(int n, int nslices, const
             acc[1] = fmax(acc[1], sqrt(nn));
         }
     }
-    write_partials<2>(acc, 2u, part_out, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) info[0] = mode;
+    write_part<2, NW>(acc, 2u, part_out, M.nblk, t.b, sh);
+    if (t.b == M.ipb[t.inst] && threadIdx.x == 0) info[t.inst] = mode;
 }
 
-// energy split: 1/2 m.(S m)  (exchange part)
+// exchange part of the energy: 1/2 m.(S m)
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_energy_split(SV<V> S, const double *__restrict__ m, double *__restrict__ part) {
-    __shared__ double sh[kWaves];
-    int s0, s1;
-    slice_range(S.nslices, s0, s1);
-    int ln = lane_id();
+__global__ __launch_bounds__(kBlock) void k_energy_split(SV<V> S, RowMap M, const double *__restrict__ m,
+                                                         double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    __shared__ double sh[NW];
+    const int rend = M.rend[t.inst], ln = lane_id();
     double acc[1] = {0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
-        int64_t base = S.sptr[s];
-        int w = (int)((S.sptr[s + 1] - base) >> 6);
-        double e0 = 0, e1 = 0, e2 = 0;
-        for (int k = 0; k < w; ++k) {
-            int64_t e = base + 64 * k + ln;
-            double a = (double)S.val[e];
-            int64_t c = S.col[e];
-            e0 += a * m[3 * c];
-            e1 += a * m[3 * c + 1];
-            e2 += a * m[3 * c + 2];
-        }
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        double e0, e1, e2;
+        row_scalar3(S, s, ln, m, e0, e1, e2);
         int a = s * 64 + ln;
-        if (a < S.nrows) acc[0] += 0.5 * (m[3 * (int64_t)a] * e0 + m[3 * (int64_t)a + 1] * e1 + m[3 * (int64_t)a + 2] * e2);
+        if (a < rend)
+            acc[0] += 0.5 * (m[3 * (int64_t)a] * e0 + m[3 * (int64_t)a + 1] * e1 + m[3 * (int64_t)a + 2] * e2);
     }
-    write_partials<1>(acc, 0u, part, sh);
+    write_part<1, NW>(acc, 0u, part, M.nblk, t.b, sh);
 }
 
-// mean magnetization sums (L m, L) and max | |m_a| - 1 |
-__global__ __launch_bounds__(kBlock) void k_mavg(int n, int nslices, const double *__restrict__ m,
-                                                 const double *__restrict__ L, double *__restrict__ part) {
-    __shared__ double sh[kWaves * 5];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+// sums (L m, L) and max | |m_a| - 1 | (NaN counts as a huge deviation)
+__global__ __launch_bounds__(kBlock) void k_mavg(RowMap M, const double *__restrict__ m, const double *__restrict__ L,
+                                                 double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    __shared__ double sh[NW * 5];
+    const int rend = M.rend[t.inst];
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kWaves) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int a = s * 64 + lane_id();
-        if (a < n) {
+        if (a < rend) {
             int64_t a3 = 3 * (int64_t)a;
             double La = L[a];
             double m0 = m[a3], m1 = m[a3 + 1], m2 = m[a3 + 2];
@@ -522,16 +542,22 @@ __global__ __launch_bounds__(kBlock) void k_mavg(int n, int nslices, const doubl
             acc[4] = fmax(acc[4], (nn == nn) ? fabs(nn - 1.0) : 1e300);
         }
     }
-    write_partials<5>(acc, 1u << 4, part, sh);
+    write_part<5, NW>(acc, 1u << 4, part, M.nblk, t.b, sh);
 }
 
 // lambda_a = m_a . G_a
-__global__ __launch_bounds__(kBlock) void k_lambda(int n, const double *__restrict__ m, const double *__restrict__ G,
-                                                   double *__restrict__ lam) {
-    int a = blockIdx.x * kBlock + threadIdx.x;
-    if (a >= n) return;
-    int64_t a3 = 3 * (int64_t)a;
-    lam[a] = m[a3] * G[a3] + m[a3 + 1] * G[a3 + 1] + m[a3 + 2] * G[a3 + 2];
+__global__ __launch_bounds__(kBlock) void k_lambda(RowMap M, const double *__restrict__ m,
+                                                   const double *__restrict__ G, double *__restrict__ lam) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        int a = s * 64 + lane_id();
+        if (a < rend) {
+            int64_t a3 = 3 * (int64_t)a;
+            lam[a] = m[a3] * G[a3] + m[a3 + 1] * G[a3 + 1] + m[a3 + 2] * G[a3 + 2];
+        }
+    }
 }
 
 __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restrict__ y) {
@@ -539,137 +565,111 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restr
     if (i < n) y[i] = (float)x[i];
 }
 
-inline int nslices_of(int n) { return (n + 63) / 64; }
+__global__ void k_fill(int64_t n, double *__restrict__ x, double v) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = v;
+}
 
 }  // namespace
 
 // ===========================================================================
 // launchers
 // ===========================================================================
-int grid_for_rows(int nrows) {
-    int ns = nslices_of(nrows);
-    int g = (ns + kWaves - 1) / kWaves;
-    if (g < 1) g = 1;
-    if (g > kMaxPartials) g = kMaxPartials;
-    if (g >= 8) g = (g + 7) & ~7;
-    if (g > kMaxPartials) g = kMaxPartials;
-    return g;
-}
-
-
-void launch_spmv_block6(const Sell &C, const double *x, double *y, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(C.nrows);
-    if (fp32) hipLaunchKernelGGL(k_spmv_block6<float>, dim3(g), dim3(kBlock), 0, s, view<float>(C), x, y);
-    else hipLaunchKernelGGL(k_spmv_block6<double>, dim3(g), dim3(kBlock), 0, s, view<double>(C), x, y);
-}
-void launch_spmv_scalar(const Sell &A, const double *x, double *y, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(A.nrows);
-    if (fp32) hipLaunchKernelGGL(k_spmv_scalar<float>, dim3(g), dim3(kBlock), 0, s, view<float>(A), x, y);
-    else hipLaunchKernelGGL(k_spmv_scalar<double>, dim3(g), dim3(kBlock), 0, s, view<double>(A), x, y);
-}
-void launch_spmv_scalar3(const Sell &A, const double *x, double *y, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(A.nrows);
-    if (fp32) hipLaunchKernelGGL(k_spmv_scalar3<float>, dim3(g), dim3(kBlock), 0, s, view<float>(A), x, y);
-    else hipLaunchKernelGGL(k_spmv_scalar3<double>, dim3(g), dim3(kBlock), 0, s, view<double>(A), x, y);
-}
-void launch_bmul(const Sell &B, const double *m, double *b, bool fp32, hipStream_t s) {
-    if (B.nrows == 0) return;
-    int g = grid_for_rows(B.nrows);
-    if (fp32) hipLaunchKernelGGL(k_bmul<float>, dim3(g), dim3(kBlock), 0, s, view<float>(B), m, b);
-    else hipLaunchKernelGGL(k_bmul<double>, dim3(g), dim3(kBlock), 0, s, view<double>(B), m, b);
-}
-void launch_btmul(const Sell &Bt, const double *u, double *gout, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(Bt.nrows);
-    if (fp32) hipLaunchKernelGGL(k_btmul<float>, dim3(g), dim3(kBlock), 0, s, view<float>(Bt), u, gout);
-    else hipLaunchKernelGGL(k_btmul<double>, dim3(g), dim3(kBlock), 0, s, view<double>(Bt), u, gout);
-}
-
-void launch_eval_epilogue(const Sell &C, const Sell &S, const Sell &Bt, int cmode, int use_demag, const double *m,
-                          const double *u, const double *L, const double h[3], double *G, double *g, double *lam,
-                          const double *x0, const double *g0, const double *lam0, const double *d, double alpha,
-                          double *part, bool fp32, hipStream_t s) {
-    int gr = grid_for_rows(C.nrows);
-    if (fp32)
-        hipLaunchKernelGGL(k_eval_epilogue<float>, dim3(gr), dim3(kBlock), 0, s, view<float>(C), view<float>(S),
-                           view<float>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, g0, lam0, d,
-                           alpha, part);
-    else
-        hipLaunchKernelGGL(k_eval_epilogue<double>, dim3(gr), dim3(kBlock), 0, s, view<double>(C), view<double>(S),
-                           view<double>(Bt), cmode, use_demag, m, u, L, h[0], h[1], h[2], G, g, lam, x0, g0, lam0, d,
-                           alpha, part);
-}
 unsigned eval_max_mask() { return kEvalMaxMask; }
 
-void launch_trial(int n, const double *x0, const double *d, double alpha, double *xt, hipStream_t s) {
-    int g = (n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_trial, dim3(g), dim3(kBlock), 0, s, n, x0, d, alpha, xt);
+void launch_spmv_block6(const Sell &C, const RowMap &M, const double *x, double *y, bool fp32, hipStream_t s) {
+    if (fp32) hipLaunchKernelGGL(k_spmv_block6<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(C), M, x, y);
+    else hipLaunchKernelGGL(k_spmv_block6<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(C), M, x, y);
 }
-void launch_finalize(const double *part, int nblk, int nslot, unsigned is_max, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, part, nblk, nslot, is_max, out);
+void launch_spmv_scalar(const Sell &A, const RowMap &M, const double *x, double *y, bool fp32, hipStream_t s) {
+    if (fp32) hipLaunchKernelGGL(k_spmv_scalar<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(A), M, x, y);
+    else hipLaunchKernelGGL(k_spmv_scalar<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(A), M, x, y);
 }
-
-void launch_prec_init(int n, const double *gv, const double *invDex, const double *dscale, double *y, double *r,
-                      double *p, double *part, int *flags, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_prec_init, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), gv, invDex, dscale, y, r, p, part,
-                       flags);
-}
-void launch_prec_apply(const Sell &C, const double *m, const double *lam, const double *p, double *q, double *part,
-                       const int *flags, int phase, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(C.nrows);
+void launch_bmul(const Sell &B, const RowMap &MB, const int *act, const StateV *sv, const int *role, double *b,
+                 bool fp32, hipStream_t s) {
+    if (B.nrows == 0) return;
     if (fp32)
-        hipLaunchKernelGGL(k_prec_apply<float>, dim3(g), dim3(kBlock), 0, s, view<float>(C), m, lam, p, q, part, flags,
-                           phase);
+        hipLaunchKernelGGL(k_bmul<float>, dim3(MB.nblk), dim3(kBlock), 0, s, view<float>(B), MB, act, sv[0], sv[1],
+                           sv[2], role, b);
     else
-        hipLaunchKernelGGL(k_prec_apply<double>, dim3(g), dim3(kBlock), 0, s, view<double>(C), m, lam, p, q, part,
-                           flags, phase);
+        hipLaunchKernelGGL(k_bmul<double>, dim3(MB.nblk), dim3(kBlock), 0, s, view<double>(B), MB, act, sv[0], sv[1],
+                           sv[2], role, b);
 }
-void launch_prec_update(int n, int j, const double *gv, const double *invDex, const double *dscale, double *y,
-                        double *r, const double *p, const double *q, const double *part_pq, const double *part_rz_prev,
-                        int rz_slot, double *part_out, int *flags, int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_prec_update, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), j, gv, invDex, dscale, y, r, p, q,
-                       part_pq, part_rz_prev, rz_slot, part_out, g, flags, phase);
-}
-void launch_prec_pupdate(int n, const double *invDex, const double *dscale, double *p, const double *r,
-                         const double *part_init, const double *part_new, const double *part_old, int old_slot,
-                         int *flags, int phase, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_prec_pupdate, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), invDex, dscale, p, r, part_init,
-                       part_new, part_old, old_slot, g, flags, phase);
+void launch_btmul(const Sell &Bt, const RowMap &M, const double *u, double *gout, bool fp32, hipStream_t s) {
+    if (fp32) hipLaunchKernelGGL(k_btmul<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(Bt), M, u, gout);
+    else hipLaunchKernelGGL(k_btmul<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(Bt), M, u, gout);
 }
 
-void launch_dir_dots(int n, const double *g1, const double *g0, const double *y1, const double *d, double *part,
-                     int *nblk_out, hipStream_t s) {
-    int n3 = 3 * n;
-    int g = grid_for_rows(n3);
-    *nblk_out = g;
-    hipLaunchKernelGGL(k_dir_dots, dim3(g), dim3(kBlock), 0, s, n3, nslices_of(n3), g1, g0, y1, d, part);
+void launch_trial(const RowMap &M, const int *act, const int *role, const StateV st[3], const double *d,
+                  const double *alpha, hipStream_t s) {
+    hipLaunchKernelGGL(k_trial, dim3(M.nblk), dim3(kBlock), 0, s, M, act, role, st[0], st[1], st[2], d, alpha);
 }
-void launch_dir_update(int n, const double *g1, const double *y1, double *d, const double *part_dots, int nblk_dots,
-                       int first, double *part_out, int *info, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_dir_update, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), g1, y1, d, part_dots, nblk_dots,
-                       first, part_out, info);
+void launch_eval_epilogue(const EvalLaunch &e, hipStream_t s) {
+    const RowMap &M = *e.M;
+    if (e.fp32)
+        hipLaunchKernelGGL(k_eval_epilogue<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(*e.C),
+                           view<float>(*e.S), view<float>(*e.Bt), M, e.cmode, e.use_demag, e.act, e.role, e.st[0],
+                           e.st[1], e.st[2], e.u, e.L, e.h3, e.d, e.alpha, e.part);
+    else
+        hipLaunchKernelGGL(k_eval_epilogue<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(*e.C),
+                           view<double>(*e.S), view<double>(*e.Bt), M, e.cmode, e.use_demag, e.act, e.role, e.st[0],
+                           e.st[1], e.st[2], e.u, e.L, e.h3, e.d, e.alpha, e.part);
+}
+void launch_finalize_inst(const RowMap &M, const double *part, int nslot, unsigned is_max, double *out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_inst, dim3(M.ninst), dim3(kBlock), 0, s, part, M.nblk, M.ipb, nslot, is_max, out);
+}
+void launch_copy_state(const RowMap &M, const int *from, const StateV st[3], double *gprev, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_state, dim3(M.nblk), dim3(kBlock), 0, s, M, from, st[0], st[1], st[2], gprev);
 }
 
-void launch_energy_split(const Sell &S, const double *m, double *part, bool fp32, hipStream_t s) {
-    int g = grid_for_rows(S.nrows);
-    if (fp32) hipLaunchKernelGGL(k_energy_split<float>, dim3(g), dim3(kBlock), 0, s, view<float>(S), m, part);
-    else hipLaunchKernelGGL(k_energy_split<double>, dim3(g), dim3(kBlock), 0, s, view<double>(S), m, part);
+void launch_prec_init(const PrecLaunch &a, hipStream_t s) {
+    const RowMap &M = *a.M;
+    hipLaunchKernelGGL(k_prec_init, dim3(M.nblk), dim3(kBlock), 0, s, M, a.act, a.g, a.invDex, a.dscale, a.y, a.r,
+                       a.p, a.part, a.flags);
 }
-void launch_mavg(int n, const double *m, const double *L, double *part, hipStream_t s) {
-    int g = grid_for_rows(n);
-    hipLaunchKernelGGL(k_mavg, dim3(g), dim3(kBlock), 0, s, n, nslices_of(n), m, L, part);
+void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s) {
+    const RowMap &M = *a.M;
+    const int ph = 3 * j;
+    if (a.fp32)
+        hipLaunchKernelGGL(k_prec_apply<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(*a.C), M, a.act, a.m,
+                           a.lam, a.p, a.q, a.part, a.flags, ph + 1);
+    else
+        hipLaunchKernelGGL(k_prec_apply<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(*a.C), M, a.act, a.m,
+                           a.lam, a.p, a.q, a.part, a.flags, ph + 1);
+    hipLaunchKernelGGL(k_prec_update, dim3(M.nblk), dim3(kBlock), 0, s, M, a.act, j, a.g, a.invDex, a.dscale, a.y,
+                       a.r, a.p, a.q, a.part, a.flags, ph + 2);
+    if (!last)
+        hipLaunchKernelGGL(k_prec_pupdate, dim3(M.nblk), dim3(kBlock), 0, s, M, a.act, j, a.invDex, a.dscale, a.p, a.r,
+                           a.part, a.flags, ph + 3);
 }
-void launch_lambda(int n, const double *m, const double *G, double *lam, hipStream_t s) {
-    int g = (n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_lambda, dim3(g), dim3(kBlock), 0, s, n, m, G, lam);
+
+void launch_dir(const RowMap &M, const int *act, const int *first, const double *g1, const double *g0,
+                const double *y1, double *d, double *part_dots, double *part_out, int *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_dir_dots, dim3(M.nblk), dim3(kBlock), 0, s, M, act, first, g1, g0, y1, d, part_dots);
+    hipLaunchKernelGGL(k_dir_update, dim3(M.nblk), dim3(kBlock), 0, s, M, act, first, g1, y1, d, part_dots, part_out,
+                       info);
+}
+
+void launch_energy_split(const Sell &S, const RowMap &M, const double *m, double *part, bool fp32, hipStream_t s) {
+    if (fp32) hipLaunchKernelGGL(k_energy_split<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(S), M, m, part);
+    else hipLaunchKernelGGL(k_energy_split<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(S), M, m, part);
+}
+void launch_mavg(const RowMap &M, const double *m, const double *L, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_mavg, dim3(M.nblk), dim3(kBlock), 0, s, M, m, L, part);
+}
+void launch_lambda(const RowMap &M, const double *m, const double *G, double *lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_lambda, dim3(M.nblk), dim3(kBlock), 0, s, M, m, G, lam);
 }
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s) {
     if (n <= 0) return;
     int64_t g = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)g), dim3(kBlock), 0, s, n, x, y);
+}
+void launch_fill(int64_t n, double *x, double v, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(kBlock), 0, s, n, x, v);
 }
 
 }  // namespace mmncg

@@ -1,6 +1,6 @@
 // Scalar-potential solve K u = b (the magnetostatic subproblem of every energy
 // evaluation; the paper solves it with preconditioned CG, Sec. 3.1) by
-// Jacobi-preconditioned CG on gfx950.
+// Jacobi-preconditioned CG on gfx950, for every instance of a batch at once.
 //
 // Two kernels per CG iteration:
 //   A: convergence test, beta, p_new = D^-1 r + beta p_old (own rows) and
@@ -8,12 +8,17 @@
 //      from r, D^-1 and p_old (p is double-buffered, so no block reads a value
 //      another block is overwriting); partial p.q.
 //   B: alpha, x += alpha p_new, r -= alpha q; partials r.z, r.r.
-// Each kernel re-reduces the partials of the previous one in a fixed order
-// (every block gets the same scalars; no fences, no floating-point atomics),
-// and the r.z / r.r partials alternate between two slots, so every launch of a
-// chunk of iterations has fixed arguments: the chunk is captured once into a
-// HIP graph and replayed until the device-side flag reports convergence. Stop
-// flags carry the phase of the kernel that raised them (device_common.h).
+// Each kernel re-reduces the previous kernel's partials of its own instance in
+// a fixed order (every block of the instance gets the same scalars; no fences,
+// no floating-point atomics). The r.z / r.r partials alternate between two
+// slot pairs, so every launch of a chunk of iterations has fixed arguments:
+// the chunk is captured once into a HIP graph and replayed until every
+// instance's flag reports convergence. Once an instance's flag is up, every
+// later kernel of it returns at once, in this replay and in any further one
+// (replays are launched speculatively, ahead of the host seeing the flag).
+// All blocks of a kernel A take the same convergence decision from the same
+// partials, so a block that already sees the flag raised by its own launch
+// behaves as if it had decided itself.
 //
 // Vector type VT is double (FP64 mode) or float (inner solve of the FP32-bulk
 // mode, wrapped in FP64 defect correction); reductions are always FP64.
@@ -29,34 +34,35 @@ using namespace dev;
 namespace {
 
 // Poisson kernels run 1024-thread blocks (16 waves, one SELL slice each at a
-// time) on at most 256 blocks: every CU holds a block of 16 waves, and the
-// partials a kernel re-reduces fit one load per thread.
-constexpr int kPB = 1024;
+// time), at most kMaxBlocksPerInst blocks per instance.
+constexpr int kPB = kPoissonBlock;
 constexpr int kPW = kPB / 64;
-constexpr int kPMaxBlocks = 256;
 
-// partial regions (slot q of region R at part + (R + q) * kMaxPartials):
-//   RZ0 = 0, RZ1 = 2 (r.z, r.r written by kernel B of even / odd iterations),
-//   PQ = 4 (p.q of kernel A), INIT = 5 (b.b, r.z, r.r of the start)
+// partial slots (slot q at part + q * stride):
+//   RZ0 = 0-1, RZ1 = 2-3 (r.z, r.r written by kernel B of even / odd iterations),
+//   PQ = 4 (p.q of kernel A), INIT = 5-7 (b.b, r.z, r.r of the start)
 constexpr int kRZ0 = 0, kRZ1 = 2, kPQ = 4, kINIT = 5;
-__device__ __forceinline__ double *pslot(double *part, int r) { return part + (size_t)r * kMaxPartials; }
-__device__ __forceinline__ const double *pslot(const double *part, int r) { return part + (size_t)r * kMaxPartials; }
+
+__device__ __forceinline__ double *slot(double *part, int stride, int q) { return part + (size_t)q * stride; }
+__device__ __forceinline__ const double *slot(const double *part, int stride, int q) {
+    return part + (size_t)q * stride;
+}
 
 // r = b - K u; partials (b.b, r.D^-1.r, r.r)
 template <class MT>
-__global__ __launch_bounds__(kPB) void k_pcg_init64(SV<MT> K, const double *__restrict__ b,
-                                                       const double *__restrict__ u, double *__restrict__ r,
-                                                       const double *__restrict__ invD, double *__restrict__ part,
-                                                       int with_rz) {
+__global__ __launch_bounds__(kPB) void k_pcg_init64(SV<MT> K, RowMap M, const int *__restrict__ act,
+                                                    const double *__restrict__ b, const double *__restrict__ u,
+                                                    double *__restrict__ r, const double *__restrict__ invD,
+                                                    double *__restrict__ part, int with_rz) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || (act && !act[t.inst])) return;
     __shared__ double sh[kPW * 3];
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
+    const int rend = M.rend[t.inst], ln = lane_id();
     double acc[3] = {0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
         double ku = row_scalar(K, s, ln, u);
         int row = s * 64 + ln;
-        if (row < K.nrows) {
+        if (row < rend) {
             double bi = b[row];
             double ri = bi - ku;
             r[row] = ri;
@@ -65,20 +71,23 @@ __global__ __launch_bounds__(kPB) void k_pcg_init64(SV<MT> K, const double *__re
             acc[2] += ri * ri;
         }
     }
-    write_partials<3, kPW>(acc, 0u, pslot(part, kINIT), sh);
+    write_part<3, kPW>(acc, 0u, slot(part, M.nblk, kINIT), M.nblk, t.b, sh);
 }
 
-// start of the FP32 inner solve K x = r64 * scale: x = 0, r32 = r64 * scale; partials (-, r.z, r.r)
-__global__ __launch_bounds__(kPB) void k_pcg_init32(int n, int nslices, const double *__restrict__ r64,
-                                                       double scale, float *__restrict__ x, float *__restrict__ r,
-                                                       const float *__restrict__ invD, double *__restrict__ part) {
+// start of the FP32 inner solve K x = r64 * scale_i: x = 0, r32 = r64 * scale_i
+__global__ __launch_bounds__(kPB) void k_pcg_init32(RowMap M, const double *__restrict__ pin,
+                                                    const double *__restrict__ r64, float *__restrict__ x,
+                                                    float *__restrict__ r, const float *__restrict__ invD,
+                                                    double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !(pin[4 * t.inst + 1] > 0.0)) return;
     __shared__ double sh[kPW * 3];
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+    const double scale = pin[4 * t.inst];
+    const int rend = M.rend[t.inst];
     double acc[3] = {0, 0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
         int i = s * 64 + lane_id();
-        if (i < n) {
+        if (i < rend) {
             float ri = (float)(r64[i] * scale);
             x[i] = 0.0f;
             r[i] = ri;
@@ -86,42 +95,54 @@ __global__ __launch_bounds__(kPB) void k_pcg_init32(int n, int nslices, const do
             acc[2] += (double)ri * (double)ri;
         }
     }
-    write_partials<3, kPW>(acc, 0u, pslot(part, kINIT), sh);
+    write_part<3, kPW>(acc, 0u, slot(part, M.nblk, kINIT), M.nblk, t.b, sh);
 }
 
-// one block: reduce the start partials into the CG state and seed the ring so
-// that the first kernel A sees r.z (new) and +inf (old), i.e. beta = 0.
-// mode 0: tol2 = rtol2 * b.b (FP64 solve); mode 1: tol2 = rtol2 * r.r (FP32
-// inner solve, relative to its own start); mode 2: residual only (no CG start).
-__global__ __launch_bounds__(kPB) void k_pcg_init_fin(double *__restrict__ part, int nblk, double rtol2, int mode,
-                                                         PcgState *__restrict__ st) {
+// one block per instance: reduce the start partials into the instance's CG
+// state and seed the ring so that the first kernel A sees r.z (new) and +inf
+// (old), i.e. beta = 0.
+// mode 0: CG start, tol2 = rtol2 * b.b; mode 1: FP32 inner start, tol2 =
+// pin[1] * r.r (inactive when pin[1] <= 0); mode 2: residual only (no CG).
+__global__ __launch_bounds__(kPB) void k_pcg_init_fin(RowMap M, double *__restrict__ part, double rtol2, int mode,
+                                                      const int *__restrict__ act, const double *__restrict__ pin,
+                                                      PcgState *__restrict__ st) {
     __shared__ double sh[kPW * 3];
+    const int i = blockIdx.x;
+    const bool on = (mode == 1) ? (pin[4 * i + 1] > 0.0) : (act ? act[i] != 0 : true);
+    if (!on) {
+        if (threadIdx.x == 0) {
+            st[i].done = 1;
+            st[i].active = 0;
+        }
+        return;
+    }
+    const int S = M.nblk, b0 = M.ipb[i], b1 = M.ipb[i + 1];
     double t[3];
-    read_partials<3, kPW>(pslot(part, kINIT), nblk, 0u, t, sh);
+    read_part<3, kPW>(slot(part, S, kINIT), S, b0, b1, 0u, t, sh);
     const double bb = t[0], rz = t[1], rr = t[2];
-    const double tol2 = (mode == 1) ? rtol2 * rr : rtol2 * bb;
+    const double tol2 = (mode == 1) ? pin[4 * i + 1] * rr : rtol2 * bb;
     if (threadIdx.x == 0) {
-        st->bb = bb;
-        st->rz = rz;
-        st->rr = rr;
-        st->tol2 = tol2;
-        st->iters = 0;
-        st->zero_u = (mode != 1 && bb == 0.0) ? 1 : 0;
-        st->done = (mode == 2 || (mode != 1 && bb == 0.0) || rr <= tol2) ? 1 : 0;
+        st[i].bb = bb;
+        st[i].rr = rr;
+        st[i].tol2 = tol2;
+        st[i].iters = 0;
+        st[i].active = 1;
+        st[i].zero_u = (mode != 1 && bb == 0.0) ? 1 : 0;
+        st[i].done = (mode == 2 || (mode != 1 && bb == 0.0) || rr <= tol2) ? 1 : 0;
     }
     if (mode == 2) return;
-    double *nw = pslot(part, kRZ1), *od = pslot(part, kRZ0);
-    for (int i = threadIdx.x; i < nblk; i += kPB) {
-        nw[i] = (i == 0) ? rz : 0.0;
-        nw[kMaxPartials + i] = (i == 0) ? rr : 0.0;
-        od[i] = (i == 0) ? __builtin_huge_val() : 0.0;
-        od[kMaxPartials + i] = 0.0;
+    double *nw = slot(part, S, kRZ1), *od = slot(part, S, kRZ0);
+    for (int k = b0 + (int)threadIdx.x; k < b1; k += kPB) {
+        nw[k] = (k == b0) ? rz : 0.0;
+        nw[(size_t)S + k] = (k == b0) ? rr : 0.0;
+        od[k] = (k == b0) ? __builtin_huge_val() : 0.0;
+        od[(size_t)S + k] = 0.0;
     }
 }
 
-__device__ __forceinline__ int row_or_zero(int s, int ln, int nrows) {
+__device__ __forceinline__ int row_or_zero(int s, int ln, int rend) {
     int row = s * 64 + ln;
-    return row < nrows ? row : 0;
+    return row < rend ? row : 0;
 }
 
 template <class VT>
@@ -132,30 +153,32 @@ __device__ __forceinline__ VT pval(const VT *__restrict__ r, const VT *__restric
 }
 
 // kernel A of iteration j (odd = j & 1): convergence test on the residual of
-// iteration j-1 (every block decides alike; block 0 raises the flag), then
-// beta, p_new = D^-1 r + beta p_old, q = K p_new, partial p_new.q
+// iteration j-1 (every block of the instance decides alike; its first block
+// raises the flag), then beta, p_new = D^-1 r + beta p_old, q = K p_new,
+// partial p_new.q
 template <class MT, class VT>
-__global__ __launch_bounds__(kPB) void k_pcg_a(SV<MT> K, const VT *__restrict__ r, const VT *__restrict__ invD,
-                                                  const VT *__restrict__ p_old, VT *__restrict__ p_new,
-                                                  VT *__restrict__ q, PcgState *__restrict__ st, int phase, int odd,
-                                                  double *__restrict__ part) {
-    if (stopped_before(&st->done, phase)) return;
+__global__ __launch_bounds__(kPB) void k_pcg_a(SV<MT> K, RowMap M, const VT *__restrict__ r,
+                                               const VT *__restrict__ invD, const VT *__restrict__ p_old,
+                                               VT *__restrict__ p_new, VT *__restrict__ q, PcgState *__restrict__ st,
+                                               int phase, int odd, double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    PcgState *si = st + t.inst;
+    if (si->done) return;
     __shared__ double sh[kPW * 2];
-    const int nblk = gridDim.x;
+    const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
     double nw[2], od[1];
-    read_partials<2, kPW>(pslot(part, odd ? kRZ0 : kRZ1), nblk, 0u, nw, sh);
-    if (nw[1] <= st->tol2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->done = phase;
+    read_part<2, kPW>(slot(part, S, odd ? kRZ0 : kRZ1), S, b0, b1, 0u, nw, sh);
+    if (nw[1] <= si->tol2) {
+        if (t.b == b0 && threadIdx.x == 0) si->done = phase;
         return;
     }
-    read_partials<1, kPW>(pslot(part, odd ? kRZ1 : kRZ0), nblk, 0u, od, sh);
+    read_part<1, kPW>(slot(part, S, odd ? kRZ1 : kRZ0), S, b0, b1, 0u, od, sh);
     const VT beta = (VT)(nw[0] / od[0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->iters += 1;
-    int s0, s1;
-    slice_range(K.nslices, s0, s1);
-    int ln = lane_id();
+    if (t.b == b0 && threadIdx.x == 0) si->iters += 1;
+    const int rend = M.rend[t.inst], ln = lane_id();
     double acc[1] = {0};
-    for (int s = s0 + wave_id(); s < s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
         int64_t base = K.sptr[s];
         int w = (int)((K.sptr[s + 1] - base) >> 6);
         VT qv = 0;
@@ -167,43 +190,43 @@ __global__ __launch_bounds__(kPB) void k_pcg_a(SV<MT> K, const VT *__restrict__ 
             for (int k = 0; k < 8; ++k) {
                 bool in = k0 + k < w;
                 int64_t e = base + 64 * (k0 + k) + ln;
-                cc[k] = in ? K.col[e] : row_or_zero(s, ln, K.nrows);
+                cc[k] = in ? K.col[e] : row_or_zero(s, ln, rend);
                 vv[k] = in ? (VT)K.val[e] : (VT)0;
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) qv += vv[k] * pval(r, invD, p_old, beta, cc[k]);
         }
         int row = s * 64 + ln;
-        if (row < K.nrows) {
+        if (row < rend) {
             VT pn = pval(r, invD, p_old, beta, row);
             p_new[row] = pn;
             q[row] = qv;
             acc[0] += (double)pn * (double)qv;
         }
     }
-    write_partials<1, kPW>(acc, 0u, pslot(part, kPQ), sh);
+    write_part<1, kPW>(acc, 0u, slot(part, S, kPQ), S, t.b, sh);
 }
 
 // kernel B of iteration j: alpha = r.z / p.q; x += alpha p, r -= alpha q;
 // partials (r.z, r.r) into the ring slot of iteration j
 template <class VT, class XT>
-__global__ __launch_bounds__(kPB) void k_pcg_b(int n, int nslices, XT *__restrict__ x, VT *__restrict__ r,
-                                                  const VT *__restrict__ p, const VT *__restrict__ q,
-                                                  const VT *__restrict__ invD, PcgState *__restrict__ st, int phase,
-                                                  int odd, double *__restrict__ part) {
-    if (stopped_before(&st->done, phase)) return;
+__global__ __launch_bounds__(kPB) void k_pcg_b(RowMap M, XT *__restrict__ x, VT *__restrict__ r,
+                                               const VT *__restrict__ p, const VT *__restrict__ q,
+                                               const VT *__restrict__ invD, PcgState *__restrict__ st, int phase,
+                                               int odd, double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || st[t.inst].done) return;
     __shared__ double sh[kPW * 2];
-    const int nblk = gridDim.x;
+    const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
     double pq[1], rz[1];
-    read_partials<1, kPW>(pslot(part, kPQ), nblk, 0u, pq, sh);
-    read_partials<1, kPW>(pslot(part, odd ? kRZ0 : kRZ1), nblk, 0u, rz, sh);
+    read_part<1, kPW>(slot(part, S, kPQ), S, b0, b1, 0u, pq, sh);
+    read_part<1, kPW>(slot(part, S, odd ? kRZ0 : kRZ1), S, b0, b1, 0u, rz, sh);
     const VT a = (VT)(rz[0] / pq[0]);
-    int s0, s1;
-    slice_range(nslices, s0, s1);
+    const int rend = M.rend[t.inst];
     double acc[2] = {0, 0};
-    for (int s = s0 + wave_id(); s < s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
         int i = s * 64 + lane_id();
-        if (i < n) {
+        if (i < rend) {
             x[i] += (XT)(a * p[i]);
             VT ri = r[i] - a * q[i];
             r[i] = ri;
@@ -211,72 +234,69 @@ __global__ __launch_bounds__(kPB) void k_pcg_b(int n, int nslices, XT *__restric
             acc[1] += (double)ri * (double)ri;
         }
     }
-    write_partials<2, kPW>(acc, 0u, pslot(part, odd ? kRZ1 : kRZ0), sh);
+    write_part<2, kPW>(acc, 0u, slot(part, S, odd ? kRZ1 : kRZ0), S, t.b, sh);
 }
 
-__global__ __launch_bounds__(kPB) void k_add_correction(int n, double *__restrict__ u, const float *__restrict__ x,
-                                                           double scale) {
-    int i = blockIdx.x * kPB + threadIdx.x;
-    if (i < n) u[i] += scale * (double)x[i];
-}
-
-inline int nslices_of(int n) { return (n + 63) / 64; }
-
-inline int pgrid(int nrows) {
-    int g = (nslices_of(nrows) + kPW - 1) / kPW;
-    if (g < 1) g = 1;
-    if (g > kPMaxBlocks) g = kPMaxBlocks;
-    if (g >= 8) g = (g + 7) & ~7;
-    return g;
+// u += rn_i * x32 for the instances with an inner solve
+__global__ __launch_bounds__(kPB) void k_add_correction(RowMap M, const double *__restrict__ pin, double *__restrict__ u,
+                                                        const float *__restrict__ x) {
+    Tile t = tile_of(M);
+    if (t.inst < 0 || !(pin[4 * t.inst + 1] > 0.0)) return;
+    const double sc = pin[4 * t.inst + 2];
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
+        int i = s * 64 + lane_id();
+        if (i < rend) u[i] += sc * (double)x[i];
+    }
 }
 
 }  // namespace
 
-void launch_pcg_init64(const Sell &K, const double *b, const double *u, double *r, const double *invD, double rtol2,
-                       PcgState *st, double *part, bool fp32, hipStream_t s) {
-    int g = pgrid(K.nrows);
-    if (fp32)
-        hipLaunchKernelGGL(k_pcg_init64<float>, dim3(g), dim3(kPB), 0, s, view<float>(K), b, u, r, invD, part, 1);
+void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, bool fp32_matrix, hipStream_t s) {
+    const RowMap &M = *a.M;
+    if (fp32_matrix)
+        hipLaunchKernelGGL(k_pcg_init64<float>, dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, act, a.b, a.u,
+                           a.r, a.invD, a.part, 1);
     else
-        hipLaunchKernelGGL(k_pcg_init64<double>, dim3(g), dim3(kPB), 0, s, view<double>(K), b, u, r, invD, part, 1);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(kPB), 0, s, part, g, rtol2, 0, st);
+        hipLaunchKernelGGL(k_pcg_init64<double>, dim3(M.nblk), dim3(kPB), 0, s, view<double>(*a.K), M, act, a.b, a.u,
+                           a.r, a.invD, a.part, 1);
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, rtol2, 0, act, a.pin, a.st);
 }
 
-void launch_residual64(const Sell &K, const double *b, const double *u, double *r, PcgState *st, double *part,
-                       hipStream_t s) {
-    int g = pgrid(K.nrows);
-    hipLaunchKernelGGL(k_pcg_init64<float>, dim3(g), dim3(kPB), 0, s, view<float>(K), b, u, r, nullptr, part, 0);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(kPB), 0, s, part, g, 0.0, 2, st);
+void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s) {
+    const RowMap &M = *a.M;
+    hipLaunchKernelGGL(k_pcg_init64<float>, dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, act, a.b, a.u, a.r,
+                       a.invD, a.part, 0);
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, 0.0, 2, act, a.pin, a.st);
 }
 
-void launch_pcg_init32(int n, const double *r64, double scale, float *x, float *r, const float *invD, double inner2,
-                       PcgState *st, double *part, hipStream_t s) {
-    int g = pgrid(n);
-    hipLaunchKernelGGL(k_pcg_init32, dim3(g), dim3(kPB), 0, s, n, nslices_of(n), r64, scale, x, r, invD, part);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(kPB), 0, s, part, g, inner2, 1, st);
+void launch_pcg_init32(const PcgLaunch &a, hipStream_t s) {
+    const RowMap &M = *a.M;
+    hipLaunchKernelGGL(k_pcg_init32, dim3(M.nblk), dim3(kPB), 0, s, M, a.pin, a.r, a.x32, a.r32, a.invD32, a.part);
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, 0.0, 1, nullptr, a.pin, a.st);
 }
 
-void launch_pcg_iter64(const Sell &K, double *u, double *r, double *p_old, double *p_new, double *q,
-                       const double *invD, PcgState *st, int phase_a, int odd, double *part, hipStream_t s) {
-    int g = pgrid(K.nrows);
-    hipLaunchKernelGGL((k_pcg_a<double, double>), dim3(g), dim3(kPB), 0, s, view<double>(K), r, invD, p_old,
-                       p_new, q, st, phase_a, odd, part);
-    hipLaunchKernelGGL((k_pcg_b<double, double>), dim3(g), dim3(kPB), 0, s, K.nrows, nslices_of(K.nrows), u, r,
-                       p_new, q, invD, st, phase_a + 1, odd, part);
+void launch_pcg_iter64(const PcgLaunch &a, int phase_a, int odd, hipStream_t s) {
+    const RowMap &M = *a.M;
+    double *po = odd ? a.p1 : a.p0, *pn = odd ? a.p0 : a.p1;
+    hipLaunchKernelGGL((k_pcg_a<double, double>), dim3(M.nblk), dim3(kPB), 0, s, view<double>(*a.K), M, a.r, a.invD,
+                       po, pn, a.q, a.st, phase_a, odd, a.part);
+    hipLaunchKernelGGL((k_pcg_b<double, double>), dim3(M.nblk), dim3(kPB), 0, s, M, a.u, a.r, pn, a.q, a.invD, a.st,
+                       phase_a + 1, odd, a.part);
 }
 
-void launch_pcg_iter32(const Sell &K, float *x, float *r, float *p_old, float *p_new, float *q, const float *invD,
-                       PcgState *st, int phase_a, int odd, double *part, hipStream_t s) {
-    int g = pgrid(K.nrows);
-    hipLaunchKernelGGL((k_pcg_a<float, float>), dim3(g), dim3(kPB), 0, s, view<float>(K), r, invD, p_old, p_new,
-                       q, st, phase_a, odd, part);
-    hipLaunchKernelGGL((k_pcg_b<float, float>), dim3(g), dim3(kPB), 0, s, K.nrows, nslices_of(K.nrows), x, r,
-                       p_new, q, invD, st, phase_a + 1, odd, part);
+void launch_pcg_iter32(const PcgLaunch &a, int phase_a, int odd, hipStream_t s) {
+    const RowMap &M = *a.M;
+    float *po = odd ? a.p32b : a.p32a, *pn = odd ? a.p32a : a.p32b;
+    hipLaunchKernelGGL((k_pcg_a<float, float>), dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, a.r32, a.invD32,
+                       po, pn, a.q32, a.st, phase_a, odd, a.part);
+    hipLaunchKernelGGL((k_pcg_b<float, float>), dim3(M.nblk), dim3(kPB), 0, s, M, a.x32, a.r32, pn, a.q32, a.invD32,
+                       a.st, phase_a + 1, odd, a.part);
 }
 
-void launch_add_correction(int n, double *u, const float *x, double scale, hipStream_t s) {
-    int g = (n + kPB - 1) / kPB;
-    hipLaunchKernelGGL(k_add_correction, dim3(g), dim3(kPB), 0, s, n, u, x, scale);
+void launch_add_correction(const PcgLaunch &a, hipStream_t s) {
+    const RowMap &M = *a.M;
+    hipLaunchKernelGGL(k_add_correction, dim3(M.nblk), dim3(kPB), 0, s, M, a.pin, a.u, a.x32);
 }
 
 }  // namespace mmncg

@@ -1,12 +1,20 @@
-// Context, device operators and the host control of the PNCG minimizer
-// (Alg. 4 with beta*ZA, the local-field preconditioner solved by Alg. 1, and
-// field stepping), behind the C ABI of include/mmncg.h.
+// Context, batched device operators and the host control of the PNCG
+// minimizer (Alg. 4 with beta*ZA, the local-field preconditioner solved by
+// Alg. 1, and field stepping), behind the C ABI of include/mmncg.h.
 //
-// The host only makes scalar decisions (line-search steps, stopping); every
-// vector operation runs in the HIP kernels of kernels.hip on the context's
-// stream. Scalars come back through a small pinned buffer, once per
-// evaluation, once per direction update and once per chunk of Poisson CG
-// iterations.
+// A context holds one or more independent problem instances. Their operators
+// are concatenated (each instance padded to whole SELL slices) and every
+// kernel launch serves all instances at once; each instance runs its own
+// copy of the minimizer's control logic on the host. One "round" of the
+// batched driver is
+//   1. one batched evaluation (trial points of the line searches and start
+//      points of new field values, including the scalar-potential solve),
+//   2. host decisions per instance (line-search steps, acceptance, stopping),
+//   3. one batched copy of accepted trials, preconditioner solve and
+//      direction update for the instances that need a new direction.
+// Instances advance through their field lists independently. The host only
+// makes scalar decisions; every vector operation runs in the HIP kernels on
+// the context's stream. Scalars come back through small pinned buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,14 +36,15 @@ using namespace mmncg;
 namespace {
 
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr int kPcgChunk = 8;  // CG iterations per captured graph (even: the p double buffer returns)
 
 struct HipError {
     hipError_t e;
     const char *what;
 };
-#define HIPCHK(x)                                   \
-    do {                                            \
-        hipError_t _e = (x);                        \
+#define HIPCHK(x)                                     \
+    do {                                              \
+        hipError_t _e = (x);                          \
         if (_e != hipSuccess) throw HipError{_e, #x}; \
     } while (0)
 
@@ -44,32 +53,41 @@ struct ApiError {
     std::string msg;
 };
 
-// partial-buffer arena layout (units of kMaxPartials doubles)
-enum PartSlot {
-    PS_EVAL = 0,                    // 10
-    PS_CG_INIT = PS_EVAL + 10,      // 3
-    PS_CG_PQ = PS_CG_INIT + 3,      // 1
-    PS_CG_RZ0 = PS_CG_PQ + 1,       // 2
-    PS_CG_RZ1 = PS_CG_RZ0 + 2,      // 2
-    PS_PR_INIT = PS_CG_RZ1 + 2,     // 2
-    PS_PR_PQ = PS_PR_INIT + 2,      // 1
-    PS_PR_RZ0 = PS_PR_PQ + 1,       // 2
-    PS_PR_RZ1 = PS_PR_RZ0 + 2,      // 2
-    PS_DIR_DOTS = PS_PR_RZ1 + 2,    // 6
-    PS_DIR_OUT = PS_DIR_DOTS + 6,   // 2
-    PS_MISC = PS_DIR_OUT + 2,       // 5
-    PS_TOTAL = PS_MISC + 5
+// magnet-row partial slots (each M.nblk doubles)
+enum MagSlot {
+    MS_EVAL = 0,                   // kEvalParts
+    MS_PREC = MS_EVAL + kEvalParts,  // 7
+    MS_DOTS = MS_PREC + 7,         // kDirParts
+    MS_DOUT = MS_DOTS + kDirParts,  // 2
+    MS_MISC = MS_DOUT + 2,         // 5
+    MS_TOTAL = MS_MISC + 5
 };
-// device scalar slots
-enum ScSlot { SC_EVAL = 0, SC_CG = 16, SC_DIR = 24, SC_MISC = 32, SC_TOTAL = 48 };
-// device int flags
-enum FlagSlot { FL_CG_DONE = 0, FL_CG_ITERS = 1, FL_PREC = 4, FL_DIR = 8, FL_TOTAL = 16 };
 
-struct State {
-    double *x = nullptr, *G = nullptr, *g = nullptr, *lam = nullptr;
-    double E = 0;       // total energy
-    double Eloc = 0, Ez = 0, Ed = 0;
-    double tmax = 0, ginf = 0, minf = 0;
+// per-instance metadata kept on the host
+struct InstInfo {
+    long n_nodes = 0, n_tets = 0;
+    int n_mag = 0, n_pot = 0, n_brow = 0;
+    int mag_off = 0, pot_off = 0, brow_off = 0;  // first global (padded) row
+    long user_off = 0;                           // first magnet node in caller arrays
+    long nnz_C = 0, nnz_K = 0, nnz_B = 0;
+    double Ms_ref = 0;
+    std::vector<int> node_of_mag;
+};
+
+// device tables of one RowMap
+struct DevMap {
+    RowMap map;
+};
+
+// scalars of one evaluation point
+struct Sc {
+    double E = 0, Eloc = 0, Ez = 0, Ed = 0, tmax = 0, ginf = 0, minf = 0, dF = 0, dphi = 0, dxinf = 0;
+};
+
+// running counters of an instance (monotone; per-field stats are differences)
+struct Cnt {
+    long evals = 0, mi = 0, li = 0;
+    double t_mag = 0, t_lin = 0;
 };
 
 }  // namespace
@@ -83,64 +101,81 @@ struct mm_ctx {
     void *user = nullptr;
     std::string err;
     std::vector<void *> allocs;
+    size_t dev_bytes = 0;
 
-    // mesh (host copy until materials arrive)
+    // single-instance mesh (host copy until materials arrive)
     std::vector<double> xyz;
     std::vector<int> tets, region;
     bool have_mesh = false, have_mat = false;
 
-    Assembly as;
+    int ninst = 0;
+    std::vector<InstInfo> inst;
+    long tot_mag = 0;   // sum of n_mag (caller layout)
+    int rows_m = 0, rows_p = 0, rows_b = 0;  // padded global row counts
+
     Sell C, S, K, B, Bt;
+    DevMap Mm, Mp, Mb;  // magnet rows, potential rows, divergence rows
     double *L = nullptr, *invDex = nullptr, *invDK = nullptr;
     float *invDK32 = nullptr;
-    bool fp32_ready = false;
 
-    // vectors on magnet nodes
-    State st[3];
-    double *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr, *dscale = nullptr,
-           *tmp3 = nullptr;
-    // vectors on potential nodes
-    double *u = nullptr, *b = nullptr, *cr = nullptr, *cp = nullptr, *cp2 = nullptr, *cq = nullptr, *usave = nullptr;
+    StateV st[3];  // current state, trial T, trial C
+    double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
+           *dscale = nullptr, *tmp3 = nullptr;
+    double *u = nullptr, *b = nullptr, *cr = nullptr, *cp = nullptr, *cp2 = nullptr, *cq = nullptr,
+           *usave = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;
-    PcgState *pst = nullptr;     // device
-    PcgState *hpst = nullptr;    // pinned host mirror
-    double *ppart = nullptr;     // partials of the Poisson kernels
+    PcgState *pst = nullptr;    // device, ninst
+    PcgState *hpst = nullptr;   // pinned host mirror
+    double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
+    double *ppart = nullptr;    // potential-row partials, kPcgSlots slots
     hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-    double *part = nullptr;
+
+    // control block: ints {act, role, first, from, pact, plive} (host-written)
+    // then {info, pflags x4} (device-written); doubles {alpha, h3 x3, pin x4}
+    int *dci = nullptr, *hci = nullptr;
+    double *dcd = nullptr, *hcd = nullptr;
+    // finalize outputs: eval (kEvalParts), dir (2), misc (5) per instance
     double *dsc = nullptr, *hsc = nullptr;
-    int *dflags = nullptr, *hflags = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
     mm_opts opts;
-    long last_poisson_iters = 16;
+    std::vector<long> last_pcg;
+    std::vector<double> pcg_bytes64, pcg_bytes32;
+    std::vector<Cnt> cnt;
     // kernel timing (mm_profile)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
     size_t prof_used = 0;
-    double prof_launches = 0, prof_seconds = 0, prof_units = 0;
-    // counters of the current minimization
-    long c_evals = 0, c_mi = 0, c_li = 0;
-    double t_mag = 0, t_lin = 0;
+    double prof_seconds = 0, prof_units = 0, prof_bytes = 0;
 
-    int n_mag() const { return as.n_mag; }
-    int n_pot() const { return as.n_pot; }
+    // control block accessors
+    int *act() const { return hci; }
+    int *role() const { return hci + ninst; }
+    int *first() const { return hci + 2 * ninst; }
+    int *from() const { return hci + 3 * ninst; }
+    int *pact() const { return hci + 4 * ninst; }
+    int *plive() const { return hci + 5 * ninst; }
+    int *info() const { return hci + 6 * ninst; }
+    int *pflags() const { return hci + 7 * ninst; }
+    double *alpha() const { return hcd; }
+    double *h3() const { return hcd + ninst; }
+    double *pin() const { return hcd + 4 * ninst; }
+    template <class T>
+    T *dev(T *hostp, T *hbase, T *dbase) const {
+        return dbase + (hostp - hbase);
+    }
+    int *d_(int *hp) const { return dci + (hp - hci); }
+    double *d_(double *hp) const { return dcd + (hp - hcd); }
 };
 
 namespace {
 
-double *partp(mm_ctx *c, int slot) { return c->part + (size_t)slot * kMaxPartials; }
-
-void set_err(mm_ctx *c, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (c) c->err = buf;
-}
-
+// ---------------------------------------------------------------------------
+// plumbing
+// ---------------------------------------------------------------------------
 void *dalloc(mm_ctx *c, size_t bytes) {
     if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
     if (c->ualloc) {
         p = c->ualloc(bytes, c->user);
@@ -153,11 +188,19 @@ void *dalloc(mm_ctx *c, size_t bytes) {
         }
     }
     c->allocs.push_back(p);
+    c->dev_bytes += bytes;
     return p;
 }
 template <class T>
 T *dalloc_n(mm_ctx *c, size_t n) {
     return (T *)dalloc(c, n * sizeof(T));
+}
+
+void free_host_ctl(mm_ctx *c) {
+    for (void **p : {(void **)&c->hci, (void **)&c->hcd, (void **)&c->hsc, (void **)&c->hpst}) {
+        if (*p) (void)hipHostFree(*p);
+        *p = nullptr;
+    }
 }
 
 void free_all(mm_ctx *c) {
@@ -171,9 +214,11 @@ void free_all(mm_ctx *c) {
         else (void)hipFree(p);
     }
     c->allocs.clear();
+    c->dev_bytes = 0;
+    free_host_ctl(c);
+    c->ninst = 0;
+    c->inst.clear();
 }
-
-size_t device_bytes_estimate(const mm_ctx *c);
 
 bool is_device_ptr(const void *p) {
     if (!p) return false;
@@ -187,22 +232,40 @@ bool is_device_ptr(const void *p) {
 }
 
 void copy_in(mm_ctx *c, double *dst, const double *src, size_t n) {
+    if (n == 0) return;
     HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
                           is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
 }
 void copy_out(mm_ctx *c, double *dst, const double *src, size_t n) {
+    if (n == 0) return;
     HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
                           is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
 }
 void sync(mm_ctx *c) { HIPCHK(hipStreamSynchronize(c->stream)); }
 
-// pull n scalars from the device scalar area (slot) and wait
-void pull(mm_ctx *c, int slot, int n) {
-    HIPCHK(hipMemcpyAsync(c->hsc + slot, c->dsc + slot, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    sync(c);
+// The host writes the control block only after a synchronization that
+// follows the previous upload, so an upload never races with the host.
+void upload_ctl(mm_ctx *c) {
+    const int n = c->ninst;
+    HIPCHK(hipMemcpyAsync(c->dci, c->hci, 6 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->dcd, c->hcd, 8 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream));
 }
+void pull_flags(mm_ctx *c) {
+    const int n = c->ninst;
+    HIPCHK(hipMemcpyAsync(c->hci + 6 * n, c->dci + 6 * n, 5 * (size_t)n * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+}
+enum { SC_EVAL = 0, SC_DIR = kEvalParts, SC_MISC = kEvalParts + 2, SC_PER = kEvalParts + 7 };
+double *dsc_at(mm_ctx *c, int slot) { return c->dsc + (size_t)slot * c->ninst; }
+double *hsc_at(mm_ctx *c, int slot) { return c->hsc + (size_t)slot * c->ninst; }
+// finalize output of slot group `slot` with `nq` quantities is [inst][nq]
+void pull_sc(mm_ctx *c, int slot, int nq) {
+    HIPCHK(hipMemcpyAsync(hsc_at(c, slot), dsc_at(c, slot), (size_t)nq * c->ninst * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+}
+double *mslot(mm_ctx *c, int q) { return c->mpart + (size_t)q * c->Mm.map.nblk; }
 
-// event pairs around the timed kernel; harvested at the next synchronization
+// event pairs around the timed kernels; harvested at the next synchronization
 void prof_mark(mm_ctx *c) {
     if (!c->prof_on) return;
     if (c->prof_used == c->prof_ev.size()) {
@@ -213,30 +276,70 @@ void prof_mark(mm_ctx *c) {
     HIPCHK(hipEventRecord(c->prof_ev[c->prof_used++], c->stream));
 }
 void prof_harvest(mm_ctx *c) {
-    if (c->prof_used < 2) {
-        c->prof_used = 0;
-        return;
-    }
     for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]));
         c->prof_seconds += ms * 1e-3;
-        c->prof_launches += 1;
     }
     c->prof_used = 0;
 }
 
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // ---------------------------------------------------------------------------
-// SELL-64 upload
+// operator concatenation and SELL-64 upload
 // ---------------------------------------------------------------------------
+// append instance operator h to the global G: rows from row_off (padding rows
+// before it are empty), columns shifted by col_off, output rows by out_off
+void append_csr(HostCsr &G, const HostCsr &h, int row_off, int col_off, int out_off) {
+    if (G.ptr.empty()) G.ptr.push_back(0);
+    G.vw = h.vw;
+    const bool ro = !h.row_out.empty();
+    while (G.nrows < row_off) {
+        G.ptr.push_back(G.ptr.back());
+        if (ro || !G.row_out.empty()) G.row_out.push_back(0);
+        G.nrows++;
+    }
+    if (ro && G.row_out.size() < (size_t)G.nrows) G.row_out.resize(G.nrows, 0);
+    for (int r = 0; r < h.nrows; ++r) {
+        for (int64_t k = h.ptr[r]; k < h.ptr[r + 1]; ++k) {
+            G.col.push_back(h.col[k] + col_off);
+            for (int q = 0; q < h.vw; ++q) G.val.push_back(h.val[k * h.vw + q]);
+        }
+        G.ptr.push_back((int64_t)G.col.size());
+        if (ro) G.row_out.push_back(h.row_out[r] + out_off);
+        G.nrows++;
+    }
+}
+void pad_rows(HostCsr &G, int nrows) {
+    if (G.ptr.empty()) G.ptr.push_back(0);
+    while (G.nrows < nrows) {
+        G.ptr.push_back(G.ptr.back());
+        if (!G.row_out.empty()) G.row_out.push_back(0);
+        G.nrows++;
+    }
+}
+
+// Padding entries of a slice point at a column that a real entry of the same
+// slice uses (so they stay inside the instance) with value 0.
 void upload_sell(mm_ctx *c, const HostCsr &h, Sell &d) {
     d.nrows = h.nrows;
     d.vw = h.vw;
     d.nslices = (h.nrows + kSlice - 1) / kSlice;
     std::vector<int64_t> sptr(d.nslices + 1, 0);
+    std::vector<int> padc(d.nslices, 0);
     for (int s = 0; s < d.nslices; ++s) {
         int64_t w = 0;
-        for (int r = s * kSlice; r < std::min(h.nrows, (s + 1) * kSlice); ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+        bool got = false;
+        for (int r = s * kSlice; r < std::min(h.nrows, (s + 1) * kSlice); ++r) {
+            w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+            if (!got && h.ptr[r + 1] > h.ptr[r]) {
+                padc[s] = h.col[h.ptr[r]];
+                got = true;
+            }
+        }
         sptr[s + 1] = sptr[s] + w * kSlice;
     }
     d.padded = sptr[d.nslices];
@@ -244,13 +347,19 @@ void upload_sell(mm_ctx *c, const HostCsr &h, Sell &d) {
     std::vector<int> col(std::max<int64_t>(d.padded, 1), 0);
     std::vector<double> val(std::max<int64_t>(d.padded * h.vw, 1), 0.0);
     for (int s = 0; s < d.nslices; ++s) {
+        const int64_t w = (sptr[s + 1] - sptr[s]) / kSlice;
         for (int ln = 0; ln < kSlice; ++ln) {
             int r = s * kSlice + ln;
-            if (r >= h.nrows) break;
-            for (int64_t k = 0; k < h.ptr[r + 1] - h.ptr[r]; ++k) {
+            int64_t len = r < h.nrows ? h.ptr[r + 1] - h.ptr[r] : 0;
+            for (int64_t k = 0; k < w; ++k) {
                 int64_t e = sptr[s] + kSlice * k;
-                col[e + ln] = h.col[h.ptr[r] + k];
-                for (int q = 0; q < h.vw; ++q) val[e * h.vw + q * kSlice + ln] = h.val[(h.ptr[r] + k) * h.vw + q];
+                if (k < len) {
+                    col[e + ln] = h.col[h.ptr[r] + k];
+                    for (int q = 0; q < h.vw; ++q)
+                        val[e * h.vw + q * kSlice + ln] = h.val[(h.ptr[r] + k) * h.vw + q];
+                } else {
+                    col[e + ln] = padc[s];
+                }
             }
         }
     }
@@ -271,108 +380,241 @@ void upload_sell(mm_ctx *c, const HostCsr &h, Sell &d) {
 }
 
 void upload_vec(mm_ctx *c, double *dst, const std::vector<double> &v) {
+    if (v.empty()) return;
     HIPCHK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     sync(c);
 }
 
-void setup_device(mm_ctx *c) {
-    free_all(c);
-    const int nm = c->n_mag(), np = c->n_pot();
-    upload_sell(c, c->as.C, c->C);
-    upload_sell(c, c->as.S, c->S);
-    upload_sell(c, c->as.K, c->K);
-    upload_sell(c, c->as.B, c->B);
-    upload_sell(c, c->as.Bt, c->Bt);
-    c->L = dalloc_n<double>(c, nm);
-    c->invDex = dalloc_n<double>(c, nm);
-    c->invDK = dalloc_n<double>(c, np);
-    c->invDK32 = dalloc_n<float>(c, np);
-    upload_vec(c, c->L, c->as.L);
-    std::vector<double> t(nm);
-    for (int a = 0; a < nm; ++a) t[a] = 1.0 / c->as.Dex[a];
-    upload_vec(c, c->invDex, t);
-    std::vector<double> tk(np);
-    for (int r = 0; r < np; ++r) tk[r] = 1.0 / c->as.DK[r];
-    upload_vec(c, c->invDK, tk);
-    launch_to_f32(np, c->invDK, c->invDK32, c->stream);
-    for (auto &s : c->st) {
-        s.x = dalloc_n<double>(c, 3 * (size_t)nm);
-        s.G = dalloc_n<double>(c, 3 * (size_t)nm);
-        s.g = dalloc_n<double>(c, 3 * (size_t)nm);
-        s.lam = dalloc_n<double>(c, nm);
-    }
-    c->d = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->y = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->pr = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->pp = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->pq = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->tmp3 = dalloc_n<double>(c, 3 * (size_t)nm);
-    c->dscale = dalloc_n<double>(c, nm);
-    c->u = dalloc_n<double>(c, np);
-    c->b = dalloc_n<double>(c, np);
-    c->cr = dalloc_n<double>(c, np);
-    c->cp = dalloc_n<double>(c, np);
-    c->cp2 = dalloc_n<double>(c, np);
-    c->cq = dalloc_n<double>(c, np);
-    c->usave = dalloc_n<double>(c, np);
-    c->p32b = dalloc_n<float>(c, np);
-    c->pst = dalloc_n<PcgState>(c, 1);
-    c->ppart = dalloc_n<double>(c, kPcgPartDoubles);
-    c->x32 = dalloc_n<float>(c, np);
-    c->r32 = dalloc_n<float>(c, np);
-    c->p32 = dalloc_n<float>(c, np);
-    c->q32 = dalloc_n<float>(c, np);
-    c->part = dalloc_n<double>(c, (size_t)PS_TOTAL * kMaxPartials);
-    c->dsc = dalloc_n<double>(c, SC_TOTAL);
-    c->dflags = dalloc_n<int>(c, FL_TOTAL);
-    HIPCHK(hipMemsetAsync(c->u, 0, np * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->b, 0, np * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->part, 0, (size_t)PS_TOTAL * kMaxPartials * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(c->dflags, 0, FL_TOTAL * sizeof(int), c->stream));
-    HIPCHK(hipMemsetAsync(c->pst, 0, sizeof(PcgState), c->stream));
-    HIPCHK(hipMemsetAsync(c->ppart, 0, kPcgPartDoubles * sizeof(double), c->stream));
-    sync(c);
-    c->last_poisson_iters = 16;
-}
-
-// ---------------------------------------------------------------------------
-// Poisson: K u = b (warm start u), Jacobi-PCG; FP64 or FP32 defect correction
-// ---------------------------------------------------------------------------
-constexpr int kPcgChunk = 8;  // CG iterations per captured graph (even: the p double buffer returns)
-
-// capture kPcgChunk iterations (2 kernels each) once per context and mode
-hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32) {
-    hipGraphExec_t &ge = fp32 ? c->graph32 : c->graph64;
-    if (ge) return ge;
-    hipStream_t s = c->stream;
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < kPcgChunk; ++j) {
-        const int ph = 2 * j + 2;
-        if (fp32) {
-            float *po = (j & 1) ? c->p32b : c->p32, *pn = (j & 1) ? c->p32 : c->p32b;
-            launch_pcg_iter32(c->K, c->x32, c->r32, po, pn, c->q32, c->invDK32, c->pst, ph, j & 1, c->ppart, s);
-        } else {
-            double *po = (j & 1) ? c->cp2 : c->cp, *pn = (j & 1) ? c->cp : c->cp2;
-            launch_pcg_iter64(c->K, c->u, c->cr, po, pn, c->cq, c->invDK, c->pst, ph, j & 1, c->ppart, s);
+// Partition of one row space into logical blocks: instance i owns rows
+// [off[i], off[i] + n[i]) (off a multiple of 64); its ns = ceil(n/64) slices
+// are split evenly over min(kMaxBlocksPerInst, ceil(ns / slices_per_block))
+// blocks. The table is padded with empty blocks to a multiple of 8 (XCD
+// renumbering).
+void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vector<int> &n, int slices_per_block) {
+    const int ni = (int)off.size();
+    std::vector<int> tab;
+    std::vector<int> ipb(ni + 1, 0), rend(ni, 0);
+    for (int i = 0; i < ni; ++i) {
+        ipb[i] = (int)tab.size() / 4;
+        const int ns = (n[i] + kSlice - 1) / kSlice;
+        const int sf = off[i] / kSlice;
+        rend[i] = off[i] + n[i];
+        if (ns == 0) continue;
+        const int nb = std::min(kMaxBlocksPerInst, (ns + slices_per_block - 1) / slices_per_block);
+        for (int k = 0; k < nb; ++k) {
+            tab.push_back(i);
+            tab.push_back(sf + (int)((int64_t)k * ns / nb));
+            tab.push_back(sf + (int)((int64_t)(k + 1) * ns / nb));
+            tab.push_back(0);
         }
     }
-    HIPCHK(hipStreamEndCapture(s, &g));
-    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPCHK(e);
-    return ge;
-}
-
-void pull_pcg(mm_ctx *c) {
-    HIPCHK(hipMemcpyAsync(c->hpst, c->pst, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    ipb[ni] = (int)tab.size() / 4;
+    while (tab.size() / 4 < 8 || (tab.size() / 4) % 8 != 0) {
+        tab.push_back(-1);
+        tab.push_back(0);
+        tab.push_back(0);
+        tab.push_back(0);
+    }
+    const int nblk = (int)tab.size() / 4;
+    int4 *dtab = dalloc_n<int4>(c, nblk);
+    int *dipb = dalloc_n<int>(c, ni + 1);
+    int *drend = dalloc_n<int>(c, std::max(ni, 1));
+    HIPCHK(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dipb, ipb.data(), ipb.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(drend, rend.data(), rend.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     sync(c);
+    dm.map.tab = dtab;
+    dm.map.ipb = dipb;
+    dm.map.rend = drend;
+    dm.map.nblk = nblk;
+    dm.map.ninst = ni;
 }
 
-// replay graph chunks until the device flag reports convergence; returns
-// iterations. With timing on, HIP events bracket every batch of replays and
-// the executed iterations of the batch are counted (speculative replays after
-// convergence return at once; their time stays in the measurement).
+int pad64(int n) { return (n + kSlice - 1) / kSlice * kSlice; }
+
+// Builds every device structure of a batch from the per-instance assemblies.
+void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> &nn, const std::vector<long> &nt) {
+    free_all(c);
+    const int ni = (int)as.size();
+    c->ninst = ni;
+    c->inst.assign(ni, InstInfo());
+    std::vector<int> moff(ni), poff(ni), boff(ni), nm(ni), np(ni), nb(ni);
+    int rm = 0, rp = 0, rb = 0;
+    long uo = 0;
+    for (int i = 0; i < ni; ++i) {
+        InstInfo &I = c->inst[i];
+        I.n_nodes = nn[i];
+        I.n_tets = nt[i];
+        I.n_mag = as[i].n_mag;
+        I.n_pot = as[i].n_pot;
+        I.n_brow = as[i].B.nrows;
+        I.mag_off = moff[i] = rm;
+        I.pot_off = poff[i] = rp;
+        I.brow_off = boff[i] = rb;
+        I.user_off = uo;
+        I.nnz_C = as[i].C.ptr.empty() ? 0 : as[i].C.ptr[as[i].C.nrows];
+        I.nnz_K = as[i].K.ptr.empty() ? 0 : as[i].K.ptr[as[i].K.nrows];
+        I.nnz_B = as[i].B.ptr.empty() ? 0 : as[i].B.ptr[as[i].B.nrows];
+        I.Ms_ref = as[i].Ms_ref;
+        I.node_of_mag = as[i].node_of_mag;
+        nm[i] = I.n_mag;
+        np[i] = I.n_pot;
+        nb[i] = I.n_brow;
+        rm += pad64(I.n_mag);
+        rp += pad64(I.n_pot);
+        rb += pad64(I.n_brow);
+        uo += I.n_mag;
+    }
+    c->rows_m = rm;
+    c->rows_p = rp;
+    c->rows_b = rb;
+    c->tot_mag = uo;
+    {
+        HostCsr C, S, K, B, Bt;
+        for (int i = 0; i < ni; ++i) {
+            append_csr(C, as[i].C, moff[i], moff[i], 0);
+            append_csr(S, as[i].S, moff[i], moff[i], 0);
+            append_csr(K, as[i].K, poff[i], poff[i], 0);
+            append_csr(B, as[i].B, boff[i], moff[i], poff[i]);
+            append_csr(Bt, as[i].Bt, moff[i], poff[i], 0);
+            as[i].C = HostCsr();
+            as[i].S = HostCsr();
+            as[i].K = HostCsr();
+            as[i].B = HostCsr();
+            as[i].Bt = HostCsr();
+        }
+        pad_rows(C, rm);
+        pad_rows(S, rm);
+        pad_rows(K, rp);
+        pad_rows(B, rb);
+        pad_rows(Bt, rm);
+        C.vw = 6;
+        S.vw = 1;
+        K.vw = 1;
+        B.vw = 3;
+        Bt.vw = 3;
+        upload_sell(c, C, c->C);
+        upload_sell(c, S, c->S);
+        upload_sell(c, K, c->K);
+        upload_sell(c, B, c->B);
+        upload_sell(c, Bt, c->Bt);
+    }
+    make_map(c, c->Mm, moff, nm, kBlock / kSlice);
+    make_map(c, c->Mp, poff, np, kPoissonBlock / kSlice);
+    make_map(c, c->Mb, boff, nb, kBlock / kSlice);
+
+    const size_t RM = std::max(rm, 1), RP = std::max(rp, 1);
+    c->L = dalloc_n<double>(c, RM);
+    c->invDex = dalloc_n<double>(c, RM);
+    c->invDK = dalloc_n<double>(c, RP);
+    c->invDK32 = dalloc_n<float>(c, RP);
+    {
+        std::vector<double> L(RM, 0.0), iD(RM, 1.0), iK(RP, 1.0);
+        for (int i = 0; i < ni; ++i) {
+            for (int a = 0; a < nm[i]; ++a) {
+                L[moff[i] + a] = as[i].L[a];
+                iD[moff[i] + a] = 1.0 / as[i].Dex[a];
+            }
+            for (int r = 0; r < np[i]; ++r) iK[poff[i] + r] = 1.0 / as[i].DK[r];
+        }
+        upload_vec(c, c->L, L);
+        upload_vec(c, c->invDex, iD);
+        upload_vec(c, c->invDK, iK);
+        launch_to_f32((int64_t)RP, c->invDK, c->invDK32, c->stream);
+    }
+    for (auto &s : c->st) {
+        s.x = dalloc_n<double>(c, 3 * RM);
+        s.G = dalloc_n<double>(c, 3 * RM);
+        s.g = dalloc_n<double>(c, 3 * RM);
+        s.lam = dalloc_n<double>(c, RM);
+    }
+    for (double **p : {&c->gprev, &c->d, &c->y, &c->pr, &c->pp, &c->pq, &c->tmp3}) *p = dalloc_n<double>(c, 3 * RM);
+    c->dscale = dalloc_n<double>(c, RM);
+    for (double **p : {&c->u, &c->b, &c->cr, &c->cp, &c->cp2, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
+    for (float **p : {&c->x32, &c->r32, &c->p32, &c->p32b, &c->q32}) *p = dalloc_n<float>(c, RP);
+    c->pst = dalloc_n<PcgState>(c, ni);
+    c->mpart = dalloc_n<double>(c, (size_t)MS_TOTAL * c->Mm.map.nblk);
+    c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
+    c->dci = dalloc_n<int>(c, 11 * (size_t)ni);
+    c->dcd = dalloc_n<double>(c, 8 * (size_t)ni);
+    c->dsc = dalloc_n<double>(c, (size_t)SC_PER * ni);
+    HIPCHK(hipHostMalloc((void **)&c->hci, 11 * (size_t)ni * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hcd, 8 * (size_t)ni * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hsc, (size_t)SC_PER * ni * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hpst, (size_t)ni * sizeof(PcgState), hipHostMallocDefault));
+    std::memset(c->hci, 0, 11 * (size_t)ni * sizeof(int));
+    std::memset(c->hcd, 0, 8 * (size_t)ni * sizeof(double));
+    std::memset(c->hsc, 0, (size_t)SC_PER * ni * sizeof(double));
+    std::memset(c->hpst, 0, (size_t)ni * sizeof(PcgState));
+    // every vector starts at zero (padding rows stay zero for good)
+    for (const StateV &s : c->st) {
+        HIPCHK(hipMemsetAsync(s.x, 0, 3 * RM * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(s.G, 0, 3 * RM * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(s.g, 0, 3 * RM * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(s.lam, 0, RM * sizeof(double), c->stream));
+    }
+    for (double *p : {c->gprev, c->d, c->y, c->pr, c->pp, c->pq, c->tmp3})
+        HIPCHK(hipMemsetAsync(p, 0, 3 * RM * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->dscale, 0, RM * sizeof(double), c->stream));
+    for (double *p : {c->u, c->b, c->cr, c->cp, c->cp2, c->cq, c->usave})
+        HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
+    for (float *p : {c->x32, c->r32, c->p32, c->p32b, c->q32})
+        HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->pst, 0, ni * sizeof(PcgState), c->stream));
+    HIPCHK(hipMemsetAsync(c->mpart, 0, (size_t)MS_TOTAL * c->Mm.map.nblk * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->ppart, 0, (size_t)kPcgSlots * c->Mp.map.nblk * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->dci, 0, 11 * (size_t)ni * sizeof(int), c->stream));
+    HIPCHK(hipMemsetAsync(c->dcd, 0, 8 * (size_t)ni * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->dsc, 0, (size_t)SC_PER * ni * sizeof(double), c->stream));
+    sync(c);
+    c->last_pcg.assign(ni, 16);
+    c->cnt.assign(ni, Cnt());
+    c->pcg_bytes64.assign(ni, 0.0);
+    c->pcg_bytes32.assign(ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        // kernel A: matrix + r, D^-1, p_old read + p_new, q written;
+        // kernel B: x, r, p, q, D^-1 read + x, r written
+        const double nnz = (double)c->inst[i].nnz_K, rows = (double)c->inst[i].n_pot;
+        c->pcg_bytes64[i] = nnz * (8.0 + 4.0) + 12.0 * 8.0 * rows;
+        c->pcg_bytes32[i] = nnz * (4.0 + 4.0) + 12.0 * 4.0 * rows;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scalar-potential solve K u = b (warm start u), Jacobi-PCG; FP64, or FP32 CG
+// inside FP64 defect correction
+// ---------------------------------------------------------------------------
+PcgLaunch pcg_args(mm_ctx *c) {
+    PcgLaunch a;
+    a.K = &c->K;
+    a.M = &c->Mp.map;
+    a.st = c->pst;
+    a.part = c->ppart;
+    a.u = c->u;
+    a.b = c->b;
+    a.r = c->cr;
+    a.p0 = c->cp;
+    a.p1 = c->cp2;
+    a.q = c->cq;
+    a.invD = c->invDK;
+    a.x32 = c->x32;
+    a.r32 = c->r32;
+    a.p32a = c->p32;
+    a.p32b = c->p32b;
+    a.q32 = c->q32;
+    a.invD32 = c->invDK32;
+    a.pin = c->d_(c->pin());
+    return a;
+}
+
+void pcg_chunk(mm_ctx *c, bool fp32) {
+    PcgLaunch a = pcg_args(c);
+    for (int j = 0; j < kPcgChunk; ++j) {
+        if (fp32) launch_pcg_iter32(a, 2 * j + 2, j & 1, c->stream);
+        else launch_pcg_iter64(a, 2 * j + 2, j & 1, c->stream);
+    }
+}
+
 bool use_graphs() {
     static bool on = [] {
         const char *e = std::getenv("MMNCG_NO_GRAPH");
@@ -381,223 +623,298 @@ bool use_graphs() {
     return on;
 }
 
-void pcg_chunk_eager(mm_ctx *c, bool fp32) {
-    hipStream_t s = c->stream;
-    for (int j = 0; j < kPcgChunk; ++j) {
-        const int ph = 2 * j + 2;
-        if (fp32) {
-            float *po = (j & 1) ? c->p32b : c->p32, *pn = (j & 1) ? c->p32 : c->p32b;
-            launch_pcg_iter32(c->K, c->x32, c->r32, po, pn, c->q32, c->invDK32, c->pst, ph, j & 1, c->ppart, s);
-        } else {
-            double *po = (j & 1) ? c->cp2 : c->cp, *pn = (j & 1) ? c->cp : c->cp2;
-            launch_pcg_iter64(c->K, c->u, c->cr, po, pn, c->cq, c->invDK, c->pst, ph, j & 1, c->ppart, s);
-        }
+// capture kPcgChunk iterations (2 kernels each) once per context and mode
+hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32) {
+    hipGraphExec_t &ge = fp32 ? c->graph32 : c->graph64;
+    if (ge) return ge;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        pcg_chunk(c, fp32);
+    } catch (...) {
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
     }
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return ge;
 }
 
-long pcg_replay(mm_ctx *c, bool fp32, long maxit) {
+void pull_pcg(mm_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->hpst, c->pst, c->ninst * sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
+// Replays graph chunks until every instance in `on` reports convergence;
+// iteration counts are left in hpst. With timing on, HIP events bracket every
+// batch of replays and the executed iterations (and their algorithmic bytes)
+// are counted per instance; replays after an instance converged return at once
+// and their time stays in the measurement.
+void pcg_replay(mm_ctx *c, bool fp32, long maxit, const std::vector<int> &on) {
     hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32) : nullptr;
-    long expect = std::max<long>(kPcgChunk, c->last_poisson_iters);
+    long expect = kPcgChunk;
+    for (int i : on) expect = std::max(expect, c->last_pcg[i]);
     long nrep = (expect + kPcgChunk - 1) / kPcgChunk;
-    long launched = 0, seen = 0;
+    long launched = 0;
+    std::vector<int> seen(c->ninst, 0);
+    const std::vector<double> &bytes = fp32 ? c->pcg_bytes32 : c->pcg_bytes64;
     for (;;) {
         prof_mark(c);
         for (long k = 0; k < nrep; ++k) {
             if (ge) HIPCHK(hipGraphLaunch(ge, c->stream));
-            else pcg_chunk_eager(c, fp32);
+            else pcg_chunk(c, fp32);
         }
         prof_mark(c);
         launched += nrep * kPcgChunk;
         pull_pcg(c);
         if (c->prof_on) {
             prof_harvest(c);
-            c->prof_units += c->hpst->iters - seen;
-            seen = c->hpst->iters;
+            for (int i : on) {
+                int di = c->hpst[i].iters - seen[i];
+                c->prof_units += di;
+                c->prof_bytes += di * bytes[i];
+                seen[i] = c->hpst[i].iters;
+            }
         }
-        if (c->hpst->done || c->hpst->zero_u) break;
+        bool all = true;
+        for (int i : on) all = all && (c->hpst[i].done || c->hpst[i].zero_u);
+        if (all) break;
         if (launched >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
         nrep = std::max<long>(1, (expect / 8 + kPcgChunk - 1) / kPcgChunk);
     }
-    return c->hpst->iters;
 }
 
-long poisson_fp64(mm_ctx *c, double rtol, long maxit) {
-    const int n = c->n_pot();
-    if (n == 0) return 0;
-    launch_pcg_init64(c->K, c->b, c->u, c->cr, c->invDK, rtol * rtol, c->pst, c->ppart, false, c->stream);
-    long it = pcg_replay(c, false, maxit);
-    if (c->hpst->zero_u) {
-        HIPCHK(hipMemsetAsync(c->u, 0, n * sizeof(double), c->stream));
-        return 0;
-    }
-    c->last_poisson_iters = std::max<long>(4, it);
-    return it;
+void zero_pot(mm_ctx *c, int i) {
+    launch_fill(c->inst[i].n_pot, c->u + c->inst[i].pot_off, 0.0, c->stream);
 }
 
-long poisson_fp32(mm_ctx *c, double rtol, long maxit) {
-    const int n = c->n_pot();
-    if (n == 0) return 0;
-    hipStream_t s = c->stream;
-    long total = 0;
-    for (int outer = 0; outer < 50; ++outer) {
-        launch_residual64(c->K, c->b, c->u, c->cr, c->pst, c->ppart, s);
-        pull_pcg(c);
-        double bb = c->hpst->bb, rr = c->hpst->rr;
-        if (bb == 0.0) {
-            HIPCHK(hipMemsetAsync(c->u, 0, n * sizeof(double), s));
-            return total;
+// FP64 CG for the instances with act[i] set (uploaded); returns per-instance iterations
+std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
+    std::vector<long> it(c->ninst, 0);
+    PcgLaunch a = pcg_args(c);
+    launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, false, c->stream);
+    pcg_replay(c, false, maxit, on);
+    for (int i : on) {
+        if (c->hpst[i].zero_u) {
+            zero_pot(c, i);
+            continue;
         }
-        if (rr <= rtol * rtol * bb) return total;
-        double rn = std::sqrt(rr);
-        // relative target of the inner FP32 solve: not beyond what the last correction needs
-        double inner = std::max(1e-5, 0.5 * rtol * std::sqrt(bb) / rn);
-        inner = std::min(inner, 1e-1);
-        launch_pcg_init32(n, c->cr, 1.0 / rn, c->x32, c->r32, c->invDK32, inner * inner, c->pst, c->ppart, s);
-        long it = pcg_replay(c, true, maxit - total);
-        total += it;
-        c->last_poisson_iters = std::max<long>(4, it);
-        launch_add_correction(n, c->u, c->x32, rn, s);
-        if (total >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
+        it[i] = c->hpst[i].iters;
+        c->last_pcg[i] = std::max<long>(4, it[i]);
     }
-    throw ApiError{MM_NOT_CONVERGED, "scalar-potential defect correction did not converge"};
+    return it;
 }
 
-long poisson(mm_ctx *c, double rtol, long maxit, bool fp32) {
-    HIPCHK(hipEventRecord(c->ev[0], c->stream));
-    long it = fp32 ? poisson_fp32(c, rtol, maxit) : poisson_fp64(c, rtol, maxit);
-    HIPCHK(hipEventRecord(c->ev[1], c->stream));
-    HIPCHK(hipEventSynchronize(c->ev[1]));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    c->t_mag += ms * 1e-3;
-    c->c_mi += it;
-    return it;
+std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
+    std::vector<long> total(c->ninst, 0);
+    PcgLaunch a = pcg_args(c);
+    std::vector<int> live = on;
+    int *pl = c->plive();
+    double *pin = c->pin();
+    for (int outer = 0; outer < 50 && !live.empty(); ++outer) {
+        // the first residual serves the instances of act[] (already uploaded);
+        // later ones the instances still correcting (the host writes plive
+        // only after the synchronization of the previous pass)
+        const int *live_dev = c->d_(c->act());
+        if (outer > 0) {
+            std::fill(pl, pl + c->ninst, 0);
+            for (int i : live) pl[i] = 1;
+            upload_ctl(c);
+            live_dev = c->d_(pl);
+        }
+        launch_residual64(a, live_dev, c->stream);
+        pull_pcg(c);
+        std::vector<int> inner;
+        for (int k = 0; k < c->ninst; ++k) pin[4 * k + 1] = 0.0;
+        for (int i : live) {
+            const double bb = c->hpst[i].bb, rr = c->hpst[i].rr;
+            if (bb == 0.0) {
+                zero_pot(c, i);
+                continue;
+            }
+            if (rr <= rtol * rtol * bb) continue;
+            const double rn = std::sqrt(rr);
+            // relative target of the inner FP32 solve: not beyond what the last correction needs
+            double tol = std::max(1e-5, 0.5 * rtol * std::sqrt(bb) / rn);
+            tol = std::min(tol, 1e-1);
+            pin[4 * i] = 1.0 / rn;
+            pin[4 * i + 1] = tol * tol;
+            pin[4 * i + 2] = rn;
+            inner.push_back(i);
+        }
+        live = inner;
+        if (live.empty()) break;
+        upload_ctl(c);
+        launch_pcg_init32(a, c->stream);
+        long cap = 0;
+        for (int i : live) cap = std::max(cap, maxit - total[i]);
+        pcg_replay(c, true, cap, live);
+        for (int i : live) {
+            total[i] += c->hpst[i].iters;
+            c->last_pcg[i] = std::max<long>(4, c->hpst[i].iters);
+            if (total[i] >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
+        }
+        launch_add_correction(a, c->stream);
+    }
+    if (!live.empty()) throw ApiError{MM_NOT_CONVERGED, "scalar-potential defect correction did not converge"};
+    for (int k = 0; k < c->ninst; ++k) pin[4 * k + 1] = 0.0;
+    return total;
+}
+
+// solve for the instances in `on` (act[] uploaded with exactly these set)
+void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<int> &on) {
+    if (on.empty() || c->rows_p == 0) return;
+    const double t0 = now_s();
+    std::vector<long> it = fp32 ? poisson_fp32(c, rtol, maxit, on) : poisson_fp64(c, rtol, maxit, on);
+    sync(c);
+    const double dt = now_s() - t0;
+    for (int i : on) {
+        c->cnt[i].mi += it[i];
+        c->cnt[i].t_mag += dt;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// evaluation at st.x (energy, gradient, projection), optionally with the
-// line-search extras relative to the state x0 along d with step alpha
+// batched evaluation: every instance with act[i] evaluates its state role[i]
+// (0 current; 1, 2: trial N(x + alpha_i d) relative to the current state).
+// Fills act/role/alpha/h3 of the control block beforehand.
 // ---------------------------------------------------------------------------
 int cmode_of(int terms) { return ((terms & MM_T_EXCH) ? 1 : 0) | ((terms & MM_T_ANIS) ? 2 : 0); }
 
-void eval(mm_ctx *c, State &st, const double h[3], const mm_opts &o, const State *x0 = nullptr,
-          double alpha = 0.0, double *dF = nullptr, double *dphi = nullptr, double *dxinf = nullptr) {
+void eval_round(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool any_trial) {
     hipStream_t s = c->stream;
     const bool fp32 = o.precision == MM_FP32_BULK;
-    const int nm = c->n_mag();
-    const bool demag = (o.terms & MM_T_DEMAG) && c->n_pot() > 0 && c->B.nrows > 0;
+    if (!(o.terms & MM_T_ZEE)) std::fill(c->h3(), c->h3() + 3 * c->ninst, 0.0);
+    upload_ctl(c);
+    const int *act = c->d_(c->act()), *role = c->d_(c->role());
+    const double *alpha = c->d_(c->alpha());
+    if (any_trial) launch_trial(c->Mm.map, act, role, c->st, c->d, alpha, s);
+    const bool demag = (o.terms & MM_T_DEMAG) && c->rows_p > 0 && c->B.nrows > 0;
     if (demag) {
-        launch_bmul(c->B, st.x, c->b, fp32, s);
-        poisson(c, o.poisson_rtol, o.poisson_maxit, fp32);
+        launch_bmul(c->B, c->Mb.map, act, c->st, role, c->b, fp32, s);
+        poisson(c, o.poisson_rtol, o.poisson_maxit, fp32, on);
     }
-    double hz[3] = {0, 0, 0};
-    if (o.terms & MM_T_ZEE)
-        for (int k = 0; k < 3; ++k) hz[k] = h[k];
-    launch_eval_epilogue(c->C, c->S, c->Bt, cmode_of(o.terms), demag ? 1 : 0, st.x, c->u, c->L, hz, st.G, st.g,
-                         st.lam, x0 ? x0->x : nullptr, x0 ? x0->g : nullptr, x0 ? x0->lam : nullptr,
-                         x0 ? c->d : nullptr, alpha, partp(c, PS_EVAL), fp32, s);
-    launch_finalize(partp(c, PS_EVAL), grid_for_rows(nm), kEvalParts, eval_max_mask(), c->dsc + SC_EVAL, s);
-    pull(c, SC_EVAL, kEvalParts);
-    const double *r = c->hsc + SC_EVAL;
-    st.Eloc = r[0];
-    st.Ez = r[1];
-    st.Ed = r[2];
-    st.E = r[0] + r[1] + r[2];
-    st.tmax = r[6];
-    st.ginf = r[7];
-    st.minf = r[9];
-    if (dF) *dF = r[3];
-    if (dphi) *dphi = r[4];
-    if (dxinf) *dxinf = r[8];
-    c->c_evals++;
+    EvalLaunch e;
+    e.C = &c->C;
+    e.S = &c->S;
+    e.Bt = &c->Bt;
+    e.M = &c->Mm.map;
+    e.cmode = cmode_of(o.terms);
+    e.use_demag = demag ? 1 : 0;
+    e.act = act;
+    e.role = role;
+    for (int k = 0; k < 3; ++k) e.st[k] = c->st[k];
+    e.u = c->u;
+    e.L = c->L;
+    e.h3 = c->d_(c->h3());
+    e.d = c->d;
+    e.alpha = alpha;
+    e.part = mslot(c, MS_EVAL);
+    e.fp32 = fp32;
+    launch_eval_epilogue(e, s);
+    launch_finalize_inst(c->Mm.map, mslot(c, MS_EVAL), kEvalParts, eval_max_mask(), dsc_at(c, SC_EVAL), s);
+    pull_sc(c, SC_EVAL, kEvalParts);
+    sync(c);
+    for (int i : on) c->cnt[i].evals++;
 }
 
-double exchange_energy(mm_ctx *c, const double *m, bool fp32) {
-    launch_energy_split(c->S, m, partp(c, PS_MISC), fp32, c->stream);
-    launch_finalize(partp(c, PS_MISC), grid_for_rows(c->n_mag()), 1, 0u, c->dsc + SC_MISC, c->stream);
-    pull(c, SC_MISC, 1);
-    return c->hsc[SC_MISC];
+Sc eval_result(mm_ctx *c, int i) {
+    const double *r = hsc_at(c, SC_EVAL) + (size_t)kEvalParts * i;
+    Sc v;
+    v.Eloc = r[0];
+    v.Ez = r[1];
+    v.Ed = r[2];
+    v.E = r[0] + r[1] + r[2];
+    v.dF = r[3];
+    v.dphi = r[4];
+    v.tmax = r[6];
+    v.ginf = r[7];
+    v.dxinf = r[8];
+    v.minf = r[9];
+    return v;
 }
 
-void energy_parts(mm_ctx *c, const State &st, const mm_opts &o, double E[5]) {
+// exchange / anisotropy split of Eloc for instance i at the current state
+void energy_parts(mm_ctx *c, int i, const Sc &v, const mm_opts &o, double E[5]) {
     const bool fp32 = o.precision == MM_FP32_BULK;
     double ex = 0.0, an = 0.0;
-    int cm = cmode_of(o.terms);
+    const int cm = cmode_of(o.terms);
     if (cm == 3) {
-        ex = exchange_energy(c, st.x, fp32);
-        an = st.Eloc - ex;
+        launch_energy_split(c->S, c->Mm.map, c->st[0].x, mslot(c, MS_MISC), fp32, c->stream);
+        launch_finalize_inst(c->Mm.map, mslot(c, MS_MISC), 1, 0u, dsc_at(c, SC_MISC), c->stream);
+        pull_sc(c, SC_MISC, 1);
+        sync(c);
+        ex = hsc_at(c, SC_MISC)[i];
+        an = v.Eloc - ex;
     } else if (cm == 1) {
-        ex = st.Eloc;
+        ex = v.Eloc;
     } else if (cm == 2) {
-        an = st.Eloc;
+        an = v.Eloc;
     }
     E[0] = ex;
     E[1] = an;
-    E[2] = st.Ez;
-    E[3] = st.Ed;
-    E[4] = st.E;
+    E[2] = v.Ez;
+    E[3] = v.Ed;
+    E[4] = v.E;
 }
 
-// ---------------------------------------------------------------------------
-// preconditioner: at most jmax steps of Alg. 1 on P y = g (exits li1-li3);
-// the iteration count is fetched at the next synchronization
-// ---------------------------------------------------------------------------
-void precondition(mm_ctx *c, const State &st, int jmax, const double *dscale, const mm_opts &o) {
-    hipStream_t s = c->stream;
-    const int nm = c->n_mag();
-    const bool fp32 = o.precision == MM_FP32_BULK;
-    HIPCHK(hipEventRecord(c->ev[2], s));
-    if (jmax <= 0) {
-        HIPCHK(hipMemcpyAsync(c->y, st.g, 3 * (size_t)nm * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemsetAsync(c->dflags + FL_PREC, 0, 4 * sizeof(int), s));
-    } else {
-        int *fl = c->dflags + FL_PREC;
-        launch_prec_init(nm, st.g, c->invDex, dscale, c->y, c->pr, c->pp, partp(c, PS_PR_INIT), fl, s);
-        for (int j = 0; j < jmax; ++j) {
-            const double *prev = (j == 0) ? partp(c, PS_PR_INIT) : partp(c, (j & 1) ? PS_PR_RZ1 : PS_PR_RZ0);
-            double *nw = partp(c, ((j + 1) & 1) ? PS_PR_RZ1 : PS_PR_RZ0);
-            const int ph = 3 * j;
-            launch_prec_apply(c->C, st.x, st.lam, c->pp, c->pq, partp(c, PS_PR_PQ), fl, ph + 1, fp32, s);
-            launch_prec_update(nm, j, st.g, c->invDex, dscale, c->y, c->pr, c->pp, c->pq, partp(c, PS_PR_PQ), prev, 0,
-                               nw, fl, ph + 2, s);
-            if (j + 1 < jmax)
-                launch_prec_pupdate(nm, c->invDex, dscale, c->pp, c->pr, partp(c, PS_PR_INIT), nw, prev, 0, fl,
-                                    ph + 3, s);
-        }
+// preconditioner for the instances with pact[i]: at most jmax steps of Alg. 1
+// on P y = g at the current state (exits li1-li3)
+void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32) {
+    PrecLaunch a;
+    a.C = &c->C;
+    a.M = &c->Mm.map;
+    a.act = c->d_(c->pact());
+    a.m = c->st[0].x;
+    a.lam = c->st[0].lam;
+    a.g = c->st[0].g;
+    a.invDex = c->invDex;
+    a.dscale = dscale;
+    a.y = c->y;
+    a.r = c->pr;
+    a.p = c->pp;
+    a.q = c->pq;
+    a.part = mslot(c, MS_PREC);
+    a.flags = c->d_(c->pflags());
+    a.fp32 = fp32;
+    launch_prec_init(a, c->stream);
+    for (int j = 0; j < jmax; ++j) launch_prec_iter(a, j, j + 1 == jmax, c->stream);
+}
+
+// load m (caller layout, host or device) into the current state and check
+// that it holds finite unit vectors
+void load_m(mm_ctx *c, const double *m) {
+    for (const InstInfo &I : c->inst)
+        copy_in(c, c->st[0].x + 3 * (size_t)I.mag_off, m + 3 * I.user_off, 3 * (size_t)I.n_mag);
+    launch_mavg(c->Mm.map, c->st[0].x, c->L, mslot(c, MS_MISC), c->stream);
+    launch_finalize_inst(c->Mm.map, mslot(c, MS_MISC), 5, 1u << 4, dsc_at(c, SC_MISC), c->stream);
+    pull_sc(c, SC_MISC, 5);
+    sync(c);
+    for (int i = 0; i < c->ninst; ++i) {
+        double dev = hsc_at(c, SC_MISC)[5 * i + 4];
+        if (!(dev <= 1e-6))
+            throw ApiError{MM_EINVAL, "m must hold finite unit vectors (instance " + std::to_string(i) +
+                                          ": max | |m_i| - 1 | = " + std::to_string(dev) + ")"};
     }
-    HIPCHK(hipEventRecord(c->ev[3], s));
-    HIPCHK(hipMemcpyAsync(c->hflags + FL_PREC, c->dflags + FL_PREC, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
 }
-void account_precondition(mm_ctx *c) {
-    // call after a synchronization that follows precondition()
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-    c->t_lin += ms * 1e-3;
-    c->c_li += c->hflags[FL_PREC + 1];
+void store_m(mm_ctx *c, double *m) {
+    for (const InstInfo &I : c->inst)
+        copy_out(c, m + 3 * I.user_off, c->st[0].x + 3 * (size_t)I.mag_off, 3 * (size_t)I.n_mag);
 }
 
-// direction: first -> d = -y (or -g); else beta*ZA with the descent safeguard.
-// returns phi'(0) = <g1, d>, dmax and the safeguard mode (0, 1, 2)
-void direction(mm_ctx *c, const State &s1, const State *s0, bool first, double *dp0, double *dmax, int *mode) {
-    hipStream_t s = c->stream;
-    const int nm = c->n_mag();
-    int nb = 0;
-    launch_dir_dots(nm, s1.g, first ? nullptr : s0->g, c->y, first ? nullptr : c->d, partp(c, PS_DIR_DOTS), &nb, s);
-    launch_dir_update(nm, s1.g, c->y, c->d, partp(c, PS_DIR_DOTS), nb, first ? 1 : 0, partp(c, PS_DIR_OUT),
-                      c->dflags + FL_DIR, s);
-    launch_finalize(partp(c, PS_DIR_OUT), grid_for_rows(nm), 2, 2u, c->dsc + SC_DIR, s);
-    HIPCHK(hipMemcpyAsync(c->hflags + FL_DIR, c->dflags + FL_DIR, sizeof(int), hipMemcpyDeviceToHost, s));
-    pull(c, SC_DIR, 2);
-    *dp0 = c->hsc[SC_DIR];
-    *dmax = c->hsc[SC_DIR + 1];
-    *mode = c->hflags[FL_DIR];
+void reduce_field(const InstInfo &I, const double *BT, double h[3]) {
+    for (int k = 0; k < 3; ++k) h[k] = BT[k] / (kMu0 * I.Ms_ref);
+}
+
+void set_h3(mm_ctx *c, int i, const double h[3]) {
+    for (int k = 0; k < 3; ++k) c->h3()[3 * i + k] = h[k];
 }
 
 // ---------------------------------------------------------------------------
-// line search on phi(alpha) = F(N(x + alpha d)): capped rotation, sufficient
-// decrease on the exact quadratic energy difference, one cubic interpolation,
-// then halving (the paper asks only for an approximate search that avoids too
-// long steps)
+// the batched minimizer: Alg. 4 per instance over its list of field values
 // ---------------------------------------------------------------------------
 bool cubic_step(double at, double dFt, double dp0, double dpt, double *ac) {
     double d1 = dp0 + dpt - 3.0 * dFt / at;
@@ -612,61 +929,6 @@ bool cubic_step(double at, double dFt, double dp0, double dpt, double *ac) {
     return true;
 }
 
-struct LsResult {
-    bool ok;
-    int idx;        // state index holding the accepted point
-    double alpha;
-    double dF;
-    double dxinf;
-};
-
-LsResult line_search(mm_ctx *c, const mm_opts &o, const double h[3], int i0, double dp0, double dmax, double a0) {
-    const int nm = c->n_mag();
-    int iA = (i0 + 1) % 3, iB = (i0 + 2) % 3;
-    State &s0 = c->st[i0];
-    auto trial = [&](int idx, double alpha, double *dF, double *dp, double *dx) {
-        launch_trial(nm, s0.x, c->d, alpha, c->st[idx].x, c->stream);
-        eval(c, c->st[idx], h, o, &s0, alpha, dF, dp, dx);
-    };
-    LsResult res{false, i0, 0, 0, 0};
-    if (!(dmax > 0.0)) return res;
-    double amax = o.theta_max / dmax;
-    double at = std::min(a0, amax);
-    double dFt, dpt, dxt;
-    trial(iA, at, &dFt, &dpt, &dxt);
-    bool arm_t = dFt <= o.c1 * at * dp0;
-    if (arm_t && std::fabs(dpt) <= o.c2 * std::fabs(dp0)) return LsResult{true, iA, at, dFt, dxt};
-    bool over = !arm_t || dpt > 0.0;
-    if (!over && at >= amax) return LsResult{true, iA, at, dFt, dxt};
-    double ac;
-    if (!cubic_step(at, dFt, dp0, dpt, &ac)) ac = over ? 0.5 * at : std::min(2.0 * at, amax);
-    if (over) {
-        ac = std::max(ac, 0.1 * at);
-        ac = std::min(ac, 0.9 * at);
-    } else {
-        double hi = std::min(4.0 * at, amax);
-        ac = std::min(ac, hi);
-        ac = std::max(ac, 1.1 * at);
-        if (ac > hi) return LsResult{true, iA, at, dFt, dxt};
-    }
-    double dFc, dpc, dxc;
-    trial(iB, ac, &dFc, &dpc, &dxc);
-    if (dFc <= o.c1 * ac * dp0) return LsResult{true, iB, ac, dFc, dxc};
-    if (arm_t) return LsResult{true, iA, at, dFt, dxt};
-    double a = std::min(at, ac);
-    for (int k = 0; k < o.ls_max_halvings; ++k) {
-        a *= 0.5;
-        double dFa, dpa, dxa;
-        trial(iA, a, &dFa, &dpa, &dxa);
-        if (dFa <= o.c1 * a * dp0) return LsResult{true, iA, a, dFa, dxa};
-    }
-    return res;
-}
-
-// ---------------------------------------------------------------------------
-// Alg. 4 for one reduced field; the start point is in st[*cur].x; on return
-// *cur indexes the final state
-// ---------------------------------------------------------------------------
 int trace_level() {
     static int lvl = [] {
         const char *e = std::getenv("MMNCG_TRACE");
@@ -675,119 +937,339 @@ int trace_level() {
     return lvl;
 }
 
-int minimize(mm_ctx *c, int *cur, const double h[3], const mm_opts &o, mm_stats *stats) {
-    auto t0 = std::chrono::steady_clock::now();
-    c->c_evals = c->c_mi = c->c_li = 0;
-    c->t_mag = c->t_lin = 0;
+enum Step { S_IDLE = 0, S_EVAL0, S_TRIAL_T, S_TRIAL_C, S_HALVE, S_NEED_DIR, S_FIELD_DONE };
+
+struct Run {
+    int step = S_IDLE;
+    long field = 0;
+    double h[3] = {0, 0, 0};
+    Sc cur, trial;
+    // direction state
+    int dirmode = 0;         // first[] bits for the next direction
+    bool restarting = false;  // the next direction is the steepest-descent restart
+    bool first = true;
+    double dp0 = 0, dmax = 0, a_prev = 0, dp_prev = 0;
+    // line search
+    bool restart_ls = false, arm_t = false;
+    double amax = 0, a0 = 0, at = 0, ac = 0, a = 0, dFt = 0;
+    Sc sT;                   // scalars of the trial kept in buffer T
+    int halvings = 0;
+    // per-field accounting
     long nli = 0, restarts = 0, fallbacks = 0;
-    int i0 = *cur;
-    eval(c, c->st[i0], h, o);
-    int status = MM_NOT_CONVERGED;
-    if (o.stop_mode == MM_STOP_TORQUE && c->st[i0].tmax < o.tol_torque) {
-        status = MM_OK;
-    } else {
-        precondition(c, c->st[i0], o.jmax, nullptr, o);
-        double dp0, dmax;
-        int mode;
-        direction(c, c->st[i0], nullptr, true, &dp0, &dmax, &mode);
-        account_precondition(c);
-        if (mode != 0) fallbacks++;
-        bool first = true;
-        double a_prev = 0, dp_prev = 0;
-        for (long it = 0; it < o.max_nli; ++it) {
-            if (!(dp0 < 0.0)) {
-                status = MM_OK;
-                break;
-            }
-            double a0 = first ? (o.jmax > 0 ? 1.0 : o.theta_init / dmax) : a_prev * dp_prev / dp0;
-            LsResult ls = line_search(c, o, h, i0, dp0, dmax, a0);
-            if (!ls.ok) {
-                restarts++;
-                // steepest descent restart: d = -g (direction() with y = g, first = true)
-                HIPCHK(hipMemcpyAsync(c->y, c->st[i0].g, 3 * (size_t)c->n_mag() * sizeof(double),
-                                      hipMemcpyDeviceToDevice, c->stream));
-                direction(c, c->st[i0], nullptr, true, &dp0, &dmax, &mode);
-                if (!(dp0 < 0.0) || !(dmax > 0.0)) {
-                    status = MM_STALLED;
-                    break;
+    Cnt c0;
+    double t0 = 0;
+    int status = MM_OK;
+    bool prec_ran = false;
+};
+
+struct CurveOut {
+    double *m_avg = nullptr;    // [ninst][nfield][3]
+    double *E_tot = nullptr;    // [ninst][nfield]
+    mm_stats *st = nullptr;     // [ninst][nfield]
+    double *m_hist = nullptr;   // single instance: [nfield][n_mag][3]
+};
+
+class Driver {
+public:
+    Driver(mm_ctx *c, const mm_opts &o, const std::vector<double> &hred, long nfield, const CurveOut &out)
+        : c_(c), o_(o), h_(hred), nf_(nfield), out_(out), r_(c->ninst) {}
+
+    int run() {
+        const int n = c_->ninst;
+        for (int i = 0; i < n; ++i) start_field(i, 0);
+        for (;;) {
+            // ---- 1. evaluation of every instance that needs one
+            std::vector<int> on;
+            bool any_trial = false;
+            for (int i = 0; i < n; ++i) {
+                Run &R = r_[i];
+                int a = 0, rl = 0;
+                double al = 0.0;
+                switch (R.step) {
+                    case S_EVAL0: a = 1; break;
+                    case S_TRIAL_T: a = 1; rl = 1; al = R.at; break;
+                    case S_HALVE: a = 1; rl = 1; al = R.a; break;
+                    case S_TRIAL_C: a = 1; rl = 2; al = R.ac; break;
+                    default: break;
                 }
-                ls = line_search(c, o, h, i0, dp0, dmax, o.theta_init / dmax);
-                if (!ls.ok) {
-                    status = MM_STALLED;
-                    break;
+                c_->act()[i] = a;
+                c_->role()[i] = rl;
+                c_->alpha()[i] = al;
+                c_->from()[i] = 0;
+                c_->pact()[i] = 0;
+                c_->first()[i] = 0;
+                set_h3(c_, i, R.h);
+                if (a) on.push_back(i);
+                any_trial = any_trial || rl != 0;
+            }
+            bool busy = !on.empty();
+            for (int i = 0; i < n; ++i) busy = busy || r_[i].step == S_NEED_DIR || r_[i].step == S_FIELD_DONE;
+            if (!busy) break;
+            if (!on.empty()) {
+                eval_round(c_, o_, on, any_trial);
+                for (int i : on) after_eval(i, eval_result(c_, i));
+            }
+            // ---- 2. copy accepted trials, precondition and direction
+            std::vector<int> dir, fin;
+            bool any_from = false, any_prec = false;
+            for (int i = 0; i < n; ++i) {
+                Run &R = r_[i];
+                c_->act()[i] = 0;
+                any_from = any_from || c_->from()[i] != 0;
+                if (R.step == S_NEED_DIR) {
+                    c_->act()[i] = 1;
+                    c_->first()[i] = R.dirmode;
+                    R.prec_ran = !(R.dirmode & 2) && o_.jmax > 0;
+                    c_->pact()[i] = R.prec_ran ? 1 : 0;
+                    any_prec = any_prec || R.prec_ran;
+                    dir.push_back(i);
                 }
+                if (R.step == S_FIELD_DONE) fin.push_back(i);
             }
-            nli++;
-            State &s1 = c->st[ls.idx];
-            State &s0 = c->st[i0];
-            if (trace_level() > 0 && (nli <= 40 || nli % 100 == 0))
-                std::fprintf(stderr,
-                             "[mmncg] nli %ld alpha %.4e amax %.4e a0 %.4e dp0 %.4e dF %.4e dE %.4e tmax %.4e "
-                             "E %.12e evals %ld\n",
-                             nli, ls.alpha, o.theta_max / dmax, a0, dp0, ls.dF, s1.E - s0.E, s1.tmax, s1.E,
-                             c->c_evals);
-            bool conv;
-            if (o.stop_mode == MM_STOP_TORQUE) {
-                conv = s1.tmax < o.tol_torque;
-            } else {
-                double tau = o.tau_F;
-                bool t1 = (s0.E - s1.E) < tau * (1.0 + std::fabs(s1.E));
-                bool t2 = ls.dxinf < std::sqrt(tau) * (1.0 + s1.minf);
-                bool t3 = s1.ginf < std::cbrt(tau) * (1.0 + std::fabs(s1.E));
-                conv = t1 && t2 && t3;
+            if (!any_from && dir.empty() && fin.empty()) continue;
+            upload_ctl(c_);
+            hipStream_t s = c_->stream;
+            if (any_from) launch_copy_state(c_->Mm.map, c_->d_(c_->from()), c_->st, c_->gprev, s);
+            if (any_prec) {
+                HIPCHK(hipEventRecord(c_->ev[2], s));
+                precondition(c_, o_.jmax, nullptr, o_.precision == MM_FP32_BULK);
+                HIPCHK(hipEventRecord(c_->ev[3], s));
             }
-            if (conv) {
-                i0 = ls.idx;
-                status = MM_OK;
+            if (!dir.empty()) {
+                launch_dir(c_->Mm.map, c_->d_(c_->act()), c_->d_(c_->first()), c_->st[0].g, c_->gprev, c_->y, c_->d,
+                           mslot(c_, MS_DOTS), mslot(c_, MS_DOUT), c_->d_(c_->info()), s);
+                launch_finalize_inst(c_->Mm.map, mslot(c_, MS_DOUT), 2, 2u, dsc_at(c_, SC_DIR), s);
+                pull_sc(c_, SC_DIR, 2);
+                pull_flags(c_);
+            }
+            if (!fin.empty() && out_.m_avg) {
+                launch_mavg(c_->Mm.map, c_->st[0].x, c_->L, mslot(c_, MS_MISC), s);
+                launch_finalize_inst(c_->Mm.map, mslot(c_, MS_MISC), 4, 0u, dsc_at(c_, SC_MISC), s);
+                pull_sc(c_, SC_MISC, 4);
+            }
+            sync(c_);
+            if (any_prec) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, c_->ev[2], c_->ev[3]));
+                for (int i : dir)
+                    if (r_[i].prec_ran) c_->cnt[i].t_lin += ms * 1e-3;
+            }
+            for (int i : fin) finish_field(i);
+            for (int i : dir) after_dir(i);
+        }
+        return worst_;
+    }
+
+    const Sc &final_scalars(int i) const { return r_[i].cur; }
+    long last_nli(int i) const { return r_[i].nli; }
+
+private:
+    mm_ctx *c_;
+    const mm_opts &o_;
+    const std::vector<double> &h_;
+    long nf_;
+    CurveOut out_;
+    std::vector<Run> r_;
+    int worst_ = MM_OK;
+
+    void start_field(int i, long k) {
+        Run &R = r_[i];
+        if (k >= nf_) {
+            R.step = S_IDLE;
+            return;
+        }
+        R.field = k;
+        for (int q = 0; q < 3; ++q) R.h[q] = h_[(size_t)3 * (i * nf_ + k) + q];
+        R.step = S_EVAL0;
+        R.first = true;
+        R.restarting = false;
+        R.a_prev = R.dp_prev = 0.0;
+        R.nli = R.restarts = R.fallbacks = 0;
+        R.c0 = c_->cnt[i];
+        R.t0 = now_s();
+        R.status = MM_NOT_CONVERGED;
+    }
+
+    void finish(int i, int status) {
+        r_[i].status = status;
+        r_[i].step = S_FIELD_DONE;
+    }
+
+    void need_dir(int i, int mode, bool restart) {
+        Run &R = r_[i];
+        R.dirmode = mode | (o_.jmax > 0 ? 0 : 2);
+        R.restarting = restart;
+        R.step = S_NEED_DIR;
+    }
+
+    void after_eval(int i, const Sc &v) {
+        Run &R = r_[i];
+        switch (R.step) {
+            case S_EVAL0:
+                R.cur = v;
+                if (o_.stop_mode == MM_STOP_TORQUE && v.tmax < o_.tol_torque) finish(i, MM_OK);
+                else need_dir(i, 1, false);
                 break;
-            }
-            precondition(c, s1, o.jmax, nullptr, o);
-            double dpn, dmx;
-            direction(c, s1, &s0, false, &dpn, &dmx, &mode);
-            account_precondition(c);
-            if (mode != 0) fallbacks++;
-            a_prev = ls.alpha;
-            dp_prev = dp0;
-            first = false;
-            i0 = ls.idx;
-            dp0 = dpn;
-            dmax = dmx;
+            case S_TRIAL_T: after_T(i, v); break;
+            case S_TRIAL_C: after_C(i, v); break;
+            case S_HALVE:
+                if (v.dF <= o_.c1 * R.a * R.dp0) accept(i, 1, R.a, v);
+                else halve(i);
+                break;
+            default: break;
         }
     }
-    *cur = i0;
-    auto t1 = std::chrono::steady_clock::now();
-    if (stats) {
-        stats->evals = c->c_evals;
-        stats->nli = nli;
-        stats->li = c->c_li;
-        stats->mi = c->c_mi;
-        stats->restarts = restarts;
-        stats->fallbacks = fallbacks;
-        stats->t_nl = std::chrono::duration<double>(t1 - t0).count();
-        stats->t_lin = c->t_lin;
-        stats->t_mag = c->t_mag;
-        stats->F = c->st[i0].E;
-        stats->torque_max = c->st[i0].tmax;
-        stats->status = status;
+
+    // line search on phi(alpha) = F(N(x + alpha d)): capped rotation,
+    // sufficient decrease on the exact energy difference, one cubic
+    // interpolation, then halving
+    void start_ls(int i, double a0, bool restart) {
+        Run &R = r_[i];
+        R.restart_ls = restart;
+        if (!(R.dmax > 0.0)) {
+            ls_fail(i);
+            return;
+        }
+        R.a0 = a0;
+        R.amax = o_.theta_max / R.dmax;
+        R.at = std::min(a0, R.amax);
+        R.step = S_TRIAL_T;
     }
-    return status;
-}
 
-void reduce_field(const mm_ctx *c, const double *BT, double h[3]) {
-    for (int k = 0; k < 3; ++k) h[k] = BT[k] / (kMu0 * c->as.Ms_ref);
-}
+    void after_T(int i, const Sc &v) {
+        Run &R = r_[i];
+        const double at = R.at, dp0 = R.dp0;
+        R.sT = v;
+        R.dFt = v.dF;
+        R.arm_t = v.dF <= o_.c1 * at * dp0;
+        if (R.arm_t && std::fabs(v.dphi) <= o_.c2 * std::fabs(dp0)) return accept(i, 1, at, v);
+        const bool over = !R.arm_t || v.dphi > 0.0;
+        if (!over && at >= R.amax) return accept(i, 1, at, v);
+        double ac;
+        if (!cubic_step(at, v.dF, dp0, v.dphi, &ac)) ac = over ? 0.5 * at : std::min(2.0 * at, R.amax);
+        if (over) {
+            ac = std::max(ac, 0.1 * at);
+            ac = std::min(ac, 0.9 * at);
+        } else {
+            const double hi = std::min(4.0 * at, R.amax);
+            ac = std::min(ac, hi);
+            ac = std::max(ac, 1.1 * at);
+            if (ac > hi) return accept(i, 1, at, v);
+        }
+        R.ac = ac;
+        R.step = S_TRIAL_C;
+    }
 
-// load m (host or device), check finite and unit length
-void load_m(mm_ctx *c, State &st, const double *m) {
-    const int nm = c->n_mag();
-    copy_in(c, st.x, m, 3 * (size_t)nm);
-    launch_mavg(nm, st.x, c->L, partp(c, PS_MISC), c->stream);
-    launch_finalize(partp(c, PS_MISC), grid_for_rows(nm), 5, 1u << 4, c->dsc + SC_MISC, c->stream);
-    pull(c, SC_MISC, 5);
-    double dev = c->hsc[SC_MISC + 4];
-    if (!(dev <= 1e-6)) throw ApiError{MM_EINVAL, "m must hold finite unit vectors (max | |m_i| - 1 | = " +
-                                                      std::to_string(dev) + ")"};
-}
+    void after_C(int i, const Sc &v) {
+        Run &R = r_[i];
+        if (v.dF <= o_.c1 * R.ac * R.dp0) return accept(i, 2, R.ac, v);
+        if (R.arm_t) return accept(i, 1, R.at, R.sT);
+        R.a = std::min(R.at, R.ac);
+        R.halvings = 0;
+        halve(i);
+    }
+
+    void halve(int i) {
+        Run &R = r_[i];
+        if (R.halvings >= o_.ls_max_halvings) return ls_fail(i);
+        R.halvings++;
+        R.a *= 0.5;
+        R.step = S_HALVE;
+    }
+
+    void ls_fail(int i) {
+        Run &R = r_[i];
+        if (!R.restart_ls) {
+            // restart along the steepest-descent direction
+            R.restarts++;
+            need_dir(i, 3, true);
+        } else {
+            finish(i, MM_STALLED);
+        }
+    }
+
+    void accept(int i, int from, double alpha, const Sc &v) {
+        Run &R = r_[i];
+        c_->from()[i] = from;
+        R.nli++;
+        const Sc &s0 = R.cur;
+        bool conv;
+        if (o_.stop_mode == MM_STOP_TORQUE) {
+            conv = v.tmax < o_.tol_torque;
+        } else {
+            const double tau = o_.tau_F;
+            const bool t1 = (s0.E - v.E) < tau * (1.0 + std::fabs(v.E));
+            const bool t2 = v.dxinf < std::sqrt(tau) * (1.0 + v.minf);
+            const bool t3 = v.ginf < std::cbrt(tau) * (1.0 + std::fabs(v.E));
+            conv = t1 && t2 && t3;
+        }
+        if (trace_level() > 0 && (R.nli <= 40 || R.nli % 100 == 0))
+            std::fprintf(stderr,
+                         "[mmncg] inst %d field %ld nli %ld alpha %.4e amax %.4e a0 %.4e dp0 %.4e dF %.4e dE %.4e "
+                         "tmax %.4e E %.12e\n",
+                         i, R.field, R.nli, alpha, R.amax, R.a0, R.dp0, v.dF, v.E - s0.E, v.tmax, v.E);
+        R.cur = v;
+        if (conv) return finish(i, MM_OK);
+        R.a_prev = alpha;
+        R.dp_prev = R.dp0;
+        R.first = false;
+        need_dir(i, 0, false);
+    }
+
+    void after_dir(int i) {
+        Run &R = r_[i];
+        const double *r = hsc_at(c_, SC_DIR) + 2 * (size_t)i;
+        R.dp0 = r[0];
+        R.dmax = r[1];
+        if (R.prec_ran) c_->cnt[i].li += c_->pflags()[4 * i + 1];
+        if (R.restarting) {
+            R.restarting = false;
+            if (!(R.dp0 < 0.0) || !(R.dmax > 0.0)) return finish(i, MM_STALLED);
+            return start_ls(i, o_.theta_init / R.dmax, true);
+        }
+        if (c_->info()[i] != 0) R.fallbacks++;
+        // top of the nonlinear iteration
+        if (R.nli >= o_.max_nli) return finish(i, MM_NOT_CONVERGED);
+        if (!(R.dp0 < 0.0)) return finish(i, MM_OK);
+        double a0;
+        if (R.first) a0 = o_.jmax > 0 ? 1.0 : o_.theta_init / R.dmax;
+        else a0 = R.a_prev * R.dp_prev / R.dp0;
+        start_ls(i, a0, false);
+    }
+
+    void finish_field(int i) {
+        Run &R = r_[i];
+        const long k = R.field;
+        const size_t at = (size_t)i * nf_ + k;
+        const Cnt &cn = c_->cnt[i];
+        if (out_.st) {
+            mm_stats &s = out_.st[at];
+            s.evals = cn.evals - R.c0.evals;
+            s.nli = R.nli;
+            s.li = cn.li - R.c0.li;
+            s.mi = cn.mi - R.c0.mi;
+            s.restarts = R.restarts;
+            s.fallbacks = R.fallbacks;
+            s.t_nl = now_s() - R.t0;
+            s.t_lin = cn.t_lin - R.c0.t_lin;
+            s.t_mag = cn.t_mag - R.c0.t_mag;
+            s.F = R.cur.E;
+            s.torque_max = R.cur.tmax;
+            s.status = R.status;
+        }
+        if (out_.m_avg) {
+            const double *mv = hsc_at(c_, SC_MISC) + 4 * (size_t)i;
+            for (int q = 0; q < 3; ++q) out_.m_avg[3 * at + q] = mv[q] / mv[3];
+        }
+        if (out_.E_tot) out_.E_tot[at] = R.cur.E;
+        if (out_.m_hist && c_->ninst == 1) {
+            const InstInfo &I = c_->inst[0];
+            copy_out(c_, out_.m_hist + 3 * (size_t)I.n_mag * k, c_->st[0].x, 3 * (size_t)I.n_mag);
+        }
+        worst_ = std::max(worst_, R.status);
+        start_field(i, k + 1);
+    }
+};
 
 bool opts_valid(const mm_opts &o, std::string &why) {
     if (o.jmax < 0) why = "jmax < 0";
@@ -800,8 +1282,18 @@ bool opts_valid(const mm_opts &o, std::string &why) {
     else if (o.stop_mode != MM_STOP_TORQUE && o.stop_mode != MM_STOP_PAPER) why = "unknown stop_mode";
     else if (o.stop_mode == MM_STOP_PAPER && !(o.tau_F > 0)) why = "tau_F <= 0";
     else if (o.poisson_maxit < 1) why = "poisson_maxit < 1";
+    else if (o.ls_max_halvings < 0) why = "ls_max_halvings < 0";
     else return true;
     return false;
+}
+
+mm_opts resolve_opts(const mm_opts *o) {
+    mm_opts op;
+    if (o) op = *o;
+    else mm_opts_default(&op);
+    std::string why;
+    if (!opts_valid(op, why)) throw ApiError{MM_EINVAL, why};
+    return op;
 }
 
 template <class F>
@@ -829,7 +1321,45 @@ int guarded(mm_ctx *c, F &&f) {
 }
 
 void require_ready(mm_ctx *c) {
-    if (!c->have_mesh || !c->have_mat) throw ApiError{MM_ESTATE, "mesh and material must be set first"};
+    if (!c->have_mat || c->ninst < 1) throw ApiError{MM_ESTATE, "mesh and material must be set first"};
+}
+void require_single(mm_ctx *c) {
+    require_ready(c);
+    if (c->ninst != 1) throw ApiError{MM_ESTATE, "this call needs a context with exactly one instance"};
+}
+
+// evaluation of every instance at the current state for fields h (reduced, [inst][3])
+void eval_all(mm_ctx *c, const mm_opts &o, const std::vector<double> &h) {
+    std::vector<int> on;
+    for (int i = 0; i < c->ninst; ++i) {
+        c->act()[i] = 1;
+        c->role()[i] = 0;
+        c->alpha()[i] = 0.0;
+        set_h3(c, i, &h[3 * (size_t)i]);
+        on.push_back(i);
+    }
+    eval_round(c, o, on, false);
+}
+
+// check mesh arrays of one instance
+void check_mesh(const double *xyz, long n_nodes, const int *tets, long n_tets) {
+    if (!xyz || !tets || n_nodes < 4 || n_tets < 1) throw ApiError{MM_EINVAL, "bad mesh arguments"};
+    for (long e = 0; e < 4 * n_tets; ++e)
+        if (tets[e] < 0 || tets[e] >= n_nodes) throw ApiError{MM_EMESH, "tet node index out of range"};
+    for (long i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(xyz[i])) throw ApiError{MM_EMESH, "non-finite coordinate"};
+}
+
+Assembly assemble_checked(const double *xyz, long n_nodes, const int *tets, long n_tets, const int *region,
+                          const double *Ms, const double *A, const double *K1, const double *axis, int inst) {
+    Assembly as;
+    std::string e = assemble(xyz, n_nodes, tets, n_tets, region, Ms, A, K1, axis, as);
+    std::string where = inst >= 0 ? " (instance " + std::to_string(inst) + ")" : "";
+    if (!e.empty()) throw ApiError{MM_EMESH, e + where};
+    if (as.n_mag == 0) throw ApiError{MM_EMESH, "no magnet nodes" + where};
+    for (int a = 0; a < as.n_mag; ++a)
+        if (!(as.Dex[a] > 0.0)) throw ApiError{MM_EMESH, "zero exchange diagonal at a magnet node" + where};
+    return as;
 }
 
 }  // namespace
@@ -884,12 +1414,6 @@ int mm_create(mm_ctx **out, int device, void *hip_stream, mm_alloc_fn dev_alloc,
             c->own_stream = true;
         }
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
-        HIPCHK(hipHostMalloc((void **)&c->hsc, SC_TOTAL * sizeof(double), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void **)&c->hflags, FL_TOTAL * sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void **)&c->hpst, sizeof(PcgState), hipHostMallocDefault));
-        std::memset(c->hpst, 0, sizeof(PcgState));
-        std::memset(c->hsc, 0, SC_TOTAL * sizeof(double));
-        std::memset(c->hflags, 0, FL_TOTAL * sizeof(int));
         return MM_OK;
     });
     if (rc != MM_OK) {
@@ -907,9 +1431,6 @@ int mm_destroy(mm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
-    if (c->hsc) (void)hipHostFree(c->hsc);
-    if (c->hflags) (void)hipHostFree(c->hflags);
-    if (c->hpst) (void)hipHostFree(c->hpst);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return MM_OK;
@@ -920,40 +1441,37 @@ const char *mm_last_error(const mm_ctx *c) { return c ? c->err.c_str() : "null c
 int mm_get_info(const mm_ctx *c, mm_info *info) {
     if (!c || !info) return MM_EINVAL;
     std::memset(info, 0, sizeof *info);
-    info->n_nodes = (long)c->xyz.size() / 3;
-    info->n_tets = (long)c->tets.size() / 4;
-    if (c->have_mat) {
-        info->n_mag = c->as.n_mag;
-        info->n_pot = c->as.n_pot;
-        info->nnz_C_blocks = (long)c->C.nnz;
-        info->nnz_K = (long)c->K.nnz;
-        info->nnz_B = (long)c->B.nnz;
-        info->Ms_ref = c->as.Ms_ref;
-        size_t bytes = 0;
-        for (const Sell *m : {&c->C, &c->S, &c->K, &c->B, &c->Bt})
-            bytes += (size_t)m->padded * (sizeof(int) + m->vw * (sizeof(double) + sizeof(float)));
-        bytes += (size_t)c->as.n_mag * (3 * 3 * 8 + 3 * 8 + 6 * 3 * 8 + 3 * 8);
-        bytes += (size_t)c->as.n_pot * (8 * 6 + 4 * 5);
-        info->device_bytes = bytes;
+    if (!c->have_mat) {
+        info->n_nodes = (long)c->xyz.size() / 3;
+        info->n_tets = (long)c->tets.size() / 4;
+        return MM_OK;
     }
+    for (const InstInfo &I : c->inst) {
+        info->n_nodes += I.n_nodes;
+        info->n_tets += I.n_tets;
+        info->n_mag += I.n_mag;
+        info->n_pot += I.n_pot;
+        info->nnz_C_blocks += I.nnz_C;
+        info->nnz_K += I.nnz_K;
+        info->nnz_B += I.nnz_B;
+    }
+    info->Ms_ref = c->inst.empty() ? 0.0 : c->inst[0].Ms_ref;
+    info->device_bytes = c->dev_bytes;
     return MM_OK;
 }
 
 int mm_mesh_upload(mm_ctx *c, const double *xyz, long n_nodes, const int *tets, long n_tets, const int *region) {
     return guarded(c, [&] {
-        if (!xyz || !tets || !region || n_nodes < 4 || n_tets < 1) throw ApiError{MM_EINVAL, "bad mesh arguments"};
+        if (!region) throw ApiError{MM_EINVAL, "bad mesh arguments"};
+        check_mesh(xyz, n_nodes, tets, n_tets);
         if (is_device_ptr(xyz) || is_device_ptr(tets) || is_device_ptr(region))
             throw ApiError{MM_EINVAL, "mesh arrays must be host memory"};
-        for (long e = 0; e < 4 * n_tets; ++e)
-            if (tets[e] < 0 || tets[e] >= n_nodes) throw ApiError{MM_EMESH, "tet node index out of range"};
-        for (long i = 0; i < 3 * n_nodes; ++i)
-            if (!std::isfinite(xyz[i])) throw ApiError{MM_EMESH, "non-finite coordinate"};
+        free_all(c);
         c->xyz.assign(xyz, xyz + 3 * n_nodes);
         c->tets.assign(tets, tets + 4 * n_tets);
         c->region.assign(region, region + n_tets);
         c->have_mesh = true;
         c->have_mat = false;
-        free_all(c);
         return MM_OK;
     });
 }
@@ -962,34 +1480,95 @@ int mm_material_set(mm_ctx *c, const double *Ms, const double *A, const double *
     return guarded(c, [&] {
         if (!c->have_mesh) throw ApiError{MM_ESTATE, "upload the mesh first"};
         if (!Ms || !A || !K1) throw ApiError{MM_EINVAL, "Ms, A and K1 are required"};
-        Assembly as;
-        std::string e = assemble(c->xyz.data(), (long)c->xyz.size() / 3, c->tets.data(), (long)c->tets.size() / 4,
-                                 c->region.data(), Ms, A, K1, axis, as);
-        if (!e.empty()) throw ApiError{MM_EMESH, e};
-        if (as.n_mag == 0) throw ApiError{MM_EMESH, "no magnet nodes"};
-        for (int a = 0; a < as.n_mag; ++a)
-            if (!(as.Dex[a] > 0.0)) throw ApiError{MM_EMESH, "zero exchange diagonal at a magnet node"};
-        c->as = std::move(as);
-        setup_device(c);
+        const long nn = (long)c->xyz.size() / 3, nt = (long)c->tets.size() / 4;
+        std::vector<Assembly> as;
+        as.push_back(assemble_checked(c->xyz.data(), nn, c->tets.data(), nt, c->region.data(), Ms, A, K1, axis, -1));
+        c->have_mat = false;
+        setup_device(c, as, {nn}, {nt});
         c->have_mat = true;
         return MM_OK;
     });
 }
 
+int mm_batch_upload(mm_ctx *c, int n_inst, const long *n_nodes, const long *n_tets, const double *xyz,
+                    const int *tets, const int *region, const double *Ms, const double *A, const double *K1,
+                    const double *axis) {
+    return guarded(c, [&] {
+        if (n_inst < 1 || !n_nodes || !n_tets || !xyz || !tets || !region || !Ms || !A || !K1)
+            throw ApiError{MM_EINVAL, "bad batch arguments"};
+        for (const void *p : {(const void *)xyz, (const void *)tets, (const void *)region, (const void *)Ms,
+                              (const void *)A, (const void *)K1, (const void *)axis})
+            if (is_device_ptr(p)) throw ApiError{MM_EINVAL, "batch arrays must be host memory"};
+        std::vector<Assembly> as;
+        std::vector<long> nn(n_inst), nt(n_inst);
+        long on = 0, ot = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            nn[i] = n_nodes[i];
+            nt[i] = n_tets[i];
+            if (nn[i] < 4 || nt[i] < 1) throw ApiError{MM_EINVAL, "bad mesh size of instance " + std::to_string(i)};
+            check_mesh(xyz + 3 * on, nn[i], tets + 4 * ot, nt[i]);
+            as.push_back(assemble_checked(xyz + 3 * on, nn[i], tets + 4 * ot, nt[i], region + ot, Ms + ot, A + ot,
+                                          K1 + ot, axis ? axis + 3 * ot : nullptr, i));
+            on += nn[i];
+            ot += nt[i];
+        }
+        free_all(c);
+        c->xyz.clear();
+        c->tets.clear();
+        c->region.clear();
+        c->have_mesh = true;
+        c->have_mat = false;
+        setup_device(c, as, nn, nt);
+        c->have_mat = true;
+        return MM_OK;
+    });
+}
+
+int mm_batch_info(const mm_ctx *c, int inst, mm_info *info) {
+    if (!c || !info) return MM_EINVAL;
+    if (!c->have_mat) return MM_ESTATE;
+    if (inst < 0 || inst >= c->ninst) return MM_EINVAL;
+    const InstInfo &I = c->inst[inst];
+    std::memset(info, 0, sizeof *info);
+    info->n_nodes = I.n_nodes;
+    info->n_tets = I.n_tets;
+    info->n_mag = I.n_mag;
+    info->n_pot = I.n_pot;
+    info->nnz_C_blocks = I.nnz_C;
+    info->nnz_K = I.nnz_K;
+    info->nnz_B = I.nnz_B;
+    info->Ms_ref = I.Ms_ref;
+    info->device_bytes = c->dev_bytes;
+    return MM_OK;
+}
+
+int mm_batch_size(const mm_ctx *c, int *n_inst) {
+    if (!c || !n_inst) return MM_EINVAL;
+    *n_inst = c->have_mat ? c->ninst : 0;
+    return MM_OK;
+}
+
+int mm_batch_magnet_nodes(const mm_ctx *c, int inst, long *n_mag, int *node_ids) {
+    if (!c || !n_mag) return MM_EINVAL;
+    if (!c->have_mat) return MM_ESTATE;
+    if (inst < 0 || inst >= c->ninst) return MM_EINVAL;
+    const InstInfo &I = c->inst[inst];
+    *n_mag = I.n_mag;
+    if (node_ids) std::memcpy(node_ids, I.node_of_mag.data(), sizeof(int) * I.n_mag);
+    return MM_OK;
+}
+
 int mm_magnet_nodes(const mm_ctx *c, long *n_mag, int *node_ids) {
     if (!c || !n_mag) return MM_EINVAL;
     if (!c->have_mat) return MM_ESTATE;
-    *n_mag = c->as.n_mag;
-    if (node_ids) std::memcpy(node_ids, c->as.node_of_mag.data(), sizeof(int) * c->as.n_mag);
-    return MM_OK;
+    if (c->ninst != 1) return MM_ESTATE;
+    return mm_batch_magnet_nodes(c, 0, n_mag, node_ids);
 }
 
 int mm_set_opts(mm_ctx *c, const mm_opts *o) {
     return guarded(c, [&] {
         if (!o) throw ApiError{MM_EINVAL, "null opts"};
-        std::string why;
-        if (!opts_valid(*o, why)) throw ApiError{MM_EINVAL, why};
-        c->opts = *o;
+        c->opts = resolve_opts(o);
         return MM_OK;
     });
 }
@@ -997,9 +1576,9 @@ int mm_set_opts(mm_ctx *c, const mm_opts *o) {
 int mm_reset_warm_start(mm_ctx *c) {
     return guarded(c, [&] {
         require_ready(c);
-        HIPCHK(hipMemsetAsync(c->u, 0, c->n_pot() * sizeof(double), c->stream));
+        launch_fill(c->rows_p, c->u, 0.0, c->stream);
         sync(c);
-        c->last_poisson_iters = 16;
+        c->last_pcg.assign(c->ninst, 16);
         return MM_OK;
     });
 }
@@ -1007,18 +1586,41 @@ int mm_reset_warm_start(mm_ctx *c) {
 int mm_energy_grad(mm_ctx *c, const double *m, const double h_ext[3], double E_parts[5], double *grad, double *gproj,
                    double *torque_max) {
     return guarded(c, [&] {
+        require_single(c);
+        if (!m || !h_ext) throw ApiError{MM_EINVAL, "m and h_ext are required"};
+        load_m(c, m);
+        std::vector<double> h(3);
+        reduce_field(c->inst[0], h_ext, h.data());
+        eval_all(c, c->opts, h);
+        const Sc v = eval_result(c, 0);
+        const size_t n3 = 3 * (size_t)c->inst[0].n_mag;
+        if (E_parts) energy_parts(c, 0, v, c->opts, E_parts);
+        if (grad) copy_out(c, grad, c->st[0].G, n3);
+        if (gproj) copy_out(c, gproj, c->st[0].g, n3);
+        if (torque_max) *torque_max = v.tmax;
+        sync(c);
+        return MM_OK;
+    });
+}
+
+int mm_batch_energy_grad(mm_ctx *c, const double *m, const double *h_ext, double *E_tot, double *grad, double *gproj,
+                         double *torque_max) {
+    return guarded(c, [&] {
         require_ready(c);
         if (!m || !h_ext) throw ApiError{MM_EINVAL, "m and h_ext are required"};
-        State &st = c->st[0];
-        load_m(c, st, m);
-        double h[3];
-        reduce_field(c, h_ext, h);
-        eval(c, st, h, c->opts);
-        const size_t n3 = 3 * (size_t)c->n_mag();
-        if (E_parts) energy_parts(c, st, c->opts, E_parts);
-        if (grad) copy_out(c, grad, st.G, n3);
-        if (gproj) copy_out(c, gproj, st.g, n3);
-        if (torque_max) *torque_max = st.tmax;
+        load_m(c, m);
+        std::vector<double> h(3 * (size_t)c->ninst);
+        for (int i = 0; i < c->ninst; ++i) reduce_field(c->inst[i], h_ext + 3 * i, &h[3 * (size_t)i]);
+        eval_all(c, c->opts, h);
+        for (int i = 0; i < c->ninst; ++i) {
+            const Sc v = eval_result(c, i);
+            if (E_tot) E_tot[i] = v.E;
+            if (torque_max) torque_max[i] = v.tmax;
+        }
+        for (const InstInfo &I : c->inst) {
+            if (grad) copy_out(c, grad + 3 * I.user_off, c->st[0].G + 3 * (size_t)I.mag_off, 3 * (size_t)I.n_mag);
+            if (gproj) copy_out(c, gproj + 3 * I.user_off, c->st[0].g + 3 * (size_t)I.mag_off, 3 * (size_t)I.n_mag);
+        }
         sync(c);
         return MM_OK;
     });
@@ -1027,26 +1629,32 @@ int mm_energy_grad(mm_ctx *c, const double *m, const double h_ext[3], double E_p
 int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax, const double *dscale,
                     double *y, int *inner_iters) {
     return guarded(c, [&] {
-        require_ready(c);
+        require_single(c);
         if (!m || !grad || !gproj || !y || jmax < 0) throw ApiError{MM_EINVAL, "bad precondition arguments"};
-        const int nm = c->n_mag();
-        State &st = c->st[0];
-        load_m(c, st, m);
-        copy_in(c, st.G, grad, 3 * (size_t)nm);
-        copy_in(c, st.g, gproj, 3 * (size_t)nm);
-        launch_lambda(nm, st.x, st.G, st.lam, c->stream);
-        const double *ds = nullptr;
-        if (dscale) {
-            copy_in(c, c->dscale, dscale, nm);
-            ds = c->dscale;
+        const int nm = c->inst[0].n_mag;
+        load_m(c, m);
+        copy_in(c, c->st[0].G, grad, 3 * (size_t)nm);
+        copy_in(c, c->st[0].g, gproj, 3 * (size_t)nm);
+        launch_lambda(c->Mm.map, c->st[0].x, c->st[0].G, c->st[0].lam, c->stream);
+        int it = 0;
+        if (jmax == 0) {
+            HIPCHK(hipMemcpyAsync(c->y, c->st[0].g, 3 * (size_t)nm * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+        } else {
+            const double *ds = nullptr;
+            if (dscale) {
+                copy_in(c, c->dscale, dscale, nm);
+                ds = c->dscale;
+            }
+            c->pact()[0] = 1;
+            upload_ctl(c);
+            precondition(c, jmax, ds, c->opts.precision == MM_FP32_BULK);
+            pull_flags(c);
         }
-        c->c_li = 0;
-        c->t_lin = 0;
-        precondition(c, st, jmax, ds, c->opts);
         copy_out(c, y, c->y, 3 * (size_t)nm);
         sync(c);
-        account_precondition(c);
-        if (inner_iters) *inner_iters = (int)c->c_li;
+        if (jmax > 0) it = c->pflags()[1];
+        if (inner_iters) *inner_iters = it;
         return MM_OK;
     });
 }
@@ -1054,21 +1662,19 @@ int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double
 int mm_ncg_minimize(mm_ctx *c, double *m_inout, const double h_ext[3], const mm_opts *o, mm_stats *st,
                     double E_parts[5]) {
     return guarded(c, [&] {
-        require_ready(c);
+        require_single(c);
         if (!m_inout || !h_ext) throw ApiError{MM_EINVAL, "m and h_ext are required"};
-        mm_opts op;
-        if (o) op = *o;
-        else mm_opts_default(&op);
-        std::string why;
-        if (!opts_valid(op, why)) throw ApiError{MM_EINVAL, why};
-        int cur = 0;
-        load_m(c, c->st[cur], m_inout);
-        double h[3];
-        reduce_field(c, h_ext, h);
+        mm_opts op = resolve_opts(o);
+        load_m(c, m_inout);
+        std::vector<double> h(3);
+        reduce_field(c->inst[0], h_ext, h.data());
         mm_stats s;
-        int rc = minimize(c, &cur, h, op, &s);
-        if (E_parts) energy_parts(c, c->st[cur], op, E_parts);
-        copy_out(c, m_inout, c->st[cur].x, 3 * (size_t)c->n_mag());
+        CurveOut out;
+        out.st = &s;
+        Driver drv(c, op, h, 1, out);
+        int rc = drv.run();
+        if (E_parts) energy_parts(c, 0, drv.final_scalars(0), op, E_parts);
+        store_m(c, m_inout);
         sync(c);
         if (st) *st = s;
         return rc;
@@ -1078,66 +1684,81 @@ int mm_ncg_minimize(mm_ctx *c, double *m_inout, const double h_ext[3], const mm_
 int mm_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, const mm_opts *o, double *m_avg,
                    double *E_tot, mm_stats *st, double *m_hist) {
     return guarded(c, [&] {
+        require_single(c);
+        if (!m_inout || !h_list || n < 0) throw ApiError{MM_EINVAL, "bad curve arguments"};
+        mm_opts op = resolve_opts(o);
+        load_m(c, m_inout);
+        std::vector<double> h(3 * (size_t)n);
+        for (long k = 0; k < n; ++k) reduce_field(c->inst[0], h_list + 3 * k, &h[3 * k]);
+        CurveOut out;
+        out.m_avg = m_avg;
+        out.E_tot = E_tot;
+        out.st = st;
+        out.m_hist = m_hist;
+        Driver drv(c, op, h, n, out);
+        int rc = drv.run();
+        store_m(c, m_inout);
+        sync(c);
+        return rc;
+    });
+}
+
+int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, const mm_opts *o, double *m_avg,
+                         double *E_tot, mm_stats *st) {
+    return guarded(c, [&] {
         require_ready(c);
         if (!m_inout || !h_list || n < 0) throw ApiError{MM_EINVAL, "bad curve arguments"};
-        mm_opts op;
-        if (o) op = *o;
-        else mm_opts_default(&op);
-        std::string why;
-        if (!opts_valid(op, why)) throw ApiError{MM_EINVAL, why};
-        const int nm = c->n_mag();
-        int cur = 0;
-        load_m(c, c->st[cur], m_inout);
-        int worst = MM_OK;
-        for (long k = 0; k < n; ++k) {
-            double h[3];
-            reduce_field(c, h_list + 3 * k, h);
-            mm_stats s;
-            int rc = minimize(c, &cur, h, op, &s);
-            worst = std::max(worst, rc);
-            if (m_avg) {
-                launch_mavg(nm, c->st[cur].x, c->L, partp(c, PS_MISC), c->stream);
-                launch_finalize(partp(c, PS_MISC), grid_for_rows(nm), 4, 0u, c->dsc + SC_MISC, c->stream);
-                pull(c, SC_MISC, 4);
-                for (int q = 0; q < 3; ++q) m_avg[3 * k + q] = c->hsc[SC_MISC + q] / c->hsc[SC_MISC + 3];
+        mm_opts op = resolve_opts(o);
+        load_m(c, m_inout);
+        const int ni = c->ninst;
+        std::vector<double> h(3 * (size_t)n * ni);
+        for (int i = 0; i < ni; ++i)
+            for (long k = 0; k < n; ++k) {
+                const size_t at = 3 * ((size_t)i * n + k);
+                reduce_field(c->inst[i], h_list + at, &h[at]);
             }
-            if (E_tot) E_tot[k] = c->st[cur].E;
-            if (st) st[k] = s;
-            if (m_hist) copy_out(c, m_hist + 3 * (size_t)nm * k, c->st[cur].x, 3 * (size_t)nm);
-        }
-        copy_out(c, m_inout, c->st[cur].x, 3 * (size_t)nm);
+        CurveOut out;
+        out.m_avg = m_avg;
+        out.E_tot = E_tot;
+        out.st = st;
+        Driver drv(c, op, h, n, out);
+        int rc = drv.run();
+        store_m(c, m_inout);
         sync(c);
-        return worst;
+        return rc;
     });
 }
 
 int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out) {
     return guarded(c, [&] {
-        require_ready(c);
+        require_single(c);
         if (!in || !out) throw ApiError{MM_EINVAL, "null vector"};
-        const int nm = c->n_mag(), np = c->n_pot();
+        const int nm = c->inst[0].n_mag, np = c->inst[0].n_pot;
         const bool fp32 = c->opts.precision == MM_FP32_BULK;
         hipStream_t s = c->stream;
         switch (op) {
             case MM_OP_C:
                 copy_in(c, c->tmp3, in, 3 * (size_t)nm);
-                launch_spmv_block6(c->C, c->tmp3, c->pq, fp32, s);
+                launch_spmv_block6(c->C, c->Mm.map, c->tmp3, c->pq, fp32, s);
                 copy_out(c, out, c->pq, 3 * (size_t)nm);
                 break;
-            case MM_OP_B:
+            case MM_OP_B: {
                 copy_in(c, c->tmp3, in, 3 * (size_t)nm);
-                HIPCHK(hipMemsetAsync(c->cq, 0, np * sizeof(double), s));
-                launch_bmul(c->B, c->tmp3, c->cq, fp32, s);
+                launch_fill(np, c->cq, 0.0, s);
+                StateV sv[3];
+                sv[0].x = c->tmp3;
+                launch_bmul(c->B, c->Mb.map, nullptr, sv, nullptr, c->cq, fp32, s);
                 copy_out(c, out, c->cq, np);
                 break;
+            }
             case MM_OP_BT:
                 copy_in(c, c->cq, in, np);
-                launch_btmul(c->Bt, c->cq, c->pq, fp32, s);
+                launch_btmul(c->Bt, c->Mm.map, c->cq, c->pq, fp32, s);
                 copy_out(c, out, c->pq, 3 * (size_t)nm);
                 break;
             case MM_OP_K:
                 copy_in(c, c->cr, in, np);
-                launch_spmv_scalar(c->K, c->cr, c->cq, fp32, s);
+                launch_spmv_scalar(c->K, c->Mp.map, c->cr, c->cq, fp32, s);
                 copy_out(c, out, c->cq, np);
                 break;
             default:
@@ -1150,19 +1771,21 @@ int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out) {
 
 int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters) {
     return guarded(c, [&] {
-        require_ready(c);
+        require_single(c);
         if (!b || !u_inout || !(rtol > 0)) throw ApiError{MM_EINVAL, "bad Poisson arguments"};
-        const int np = c->n_pot();
+        const int np = c->inst[0].n_pot;
         // the solve runs on the context's b and u: keep the warm start aside
         HIPCHK(hipMemcpyAsync(c->usave, c->u, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         copy_in(c, c->b, b, np);
         copy_in(c, c->u, u_inout, np);
-        c->t_mag = 0;
-        c->c_mi = 0;
-        long it = poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK);
+        c->act()[0] = 1;
+        upload_ctl(c);
+        const long mi0 = c->cnt[0].mi;
+        poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK, {0});
+        const long it = c->cnt[0].mi - mi0;
         copy_out(c, u_inout, c->u, np);
         // evaluations write only the magnet rows of b: clear it; restore u
-        HIPCHK(hipMemsetAsync(c->b, 0, np * sizeof(double), c->stream));
+        launch_fill(np, c->b, 0.0, c->stream);
         HIPCHK(hipMemcpyAsync(c->u, c->usave, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         sync(c);
         if (iters) *iters = it;
@@ -1172,22 +1795,20 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
 
 int mm_profile(mm_ctx *c, int enable, double out[4]) {
     return guarded(c, [&] {
-        sync(c);
+        if (c->stream) sync(c);
         prof_harvest(c);
         if (enable < 0) {
-            c->prof_launches = c->prof_seconds = c->prof_units = 0;
+            c->prof_seconds = c->prof_units = c->prof_bytes = 0;
         } else {
             c->prof_on = enable != 0;
         }
         if (out) {
-            const bool fp32 = c->opts.precision == MM_FP32_BULK;
-            const double vb = fp32 ? 4.0 : 8.0;
             out[0] = c->prof_units;
             out[1] = c->prof_seconds;
-            // kernel A: matrix + r, D^-1, p_old read + p_new, q written;
-            // kernel B: x, r, p, q, D^-1 read + x, r written (x is FP64 in the FP64 mode only)
-            out[2] = c->have_mat ? (double)c->K.nnz * (vb + 4.0) + 12.0 * vb * c->K.nrows : 0.0;
-            out[3] = c->have_mat ? (double)c->K.nrows : 0.0;
+            out[2] = c->prof_bytes;
+            double rows = 0;
+            for (const InstInfo &I : c->inst) rows += I.n_pot;
+            out[3] = rows;
         }
         return MM_OK;
     });

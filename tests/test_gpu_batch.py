@@ -1,0 +1,161 @@
+"""GPU: batches of independent instances solved by shared launches.
+
+Every instance of a batch is checked against the oracle run on that instance
+alone (FP64: relative energy error 1e-8, largest nodal |dm| 1e-5), and a batch
+must reproduce separate single-instance contexts bit for bit: the block
+partition of an instance and the order of its reductions do not depend on
+its neighbours in the batch. Inputs are seeded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1801_03690_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MU0 = 4e-7 * math.pi
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not _gpu_available():
+        pytest.skip("no GPU")
+    from paper_1801_03690_amd import binding
+    return binding
+
+
+def batch_meshes():
+    """Uneven instances: soft with air, hard tilted axis, no air box, and a
+    cube whose magnet rows span several blocks and potential rows 16 blocks."""
+    return [
+        inputs.small_box((3, 2, 2), 4.0),
+        inputs.small_box((5, 4, 3), 3.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.2, 0.1, 0.97)),
+        inputs.small_box((4, 3, 2), 4.0, air=False),
+        inputs.small_box((8, 8, 8), 4.0, Ms=1.61 / MU0, A=7.7e-12, K1=3.5e6, axis=(0.1, 0.0, 0.995)),
+    ]
+
+
+def start_states(meshes, seed=5):
+    out = []
+    for i, m in enumerate(meshes):
+        rng = np.random.Generator(np.random.PCG64(seed + i))
+        out.append(inputs.tilted_state(m.magnet_nodes().size, (0.0, 0.0, 1.0), 0.01, rng))
+    return out
+
+
+def fields_for(n_inst, values_T):
+    f = np.zeros((n_inst, len(values_T), 3))
+    for i in range(n_inst):
+        f[i, :, 2] = values_T
+        f[i, :, 0] = 0.01 * (i + 1)
+    return f
+
+
+def test_batch_layout_and_info(B):
+    meshes = batch_meshes()
+    ctx = B.Context(0).upload_batch(meshes)
+    assert ctx.batch_size() == len(meshes)
+    for i, mesh in enumerate(meshes):
+        single = B.Context(0).upload(mesh)
+        a, b = ctx.batch_info(i), single.info()
+        for k in ("n_nodes", "n_tets", "n_mag", "n_pot", "nnz_C_blocks", "nnz_K", "nnz_B", "Ms_ref"):
+            assert a[k] == b[k], (i, k)
+        np.testing.assert_array_equal(ctx.batch_magnet_nodes(i), single.magnet_nodes())
+        single.close()
+    # single-instance calls are refused on a batch
+    with pytest.raises(B.MMError) as e:
+        ctx.energy_grad(np.tile([0.0, 0.0, 1.0], (ctx.n_mag, 1)), [0, 0, 1.0])
+    assert e.value.code == B.MM_ESTATE
+    ctx.close()
+
+
+def test_batch_energy_grad_matches_oracle(B, oracle_mod):
+    meshes = batch_meshes()
+    ctx = B.Context(0).upload_batch(meshes)
+    ctx.set_opts(poisson_rtol=1e-12)
+    ms = [inputs.random_unit(m.magnet_nodes().size, 10 + i) for i, m in enumerate(meshes)]
+    h = np.array([[0.1, 0.0, 0.5], [0.0, 0.3, -1.0], [0.2, 0.2, 0.2], [0.0, 0.0, -2.0]])
+    r = ctx.batch_energy_grad(np.concatenate(ms), h)
+    Gs = ctx.split(r["G"])
+    for i, mesh in enumerate(meshes):
+        o = oracle_mod.Oracle(mesh)
+        o.set_poisson(1e-12)
+        ro = o.eval_T(ms[i], h[i])
+        assert abs(r["E"][i] - ro["E"][4]) <= 1e-10 * np.abs(ro["E"][:4]).sum(), i
+        scale = np.abs(ro["G"]).max()
+        assert np.abs(Gs[i] - ro["G"]).max() <= 1e-8 * scale, i
+    ctx.close()
+
+
+def test_batch_curve_matches_oracle(B, oracle_mod):
+    meshes = batch_meshes()
+    m0 = start_states(meshes)
+    F = fields_for(len(meshes), [0.0, -0.5, -1.0])
+    ctx = B.Context(0).upload_batch(meshes)
+    rg = ctx.batch_curve(np.concatenate(m0), F, jmax=4)
+    assert rg["rc"] == 0
+    mg = ctx.split(rg["m"])
+    for i, mesh in enumerate(meshes):
+        o = oracle_mod.Oracle(mesh)
+        ro = o.curve(m0[i], F[i], jmax=4)
+        assert ro["rc"] == 0
+        for k in range(F.shape[1]):
+            assert abs(rg["E"][i, k] - ro["E"][k]) <= 1e-8 * max(abs(ro["E"][k]), 1.0), (i, k)
+            assert rg["stats"][i][k]["torque_max"] < 1e-6
+        assert np.abs(rg["m_avg"][i] - ro["m_avg"]).max() < 1e-5, i
+        assert np.abs(mg[i] - ro["m"]).max() <= 1e-5, i
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_single_instances(B, precision):
+    meshes = batch_meshes()
+    m0 = start_states(meshes, seed=7)
+    F = fields_for(len(meshes), [0.0, -1.0, -2.5])
+    opts = dict(jmax=10, precision=precision)
+    ctx = B.Context(0).upload_batch(meshes)
+    ctx.set_opts(precision=precision)
+    rb = ctx.batch_curve(np.concatenate(m0), F, **opts)
+    mb = ctx.split(rb["m"])
+    ctx.close()
+    for i, mesh in enumerate(meshes):
+        s = B.Context(0).upload(mesh)
+        s.set_opts(precision=precision)
+        rs = s.curve(m0[i], F[i], **opts)
+        s.close()
+        np.testing.assert_array_equal(mb[i], rs["m"])
+        np.testing.assert_array_equal(rb["E"][i], rs["E"])
+        np.testing.assert_array_equal(rb["m_avg"][i], rs["m_avg"])
+        for k in range(F.shape[1]):
+            for key in ("evals", "nli", "li", "mi", "restarts", "fallbacks", "status"):
+                assert rb["stats"][i][k][key] == rs["stats"][k][key], (i, k, key)
+
+
+def test_batch_empty_field_list_and_device_state(B):
+    import torch
+    meshes = batch_meshes()[:2]
+    m0 = np.concatenate(start_states(meshes))
+    ctx = B.Context(0).upload_batch(meshes)
+    r = ctx.batch_curve(m0, np.zeros((2, 0, 3)), jmax=4)
+    assert r["rc"] == 0
+    np.testing.assert_array_equal(r["m"], m0)
+    # device-resident start state
+    F = fields_for(2, [0.0, -0.5])
+    md = torch.tensor(m0, dtype=torch.float64, device="cuda")
+    rd = ctx.batch_curve(md, F, jmax=4)
+    torch.cuda.synchronize()
+    ctx.reset_warm_start()
+    rh = ctx.batch_curve(m0, F, jmax=4)
+    np.testing.assert_array_equal(md.cpu().numpy(), rh["m"])
+    np.testing.assert_array_equal(rd["E"], rh["E"])
+    ctx.close()
