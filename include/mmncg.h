@@ -205,6 +205,26 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
    FP64 mode and 4-byte values in the FP32 inner solves. */
 int mm_profile(mm_ctx *c, int enable, double out[4]);
 
+/* Block shape of the scalar-potential kernels (the dominant work). Waves per
+   block NW in {4, 8, 16} is one choice for the whole launch; SELL slices per
+   wave in {1, 2, 4} is chosen per instance size bucket (bucket =
+   floor(log2(n_pot / 4096)) clamped to 0..7). A block of an instance covers NW
+   x slices-per-wave slices (at most 256 blocks per instance).
+   MM_TUNE_DEFAULT: NW = 16, one slice per wave (the state after upload).
+   MM_TUNE_MEASURE: for every NW and bucket, time 32 CG iterations (best of 3,
+   HIP events) of a synthetic solve (b = 1, u = 0) for each slices-per-wave
+   candidate, keep the fastest, then pick the NW with the least total time.
+   MM_TUNE_CACHE: as MEASURE, but first read winners for this device, bucket,
+   NW and precision (options of mm_set_opts) from the JSON file cache_path and
+   time only what is missing; the file is rewritten when something was timed.
+   The chosen shape stays fixed until the next mm_tune or upload, so a run is
+   deterministic; another shape may change the rounding of the potential
+   solves (another grouping of the reductions), never their tolerance. The
+   warm start and the context's right-hand side are preserved. Outputs (may be
+   NULL): waves_per_block, slices_per_wave (n_inst ints). */
+enum { MM_TUNE_DEFAULT = 0, MM_TUNE_MEASURE = 1, MM_TUNE_CACHE = 2 };
+int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave);
+
 /* ---------------------------------------------------------------------------
    Batches of independent instances (parameter studies, Sec. 3.1 curves of
    many grains). A context may hold n_inst independent problems, each with

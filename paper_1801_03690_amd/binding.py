@@ -27,6 +27,7 @@ MM_FP64, MM_FP32_BULK = 0, 1
 MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
 MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
+MM_TUNE_DEFAULT, MM_TUNE_MEASURE, MM_TUNE_CACHE = 0, 1, 2
 
 
 class MMError(RuntimeError):
@@ -102,6 +103,7 @@ def load_library(path=LIB_PATH):
     L.mm_batch_info.argtypes = [_vp, C.c_int, C.POINTER(Info)]
     L.mm_batch_magnet_nodes.argtypes = [_vp, C.c_int, _lp, _ip]
     L.mm_batch_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
+    L.mm_tune.argtypes = [_vp, C.c_int, C.c_char_p, _ip, _ip]
     L.mm_batch_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats)]
     for name in header_symbols():
         if getattr(L, name).restype is C.c_int or name != "mm_last_error":
@@ -235,6 +237,8 @@ class Context:
                                             K1.ctypes.data_as(_dp), ax.ctypes.data_as(_dp)))
         inf = self.info()
         self.n_mag, self.n_pot = inf["n_mag"], inf["n_pot"]
+        self.n_inst = 1
+        self.n_mag_list = [self.n_mag]
         return self
 
     def info(self):
@@ -322,6 +326,15 @@ class Context:
         it = int(out[0])
         return dict(iterations=it, seconds=float(out[1]), bytes=float(out[2]),
                     bytes_per_iteration=float(out[2]) / it if it else 0.0, rows=int(out[3]))
+
+    def tune(self, mode=MM_TUNE_MEASURE, cache_path=None):
+        """Pick the block shape of the scalar-potential kernels (mm_tune)."""
+        ni = max(1, getattr(self, "n_inst", 1))
+        nw = C.c_int()
+        spw = np.zeros(ni, dtype=np.int32)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self._L.mm_tune(self.h, int(mode), path, C.byref(nw), spw.ctypes.data_as(_ip)))
+        return nw.value, spw
 
     def poisson(self, b, u0=None, rtol=1e-10):
         bp, k1 = _vec_ptr(b)

@@ -13,7 +13,7 @@ namespace mmncg {
 constexpr int kSlice = 64;      // rows per SELL slice = one wavefront
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kMaxBlocksPerInst = 256;  // per instance and row space
-constexpr int kPoissonBlock = 1024;     // threads per block of the scalar-potential kernels
+constexpr int kPoissonWaves = 16;       // default waves per block of the scalar-potential kernels
 
 // ---------------------------------------------------------------------------
 // host-side CSR produced by the assembly (row-major, sorted columns)
@@ -87,9 +87,11 @@ struct StateV {
     double *x = nullptr, *G = nullptr, *g = nullptr, *lam = nullptr;
 };
 
-// per-instance scalar-potential CG state (device memory)
+// per-instance scalar-potential CG state (device memory). alpha/gamma hold
+// the step and r.z of the last two iterations (slot = iteration parity).
 struct PcgState {
     double tol2, bb, rr, scale;
+    double alpha[2], gamma[2];
     int done, iters, zero_u, active;
 };
 
@@ -149,22 +151,31 @@ void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
 
 // --- scalar-potential CG (poisson.hip) ---
+// vectors of the single-reduction CG: residual r, w = K D^-1 r and s = K p
+// double-buffered by iteration parity, direction p
+template <class VT>
+struct PcgVecs {
+    VT *r[2], *w[2], *s[2], *p;
+};
 struct PcgLaunch {
     const Sell *K;
     const RowMap *M;
     PcgState *st;              // per instance
     double *part;              // kPcgSlots slots of M->nblk
-    double *u, *b, *r, *p0, *p1, *q;   // FP64 vectors
+    double *u, *b;             // FP64 solution and right-hand side
     const double *invD;
-    float *x32, *r32, *p32a, *p32b, *q32;
+    PcgVecs<double> v64;
+    float *x32;                // FP32 correction of the defect-correction mode
     const float *invD32;
+    PcgVecs<float> v32;
     const double *pin;         // per instance 4 doubles: FP32 rhs scale, inner tol^2 (<= 0: inactive), rn, -
+    int nw;                    // waves per block of the row map M (4, 8 or 16)
 };
-void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, bool fp32_matrix, hipStream_t s);
+void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, hipStream_t s);
 void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s);
 void launch_pcg_init32(const PcgLaunch &a, hipStream_t s);
-void launch_pcg_iter64(const PcgLaunch &a, int phase_a, int odd, hipStream_t s);
-void launch_pcg_iter32(const PcgLaunch &a, int phase_a, int odd, hipStream_t s);
+void launch_pcg_iter64(const PcgLaunch &a, int parity, hipStream_t s);
+void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s);
 void launch_add_correction(const PcgLaunch &a, hipStream_t s);
 
 }  // namespace mmncg

@@ -2,23 +2,28 @@
 // evaluation; the paper solves it with preconditioned CG, Sec. 3.1) by
 // Jacobi-preconditioned CG on gfx950, for every instance of a batch at once.
 //
-// Two kernels per CG iteration:
-//   A: convergence test, beta, p_new = D^-1 r + beta p_old (own rows) and
-//      q = K p_new, where the neighbour values of p_new are formed on the fly
-//      from r, D^-1 and p_old (p is double-buffered, so no block reads a value
-//      another block is overwriting); partial p.q.
-//   B: alpha, x += alpha p_new, r -= alpha q; partials r.z, r.r.
-// Each kernel re-reduces the previous kernel's partials of its own instance in
-// a fixed order (every block of the instance gets the same scalars; no fences,
-// no floating-point atomics). The r.z / r.r partials alternate between two
-// slot pairs, so every launch of a chunk of iterations has fixed arguments:
-// the chunk is captured once into a HIP graph and replayed until every
-// instance's flag reports convergence. Once an instance's flag is up, every
-// later kernel of it returns at once, in this replay and in any further one
-// (replays are launched speculatively, ahead of the host seeing the flag).
-// All blocks of a kernel A take the same convergence decision from the same
-// partials, so a block that already sees the flag raised by its own launch
-// behaves as if it had decided itself.
+// The CG runs in its single-reduction form (Chronopoulos and Gear), which
+// produces the iterates of preconditioned CG in exact arithmetic but needs
+// one global reduction per iteration. With u = D^-1 r and w = K u:
+//   gamma = r.u, delta = w.u, beta = gamma / gamma_prev,
+//   alpha = gamma / (delta - beta gamma / alpha_prev),
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+//   w = K D^-1 r (new r), partials of the new gamma, delta and r.r.
+// A kernel boundary is the only grid-wide synchronization used, so one kernel
+// is one iteration: it re-reduces the previous kernel's partials of its own
+// instance in a fixed order (every block of the instance gets the same
+// scalars; no fences, no floating-point atomics), updates its own rows, and
+// forms K u_new where the neighbour values u_new = D^-1 (r - alpha (w + beta
+// s)) are computed on the fly from the previous iteration's r, w and s. Those
+// three vectors are double-buffered by iteration parity, so no block reads a
+// value another block is overwriting. Every launch of a chunk of iterations
+// has fixed arguments: the chunk is captured once into a HIP graph and
+// replayed until every instance's flag reports convergence. Once an
+// instance's flag is up, every later kernel of it returns at once, in this
+// replay and in any further one (replays are launched ahead of the host
+// seeing the flag). All blocks of an iteration take the same convergence
+// decision from the same partials, so a block that already sees the flag
+// raised by its own launch behaves as if it had decided itself.
 //
 // Vector type VT is double (FP64 mode) or float (inner solve of the FP32-bulk
 // mode, wrapped in FP64 defect correction); reductions are always FP64.
@@ -33,33 +38,34 @@ using namespace dev;
 
 namespace {
 
-// Poisson kernels run 1024-thread blocks (16 waves, one SELL slice each at a
-// time), at most kMaxBlocksPerInst blocks per instance.
-constexpr int kPB = kPoissonBlock;
-constexpr int kPW = kPB / 64;
+// Poisson kernels run blocks of NW waves (4, 8 or 16; one SELL slice per wave
+// at a time), at most kMaxBlocksPerInst blocks per instance; the block shape
+// and the slices per block of each instance come from the row map and the
+// launch (autotuned or defaults).
+constexpr int kFinBlock = 256;  // one block per instance for the start reductions
+constexpr int kFinW = kFinBlock / 64;
 
 // partial slots (slot q at part + q * stride):
-//   RZ0 = 0-1, RZ1 = 2-3 (r.z, r.r written by kernel B of even / odd iterations),
-//   PQ = 4 (p.q of kernel A), INIT = 5-7 (b.b, r.z, r.r of the start)
-constexpr int kRZ0 = 0, kRZ1 = 2, kPQ = 4, kINIT = 5;
+//   P0 = 0-2, P1 = 3-5 (gamma, delta, r.r for iterations of even / odd
+//   parity to read), INIT = 6-7 (b.b, r.r of the start residual)
+constexpr int kP0 = 0, kP1 = 3, kINIT = 6;
 
 __device__ __forceinline__ double *slot(double *part, int stride, int q) { return part + (size_t)q * stride; }
 __device__ __forceinline__ const double *slot(const double *part, int stride, int q) {
     return part + (size_t)q * stride;
 }
 
-// r = b - K u; partials (b.b, r.D^-1.r, r.r)
-template <class MT>
-__global__ __launch_bounds__(kPB) void k_pcg_init64(SV<MT> K, RowMap M, const int *__restrict__ act,
-                                                    const double *__restrict__ b, const double *__restrict__ u,
-                                                    double *__restrict__ r, const double *__restrict__ invD,
-                                                    double *__restrict__ part, int with_rz) {
+// r = b - K u; partials (b.b, r.r)
+template <class MT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_pcg_residual(SV<MT> K, RowMap M, const int *__restrict__ act,
+                                                      const double *__restrict__ b, const double *__restrict__ u,
+                                                      double *__restrict__ r, double *__restrict__ part) {
     Tile t = tile_of(M);
     if (t.inst < 0 || (act && !act[t.inst])) return;
-    __shared__ double sh[kPW * 3];
+    __shared__ double sh[NW * 2];
     const int rend = M.rend[t.inst], ln = lane_id();
-    double acc[3] = {0, 0, 0};
-    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
+    double acc[2] = {0, 0};
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double ku = row_scalar(K, s, ln, u);
         int row = s * 64 + ln;
         if (row < rend) {
@@ -67,46 +73,73 @@ __global__ __launch_bounds__(kPB) void k_pcg_init64(SV<MT> K, RowMap M, const in
             double ri = bi - ku;
             r[row] = ri;
             acc[0] += bi * bi;
-            if (with_rz) acc[1] += ri * (ri * invD[row]);
-            acc[2] += ri * ri;
+            acc[1] += ri * ri;
         }
     }
-    write_part<3, kPW>(acc, 0u, slot(part, M.nblk, kINIT), M.nblk, t.b, sh);
+    write_part<2, NW>(acc, 0u, slot(part, M.nblk, kINIT), M.nblk, t.b, sh);
 }
 
 // start of the FP32 inner solve K x = r64 * scale_i: x = 0, r32 = r64 * scale_i
-__global__ __launch_bounds__(kPB) void k_pcg_init32(RowMap M, const double *__restrict__ pin,
-                                                    const double *__restrict__ r64, float *__restrict__ x,
-                                                    float *__restrict__ r, const float *__restrict__ invD,
-                                                    double *__restrict__ part) {
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_pcg_start32(RowMap M, const double *__restrict__ pin,
+                                                     const double *__restrict__ r64, float *__restrict__ x,
+                                                     float *__restrict__ r) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !(pin[4 * t.inst + 1] > 0.0)) return;
-    __shared__ double sh[kPW * 3];
     const double scale = pin[4 * t.inst];
     const int rend = M.rend[t.inst];
-    double acc[3] = {0, 0, 0};
-    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int i = s * 64 + lane_id();
         if (i < rend) {
-            float ri = (float)(r64[i] * scale);
             x[i] = 0.0f;
-            r[i] = ri;
-            acc[1] += (double)ri * (double)(ri * invD[i]);
+            r[i] = (float)(r64[i] * scale);
+        }
+    }
+}
+
+// w = K D^-1 r for the start residual; partials (gamma, delta, r.r) into P0.
+// Active instances: act[i] when act is given, else those with an inner solve.
+template <class MT, class VT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_pcg_start_w(SV<MT> K, RowMap M, const int *__restrict__ act,
+                                                     const double *__restrict__ pin, const VT *__restrict__ r,
+                                                     const VT *__restrict__ invD, VT *__restrict__ w,
+                                                     double *__restrict__ part) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    if (act ? !act[t.inst] : !(pin[4 * t.inst + 1] > 0.0)) return;
+    __shared__ double sh[NW * 3];
+    const int rend = M.rend[t.inst], ln = lane_id();
+    double acc[3] = {0, 0, 0};
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        int64_t base = K.sptr[s];
+        int wd = (int)((K.sptr[s + 1] - base) >> 6);
+        VT wv = 0;
+        for (int k = 0; k < wd; ++k) {
+            int64_t e = base + 64 * k + ln;
+            int c = K.col[e];
+            wv += (VT)K.val[e] * (invD[c] * r[c]);
+        }
+        int row = s * 64 + ln;
+        if (row < rend) {
+            VT ri = r[row];
+            VT ui = invD[row] * ri;
+            w[row] = wv;
+            acc[0] += (double)ri * (double)ui;
+            acc[1] += (double)wv * (double)ui;
             acc[2] += (double)ri * (double)ri;
         }
     }
-    write_part<3, kPW>(acc, 0u, slot(part, M.nblk, kINIT), M.nblk, t.b, sh);
+    write_part<3, NW>(acc, 0u, slot(part, M.nblk, kP0), M.nblk, t.b, sh);
 }
 
 // one block per instance: reduce the start partials into the instance's CG
-// state and seed the ring so that the first kernel A sees r.z (new) and +inf
-// (old), i.e. beta = 0.
+// state and seed the scalar ring so that the first iteration has beta = 0.
 // mode 0: CG start, tol2 = rtol2 * b.b; mode 1: FP32 inner start, tol2 =
 // pin[1] * r.r (inactive when pin[1] <= 0); mode 2: residual only (no CG).
-__global__ __launch_bounds__(kPB) void k_pcg_init_fin(RowMap M, double *__restrict__ part, double rtol2, int mode,
-                                                      const int *__restrict__ act, const double *__restrict__ pin,
-                                                      PcgState *__restrict__ st) {
-    __shared__ double sh[kPW * 3];
+__global__ __launch_bounds__(kFinBlock) void k_pcg_init_fin(RowMap M, const double *__restrict__ part, double rtol2,
+                                                      int mode, const int *__restrict__ act,
+                                                      const double *__restrict__ pin, PcgState *__restrict__ st) {
+    __shared__ double sh[kFinW * 3];
     const int i = blockIdx.x;
     const bool on = (mode == 1) ? (pin[4 * i + 1] > 0.0) : (act ? act[i] != 0 : true);
     if (!on) {
@@ -117,9 +150,10 @@ __global__ __launch_bounds__(kPB) void k_pcg_init_fin(RowMap M, double *__restri
         return;
     }
     const int S = M.nblk, b0 = M.ipb[i], b1 = M.ipb[i + 1];
-    double t[3];
-    read_part<3, kPW>(slot(part, S, kINIT), S, b0, b1, 0u, t, sh);
-    const double bb = t[0], rz = t[1], rr = t[2];
+    double ini[2] = {0, 0}, p0[3] = {0, 0, 0};
+    if (mode != 1) read_part<2, kFinW>(slot(part, S, kINIT), S, b0, b1, 0u, ini, sh);
+    if (mode != 2) read_part<3, kFinW>(slot(part, S, kP0), S, b0, b1, 0u, p0, sh);
+    const double bb = ini[0], rr = (mode == 1) ? p0[2] : ini[1];
     const double tol2 = (mode == 1) ? pin[4 * i + 1] * rr : rtol2 * bb;
     if (threadIdx.x == 0) {
         st[i].bb = bb;
@@ -129,122 +163,122 @@ __global__ __launch_bounds__(kPB) void k_pcg_init_fin(RowMap M, double *__restri
         st[i].active = 1;
         st[i].zero_u = (mode != 1 && bb == 0.0) ? 1 : 0;
         st[i].done = (mode == 2 || (mode != 1 && bb == 0.0) || rr <= tol2) ? 1 : 0;
-    }
-    if (mode == 2) return;
-    double *nw = slot(part, S, kRZ1), *od = slot(part, S, kRZ0);
-    for (int k = b0 + (int)threadIdx.x; k < b1; k += kPB) {
-        nw[k] = (k == b0) ? rz : 0.0;
-        nw[(size_t)S + k] = (k == b0) ? rr : 0.0;
-        od[k] = (k == b0) ? __builtin_huge_val() : 0.0;
-        od[(size_t)S + k] = 0.0;
+        // iteration 0 reads slot 1: gamma_prev = inf gives beta = 0
+        st[i].gamma[1] = __builtin_huge_val();
+        st[i].alpha[1] = 1.0;
     }
 }
 
-__device__ __forceinline__ int row_or_zero(int s, int ln, int rend) {
-    int row = s * 64 + ln;
-    return row < rend ? row : 0;
-}
-
-template <class VT>
-__device__ __forceinline__ VT pval(const VT *__restrict__ r, const VT *__restrict__ invD,
-                                   const VT *__restrict__ p_old, VT beta, int64_t c) {
-    VT z = r[c] * invD[c];
-    return beta != (VT)0 ? z + beta * p_old[c] : z;
-}
-
-// kernel A of iteration j (odd = j & 1): convergence test on the residual of
-// iteration j-1 (every block of the instance decides alike; its first block
-// raises the flag), then beta, p_new = D^-1 r + beta p_old, q = K p_new,
-// partial p_new.q
-template <class MT, class VT>
-__global__ __launch_bounds__(kPB) void k_pcg_a(SV<MT> K, RowMap M, const VT *__restrict__ r,
-                                               const VT *__restrict__ invD, const VT *__restrict__ p_old,
-                                               VT *__restrict__ p_new, VT *__restrict__ q, PcgState *__restrict__ st,
-                                               int phase, int odd, double *__restrict__ part) {
+// one CG iteration of parity `par`: reads r, w, s of buffer par and the
+// partials P[par]; writes buffer par ^ 1 and P[par ^ 1].
+// w_new = K D^-1 (r - alpha (w + beta s)) is formed as A - alpha (B + beta C)
+// with A, B, C the products of K D^-1 with r, w and s: these do not depend on
+// the iteration's scalars, so the matrix gathers of a wave's first slice are
+// issued before the block has reduced the previous partials.
+template <class MT, class VT, class XT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
+                                                      const VT *__restrict__ invD, PcgState *__restrict__ st, int par,
+                                                      double *__restrict__ part) {
     Tile t = tile_of(M);
     if (t.inst < 0) return;
     PcgState *si = st + t.inst;
-    if (si->done) return;
-    __shared__ double sh[kPW * 2];
+    __shared__ double sh[NW * 3];
+    __shared__ int sdone;
     const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
-    double nw[2], od[1];
-    read_part<2, kPW>(slot(part, S, odd ? kRZ0 : kRZ1), S, b0, b1, 0u, nw, sh);
-    if (nw[1] <= si->tol2) {
-        if (t.b == b0 && threadIdx.x == 0) si->done = phase;
+    const double *pp = slot((const double *)part, S, par ? kP1 : kP0);
+    double g3[3] = {0, 0, 0};
+    for (int i = b0 + (int)threadIdx.x; i < b1; i += NW * 64) {
+        g3[0] += pp[i];
+        g3[1] += pp[(size_t)S + i];
+        g3[2] += pp[2 * (size_t)S + i];
+    }
+    // the flag is read once per block, so every wave of the block takes the
+    // same branch even while another block raises it
+    if (threadIdx.x == 0) sdone = si->done;
+    __syncthreads();
+    if (sdone) return;
+    const VT *__restrict__ r0 = v.r[par];
+    const VT *__restrict__ w0 = v.w[par];
+    const VT *__restrict__ s0 = v.s[par];
+    VT *__restrict__ r1 = v.r[par ^ 1];
+    VT *__restrict__ w1 = v.w[par ^ 1];
+    VT *__restrict__ s1 = v.s[par ^ 1];
+    VT *__restrict__ p = v.p;
+    const int rend = M.rend[t.inst], ln = lane_id();
+    // products of the wave's first slice
+    const int sf = t.s0 + wave_id();
+    VT pa = 0, pb = 0, pc = 0;
+    if (sf < t.s1) {
+        int64_t base = K.sptr[sf];
+        int wd = (int)((K.sptr[sf + 1] - base) >> 6);
+        for (int k = 0; k < wd; ++k) {
+            int64_t e = base + 64 * k + ln;
+            int c = K.col[e];
+            VT kd = (VT)K.val[e] * invD[c];
+            pa += kd * r0[c];
+            pb += kd * w0[c];
+            pc += kd * s0[c];
+        }
+    }
+    block_reduce<3, NW>(g3, 0u, sh);
+    const double gam = g3[0], del = g3[1], rr = g3[2];
+    if (rr <= si->tol2) {
+        if (t.b == b0 && threadIdx.x == 0) si->done = 2 + par;
         return;
     }
-    read_part<1, kPW>(slot(part, S, odd ? kRZ1 : kRZ0), S, b0, b1, 0u, od, sh);
-    const VT beta = (VT)(nw[0] / od[0]);
-    if (t.b == b0 && threadIdx.x == 0) si->iters += 1;
-    const int rend = M.rend[t.inst], ln = lane_id();
-    double acc[1] = {0};
-    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
-        int64_t base = K.sptr[s];
-        int w = (int)((K.sptr[s + 1] - base) >> 6);
-        VT qv = 0;
-        // entries in groups of 8 with every load of a group issued before use
-        for (int k0 = 0; k0 < w; k0 += 8) {
-            int cc[8];
-            VT vv[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                bool in = k0 + k < w;
-                int64_t e = base + 64 * (k0 + k) + ln;
-                cc[k] = in ? K.col[e] : row_or_zero(s, ln, rend);
-                vv[k] = in ? (VT)K.val[e] : (VT)0;
+    const double beta = gam / si->gamma[par ^ 1];
+    const double alpha = gam / (del - beta * gam / si->alpha[par ^ 1]);
+    if (t.b == b0 && threadIdx.x == 0) {
+        si->gamma[par] = gam;
+        si->alpha[par] = alpha;
+        si->iters += 1;
+    }
+    const VT a = (VT)alpha, bt = (VT)beta;
+    double acc[3] = {0, 0, 0};
+    for (int s = sf; s < t.s1; s += NW) {
+        if (s != sf) {
+            int64_t base = K.sptr[s];
+            int wd = (int)((K.sptr[s + 1] - base) >> 6);
+            pa = pb = pc = 0;
+            for (int k = 0; k < wd; ++k) {
+                int64_t e = base + 64 * k + ln;
+                int c = K.col[e];
+                VT kd = (VT)K.val[e] * invD[c];
+                pa += kd * r0[c];
+                pb += kd * w0[c];
+                pc += kd * s0[c];
             }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) qv += vv[k] * pval(r, invD, p_old, beta, cc[k]);
         }
         int row = s * 64 + ln;
         if (row < rend) {
-            VT pn = pval(r, invD, p_old, beta, row);
-            p_new[row] = pn;
-            q[row] = qv;
-            acc[0] += (double)pn * (double)qv;
+            const VT dinv = invD[row], ri = r0[row];
+            VT sn = bt != (VT)0 ? w0[row] + bt * s0[row] : w0[row];
+            VT pn = bt != (VT)0 ? dinv * ri + bt * p[row] : dinv * ri;
+            VT rn = ri - a * sn;
+            VT wn = bt != (VT)0 ? pa - a * (pb + bt * pc) : pa - a * pb;
+            x[row] += (XT)(a * pn);
+            p[row] = pn;
+            s1[row] = sn;
+            r1[row] = rn;
+            w1[row] = wn;
+            VT un = dinv * rn;
+            acc[0] += (double)rn * (double)un;
+            acc[1] += (double)wn * (double)un;
+            acc[2] += (double)rn * (double)rn;
         }
     }
-    write_part<1, kPW>(acc, 0u, slot(part, S, kPQ), S, t.b, sh);
-}
-
-// kernel B of iteration j: alpha = r.z / p.q; x += alpha p, r -= alpha q;
-// partials (r.z, r.r) into the ring slot of iteration j
-template <class VT, class XT>
-__global__ __launch_bounds__(kPB) void k_pcg_b(RowMap M, XT *__restrict__ x, VT *__restrict__ r,
-                                               const VT *__restrict__ p, const VT *__restrict__ q,
-                                               const VT *__restrict__ invD, PcgState *__restrict__ st, int phase,
-                                               int odd, double *__restrict__ part) {
-    Tile t = tile_of(M);
-    if (t.inst < 0 || st[t.inst].done) return;
-    __shared__ double sh[kPW * 2];
-    const int S = M.nblk, b0 = M.ipb[t.inst], b1 = M.ipb[t.inst + 1];
-    double pq[1], rz[1];
-    read_part<1, kPW>(slot(part, S, kPQ), S, b0, b1, 0u, pq, sh);
-    read_part<1, kPW>(slot(part, S, odd ? kRZ0 : kRZ1), S, b0, b1, 0u, rz, sh);
-    const VT a = (VT)(rz[0] / pq[0]);
-    const int rend = M.rend[t.inst];
-    double acc[2] = {0, 0};
-    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
-        int i = s * 64 + lane_id();
-        if (i < rend) {
-            x[i] += (XT)(a * p[i]);
-            VT ri = r[i] - a * q[i];
-            r[i] = ri;
-            acc[0] += (double)ri * (double)(ri * invD[i]);
-            acc[1] += (double)ri * (double)ri;
-        }
-    }
-    write_part<2, kPW>(acc, 0u, slot(part, S, odd ? kRZ1 : kRZ0), S, t.b, sh);
+    write_part<3, NW>(acc, 0u, slot(part, S, par ? kP0 : kP1), S, t.b, sh);
 }
 
 // u += rn_i * x32 for the instances with an inner solve
-__global__ __launch_bounds__(kPB) void k_add_correction(RowMap M, const double *__restrict__ pin, double *__restrict__ u,
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_add_correction(RowMap M, const double *__restrict__ pin, double *__restrict__ u,
                                                         const float *__restrict__ x) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !(pin[4 * t.inst + 1] > 0.0)) return;
     const double sc = pin[4 * t.inst + 2];
     const int rend = M.rend[t.inst];
-    for (int s = t.s0 + wave_id(); s < t.s1; s += kPW) {
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         int i = s * 64 + lane_id();
         if (i < rend) u[i] += sc * (double)x[i];
     }
@@ -252,51 +286,69 @@ __global__ __launch_bounds__(kPB) void k_add_correction(RowMap M, const double *
 
 }  // namespace
 
-void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, bool fp32_matrix, hipStream_t s) {
+// instantiate the launch for the block shape of the row map
+#define MMNCG_NW_SWITCH(nw, ...)            \
+    switch (nw) {                           \
+        case 4: {                           \
+            constexpr int NW = 4;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 8: {                           \
+            constexpr int NW = 8;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        default: {                          \
+            constexpr int NW = 16;          \
+            __VA_ARGS__;                    \
+        } break;                            \
+    }
+
+void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, hipStream_t s) {
     const RowMap &M = *a.M;
-    if (fp32_matrix)
-        hipLaunchKernelGGL(k_pcg_init64<float>, dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, act, a.b, a.u,
-                           a.r, a.invD, a.part, 1);
-    else
-        hipLaunchKernelGGL(k_pcg_init64<double>, dim3(M.nblk), dim3(kPB), 0, s, view<double>(*a.K), M, act, a.b, a.u,
-                           a.r, a.invD, a.part, 1);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, rtol2, 0, act, a.pin, a.st);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<double>(*a.K), M, act, a.b, a.u, a.v64.r[0], a.part);
+                    hipLaunchKernelGGL((k_pcg_start_w<double, double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                       view<double>(*a.K), M, act, a.pin, (const double *)a.v64.r[0], a.invD,
+                                       a.v64.w[0], a.part))
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, rtol2, 0, act,
+                       a.pin, a.st);
 }
 
 void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s) {
     const RowMap &M = *a.M;
-    hipLaunchKernelGGL(k_pcg_init64<float>, dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, act, a.b, a.u, a.r,
-                       a.invD, a.part, 0);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, 0.0, 2, act, a.pin, a.st);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<float>(*a.K), M, act, a.b, a.u, a.v64.r[0], a.part))
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, 0.0, 2, act,
+                       a.pin, a.st);
 }
 
 void launch_pcg_init32(const PcgLaunch &a, hipStream_t s) {
     const RowMap &M = *a.M;
-    hipLaunchKernelGGL(k_pcg_init32, dim3(M.nblk), dim3(kPB), 0, s, M, a.pin, a.r, a.x32, a.r32, a.invD32, a.part);
-    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kPB), 0, s, M, a.part, 0.0, 1, nullptr, a.pin, a.st);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_start32<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,
+                                             (const double *)a.v64.r[0], a.x32, a.v32.r[0]);
+                    hipLaunchKernelGGL((k_pcg_start_w<float, float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                       view<float>(*a.K), M, (const int *)nullptr, a.pin, (const float *)a.v32.r[0],
+                                       a.invD32, a.v32.w[0], a.part))
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, 0.0, 1,
+                       (const int *)nullptr, a.pin, a.st);
 }
 
-void launch_pcg_iter64(const PcgLaunch &a, int phase_a, int odd, hipStream_t s) {
+void launch_pcg_iter64(const PcgLaunch &a, int parity, hipStream_t s) {
     const RowMap &M = *a.M;
-    double *po = odd ? a.p1 : a.p0, *pn = odd ? a.p0 : a.p1;
-    hipLaunchKernelGGL((k_pcg_a<double, double>), dim3(M.nblk), dim3(kPB), 0, s, view<double>(*a.K), M, a.r, a.invD,
-                       po, pn, a.q, a.st, phase_a, odd, a.part);
-    hipLaunchKernelGGL((k_pcg_b<double, double>), dim3(M.nblk), dim3(kPB), 0, s, M, a.u, a.r, pn, a.q, a.invD, a.st,
-                       phase_a + 1, odd, a.part);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<double, double, double, NW>), dim3(M.nblk), dim3(NW * 64),
+                                             0, s, view<double>(*a.K), M, a.v64, a.u, a.invD, a.st, parity, a.part))
 }
 
-void launch_pcg_iter32(const PcgLaunch &a, int phase_a, int odd, hipStream_t s) {
+void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s) {
     const RowMap &M = *a.M;
-    float *po = odd ? a.p32b : a.p32a, *pn = odd ? a.p32a : a.p32b;
-    hipLaunchKernelGGL((k_pcg_a<float, float>), dim3(M.nblk), dim3(kPB), 0, s, view<float>(*a.K), M, a.r32, a.invD32,
-                       po, pn, a.q32, a.st, phase_a, odd, a.part);
-    hipLaunchKernelGGL((k_pcg_b<float, float>), dim3(M.nblk), dim3(kPB), 0, s, M, a.x32, a.r32, pn, a.q32, a.invD32,
-                       a.st, phase_a + 1, odd, a.part);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<float, float, float, NW>), dim3(M.nblk), dim3(NW * 64), 0,
+                                             s, view<float>(*a.K), M, a.v32, a.x32, a.invD32, a.st, parity, a.part))
 }
 
 void launch_add_correction(const PcgLaunch &a, hipStream_t s) {
     const RowMap &M = *a.M;
-    hipLaunchKernelGGL(k_add_correction, dim3(M.nblk), dim3(kPB), 0, s, M, a.pin, a.u, a.x32);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_add_correction<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,
+                                             a.u, a.x32))
 }
 
 }  // namespace mmncg

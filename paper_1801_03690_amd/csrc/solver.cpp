@@ -36,7 +36,7 @@ using namespace mmncg;
 namespace {
 
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
-constexpr int kPcgChunk = 8;  // CG iterations per captured graph (even: the p double buffer returns)
+constexpr int kPcgChunk = 16;  // CG iterations per captured graph (even: the double buffers return to parity 0)
 
 struct HipError {
     hipError_t e;
@@ -100,7 +100,7 @@ struct mm_ctx {
     mm_free_fn ufree = nullptr;
     void *user = nullptr;
     std::string err;
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;
     size_t dev_bytes = 0;
 
     // single-instance mesh (host copy until materials arrive)
@@ -115,15 +115,21 @@ struct mm_ctx {
 
     Sell C, S, K, B, Bt;
     DevMap Mm, Mp, Mb;  // magnet rows, potential rows, divergence rows
+    // block shape of the scalar-potential kernels: waves per block (launch
+    // wide) and SELL slices per wave of each instance
+    int pnw = kPoissonWaves;
+    std::vector<int> pspw, poff, pn;
+    bool tuned = false;
     double *L = nullptr, *invDex = nullptr, *invDK = nullptr;
     float *invDK32 = nullptr;
 
     StateV st[3];  // current state, trial T, trial C
     double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
            *dscale = nullptr, *tmp3 = nullptr;
-    double *u = nullptr, *b = nullptr, *cr = nullptr, *cp = nullptr, *cp2 = nullptr, *cq = nullptr,
-           *usave = nullptr;
-    float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr;
+    double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
+    double *cg64[7] = {};  // CG vectors: r[2], w[2], s[2], p
+    float *cg32[7] = {};
+    float *x32 = nullptr;
     PcgState *pst = nullptr;    // device, ninst
     PcgState *hpst = nullptr;   // pinned host mirror
     double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
@@ -187,9 +193,20 @@ void *dalloc(mm_ctx *c, size_t bytes) {
             throw ApiError{MM_ENOMEM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)"};
         }
     }
-    c->allocs.push_back(p);
+    c->allocs.push_back({p, bytes});
     c->dev_bytes += bytes;
     return p;
+}
+void dfree(mm_ctx *c, void *p) {
+    if (!p) return;
+    for (size_t k = 0; k < c->allocs.size(); ++k)
+        if (c->allocs[k].first == p) {
+            c->dev_bytes -= c->allocs[k].second;
+            c->allocs.erase(c->allocs.begin() + (long)k);
+            if (c->ufree) c->ufree(p, c->user);
+            else (void)hipFree(p);
+            return;
+        }
 }
 template <class T>
 T *dalloc_n(mm_ctx *c, size_t n) {
@@ -209,9 +226,9 @@ void free_all(mm_ctx *c) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
-    for (void *p : c->allocs) {
-        if (c->ufree) c->ufree(p, c->user);
-        else (void)hipFree(p);
+    for (auto &a : c->allocs) {
+        if (c->ufree) c->ufree(a.first, c->user);
+        else (void)hipFree(a.first);
     }
     c->allocs.clear();
     c->dev_bytes = 0;
@@ -390,7 +407,8 @@ void upload_vec(mm_ctx *c, double *dst, const std::vector<double> &v) {
 // are split evenly over min(kMaxBlocksPerInst, ceil(ns / slices_per_block))
 // blocks. The table is padded with empty blocks to a multiple of 8 (XCD
 // renumbering).
-void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vector<int> &n, int slices_per_block) {
+void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vector<int> &n,
+              const std::vector<int> &slices_per_block) {
     const int ni = (int)off.size();
     std::vector<int> tab;
     std::vector<int> ipb(ni + 1, 0), rend(ni, 0);
@@ -400,7 +418,8 @@ void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vec
         const int sf = off[i] / kSlice;
         rend[i] = off[i] + n[i];
         if (ns == 0) continue;
-        const int nb = std::min(kMaxBlocksPerInst, (ns + slices_per_block - 1) / slices_per_block);
+        const int spb = std::max(1, slices_per_block[i]);
+        const int nb = std::min(kMaxBlocksPerInst, (ns + spb - 1) / spb);
         for (int k = 0; k < nb; ++k) {
             tab.push_back(i);
             tab.push_back(sf + (int)((int64_t)k * ns / nb));
@@ -499,9 +518,13 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
         upload_sell(c, B, c->B);
         upload_sell(c, Bt, c->Bt);
     }
-    make_map(c, c->Mm, moff, nm, kBlock / kSlice);
-    make_map(c, c->Mp, poff, np, kPoissonBlock / kSlice);
-    make_map(c, c->Mb, boff, nb, kBlock / kSlice);
+    make_map(c, c->Mm, moff, nm, std::vector<int>(ni, kBlock / kSlice));
+    make_map(c, c->Mb, boff, nb, std::vector<int>(ni, kBlock / kSlice));
+    c->pnw = kPoissonWaves;
+    c->pspw.assign(ni, 1);
+    c->poff = poff;
+    c->pn = np;
+    make_map(c, c->Mp, poff, np, std::vector<int>(ni, kPoissonWaves));
 
     const size_t RM = std::max(rm, 1), RP = std::max(rp, 1);
     c->L = dalloc_n<double>(c, RM);
@@ -530,8 +553,10 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     }
     for (double **p : {&c->gprev, &c->d, &c->y, &c->pr, &c->pp, &c->pq, &c->tmp3}) *p = dalloc_n<double>(c, 3 * RM);
     c->dscale = dalloc_n<double>(c, RM);
-    for (double **p : {&c->u, &c->b, &c->cr, &c->cp, &c->cp2, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
-    for (float **p : {&c->x32, &c->r32, &c->p32, &c->p32b, &c->q32}) *p = dalloc_n<float>(c, RP);
+    for (double **p : {&c->u, &c->b, &c->cr, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
+    for (double *&p : c->cg64) p = dalloc_n<double>(c, RP);
+    for (float *&p : c->cg32) p = dalloc_n<float>(c, RP);
+    c->x32 = dalloc_n<float>(c, RP);
     c->pst = dalloc_n<PcgState>(c, ni);
     c->mpart = dalloc_n<double>(c, (size_t)MS_TOTAL * c->Mm.map.nblk);
     c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
@@ -556,10 +581,11 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     for (double *p : {c->gprev, c->d, c->y, c->pr, c->pp, c->pq, c->tmp3})
         HIPCHK(hipMemsetAsync(p, 0, 3 * RM * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->dscale, 0, RM * sizeof(double), c->stream));
-    for (double *p : {c->u, c->b, c->cr, c->cp, c->cp2, c->cq, c->usave})
+    for (double *p : {c->u, c->b, c->cr, c->cq, c->usave})
         HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
-    for (float *p : {c->x32, c->r32, c->p32, c->p32b, c->q32})
-        HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(float), c->stream));
+    for (double *p : c->cg64) HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
+    for (float *p : c->cg32) HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(float), c->stream));
+    HIPCHK(hipMemsetAsync(c->x32, 0, RP * sizeof(float), c->stream));
     HIPCHK(hipMemsetAsync(c->pst, 0, ni * sizeof(PcgState), c->stream));
     HIPCHK(hipMemsetAsync(c->mpart, 0, (size_t)MS_TOTAL * c->Mm.map.nblk * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->ppart, 0, (size_t)kPcgSlots * c->Mp.map.nblk * sizeof(double), c->stream));
@@ -572,11 +598,11 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     c->pcg_bytes64.assign(ni, 0.0);
     c->pcg_bytes32.assign(ni, 0.0);
     for (int i = 0; i < ni; ++i) {
-        // kernel A: matrix + r, D^-1, p_old read + p_new, q written;
-        // kernel B: x, r, p, q, D^-1 read + x, r written
+        // one iteration: the matrix (values + column indices) once; r, w, s,
+        // D^-1, p, x read and r, w, s, p, x written once per row
         const double nnz = (double)c->inst[i].nnz_K, rows = (double)c->inst[i].n_pot;
-        c->pcg_bytes64[i] = nnz * (8.0 + 4.0) + 12.0 * 8.0 * rows;
-        c->pcg_bytes32[i] = nnz * (4.0 + 4.0) + 12.0 * 4.0 * rows;
+        c->pcg_bytes64[i] = nnz * (8.0 + 4.0) + 11.0 * 8.0 * rows;
+        c->pcg_bytes32[i] = nnz * (4.0 + 4.0) + 11.0 * 4.0 * rows;
     }
 }
 
@@ -592,26 +618,21 @@ PcgLaunch pcg_args(mm_ctx *c) {
     a.part = c->ppart;
     a.u = c->u;
     a.b = c->b;
-    a.r = c->cr;
-    a.p0 = c->cp;
-    a.p1 = c->cp2;
-    a.q = c->cq;
     a.invD = c->invDK;
+    a.v64 = PcgVecs<double>{{c->cg64[0], c->cg64[1]}, {c->cg64[2], c->cg64[3]}, {c->cg64[4], c->cg64[5]}, c->cg64[6]};
     a.x32 = c->x32;
-    a.r32 = c->r32;
-    a.p32a = c->p32;
-    a.p32b = c->p32b;
-    a.q32 = c->q32;
     a.invD32 = c->invDK32;
+    a.v32 = PcgVecs<float>{{c->cg32[0], c->cg32[1]}, {c->cg32[2], c->cg32[3]}, {c->cg32[4], c->cg32[5]}, c->cg32[6]};
     a.pin = c->d_(c->pin());
+    a.nw = c->pnw;
     return a;
 }
 
 void pcg_chunk(mm_ctx *c, bool fp32) {
     PcgLaunch a = pcg_args(c);
     for (int j = 0; j < kPcgChunk; ++j) {
-        if (fp32) launch_pcg_iter32(a, 2 * j + 2, j & 1, c->stream);
-        else launch_pcg_iter64(a, 2 * j + 2, j & 1, c->stream);
+        if (fp32) launch_pcg_iter32(a, j & 1, c->stream);
+        else launch_pcg_iter64(a, j & 1, c->stream);
     }
 }
 
@@ -623,7 +644,7 @@ bool use_graphs() {
     return on;
 }
 
-// capture kPcgChunk iterations (2 kernels each) once per context and mode
+// capture kPcgChunk iterations (one kernel each) once per context and mode
 hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32) {
     hipGraphExec_t &ge = fp32 ? c->graph32 : c->graph64;
     if (ge) return ge;
@@ -695,7 +716,7 @@ void zero_pot(mm_ctx *c, int i) {
 std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
     std::vector<long> it(c->ninst, 0);
     PcgLaunch a = pcg_args(c);
-    launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, false, c->stream);
+    launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, c->stream);
     pcg_replay(c, false, maxit, on);
     for (int i : on) {
         if (c->hpst[i].zero_u) {
@@ -775,6 +796,200 @@ void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<in
         c->cnt[i].mi += it[i];
         c->cnt[i].t_mag += dt;
     }
+}
+
+// ---------------------------------------------------------------------------
+// block shape of the scalar-potential kernels and its autotuner
+// ---------------------------------------------------------------------------
+// Rebuilds the potential-row map for nw waves per block and spw[i] slices per
+// wave of instance i. Captured graphs hold the old map: they are dropped.
+void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
+    sync(c);
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
+    dfree(c, (void *)c->Mp.map.tab);
+    dfree(c, (void *)c->Mp.map.ipb);
+    dfree(c, (void *)c->Mp.map.rend);
+    std::vector<int> spb(c->ninst);
+    for (int i = 0; i < c->ninst; ++i) spb[i] = nw * spw[i];
+    const int old = c->Mp.map.nblk;
+    make_map(c, c->Mp, c->poff, c->pn, spb);
+    if (c->Mp.map.nblk > old) {
+        dfree(c, c->ppart);
+        c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
+        HIPCHK(hipMemsetAsync(c->ppart, 0, (size_t)kPcgSlots * c->Mp.map.nblk * sizeof(double), c->stream));
+        sync(c);
+    }
+    c->pnw = nw;
+    c->pspw = spw;
+}
+
+// size bucket of an instance for the tuner: floor(log2(n_pot / 4096)), 0..7
+int size_bucket(int n_pot) {
+    int b = 0;
+    for (long v = n_pot / 4096; v > 1 && b < 7; v >>= 1) ++b;
+    return b;
+}
+
+// Average time of one CG iteration (seconds) over the instances in `on`, for
+// the current block shape: a synthetic right-hand side (b = 1 on every free
+// node, u = 0), a tolerance that never stops, 4 untimed and 32 timed eager
+// iterations, best of 3. The caller saves and restores u and b.
+double time_pcg(mm_ctx *c, const std::vector<int> &on, bool fp32) {
+    hipStream_t s = c->stream;
+    PcgLaunch a = pcg_args(c);
+    std::fill(c->act(), c->act() + c->ninst, 0);
+    for (int k = 0; k < c->ninst; ++k) c->pin()[4 * k + 1] = 0.0;
+    for (int i : on) {
+        c->act()[i] = 1;
+        c->pin()[4 * i] = 1.0;
+        c->pin()[4 * i + 1] = 1e-300;
+        c->pin()[4 * i + 2] = 1.0;
+    }
+    upload_ctl(c);
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+        launch_fill(c->rows_p, c->b, 1.0, s);
+        launch_fill(c->rows_p, c->u, 0.0, s);
+        launch_pcg_init64(a, c->d_(c->act()), 0.0, s);
+        if (fp32) launch_pcg_init32(a, s);
+        for (int j = 0; j < 4; ++j) fp32 ? launch_pcg_iter32(a, j & 1, s) : launch_pcg_iter64(a, j & 1, s);
+        HIPCHK(hipEventRecord(c->ev[0], s));
+        for (int j = 0; j < 32; ++j) fp32 ? launch_pcg_iter32(a, j & 1, s) : launch_pcg_iter64(a, j & 1, s);
+        HIPCHK(hipEventRecord(c->ev[1], s));
+        HIPCHK(hipEventSynchronize(c->ev[1]));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        best = std::min(best, ms * 1e-3 / 32.0);
+    }
+    sync(c);
+    std::fill(c->act(), c->act() + c->ninst, 0);
+    for (int k = 0; k < c->ninst; ++k) c->pin()[4 * k + 1] = 0.0;
+    return best;
+}
+
+struct TuneEntry {
+    std::string device;
+    int bucket, nw, spw, fp32;
+    double us;
+};
+
+std::string device_key(mm_ctx *c) {
+    hipDeviceProp_t p;
+    HIPCHK(hipGetDeviceProperties(&p, c->device));
+    std::string k = std::string(p.gcnArchName) + ":" + p.name + ":cu" + std::to_string(p.multiProcessorCount);
+    for (char &ch : k)
+        if (ch == '"' || ch == '\\' || ch == '\n') ch = '_';
+    return k;
+}
+
+// the cache is JSON with one entry object per line (written by tune_write)
+std::vector<TuneEntry> tune_read(const char *path) {
+    std::vector<TuneEntry> out;
+    if (!path) return out;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        char dev[512];
+        TuneEntry e;
+        if (std::sscanf(line, " {\"device\": \"%511[^\"]\", \"bucket\": %d, \"fp32\": %d, \"nw\": %d, \"spw\": %d, "
+                              "\"us\": %lf}",
+                        dev, &e.bucket, &e.fp32, &e.nw, &e.spw, &e.us) == 6) {
+            e.device = dev;
+            out.push_back(e);
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+void tune_write(const char *path, const std::vector<TuneEntry> &v) {
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) throw ApiError{MM_EINVAL, std::string("cannot write tuning cache ") + path};
+    std::fprintf(f, "{\"mmncg_tune\": 1, \"entries\": [\n");
+    for (size_t k = 0; k < v.size(); ++k)
+        std::fprintf(f, "  {\"device\": \"%s\", \"bucket\": %d, \"fp32\": %d, \"nw\": %d, \"spw\": %d, \"us\": %.4f}%s\n",
+                     v[k].device.c_str(), v[k].bucket, v[k].fp32, v[k].nw, v[k].spw, v[k].us,
+                     k + 1 < v.size() ? "," : "");
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+    if (std::rename(tmp.c_str(), path) != 0) throw ApiError{MM_EINVAL, std::string("cannot write ") + path};
+}
+
+constexpr int kTuneNw[3] = {4, 8, 16};
+constexpr int kTuneSpw[3] = {1, 2, 4};
+
+// Picks the block shape: per size bucket and waves-per-block candidate the
+// fastest slices-per-wave (timed, or taken from the cache), then the
+// waves-per-block value with the least total time over the batch.
+void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
+    const int ni = c->ninst;
+    std::vector<int> bucket(ni);
+    std::vector<std::vector<int>> members(8);
+    for (int i = 0; i < ni; ++i) {
+        bucket[i] = size_bucket(c->pn[i]);
+        if (c->pn[i] > 0) members[bucket[i]].push_back(i);
+    }
+    const std::string dev = device_key(c);
+    std::vector<TuneEntry> cache = use_cache ? tune_read(path) : std::vector<TuneEntry>();
+    auto cached = [&](int b, int nw) -> const TuneEntry * {
+        for (const TuneEntry &e : cache)
+            if (e.device == dev && e.bucket == b && e.nw == nw && e.fp32 == (fp32 ? 1 : 0)) return &e;
+        return nullptr;
+    };
+    // keep the warm start and the right-hand side aside
+    const size_t RP = std::max(c->rows_p, 1);
+    HIPCHK(hipMemcpyAsync(c->usave, c->u, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    double best_total = 1e300;
+    int best_nw = kPoissonWaves;
+    std::vector<int> best_spw(ni, 1);
+    bool measured = false;
+    for (int nw : kTuneNw) {
+        std::vector<int> spw(ni, 1);
+        double total = 0.0;
+        for (int b = 0; b < 8; ++b) {
+            if (members[b].empty()) continue;
+            const TuneEntry *e = cached(b, nw);
+            int pick = 1;
+            double t_pick = 0.0;
+            if (e) {
+                pick = e->spw;
+                t_pick = e->us * 1e-6;
+            } else {
+                double tb = 1e300;
+                for (int cand : kTuneSpw) {
+                    for (int i : members[b]) spw[i] = cand;
+                    set_poisson_shape(c, nw, spw);
+                    const double t = time_pcg(c, members[b], fp32);
+                    if (t < tb) {
+                        tb = t;
+                        pick = cand;
+                    }
+                }
+                t_pick = tb;
+                cache.push_back(TuneEntry{dev, b, nw, pick, fp32 ? 1 : 0, tb * 1e6});
+                measured = true;
+            }
+            for (int i : members[b]) spw[i] = pick;
+            total += t_pick;
+        }
+        if (total < best_total) {
+            best_total = total;
+            best_nw = nw;
+            best_spw = spw;
+        }
+    }
+    set_poisson_shape(c, best_nw, best_spw);
+    launch_fill((int64_t)RP, c->b, 0.0, c->stream);
+    HIPCHK(hipMemcpyAsync(c->u, c->usave, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    upload_ctl(c);
+    sync(c);
+    if (use_cache && measured) tune_write(path, cache);
+    c->tuned = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1789,6 +2004,32 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
         HIPCHK(hipMemcpyAsync(c->u, c->usave, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         sync(c);
         if (iters) *iters = it;
+        return MM_OK;
+    });
+}
+
+int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave) {
+    return guarded(c, [&] {
+        require_ready(c);
+        const bool fp32 = c->opts.precision == MM_FP32_BULK;
+        switch (mode) {
+            case MM_TUNE_DEFAULT:
+                set_poisson_shape(c, kPoissonWaves, std::vector<int>(c->ninst, 1));
+                c->tuned = false;
+                break;
+            case MM_TUNE_MEASURE:
+                autotune(c, false, nullptr, fp32);
+                break;
+            case MM_TUNE_CACHE:
+                if (!cache_path) throw ApiError{MM_EINVAL, "cache_path is required"};
+                autotune(c, true, cache_path, fp32);
+                break;
+            default:
+                throw ApiError{MM_EINVAL, "unknown tuning mode"};
+        }
+        if (waves_per_block) *waves_per_block = c->pnw;
+        if (slices_per_wave)
+            for (int i = 0; i < c->ninst; ++i) slices_per_wave[i] = c->pspw[i];
         return MM_OK;
     });
 }

@@ -6,6 +6,7 @@ must reproduce separate single-instance contexts bit for bit: the block
 partition of an instance and the order of its reductions do not depend on
 its neighbours in the batch. Inputs are seeded.
 """
+import json
 import math
 
 import numpy as np
@@ -158,4 +159,69 @@ def test_batch_empty_field_list_and_device_state(B):
     rh = ctx.batch_curve(m0, F, jmax=4)
     np.testing.assert_array_equal(md.cpu().numpy(), rh["m"])
     np.testing.assert_array_equal(rd["E"], rh["E"])
+    ctx.close()
+
+
+def _force_shape(path, nw, spw):
+    """Rewrite a tuning cache so that every bucket prefers (nw, spw)."""
+    out = []
+    for line in path.read_text().splitlines():
+        if '"device"' in line:
+            comma = line.rstrip().endswith(",")
+            d = json.loads(line.strip().rstrip(","))
+            d["spw"] = spw
+            d["us"] = 1.0 if d["nw"] == nw else 1000.0
+            line = "  " + json.dumps(d) + ("," if comma else "")
+        out.append(line)
+    path.write_text("\n".join(out) + "\n")
+
+
+def test_tuner_cache_and_forced_shape(B, oracle_mod, tmp_path):
+    meshes = batch_meshes()
+    cache = tmp_path / "tune.json"
+    ctx = B.Context(0).upload_batch(meshes)
+    nw, spw = ctx.tune(B.MM_TUNE_CACHE, str(cache))
+    assert nw in (4, 8, 16) and set(spw.tolist()) <= {1, 2, 4}
+    text = cache.read_text()
+    assert '"mmncg_tune": 1' in text
+    # a second call is served from the cache alone (the file is not rewritten)
+    mtime = cache.stat().st_mtime_ns
+    nw2, spw2 = ctx.tune(B.MM_TUNE_CACHE, str(cache))
+    assert (nw2, spw2.tolist()) == (nw, spw.tolist()) and cache.stat().st_mtime_ns == mtime
+    # force another shape: the batch still matches the oracle and equals
+    # single-instance contexts of the same shape bit for bit
+    _force_shape(cache, 8, 2)
+    nw3, spw3 = ctx.tune(B.MM_TUNE_CACHE, str(cache))
+    assert nw3 == 8 and set(spw3.tolist()) == {2}
+    m0 = start_states(meshes, seed=9)
+    F = fields_for(len(meshes), [0.0, -1.5])
+    rb = ctx.batch_curve(np.concatenate(m0), F, jmax=10)
+    mb = ctx.split(rb["m"])
+    ctx.close()
+    for i, mesh in enumerate(meshes):
+        s = B.Context(0).upload(mesh)
+        assert s.tune(B.MM_TUNE_CACHE, str(cache))[0] == 8
+        rs = s.curve(m0[i], F[i], jmax=10)
+        s.close()
+        np.testing.assert_array_equal(mb[i], rs["m"])
+        np.testing.assert_array_equal(rb["E"][i], rs["E"])
+        ro = oracle_mod.Oracle(mesh).curve(m0[i], F[i], jmax=10)
+        for k in range(F.shape[1]):
+            assert abs(rb["E"][i, k] - ro["E"][k]) <= 1e-8 * max(abs(ro["E"][k]), 1.0), (i, k)
+        assert np.abs(mb[i] - ro["m"]).max() <= 1e-5, i
+
+
+def test_tuner_measure_keeps_warm_start_and_results(B, oracle_mod):
+    mesh = batch_meshes()[1]
+    o = oracle_mod.Oracle(mesh)
+    m0 = start_states([mesh], seed=3)[0]
+    ctx = B.Context(0).upload(mesh)
+    r1 = ctx.minimize(m0, [0.0, 0.0, -1.0], jmax=10)
+    ctx.tune(B.MM_TUNE_MEASURE)
+    r2 = ctx.minimize(r1[0], [0.0, 0.0, -1.2], jmax=10)
+    ro1 = o.minimize(m0, [0.0, 0.0, -1.0], jmax=10)
+    ro2 = o.minimize(ro1[0], [0.0, 0.0, -1.2], jmax=10)
+    assert abs(r2[1][4] - ro2[1][4]) <= 1e-8 * abs(ro2[1][4])
+    assert np.abs(r2[0] - ro2[0]).max() <= 1e-5
+    ctx.tune(B.MM_TUNE_DEFAULT)
     ctx.close()
