@@ -332,3 +332,57 @@ CONFIGS = {
     3: film,
     4: polycrystal,
 }
+
+
+# ---------------------------------------------------------------------------
+# learned component: seeded parameters, probes and training films
+# ---------------------------------------------------------------------------
+
+GNN_F_IN, GNN_WIDTH, GNN_LAYERS, GNN_E_DIM = 32, 64, 3, 4
+
+
+def gnn_param_shapes():
+    """Flat parameter layout of the graph network (row-major [in][out])."""
+    shp = [("W_in", (GNN_F_IN, GNN_WIDTH)), ("b_in", (GNN_WIDTH,))]
+    for l in range(GNN_LAYERS):
+        shp += [(f"We1_{l}", (GNN_WIDTH, GNN_WIDTH)), (f"We2_{l}", (GNN_E_DIM, GNN_WIDTH)),
+                (f"W1_{l}", (2 * GNN_WIDTH, GNN_WIDTH)), (f"b1_{l}", (GNN_WIDTH,)),
+                (f"W2_{l}", (GNN_WIDTH, GNN_WIDTH)), (f"b2_{l}", (GNN_WIDTH,))]
+    shp += [("Wm", (GNN_WIDTH, 3)), ("bm", (3,)), ("Ws", (GNN_WIDTH, 1)), ("bs", (1,))]
+    return shp
+
+
+def gnn_init(seed, head_scale=0.01):
+    """Uniform(-r, r) weights with r = sqrt(6 / (fan_in + fan_out)), zero
+    biases; the residual branches' last matrices and the heads scaled down so
+    that the untrained network starts near dm = 0, s = softplus(0) + 1/4."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for name, s in gnn_param_shapes():
+        if len(s) == 1:
+            out.append(np.zeros(s))
+            continue
+        r = math.sqrt(6.0 / (s[0] + s[1]))
+        w = rng.uniform(-r, r, size=s)
+        if name.startswith("W2_"):
+            w *= 0.1
+        if name in ("Wm", "Ws"):
+            w *= head_scale
+        out.append(w)
+    return np.concatenate([w.ravel() for w in out])
+
+
+def rademacher(n_probe, n_rows, seed):
+    """Probe vectors with independent +-1 entries, shape (n_probe, n_rows, 3)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 2, size=(n_probe, n_rows, 3)).astype(np.float64) * 2.0 - 1.0
+
+
+def small_film(seed, lo=120.0, hi=280.0, h=5.0, nz=2, step_T=0.001, start_T=0.05):
+    """Training-size soft film: side lengths uniform in [lo, hi] nm (cells of
+    h nm, nz cells thick), field along x from +start_T to -start_T."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Lx, Ly = rng.uniform(lo, hi, size=2)
+    nx = max(2, int(round(Lx / h)))
+    ny = max(2, int(round(Ly / h)))
+    return film(nx=nx, ny=ny, nz=nz, h=h, seed=seed, step_T=step_T, start_T=start_T)
