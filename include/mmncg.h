@@ -278,6 +278,98 @@ int mm_batch_energy_grad(mm_ctx *c, const double *m, const double *h_ext, double
 int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, const mm_opts *o,
                          double *m_avg, double *E_tot, mm_stats *st);
 
+
+/* ---------------------------------------------------------------------------
+   Learned warm start and preconditioner scaling. Not part of the paper's
+   method: an addition on top of it. A small graph network on the magnet nodes
+   of a single-instance context proposes, for the step from the minimizer m_k
+   at field h_k to the next field h_{k+1}, a tangent update dm (candidate
+   start N(m_k + dm)) and a factor s_a in [1/4, 4] per node that multiplies
+   the exchange diagonal used as Jacobi preconditioner inside the
+   preconditioner's CG (the mm_precondition dscale). Alg. 4 always runs to the
+   same stopping rule afterwards, and the candidate start is used only when
+   its energy at h_{k+1} is lower than that of m_k (energy-raise fallback).
+
+   Network (widths fixed): inputs X (n x 32 node features, below); h0 =
+   SiLU(X W_in + b_in); three layers a = mean of h over the mesh neighbours, q
+   = a We1 + ebar We2 (ebar: mean edge features (x_j - x_i)/l, |x_j - x_i|/l,
+   l the mean edge length), t = SiLU([h | q] W1 + b1), h <- h + t W2 + b2;
+   heads dm = P_m(h Wm + bm), s = clip(softplus(h Ws + bs) + 1/4, 1/4, 4).
+   Neighbours: magnet nodes sharing a magnetic tet. The products with W_in,
+   We1, W1, W2 (and their gradients) run on BF16 operands (inputs rounded to
+   nearest even) with FP32 accumulation; everything else in FP32, losses and
+   node reductions accumulated in FP64. Parameters: one flat vector of
+   mm_gnn_param_count() values, matrices row-major [in][out], in the order
+   W_in (32x64), b_in, then per layer We1 (64x64), We2 (4x64), W1 (128x64),
+   b1, W2 (64x64), b2, then Wm (64x3), bm (3), Ws (64x1), bs (1).
+
+   Node features (columns): 0-2 m; 3-5 h_{k+1}; 6-8 h_{k+1} - h_k (reduced
+   units); 9-11 -(C m)_a / L_a; 12-14 -(B^T u)_a / L_a; 15-17 -g_a / L_a, all
+   at (m, h_{k+1}) with the options of mm_set_opts; 18 D_a / mean D (exchange
+   diagonal); 19 L_a / mean L; 20 deg_a / max deg; 21-31 zero.
+
+   Objects: a graph belongs to the context it was created on and is invalid
+   after that context's next upload or its destruction; destroy it before.
+   --------------------------------------------------------------------------- */
+typedef struct mm_gnn mm_gnn;
+typedef struct mm_graph mm_graph;
+enum { MM_LEARN_START = 1, MM_LEARN_SCALE = 2 };
+
+long mm_gnn_param_count(void);
+/* Network on the context's device; parameters zero until set. */
+int mm_gnn_create(mm_ctx *c, mm_gnn **out);
+int mm_gnn_destroy(mm_gnn *g);
+/* Message of the network's last failed call. The network keeps the device,
+   stream and allocator callbacks of its creating context, not that context's
+   buffers: it may serve graphs of any context on the same device and outlives
+   uploads to the creating context. */
+const char *mm_gnn_last_error(const mm_gnn *g);
+/* Parameters as doubles (host or device), kept as FP32 masters; setting
+   them also resets the optimizer state. */
+int mm_gnn_set_params(mm_gnn *g, const double *theta);
+int mm_gnn_get_params(mm_gnn *g, double *theta);
+
+/* Graph of the magnet nodes of a single-instance context set with
+   mm_mesh_upload + mm_material_set. */
+int mm_graph_create(mm_ctx *c, mm_graph **out);
+int mm_graph_destroy(mm_graph *gr);
+int mm_graph_size(const mm_graph *gr, long *n_nodes, long *n_edges);
+
+/* Node features for (m, h_prev -> h_next) (Tesla): one evaluation at
+   (m, h_next). Kept in the graph; copied to X (n x 32 floats, host or device)
+   when X != NULL. */
+int mm_gnn_features(mm_graph *gr, const double *m, const double h_prev[3], const double h_next[3], float *X);
+
+/* Forward pass: X (n x 32 floats, host or device; NULL = the graph's last
+   features), m (n x 3) -> dm (n x 3), s (n); outputs may be NULL. */
+int mm_gnn_forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *dm, double *s);
+
+/* Loss inv_dm2 * sum_a L_a |dm_a - dm*_a|^2 / sum_a L_a + w_s * mean_a
+   (log s_a - log s*_a)^2 (L: the lumped Ms-weighted volumes) and its gradient
+   with respect to the parameters, which is kept for mm_gnn_adam and copied to
+   grad (mm_gnn_param_count() doubles, host or device) when grad != NULL. */
+int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, const double *dm_target,
+                     const double *s_target, double inv_dm2, double w_s, double *loss, double *grad);
+
+/* One Adam step (bias-corrected) with the last gradient. */
+int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps);
+
+/* Hutchinson estimate of the diagonal of the magnetostatic Hessian block
+   B^T K^-1 B of instance 0: mean over the n_probe probe vectors z (n_probe x
+   n_mag x 3, host or device) of z * (B^T K^-1 B z), each potential solved to
+   |r| <= rtol |b| from zero. diag: n_mag x 3. The warm start is kept. */
+int mm_demag_diag(mm_ctx *c, const double *probes, int n_probe, double rtol, double *diag);
+
+/* Demagnetization curve (as mm_demag_curve, single instance) with the
+   learned proposal at every field after the first: mode MM_LEARN_START uses
+   the candidate start when it lowers the energy, MM_LEARN_SCALE uses the
+   Jacobi factors for that field step's preconditioner solves; mode 0 is the
+   plain method. accepted (n ints, may be NULL) marks the fields whose
+   candidate start was taken. */
+int mm_demag_curve_learned(mm_ctx *c, mm_gnn *net, mm_graph *graph, int mode, double *m_inout,
+                           const double *h_list, long n, const mm_opts *o, double *m_avg, double *E_tot,
+                           mm_stats *st, int *accepted);
+
 #ifdef __cplusplus
 }
 #endif

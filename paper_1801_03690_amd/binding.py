@@ -28,6 +28,7 @@ MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
 MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
 MM_TUNE_DEFAULT, MM_TUNE_MEASURE, MM_TUNE_CACHE = 0, 1, 2
+MM_LEARN_START, MM_LEARN_SCALE = 1, 2
 
 
 class MMError(RuntimeError):
@@ -72,7 +73,7 @@ _vp = C.c_void_p
 def header_symbols():
     """Names of the functions the public header declares."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(mm_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|long|const char \*)\s*(mm_\w+)\s*\(", txt, re.M)))
 
 
 def load_library(path=LIB_PATH):
@@ -104,11 +105,29 @@ def load_library(path=LIB_PATH):
     L.mm_batch_magnet_nodes.argtypes = [_vp, C.c_int, _lp, _ip]
     L.mm_batch_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
     L.mm_tune.argtypes = [_vp, C.c_int, C.c_char_p, _ip, _ip]
+    _fp = C.POINTER(C.c_float)
+    L.mm_gnn_param_count.restype = C.c_long
+    L.mm_gnn_param_count.argtypes = []
+    L.mm_gnn_create.argtypes = [_vp, C.POINTER(_vp)]
+    L.mm_gnn_destroy.argtypes = [_vp]
+    L.mm_gnn_last_error.restype = C.c_char_p
+    L.mm_gnn_last_error.argtypes = [_vp]
+    L.mm_gnn_set_params.argtypes = [_vp, _vp]
+    L.mm_gnn_get_params.argtypes = [_vp, _vp]
+    L.mm_graph_create.argtypes = [_vp, C.POINTER(_vp)]
+    L.mm_graph_destroy.argtypes = [_vp]
+    L.mm_graph_size.argtypes = [_vp, _lp, _lp]
+    L.mm_gnn_features.argtypes = [_vp, _vp, _dp, _dp, _vp]
+    L.mm_gnn_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.mm_gnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp]
+    L.mm_gnn_adam.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.mm_demag_diag.argtypes = [_vp, _vp, C.c_int, C.c_double, _vp]
+    L.mm_demag_curve_learned.argtypes = [_vp, _vp, _vp, C.c_int, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp,
+                                         C.POINTER(Stats), _ip]
     L.mm_batch_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats)]
     for name in header_symbols():
-        if getattr(L, name).restype is C.c_int or name != "mm_last_error":
-            if name != "mm_last_error":
-                getattr(L, name).restype = C.c_int
+        if name not in ("mm_last_error", "mm_gnn_last_error", "mm_gnn_param_count"):
+            getattr(L, name).restype = C.c_int
     return L
 
 
@@ -116,9 +135,18 @@ _LIB = None
 _LIVE = weakref.WeakSet()
 
 
+_LIVE_NETS = weakref.WeakSet()
+
+
 @atexit.register
 def _close_all():
-    # release device memory through the allocator callbacks while torch is alive
+    # release device memory through the allocator callbacks while torch is
+    # alive: networks and graphs first, then the contexts
+    for net in list(_LIVE_NETS):
+        try:
+            net.close()
+        except Exception:
+            pass
     for ctx in list(_LIVE):
         try:
             ctx.close()
@@ -148,22 +176,23 @@ def _host_f64(a, shape=None):
     return a if shape is None else a.reshape(shape)
 
 
-def _vec_ptr(x):
+def _vec_ptr(x, dtype=np.float64):
     """Pointer for a vector argument: torch CUDA tensor -> its device pointer,
-    anything else -> contiguous float64 numpy array on the host. Work queued by
-    torch on its current stream is waited for first (the library may run on
-    a stream of its own)."""
+    anything else -> contiguous numpy array of `dtype` on the host. Work
+    queued by torch on its current stream is waited for first (the library
+    may run on a stream of its own)."""
     try:
         import torch
         if isinstance(x, torch.Tensor):
-            if x.dtype != torch.float64 or not x.is_contiguous():
-                raise TypeError("device vectors must be contiguous float64 tensors")
+            want = torch.float64 if dtype == np.float64 else torch.float32
+            if x.dtype != want or not x.is_contiguous():
+                raise TypeError(f"device vectors must be contiguous {want} tensors")
             if x.is_cuda:
                 torch.cuda.current_stream(x.device).synchronize()
             return C.c_void_p(x.data_ptr()), x
     except ImportError:
         pass
-    a = np.ascontiguousarray(x, dtype=np.float64)
+    a = np.ascontiguousarray(x, dtype=dtype)
     return C.c_void_p(a.ctypes.data), a
 
 
@@ -425,3 +454,131 @@ class Context:
                                                       mavg.ctypes.data_as(_dp), Et.ctypes.data_as(_dp), st))
         stats = [[st[i * nf + k].as_dict() for k in range(nf)] for i in range(ni)]
         return dict(m=keep, m_avg=mavg, E=Et, stats=stats, rc=rc)
+
+    # ----------------------------------------------------------------
+    # learned warm start / scaling (single instance)
+    def demag_diag(self, probes, rtol=1e-10):
+        """Hutchinson estimate of diag(B^T K^-1 B) from probes (P, n_mag, 3)."""
+        pp, keep = _vec_ptr(probes)
+        P = int(np.asarray(probes.shape)[0]) if hasattr(probes, "shape") else len(probes)
+        out = np.zeros((self.n_mag, 3))
+        self._check(self._L.mm_demag_diag(self.h, pp, P, float(rtol), C.c_void_p(out.ctypes.data)))
+        return out
+
+    def curve_learned(self, net, graph, mode, m, fields_T, opts=None, **kw):
+        o = opts or default_opts(**kw)
+        mp, keep = _vec_ptr(m)
+        if isinstance(keep, np.ndarray):
+            keep = keep.copy()
+            mp = C.c_void_p(keep.ctypes.data)
+        F = _host_f64(fields_T, (-1, 3))
+        nf = F.shape[0]
+        mavg = np.zeros((nf, 3))
+        Et = np.zeros(nf)
+        st = (Stats * nf)()
+        acc = np.zeros(nf, dtype=np.int32)
+        rc = self._check(self._L.mm_demag_curve_learned(
+            self.h, net.h if net else None, graph.h if graph else None, int(mode), mp, F.ctypes.data_as(_dp), nf,
+            C.byref(o), mavg.ctypes.data_as(_dp), Et.ctypes.data_as(_dp), st, acc.ctypes.data_as(_ip)))
+        return dict(m=keep, m_avg=mavg, E=Et, stats=[s.as_dict() for s in st], rc=rc, accepted=acc)
+
+
+def gnn_param_count():
+    return int(lib().mm_gnn_param_count())
+
+
+class Graph:
+    """Magnet-node graph of a single-instance context (mm_graph)."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self._L = ctx._L
+        h = C.c_void_p()
+        ctx._check(self._L.mm_graph_create(ctx.h, C.byref(h)))
+        self.h = h
+        n, e = C.c_long(), C.c_long()
+        self._L.mm_graph_size(h, C.byref(n), C.byref(e))
+        self.n, self.n_edges = n.value, e.value
+        _LIVE_NETS.add(self)
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self._L.mm_graph_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def features(self, m, h_prev_T, h_next_T, out=None):
+        """Node features (n x 32 float32) for (m, h_prev -> h_next)."""
+        mp, keep = _vec_ptr(m)
+        hp = _host_f64(h_prev_T, (3,))
+        hn = _host_f64(h_next_T, (3,))
+        X = np.zeros((self.n, 32), dtype=np.float32) if out is None else out
+        xp, xk = _vec_ptr(X, np.float32)
+        self.ctx._check(self._L.mm_gnn_features(self.h, mp, hp.ctypes.data_as(_dp), hn.ctypes.data_as(_dp), xp))
+        return X
+
+
+class Gnn:
+    """Graph network of the learned warm start / scaling (mm_gnn)."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self._L = ctx._L
+        h = C.c_void_p()
+        ctx._check(self._L.mm_gnn_create(ctx.h, C.byref(h)))
+        self.h = h
+        self.n_params = gnn_param_count()
+        _LIVE_NETS.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mm_gnn_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc < 0:
+            raise MMError(rc, self._L.mm_gnn_last_error(self.h).decode())
+        return rc
+
+    def set_params(self, theta):
+        tp, keep = _vec_ptr(theta)
+        self._chk(self._L.mm_gnn_set_params(self.h, tp))
+
+    def get_params(self):
+        out = np.zeros(self.n_params)
+        self._chk(self._L.mm_gnn_get_params(self.h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def forward(self, graph, X, m):
+        xp, xk = (None, None) if X is None else _vec_ptr(X, np.float32)
+        mp, mk = _vec_ptr(m)
+        dm = np.zeros((graph.n, 3))
+        s = np.zeros(graph.n)
+        self._chk(self._L.mm_gnn_forward(self.h, graph.h, xp, mp, C.c_void_p(dm.ctypes.data),
+                                         C.c_void_p(s.ctypes.data)))
+        return dm, s
+
+    def loss_grad(self, graph, X, m, dm_target, s_target, inv_dm2=1.0, w_s=1.0, want_grad=True):
+        xp, xk = (None, None) if X is None else _vec_ptr(X, np.float32)
+        mp, mk = _vec_ptr(m)
+        tp, tk = _vec_ptr(dm_target)
+        sp, sk = _vec_ptr(s_target)
+        loss = C.c_double()
+        grad = np.zeros(self.n_params) if want_grad else None
+        self._chk(self._L.mm_gnn_loss_grad(self.h, graph.h, xp, mp, tp, sp, float(inv_dm2), float(w_s),
+                                           C.byref(loss), None if grad is None else C.c_void_p(grad.ctypes.data)))
+        return loss.value, grad
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._chk(self._L.mm_gnn_adam(self.h, float(lr), float(beta1), float(beta2), float(eps)))

@@ -1,0 +1,217 @@
+// Context of the mmncg library shared by its host translation units (the
+// solver control in solver.cpp, the learned component in gnn.cpp): device
+// buffers and control block of a batch of instances, error handling and the
+// helpers both use. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mmncg.h"
+#include "internal.h"
+
+namespace mmncg {
+
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr int kPcgChunk = 16;  // CG iterations per captured graph (even: the double buffers return to parity 0)
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+#define HIPCHK(x)                                     \
+    do {                                              \
+        hipError_t _e = (x);                          \
+        if (_e != hipSuccess) throw HipError{_e, #x}; \
+    } while (0)
+
+struct ApiError {
+    int code;
+    std::string msg;
+};
+
+// magnet-row partial slots (each M.nblk doubles)
+enum MagSlot {
+    MS_EVAL = 0,                   // kEvalParts
+    MS_PREC = MS_EVAL + kEvalParts,  // 7
+    MS_DOTS = MS_PREC + 7,         // kDirParts
+    MS_DOUT = MS_DOTS + kDirParts,  // 2
+    MS_MISC = MS_DOUT + 2,         // 5
+    MS_TOTAL = MS_MISC + 5
+};
+
+// per-instance metadata kept on the host
+struct InstInfo {
+    long n_nodes = 0, n_tets = 0;
+    int n_mag = 0, n_pot = 0, n_brow = 0;
+    int mag_off = 0, pot_off = 0, brow_off = 0;  // first global (padded) row
+    long user_off = 0;                           // first magnet node in caller arrays
+    long nnz_C = 0, nnz_K = 0, nnz_B = 0;
+    double Ms_ref = 0;
+    std::vector<int> node_of_mag;
+};
+
+// device tables of one RowMap
+struct DevMap {
+    RowMap map;
+};
+
+// scalars of one evaluation point
+struct Sc {
+    double E = 0, Eloc = 0, Ez = 0, Ed = 0, tmax = 0, ginf = 0, minf = 0, dF = 0, dphi = 0, dxinf = 0;
+};
+
+// running counters of an instance (monotone; per-field stats are differences)
+struct Cnt {
+    long evals = 0, mi = 0, li = 0;
+    double t_mag = 0, t_lin = 0;
+};
+
+
+}  // namespace mmncg
+
+struct mm_gnn;
+struct mm_graph;
+
+using namespace mmncg;  // private header: the context's members are library types
+
+struct mm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mm_alloc_fn ualloc = nullptr;
+    mm_free_fn ufree = nullptr;
+    void *user = nullptr;
+    std::string err;
+    std::vector<std::pair<void *, size_t>> allocs;
+    size_t dev_bytes = 0;
+
+    // single-instance mesh (host copy until materials arrive)
+    std::vector<double> xyz;
+    std::vector<int> tets, region;
+    bool have_mesh = false, have_mat = false;
+
+    int ninst = 0;
+    std::vector<InstInfo> inst;
+    long tot_mag = 0;   // sum of n_mag (caller layout)
+    int rows_m = 0, rows_p = 0, rows_b = 0;  // padded global row counts
+
+    Sell C, S, K, B, Bt;
+    DevMap Mm, Mp, Mb;  // magnet rows, potential rows, divergence rows
+    // block shape of the scalar-potential kernels: waves per block (launch
+    // wide) and SELL slices per wave of each instance
+    int pnw = kPoissonWaves;
+    std::vector<int> pspw, poff, pn;
+    bool tuned = false;
+    double *L = nullptr, *invDex = nullptr, *invDK = nullptr;
+    float *invDK32 = nullptr;
+
+    StateV st[3];  // current state, trial T, trial C
+    double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
+           *dscale = nullptr, *tmp3 = nullptr;
+    double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
+    double *cg64[7] = {};  // CG vectors: r[2], w[2], s[2], p
+    float *cg32[7] = {};
+    float *x32 = nullptr;
+    PcgState *pst = nullptr;    // device, ninst
+    PcgState *hpst = nullptr;   // pinned host mirror
+    double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
+    double *ppart = nullptr;    // potential-row partials, kPcgSlots slots
+    hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+
+    // control block: ints {act, role, first, from, pact, plive} (host-written)
+    // then {info, pflags x4} (device-written); doubles {alpha, h3 x3, pin x4}
+    int *dci = nullptr, *hci = nullptr;
+    double *dcd = nullptr, *hcd = nullptr;
+    // finalize outputs: eval (kEvalParts), dir (2), misc (5) per instance
+    double *dsc = nullptr, *hsc = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+    mm_opts opts;
+    std::vector<long> last_pcg;
+    std::vector<double> pcg_bytes64, pcg_bytes32;
+    std::vector<Cnt> cnt;
+    // kernel timing (mm_profile)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_seconds = 0, prof_units = 0, prof_bytes = 0;
+
+    // control block accessors
+    int *act() const { return hci; }
+    int *role() const { return hci + ninst; }
+    int *first() const { return hci + 2 * ninst; }
+    int *from() const { return hci + 3 * ninst; }
+    int *pact() const { return hci + 4 * ninst; }
+    int *plive() const { return hci + 5 * ninst; }
+    int *info() const { return hci + 6 * ninst; }
+    int *pflags() const { return hci + 7 * ninst; }
+    double *alpha() const { return hcd; }
+    double *h3() const { return hcd + ninst; }
+    double *pin() const { return hcd + 4 * ninst; }
+    template <class T>
+    T *dev(T *hostp, T *hbase, T *dbase) const {
+        return dbase + (hostp - hbase);
+    }
+    int *d_(int *hp) const { return dci + (hp - hci); }
+    double *d_(double *hp) const { return dcd + (hp - hcd); }
+};
+
+namespace mmncg {
+
+// --- helpers (solver.cpp) ---
+void *dalloc(mm_ctx *c, size_t bytes);
+template <class T>
+T *dalloc_n(mm_ctx *c, size_t n) {
+    return (T *)dalloc(c, n * sizeof(T));
+}
+void dfree(mm_ctx *c, void *p);
+bool is_device_ptr(const void *p);
+void copy_in(mm_ctx *c, double *dst, const double *src, size_t n);
+void copy_out(mm_ctx *c, double *dst, const double *src, size_t n);
+void sync(mm_ctx *c);
+void upload_ctl(mm_ctx *c);
+void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<int> &on);
+void load_m(mm_ctx *c, const double *m);
+void reduce_field(const InstInfo &I, const double *BT, double h[3]);
+void eval_all(mm_ctx *c, const mm_opts &o, const std::vector<double> &h);
+Sc eval_result(mm_ctx *c, int i);
+mm_opts resolve_opts(const mm_opts *o);
+void require_ready(mm_ctx *c);
+void require_single(mm_ctx *c);
+
+// --- learned component (gnn.cpp) ---
+// After the evaluation of instance 0 at (m_k, h_next) has filled the current
+// state, writes the network's tangent proposal into c->d and its Jacobi
+// factors into c->dscale (both on the magnet rows).
+void gnn_propose(mm_ctx *c, mm_gnn *g, mm_graph *gr, const double h_prev[3], const double h_next[3]);
+
+template <class F>
+int guarded(mm_ctx *c, F &&f) {
+    if (!c) return MM_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(c->device));
+        int rc = f();
+        if (rc >= 0) c->err.clear();
+        return rc;
+    } catch (const ApiError &e) {
+        c->err = e.msg;
+        return e.code;
+    } catch (const HipError &e) {
+        c->err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+        (void)hipGetLastError();
+        return MM_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return MM_ENOMEM;
+    } catch (const std::exception &e) {
+        c->err = e.what();
+        return MM_EDEVICE;
+    }
+}
+
+}  // namespace mmncg

@@ -1,0 +1,578 @@
+// Host side of the learned component (not part of the paper's method): the
+// graph of a context's magnet nodes, the network's parameters and optimizer
+// state, forward and backward passes built from the kernels of gnn.hip, the
+// Hutchinson probe of the magnetostatic diagonal, and the proposal the curve
+// driver asks for at each new field value.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <vector>
+
+#include "context.h"
+
+struct mm_graph {
+    mm_ctx *c = nullptr;
+    int n = 0;
+    long nnz = 0;
+    int *ptr = nullptr, *idx = nullptr;
+    float *invdeg = nullptr, *ebar = nullptr, *stat = nullptr, *X = nullptr;
+    double sumL = 0.0;
+    std::vector<void *> mem;
+};
+
+// The network is independent of any one context: it keeps the device, the
+// stream and the allocator callbacks of the context it was created on (not
+// that context's buffers), so graphs of other contexts on the same device can
+// use it and it survives their uploads.
+struct mm_gnn {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mm_alloc_fn ualloc = nullptr;
+    mm_free_fn ufree = nullptr;
+    void *user = nullptr;
+    std::string err;
+    float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+    long t = 0;
+    int cap = 0;  // workspace rows
+    std::vector<void *> ws;
+    float *X = nullptr, *y0 = nullptr, *h3 = nullptr, *zm = nullptr, *zs = nullptr, *dh = nullptr, *dt = nullptr,
+          *dy = nullptr, *dz = nullptr, *da = nullptr, *d_zm = nullptr, *d_zs = nullptr, *part = nullptr;
+    float *z[3] = {}, *a[3] = {}, *y1[3] = {}, *tt[3] = {};
+    double *m = nullptr, *dmt = nullptr, *st = nullptr, *lpart = nullptr, *loss = nullptr, *dm = nullptr,
+           *s = nullptr;
+    std::vector<void *> mem;
+};
+
+namespace mmncg {
+namespace {
+
+constexpr int kF = 32, kW = 64, kLayers = 3;
+// flat parameter offsets (row-major [in][out]; see the C ABI)
+constexpr int oWin = 0, oBin = kF * kW, oLayer0 = oBin + kW;
+constexpr int kLayerSize = kW * kW + 4 * kW + 2 * kW * kW + kW + kW * kW + kW;
+constexpr int oHeads = oLayer0 + kLayers * kLayerSize;
+constexpr int kNParams = oHeads + kW * 3 + 3 + kW + 1;
+int oWe1(int l) { return oLayer0 + l * kLayerSize; }
+int oWe2(int l) { return oWe1(l) + kW * kW; }
+int oW1(int l) { return oWe2(l) + 4 * kW; }
+int ob1(int l) { return oW1(l) + 2 * kW * kW; }
+int oW2(int l) { return ob1(l) + kW; }
+int ob2(int l) { return oW2(l) + kW * kW; }
+constexpr int oWm = oHeads, obm = oWm + kW * 3, oWs = obm + 3, obs = oWs + kW;
+
+template <class T>
+T *galloc(mm_ctx *c, std::vector<void *> &keep, size_t n) {
+    T *p = dalloc_n<T>(c, n);
+    keep.push_back(p);
+    return p;
+}
+void release(mm_ctx *c, std::vector<void *> &keep) {
+    for (void *p : keep) dfree(c, p);
+    keep.clear();
+}
+
+// network memory: the creating context's allocator, not tracked by it
+template <class T>
+T *nalloc(mm_gnn *g, std::vector<void *> &keep, size_t n) {
+    size_t bytes = std::max<size_t>(n * sizeof(T), 256);
+    void *p = nullptr;
+    if (g->ualloc) {
+        p = g->ualloc(bytes, g->user);
+        if (!p) throw ApiError{MM_ENOMEM, "device allocation callback failed"};
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw ApiError{MM_ENOMEM, "hipMalloc failed"};
+    }
+    keep.push_back(p);
+    return (T *)p;
+}
+void nrelease(mm_gnn *g, std::vector<void *> &keep) {
+    for (void *p : keep) {
+        if (g->ufree) g->ufree(p, g->user);
+        else (void)hipFree(p);
+    }
+    keep.clear();
+}
+
+template <class F>
+int gguard(mm_gnn *g, F &&f) {
+    if (!g) return MM_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(g->device));
+        int rc = f();
+        if (rc >= 0) g->err.clear();
+        return rc;
+    } catch (const ApiError &e) {
+        g->err = e.msg;
+        return e.code;
+    } catch (const HipError &e) {
+        g->err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+        (void)hipGetLastError();
+        return MM_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        g->err = "host allocation failed";
+        return MM_ENOMEM;
+    } catch (const std::exception &e) {
+        g->err = e.what();
+        return MM_EDEVICE;
+    }
+}
+void gsync(mm_gnn *g) { HIPCHK(hipStreamSynchronize(g->stream)); }
+
+void copy_d_in(hipStream_t s, double *dst, const double *src, size_t n) {
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+void copy_d_out(hipStream_t s, double *dst, const double *src, size_t n) {
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+}
+
+void copy_f32_in(hipStream_t s, float *dst, const float *src, size_t n) {
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(float),
+                          is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+void copy_f32_out(mm_ctx *c, float *dst, const float *src, size_t n) {
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(float),
+                          is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+}
+
+void ensure_ws(mm_gnn *g, int n) {
+    if (n <= g->cap) return;
+    gsync(g);
+    nrelease(g, g->ws);
+    const size_t N = (size_t)std::max(n, 1);
+    g->X = nalloc<float>(g, g->ws, N * kF);
+    g->y0 = nalloc<float>(g, g->ws, N * kW);
+    for (int l = 0; l < kLayers; ++l) {
+        g->z[l] = nalloc<float>(g, g->ws, N * 2 * kW);
+        g->a[l] = nalloc<float>(g, g->ws, N * kW);
+        g->y1[l] = nalloc<float>(g, g->ws, N * kW);
+        g->tt[l] = nalloc<float>(g, g->ws, N * kW);
+    }
+    g->h3 = nalloc<float>(g, g->ws, N * kW);
+    g->zm = nalloc<float>(g, g->ws, N * 3);
+    g->zs = nalloc<float>(g, g->ws, N);
+    g->dh = nalloc<float>(g, g->ws, N * kW);
+    g->dt = nalloc<float>(g, g->ws, N * kW);
+    g->dy = nalloc<float>(g, g->ws, N * kW);
+    g->dz = nalloc<float>(g, g->ws, N * 2 * kW);
+    g->da = nalloc<float>(g, g->ws, N * kW);
+    g->d_zm = nalloc<float>(g, g->ws, N * 3);
+    g->d_zs = nalloc<float>(g, g->ws, N);
+    g->part = nalloc<float>(g, g->ws, (size_t)gnn_tn_blocks(n) * 2 * kW * kW);
+    g->m = nalloc<double>(g, g->ws, N * 3);
+    g->dmt = nalloc<double>(g, g->ws, N * 3);
+    g->st = nalloc<double>(g, g->ws, N);
+    g->dm = nalloc<double>(g, g->ws, N * 3);
+    g->s = nalloc<double>(g, g->ws, N);
+    g->lpart = nalloc<double>(g, g->ws, (size_t)gnn_loss_blocks(n) + 1);
+    g->loss = nalloc<double>(g, g->ws, 1);
+    g->cap = n;
+}
+
+// forward pass on X (device, n x 32) and m (device, n x 3); dm, s (device
+// doubles, may be null) receive the heads' outputs
+void forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *dm, double *sv) {
+    const int n = gr->n;
+    hipStream_t s = g->stream;
+    const float *th = g->theta;
+    gnn_mm(n, kF, kW, 1, X, kF, th + oWin, kW, false, th + oBin, g->z[0], 2 * kW, g->y0, kW, nullptr, 0, s);
+    for (int l = 0; l < kLayers; ++l) {
+        float *z = g->z[l];
+        gnn_agg(n, gr->ptr, gr->idx, gr->invdeg, z, 2 * kW, g->a[l], kW, s);
+        gnn_mm(n, kW, kW, 0, g->a[l], kW, th + oWe1(l), kW, false, nullptr, z + kW, 2 * kW, nullptr, 0, nullptr, 0, s);
+        gnn_edge_add(n, gr->ebar, th + oWe2(l), z + kW, 2 * kW, s);
+        gnn_mm(n, 2 * kW, kW, 1, z, 2 * kW, th + oW1(l), kW, false, th + ob1(l), g->tt[l], kW, g->y1[l], kW, nullptr,
+               0, s);
+        float *hn = (l + 1 < kLayers) ? g->z[l + 1] : g->h3;
+        const int ldh = (l + 1 < kLayers) ? 2 * kW : kW;
+        gnn_mm(n, kW, kW, 2, g->tt[l], kW, th + oW2(l), kW, false, th + ob2(l), hn, ldh, nullptr, 0, z, 2 * kW, s);
+    }
+    gnn_heads(n, g->h3, th + oWm, th + obm, th + oWs, th + obs, m, g->zm, g->zs, dm, sv, s);
+}
+
+// backward pass after forward(); d_zm, d_zs hold the loss gradient at the heads
+void backward(mm_gnn *g, mm_graph *gr, const float *X) {
+    const int n = gr->n;
+    hipStream_t s = g->stream;
+    const float *th = g->theta;
+    float *gr_ = g->grad;
+    float *part = g->part;
+    gnn_tn32(n, kW, 3, g->h3, kW, g->d_zm, 3, part, gr_ + oWm, s);
+    gnn_tn32(n, 1, 3, nullptr, 0, g->d_zm, 3, part, gr_ + obm, s);
+    gnn_tn32(n, kW, 1, g->h3, kW, g->d_zs, 1, part, gr_ + oWs, s);
+    gnn_tn32(n, 1, 1, nullptr, 0, g->d_zs, 1, part, gr_ + obs, s);
+    gnn_heads_dh(n, g->d_zm, g->d_zs, th + oWm, th + oWs, g->dh, s);
+    for (int l = kLayers - 1; l >= 0; --l) {
+        float *z = g->z[l];
+        gnn_mm_tn(n, kW, kW, g->tt[l], kW, g->dh, kW, part, gr_ + oW2(l), false, s);
+        gnn_tn32(n, 1, kW, nullptr, 0, g->dh, kW, part, gr_ + ob2(l), s);
+        gnn_mm(n, kW, kW, 0, g->dh, kW, th + oW2(l), kW, true, nullptr, g->dt, kW, nullptr, 0, nullptr, 0, s);
+        gnn_silu_bwd((int64_t)n * kW, g->dt, g->y1[l], g->dy, s);
+        gnn_mm_tn(n, 2 * kW, kW, z, 2 * kW, g->dy, kW, part, gr_ + oW1(l), false, s);
+        gnn_tn32(n, 1, kW, nullptr, 0, g->dy, kW, part, gr_ + ob1(l), s);
+        gnn_mm(n, kW, 2 * kW, 0, g->dy, kW, th + oW1(l), kW, true, nullptr, g->dz, 2 * kW, nullptr, 0, nullptr, 0, s);
+        gnn_add64(n, g->dz, 2 * kW, g->dh, kW, s);
+        gnn_mm_tn(n, kW, kW, g->a[l], kW, g->dz + kW, 2 * kW, part, gr_ + oWe1(l), false, s);
+        gnn_tn32(n, 4, kW, gr->ebar, 4, g->dz + kW, 2 * kW, part, gr_ + oWe2(l), s);
+        gnn_mm(n, kW, kW, 0, g->dz + kW, 2 * kW, th + oWe1(l), kW, true, nullptr, g->da, kW, nullptr, 0, nullptr, 0, s);
+        gnn_agg_t_add(n, gr->ptr, gr->idx, gr->invdeg, g->da, kW, g->dh, kW, s);
+    }
+    gnn_silu_bwd((int64_t)n * kW, g->dh, g->y0, g->dy, s);
+    gnn_mm_tn(n, kF, kW, X, kF, g->dy, kW, part, gr_ + oWin, false, s);
+    gnn_tn32(n, 1, kW, nullptr, 0, g->dy, kW, part, gr_ + oBin, s);
+}
+
+// features of the current state of instance 0 (st[0] filled by an
+// evaluation at h_next) into gr->X
+void features_from_state(mm_ctx *c, mm_graph *gr, const double hp[3], const double hn[3]) {
+    launch_spmv_block6(c->C, c->Mm.map, c->st[0].x, c->tmp3, false, c->stream);
+    gnn_features(gr->n, c->st[0].x, c->st[0].G, c->st[0].g, c->tmp3, c->L, gr->stat, hn, hp, gr->X, c->stream);
+}
+
+// a graph of any context on the network's device; that context's queued
+// work is finished first (its buffers are read on the network's stream)
+void check_pair(mm_gnn *g, mm_graph *gr) {
+    if (!g || !gr) throw ApiError{MM_EINVAL, "null network or graph"};
+    if (gr->c->device != g->device) throw ApiError{MM_EINVAL, "network and graph are on different devices"};
+    if (gr->c->stream != g->stream) sync(gr->c);
+}
+
+}  // namespace
+
+void gnn_propose(mm_ctx *c, mm_gnn *g, mm_graph *gr, const double h_prev[3], const double h_next[3]) {
+    if (!g || !gr || gr->c != c) throw ApiError{MM_EINVAL, "network and graph of this context are required"};
+    ensure_ws(g, gr->n);
+    features_from_state(c, gr, h_prev, h_next);
+    check_pair(g, gr);
+    forward(g, gr, gr->X, c->st[0].x, c->d, c->dscale);
+    if (g->stream != c->stream) gsync(g);
+}
+
+}  // namespace mmncg
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+long mm_gnn_param_count(void) { return mmncg::kNParams; }
+
+int mm_gnn_create(mm_ctx *c, mm_gnn **out) {
+    if (!out) return MM_EINVAL;
+    *out = nullptr;
+    return guarded(c, [&] {
+        mm_gnn *g = new mm_gnn();
+        g->device = c->device;
+        g->stream = c->stream;
+        g->ualloc = c->ualloc;
+        g->ufree = c->ufree;
+        g->user = c->user;
+        try {
+            g->theta = nalloc<float>(g, g->mem, kNParams);
+            g->grad = nalloc<float>(g, g->mem, kNParams);
+            g->m1 = nalloc<float>(g, g->mem, kNParams);
+            g->m2 = nalloc<float>(g, g->mem, kNParams);
+            for (float *p : {g->theta, g->grad, g->m1, g->m2})
+                HIPCHK(hipMemsetAsync(p, 0, kNParams * sizeof(float), g->stream));
+            gsync(g);
+        } catch (...) {
+            nrelease(g, g->mem);
+            delete g;
+            throw;
+        }
+        *out = g;
+        return MM_OK;
+    });
+}
+
+int mm_gnn_destroy(mm_gnn *g) {
+    if (!g) return MM_EINVAL;
+    (void)hipSetDevice(g->device);
+    (void)hipStreamSynchronize(g->stream);
+    nrelease(g, g->ws);
+    nrelease(g, g->mem);
+    delete g;
+    return MM_OK;
+}
+
+const char *mm_gnn_last_error(const mm_gnn *g) { return g ? g->err.c_str() : "null network"; }
+
+int mm_gnn_set_params(mm_gnn *g, const double *theta) {
+    return gguard(g, [&] {
+        if (!theta) throw ApiError{MM_EINVAL, "null parameters"};
+        std::vector<float> h(kNParams);
+        std::vector<double> src(kNParams);
+        if (is_device_ptr(theta)) HIPCHK(hipMemcpy(src.data(), theta, kNParams * sizeof(double), hipMemcpyDeviceToHost));
+        else std::memcpy(src.data(), theta, kNParams * sizeof(double));
+        for (int i = 0; i < kNParams; ++i) {
+            if (!std::isfinite(src[i])) throw ApiError{MM_EINVAL, "non-finite parameter"};
+            h[i] = (float)src[i];
+        }
+        HIPCHK(hipMemcpyAsync(g->theta, h.data(), kNParams * sizeof(float), hipMemcpyHostToDevice, g->stream));
+        for (float *p : {g->m1, g->m2}) HIPCHK(hipMemsetAsync(p, 0, kNParams * sizeof(float), g->stream));
+        g->t = 0;
+        gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_get_params(mm_gnn *g, double *theta) {
+    return gguard(g, [&] {
+        if (!theta) throw ApiError{MM_EINVAL, "null parameters"};
+        std::vector<float> h(kNParams);
+        HIPCHK(hipMemcpyAsync(h.data(), g->theta, kNParams * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+        gsync(g);
+        std::vector<double> d(h.begin(), h.end());
+        if (is_device_ptr(theta)) HIPCHK(hipMemcpy(theta, d.data(), kNParams * sizeof(double), hipMemcpyHostToDevice));
+        else std::memcpy(theta, d.data(), kNParams * sizeof(double));
+        return MM_OK;
+    });
+}
+
+int mm_graph_create(mm_ctx *c, mm_graph **out) {
+    if (!out) return MM_EINVAL;
+    *out = nullptr;
+    return guarded(c, [&] {
+        require_single(c);
+        if (c->tets.empty()) throw ApiError{MM_ESTATE, "the graph needs a mesh set with mm_mesh_upload"};
+        const InstInfo &I = c->inst[0];
+        const int n = I.n_mag;
+        std::vector<int> local(c->xyz.size() / 3, -1);
+        for (int a = 0; a < n; ++a) local[I.node_of_mag[a]] = a;
+        std::vector<std::set<int>> nb(n);
+        const long nt = (long)c->region.size();
+        for (long t = 0; t < nt; ++t) {
+            if (c->region[t] <= 0) continue;
+            int v[4];
+            for (int k = 0; k < 4; ++k) v[k] = local[c->tets[4 * t + k]];
+            for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q)
+                    if (p != q) nb[v[p]].insert(v[q]);
+        }
+        std::vector<int> ptr(n + 1, 0), idx;
+        for (int a = 0; a < n; ++a) {
+            for (int b : nb[a]) idx.push_back(b);
+            ptr[a + 1] = (int)idx.size();
+        }
+        auto X = [&](int a, int k) { return c->xyz[3 * (size_t)I.node_of_mag[a] + k]; };
+        double lsum = 0.0;
+        for (int a = 0; a < n; ++a)
+            for (int e = ptr[a]; e < ptr[a + 1]; ++e) {
+                const int b = idx[e];
+                double d2 = 0.0;
+                for (int k = 0; k < 3; ++k) d2 += (X(b, k) - X(a, k)) * (X(b, k) - X(a, k));
+                lsum += std::sqrt(d2);
+            }
+        const double ell = idx.empty() ? 1.0 : lsum / (double)idx.size();
+        std::vector<float> ebar(4 * (size_t)n, 0.0f), invdeg(n, 0.0f), stat(3 * (size_t)n);
+        int maxdeg = 1;
+        for (int a = 0; a < n; ++a) maxdeg = std::max(maxdeg, ptr[a + 1] - ptr[a]);
+        // lumped volumes and exchange diagonal of the context
+        std::vector<double> L(n), iD(n);
+        HIPCHK(hipMemcpyAsync(L.data(), c->L, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(iD.data(), c->invDex, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        double Lm = 0.0, Dm = 0.0;
+        for (int a = 0; a < n; ++a) {
+            Lm += L[a];
+            Dm += 1.0 / iD[a];
+        }
+        const double sumL = Lm;
+        Lm /= n;
+        Dm /= n;
+        for (int a = 0; a < n; ++a) {
+            const int dg = ptr[a + 1] - ptr[a];
+            double acc[4] = {0, 0, 0, 0};
+            for (int e = ptr[a]; e < ptr[a + 1]; ++e) {
+                const int b = idx[e];
+                double d[3], d2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    d[k] = (X(b, k) - X(a, k)) / ell;
+                    d2 += d[k] * d[k];
+                }
+                for (int k = 0; k < 3; ++k) acc[k] += d[k];
+                acc[3] += std::sqrt(d2);
+            }
+            for (int k = 0; k < 4; ++k) ebar[4 * (size_t)a + k] = dg ? (float)(acc[k] / dg) : 0.0f;
+            invdeg[a] = dg ? 1.0f / (float)dg : 0.0f;
+            stat[3 * (size_t)a] = (float)((1.0 / iD[a]) / Dm);
+            stat[3 * (size_t)a + 1] = (float)(L[a] / Lm);
+            stat[3 * (size_t)a + 2] = (float)dg / (float)maxdeg;
+        }
+        mm_graph *gr = new mm_graph();
+        gr->c = c;
+        gr->n = n;
+        gr->nnz = (long)idx.size();
+        gr->sumL = sumL;
+        try {
+            gr->ptr = galloc<int>(c, gr->mem, n + 1);
+            gr->idx = galloc<int>(c, gr->mem, std::max<size_t>(idx.size(), 1));
+            gr->invdeg = galloc<float>(c, gr->mem, n);
+            gr->ebar = galloc<float>(c, gr->mem, 4 * (size_t)n);
+            gr->stat = galloc<float>(c, gr->mem, 3 * (size_t)n);
+            gr->X = galloc<float>(c, gr->mem, (size_t)kF * n);
+            HIPCHK(hipMemcpyAsync(gr->ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+            if (!idx.empty())
+                HIPCHK(hipMemcpyAsync(gr->idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(gr->invdeg, invdeg.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(gr->ebar, ebar.data(), ebar.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(gr->stat, stat.data(), stat.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemsetAsync(gr->X, 0, (size_t)kF * n * sizeof(float), c->stream));
+            sync(c);
+        } catch (...) {
+            release(c, gr->mem);
+            delete gr;
+            throw;
+        }
+        *out = gr;
+        return MM_OK;
+    });
+}
+
+int mm_graph_destroy(mm_graph *gr) {
+    if (!gr) return MM_EINVAL;
+    mm_ctx *c = gr->c;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c, gr->mem);
+    delete gr;
+    return MM_OK;
+}
+
+int mm_graph_size(const mm_graph *gr, long *n_nodes, long *n_edges) {
+    if (!gr) return MM_EINVAL;
+    if (n_nodes) *n_nodes = gr->n;
+    if (n_edges) *n_edges = gr->nnz;
+    return MM_OK;
+}
+
+int mm_gnn_features(mm_graph *gr, const double *m, const double h_prev[3], const double h_next[3], float *X) {
+    if (!gr) return MM_EINVAL;
+    mm_ctx *c = gr->c;
+    return guarded(c, [&] {
+        require_single(c);
+        if (!m || !h_prev || !h_next) throw ApiError{MM_EINVAL, "m and both fields are required"};
+        load_m(c, m);
+        double hp[3], hn[3];
+        reduce_field(c->inst[0], h_prev, hp);
+        reduce_field(c->inst[0], h_next, hn);
+        eval_all(c, c->opts, std::vector<double>(hn, hn + 3));
+        features_from_state(c, gr, hp, hn);
+        if (X) copy_f32_out(c, X, gr->X, (size_t)kF * gr->n);
+        sync(c);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *dm, double *s) {
+    return gguard(g, [&] {
+        check_pair(g, gr);
+        if (!m) throw ApiError{MM_EINVAL, "m is required"};
+        const int n = gr->n;
+        ensure_ws(g, n);
+        const float *Xd = gr->X;
+        if (X) {
+            copy_f32_in(g->stream, g->X, X, (size_t)kF * n);
+            Xd = g->X;
+        }
+        copy_d_in(g->stream, g->m, m, 3 * (size_t)n);
+        forward(g, gr, Xd, g->m, g->dm, g->s);
+        if (dm) copy_d_out(g->stream, dm, g->dm, 3 * (size_t)n);
+        if (s) copy_d_out(g->stream, s, g->s, n);
+        gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, const double *dm_target,
+                     const double *s_target, double inv_dm2, double w_s, double *loss, double *grad) {
+    return gguard(g, [&] {
+        check_pair(g, gr);
+        if (!m || !dm_target || !s_target) throw ApiError{MM_EINVAL, "m and both targets are required"};
+        if (!(inv_dm2 >= 0) || !(w_s >= 0)) throw ApiError{MM_EINVAL, "loss weights must be >= 0"};
+        const int n = gr->n;
+        ensure_ws(g, n);
+        hipStream_t st = g->stream;
+        const float *Xd = gr->X;
+        if (X) {
+            copy_f32_in(st, g->X, X, (size_t)kF * n);
+            Xd = g->X;
+        }
+        copy_d_in(st, g->m, m, 3 * (size_t)n);
+        copy_d_in(st, g->dmt, dm_target, 3 * (size_t)n);
+        copy_d_in(st, g->st, s_target, n);
+        forward(g, gr, Xd, g->m, nullptr, nullptr);
+        gnn_loss_heads(n, g->zm, g->zs, g->m, g->dmt, g->st, gr->c->L, 1.0 / gr->sumL, inv_dm2, w_s, g->d_zm,
+                       g->d_zs, g->lpart, g->loss, st);
+        backward(g, gr, Xd);
+        double lv = 0.0;
+        HIPCHK(hipMemcpyAsync(&lv, g->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (grad) {
+            std::vector<float> h(kNParams);
+            HIPCHK(hipMemcpyAsync(h.data(), g->grad, kNParams * sizeof(float), hipMemcpyDeviceToHost, st));
+            gsync(g);
+            std::vector<double> d(h.begin(), h.end());
+            if (is_device_ptr(grad)) HIPCHK(hipMemcpy(grad, d.data(), kNParams * sizeof(double), hipMemcpyHostToDevice));
+            else std::memcpy(grad, d.data(), kNParams * sizeof(double));
+        }
+        gsync(g);
+        if (loss) *loss = lv;
+        return MM_OK;
+    });
+}
+
+int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps) {
+    return gguard(g, [&] {
+        if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+            throw ApiError{MM_EINVAL, "bad Adam constants"};
+        g->t += 1;
+        const double bc1 = 1.0 - std::pow(beta1, (double)g->t), bc2 = 1.0 - std::pow(beta2, (double)g->t);
+        gnn_adam(kNParams, g->theta, g->grad, g->m1, g->m2, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                 (float)bc1, (float)bc2, g->stream);
+        gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_demag_diag(mm_ctx *c, const double *probes, int n_probe, double rtol, double *diag) {
+    return guarded(c, [&] {
+        require_single(c);
+        if (!probes || n_probe < 1 || !diag || !(rtol > 0)) throw ApiError{MM_EINVAL, "bad probe arguments"};
+        const InstInfo &I = c->inst[0];
+        const int nm = I.n_mag, np = I.n_pot;
+        std::vector<double> acc(3 * (size_t)nm, 0.0), z(3 * (size_t)nm), v(3 * (size_t)nm);
+        // keep the warm start aside; every probe solves from u = 0
+        HIPCHK(hipMemcpyAsync(c->usave, c->u, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        for (int p = 0; p < n_probe; ++p) {
+            const double *zp = probes + 3 * (size_t)nm * p;
+            copy_in(c, c->tmp3, zp, 3 * (size_t)nm);
+            HIPCHK(hipMemcpyAsync(z.data(), c->tmp3, z.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            launch_fill(np, c->b, 0.0, c->stream);
+            launch_fill(np, c->u, 0.0, c->stream);
+            StateV sv[3];
+            sv[0].x = c->tmp3;
+            if (c->B.nrows > 0) launch_bmul(c->B, c->Mb.map, nullptr, sv, nullptr, c->b, false, c->stream);
+            c->act()[0] = 1;
+            upload_ctl(c);
+            poisson(c, rtol, c->opts.poisson_maxit, false, {0});
+            launch_btmul(c->Bt, c->Mm.map, c->u, c->pq, false, c->stream);
+            HIPCHK(hipMemcpyAsync(v.data(), c->pq, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+            for (size_t e = 0; e < acc.size(); ++e) acc[e] += z[e] * v[e];
+        }
+        launch_fill(np, c->b, 0.0, c->stream);
+        HIPCHK(hipMemcpyAsync(c->u, c->usave, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        sync(c);
+        for (double &a : acc) a /= n_probe;
+        if (is_device_ptr(diag)) HIPCHK(hipMemcpy(diag, acc.data(), acc.size() * sizeof(double), hipMemcpyHostToDevice));
+        else std::memcpy(diag, acc.data(), acc.size() * sizeof(double));
+        return MM_OK;
+    });
+}
+
+}  // extern "C"

@@ -178,4 +178,35 @@ void launch_pcg_iter64(const PcgLaunch &a, int parity, hipStream_t s);
 void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s);
 void launch_add_correction(const PcgLaunch &a, hipStream_t s);
 
+// --- learned component (gnn.hip); widths fixed: 32 features, 64 channels ---
+void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float *W, int ldw, bool transW,
+            const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, hipStream_t s);
+int gnn_tn_blocks(int M);
+void gnn_mm_tn(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
+               bool accumulate, hipStream_t s);
+void gnn_tn32(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
+              hipStream_t s);
+void gnn_agg(int n, const int *ptr, const int *idx, const float *invdeg, const float *H, int ldh, float *out, int ldo,
+             hipStream_t s);
+void gnn_agg_t_add(int n, const int *ptr, const int *idx, const float *invdeg, const float *G, int ldg, float *out,
+                   int ldo, hipStream_t s);
+void gnn_edge_add(int n, const float *ebar, const float *We2, float *q, int ldq, hipStream_t s);
+void gnn_silu_bwd(int64_t len, const float *x, const float *pre, float *y, hipStream_t s);
+void gnn_add64(int n, const float *in, int ldi, float *out, int ldo, hipStream_t s);
+void gnn_copy64(int n, const float *in, int ldi, float *out, int ldo, hipStream_t s);
+void gnn_heads(int n, const float *h, const float *Wm, const float *bm, const float *Ws, const float *bs,
+               const double *m, float *zm, float *zs, double *dm, double *sv, hipStream_t s);
+int gnn_loss_blocks(int n);
+void gnn_loss_heads(int n, const float *zm, const float *zs, const double *m, const double *dm_t, const double *s_t,
+                    const double *L, double inv_sumL, double inv_dm2, double w_s, float *d_zm, float *d_zs,
+                    double *part, double *loss_out, hipStream_t s);
+void gnn_heads_dh(int n, const float *d_zm, const float *d_zs, const float *Wm, const float *Ws, float *dh,
+                  hipStream_t s);
+void gnn_adam(int np, float *th, const float *g, float *m1, float *m2, float lr, float b1, float b2, float eps,
+              float bc1, float bc2, hipStream_t s);
+void gnn_features(int n, const double *m, const double *G, const double *g, const double *Cm, const double *L,
+                  const float *stat, const double hn[3], const double hp[3], float *X, hipStream_t s);
+void gnn_f64_to_f32(int64_t n, const double *a, float *b, hipStream_t s);
+void gnn_f32_to_f64(int64_t n, const float *a, double *b, hipStream_t s);
+
 }  // namespace mmncg

@@ -30,151 +30,11 @@
 
 #include "mmncg.h"
 #include "internal.h"
+#include "context.h"
 
 using namespace mmncg;
 
-namespace {
-
-constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
-constexpr int kPcgChunk = 16;  // CG iterations per captured graph (even: the double buffers return to parity 0)
-
-struct HipError {
-    hipError_t e;
-    const char *what;
-};
-#define HIPCHK(x)                                     \
-    do {                                              \
-        hipError_t _e = (x);                          \
-        if (_e != hipSuccess) throw HipError{_e, #x}; \
-    } while (0)
-
-struct ApiError {
-    int code;
-    std::string msg;
-};
-
-// magnet-row partial slots (each M.nblk doubles)
-enum MagSlot {
-    MS_EVAL = 0,                   // kEvalParts
-    MS_PREC = MS_EVAL + kEvalParts,  // 7
-    MS_DOTS = MS_PREC + 7,         // kDirParts
-    MS_DOUT = MS_DOTS + kDirParts,  // 2
-    MS_MISC = MS_DOUT + 2,         // 5
-    MS_TOTAL = MS_MISC + 5
-};
-
-// per-instance metadata kept on the host
-struct InstInfo {
-    long n_nodes = 0, n_tets = 0;
-    int n_mag = 0, n_pot = 0, n_brow = 0;
-    int mag_off = 0, pot_off = 0, brow_off = 0;  // first global (padded) row
-    long user_off = 0;                           // first magnet node in caller arrays
-    long nnz_C = 0, nnz_K = 0, nnz_B = 0;
-    double Ms_ref = 0;
-    std::vector<int> node_of_mag;
-};
-
-// device tables of one RowMap
-struct DevMap {
-    RowMap map;
-};
-
-// scalars of one evaluation point
-struct Sc {
-    double E = 0, Eloc = 0, Ez = 0, Ed = 0, tmax = 0, ginf = 0, minf = 0, dF = 0, dphi = 0, dxinf = 0;
-};
-
-// running counters of an instance (monotone; per-field stats are differences)
-struct Cnt {
-    long evals = 0, mi = 0, li = 0;
-    double t_mag = 0, t_lin = 0;
-};
-
-}  // namespace
-
-struct mm_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    mm_alloc_fn ualloc = nullptr;
-    mm_free_fn ufree = nullptr;
-    void *user = nullptr;
-    std::string err;
-    std::vector<std::pair<void *, size_t>> allocs;
-    size_t dev_bytes = 0;
-
-    // single-instance mesh (host copy until materials arrive)
-    std::vector<double> xyz;
-    std::vector<int> tets, region;
-    bool have_mesh = false, have_mat = false;
-
-    int ninst = 0;
-    std::vector<InstInfo> inst;
-    long tot_mag = 0;   // sum of n_mag (caller layout)
-    int rows_m = 0, rows_p = 0, rows_b = 0;  // padded global row counts
-
-    Sell C, S, K, B, Bt;
-    DevMap Mm, Mp, Mb;  // magnet rows, potential rows, divergence rows
-    // block shape of the scalar-potential kernels: waves per block (launch
-    // wide) and SELL slices per wave of each instance
-    int pnw = kPoissonWaves;
-    std::vector<int> pspw, poff, pn;
-    bool tuned = false;
-    double *L = nullptr, *invDex = nullptr, *invDK = nullptr;
-    float *invDK32 = nullptr;
-
-    StateV st[3];  // current state, trial T, trial C
-    double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
-           *dscale = nullptr, *tmp3 = nullptr;
-    double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
-    double *cg64[7] = {};  // CG vectors: r[2], w[2], s[2], p
-    float *cg32[7] = {};
-    float *x32 = nullptr;
-    PcgState *pst = nullptr;    // device, ninst
-    PcgState *hpst = nullptr;   // pinned host mirror
-    double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
-    double *ppart = nullptr;    // potential-row partials, kPcgSlots slots
-    hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-
-    // control block: ints {act, role, first, from, pact, plive} (host-written)
-    // then {info, pflags x4} (device-written); doubles {alpha, h3 x3, pin x4}
-    int *dci = nullptr, *hci = nullptr;
-    double *dcd = nullptr, *hcd = nullptr;
-    // finalize outputs: eval (kEvalParts), dir (2), misc (5) per instance
-    double *dsc = nullptr, *hsc = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-
-    mm_opts opts;
-    std::vector<long> last_pcg;
-    std::vector<double> pcg_bytes64, pcg_bytes32;
-    std::vector<Cnt> cnt;
-    // kernel timing (mm_profile)
-    bool prof_on = false;
-    std::vector<hipEvent_t> prof_ev;
-    size_t prof_used = 0;
-    double prof_seconds = 0, prof_units = 0, prof_bytes = 0;
-
-    // control block accessors
-    int *act() const { return hci; }
-    int *role() const { return hci + ninst; }
-    int *first() const { return hci + 2 * ninst; }
-    int *from() const { return hci + 3 * ninst; }
-    int *pact() const { return hci + 4 * ninst; }
-    int *plive() const { return hci + 5 * ninst; }
-    int *info() const { return hci + 6 * ninst; }
-    int *pflags() const { return hci + 7 * ninst; }
-    double *alpha() const { return hcd; }
-    double *h3() const { return hcd + ninst; }
-    double *pin() const { return hcd + 4 * ninst; }
-    template <class T>
-    T *dev(T *hostp, T *hbase, T *dbase) const {
-        return dbase + (hostp - hbase);
-    }
-    int *d_(int *hp) const { return dci + (hp - hci); }
-    double *d_(double *hp) const { return dcd + (hp - hcd); }
-};
-
-namespace {
+namespace mmncg {
 
 // ---------------------------------------------------------------------------
 // plumbing
@@ -207,10 +67,6 @@ void dfree(mm_ctx *c, void *p) {
             else (void)hipFree(p);
             return;
         }
-}
-template <class T>
-T *dalloc_n(mm_ctx *c, size_t n) {
-    return (T *)dalloc(c, n * sizeof(T));
 }
 
 void free_host_ctl(mm_ctx *c) {
@@ -1152,7 +1008,7 @@ int trace_level() {
     return lvl;
 }
 
-enum Step { S_IDLE = 0, S_EVAL0, S_TRIAL_T, S_TRIAL_C, S_HALVE, S_NEED_DIR, S_FIELD_DONE };
+enum Step { S_IDLE = 0, S_EVAL0, S_LEARN_T, S_TRIAL_T, S_TRIAL_C, S_HALVE, S_NEED_DIR, S_FIELD_DONE };
 
 struct Run {
     int step = S_IDLE;
@@ -1175,6 +1031,7 @@ struct Run {
     double t0 = 0;
     int status = MM_OK;
     bool prec_ran = false;
+    bool scaled = false;     // the learned Jacobi factors apply to this field
 };
 
 struct CurveOut {
@@ -1182,12 +1039,21 @@ struct CurveOut {
     double *E_tot = nullptr;    // [ninst][nfield]
     mm_stats *st = nullptr;     // [ninst][nfield]
     double *m_hist = nullptr;   // single instance: [nfield][n_mag][3]
+    int *accepted = nullptr;    // single instance, learned start: [nfield] 1 when taken
+};
+
+// learned warm start / scaling (single instance): bits of `mode`
+struct Learned {
+    mm_gnn *net = nullptr;
+    mm_graph *graph = nullptr;
+    int mode = 0;
 };
 
 class Driver {
 public:
-    Driver(mm_ctx *c, const mm_opts &o, const std::vector<double> &hred, long nfield, const CurveOut &out)
-        : c_(c), o_(o), h_(hred), nf_(nfield), out_(out), r_(c->ninst) {}
+    Driver(mm_ctx *c, const mm_opts &o, const std::vector<double> &hred, long nfield, const CurveOut &out,
+           Learned ln = Learned())
+        : c_(c), o_(o), h_(hred), nf_(nfield), out_(out), r_(c->ninst), ln_(ln) {}
 
     int run() {
         const int n = c_->ninst;
@@ -1202,6 +1068,7 @@ public:
                 double al = 0.0;
                 switch (R.step) {
                     case S_EVAL0: a = 1; break;
+                    case S_LEARN_T: a = 1; rl = 1; al = 1.0; break;
                     case S_TRIAL_T: a = 1; rl = 1; al = R.at; break;
                     case S_HALVE: a = 1; rl = 1; al = R.a; break;
                     case S_TRIAL_C: a = 1; rl = 2; al = R.ac; break;
@@ -1247,7 +1114,8 @@ public:
             if (any_from) launch_copy_state(c_->Mm.map, c_->d_(c_->from()), c_->st, c_->gprev, s);
             if (any_prec) {
                 HIPCHK(hipEventRecord(c_->ev[2], s));
-                precondition(c_, o_.jmax, nullptr, o_.precision == MM_FP32_BULK);
+                const bool scaled = (ln_.mode & 2) && r_[0].scaled;
+                precondition(c_, o_.jmax, scaled ? c_->dscale : nullptr, o_.precision == MM_FP32_BULK);
                 HIPCHK(hipEventRecord(c_->ev[3], s));
             }
             if (!dir.empty()) {
@@ -1285,6 +1153,7 @@ private:
     long nf_;
     CurveOut out_;
     std::vector<Run> r_;
+    Learned ln_;
     int worst_ = MM_OK;
 
     void start_field(int i, long k) {
@@ -1303,6 +1172,8 @@ private:
         R.c0 = c_->cnt[i];
         R.t0 = now_s();
         R.status = MM_NOT_CONVERGED;
+        R.scaled = false;
+        if (out_.accepted) out_.accepted[(size_t)i * nf_ + k] = 0;
     }
 
     void finish(int i, int status) {
@@ -1322,7 +1193,28 @@ private:
         switch (R.step) {
             case S_EVAL0:
                 R.cur = v;
-                if (o_.stop_mode == MM_STOP_TORQUE && v.tmax < o_.tol_torque) finish(i, MM_OK);
+                if (o_.stop_mode == MM_STOP_TORQUE && v.tmax < o_.tol_torque) {
+                    finish(i, MM_OK);
+                } else if (ln_.mode && R.field > 0) {
+                    // proposal of the network for this field step: start
+                    // N(m + dm) and Jacobi factors s
+                    const double *hp = &h_[(size_t)3 * (i * nf_ + R.field - 1)];
+                    gnn_propose(c_, ln_.net, ln_.graph, hp, R.h);
+                    R.scaled = (ln_.mode & 2) != 0;
+                    if (ln_.mode & 1) R.step = S_LEARN_T;
+                    else need_dir(i, 1, false);
+                } else {
+                    need_dir(i, 1, false);
+                }
+                break;
+            case S_LEARN_T:
+                // energy-raise fallback: keep m_k unless the proposal is lower
+                if (v.E < R.cur.E) {
+                    c_->from()[i] = 1;
+                    R.cur = v;
+                    if (out_.accepted) out_.accepted[(size_t)i * nf_ + R.field] = 1;
+                }
+                if (o_.stop_mode == MM_STOP_TORQUE && R.cur.tmax < o_.tol_torque) finish(i, MM_OK);
                 else need_dir(i, 1, false);
                 break;
             case S_TRIAL_T: after_T(i, v); break;
@@ -1511,30 +1403,6 @@ mm_opts resolve_opts(const mm_opts *o) {
     return op;
 }
 
-template <class F>
-int guarded(mm_ctx *c, F &&f) {
-    if (!c) return MM_EINVAL;
-    try {
-        HIPCHK(hipSetDevice(c->device));
-        int rc = f();
-        if (rc >= 0) c->err.clear();
-        return rc;
-    } catch (const ApiError &e) {
-        c->err = e.msg;
-        return e.code;
-    } catch (const HipError &e) {
-        c->err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
-        (void)hipGetLastError();
-        return MM_EDEVICE;
-    } catch (const std::bad_alloc &) {
-        c->err = "host allocation failed";
-        return MM_ENOMEM;
-    } catch (const std::exception &e) {
-        c->err = e.what();
-        return MM_EDEVICE;
-    }
-}
-
 void require_ready(mm_ctx *c) {
     if (!c->have_mat || c->ninst < 1) throw ApiError{MM_ESTATE, "mesh and material must be set first"};
 }
@@ -1577,7 +1445,7 @@ Assembly assemble_checked(const double *xyz, long n_nodes, const int *tets, long
     return as;
 }
 
-}  // namespace
+}  // namespace mmncg
 
 // ===========================================================================
 // C ABI
@@ -1937,6 +1805,35 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
         out.E_tot = E_tot;
         out.st = st;
         Driver drv(c, op, h, n, out);
+        int rc = drv.run();
+        store_m(c, m_inout);
+        sync(c);
+        return rc;
+    });
+}
+
+int mm_demag_curve_learned(mm_ctx *c, mm_gnn *net, mm_graph *graph, int mode, double *m_inout,
+                           const double *h_list, long n, const mm_opts *o, double *m_avg, double *E_tot,
+                           mm_stats *st, int *accepted) {
+    return guarded(c, [&] {
+        require_single(c);
+        if (!m_inout || !h_list || n < 0) throw ApiError{MM_EINVAL, "bad curve arguments"};
+        if (mode < 0 || mode > 3) throw ApiError{MM_EINVAL, "unknown learned mode"};
+        if (mode && (!net || !graph)) throw ApiError{MM_EINVAL, "network and graph are required"};
+        mm_opts op = resolve_opts(o);
+        load_m(c, m_inout);
+        std::vector<double> h(3 * (size_t)n);
+        for (long k = 0; k < n; ++k) reduce_field(c->inst[0], h_list + 3 * k, &h[3 * k]);
+        CurveOut out;
+        out.m_avg = m_avg;
+        out.E_tot = E_tot;
+        out.st = st;
+        out.accepted = accepted;
+        Learned ln;
+        ln.net = net;
+        ln.graph = graph;
+        ln.mode = mode;
+        Driver drv(c, op, h, n, out, ln);
         int rc = drv.run();
         store_m(c, m_inout);
         sync(c);
