@@ -354,6 +354,10 @@ int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, c
 /* One Adam step (bias-corrected) with the last gradient. */
 int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps);
 
+/* Exchange diagonal D (n_mag): the Jacobi preconditioner of Alg. 1 inside
+   mm_precondition (before any dscale). */
+int mm_jacobi_diag(mm_ctx *c, double *D);
+
 /* Hutchinson estimate of the diagonal of the magnetostatic Hessian block
    B^T K^-1 B of instance 0: mean over the n_probe probe vectors z (n_probe x
    n_mag x 3, host or device) of z * (B^T K^-1 B z), each potential solved to

@@ -122,6 +122,7 @@ def load_library(path=LIB_PATH):
     L.mm_gnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp]
     L.mm_gnn_adam.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double]
     L.mm_demag_diag.argtypes = [_vp, _vp, C.c_int, C.c_double, _vp]
+    L.mm_jacobi_diag.argtypes = [_vp, _vp]
     L.mm_demag_curve_learned.argtypes = [_vp, _vp, _vp, C.c_int, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp,
                                          C.POINTER(Stats), _ip]
     L.mm_batch_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats)]
@@ -463,6 +464,11 @@ class Context:
         P = int(np.asarray(probes.shape)[0]) if hasattr(probes, "shape") else len(probes)
         out = np.zeros((self.n_mag, 3))
         self._check(self._L.mm_demag_diag(self.h, pp, P, float(rtol), C.c_void_p(out.ctypes.data)))
+        return out
+
+    def jacobi_diag(self):
+        out = np.zeros(self.n_mag)
+        self._check(self._L.mm_jacobi_diag(self.h, C.c_void_p(out.ctypes.data)))
         return out
 
     def curve_learned(self, net, graph, mode, m, fields_T, opts=None, **kw):

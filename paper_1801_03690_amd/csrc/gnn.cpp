@@ -539,6 +539,21 @@ int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps) {
     });
 }
 
+int mm_jacobi_diag(mm_ctx *c, double *D) {
+    return guarded(c, [&] {
+        require_single(c);
+        if (!D) throw ApiError{MM_EINVAL, "null output"};
+        const int nm = c->inst[0].n_mag;
+        std::vector<double> iD(nm);
+        HIPCHK(hipMemcpyAsync(iD.data(), c->invDex, nm * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        for (double &v : iD) v = 1.0 / v;
+        if (is_device_ptr(D)) HIPCHK(hipMemcpy(D, iD.data(), nm * sizeof(double), hipMemcpyHostToDevice));
+        else std::memcpy(D, iD.data(), nm * sizeof(double));
+        return MM_OK;
+    });
+}
+
 int mm_demag_diag(mm_ctx *c, const double *probes, int n_probe, double rtol, double *diag) {
     return guarded(c, [&] {
         require_single(c);

@@ -1,0 +1,250 @@
+"""Training and evaluation of the learned warm start / preconditioner scaling.
+
+Orchestration only: every step runs in the library through its C ABI (plain
+demagnetization curves that produce the training trajectories, node features,
+the Hutchinson probe of the magnetostatic diagonal, the network's forward and
+backward kernels and Adam). Device arrays are torch tensors (memory only).
+
+Training data: for each seeded film, the plain method's minimizers m_k along
+its field sweep; one sample per step k -> k+1 with
+  X     = features(m_k, h_k -> h_{k+1}),
+  dm*   = P_{m_k}(m_{k+1} - m_k),
+  s*_a  = 1 + t_a / D_a, t_a the mean of the magnetostatic Hessian diagonal
+          (Hutchinson, Rademacher probes) over the two directions normal to
+          m_k, D_a the exchange diagonal (the preconditioner's Jacobi).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import inputs
+
+
+class Film:
+    """One film: its context, graph, trajectory and training samples (device)."""
+
+    def __init__(self, work, jmax=4, n_probe=32, probe_seed=0, keep=True):
+        import torch
+        self.work = work
+        self.ctx = B.Context(0).upload(work.mesh)
+        self.graph = B.Graph(self.ctx)
+        self.n = self.ctx.n_mag
+        self.jmax = jmax
+        t0 = time.perf_counter()
+        r = self.ctx.curve(work.m0, work.fields, jmax=jmax, keep_hist=True)
+        self.t_curve = time.perf_counter() - t0
+        self.plain = r
+        hist = r["hist"]
+        z = inputs.rademacher(n_probe, self.n, seed=probe_seed)
+        self.diag3 = self.ctx.demag_diag(z, rtol=1e-8)
+        D = self.ctx.jacobi_diag()
+        F = work.fields
+        self.samples = []
+        for k in range(len(F) - 1):
+            mk = hist[k]
+            X = self.graph.features(mk, F[k], F[k + 1])
+            d = hist[k + 1] - mk
+            dmt = d - (d * mk).sum(axis=1, keepdims=True) * mk
+            t = 0.5 * (self.diag3.sum(axis=1) - (mk * mk * self.diag3).sum(axis=1))
+            st = 1.0 + t / D
+            dev = "cuda"
+            self.samples.append(tuple(torch.tensor(a, device=dev) for a in
+                                      (X, mk, dmt, st)))
+        self.ctx.reset_warm_start()
+
+    def close(self):
+        self.graph.close()
+        self.ctx.close()
+
+
+class Normalizer:
+    """Per-column mean and spread of the features and the RMS of dm* over
+    the training samples. Training sees standardized inputs and targets;
+    fold() turns trained parameters into ones for raw features and dm."""
+
+    def __init__(self, films):
+        import torch
+        s1 = torch.zeros(32, dtype=torch.float64, device="cuda")
+        s2 = torch.zeros_like(s1)
+        cnt = 0
+        d2, dn = 0.0, 0
+        for f in films:
+            for X, m, dmt, st in f.samples:
+                Xd = X.double()
+                s1 += Xd.sum(dim=0)
+                s2 += (Xd * Xd).sum(dim=0)
+                cnt += X.shape[0]
+                d2 += float((dmt * dmt).sum())
+                dn += dmt.shape[0]
+        mu = (s1 / cnt).cpu().numpy()
+        var = (s2 / cnt).cpu().numpy() - mu * mu
+        sd = np.sqrt(np.maximum(var, 0.0))
+        self.mu = np.where(sd > 1e-12, mu, 0.0)
+        self.sd = np.where(sd > 1e-12, sd, 1.0)
+        self.dm_rms = float(np.sqrt(d2 / max(dn, 1)))
+
+    def apply(self, films):
+        """Standardize the samples of `films` in place; per-sample weights
+        make the warm-start loss relative to the size of each step."""
+        import torch
+        mu = torch.tensor(self.mu, dtype=torch.float32, device="cuda")
+        sd = torch.tensor(self.sd, dtype=torch.float32, device="cuda")
+        for f in films:
+            out = []
+            for X, m, dmt, st in f.samples:
+                Xn = ((X - mu) / sd).contiguous()
+                dn = (dmt / self.dm_rms).contiguous()
+                w = 1.0 / (float((dn * dn).sum(dim=1).mean()) + 1e-4)
+                out.append((Xn, m, dn, st, w))
+            f.samples = out
+
+    def fold(self, theta):
+        """Parameters for raw features and unscaled dm."""
+        th = np.array(theta, dtype=np.float64)
+        W = th[0:32 * 64].reshape(32, 64)
+        b = th[32 * 64:32 * 64 + 64]
+        b_new = b - (self.mu / self.sd) @ W
+        W_new = W / self.sd[:, None]
+        th[0:32 * 64] = W_new.ravel()
+        th[32 * 64:32 * 64 + 64] = b_new
+        n = th.size
+        # heads at the end: Wm (64x3), bm (3), Ws (64x1), bs (1)
+        o_wm = n - (64 * 3 + 3 + 64 + 1)
+        th[o_wm:o_wm + 64 * 3 + 3] *= self.dm_rms
+        return th
+
+
+def train(films, net, epochs=10, lr=1e-3, w_s=1.0, seed=0, log=None, val=None):
+    """Adam over every sample of every film (standardized by Normalizer.apply),
+    shuffled each epoch (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = [(i, k) for i, f in enumerate(films) for k in range(len(f.samples))]
+    hist = []
+    for ep in range(epochs):
+        rng.shuffle(order)
+        tot = 0.0
+        t0 = time.perf_counter()
+        for i, k in order:
+            f = films[i]
+            X, m, dmt, st, w = f.samples[k]
+            loss, _ = net.loss_grad(f.graph, X, m, dmt, st, inv_dm2=w, w_s=w_s, want_grad=False)
+            net.adam(lr)
+            tot += loss
+        rec = dict(epoch=ep, train_loss=tot / len(order), seconds=time.perf_counter() - t0)
+        if val is not None:
+            rec["val_dm_loss"] = evaluate(val, net, w_s=0.0)
+            rec["val_s_loss"] = evaluate(val, net, w_s=1.0, dm=False)
+        hist.append(rec)
+        if log:
+            log(rec)
+    return hist
+
+
+def evaluate(films, net, w_s=1.0, dm=True):
+    """Mean loss over the samples (the warm-start part relative to each
+    step's size; dm=False keeps only the scaling part)."""
+    tot, cnt = 0.0, 0
+    for f in films:
+        for X, m, dmt, st, w in f.samples:
+            loss, _ = net.loss_grad(f.graph, X, m, dmt, st, inv_dm2=(w if dm else 0.0), w_s=w_s, want_grad=False)
+            tot += loss
+            cnt += 1
+    return tot / max(cnt, 1)
+
+
+def compare(work, net, jmax=4, modes=(0, 3), ctx=None):
+    """Plain (mode 0) against learned curves on one workload, same stopping
+    rule. Returns per mode: seconds, evaluations, NCG and CG iterations,
+    accepted starts, and the largest difference of <m> from the plain curve
+    (a different basin shows as an O(1) difference)."""
+    own = ctx is None
+    if own:
+        ctx = B.Context(0).upload(work.mesh)
+    graph = B.Graph(ctx)
+    out = {}
+    ref = None
+    for mode in modes:
+        ctx.reset_warm_start()
+        t0 = time.perf_counter()
+        r = ctx.curve_learned(net, graph, mode, work.m0, work.fields, jmax=jmax)
+        dt = time.perf_counter() - t0
+        st = r["stats"]
+        rec = dict(seconds=dt, evals=int(sum(s["evals"] for s in st)), nli=int(sum(s["nli"] for s in st)),
+                   li=int(sum(s["li"] for s in st)), mi=int(sum(s["mi"] for s in st)),
+                   accepted=int(r["accepted"].sum()), rc=int(r["rc"]))
+        if ref is None:
+            ref = r
+        rec["max_dmavg_vs_plain"] = float(np.abs(r["m_avg"] - ref["m_avg"]).max())
+        rec["basin_mismatches"] = int((np.abs(r["m_avg"] - ref["m_avg"]).max(axis=1) > 1e-2).sum())
+        rec["max_rel_dE_vs_plain"] = float(np.max(np.abs(r["E"] - ref["E"]) / np.maximum(np.abs(ref["E"]), 1e-30)))
+        out[mode] = rec
+    graph.close()
+    if own:
+        ctx.close()
+    return out
+
+
+def main(argv=None):
+    """Train on seeded small films, evaluate on held-out ones, save the
+    folded parameters (npz) and a JSON report."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--films", type=int, default=32)
+    ap.add_argument("--heldout", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=15)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--probes", type=int, default=32)
+    ap.add_argument("--lo", type=float, default=120.0)
+    ap.add_argument("--hi", type=float, default=280.0)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--out", default="gnn_films.npz")
+    ap.add_argument("--report", default="gnn_films.json")
+    args = ap.parse_args(argv)
+    t0 = time.perf_counter()
+
+    def say(*a):
+        print(f"[{time.perf_counter() - t0:7.1f}s]", *a, flush=True)
+
+    films = []
+    for i in range(args.films):
+        w = inputs.small_film(100 + i, lo=args.lo, hi=args.hi)
+        films.append(Film(w, n_probe=args.probes, probe_seed=500 + i))
+        say(f"film {i} {w.name} n={films[-1].n} plain curve {films[-1].t_curve:.2f}s")
+    val = []
+    for i in range(args.heldout):
+        w = inputs.small_film(900 + i, lo=args.lo, hi=args.hi)
+        val.append(Film(w, n_probe=args.probes, probe_seed=1900 + i))
+        say(f"held-out {i} {w.name} n={val[-1].n}")
+    nz = Normalizer(films)
+    nz.apply(films)
+    nz.apply(val)
+    net = B.Gnn(films[0].ctx)
+    net.set_params(inputs.gnn_init(args.seed))
+    untrained = dict(val_dm_loss=evaluate(val, net, w_s=0.0), val_s_loss=evaluate(val, net, w_s=1.0, dm=False))
+    say("untrained", untrained)
+    hist = train(films, net, epochs=args.epochs, lr=args.lr, seed=args.seed, log=lambda r: say(r), val=val)
+    theta = nz.fold(net.get_params())
+    np.savez(args.out, theta=theta, mu=nz.mu, sd=nz.sd, dm_rms=nz.dm_rms,
+             meta=json.dumps(dict(films=args.films, epochs=args.epochs, lr=args.lr, lo=args.lo, hi=args.hi,
+                                  probes=args.probes, seed=args.seed)))
+    gains = []
+    for f in val:
+        dep = B.Gnn(f.ctx)
+        dep.set_params(theta)
+        res = compare(f.work, dep, modes=(0, 1, 2, 3), ctx=f.ctx)
+        say(f.work.name, res)
+        gains.append(dict(name=f.work.name, n=f.n, **{f"mode{k}": v for k, v in res.items()}))
+        dep.close()
+    rep = dict(untrained=untrained, history=hist, heldout=gains, seconds=time.perf_counter() - t0)
+    with open(args.report, "w") as fh:
+        json.dump(rep, fh, indent=1)
+    say("done")
+    return rep
+
+
+if __name__ == "__main__":
+    main()
