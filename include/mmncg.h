@@ -211,12 +211,14 @@ int mm_profile(mm_ctx *c, int enable, double out[4]);
    floor(log2(n_pot / 4096)) clamped to 0..7). A block of an instance covers NW
    x slices-per-wave slices (at most 256 blocks per instance).
    MM_TUNE_DEFAULT: NW = 16, one slice per wave (the state after upload).
-   MM_TUNE_MEASURE: for every NW and bucket, time 32 CG iterations (best of 3,
-   HIP events) of a synthetic solve (b = 1, u = 0) for each slices-per-wave
-   candidate, keep the fastest, then pick the NW with the least total time.
-   MM_TUNE_CACHE: as MEASURE, but first read winners for this device, bucket,
-   NW and precision (options of mm_set_opts) from the JSON file cache_path and
-   time only what is missing; the file is rewritten when something was timed.
+   MM_TUNE_MEASURE: times 32 CG iterations (best of 3, HIP events) of a
+   synthetic solve of the whole batch (b = 1, u = 0, every instance active):
+   for each NW one slices-per-wave value for all buckets, then each bucket's
+   value in turn with the others fixed; the fastest NW wins.
+   MM_TUNE_CACHE: as MEASURE, but a batch of the same composition (buckets and
+   their instance counts) on the same device and precision (options of
+   mm_set_opts) reuses the choice stored in the JSON file cache_path without
+   timing; otherwise the new choice is appended to the file.
    The chosen shape stays fixed until the next mm_tune or upload, so a run is
    deterministic; another shape may change the rounding of the potential
    solves (another grouping of the reductions), never their tolerance. The

@@ -114,8 +114,10 @@ struct mm_ctx {
     double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
            *dscale = nullptr, *tmp3 = nullptr;
     double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
-    double *cg64[7] = {};  // CG vectors: r[2], w[2], s[2], p
-    float *cg32[7] = {};
+    PcgNode<double> *q64[2] = {};  // CG node records by parity
+    PcgNode<float> *q32[2] = {};
+    double *p64 = nullptr;         // CG directions
+    float *p32 = nullptr;
     float *x32 = nullptr;
     PcgState *pst = nullptr;    // device, ninst
     PcgState *hpst = nullptr;   // pinned host mirror

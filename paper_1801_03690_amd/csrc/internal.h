@@ -151,11 +151,19 @@ void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
 
 // --- scalar-potential CG (poisson.hip) ---
-// vectors of the single-reduction CG: residual r, w = K D^-1 r and s = K p
-// double-buffered by iteration parity, direction p
+// per-node record of the single-reduction CG: residual r, w = K D^-1 r,
+// s = K p and the Jacobi factor d = D^-1, interleaved so that the neighbour
+// values one stored matrix entry needs come in one 16-byte (FP32) or 32-byte
+// (FP64) load; double-buffered by iteration parity (d is written to both
+// buffers at the start of a solve). The direction p is a plain array.
+template <class VT>
+struct alignas(4 * sizeof(VT)) PcgNode {
+    VT r, w, s, d;
+};
 template <class VT>
 struct PcgVecs {
-    VT *r[2], *w[2], *s[2], *p;
+    PcgNode<VT> *q[2];
+    VT *p;
 };
 struct PcgLaunch {
     const Sell *K;
@@ -163,6 +171,7 @@ struct PcgLaunch {
     PcgState *st;              // per instance
     double *part;              // kPcgSlots slots of M->nblk
     double *u, *b;             // FP64 solution and right-hand side
+    double *r64;               // FP64 residual of the defect-correction mode
     const double *invD;
     PcgVecs<double> v64;
     float *x32;                // FP32 correction of the defect-correction mode

@@ -14,9 +14,10 @@
 // instance in a fixed order (every block of the instance gets the same
 // scalars; no fences, no floating-point atomics), updates its own rows, and
 // forms K u_new where the neighbour values u_new = D^-1 (r - alpha (w + beta
-// s)) are computed on the fly from the previous iteration's r, w and s. Those
-// three vectors are double-buffered by iteration parity, so no block reads a
-// value another block is overwriting. Every launch of a chunk of iterations
+// s)) are computed on the fly from the previous iteration's r, w and s, kept
+// per node in one record with D^-1 (one load per stored matrix entry). The
+// records are double-buffered by iteration parity, so no block reads a value
+// another block is overwriting. Every launch of a chunk of iterations
 // has fixed arguments: the chunk is captured once into a HIP graph and
 // replayed until every instance's flag reports convergence. Once an
 // instance's flag is up, every later kernel of it returns at once, in this
@@ -56,10 +57,11 @@ __device__ __forceinline__ const double *slot(const double *part, int stride, in
 }
 
 // r = b - K u; partials (b.b, r.r)
+// (r at r[row * rs]: rs = 1 for a plain array, 4 for the r field of PcgNode<double>)
 template <class MT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_pcg_residual(SV<MT> K, RowMap M, const int *__restrict__ act,
                                                       const double *__restrict__ b, const double *__restrict__ u,
-                                                      double *__restrict__ r, double *__restrict__ part) {
+                                                      double *__restrict__ r, int rs, double *__restrict__ part) {
     Tile t = tile_of(M);
     if (t.inst < 0 || (act && !act[t.inst])) return;
     __shared__ double sh[NW * 2];
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_residual(SV<MT> K, RowMap M, co
         if (row < rend) {
             double bi = b[row];
             double ri = bi - ku;
-            r[row] = ri;
+            r[(int64_t)row * rs] = ri;
             acc[0] += bi * bi;
             acc[1] += ri * ri;
         }
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_residual(SV<MT> K, RowMap M, co
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_pcg_start32(RowMap M, const double *__restrict__ pin,
                                                      const double *__restrict__ r64, float *__restrict__ x,
-                                                     float *__restrict__ r) {
+                                                     PcgNode<float> *__restrict__ q) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !(pin[4 * t.inst + 1] > 0.0)) return;
     const double scale = pin[4 * t.inst];
@@ -92,17 +94,20 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_start32(RowMap M, const double 
         int i = s * 64 + lane_id();
         if (i < rend) {
             x[i] = 0.0f;
-            r[i] = (float)(r64[i] * scale);
+            q[i].r = (float)(r64[i] * scale);
         }
     }
 }
 
-// w = K D^-1 r for the start residual; partials (gamma, delta, r.r) into P0.
-// Active instances: act[i] when act is given, else those with an inner solve.
+// w = K D^-1 r for the start residual (r in the records of buffer 0); sets
+// w, s = 0 and d = D^-1 in buffer 0 and d in buffer 1; partials (gamma,
+// delta, r.r) into P0. Only the r fields of neighbours are read, and no r
+// field is written. Active instances: act[i] when act is given, else those
+// with an inner solve.
 template <class MT, class VT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_pcg_start_w(SV<MT> K, RowMap M, const int *__restrict__ act,
-                                                     const double *__restrict__ pin, const VT *__restrict__ r,
-                                                     const VT *__restrict__ invD, VT *__restrict__ w,
+                                                     const double *__restrict__ pin, PcgNode<VT> *__restrict__ q0,
+                                                     PcgNode<VT> *__restrict__ q1, const VT *__restrict__ invD,
                                                      double *__restrict__ part) {
     Tile t = tile_of(M);
     if (t.inst < 0) return;
@@ -117,13 +122,16 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_start_w(SV<MT> K, RowMap M, con
         for (int k = 0; k < wd; ++k) {
             int64_t e = base + 64 * k + ln;
             int c = K.col[e];
-            wv += (VT)K.val[e] * (invD[c] * r[c]);
+            wv += (VT)K.val[e] * (invD[c] * q0[c].r);
         }
         int row = s * 64 + ln;
         if (row < rend) {
-            VT ri = r[row];
-            VT ui = invD[row] * ri;
-            w[row] = wv;
+            const VT ri = q0[row].r, di = invD[row];
+            const VT ui = di * ri;
+            q0[row].w = wv;
+            q0[row].s = (VT)0;
+            q0[row].d = di;
+            q1[row].d = di;
             acc[0] += (double)ri * (double)ui;
             acc[1] += (double)wv * (double)ui;
             acc[2] += (double)ri * (double)ri;
@@ -197,12 +205,8 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
     if (threadIdx.x == 0) sdone = si->done;
     __syncthreads();
     if (sdone) return;
-    const VT *__restrict__ r0 = v.r[par];
-    const VT *__restrict__ w0 = v.w[par];
-    const VT *__restrict__ s0 = v.s[par];
-    VT *__restrict__ r1 = v.r[par ^ 1];
-    VT *__restrict__ w1 = v.w[par ^ 1];
-    VT *__restrict__ s1 = v.s[par ^ 1];
+    const PcgNode<VT> *__restrict__ q0 = v.q[par];
+    PcgNode<VT> *__restrict__ q1 = v.q[par ^ 1];
     VT *__restrict__ p = v.p;
     const int rend = M.rend[t.inst], ln = lane_id();
     // products of the wave's first slice
@@ -214,10 +218,11 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
         for (int k = 0; k < wd; ++k) {
             int64_t e = base + 64 * k + ln;
             int c = K.col[e];
-            VT kd = (VT)K.val[e] * invD[c];
-            pa += kd * r0[c];
-            pb += kd * w0[c];
-            pc += kd * s0[c];
+            const PcgNode<VT> nq = q0[c];
+            VT kd = (VT)K.val[e] * nq.d;
+            pa += kd * nq.r;
+            pb += kd * nq.w;
+            pc += kd * nq.s;
         }
     }
     block_reduce<3, NW>(g3, 0u, sh);
@@ -243,24 +248,26 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
             for (int k = 0; k < wd; ++k) {
                 int64_t e = base + 64 * k + ln;
                 int c = K.col[e];
-                VT kd = (VT)K.val[e] * invD[c];
-                pa += kd * r0[c];
-                pb += kd * w0[c];
-                pc += kd * s0[c];
+                const PcgNode<VT> nq = q0[c];
+                VT kd = (VT)K.val[e] * nq.d;
+                pa += kd * nq.r;
+                pb += kd * nq.w;
+                pc += kd * nq.s;
             }
         }
         int row = s * 64 + ln;
         if (row < rend) {
-            const VT dinv = invD[row], ri = r0[row];
-            VT sn = bt != (VT)0 ? w0[row] + bt * s0[row] : w0[row];
+            const PcgNode<VT> me = q0[row];
+            const VT dinv = me.d, ri = me.r;
+            VT sn = bt != (VT)0 ? me.w + bt * me.s : me.w;
             VT pn = bt != (VT)0 ? dinv * ri + bt * p[row] : dinv * ri;
             VT rn = ri - a * sn;
             VT wn = bt != (VT)0 ? pa - a * (pb + bt * pc) : pa - a * pb;
             x[row] += (XT)(a * pn);
             p[row] = pn;
-            s1[row] = sn;
-            r1[row] = rn;
-            w1[row] = wn;
+            // whole record in one store (partial-record stores leave every
+            // cache line partly written)
+            q1[row] = PcgNode<VT>{rn, wn, sn, dinv};
             VT un = dinv * rn;
             acc[0] += (double)rn * (double)un;
             acc[1] += (double)wn * (double)un;
@@ -306,10 +313,9 @@ __global__ __launch_bounds__(NW * 64) void k_add_correction(RowMap M, const doub
 void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, hipStream_t s) {
     const RowMap &M = *a.M;
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<double>(*a.K), M, act, a.b, a.u, a.v64.r[0], a.part);
+                                             view<double>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part);
                     hipLaunchKernelGGL((k_pcg_start_w<double, double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<double>(*a.K), M, act, a.pin, (const double *)a.v64.r[0], a.invD,
-                                       a.v64.w[0], a.part))
+                                       view<double>(*a.K), M, act, a.pin, a.v64.q[0], a.v64.q[1], a.invD, a.part))
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, rtol2, 0, act,
                        a.pin, a.st);
 }
@@ -317,7 +323,7 @@ void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, hipStre
 void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s) {
     const RowMap &M = *a.M;
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<float>(*a.K), M, act, a.b, a.u, a.v64.r[0], a.part))
+                                             view<float>(*a.K), M, act, a.b, a.u, a.r64, 1, a.part))
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, 0.0, 2, act,
                        a.pin, a.st);
 }
@@ -325,10 +331,10 @@ void launch_residual64(const PcgLaunch &a, const int *act, hipStream_t s) {
 void launch_pcg_init32(const PcgLaunch &a, hipStream_t s) {
     const RowMap &M = *a.M;
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_start32<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,
-                                             (const double *)a.v64.r[0], a.x32, a.v32.r[0]);
+                                             (const double *)a.r64, a.x32, a.v32.q[0]);
                     hipLaunchKernelGGL((k_pcg_start_w<float, float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<float>(*a.K), M, (const int *)nullptr, a.pin, (const float *)a.v32.r[0],
-                                       a.invD32, a.v32.w[0], a.part))
+                                       view<float>(*a.K), M, (const int *)nullptr, a.pin, a.v32.q[0], a.v32.q[1],
+                                       a.invD32, a.part))
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, 0.0, 1,
                        (const int *)nullptr, a.pin, a.st);
 }

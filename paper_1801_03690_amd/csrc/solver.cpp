@@ -410,8 +410,10 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     for (double **p : {&c->gprev, &c->d, &c->y, &c->pr, &c->pp, &c->pq, &c->tmp3}) *p = dalloc_n<double>(c, 3 * RM);
     c->dscale = dalloc_n<double>(c, RM);
     for (double **p : {&c->u, &c->b, &c->cr, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
-    for (double *&p : c->cg64) p = dalloc_n<double>(c, RP);
-    for (float *&p : c->cg32) p = dalloc_n<float>(c, RP);
+    for (auto &q : c->q64) q = dalloc_n<PcgNode<double>>(c, RP);
+    for (auto &q : c->q32) q = dalloc_n<PcgNode<float>>(c, RP);
+    c->p64 = dalloc_n<double>(c, RP);
+    c->p32 = dalloc_n<float>(c, RP);
     c->x32 = dalloc_n<float>(c, RP);
     c->pst = dalloc_n<PcgState>(c, ni);
     c->mpart = dalloc_n<double>(c, (size_t)MS_TOTAL * c->Mm.map.nblk);
@@ -439,8 +441,10 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     HIPCHK(hipMemsetAsync(c->dscale, 0, RM * sizeof(double), c->stream));
     for (double *p : {c->u, c->b, c->cr, c->cq, c->usave})
         HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
-    for (double *p : c->cg64) HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
-    for (float *p : c->cg32) HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(float), c->stream));
+    for (auto *q : c->q64) HIPCHK(hipMemsetAsync(q, 0, RP * sizeof(PcgNode<double>), c->stream));
+    for (auto *q : c->q32) HIPCHK(hipMemsetAsync(q, 0, RP * sizeof(PcgNode<float>), c->stream));
+    HIPCHK(hipMemsetAsync(c->p64, 0, RP * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(c->p32, 0, RP * sizeof(float), c->stream));
     HIPCHK(hipMemsetAsync(c->x32, 0, RP * sizeof(float), c->stream));
     HIPCHK(hipMemsetAsync(c->pst, 0, ni * sizeof(PcgState), c->stream));
     HIPCHK(hipMemsetAsync(c->mpart, 0, (size_t)MS_TOTAL * c->Mm.map.nblk * sizeof(double), c->stream));
@@ -475,10 +479,11 @@ PcgLaunch pcg_args(mm_ctx *c) {
     a.u = c->u;
     a.b = c->b;
     a.invD = c->invDK;
-    a.v64 = PcgVecs<double>{{c->cg64[0], c->cg64[1]}, {c->cg64[2], c->cg64[3]}, {c->cg64[4], c->cg64[5]}, c->cg64[6]};
+    a.r64 = c->cr;  // scratch: the FP64 residual of the defect correction
+    a.v64 = PcgVecs<double>{{c->q64[0], c->q64[1]}, c->p64};
     a.x32 = c->x32;
     a.invD32 = c->invDK32;
-    a.v32 = PcgVecs<float>{{c->cg32[0], c->cg32[1]}, {c->cg32[2], c->cg32[3]}, {c->cg32[4], c->cg32[5]}, c->cg32[6]};
+    a.v32 = PcgVecs<float>{{c->q32[0], c->q32[1]}, c->p32};
     a.pin = c->d_(c->pin());
     a.nw = c->pnw;
     return a;
@@ -709,8 +714,13 @@ double time_pcg(mm_ctx *c, const std::vector<int> &on, bool fp32) {
     for (int rep = 0; rep < 3; ++rep) {
         launch_fill(c->rows_p, c->b, 1.0, s);
         launch_fill(c->rows_p, c->u, 0.0, s);
-        launch_pcg_init64(a, c->d_(c->act()), 0.0, s);
-        if (fp32) launch_pcg_init32(a, s);
+        if (fp32) {
+            // the FP32 inner solve starts from the FP64 residual, as in the defect correction
+            launch_residual64(a, c->d_(c->act()), s);
+            launch_pcg_init32(a, s);
+        } else {
+            launch_pcg_init64(a, c->d_(c->act()), 0.0, s);
+        }
         for (int j = 0; j < 4; ++j) fp32 ? launch_pcg_iter32(a, j & 1, s) : launch_pcg_iter64(a, j & 1, s);
         HIPCHK(hipEventRecord(c->ev[0], s));
         for (int j = 0; j < 32; ++j) fp32 ? launch_pcg_iter32(a, j & 1, s) : launch_pcg_iter64(a, j & 1, s);
@@ -726,9 +736,13 @@ double time_pcg(mm_ctx *c, const std::vector<int> &on, bool fp32) {
     return best;
 }
 
+// One cached result: the shape chosen for a batch of this composition
+// (`batch` lists the size buckets present with their instance counts; `spw`
+// the slices per wave of those buckets in the same order) and its measured
+// time per CG iteration of the whole batch.
 struct TuneEntry {
-    std::string device;
-    int bucket, nw, spw, fp32;
+    std::string device, batch, spw;
+    int fp32, nw;
     double us;
 };
 
@@ -747,14 +761,17 @@ std::vector<TuneEntry> tune_read(const char *path) {
     if (!path) return out;
     FILE *f = std::fopen(path, "r");
     if (!f) return out;
-    char line[1024];
+    char line[2048];
     while (std::fgets(line, sizeof line, f)) {
-        char dev[512];
+        char dev[512], batch[512], spw[512];
         TuneEntry e;
-        if (std::sscanf(line, " {\"device\": \"%511[^\"]\", \"bucket\": %d, \"fp32\": %d, \"nw\": %d, \"spw\": %d, "
-                              "\"us\": %lf}",
-                        dev, &e.bucket, &e.fp32, &e.nw, &e.spw, &e.us) == 6) {
+        if (std::sscanf(line,
+                        " {\"device\": \"%511[^\"]\", \"fp32\": %d, \"batch\": \"%511[^\"]\", \"nw\": %d, "
+                        "\"spw\": \"%511[^\"]\", \"us\": %lf}",
+                        dev, &e.fp32, batch, &e.nw, spw, &e.us) == 6) {
             e.device = dev;
+            e.batch = batch;
+            e.spw = spw;
             out.push_back(e);
         }
     }
@@ -766,10 +783,12 @@ void tune_write(const char *path, const std::vector<TuneEntry> &v) {
     std::string tmp = std::string(path) + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) throw ApiError{MM_EINVAL, std::string("cannot write tuning cache ") + path};
-    std::fprintf(f, "{\"mmncg_tune\": 1, \"entries\": [\n");
+    std::fprintf(f, "{\"mmncg_tune\": 2, \"entries\": [\n");
     for (size_t k = 0; k < v.size(); ++k)
-        std::fprintf(f, "  {\"device\": \"%s\", \"bucket\": %d, \"fp32\": %d, \"nw\": %d, \"spw\": %d, \"us\": %.4f}%s\n",
-                     v[k].device.c_str(), v[k].bucket, v[k].fp32, v[k].nw, v[k].spw, v[k].us,
+        std::fprintf(f,
+                     "  {\"device\": \"%s\", \"fp32\": %d, \"batch\": \"%s\", \"nw\": %d, \"spw\": \"%s\", "
+                     "\"us\": %.4f}%s\n",
+                     v[k].device.c_str(), v[k].fp32, v[k].batch.c_str(), v[k].nw, v[k].spw.c_str(), v[k].us,
                      k + 1 < v.size() ? "," : "");
     std::fprintf(f, "]}\n");
     std::fclose(f);
@@ -779,72 +798,105 @@ void tune_write(const char *path, const std::vector<TuneEntry> &v) {
 constexpr int kTuneNw[3] = {4, 8, 16};
 constexpr int kTuneSpw[3] = {1, 2, 4};
 
-// Picks the block shape: per size bucket and waves-per-block candidate the
-// fastest slices-per-wave (timed, or taken from the cache), then the
-// waves-per-block value with the least total time over the batch.
+// Picks the block shape by timing CG iterations of the whole batch (every
+// instance active, synthetic right-hand side): for every waves-per-block
+// value, first one slices-per-wave value for all size buckets, then each
+// bucket's value in turn with the others fixed; the fastest waves-per-block
+// value wins. With a cache, a batch of the same composition on the same
+// device and precision reuses the stored choice without timing.
 void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
     const int ni = c->ninst;
     std::vector<int> bucket(ni);
     std::vector<std::vector<int>> members(8);
+    std::vector<int> all;
     for (int i = 0; i < ni; ++i) {
         bucket[i] = size_bucket(c->pn[i]);
-        if (c->pn[i] > 0) members[bucket[i]].push_back(i);
+        if (c->pn[i] > 0) {
+            members[bucket[i]].push_back(i);
+            all.push_back(i);
+        }
     }
+    std::vector<int> present;
+    std::string sig;
+    for (int b = 0; b < 8; ++b)
+        if (!members[b].empty()) {
+            present.push_back(b);
+            sig += (sig.empty() ? "" : "+") + std::string("b") + std::to_string(b) + "x" +
+                   std::to_string(members[b].size());
+        }
     const std::string dev = device_key(c);
     std::vector<TuneEntry> cache = use_cache ? tune_read(path) : std::vector<TuneEntry>();
-    auto cached = [&](int b, int nw) -> const TuneEntry * {
-        for (const TuneEntry &e : cache)
-            if (e.device == dev && e.bucket == b && e.nw == nw && e.fp32 == (fp32 ? 1 : 0)) return &e;
-        return nullptr;
+    auto apply = [&](int nw, const std::vector<int> &bspw) {
+        std::vector<int> spw(ni, 1);
+        for (size_t k = 0; k < present.size(); ++k)
+            for (int i : members[present[k]]) spw[i] = bspw[k];
+        set_poisson_shape(c, nw, spw);
     };
+    for (const TuneEntry &e : cache) {
+        if (e.device != dev || e.fp32 != (fp32 ? 1 : 0) || e.batch != sig) continue;
+        std::vector<int> bspw;
+        size_t pos = 0;
+        while (pos <= e.spw.size() && bspw.size() < present.size()) {
+            bspw.push_back(std::atoi(e.spw.c_str() + pos));
+            size_t nx = e.spw.find(',', pos);
+            if (nx == std::string::npos) break;
+            pos = nx + 1;
+        }
+        bool ok = bspw.size() == present.size() && (e.nw == 4 || e.nw == 8 || e.nw == 16);
+        for (int v : bspw) ok = ok && (v == 1 || v == 2 || v == 4);
+        if (!ok) continue;
+        apply(e.nw, bspw);
+        c->tuned = true;
+        return;
+    }
     // keep the warm start and the right-hand side aside
     const size_t RP = std::max(c->rows_p, 1);
     HIPCHK(hipMemcpyAsync(c->usave, c->u, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    double best_total = 1e300;
+    double best_t = 1e300;
     int best_nw = kPoissonWaves;
-    std::vector<int> best_spw(ni, 1);
-    bool measured = false;
+    std::vector<int> best_b(present.size(), 1);
     for (int nw : kTuneNw) {
-        std::vector<int> spw(ni, 1);
-        double total = 0.0;
-        for (int b = 0; b < 8; ++b) {
-            if (members[b].empty()) continue;
-            const TuneEntry *e = cached(b, nw);
-            int pick = 1;
-            double t_pick = 0.0;
-            if (e) {
-                pick = e->spw;
-                t_pick = e->us * 1e-6;
-            } else {
-                double tb = 1e300;
+        std::vector<int> bspw(present.size(), 1);
+        double tcur = 1e300;
+        for (int cand : kTuneSpw) {
+            std::vector<int> trial(present.size(), cand);
+            apply(nw, trial);
+            const double t = time_pcg(c, all, fp32);
+            if (t < tcur) {
+                tcur = t;
+                bspw = trial;
+            }
+        }
+        if (present.size() > 1)
+            for (size_t k = 0; k < present.size(); ++k)
                 for (int cand : kTuneSpw) {
-                    for (int i : members[b]) spw[i] = cand;
-                    set_poisson_shape(c, nw, spw);
-                    const double t = time_pcg(c, members[b], fp32);
-                    if (t < tb) {
-                        tb = t;
-                        pick = cand;
+                    if (cand == bspw[k]) continue;
+                    std::vector<int> trial = bspw;
+                    trial[k] = cand;
+                    apply(nw, trial);
+                    const double t = time_pcg(c, all, fp32);
+                    if (t < tcur) {
+                        tcur = t;
+                        bspw = trial;
                     }
                 }
-                t_pick = tb;
-                cache.push_back(TuneEntry{dev, b, nw, pick, fp32 ? 1 : 0, tb * 1e6});
-                measured = true;
-            }
-            for (int i : members[b]) spw[i] = pick;
-            total += t_pick;
-        }
-        if (total < best_total) {
-            best_total = total;
+        if (tcur < best_t) {
+            best_t = tcur;
             best_nw = nw;
-            best_spw = spw;
+            best_b = bspw;
         }
     }
-    set_poisson_shape(c, best_nw, best_spw);
+    apply(best_nw, best_b);
     launch_fill((int64_t)RP, c->b, 0.0, c->stream);
     HIPCHK(hipMemcpyAsync(c->u, c->usave, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     upload_ctl(c);
     sync(c);
-    if (use_cache && measured) tune_write(path, cache);
+    if (use_cache) {
+        std::string spw;
+        for (size_t k = 0; k < best_b.size(); ++k) spw += (k ? "," : "") + std::to_string(best_b[k]);
+        cache.push_back(TuneEntry{dev, sig, spw, fp32 ? 1 : 0, best_nw, best_t * 1e6});
+        tune_write(path, cache);
+    }
     c->tuned = true;
 }
 

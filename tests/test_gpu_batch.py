@@ -163,14 +163,14 @@ def test_batch_empty_field_list_and_device_state(B):
 
 
 def _force_shape(path, nw, spw):
-    """Rewrite a tuning cache so that every bucket prefers (nw, spw)."""
+    """Rewrite a tuning cache so that every stored batch uses (nw, spw)."""
     out = []
     for line in path.read_text().splitlines():
         if '"device"' in line:
             comma = line.rstrip().endswith(",")
             d = json.loads(line.strip().rstrip(","))
-            d["spw"] = spw
-            d["us"] = 1.0 if d["nw"] == nw else 1000.0
+            d["nw"] = nw
+            d["spw"] = ",".join([str(spw)] * (d["batch"].count("+") + 1))
             line = "  " + json.dumps(d) + ("," if comma else "")
         out.append(line)
     path.write_text("\n".join(out) + "\n")
@@ -183,7 +183,7 @@ def test_tuner_cache_and_forced_shape(B, oracle_mod, tmp_path):
     nw, spw = ctx.tune(B.MM_TUNE_CACHE, str(cache))
     assert nw in (4, 8, 16) and set(spw.tolist()) <= {1, 2, 4}
     text = cache.read_text()
-    assert '"mmncg_tune": 1' in text
+    assert '"mmncg_tune": 2' in text
     # a second call is served from the cache alone (the file is not rewritten)
     mtime = cache.stat().st_mtime_ns
     nw2, spw2 = ctx.tune(B.MM_TUNE_CACHE, str(cache))
@@ -200,7 +200,10 @@ def test_tuner_cache_and_forced_shape(B, oracle_mod, tmp_path):
     ctx.close()
     for i, mesh in enumerate(meshes):
         s = B.Context(0).upload(mesh)
-        assert s.tune(B.MM_TUNE_CACHE, str(cache))[0] == 8
+        s.tune(B.MM_TUNE_CACHE, str(cache))   # times and stores this composition
+        _force_shape(cache, 8, 2)
+        nw_s, spw_s = s.tune(B.MM_TUNE_CACHE, str(cache))
+        assert nw_s == 8 and spw_s.tolist() == [2]
         rs = s.curve(m0[i], F[i], jmax=10)
         s.close()
         np.testing.assert_array_equal(mb[i], rs["m"])
