@@ -44,6 +44,13 @@ def measured_traffic(precision):
     return float(kv["traffic_bytes_per_iteration"])
 
 
+def tune(ctx, binding, args):
+    """Block shape of the scalar-potential kernels, fixed for the run."""
+    if args.tune_cache:
+        return ctx.tune(binding.MM_TUNE_CACHE, args.tune_cache)
+    return ctx.tune(binding.MM_TUNE_MEASURE)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default block shape (no autotuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON cache of tuned block shapes (reused when it holds this workload)")
     ap.add_argument("--workload", choices=["hard_cube", "batch64"], default="hard_cube",
                     help="hard_cube: one 20^3 grain (default); batch64: 64 uneven grains in shared launches")
     ap.add_argument("--calibrate", action="store_true",
@@ -104,7 +113,7 @@ def main():
     # like the assembly, and fixed for the run
     shape = (16, [1])
     if not args.no_tune:
-        nw, spw = ctx.tune(binding.MM_TUNE_MEASURE)
+        nw, spw = tune(ctx, binding, args)
         shape = (nw, spw.tolist())
         print(f"# tuned shape: {nw} waves per block, slices per wave {spw.tolist()}", file=sys.stderr, flush=True)
 
@@ -174,7 +183,7 @@ def main():
         o64 = binding.default_opts(jmax=w.jmax, precision=binding.MM_FP64)
         ctx.set_opts(o64)
         if not args.no_tune:
-            ctx.tune(binding.MM_TUNE_MEASURE)
+            tune(ctx, binding, args)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         rp = one_curve(o64)
@@ -238,7 +247,7 @@ def bench_batch(args):
     ctx.set_opts(opts)
     shape = (16, [1] * len(ws))
     if not args.no_tune:
-        nw, spw = ctx.tune(binding.MM_TUNE_MEASURE)
+        nw, spw = tune(ctx, binding, args)
         shape = (nw, spw.tolist())
         print(f"# tuned shape: {nw} waves per block, slices per wave {spw.tolist()}", file=sys.stderr, flush=True)
     m0 = torch.tensor(np.concatenate([w.m0 for w in ws]), dtype=torch.float64, device="cuda")

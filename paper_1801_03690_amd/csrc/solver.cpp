@@ -749,7 +749,9 @@ struct TuneEntry {
 std::string device_key(mm_ctx *c) {
     hipDeviceProp_t p;
     HIPCHK(hipGetDeviceProperties(&p, c->device));
-    std::string k = std::string(p.gcnArchName) + ":" + p.name + ":cu" + std::to_string(p.multiProcessorCount);
+    // architecture and compute units only: the marketing name is not stable
+    // (a profiler's runtime reports another one)
+    std::string k = std::string(p.gcnArchName) + ":cu" + std::to_string(p.multiProcessorCount);
     for (char &ch : k)
         if (ch == '"' || ch == '\\' || ch == '\n') ch = '_';
     return k;
