@@ -177,6 +177,43 @@ __global__ __launch_bounds__(kFinBlock) void k_pcg_init_fin(RowMap M, const doub
     }
 }
 
+// A, B, C of one row: sums over the slice's entries of K_ac D_c^-1 times r_c,
+// w_c and s_c, from the neighbour records. Entries go in groups (8 in FP32,
+// 4 in FP64) whose column/value loads and record gathers are all issued
+// before any is used, so a wave keeps several gathers in flight. Entries past
+// the slice's width stand in as the slice's first row (a row of the same
+// instance) with value 0; the width is uniform over the wave, so those lanes
+// issue no loads of matrix storage.
+template <class MT, class VT>
+__device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0, VT &pa,
+                                        VT &pb, VT &pc) {
+    constexpr int G = sizeof(VT) == 4 ? 8 : 4;
+    const int64_t base = K.sptr[s];
+    const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+    pa = pb = pc = (VT)0;
+    for (int k0 = 0; k0 < wd; k0 += G) {
+        int cc[G];
+        VT vv[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const bool in = k0 + k < wd;
+            const int64_t e = base + 64 * (k0 + k) + ln;
+            cc[k] = in ? K.col[e] : s * 64;
+            vv[k] = in ? (VT)K.val[e] : (VT)0;
+        }
+        PcgNode<VT> nq[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) nq[k] = q0[cc[k]];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const VT kd = vv[k] * nq[k].d;
+            pa += kd * nq[k].r;
+            pb += kd * nq[k].w;
+            pc += kd * nq[k].s;
+        }
+    }
+}
+
 // one CG iteration of parity `par`: reads r, w, s of buffer par and the
 // partials P[par]; writes buffer par ^ 1 and P[par ^ 1].
 // w_new = K D^-1 (r - alpha (w + beta s)) is formed as A - alpha (B + beta C)
@@ -209,30 +246,30 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
     PcgNode<VT> *__restrict__ q1 = v.q[par ^ 1];
     VT *__restrict__ p = v.p;
     const int rend = M.rend[t.inst], ln = lane_id();
-    // products of the wave's first slice
+    // everything of the wave's first slice that does not depend on this
+    // iteration's scalars is loaded before the block reduces the partials:
+    // the instance's CG scalars, the matrix products and the own-row values
+    const double tol2 = si->tol2, gprev = si->gamma[par ^ 1], aprev = si->alpha[par ^ 1];
     const int sf = t.s0 + wave_id();
+    const int rf = sf * 64 + ln;
     VT pa = 0, pb = 0, pc = 0;
-    if (sf < t.s1) {
-        int64_t base = K.sptr[sf];
-        int wd = (int)((K.sptr[sf + 1] - base) >> 6);
-        for (int k = 0; k < wd; ++k) {
-            int64_t e = base + 64 * k + ln;
-            int c = K.col[e];
-            const PcgNode<VT> nq = q0[c];
-            VT kd = (VT)K.val[e] * nq.d;
-            pa += kd * nq.r;
-            pb += kd * nq.w;
-            pc += kd * nq.s;
-        }
+    if (sf < t.s1) row_abc(K, sf, ln, q0, pa, pb, pc);
+    PcgNode<VT> me_f{0, 0, 0, 0};
+    VT p_f = 0;
+    XT x_f = 0;
+    if (sf < t.s1 && rf < rend) {
+        me_f = q0[rf];
+        p_f = p[rf];
+        x_f = x[rf];
     }
     block_reduce<3, NW>(g3, 0u, sh);
     const double gam = g3[0], del = g3[1], rr = g3[2];
-    if (rr <= si->tol2) {
+    if (rr <= tol2) {
         if (t.b == b0 && threadIdx.x == 0) si->done = 2 + par;
         return;
     }
-    const double beta = gam / si->gamma[par ^ 1];
-    const double alpha = gam / (del - beta * gam / si->alpha[par ^ 1]);
+    const double beta = gam / gprev;
+    const double alpha = gam / (del - beta * gam / aprev);
     if (t.b == b0 && threadIdx.x == 0) {
         si->gamma[par] = gam;
         si->alpha[par] = alpha;
@@ -241,29 +278,18 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
     const VT a = (VT)alpha, bt = (VT)beta;
     double acc[3] = {0, 0, 0};
     for (int s = sf; s < t.s1; s += NW) {
-        if (s != sf) {
-            int64_t base = K.sptr[s];
-            int wd = (int)((K.sptr[s + 1] - base) >> 6);
-            pa = pb = pc = 0;
-            for (int k = 0; k < wd; ++k) {
-                int64_t e = base + 64 * k + ln;
-                int c = K.col[e];
-                const PcgNode<VT> nq = q0[c];
-                VT kd = (VT)K.val[e] * nq.d;
-                pa += kd * nq.r;
-                pb += kd * nq.w;
-                pc += kd * nq.s;
-            }
-        }
+        if (s != sf) row_abc(K, s, ln, q0, pa, pb, pc);
         int row = s * 64 + ln;
         if (row < rend) {
-            const PcgNode<VT> me = q0[row];
+            const PcgNode<VT> me = (s == sf) ? me_f : q0[row];
+            const VT pold = (s == sf) ? p_f : p[row];
+            const XT xold = (s == sf) ? x_f : x[row];
             const VT dinv = me.d, ri = me.r;
             VT sn = bt != (VT)0 ? me.w + bt * me.s : me.w;
-            VT pn = bt != (VT)0 ? dinv * ri + bt * p[row] : dinv * ri;
+            VT pn = bt != (VT)0 ? dinv * ri + bt * pold : dinv * ri;
             VT rn = ri - a * sn;
             VT wn = bt != (VT)0 ? pa - a * (pb + bt * pc) : pa - a * pb;
-            x[row] += (XT)(a * pn);
+            x[row] = xold + (XT)(a * pn);
             p[row] = pn;
             // whole record in one store (partial-record stores leave every
             // cache line partly written)
