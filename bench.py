@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default block shape (no autotuning)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the plain-vs-learned comparison on a held-out film")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of tuned block shapes (reused when it holds this workload)")
     ap.add_argument("--workload", choices=["hard_cube", "batch64"], default="hard_cube",
@@ -198,6 +200,9 @@ def main():
                              "max_rel_dE_vs_fp32": dE, "max_dmavg_vs_fp32": dmav}
         print(f"# plain fp64 curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
 
+    if not args.no_learned:
+        out["learned_film"] = bench_learned(args, binding, inputs, np, torch)
+
     if not args.no_cpu:
         import oracle
         o = oracle.Oracle(w.mesh)
@@ -218,6 +223,52 @@ def main():
             "sample_seconds": round(t_sample, 3),
         }
     print(json.dumps(out), flush=True)
+
+
+def bench_learned(args, binding, inputs, np, torch):
+    """Plain FP64 method against learned start + scaling in the FP32-bulk
+    mode on a held-out soft film (seed 901 of the training family: 235 x 270
+    nm, 5 nm cells, 2 cells thick, 3x air box, field along x from +50 to -50
+    mT in 1 mT steps, jmax 4, same stopping rule), with the parameters
+    trained by `python -m paper_1801_03690_amd.learn` (data/gnn_films.npz)."""
+    path = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films.npz")
+    theta = np.load(path)["theta"]
+    w = inputs.small_film(901)
+    ctx = binding.Context(0)
+    ctx.upload(w.mesh)
+    graph = binding.Graph(ctx)
+    net = binding.Gnn(ctx)
+    net.set_params(theta)
+    res = {}
+    for name, mode, prec in (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
+                             ("learned_fp32", 3, binding.MM_FP32_BULK)):
+        o = binding.default_opts(jmax=4, precision=prec)
+        ctx.set_opts(o)
+        if not args.no_tune:
+            tune(ctx, binding, args)
+        ctx.reset_warm_start()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.curve_learned(net, graph, mode, w.m0, w.fields, opts=o)
+        dt = time.perf_counter() - t0
+        st = r["stats"]
+        res[name] = dict(seconds=round(dt, 4), evals=int(sum(x["evals"] for x in st)),
+                         nli=int(sum(x["nli"] for x in st)), cg_iterations=int(sum(x["mi"] for x in st)),
+                         starts_taken=int(r["accepted"].sum()), rc=int(r["rc"]), _r=r)
+        print(f"# film {name}: {dt:.2f}s", file=sys.stderr, flush=True)
+    ref = res["plain_fp64"]["_r"]
+    for k in res:
+        r = res[k].pop("_r")
+        d = np.abs(r["m_avg"] - ref["m_avg"]).max(axis=1)
+        res[k]["basin_changes_vs_plain"] = int((d > 1e-2).sum())
+        res[k]["max_rel_dE_vs_plain"] = float(np.max(np.abs(r["E"] - ref["E"]) / np.abs(ref["E"])))
+    res["speedup_learned_fp32_vs_plain_fp64"] = round(res["plain_fp64"]["seconds"] / res["learned_fp32"]["seconds"], 3)
+    res["workload"] = (f"held-out film {w.name}: {ctx.n_mag} magnet nodes, {len(w.fields)} fields +50..-50 mT, "
+                       f"jmax 4, tol 1e-6")
+    net.close()
+    graph.close()
+    ctx.close()
+    return res
 
 
 def bench_batch(args):
