@@ -232,13 +232,12 @@ def bench_learned(args, binding, inputs, np, torch):
     mT in 1 mT steps, jmax 4, same stopping rule), with the parameters
     trained by `python -m paper_1801_03690_amd.learn` (data/gnn_films.npz)."""
     path = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films.npz")
-    theta = np.load(path)["theta"]
+    from paper_1801_03690_amd import learn
     w = inputs.small_film(901)
     ctx = binding.Context(0)
     ctx.upload(w.mesh)
     graph = binding.Graph(ctx)
-    net = binding.Gnn(ctx)
-    net.set_params(theta)
+    net = learn.load_net(path, ctx)
     res = {}
     for name, mode, prec in (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
                              ("learned_fp32", 3, binding.MM_FP32_BULK)):

@@ -292,8 +292,8 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
    same stopping rule afterwards, and the candidate start is used only when
    its energy at h_{k+1} is lower than that of m_k (energy-raise fallback).
 
-   Network (widths fixed): inputs X (n x 32 node features, below); h0 =
-   SiLU(X W_in + b_in); three layers a = mean of h over the mesh neighbours, q
+   Network (widths fixed): inputs X (n x 32 node features, below),
+   standardized per column (mm_gnn_set_input_norm); h0 = SiLU(X W_in + b_in); three layers a = mean of h over the mesh neighbours, q
    = a We1 + ebar We2 (ebar: mean edge features (x_j - x_i)/l, |x_j - x_i|/l,
    l the mean edge length), t = SiLU([h | q] W1 + b1), h <- h + t W2 + b2;
    heads dm = P_m(h Wm + bm), s = clip(softplus(h Ws + bs) + 1/4, 1/4, 4).
@@ -330,6 +330,10 @@ const char *mm_gnn_last_error(const mm_gnn *g);
    them also resets the optimizer state. */
 int mm_gnn_set_params(mm_gnn *g, const double *theta);
 int mm_gnn_get_params(mm_gnn *g, double *theta);
+/* Input standardization applied in FP32 before the first layer: X_c <-
+   (X_c - mu_c) / sd_c for the 32 feature columns (host arrays; sd > 0).
+   Default mu = 0, sd = 1. */
+int mm_gnn_set_input_norm(mm_gnn *g, const double *mu, const double *sd);
 
 /* Graph of the magnet nodes of a single-instance context set with
    mm_mesh_upload + mm_material_set. */

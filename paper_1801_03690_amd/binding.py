@@ -114,6 +114,7 @@ def load_library(path=LIB_PATH):
     L.mm_gnn_last_error.argtypes = [_vp]
     L.mm_gnn_set_params.argtypes = [_vp, _vp]
     L.mm_gnn_get_params.argtypes = [_vp, _vp]
+    L.mm_gnn_set_input_norm.argtypes = [_vp, _dp, _dp]
     L.mm_graph_create.argtypes = [_vp, C.POINTER(_vp)]
     L.mm_graph_destroy.argtypes = [_vp]
     L.mm_graph_size.argtypes = [_vp, _lp, _lp]
@@ -560,6 +561,11 @@ class Gnn:
     def set_params(self, theta):
         tp, keep = _vec_ptr(theta)
         self._chk(self._L.mm_gnn_set_params(self.h, tp))
+
+    def set_input_norm(self, mu, sd):
+        a = _host_f64(mu, (32,))
+        b = _host_f64(sd, (32,))
+        self._chk(self._L.mm_gnn_set_input_norm(self.h, a.ctypes.data_as(_dp), b.ctypes.data_as(_dp)))
 
     def get_params(self):
         out = np.zeros(self.n_params)

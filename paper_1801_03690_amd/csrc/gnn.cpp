@@ -35,10 +35,11 @@ struct mm_gnn {
     void *user = nullptr;
     std::string err;
     float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+    float *mu = nullptr, *sd = nullptr;   // input standardization (32 each)
     long t = 0;
     int cap = 0;  // workspace rows
     std::vector<void *> ws;
-    float *X = nullptr, *y0 = nullptr, *h3 = nullptr, *zm = nullptr, *zs = nullptr, *dh = nullptr, *dt = nullptr,
+    float *X = nullptr, *Xn = nullptr, *y0 = nullptr, *h3 = nullptr, *zm = nullptr, *zs = nullptr, *dh = nullptr, *dt = nullptr,
           *dy = nullptr, *dz = nullptr, *da = nullptr, *d_zm = nullptr, *d_zs = nullptr, *part = nullptr;
     float *z[3] = {}, *a[3] = {}, *y1[3] = {}, *tt[3] = {};
     double *m = nullptr, *dmt = nullptr, *st = nullptr, *lpart = nullptr, *loss = nullptr, *dm = nullptr,
@@ -146,6 +147,7 @@ void ensure_ws(mm_gnn *g, int n) {
     nrelease(g, g->ws);
     const size_t N = (size_t)std::max(n, 1);
     g->X = nalloc<float>(g, g->ws, N * kF);
+    g->Xn = nalloc<float>(g, g->ws, N * kF);
     g->y0 = nalloc<float>(g, g->ws, N * kW);
     for (int l = 0; l < kLayers; ++l) {
         g->z[l] = nalloc<float>(g, g->ws, N * 2 * kW);
@@ -174,13 +176,16 @@ void ensure_ws(mm_gnn *g, int n) {
     g->cap = n;
 }
 
-// forward pass on X (device, n x 32) and m (device, n x 3); dm, s (device
-// doubles, may be null) receive the heads' outputs
+// forward pass on raw features X (device, n x 32) and m (device, n x 3);
+// dm, s (device doubles, may be null) receive the heads' outputs. The
+// features are standardized in FP32 first (g->Xn), before the first product
+// rounds them to BF16.
 void forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *dm, double *sv) {
     const int n = gr->n;
     hipStream_t s = g->stream;
     const float *th = g->theta;
-    gnn_mm(n, kF, kW, 1, X, kF, th + oWin, kW, false, th + oBin, g->z[0], 2 * kW, g->y0, kW, nullptr, 0, s);
+    gnn_norm_features(n, X, g->mu, g->sd, g->Xn, s);
+    gnn_mm(n, kF, kW, 1, g->Xn, kF, th + oWin, kW, false, th + oBin, g->z[0], 2 * kW, g->y0, kW, nullptr, 0, s);
     for (int l = 0; l < kLayers; ++l) {
         float *z = g->z[l];
         gnn_agg(n, gr->ptr, gr->idx, gr->invdeg, z, 2 * kW, g->a[l], kW, s);
@@ -196,7 +201,7 @@ void forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *d
 }
 
 // backward pass after forward(); d_zm, d_zs hold the loss gradient at the heads
-void backward(mm_gnn *g, mm_graph *gr, const float *X) {
+void backward(mm_gnn *g, mm_graph *gr) {
     const int n = gr->n;
     hipStream_t s = g->stream;
     const float *th = g->theta;
@@ -223,7 +228,7 @@ void backward(mm_gnn *g, mm_graph *gr, const float *X) {
         gnn_agg_t_add(n, gr->ptr, gr->idx, gr->invdeg, g->da, kW, g->dh, kW, s);
     }
     gnn_silu_bwd((int64_t)n * kW, g->dh, g->y0, g->dy, s);
-    gnn_mm_tn(n, kF, kW, X, kF, g->dy, kW, part, gr_ + oWin, false, s);
+    gnn_mm_tn(n, kF, kW, g->Xn, kF, g->dy, kW, part, gr_ + oWin, false, s);
     gnn_tn32(n, 1, kW, nullptr, 0, g->dy, kW, part, gr_ + oBin, s);
 }
 
@@ -277,8 +282,13 @@ int mm_gnn_create(mm_ctx *c, mm_gnn **out) {
             g->grad = nalloc<float>(g, g->mem, kNParams);
             g->m1 = nalloc<float>(g, g->mem, kNParams);
             g->m2 = nalloc<float>(g, g->mem, kNParams);
+            g->mu = nalloc<float>(g, g->mem, kF);
+            g->sd = nalloc<float>(g, g->mem, kF);
             for (float *p : {g->theta, g->grad, g->m1, g->m2})
                 HIPCHK(hipMemsetAsync(p, 0, kNParams * sizeof(float), g->stream));
+            std::vector<float> z(kF, 0.0f), o(kF, 1.0f);
+            HIPCHK(hipMemcpyAsync(g->mu, z.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
+            HIPCHK(hipMemcpyAsync(g->sd, o.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
             gsync(g);
         } catch (...) {
             nrelease(g, g->mem);
@@ -316,6 +326,23 @@ int mm_gnn_set_params(mm_gnn *g, const double *theta) {
         HIPCHK(hipMemcpyAsync(g->theta, h.data(), kNParams * sizeof(float), hipMemcpyHostToDevice, g->stream));
         for (float *p : {g->m1, g->m2}) HIPCHK(hipMemsetAsync(p, 0, kNParams * sizeof(float), g->stream));
         g->t = 0;
+        gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_set_input_norm(mm_gnn *g, const double *mu, const double *sd) {
+    return gguard(g, [&] {
+        if (!mu || !sd) throw ApiError{MM_EINVAL, "null mean or spread"};
+        std::vector<float> a(kF), b(kF);
+        for (int c = 0; c < kF; ++c) {
+            if (!std::isfinite(mu[c]) || !(sd[c] > 0) || !std::isfinite(sd[c]))
+                throw ApiError{MM_EINVAL, "spreads must be finite and positive"};
+            a[c] = (float)mu[c];
+            b[c] = (float)sd[c];
+        }
+        HIPCHK(hipMemcpyAsync(g->mu, a.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->sd, b.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
         gsync(g);
         return MM_OK;
     });
@@ -509,7 +536,7 @@ int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, c
         forward(g, gr, Xd, g->m, nullptr, nullptr);
         gnn_loss_heads(n, g->zm, g->zs, g->m, g->dmt, g->st, gr->c->L, 1.0 / gr->sumL, inv_dm2, w_s, g->d_zm,
                        g->d_zs, g->lpart, g->loss, st);
-        backward(g, gr, Xd);
+        backward(g, gr);
         double lv = 0.0;
         HIPCHK(hipMemcpyAsync(&lv, g->loss, sizeof(double), hipMemcpyDeviceToHost, st));
         if (grad) {

@@ -361,6 +361,17 @@ __global__ __launch_bounds__(kGB) void k_features(int n, const double *__restric
     for (int c = 21; c < 32; ++c) x[c] = 0.0f;
 }
 
+// Xn = (X - mu) / sd, column-wise over the 32 features (FP32, before any BF16 rounding)
+__global__ __launch_bounds__(kGB) void k_norm_features(int64_t n32, const float *__restrict__ X,
+                                                       const float *__restrict__ mu, const float *__restrict__ sd,
+                                                       float *__restrict__ Xn) {
+    const int64_t e = (int64_t)blockIdx.x * kGB + threadIdx.x;
+    if (e < n32) {
+        const int c = (int)(e & 31);
+        Xn[e] = (X[e] - mu[c]) / sd[c];
+    }
+}
+
 __global__ void k_f64_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
     const int64_t e = (int64_t)blockIdx.x * kGB + threadIdx.x;
     if (e < n) b[e] = (float)a[e];
@@ -479,6 +490,10 @@ void gnn_features(int n, const double *m, const double *G, const double *g, cons
     if (n > 0)
         hipLaunchKernelGGL(k_features, dim3(blocks_for(n, kGB)), dim3(kGB), 0, s, n, m, G, g, Cm, L, stat, hn[0], hn[1],
                            hn[2], hp[0], hp[1], hp[2], X);
+}
+void gnn_norm_features(int n, const float *X, const float *mu, const float *sd, float *Xn, hipStream_t s) {
+    const int64_t n32 = 32 * (int64_t)n;
+    if (n32 > 0) hipLaunchKernelGGL(k_norm_features, dim3(blocks_for(n32, kGB)), dim3(kGB), 0, s, n32, X, mu, sd, Xn);
 }
 void gnn_f64_to_f32(int64_t n, const double *a, float *b, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_f64_to_f32, dim3(blocks_for(n, kGB)), dim3(kGB), 0, s, n, a, b);

@@ -215,6 +215,7 @@ void gnn_adam(int np, float *th, const float *g, float *m1, float *m2, float lr,
               float bc1, float bc2, hipStream_t s);
 void gnn_features(int n, const double *m, const double *G, const double *g, const double *Cm, const double *L,
                   const float *stat, const double hn[3], const double hp[3], float *X, hipStream_t s);
+void gnn_norm_features(int n, const float *X, const float *mu, const float *sd, float *Xn, hipStream_t s);
 void gnn_f64_to_f32(int64_t n, const double *a, float *b, hipStream_t s);
 void gnn_f32_to_f64(int64_t n, const float *a, double *b, hipStream_t s);
 

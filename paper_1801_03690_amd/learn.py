@@ -62,8 +62,13 @@ class Film:
 
 class Normalizer:
     """Per-column mean and spread of the features and the RMS of dm* over
-    the training samples. Training sees standardized inputs and targets;
-    fold() turns trained parameters into ones for raw features and dm."""
+    the training samples. The network standardizes its raw inputs itself,
+    in FP32 before the first BF16 product (set on it by configure()): folding
+    the standardization into the first layer instead would round the raw
+    features to BF16 first, and features that vary by a few per cent around
+    a large mean (|m|-like, diagonal ratios near 1) would lose their
+    variation. Training sees targets in units of the RMS step; fold() scales
+    the trained heads back to unscaled dm."""
 
     def __init__(self, films):
         import torch
@@ -86,35 +91,44 @@ class Normalizer:
         self.sd = np.where(sd > 1e-12, sd, 1.0)
         self.dm_rms = float(np.sqrt(d2 / max(dn, 1)))
 
+    def configure(self, net):
+        net.set_input_norm(self.mu, self.sd)
+        return net
+
     def apply(self, films):
-        """Standardize the samples of `films` in place; per-sample weights
-        make the warm-start loss relative to the size of each step."""
-        import torch
-        mu = torch.tensor(self.mu, dtype=torch.float32, device="cuda")
-        sd = torch.tensor(self.sd, dtype=torch.float32, device="cuda")
+        """Scale the targets of `films` in place; per-sample weights make the
+        warm-start loss relative to the size of each step."""
         for f in films:
             out = []
             for X, m, dmt, st in f.samples:
-                Xn = ((X - mu) / sd).contiguous()
                 dn = (dmt / self.dm_rms).contiguous()
                 w = 1.0 / (float((dn * dn).sum(dim=1).mean()) + 1e-4)
-                out.append((Xn, m, dn, st, w))
+                out.append((X, m, dn, st, w))
             f.samples = out
 
     def fold(self, theta):
-        """Parameters for raw features and unscaled dm."""
+        """Parameters whose warm-start head gives unscaled dm."""
         th = np.array(theta, dtype=np.float64)
-        W = th[0:32 * 64].reshape(32, 64)
-        b = th[32 * 64:32 * 64 + 64]
-        b_new = b - (self.mu / self.sd) @ W
-        W_new = W / self.sd[:, None]
-        th[0:32 * 64] = W_new.ravel()
-        th[32 * 64:32 * 64 + 64] = b_new
         n = th.size
         # heads at the end: Wm (64x3), bm (3), Ws (64x1), bs (1)
         o_wm = n - (64 * 3 + 3 + 64 + 1)
         th[o_wm:o_wm + 64 * 3 + 3] *= self.dm_rms
         return th
+
+    def save(self, path, theta, **meta):
+        import json
+        np.savez(path, theta=self.fold(theta), mu=self.mu, sd=self.sd, dm_rms=self.dm_rms,
+                 meta=json.dumps(meta))
+
+
+def load_net(path, ctx):
+    """A network on `ctx`'s device with the parameters and input
+    standardization saved by Normalizer.save."""
+    z = np.load(path)
+    net = B.Gnn(ctx)
+    net.set_params(z["theta"])
+    net.set_input_norm(z["mu"], z["sd"])
+    return net
 
 
 def train(films, net, epochs=10, lr=1e-3, w_s=1.0, seed=0, log=None, val=None):
@@ -203,6 +217,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="gnn_films.npz")
     ap.add_argument("--report", default="gnn_films.json")
+    ap.add_argument("--modes", default="0,1,2,3", help="curve modes compared on the held-out films")
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
 
@@ -222,20 +237,17 @@ def main(argv=None):
     nz = Normalizer(films)
     nz.apply(films)
     nz.apply(val)
-    net = B.Gnn(films[0].ctx)
+    net = nz.configure(B.Gnn(films[0].ctx))
     net.set_params(inputs.gnn_init(args.seed))
     untrained = dict(val_dm_loss=evaluate(val, net, w_s=0.0), val_s_loss=evaluate(val, net, w_s=1.0, dm=False))
     say("untrained", untrained)
     hist = train(films, net, epochs=args.epochs, lr=args.lr, seed=args.seed, log=lambda r: say(r), val=val)
-    theta = nz.fold(net.get_params())
-    np.savez(args.out, theta=theta, mu=nz.mu, sd=nz.sd, dm_rms=nz.dm_rms,
-             meta=json.dumps(dict(films=args.films, epochs=args.epochs, lr=args.lr, lo=args.lo, hi=args.hi,
-                                  probes=args.probes, seed=args.seed)))
+    nz.save(args.out, net.get_params(), films=args.films, epochs=args.epochs, lr=args.lr, lo=args.lo,
+            hi=args.hi, probes=args.probes, seed=args.seed)
     gains = []
     for f in val:
-        dep = B.Gnn(f.ctx)
-        dep.set_params(theta)
-        res = compare(f.work, dep, modes=(0, 1, 2, 3), ctx=f.ctx)
+        dep = load_net(args.out, f.ctx)
+        res = compare(f.work, dep, modes=tuple(int(x) for x in args.modes.split(",")), ctx=f.ctx)
         say(f.work.name, res)
         gains.append(dict(name=f.work.name, n=f.n, **{f"mode{k}": v for k, v in res.items()}))
         dep.close()

@@ -116,6 +116,31 @@ def test_forward_matches_oracle(B):
     ctx.close()
 
 
+def test_input_standardization(B):
+    """Standardization inside the network: the forward pass on raw features
+    equals the oracle's on (X - mu) / sd (rounded like the kernel, in FP32),
+    also for features with a large mean and a small spread."""
+    ctx, gr, net, o, og = setup(B, mesh_small())
+    theta = inputs.gnn_init(14, head_scale=1.0) + 0.02 * np.random.default_rng(6).standard_normal(G.n_params())
+    net.set_params(theta)
+    th32 = net.get_params()
+    X, m, _, _ = rand_inputs(gr.n, 7)
+    mu = np.linspace(-3.0, 5.0, 32)
+    sd = np.geomspace(1e-3, 10.0, 32)
+    Xr = (mu + sd * X).astype(np.float32)
+    net.set_input_norm(mu, sd)
+    dm, s = net.forward(gr, Xr, m)
+    Xn = ((Xr - mu.astype(np.float32)) / sd.astype(np.float32)).astype(np.float64)
+    dmo, so, _ = G.forward(th32, Xn, og, m, emulate_bf16=True)
+    assert np.abs(dm - dmo).max() <= 2e-3 * np.abs(dmo).max()
+    assert np.abs(s - so).max() <= 2e-3 * np.abs(so).max()
+    with pytest.raises(B.MMError):
+        net.set_input_norm(mu, np.zeros(32))
+    net.close()
+    gr.close()
+    ctx.close()
+
+
 def test_loss_and_gradient_match_oracle(B):
     ctx, gr, net, o, og = setup(B, mesh_small())
     theta = inputs.gnn_init(12, head_scale=1.0) + 0.02 * np.random.default_rng(3).standard_normal(G.n_params())
@@ -212,13 +237,13 @@ def test_training_lowers_the_loss_and_keeps_the_minima(B):
     nz = learn.Normalizer(films)
     nz.apply(films)
     nz.apply(val)
-    net = B.Gnn(films[0].ctx)
+    net = nz.configure(B.Gnn(films[0].ctx))
     net.set_params(inputs.gnn_init(1))
     before = learn.evaluate(val, net, w_s=0.0)
     learn.train(films, net, epochs=6, lr=1e-3)
     after = learn.evaluate(val, net, w_s=0.0)
     assert after < 0.5 * before, (before, after)
-    dep = B.Gnn(val[0].ctx)
+    dep = nz.configure(B.Gnn(val[0].ctx))
     dep.set_params(nz.fold(net.get_params()))
     res = learn.compare(val[0].work, dep, modes=(0, 3), ctx=val[0].ctx)
     print("gain test:", res)
