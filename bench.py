@@ -66,8 +66,10 @@ def main():
                     help="skip the plain-vs-learned comparison on a held-out film")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of tuned block shapes (reused when it holds this workload)")
-    ap.add_argument("--workload", choices=["hard_cube", "batch64"], default="hard_cube",
-                    help="hard_cube: one 20^3 grain (default); batch64: 64 uneven grains in shared launches")
+    ap.add_argument("--workload", choices=["hard_cube", "batch64", "film", "polycrystal"], default="hard_cube",
+                    help="hard_cube: one 20^3 grain (default); batch64: 64 uneven grains in shared launches; "
+                         "film: the 1000 x 1000 x 10 nm soft film, plain FP64 against learned + FP32; "
+                         "polycrystal: the 200 nm, 96^3-cell, 27-grain magnet (use --fields to bound it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain copy kernel of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -96,7 +98,14 @@ def main():
         return
     if args.workload == "batch64":
         return bench_batch(args)
-    w = inputs.hard_cube()
+    if args.workload == "film":
+        return bench_film(args)
+    if args.workload == "polycrystal":
+        w = inputs.polycrystal()
+        args.no_learned = True
+        args.no_cpu = True
+    else:
+        w = inputs.hard_cube()
     fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
     prec = binding.MM_FP32_BULK if args.precision == "fp32" else binding.MM_FP64
 
@@ -161,8 +170,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
         "data": "synthetic (seeded Kuhn mesh, tilted +z start)",
-        "config": {"workload": f"hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {len(fields)} fields "
-                               f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6",
+        "config": {"workload": (f"hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {len(fields)} fields "
+                                f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6" if args.workload == "hard_cube" else
+                                f"polycrystal 200 nm, 96^3 cells x6 tets + 3x air box, 27 Voronoi grains with a "
+                                f"2 nm boundary phase, first {len(fields)} of {len(w.fields)} fields "
+                                f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6"),
                    "precision": args.precision, "n_mag": info["n_mag"], "n_pot": info["n_pot"],
                    "nnz_K": info["nnz_K"], "pcg_waves_per_block": shape[0], "pcg_slices_per_wave": shape[1][0]},
         "counters": dict(tot, worst_status=worst),
@@ -268,6 +280,92 @@ def bench_learned(args, binding, inputs, np, torch):
     graph.close()
     ctx.close()
     return res
+
+
+def bench_film(args):
+    """The 1000 x 1000 x 10 nm soft film (200 x 200 x 2 cells of 5 nm, 3x air
+    box, 121,203 magnet nodes), field along x from +50 to -50 mT in 1 mT
+    steps, jmax 4, tol 1e-6: learned start + scaling in the FP32-bulk mode
+    (the value) against the plain FP64 method and learned FP64, with the
+    parameters trained on 400-1000 nm films (data/gnn_films_large.npz). Each
+    form runs once after a shared warm-up of one field."""
+    import numpy as np
+    import torch
+
+    from paper_1801_03690_amd import binding, inputs, learn
+
+    w = inputs.film()
+    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
+    ctx = binding.Context(0)
+    t0 = time.time()
+    ctx.upload(w.mesh)
+    info = ctx.info()
+    print(f"# setup {time.time() - t0:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}",
+          file=sys.stderr, flush=True)
+    graph = binding.Graph(ctx)
+    net = learn.load_net(os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_large.npz"), ctx)
+    legs = (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
+            ("learned_fp32", 3, binding.MM_FP32_BULK))
+    res, shapes, prof = {}, {}, None
+    for name, mode, prec in legs:
+        o = binding.default_opts(jmax=w.jmax, precision=prec)
+        ctx.set_opts(o)
+        if not args.no_tune:
+            nw, spw = tune(ctx, binding, args)
+            shapes[name] = (nw, spw.tolist())
+        if args.warmup:
+            ctx.reset_warm_start()
+            ctx.curve_learned(net, graph, mode, w.m0, fields[:1], opts=o)
+        ctx.reset_warm_start()
+        torch.cuda.synchronize()
+        if name == "learned_fp32":
+            ctx.profile(-1)
+            ctx.profile(1)
+        t0 = time.perf_counter()
+        r = ctx.curve_learned(net, graph, mode, w.m0, fields, opts=o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if name == "learned_fp32":
+            prof = ctx.profile(0)
+        st = r["stats"]
+        res[name] = dict(seconds=round(dt, 4), evals=int(sum(x["evals"] for x in st)),
+                         nli=int(sum(x["nli"] for x in st)), cg_iterations=int(sum(x["mi"] for x in st)),
+                         starts_taken=int(r["accepted"].sum()), rc=int(r["rc"]), _r=r)
+        print(f"# film {name}: {dt:.2f}s", file=sys.stderr, flush=True)
+    ref = res["plain_fp64"]["_r"]
+    for k in res:
+        r = res[k].pop("_r")
+        d = np.abs(r["m_avg"] - ref["m_avg"]).max(axis=1)
+        res[k]["basin_changes_vs_plain"] = int((d > 1e-2).sum())
+        res[k]["max_rel_dE_vs_plain"] = float(np.max(np.abs(r["E"] - ref["E"]) / np.abs(ref["E"])))
+    sec = res["learned_fp32"]["seconds"]
+    avg_iter = prof["seconds"] / max(prof["iterations"], 1)
+    achieved = prof["bytes_per_iteration"] / avg_iter / 1e9 if prof["iterations"] else None
+    out = {
+        "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
+        "value": sec, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 operators/f64 reductions (learned component bf16 MFMA)",
+        "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
+        "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, "
+                               f"{len(fields)} fields +50..{1e3 * fields[-1][0]:.0f} mT along x, jmax 4, tol 1e-6, "
+                               f"learned start + scaling, FP32 bulk",
+                   "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
+                   "pcg_shapes": shapes},
+        "forms": res,
+        "speedup_learned_fp32_vs_plain_fp64": round(res["plain_fp64"]["seconds"] / sec, 3),
+        "roofline": {
+            "bound": "hbm", "kernel": "scalar-potential CG iteration: k_pcg_iter<float> (learned_fp32 form)",
+            "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_iteration_us": round(1e6 * avg_iter, 3), "iterations": prof["iterations"],
+            "bytes_per_iteration": prof["bytes_per_iteration"],
+        },
+    }
+    net.close()
+    graph.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
