@@ -15,8 +15,10 @@ aggregation method:
   aggregates  pass 1, rows in order: a row that is not yet in an aggregate
               and whose strong neighbours are all free starts an aggregate
               with them; pass 2: every row still free joins the pass-1
-              aggregate of its strongest strong neighbour (ties: the lowest
-              column), looked up in the pass-1 assignment;
+              aggregate of its strongest strong neighbour, looked up in the
+              pass-1 assignment (weights within a relative TIE of each other
+              count as equal and the lowest column wins, so that round-off
+              in how a matrix was summed does not decide);
   prolongator P0 = aggregate indicator (one 1 per row), smoothed once:
               P = (I - omega D^-1 A) P0, omega = (4/3) / rho,
               rho = max_i sum_j |a_ij| / a_ii (a Gershgorin bound on the
@@ -41,6 +43,7 @@ THETA0 = 0.08
 COARSE_MAX = 512
 MAX_LEVELS = 12
 STALL = 0.9
+TIE = 1e-12
 
 
 class Csr:
@@ -147,7 +150,7 @@ def aggregate(A, theta):
         js, ws = S[i]
         best, bw = -1, -1.0
         for j, w in zip(js, ws):
-            if first[j] >= 0 and w > bw:
+            if first[j] >= 0 and w > bw * (1.0 + TIE):
                 best, bw = j, w
         if best < 0:
             raise RuntimeError("row without an aggregated strong neighbour")
