@@ -69,6 +69,7 @@ enum {
 };
 
 enum { MM_FP64 = 0, MM_FP32_BULK = 1 };
+enum { MM_PREC_JACOBI = 0, MM_PREC_AMG = 1 };
 enum { MM_STOP_TORQUE = 0, MM_STOP_PAPER = 1 };
 enum { MM_T_EXCH = 1, MM_T_ANIS = 2, MM_T_ZEE = 4, MM_T_DEMAG = 8, MM_T_ALL = 15 };
 
@@ -86,6 +87,9 @@ typedef struct {
     int terms;             /* energy terms, MM_T_* bitmask */
     int ls_max_halvings;   /* line-search backtracking cap */
     long poisson_maxit;    /* scalar-potential CG iteration cap per solve */
+    int poisson_prec;      /* scalar-potential CG preconditioner: MM_PREC_JACOBI,
+                              or MM_PREC_AMG (algebraic multigrid as in Sec. 3.1;
+                              single-instance contexts only) */
 } mm_opts;
 
 typedef struct {
@@ -111,7 +115,7 @@ typedef struct {
 /* Fill o with the defaults: jmax 4, tol_torque 1e-6, torque stopping,
    tau_F 1e-10, theta_max 0.2, theta_init 0.01, c1 1e-4, c2 0.1,
    poisson_rtol 1e-10, max_nli 20000, FP64, all terms, 20 halvings,
-   poisson_maxit 100000. */
+   poisson_maxit 100000, Jacobi-preconditioned scalar-potential CG. */
 int mm_opts_default(mm_opts *o);
 
 typedef void *(*mm_alloc_fn)(size_t bytes, void *user);
@@ -187,8 +191,10 @@ int mm_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long n, con
 enum { MM_OP_C = 0, MM_OP_B = 1, MM_OP_BT = 2, MM_OP_K = 3 };
 int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out);
 
-/* Scalar-potential solve K u = b by Jacobi-preconditioned CG, warm-started
-   from u_inout (n_pot), until |r| <= rtol |b|. iters may be NULL. */
+/* Scalar-potential solve K u = b by preconditioned CG (the preconditioner
+   and precision of the context's options: Jacobi or multigrid, FP64 or
+   FP32-bulk), warm-started from u_inout (n_pot), until |r| <= rtol |b|.
+   iters may be NULL. */
 int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters);
 
 /* Measurement hook. enable = 1 times the scalar-potential CG iterations (the
@@ -313,6 +319,42 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
    Objects: a graph belongs to the context it was created on and is invalid
    after that context's next upload or its destruction; destroy it before.
    --------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------
+   Algebraic multigrid preconditioner of the scalar-potential CG (Sec. 3.1:
+   the paper preconditions its CG with algebraic multigrid without fixing
+   the variant). Smoothed aggregation on the assembled matrix K (free
+   potential rows):
+     strong neighbour j of row i: |a_ij| >= theta_l sqrt(|a_ii a_jj|),
+       theta_l = 0.08 / 2^l;
+     aggregates: pass 1 over the rows in order starts an aggregate at a free
+       row whose strong neighbours are all free (with them); pass 2 adds each
+       remaining row to the pass-1 aggregate of its strongest strong
+       neighbour (weights within a relative 1e-12 are equal; lowest column);
+     P = (I - omega D^-1 A) P0, P0 the aggregate indicator, omega = (4/3) /
+       max_i sum_j |a_ij| / a_ii; next level P^T A P; coarsest level (at most
+       512 rows, or coarsening stalled, or 12 levels) solved by its dense
+       inverse;
+     cycle: V(1,1) with damped Jacobi (weight omega) from zero.
+   The hierarchy is built on the host on first use (a solve with
+   poisson_prec = MM_PREC_AMG or one of these calls) and kept until the mesh
+   changes. Single-instance contexts only (MM_ESTATE otherwise). */
+
+/* Number of levels and, per level l < 12 (arrays of 12, may be NULL): rows,
+   stored entries of the level operator and of the prolongator from level
+   l + 1 (0 on the coarsest level); the host seconds of the build. */
+int mm_amg_info(mm_ctx *c, int *n_levels, long *rows, long *nnz_A, long *nnz_P, double *setup_seconds);
+/* Aggregate (coarse row) of every row of level `level` (not the coarsest):
+   host array of rows[level] ints. */
+int mm_amg_aggregates(mm_ctx *c, int level, int *agg);
+/* Level operator (which = 0) or prolongator (which = 1, not on the coarsest
+   level) of level `level` as host CSR: ptr (rows + 1 longs), col and val
+   (nnz entries each, sizes from mm_amg_info); any of them may be NULL. */
+int mm_amg_level_matrix(mm_ctx *c, int level, int which, long *ptr, int *col, double *val);
+/* One cycle z = M r on the free potential rows (n_pot doubles, host or
+   device pointers), in FP64 (precision MM_FP64) or in FP32 operators and
+   vectors (MM_FP32_BULK; r rounded to FP32, z widened back). */
+int mm_amg_apply(mm_ctx *c, const double *r, double *z, int precision);
+
 typedef struct mm_gnn mm_gnn;
 typedef struct mm_graph mm_graph;
 enum { MM_LEARN_START = 1, MM_LEARN_SCALE = 2 };

@@ -24,6 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mmncg.h")
 MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_EMESH, MM_ESTATE = 0, -1, -2, -3, -4, -5
 MM_NOT_CONVERGED, MM_STALLED = 1, 2
 MM_FP64, MM_FP32_BULK = 0, 1
+MM_PREC_JACOBI, MM_PREC_AMG = 0, 1
 MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
 MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
@@ -41,7 +42,7 @@ class Opts(C.Structure):
     _fields_ = [("jmax", C.c_int), ("tol_torque", C.c_double), ("stop_mode", C.c_int), ("tau_F", C.c_double),
                 ("theta_max", C.c_double), ("theta_init", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
                 ("poisson_rtol", C.c_double), ("max_nli", C.c_long), ("precision", C.c_int), ("terms", C.c_int),
-                ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long)]
+                ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long), ("poisson_prec", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -81,6 +82,10 @@ def load_library(path=LIB_PATH):
         raise ImportError(f"libmmncg.so not built ({path}); run __graft_entry__.build()")
     L = C.CDLL(path)
     L.mm_opts_default.argtypes = [C.POINTER(Opts)]
+    L.mm_amg_info.argtypes = [_vp, C.POINTER(C.c_int), _vp, _vp, _vp, C.POINTER(C.c_double)]
+    L.mm_amg_aggregates.argtypes = [_vp, C.c_int, _vp]
+    L.mm_amg_level_matrix.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, _vp]
+    L.mm_amg_apply.argtypes = [_vp, _vp, _vp, C.c_int]
     L.mm_create.argtypes = [C.POINTER(_vp), C.c_int, _vp, ALLOC_FN, FREE_FN, _vp]
     L.mm_destroy.argtypes = [_vp]
     L.mm_last_error.restype = C.c_char_p
@@ -465,6 +470,44 @@ class Context:
         P = int(np.asarray(probes.shape)[0]) if hasattr(probes, "shape") else len(probes)
         out = np.zeros((self.n_mag, 3))
         self._check(self._L.mm_demag_diag(self.h, pp, P, float(rtol), C.c_void_p(out.ctypes.data)))
+        return out
+
+    # --- multigrid preconditioner of the scalar-potential CG ---
+    def amg_info(self):
+        """Levels of the multigrid hierarchy (built on first use): rows and
+        stored entries of each level's operator and prolongator, and the
+        host seconds of the build."""
+        nl = C.c_int(0)
+        rows, nA, nP = (np.zeros(12, dtype=np.int64) for _ in range(3))
+        sec = C.c_double(0)
+        self._check(self._L.mm_amg_info(self.h, C.byref(nl), C.c_void_p(rows.ctypes.data),
+                                        C.c_void_p(nA.ctypes.data), C.c_void_p(nP.ctypes.data), C.byref(sec)))
+        k = nl.value
+        return dict(levels=k, rows=rows[:k].tolist(), nnz_A=nA[:k].tolist(), nnz_P=nP[:k].tolist(),
+                    setup_seconds=sec.value)
+
+    def amg_aggregates(self, level):
+        info = self.amg_info()
+        out = np.zeros(info["rows"][level], dtype=np.int32)
+        self._check(self._L.mm_amg_aggregates(self.h, int(level), C.c_void_p(out.ctypes.data)))
+        return out
+
+    def amg_level_matrix(self, level, which):
+        """(ptr, col, val) of level `level`'s operator (which 0) or prolongator (1)."""
+        info = self.amg_info()
+        n = info["rows"][level]
+        nnz = (info["nnz_A"] if which == 0 else info["nnz_P"])[level]
+        ptr = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(nnz, dtype=np.int32)
+        val = np.zeros(nnz)
+        self._check(self._L.mm_amg_level_matrix(self.h, int(level), int(which), C.c_void_p(ptr.ctypes.data),
+                                                C.c_void_p(col.ctypes.data), C.c_void_p(val.ctypes.data)))
+        return ptr, col, val
+
+    def amg_apply(self, r, precision=MM_FP64):
+        rp, keep = _vec_ptr(r)
+        out = np.zeros(self.n_pot)
+        self._check(self._L.mm_amg_apply(self.h, rp, C.c_void_p(out.ctypes.data), int(precision)))
         return out
 
     def jacobi_diag(self):

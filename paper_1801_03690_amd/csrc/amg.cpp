@@ -1,0 +1,497 @@
+// Host side of the algebraic-multigrid preconditioner of the scalar-potential
+// CG (the paper preconditions its CG with algebraic multigrid, Sec. 3.1,
+// without fixing the variant): the smoothed-aggregation hierarchy is built
+// once per mesh from the assembled matrix (untimed like the assembly), copied
+// to the device in FP64 and FP32, and handed to the kernels of amg.hip.
+//
+// Hierarchy (level l, matrix A with diagonal a_ii):
+//   strength     j != i is strong when |a_ij| >= theta_l sqrt(|a_ii a_jj|),
+//                theta_l = 0.08 / 2^l;
+//   aggregates   pass 1 over the rows in order: a free row whose strong
+//                neighbours are all free starts an aggregate with them;
+//                pass 2: each row still free joins the pass-1 aggregate of
+//                its strongest strong neighbour (weights within a relative
+//                1e-12 count as equal; the lowest column wins);
+//   prolongator  P = (I - omega D^-1 A) P0 with P0 the aggregate indicator,
+//                omega = (4/3) / rho, rho = max_i sum_j |a_ij| / a_ii;
+//   next level   A_c = P^T A P; stop at <= 512 rows (dense inverse), when
+//                coarsening stalls (more than 0.9 n aggregates) or at 12
+//                levels.
+// Entries that sum to exactly zero are dropped from every product.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "context.h"
+
+namespace mmncg {
+
+namespace {
+
+constexpr double kTheta0 = 0.08;
+constexpr int kCoarseMax = 512;
+constexpr double kStall = 0.9;
+constexpr double kTie = 1e-12;
+constexpr int kDenseLimit = 4096;  // largest coarsest level held as a dense inverse
+
+struct Csr {
+    int n = 0, ncols = 0;
+    std::vector<int64_t> p;
+    std::vector<int> j;
+    std::vector<double> v;
+    int64_t nnz() const { return p.empty() ? 0 : p[n]; }
+};
+
+Csr from_host(const HostCsr &h, int n) {
+    Csr a;
+    a.n = n;
+    a.ncols = n;
+    a.p.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        for (int64_t e = h.ptr[r]; e < h.ptr[r + 1]; ++e)
+            if (h.val[e] != 0.0) {
+                a.j.push_back(h.col[e]);
+                a.v.push_back(h.val[e]);
+            }
+        a.p[r + 1] = (int64_t)a.j.size();
+    }
+    return a;
+}
+
+std::vector<double> diag(const Csr &a) {
+    std::vector<double> d(a.n, 0.0);
+    for (int r = 0; r < a.n; ++r)
+        for (int64_t e = a.p[r]; e < a.p[r + 1]; ++e)
+            if (a.j[e] == r) d[r] += a.v[e];
+    return d;
+}
+
+// C = A B with a dense accumulator per row: for row i, every stored a_ik
+// (columns ascending) times every stored b_kj; columns of C ascending, exact
+// zeros dropped
+Csr spmm(const Csr &A, const Csr &B) {
+    Csr C;
+    C.n = A.n;
+    C.ncols = B.ncols;
+    C.p.assign(A.n + 1, 0);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int> mark(B.ncols, -1), cols;
+    for (int i = 0; i < A.n; ++i) {
+        cols.clear();
+        for (int64_t e = A.p[i]; e < A.p[i + 1]; ++e) {
+            const int k = A.j[e];
+            const double a = A.v[e];
+            for (int64_t f = B.p[k]; f < B.p[k + 1]; ++f) {
+                const int c = B.j[f];
+                if (mark[c] != i) {
+                    mark[c] = i;
+                    acc[c] = 0.0;
+                    cols.push_back(c);
+                }
+                acc[c] += a * B.v[f];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int c : cols)
+            if (acc[c] != 0.0) {
+                C.j.push_back(c);
+                C.v.push_back(acc[c]);
+            }
+        C.p[i + 1] = (int64_t)C.j.size();
+    }
+    return C;
+}
+
+Csr transpose(const Csr &A) {
+    Csr T;
+    T.n = A.ncols;
+    T.ncols = A.n;
+    T.p.assign(T.n + 1, 0);
+    for (int64_t e = 0; e < A.nnz(); ++e) T.p[A.j[e] + 1] += 1;
+    for (int r = 0; r < T.n; ++r) T.p[r + 1] += T.p[r];
+    T.j.resize(A.nnz());
+    T.v.resize(A.nnz());
+    std::vector<int64_t> pos(T.p.begin(), T.p.end() - 1);
+    for (int r = 0; r < A.n; ++r)
+        for (int64_t e = A.p[r]; e < A.p[r + 1]; ++e) {
+            const int64_t q = pos[A.j[e]]++;
+            T.j[q] = r;
+            T.v[q] = A.v[e];
+        }
+    return T;
+}
+
+double gershgorin_rho(const Csr &A, const std::vector<double> &d) {
+    double rho = 0.0;
+    for (int r = 0; r < A.n; ++r) {
+        double s = 0.0;
+        for (int64_t e = A.p[r]; e < A.p[r + 1]; ++e) s += std::fabs(A.v[e]);
+        rho = std::max(rho, s / d[r]);
+    }
+    return rho;
+}
+
+// aggregate of every row; returns the number of aggregates
+int aggregate(const Csr &A, const std::vector<double> &d, double theta, std::vector<int> &agg) {
+    const int n = A.n;
+    auto strong = [&](int i, int64_t e) {
+        const int j = A.j[e];
+        return j != i && std::fabs(A.v[e]) >= theta * std::sqrt(std::fabs(d[i] * d[j]));
+    };
+    agg.assign(n, -1);
+    int na = 0;
+    for (int i = 0; i < n; ++i) {
+        if (agg[i] >= 0) continue;
+        bool free_nb = true;
+        for (int64_t e = A.p[i]; e < A.p[i + 1] && free_nb; ++e)
+            if (strong(i, e) && agg[A.j[e]] >= 0) free_nb = false;
+        if (!free_nb) continue;
+        agg[i] = na;
+        for (int64_t e = A.p[i]; e < A.p[i + 1]; ++e)
+            if (strong(i, e)) agg[A.j[e]] = na;
+        ++na;
+    }
+    const std::vector<int> first = agg;
+    for (int i = 0; i < n; ++i) {
+        if (first[i] >= 0) continue;
+        int best = -1;
+        double bw = -1.0;
+        for (int64_t e = A.p[i]; e < A.p[i + 1]; ++e) {
+            if (!strong(i, e)) continue;
+            const int j = A.j[e];
+            const double w = std::fabs(A.v[e]);
+            if (first[j] >= 0 && w > bw * (1.0 + kTie)) {
+                best = j;
+                bw = w;
+            }
+        }
+        if (best < 0) throw ApiError{MM_EMESH, "multigrid: a row has no aggregated strong neighbour"};
+        agg[i] = first[best];
+    }
+    return na;
+}
+
+// P = (I - omega D^-1 A) P0: entry (i, I) = [agg_i == I] + (-omega sum_{k in I} a_ik) / a_ii
+Csr smoothed_prolongator(const Csr &A, const std::vector<double> &d, const std::vector<int> &agg, int na,
+                         double omega) {
+    Csr P0;
+    P0.n = A.n;
+    P0.ncols = na;
+    P0.p.resize(A.n + 1);
+    P0.j = agg;
+    P0.v.assign(A.n, 1.0);
+    for (int i = 0; i <= A.n; ++i) P0.p[i] = i;
+    const Csr AP = spmm(A, P0);
+    Csr P;
+    P.n = A.n;
+    P.ncols = na;
+    P.p.assign(A.n + 1, 0);
+    for (int i = 0; i < A.n; ++i) {
+        bool own = false;
+        for (int64_t e = AP.p[i]; e < AP.p[i + 1]; ++e) {
+            const int c = AP.j[e];
+            if (!own && c > agg[i]) {
+                P.j.push_back(agg[i]);
+                P.v.push_back(1.0);
+                own = true;
+            }
+            double v = (-omega * AP.v[e]) / d[i];
+            if (c == agg[i]) {
+                v = 1.0 + v;
+                own = true;
+            }
+            if (v != 0.0) {
+                P.j.push_back(c);
+                P.v.push_back(v);
+            }
+        }
+        if (!own) {
+            P.j.push_back(agg[i]);
+            P.v.push_back(1.0);
+        }
+        P.p[i + 1] = (int64_t)P.j.size();
+    }
+    return P;
+}
+
+// inverse of a symmetric positive definite matrix through its Cholesky factor
+std::vector<double> spd_inverse(const Csr &A) {
+    const int n = A.n;
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int64_t e = A.p[r]; e < A.p[r + 1]; ++e) L[(size_t)r * n + A.j[e]] = A.v[e];
+    for (int k = 0; k < n; ++k) {
+        double s = L[(size_t)k * n + k];
+        for (int m = 0; m < k; ++m) s -= L[(size_t)k * n + m] * L[(size_t)k * n + m];
+        if (!(s > 0.0)) throw ApiError{MM_EMESH, "multigrid: coarsest matrix is not positive definite"};
+        const double lkk = std::sqrt(s);
+        L[(size_t)k * n + k] = lkk;
+        for (int i = k + 1; i < n; ++i) {
+            double t = L[(size_t)i * n + k];
+            for (int m = 0; m < k; ++m) t -= L[(size_t)i * n + m] * L[(size_t)k * n + m];
+            L[(size_t)i * n + k] = t / lkk;
+        }
+    }
+    std::vector<double> inv((size_t)n * n, 0.0), x(n);
+    for (int c = 0; c < n; ++c) {
+        // L y = e_c, then L^T x = y
+        for (int i = 0; i < n; ++i) {
+            double t = (i == c) ? 1.0 : 0.0;
+            for (int m = 0; m < i; ++m) t -= L[(size_t)i * n + m] * x[m];
+            x[i] = t / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = x[i];
+            for (int m = i + 1; m < n; ++m) t -= L[(size_t)m * n + i] * x[m];
+            x[i] = t / L[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
+    }
+    return inv;
+}
+
+struct HostLevel {
+    Csr A, P, R;
+    std::vector<double> d;
+    double rho = 0, omega = 0, theta = 0;
+    std::vector<int> agg;
+    std::vector<double> Ainv;
+};
+
+}  // namespace
+
+struct AmgState {
+    std::vector<HostLevel> lv;
+    AmgLaunch<double> g64;
+    AmgLaunch<float> g32;
+    double setup_seconds = 0;
+    double bytes64 = 0, bytes32 = 0;  // algorithmic bytes of one CG iteration
+};
+
+namespace {
+
+template <class T>
+T *upload(mm_ctx *c, const T *h, size_t n) {
+    T *d = dalloc_n<T>(c, std::max<size_t>(n, 1));
+    if (n) HIPCHK(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return d;
+}
+
+template <class T>
+T *upload_v(mm_ctx *c, const std::vector<T> &v) {
+    return upload(c, v.data(), v.size());
+}
+
+std::vector<float> to32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+
+std::vector<int> ptr32(const Csr &a) {
+    if (a.nnz() > 0x7fffffffLL) throw ApiError{MM_ENOMEM, "multigrid: a level has more than 2^31 entries"};
+    return std::vector<int>(a.p.begin(), a.p.end());
+}
+
+// device copies of a CSR in both precisions
+void up_csr(mm_ctx *c, const Csr &a, const int **p, const int **j, const double **v64, const int **p2,
+            const int **j2, const float **v32) {
+    const std::vector<int> pp = ptr32(a);
+    *p = *p2 = upload_v(c, pp);
+    *j = *j2 = upload_v(c, a.j);
+    *v64 = upload_v(c, a.v);
+    *v32 = upload_v(c, to32(a.v));
+}
+
+}  // namespace
+
+void amg_release(mm_ctx *c) {
+    delete c->amg;
+    c->amg = nullptr;
+}
+
+// builds the hierarchy of instance 0 (single-instance contexts) once per mesh
+AmgState *amg_get(mm_ctx *c) {
+    if (c->amg) return c->amg;
+    if (c->ninst != 1) throw ApiError{MM_ESTATE, "the multigrid preconditioner needs a single-instance context"};
+    if (c->hostK.nrows != c->inst[0].n_pot) throw ApiError{MM_ESTATE, "no host copy of the scalar-potential matrix"};
+    const double t0 = now_s();
+    std::unique_ptr<AmgState> S(new AmgState());
+    Csr A = from_host(c->hostK, c->inst[0].n_pot);
+    double theta = kTheta0;
+    for (;;) {
+        HostLevel L;
+        L.d = diag(A);
+        for (double x : L.d)
+            if (!(x > 0.0)) throw ApiError{MM_EMESH, "multigrid: non-positive diagonal"};
+        L.rho = gershgorin_rho(A, L.d);
+        L.omega = (4.0 / 3.0) / L.rho;
+        L.theta = theta;
+        const bool last = A.n <= kCoarseMax || (int)S->lv.size() + 1 == kAmgMaxLevels;
+        int na = 0;
+        if (!last) {
+            na = aggregate(A, L.d, theta, L.agg);
+            if (na > kStall * A.n || na == 0) L.agg.clear();
+        }
+        if (L.agg.empty()) {
+            if (A.n > kDenseLimit) throw ApiError{MM_EMESH, "multigrid coarsening stalled"};
+            L.A = std::move(A);
+            L.Ainv = spd_inverse(L.A);
+            S->lv.push_back(std::move(L));
+            break;
+        }
+        L.P = smoothed_prolongator(A, L.d, L.agg, na, L.omega);
+        L.R = transpose(L.P);
+        Csr Ac = spmm(L.R, spmm(A, L.P));
+        L.A = std::move(A);
+        S->lv.push_back(std::move(L));
+        A = std::move(Ac);
+        theta *= 0.5;
+    }
+    // device copies
+    const int nl = (int)S->lv.size();
+    S->g64.nlev = S->g32.nlev = nl;
+    const size_t RP = std::max(c->rows_p, 1);
+    double b64 = 0, b32 = 0;
+    for (int l = 0; l < nl; ++l) {
+        HostLevel &H = S->lv[l];
+        AmgLevel<double> &D = S->g64.lv[l];
+        AmgLevel<float> &F = S->g32.lv[l];
+        D.n = F.n = H.A.n;
+        D.omega = H.omega;
+        F.omega = (float)H.omega;
+        if (l > 0) up_csr(c, H.A, &D.Ap, &D.Aj, &D.Av, &F.Ap, &F.Aj, &F.Av);
+        std::vector<double> dinv(H.A.n);
+        for (int i = 0; i < H.A.n; ++i) dinv[i] = 1.0 / H.d[i];
+        if (l == 0) {
+            D.dinv = c->invDK;
+            F.dinv = c->invDK32;
+        } else {
+            D.dinv = upload_v(c, dinv);
+            F.dinv = upload_v(c, to32(dinv));
+        }
+        if (!H.P.p.empty()) {
+            up_csr(c, H.P, &D.Pp, &D.Pj, &D.Pv, &F.Pp, &F.Pj, &F.Pv);
+            up_csr(c, H.R, &D.Rp, &D.Rj, &D.Rv, &F.Rp, &F.Rj, &F.Rv);
+        }
+        if (!H.Ainv.empty()) {
+            D.Ainv = upload_v(c, H.Ainv);
+            F.Ainv = upload_v(c, to32(H.Ainv));
+        }
+        const size_t nv = (l == 0) ? RP : (size_t)std::max(H.A.n, 1);
+        for (double **v : {&D.b, &D.t, &D.z, &D.y}) {
+            *v = dalloc_n<double>(c, nv);
+            HIPCHK(hipMemsetAsync(*v, 0, nv * sizeof(double), c->stream));
+        }
+        for (float **v : {&F.b, &F.t, &F.z, &F.y}) {
+            *v = dalloc_n<float>(c, nv);
+            HIPCHK(hipMemsetAsync(*v, 0, nv * sizeof(float), c->stream));
+        }
+        // algorithmic bytes of one CG iteration, per level: the fine level
+        // reads K three times (iteration, post-smoothing, w = K u) and P
+        // twice; a coarse level reads A twice and P, R once each; vector
+        // passes as counted below; the coarsest reads its dense inverse
+        const double nA = (double)(l == 0 ? c->inst[0].nnz_K : H.A.nnz()), nP = (double)H.P.nnz();
+        const double n = (double)H.A.n;
+        for (int k = 0; k < 2; ++k) {
+            const double v = k ? 4.0 : 8.0;
+            double by;
+            if (!H.Ainv.empty() && l > 0) by = n * n * v + 2.0 * n * v;
+            else if (l == 0) by = 3.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 17.0 * n * v;
+            else by = 2.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 9.0 * n * v;
+            (k ? b32 : b64) += by;
+        }
+    }
+    S->g64.u = dalloc_n<double>(c, RP);
+    S->g32.u = dalloc_n<float>(c, RP);
+    HIPCHK(hipMemsetAsync(S->g64.u, 0, RP * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(S->g32.u, 0, RP * sizeof(float), c->stream));
+    sync(c);
+    S->bytes64 = b64;
+    S->bytes32 = b32;
+    S->setup_seconds = now_s() - t0;
+    c->amg = S.release();
+    return c->amg;
+}
+
+const AmgLaunch<double> &amg_launch64(AmgState *s) { return s->g64; }
+const AmgLaunch<float> &amg_launch32(AmgState *s) { return s->g32; }
+double amg_bytes(AmgState *s, bool fp32) { return fp32 ? s->bytes32 : s->bytes64; }
+
+}  // namespace mmncg
+
+using namespace mmncg;
+
+extern "C" {
+
+int mm_amg_info(mm_ctx *c, int *n_levels, long *rows, long *nnz_A, long *nnz_P, double *setup_seconds) {
+    return guarded(c, [&] {
+        require_single(c);
+        if (!n_levels) throw ApiError{MM_EINVAL, "null n_levels"};
+        AmgState *S = amg_get(c);
+        const int nl = (int)S->lv.size();
+        *n_levels = nl;
+        for (int l = 0; l < kAmgMaxLevels; ++l) {
+            const bool in = l < nl;
+            if (rows) rows[l] = in ? S->lv[l].A.n : 0;
+            if (nnz_A) nnz_A[l] = in ? (long)S->lv[l].A.nnz() : 0;
+            if (nnz_P) nnz_P[l] = in ? (long)S->lv[l].P.nnz() : 0;
+        }
+        if (setup_seconds) *setup_seconds = S->setup_seconds;
+        return MM_OK;
+    });
+}
+
+int mm_amg_aggregates(mm_ctx *c, int level, int *agg) {
+    return guarded(c, [&] {
+        require_single(c);
+        AmgState *S = amg_get(c);
+        if (!agg || level < 0 || level + 1 >= (int)S->lv.size())
+            throw ApiError{MM_EINVAL, "level must have a coarser level below it"};
+        std::memcpy(agg, S->lv[level].agg.data(), S->lv[level].agg.size() * sizeof(int));
+        return MM_OK;
+    });
+}
+
+int mm_amg_level_matrix(mm_ctx *c, int level, int which, long *ptr, int *col, double *val) {
+    return guarded(c, [&] {
+        require_single(c);
+        AmgState *S = amg_get(c);
+        if (level < 0 || level >= (int)S->lv.size()) throw ApiError{MM_EINVAL, "no such level"};
+        const HostLevel &H = S->lv[level];
+        const Csr *m = which == 0 ? &H.A : which == 1 ? &H.P : nullptr;
+        if (!m || m->p.empty()) throw ApiError{MM_EINVAL, "which: 0 = level operator, 1 = prolongator (not on the coarsest level)"};
+        if (ptr)
+            for (int r = 0; r <= m->n; ++r) ptr[r] = (long)m->p[r];
+        if (col) std::memcpy(col, m->j.data(), m->j.size() * sizeof(int));
+        if (val) std::memcpy(val, m->v.data(), m->v.size() * sizeof(double));
+        return MM_OK;
+    });
+}
+
+int mm_amg_apply(mm_ctx *c, const double *r, double *z, int precision) {
+    return guarded(c, [&] {
+        require_single(c);
+        if (!r || !z) throw ApiError{MM_EINVAL, "null vector"};
+        if (precision != MM_FP64 && precision != MM_FP32_BULK) throw ApiError{MM_EINVAL, "unknown precision"};
+        AmgState *S = amg_get(c);
+        const int n = c->inst[0].n_pot;
+        const PcgLaunch a = pcg_args(c);
+        // the fine level's b and y are not used by the cycle: input and output staging
+        double *r64 = S->g64.lv[0].b, *z64 = S->g64.lv[0].y;
+        copy_in(c, r64, r, n);
+        if (precision == MM_FP64) {
+            launch_amg_apply64(a, S->g64, r64, c->stream);
+            copy_out(c, z, S->g64.u, n);
+        } else {
+            float *r32 = S->g32.lv[0].b;
+            launch_to_f32(n, r64, r32, c->stream);
+            launch_amg_apply32(a, S->g32, r32, c->stream);
+            gnn_f32_to_f64(n, S->g32.u, z64, c->stream);
+            copy_out(c, z, z64, n);
+        }
+        sync(c);
+        return MM_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,474 @@
+// Algebraic-multigrid preconditioned CG for the scalar-potential system
+// K u = b (the paper preconditions its CG with algebraic multigrid, Sec. 3.1;
+// the hierarchy is smoothed aggregation, built on the host in amg.cpp).
+//
+// The CG keeps the single-reduction form of the Jacobi path: one global
+// reduction per iteration, read by the first kernel of the next iteration.
+// With u = M r (one V(1,1) cycle) and w = K u:
+//   gamma = r.u, delta = w.u, beta = gamma / gamma_prev,
+//   alpha = gamma / (delta - beta gamma / alpha_prev),
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s.
+// One iteration is a chain of launches:
+//   k_amg_iter     scalars, the updates of own rows, and the first half of
+//                  the fine pre-smoothing t = r - omega K D^-1 r: K D^-1 r of
+//                  the new r is formed from the previous r, w, s records of
+//                  the neighbours as in the Jacobi path (no extra pass);
+//   per level l    restriction b_{l+1} = P_l^T t_l, coarse pre-smoothing
+//                  t = b - A omega D^-1 b, ..., dense solve on the coarsest
+//                  level, prolongation z = omega D^-1 b + P y and
+//                  post-smoothing y = z + omega D^-1 (b - A z) on the way up;
+//   k_amg_post0    u = z + omega D^-1 (r - K z) on the fine level, partial
+//                  gamma;
+//   k_amg_w        w = K u, the whole record {r, w, s, D^-1} rewritten,
+//                  partials delta and r.r.
+// Every kernel of an iteration returns at once when the instance's sticky
+// flag is up (the flag only changes inside k_amg_iter, which every later
+// launch follows in stream order). Vector type VT is double (FP64 mode) or
+// float (inner solve of the FP32-bulk mode); reductions are FP64.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mmncg {
+
+using namespace dev;
+
+namespace {
+
+constexpr int kAB = 256;  // threads per block of the coarse-level kernels
+constexpr int kP0 = 0, kP1 = 3;
+
+__device__ __forceinline__ bool skip(const int *done) { return done && *done; }
+
+// sum over the GL lanes of a row group (GL divides 64)
+template <int GL, class VT>
+__device__ __forceinline__ VT group_sum(VT v) {
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GL);
+    return v;
+}
+
+// one CSR row times x, GL lanes per row; the row's sum in every lane of the group
+template <int GL, class VT>
+__device__ __forceinline__ VT csr_row(const int *__restrict__ p, const int *__restrict__ j,
+                                      const VT *__restrict__ v, const VT *__restrict__ x, int row, int gl) {
+    VT acc = 0;
+    const int e1 = p[row + 1];
+    for (int e = p[row] + gl; e < e1; e += GL) acc += v[e] * x[j[e]];
+    return group_sum<GL>(acc);
+}
+
+// y = R x (restriction; GL lanes per row of R)
+template <class VT, int GL>
+__global__ __launch_bounds__(kAB) void k_amg_restrict(int n, const int *__restrict__ p, const int *__restrict__ j,
+                                                      const VT *__restrict__ v, const VT *__restrict__ x,
+                                                      VT *__restrict__ y, const int *done) {
+    if (skip(done)) return;
+    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
+    if (row >= n) return;
+    const VT s = csr_row<GL>(p, j, v, x, row, gl);
+    if (gl == 0) y[row] = s;
+}
+
+// t = b - A (omega D^-1 b) (pre-smoothing from zero, then its residual)
+template <class VT, int GL>
+__global__ __launch_bounds__(kAB) void k_amg_pre(int n, const int *__restrict__ p, const int *__restrict__ j,
+                                                 const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
+                                                 const VT *__restrict__ b, VT *__restrict__ t, const int *done) {
+    if (skip(done)) return;
+    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
+    if (row >= n) return;
+    VT acc = 0;
+    const int e1 = p[row + 1];
+    for (int e = p[row] + gl; e < e1; e += GL) {
+        const int c = j[e];
+        acc += v[e] * (dinv[c] * b[c]);
+    }
+    acc = group_sum<GL>(acc);
+    if (gl == 0) t[row] = b[row] - omega * acc;
+}
+
+// z = omega D^-1 b + P y (b at b[row * bs]: bs = 4 for the r field of the
+// fine-level records)
+template <class VT, int GL>
+__global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restrict__ p, const int *__restrict__ j,
+                                                     const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
+                                                     const VT *__restrict__ b, int bs, const VT *__restrict__ yc,
+                                                     VT *__restrict__ z, const int *done) {
+    if (skip(done)) return;
+    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
+    if (row >= n) return;
+    const VT s = csr_row<GL>(p, j, v, yc, row, gl);
+    if (gl == 0) z[row] = omega * dinv[row] * b[(int64_t)row * bs] + s;
+}
+
+// y = z + omega D^-1 (b - A z) (post-smoothing)
+template <class VT, int GL>
+__global__ __launch_bounds__(kAB) void k_amg_post(int n, const int *__restrict__ p, const int *__restrict__ j,
+                                                  const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
+                                                  const VT *__restrict__ b, const VT *__restrict__ z,
+                                                  VT *__restrict__ y, const int *done) {
+    if (skip(done)) return;
+    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
+    if (row >= n) return;
+    const VT s = csr_row<GL>(p, j, v, z, row, gl);
+    if (gl == 0) y[row] = z[row] + omega * dinv[row] * (b[row] - s);
+}
+
+// y = Ainv b on the coarsest level: one wave per row of the dense inverse
+template <class VT>
+__global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__ Ainv, const VT *__restrict__ b,
+                                                   int bs, VT *__restrict__ y, const int *done) {
+    if (skip(done)) return;
+    const int row = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
+    if (row >= n) return;
+    const VT *a = Ainv + (int64_t)row * n;
+    VT acc = 0;
+    for (int c = ln; c < n; c += 64) acc += a[c] * b[(int64_t)c * bs];
+    acc = group_sum<64>(acc);
+    if (ln == 0) y[row] = acc;
+}
+
+// fine level, start of a cycle from a residual that is not produced by
+// k_amg_iter (the CG start, or a plain vector): t = r - omega K D^-1 r with r
+// at r[row * rs]. With q given (the CG start), also sets w = s = 0 and d =
+// D^-1 in the records q (the r fields are left alone: neighbours read them).
+template <class MT, class VT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
+                                                      const VT *__restrict__ invD, VT omega, VT *__restrict__ t,
+                                                      PcgNode<VT> *__restrict__ q) {
+    Tile tl = tile_of(M);
+    if (tl.inst < 0) return;
+    const int rend = M.rend[tl.inst], ln = lane_id();
+    for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
+        const int64_t base = K.sptr[s];
+        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+        VT acc = 0;
+        for (int k = 0; k < wd; ++k) {
+            const int64_t e = base + 64 * k + ln;
+            const int c = K.col[e];
+            acc += (VT)K.val[e] * (invD[c] * r[(int64_t)c * rs]);
+        }
+        const int row = s * 64 + ln;
+        if (row < rend) {
+            t[row] = r[(int64_t)row * rs] - omega * acc;
+            if (q) {
+                q[row].w = (VT)0;
+                q[row].s = (VT)0;
+                q[row].d = invD[row];
+            }
+        }
+    }
+}
+
+// fine level: u = z + omega D^-1 (r - K z); partial gamma = r.u into slot
+// gslot (skipped when part is null)
+template <class MT, class VT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
+                                                       const VT *__restrict__ invD, VT omega,
+                                                       const VT *__restrict__ z, VT *__restrict__ u,
+                                                       double *__restrict__ part, int gslot, const int *done) {
+    Tile tl = tile_of(M);
+    if (tl.inst < 0 || skip(done)) return;
+    __shared__ double sh[NW];
+    const int rend = M.rend[tl.inst], ln = lane_id();
+    double acc[1] = {0};
+    for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
+        const int64_t base = K.sptr[s];
+        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+        VT kz = 0;
+        for (int k = 0; k < wd; ++k) {
+            const int64_t e = base + 64 * k + ln;
+            kz += (VT)K.val[e] * z[K.col[e]];
+        }
+        const int row = s * 64 + ln;
+        if (row < rend) {
+            const VT ri = r[(int64_t)row * rs];
+            const VT ui = z[row] + omega * invD[row] * (ri - kz);
+            u[row] = ui;
+            acc[0] += (double)ri * (double)ui;
+        }
+    }
+    if (part) write_part<1, NW>(acc, 0u, part + (size_t)gslot * M.nblk, M.nblk, tl.b, sh);
+}
+
+// fine level: w = K u; the record {r, w, s, d} rewritten whole; partials
+// (delta = w.u, r.r) into slots wslot, wslot + 1
+template <class MT, class VT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
+                                                   const VT *__restrict__ u, double *__restrict__ part, int wslot,
+                                                   const int *done) {
+    Tile tl = tile_of(M);
+    if (tl.inst < 0 || skip(done)) return;
+    __shared__ double sh[NW * 2];
+    const int rend = M.rend[tl.inst], ln = lane_id();
+    double acc[2] = {0, 0};
+    for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
+        const int64_t base = K.sptr[s];
+        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+        VT ku = 0;
+        for (int k = 0; k < wd; ++k) {
+            const int64_t e = base + 64 * k + ln;
+            ku += (VT)K.val[e] * u[K.col[e]];
+        }
+        const int row = s * 64 + ln;
+        if (row < rend) {
+            PcgNode<VT> me = q[row];
+            me.w = ku;
+            q[row] = me;
+            acc[0] += (double)ku * (double)u[row];
+            acc[1] += (double)me.r * (double)me.r;
+        }
+    }
+    write_part<2, NW>(acc, 0u, part + (size_t)wslot * M.nblk, M.nblk, tl.b, sh);
+}
+
+// K D^-1 times the r, w and s fields of the neighbour records (one row of
+// the slice, this lane)
+template <class MT, class VT>
+__device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0, VT &pa,
+                                        VT &pb, VT &pc) {
+    constexpr int G = sizeof(VT) == 4 ? 8 : 4;
+    const int64_t base = K.sptr[s];
+    const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+    pa = pb = pc = (VT)0;
+    for (int k0 = 0; k0 < wd; k0 += G) {
+        int cc[G];
+        VT vv[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const bool in = k0 + k < wd;
+            const int64_t e = base + 64 * (k0 + k) + ln;
+            cc[k] = in ? K.col[e] : s * 64;
+            vv[k] = in ? (VT)K.val[e] : (VT)0;
+        }
+        PcgNode<VT> nq[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) nq[k] = q0[cc[k]];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const VT kd = vv[k] * nq[k].d;
+            pa += kd * nq[k].r;
+            pb += kd * nq[k].w;
+            pc += kd * nq[k].s;
+        }
+    }
+}
+
+// the updates of one CG iteration of parity par (reads records q[par] and the
+// partials P[par]; writes records q[par ^ 1] with w = 0, filled in by
+// k_amg_w) and t = r_new - omega K D^-1 r_new, where K D^-1 r_new = A -
+// alpha (B + beta C) with A, B, C the products of K D^-1 with the old r, w, s
+template <class MT, class VT, class XT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
+                                                      const VT *__restrict__ uu, VT *__restrict__ tt, VT omega,
+                                                      PcgState *__restrict__ st, int par,
+                                                      const double *__restrict__ part) {
+    Tile tl = tile_of(M);
+    if (tl.inst < 0) return;
+    PcgState *si = st + tl.inst;
+    __shared__ double sh[NW * 3];
+    __shared__ int sdone;
+    const int S = M.nblk, b0 = M.ipb[tl.inst], b1 = M.ipb[tl.inst + 1];
+    const double *pp = part + (size_t)(par ? kP1 : kP0) * S;
+    double g3[3] = {0, 0, 0};
+    for (int i = b0 + (int)threadIdx.x; i < b1; i += NW * 64) {
+        g3[0] += pp[i];
+        g3[1] += pp[(size_t)S + i];
+        g3[2] += pp[2 * (size_t)S + i];
+    }
+    if (threadIdx.x == 0) sdone = si->done;
+    __syncthreads();
+    if (sdone) return;
+    const PcgNode<VT> *__restrict__ q0 = v.q[par];
+    PcgNode<VT> *__restrict__ q1 = v.q[par ^ 1];
+    VT *__restrict__ p = v.p;
+    const int rend = M.rend[tl.inst], ln = lane_id();
+    const double tol2 = si->tol2, gprev = si->gamma[par ^ 1], aprev = si->alpha[par ^ 1];
+    const int sf = tl.s0 + wave_id();
+    VT pa = 0, pb = 0, pc = 0;
+    if (sf < tl.s1) row_abc(K, sf, ln, q0, pa, pb, pc);
+    block_reduce<3, NW>(g3, 0u, sh);
+    const double gam = g3[0], del = g3[1], rr = g3[2];
+    if (rr <= tol2) {
+        if (tl.b == b0 && threadIdx.x == 0) si->done = 2 + par;
+        return;
+    }
+    const double beta = gam / gprev;
+    const double alpha = gam / (del - beta * gam / aprev);
+    if (tl.b == b0 && threadIdx.x == 0) {
+        si->gamma[par] = gam;
+        si->alpha[par] = alpha;
+        si->iters += 1;
+    }
+    const VT a = (VT)alpha, bt = (VT)beta;
+    for (int s = sf; s < tl.s1; s += NW) {
+        if (s != sf) row_abc(K, s, ln, q0, pa, pb, pc);
+        const int row = s * 64 + ln;
+        if (row < rend) {
+            const PcgNode<VT> me = q0[row];
+            const VT ui = uu[row];
+            const VT sn = bt != (VT)0 ? me.w + bt * me.s : me.w;
+            const VT pn = bt != (VT)0 ? ui + bt * p[row] : ui;
+            const VT rn = me.r - a * sn;
+            const VT kdr = bt != (VT)0 ? pa - a * (pb + bt * pc) : pa - a * pb;
+            x[row] = x[row] + (XT)(a * pn);
+            p[row] = pn;
+            q1[row] = PcgNode<VT>{rn, (VT)0, sn, me.d};
+            tt[row] = rn - omega * kdr;
+        }
+    }
+}
+
+}  // namespace
+
+#define MMNCG_NW_SWITCH(nw, ...)            \
+    switch (nw) {                           \
+        case 4: {                           \
+            constexpr int NW = 4;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 8: {                           \
+            constexpr int NW = 8;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        default: {                          \
+            constexpr int NW = 16;          \
+            __VA_ARGS__;                    \
+        } break;                            \
+    }
+
+namespace {
+
+template <int GL>
+dim3 grid_rows(int n) {
+    const int64_t th = (int64_t)n * GL;
+    return dim3((unsigned)((th + kAB - 1) / kAB));
+}
+
+// the cycle below the fine level: restriction of t0, levels 1..L, and the
+// prolongation back to z0 (r0 at r[row * rs])
+template <class VT>
+void coarse_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, hipStream_t s) {
+    const int L = g.nlev - 1;
+    const AmgLevel<VT> &f = g.lv[0];
+    // down
+    for (int l = 0; l < L; ++l) {
+        const AmgLevel<VT> &a = g.lv[l], &c = g.lv[l + 1];
+        const VT *tl = a.t;
+        if (c.n > 0)
+            hipLaunchKernelGGL((k_amg_restrict<VT, 8>), grid_rows<8>(c.n), dim3(kAB), 0, s, c.n, a.Rp, a.Rj, a.Rv,
+                               tl, c.b, done);
+        if (l + 1 < L && c.n > 0)
+            hipLaunchKernelGGL((k_amg_pre<VT, 8>), grid_rows<8>(c.n), dim3(kAB), 0, s, c.n, c.Ap, c.Aj, c.Av,
+                               c.dinv, c.omega, (const VT *)c.b, c.t, done);
+    }
+    const AmgLevel<VT> &cl = g.lv[L];
+    if (cl.n > 0)
+        hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
+                           cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
+    // up
+    for (int l = L - 1; l >= 0; --l) {
+        const AmgLevel<VT> &a = g.lv[l], &c = g.lv[l + 1];
+        if (l == 0) {
+            hipLaunchKernelGGL((k_amg_prolong<VT, 4>), grid_rows<4>(f.n), dim3(kAB), 0, s, f.n, f.Pp, f.Pj, f.Pv,
+                               f.dinv, f.omega, r, rs, (const VT *)c.y, f.z, done);
+        } else if (a.n > 0) {
+            hipLaunchKernelGGL((k_amg_prolong<VT, 4>), grid_rows<4>(a.n), dim3(kAB), 0, s, a.n, a.Pp, a.Pj, a.Pv,
+                               a.dinv, a.omega, (const VT *)a.b, 1, (const VT *)c.y, a.z, done);
+            hipLaunchKernelGGL((k_amg_post<VT, 8>), grid_rows<8>(a.n), dim3(kAB), 0, s, a.n, a.Ap, a.Aj, a.Av,
+                               a.dinv, a.omega, (const VT *)a.b, (const VT *)a.z, a.y, done);
+        }
+    }
+}
+
+// everything between the fine pre-smoothing and the fine post-smoothing:
+// z0 = omega D^-1 r + P V(P^T t0); with a single level, z0 = K^-1 r from the
+// dense inverse (and the post-smoothing weight is 0, see post_omega)
+template <class VT>
+void lower_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, hipStream_t s) {
+    const AmgLevel<VT> &f = g.lv[0];
+    if (g.nlev > 1) {
+        coarse_cycle(g, r, rs, done, s);
+    } else if (f.n > 0) {
+        hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((f.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
+                           f.n, f.Ainv, r, rs, f.z, done);
+    }
+}
+
+template <class VT>
+VT post_omega(const AmgLaunch<VT> &g) {
+    return g.nlev > 1 ? g.lv[0].omega : (VT)0;
+}
+
+// one cycle on the fine level from the residual r (at r[row * rs]) into
+// g.u; with a CG, also the records' start fields (q) and the partials of
+// the start (gamma, then delta and r.r in P0)
+template <class VT>
+void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const VT *r, int rs, PcgNode<VT> *q, bool cg,
+                hipStream_t s) {
+    const RowMap &M = *a.M;
+    const AmgLevel<VT> &f = g.lv[0];
+    // t (unused with a single level) and the records' start fields
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, r, rs, f.dinv, f.omega, f.t, q))
+    lower_cycle(g, r, rs, nullptr, s);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, r, rs, f.dinv, post_omega(g), (const VT *)f.z, g.u,
+                                             cg ? a.part : (double *)nullptr, kP0, (const int *)nullptr))
+    if (cg)
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                                 view<VT>(*a.K), M, q, (const VT *)g.u, a.part, kP0 + 1,
+                                                 (const int *)nullptr))
+}
+
+template <class VT, class XT>
+void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const PcgVecs<VT> &v, XT *x, int par, hipStream_t s) {
+    const RowMap &M = *a.M;
+    const AmgLevel<VT> &f = g.lv[0];
+    const int *done = &a.st[0].done;
+    PcgNode<VT> *q1 = v.q[par ^ 1];
+    const int ws = par ? kP0 : kP1;  // this iteration's new partials
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, VT, XT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, v, x, (const VT *)g.u, f.t, f.omega, a.st,
+                                             par, (const double *)a.part))
+    lower_cycle(g, &q1->r, 4, done, s);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, (const VT *)&q1->r, 4, f.dinv, post_omega(g),
+                                             (const VT *)f.z, g.u, a.part, ws, done);
+                    hipLaunchKernelGGL((k_amg_w<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                       view<VT>(*a.K), M, q1, (const VT *)g.u, a.part, ws + 1, done))
+}
+
+}  // namespace
+
+void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s) {
+    launch_pcg_residual_q(a, act, s);
+    fine_cycle<double>(a, g, &a.v64.q[0]->r, 4, a.v64.q[0], true, s);
+    launch_pcg_fin(a, act, rtol2, 0, s);
+}
+
+void launch_amg_init32(const PcgLaunch &a, const AmgLaunch<float> &g, hipStream_t s) {
+    launch_pcg_start32_only(a, s);
+    fine_cycle<float>(a, g, &a.v32.q[0]->r, 4, a.v32.q[0], true, s);
+    launch_pcg_fin(a, nullptr, 0.0, 1, s);
+}
+
+void launch_amg_iter64(const PcgLaunch &a, const AmgLaunch<double> &g, int parity, hipStream_t s) {
+    amg_iter<double, double>(a, g, a.v64, a.u, parity, s);
+}
+
+void launch_amg_iter32(const PcgLaunch &a, const AmgLaunch<float> &g, int parity, hipStream_t s) {
+    amg_iter<float, float>(a, g, a.v32, a.x32, parity, s);
+}
+
+void launch_amg_apply64(const PcgLaunch &a, const AmgLaunch<double> &g, const double *r, hipStream_t s) {
+    fine_cycle<double>(a, g, r, 1, nullptr, false, s);
+}
+
+void launch_amg_apply32(const PcgLaunch &a, const AmgLaunch<float> &g, const float *r, hipStream_t s) {
+    fine_cycle<float>(a, g, r, 1, nullptr, false, s);
+}
+
+}  // namespace mmncg

@@ -18,6 +18,7 @@ namespace mmncg {
 
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
 constexpr int kPcgChunk = 16;  // CG iterations per captured graph (even: the double buffers return to parity 0)
+constexpr int kAmgChunk = 2;   // the same for the multigrid-preconditioned CG (about 10 launches per iteration)
 
 struct HipError {
     hipError_t e;
@@ -76,6 +77,9 @@ struct Cnt {
 
 struct mm_gnn;
 struct mm_graph;
+namespace mmncg {
+struct AmgState;
+}
 
 using namespace mmncg;  // private header: the context's members are library types
 
@@ -124,6 +128,11 @@ struct mm_ctx {
     double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
     double *ppart = nullptr;    // potential-row partials, kPcgSlots slots
     hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+    // multigrid preconditioner (single-instance contexts): host copy of the
+    // scalar-potential matrix, the hierarchy once built, its captured graphs
+    HostCsr hostK;
+    mmncg::AmgState *amg = nullptr;
+    hipGraphExec_t agraph64 = nullptr, agraph32 = nullptr;
 
     // control block: ints {act, role, first, from, pact, plive} (host-written)
     // then {info, pflags x4} (device-written); doubles {alpha, h3 x3, pin x4}
@@ -177,7 +186,16 @@ void copy_in(mm_ctx *c, double *dst, const double *src, size_t n);
 void copy_out(mm_ctx *c, double *dst, const double *src, size_t n);
 void sync(mm_ctx *c);
 void upload_ctl(mm_ctx *c);
-void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<int> &on);
+void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std::vector<int> &on);
+double now_s();
+PcgLaunch pcg_args(mm_ctx *c);
+
+// --- multigrid preconditioner (amg.cpp) ---
+AmgState *amg_get(mm_ctx *c);   // builds the hierarchy on first use
+void amg_release(mm_ctx *c);
+const AmgLaunch<double> &amg_launch64(AmgState *s);
+const AmgLaunch<float> &amg_launch32(AmgState *s);
+double amg_bytes(AmgState *s, bool fp32);
 void load_m(mm_ctx *c, const double *m);
 void reduce_field(const InstInfo &I, const double *BT, double h[3]);
 void eval_all(mm_ctx *c, const mm_opts &o, const std::vector<double> &h);

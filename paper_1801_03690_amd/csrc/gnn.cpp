@@ -601,7 +601,7 @@ int mm_demag_diag(mm_ctx *c, const double *probes, int n_probe, double rtol, dou
             if (c->B.nrows > 0) launch_bmul(c->B, c->Mb.map, nullptr, sv, nullptr, c->b, false, c->stream);
             c->act()[0] = 1;
             upload_ctl(c);
-            poisson(c, rtol, c->opts.poisson_maxit, false, {0});
+            poisson(c, rtol, c->opts.poisson_maxit, false, c->opts.poisson_prec == MM_PREC_AMG, {0});
             launch_btmul(c->Bt, c->Mm.map, c->u, c->pq, false, c->stream);
             HIPCHK(hipMemcpyAsync(v.data(), c->pq, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             sync(c);

@@ -186,6 +186,50 @@ void launch_pcg_init32(const PcgLaunch &a, hipStream_t s);
 void launch_pcg_iter64(const PcgLaunch &a, int parity, hipStream_t s);
 void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s);
 void launch_add_correction(const PcgLaunch &a, hipStream_t s);
+// pieces of the CG start shared with the multigrid variant: r = b - K u into
+// the r fields of records 0 with the partials (b.b, r.r); the FP32 inner
+// start (x = 0, r = r64 * scale); the start partials into the CG state
+// (mode 0: CG start, 1: FP32 inner start, 2: residual only)
+void launch_pcg_residual_q(const PcgLaunch &a, const int *act, hipStream_t s);
+void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s);
+void launch_pcg_fin(const PcgLaunch &a, const int *act, double rtol2, int mode, hipStream_t s);
+
+// --- algebraic multigrid preconditioner of the scalar-potential CG (amg.hip) ---
+// Level l of the smoothed-aggregation hierarchy (device pointers). Level 0 is
+// the scalar-potential matrix itself (the SELL matrix K of the CG); levels
+// >= 1 hold their Galerkin operator A as CSR. P maps the next level's
+// vectors to this level's rows (CSR, rows of this level), R = P^T (rows of
+// the next level). The coarsest level holds its dense inverse (row-major).
+constexpr int kAmgMaxLevels = 12;
+template <class VT>
+struct AmgLevel {
+    int n = 0;
+    const int *Ap = nullptr, *Aj = nullptr;
+    const VT *Av = nullptr;
+    const VT *dinv = nullptr;  // 1 / a_ii
+    VT omega = 0;              // damped-Jacobi weight
+    const int *Pp = nullptr, *Pj = nullptr;
+    const VT *Pv = nullptr;
+    const int *Rp = nullptr, *Rj = nullptr;
+    const VT *Rv = nullptr;
+    const VT *Ainv = nullptr;
+    VT *b = nullptr, *t = nullptr, *z = nullptr, *y = nullptr;  // work vectors
+};
+template <class VT>
+struct AmgLaunch {
+    int nlev = 0;
+    AmgLevel<VT> lv[kAmgMaxLevels];
+    VT *u = nullptr;  // fine level: the preconditioned residual M r
+};
+// CG start (single instance): residual, one cycle, w = K u, partials, state
+void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s);
+void launch_amg_init32(const PcgLaunch &a, const AmgLaunch<float> &g, hipStream_t s);
+// one CG iteration of parity `parity` (a chain of launches)
+void launch_amg_iter64(const PcgLaunch &a, const AmgLaunch<double> &g, int parity, hipStream_t s);
+void launch_amg_iter32(const PcgLaunch &a, const AmgLaunch<float> &g, int parity, hipStream_t s);
+// one cycle applied to the plain vector r (n_pot rows) into g.u
+void launch_amg_apply64(const PcgLaunch &a, const AmgLaunch<double> &g, const double *r, hipStream_t s);
+void launch_amg_apply32(const PcgLaunch &a, const AmgLaunch<float> &g, const float *r, hipStream_t s);
 
 // --- learned component (gnn.hip); widths fixed: 32 features, 64 channels ---
 void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float *W, int ldw, bool transW,

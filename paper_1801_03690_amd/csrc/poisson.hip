@@ -377,6 +377,24 @@ void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s) {
                                              s, view<float>(*a.K), M, a.v32, a.x32, a.invD32, a.st, parity, a.part))
 }
 
+void launch_pcg_residual_q(const PcgLaunch &a, const int *act, hipStream_t s) {
+    const RowMap &M = *a.M;
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<double>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part))
+}
+
+void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s) {
+    const RowMap &M = *a.M;
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_start32<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,
+                                             (const double *)a.r64, a.x32, a.v32.q[0]))
+}
+
+void launch_pcg_fin(const PcgLaunch &a, const int *act, double rtol2, int mode, hipStream_t s) {
+    const RowMap &M = *a.M;
+    hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, rtol2, mode,
+                       act, a.pin, a.st);
+}
+
 void launch_add_correction(const PcgLaunch &a, hipStream_t s) {
     const RowMap &M = *a.M;
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_add_correction<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,

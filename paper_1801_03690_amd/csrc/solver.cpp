@@ -78,7 +78,9 @@ void free_host_ctl(mm_ctx *c) {
 
 void free_all(mm_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (hipGraphExec_t *g : {&c->graph64, &c->graph32}) {
+    amg_release(c);
+    c->hostK = HostCsr();
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->agraph32}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -350,6 +352,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
             append_csr(C, as[i].C, moff[i], moff[i], 0);
             append_csr(S, as[i].S, moff[i], moff[i], 0);
             append_csr(K, as[i].K, poff[i], poff[i], 0);
+            if (ni == 1) c->hostK = as[i].K;  // kept for the multigrid hierarchy
             append_csr(B, as[i].B, boff[i], moff[i], poff[i]);
             append_csr(Bt, as[i].Bt, moff[i], poff[i], 0);
             as[i].C = HostCsr();
@@ -489,8 +492,15 @@ PcgLaunch pcg_args(mm_ctx *c) {
     return a;
 }
 
-void pcg_chunk(mm_ctx *c, bool fp32) {
+void pcg_chunk(mm_ctx *c, bool fp32, bool amg) {
     PcgLaunch a = pcg_args(c);
+    if (amg) {
+        for (int j = 0; j < kAmgChunk; ++j) {
+            if (fp32) launch_amg_iter32(a, amg_launch32(c->amg), j & 1, c->stream);
+            else launch_amg_iter64(a, amg_launch64(c->amg), j & 1, c->stream);
+        }
+        return;
+    }
     for (int j = 0; j < kPcgChunk; ++j) {
         if (fp32) launch_pcg_iter32(a, j & 1, c->stream);
         else launch_pcg_iter64(a, j & 1, c->stream);
@@ -505,14 +515,15 @@ bool use_graphs() {
     return on;
 }
 
-// capture kPcgChunk iterations (one kernel each) once per context and mode
-hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32) {
-    hipGraphExec_t &ge = fp32 ? c->graph32 : c->graph64;
+// capture one chunk of iterations once per context, precision and
+// preconditioner
+hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32, bool amg) {
+    hipGraphExec_t &ge = amg ? (fp32 ? c->agraph32 : c->agraph64) : (fp32 ? c->graph32 : c->graph64);
     if (ge) return ge;
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     try {
-        pcg_chunk(c, fp32);
+        pcg_chunk(c, fp32, amg);
     } catch (...) {
         (void)hipStreamEndCapture(c->stream, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -535,22 +546,24 @@ void pull_pcg(mm_ctx *c) {
 // batch of replays and the executed iterations (and their algorithmic bytes)
 // are counted per instance; replays after an instance converged return at once
 // and their time stays in the measurement.
-void pcg_replay(mm_ctx *c, bool fp32, long maxit, const std::vector<int> &on) {
-    hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32) : nullptr;
-    long expect = kPcgChunk;
+void pcg_replay(mm_ctx *c, bool fp32, bool amg, long maxit, const std::vector<int> &on) {
+    hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32, amg) : nullptr;
+    const long chunk = amg ? kAmgChunk : kPcgChunk;
+    long expect = chunk;
     for (int i : on) expect = std::max(expect, c->last_pcg[i]);
-    long nrep = (expect + kPcgChunk - 1) / kPcgChunk;
+    long nrep = (expect + chunk - 1) / chunk;
     long launched = 0;
     std::vector<int> seen(c->ninst, 0);
-    const std::vector<double> &bytes = fp32 ? c->pcg_bytes32 : c->pcg_bytes64;
+    std::vector<double> bytes = fp32 ? c->pcg_bytes32 : c->pcg_bytes64;
+    if (amg) bytes.assign(c->ninst, amg_bytes(c->amg, fp32));
     for (;;) {
         prof_mark(c);
         for (long k = 0; k < nrep; ++k) {
             if (ge) HIPCHK(hipGraphLaunch(ge, c->stream));
-            else pcg_chunk(c, fp32);
+            else pcg_chunk(c, fp32, amg);
         }
         prof_mark(c);
-        launched += nrep * kPcgChunk;
+        launched += nrep * chunk;
         pull_pcg(c);
         if (c->prof_on) {
             prof_harvest(c);
@@ -565,7 +578,7 @@ void pcg_replay(mm_ctx *c, bool fp32, long maxit, const std::vector<int> &on) {
         for (int i : on) all = all && (c->hpst[i].done || c->hpst[i].zero_u);
         if (all) break;
         if (launched >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
-        nrep = std::max<long>(1, (expect / 8 + kPcgChunk - 1) / kPcgChunk);
+        nrep = std::max<long>(1, (expect / 8 + chunk - 1) / chunk);
     }
 }
 
@@ -574,11 +587,12 @@ void zero_pot(mm_ctx *c, int i) {
 }
 
 // FP64 CG for the instances with act[i] set (uploaded); returns per-instance iterations
-std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
+std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, bool amg, const std::vector<int> &on) {
     std::vector<long> it(c->ninst, 0);
     PcgLaunch a = pcg_args(c);
-    launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, c->stream);
-    pcg_replay(c, false, maxit, on);
+    if (amg) launch_amg_init64(a, amg_launch64(c->amg), c->d_(c->act()), rtol * rtol, c->stream);
+    else launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, c->stream);
+    pcg_replay(c, false, amg, maxit, on);
     for (int i : on) {
         if (c->hpst[i].zero_u) {
             zero_pot(c, i);
@@ -590,7 +604,7 @@ std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, const std::ve
     return it;
 }
 
-std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
+std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, bool amg, const std::vector<int> &on) {
     std::vector<long> total(c->ninst, 0);
     PcgLaunch a = pcg_args(c);
     std::vector<int> live = on;
@@ -630,10 +644,11 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::ve
         live = inner;
         if (live.empty()) break;
         upload_ctl(c);
-        launch_pcg_init32(a, c->stream);
+        if (amg) launch_amg_init32(a, amg_launch32(c->amg), c->stream);
+        else launch_pcg_init32(a, c->stream);
         long cap = 0;
         for (int i : live) cap = std::max(cap, maxit - total[i]);
-        pcg_replay(c, true, cap, live);
+        pcg_replay(c, true, amg, cap, live);
         for (int i : live) {
             total[i] += c->hpst[i].iters;
             c->last_pcg[i] = std::max<long>(4, c->hpst[i].iters);
@@ -647,10 +662,11 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::ve
 }
 
 // solve for the instances in `on` (act[] uploaded with exactly these set)
-void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<int> &on) {
+void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std::vector<int> &on) {
     if (on.empty() || c->rows_p == 0) return;
+    if (amg) amg_get(c);  // first use: build the hierarchy (untimed, like the assembly)
     const double t0 = now_s();
-    std::vector<long> it = fp32 ? poisson_fp32(c, rtol, maxit, on) : poisson_fp64(c, rtol, maxit, on);
+    std::vector<long> it = fp32 ? poisson_fp32(c, rtol, maxit, amg, on) : poisson_fp64(c, rtol, maxit, amg, on);
     sync(c);
     const double dt = now_s() - t0;
     for (int i : on) {
@@ -666,7 +682,7 @@ void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, const std::vector<in
 // wave of instance i. Captured graphs hold the old map: they are dropped.
 void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
     sync(c);
-    for (hipGraphExec_t *g : {&c->graph64, &c->graph32}) {
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->agraph32}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -920,7 +936,7 @@ void eval_round(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool an
     const bool demag = (o.terms & MM_T_DEMAG) && c->rows_p > 0 && c->B.nrows > 0;
     if (demag) {
         launch_bmul(c->B, c->Mb.map, act, c->st, role, c->b, fp32, s);
-        poisson(c, o.poisson_rtol, o.poisson_maxit, fp32, on);
+        poisson(c, o.poisson_rtol, o.poisson_maxit, fp32, o.poisson_prec == MM_PREC_AMG, on);
     }
     EvalLaunch e;
     e.C = &c->C;
@@ -1444,6 +1460,7 @@ bool opts_valid(const mm_opts &o, std::string &why) {
     else if (o.stop_mode == MM_STOP_PAPER && !(o.tau_F > 0)) why = "tau_F <= 0";
     else if (o.poisson_maxit < 1) why = "poisson_maxit < 1";
     else if (o.ls_max_halvings < 0) why = "ls_max_halvings < 0";
+    else if (o.poisson_prec != MM_PREC_JACOBI && o.poisson_prec != MM_PREC_AMG) why = "unknown poisson_prec";
     else return true;
     return false;
 }
@@ -1523,6 +1540,7 @@ int mm_opts_default(mm_opts *o) {
     o->terms = MM_T_ALL;
     o->ls_max_halvings = 20;
     o->poisson_maxit = 100000;
+    o->poisson_prec = MM_PREC_JACOBI;
     return MM_OK;
 }
 
@@ -1947,7 +1965,8 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
         c->act()[0] = 1;
         upload_ctl(c);
         const long mi0 = c->cnt[0].mi;
-        poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK, {0});
+        poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK,
+                c->opts.poisson_prec == MM_PREC_AMG, {0});
         const long it = c->cnt[0].mi - mi0;
         copy_out(c, u_inout, c->u, np);
         // evaluations write only the magnet rows of b: clear it; restore u

@@ -1,0 +1,151 @@
+"""GPU: the multigrid-preconditioned scalar-potential CG against its oracle.
+
+The library builds its smoothed-aggregation hierarchy from its own assembled
+matrix, the oracle from its own: the aggregates must agree exactly on every
+level, the level operators and prolongators to round-off, one cycle in FP64
+to 1e-11 of its size (FP32 to 1e-5), and the multigrid-preconditioned solve
+to the solve tolerance, with iteration counts within one of the oracle's
+(the two CG forms differ only in rounding). Meshes span several SELL slices
+with a ragged last one; the 2x2x2 magnet has a single level.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.amg as M
+from paper_1801_03690_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not _gpu_available():
+        pytest.skip("no GPU")
+    from paper_1801_03690_amd import binding
+    return binding
+
+
+def setup(B, ncell, **mat):
+    mesh = inputs.small_box(ncell, 4.0, **mat)
+    ctx = B.Context(0).upload(mesh)
+    o = oracle.Oracle(mesh)
+    p, j, v = o.K_csr()
+    lv = M.hierarchy(M.Csr(p, j, v, o.np))
+    return mesh, ctx, o, lv
+
+
+def dense_of(ptr, col, val, ncols):
+    n = ptr.size - 1
+    d = np.zeros((n, ncols))
+    np.add.at(d, (np.repeat(np.arange(n), np.diff(ptr)), col), val)
+    return d
+
+
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (9, 8, 7)])
+def test_hierarchy_matches_oracle(B, ncell):
+    mesh, ctx, o, lv = setup(B, ncell)
+    info = ctx.amg_info()
+    print(ncell, info)
+    assert info["levels"] == len(lv) >= 3
+    assert info["rows"] == [L.A.n for L in lv]
+    for l in range(len(lv) - 1):
+        agg = ctx.amg_aggregates(l)
+        assert np.array_equal(agg, lv[l].agg), l
+        pa, ja, va = ctx.amg_level_matrix(l, 0)
+        Ad = dense_of(pa, ja, va, lv[l].A.n) if lv[l].A.n <= 6000 else None
+        if Ad is not None:
+            ref = lv[l].A.dense()
+            assert np.abs(Ad - ref).max() <= 1e-12 * np.abs(ref).max(), l
+        pp, jp, vp = ctx.amg_level_matrix(l, 1)
+        Pd = dense_of(pp, jp, vp, lv[l + 1].A.n)
+        ref = lv[l].P.dense()
+        assert np.abs(Pd - ref).max() <= 1e-12, l
+    ctx.close()
+
+
+def test_cycle_matches_oracle(B):
+    mesh, ctx, o, lv = setup(B, (9, 8, 7))
+    rng = np.random.default_rng(5)
+    for k in range(2):
+        r = rng.standard_normal(o.np)
+        z = M.vcycle(lv, r)
+        z64 = ctx.amg_apply(r, B.MM_FP64)
+        z32 = ctx.amg_apply(r, B.MM_FP32_BULK)
+        sc = np.abs(z).max()
+        assert np.abs(z64 - z).max() <= 1e-11 * sc
+        assert np.abs(z32 - z).max() <= 1e-5 * sc
+        # linear: the cycle of 2r is twice the cycle of r (FP64)
+        assert np.abs(ctx.amg_apply(2.0 * r, B.MM_FP64) - 2.0 * z64).max() <= 1e-14 * sc
+    ctx.close()
+
+
+def test_single_level_is_the_dense_inverse(B):
+    mesh, ctx, o, lv = setup(B, (2, 2, 2))
+    assert len(lv) == 1 and ctx.amg_info()["levels"] == 1
+    b = np.random.default_rng(6).standard_normal(o.np)
+    x = np.linalg.solve(lv[0].A.dense(), b)
+    assert np.abs(ctx.amg_apply(b) - x).max() <= 1e-11 * np.abs(x).max()
+    ctx.set_opts(poisson_prec=B.MM_PREC_AMG, poisson_rtol=1e-12)
+    u, it = ctx.poisson(b, rtol=1e-12)
+    assert it == 1
+    assert np.abs(u - x).max() <= 1e-10 * np.abs(x).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_amg_solve_matches_oracle(B, precision):
+    mesh, ctx, o, lv = setup(B, (9, 8, 7))
+    prec = B.MM_FP64 if precision == "fp64" else B.MM_FP32_BULK
+    ctx.set_opts(poisson_prec=B.MM_PREC_AMG, precision=prec)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(o.np)
+    xo, ito = M.solve(lv[0].A, b, rtol=1e-10, levels=lv)
+    u, it = ctx.poisson(b, rtol=1e-10)
+    xj, itj = o.poisson(b, rtol=1e-12)
+    print(precision, "amg iterations", it, "oracle", ito, "jacobi oracle", itj)
+    assert np.abs(u - xj).max() <= 1e-8 * np.abs(xj).max()
+    if precision == "fp64":
+        assert abs(it - ito) <= 1
+    # warm start at the answer: nothing to do
+    u2, it2 = ctx.poisson(b, u0=u, rtol=1e-8)
+    assert it2 == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_amg_curve_matches_jacobi_curve(B, precision):
+    """The preconditioner of the scalar-potential CG changes none of the
+    method's results beyond the solve tolerance."""
+    w = inputs.hard_cube(n=6, step_T=0.5, stop_T=-4.0)
+    ctx = B.Context(0).upload(w.mesh)
+    prec = B.MM_FP64 if precision == "fp64" else B.MM_FP32_BULK
+    rj = ctx.curve(w.m0, w.fields, opts=B.default_opts(jmax=10, precision=prec))
+    ctx.reset_warm_start()
+    ra = ctx.curve(w.m0, w.fields, opts=B.default_opts(jmax=10, precision=prec, poisson_prec=B.MM_PREC_AMG))
+    assert rj["rc"] == 0 and ra["rc"] == 0
+    dE = np.abs(ra["E"] - rj["E"]) / np.abs(rj["E"])
+    tol = 1e-8 if precision == "fp64" else 1e-5
+    print(precision, "max rel dE", dE.max(), "CG iterations jacobi", sum(s["mi"] for s in rj["stats"]),
+          "amg", sum(s["mi"] for s in ra["stats"]))
+    assert dE.max() <= tol
+    assert np.abs(ra["m_avg"] - rj["m_avg"]).max() <= 1e-5
+    assert sum(s["mi"] for s in ra["stats"]) < sum(s["mi"] for s in rj["stats"])
+    ctx.close()
+
+
+def test_amg_needs_a_single_instance(B):
+    ws = [inputs.small_box((3, 3, 3), 4.0), inputs.small_box((4, 3, 3), 4.0)]
+    ctx = B.Context(0)
+    ctx.upload_batch(ws)
+    with pytest.raises(B.MMError):
+        ctx.amg_info()
+    ctx.close()
