@@ -7,13 +7,16 @@ minimization run to max |m x h_eff| < 1e-6) of the hard-magnetic cube: edge
 1.61 T, K1 = 4.3 MJ/m^3, A = 7.7 pJ/m, easy axis z tilted 1 degree toward x,
 field along -z from 0 to -8 T in 0.05 T steps (161 values), jmax = 10, in the
 FP32-bulk mode (FP32 operators and Poisson CG, FP64 reductions, FP64
-magnetization). Inputs (mesh operators, the start state) are resident in HBM
-before the timed region; assembly is untimed, as in the paper.
+magnetization), the scalar-potential CG preconditioned by algebraic multigrid
+(as in the paper; --poisson-prec jacobi for the Jacobi-preconditioned CG).
+Inputs (mesh operators, the start state) are resident in HBM before the timed
+region; assembly and the multigrid set-up are untimed, as in the paper.
 
-Printed (one JSON line): time per curve, the dominant kernel's measured
-bandwidth against the HBM roofline (HIP events around its launches inside the
-timed region), the plain FP64 form's time for the same curve, and the CPU FP64
-oracle timed on a bounded sample of the same workload.
+Printed (one JSON line): time per curve, the measured bandwidth of the
+dominant work, one scalar-potential CG iteration, against the HBM roofline
+(HIP events around its launches inside the timed region), the plain FP64
+form's and the Jacobi-preconditioned form's times for the same curve, and the
+CPU FP64 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -27,21 +30,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_hard_cube_20_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "poisson.hip")
+# counter-measured traffic per CG iteration of the hard cube, by preconditioner:
+# (file, kernel source it was measured on)
+TRAFFIC = {
+    "jacobi": (os.path.join(ROOT, "profiles", "pcg_hard_cube_20_traffic.txt"),
+               os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "poisson.hip")),
+    "amg": (os.path.join(ROOT, "profiles", "amg_hard_cube_20_traffic.txt"),
+            os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "amg.hip")),
+}
+# preconditioner of the scalar-potential CG per workload when --poisson-prec auto:
+# multigrid where it is faster (measured), Jacobi on the thin film (a few dozen
+# Jacobi iterations per solve) and in batches (multigrid is single-instance)
+AUTO_PREC = {"hard_cube": "amg", "polycrystal": "amg", "film": "jacobi", "batch64": "jacobi"}
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, pprec):
     """Counter-measured bytes per CG iteration, if taken on the current kernel source."""
     import hashlib
+    path, src = TRAFFIC[pprec]
     try:
-        kv = dict(line.split(None, 1) for line in open(TRAFFIC_FILE) if line.strip() and not line.startswith("#"))
-        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        kv = dict(line.split(None, 1) for line in open(path) if line.strip() and not line.startswith("#"))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
     if kv.get("source_sha256_prefix", "").strip() != h or kv.get("precision", "").strip() != precision:
         return None
     return float(kv["traffic_bytes_per_iteration"])
+
+
+def cg_kernel_label(pprec, fp32):
+    t = "<float>" if fp32 else "<double>"
+    if pprec == "jacobi":
+        return "scalar-potential CG iteration: k_pcg_iter" + t
+    return ("one scalar-potential CG iteration with its multigrid cycle" + t + ": k_amg_iter, k_amg_spmv "
+            "(restriction, fused coarse-level operators), k_amg_dense, k_amg_prolong, k_amg_post0, k_amg_w")
 
 
 def tune(ctx, binding, args):
@@ -70,10 +92,17 @@ def main():
                     help="hard_cube: one 20^3 grain (default); batch64: 64 uneven grains in shared launches; "
                          "film: the 1000 x 1000 x 10 nm soft film, plain FP64 against learned + FP32; "
                          "polycrystal: the 200 nm, 96^3-cell, 27-grain magnet (use --fields to bound it)")
+    ap.add_argument("--poisson-prec", choices=["auto", "jacobi", "amg"], default="auto",
+                    help="preconditioner of the scalar-potential CG (amg: smoothed-aggregation multigrid; "
+                         "auto: the faster one for the workload)")
+    ap.add_argument("--no-jacobi", action="store_true",
+                    help="skip the Jacobi-preconditioned comparison curve of the multigrid headline")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain copy kernel of known size (for scaling HBM counters)")
     args = ap.parse_args()
 
+    if args.poisson_prec == "auto":
+        args.poisson_prec = AUTO_PREC[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -118,8 +147,12 @@ def main():
           file=sys.stderr, flush=True)
     m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
     m = torch.empty_like(m0)
-    opts = binding.default_opts(jmax=w.jmax, precision=prec)
+    pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
+    opts = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=pprec)
     ctx.set_opts(opts)
+    if pprec == binding.MM_PREC_AMG:
+        amg = ctx.amg_info()
+        print(f"# multigrid levels {amg['rows']} built in {amg['setup_seconds']:.2f}s", file=sys.stderr, flush=True)
     # block shape of the scalar-potential kernels: timed once here, untimed
     # like the assembly, and fixed for the run
     shape = (16, [1])
@@ -175,18 +208,19 @@ def main():
                                 f"polycrystal 200 nm, 96^3 cells x6 tets + 3x air box, 27 Voronoi grains with a "
                                 f"2 nm boundary phase, first {len(fields)} of {len(w.fields)} fields "
                                 f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6"),
-                   "precision": args.precision, "n_mag": info["n_mag"], "n_pot": info["n_pot"],
+                   "precision": args.precision, "poisson_preconditioner": args.poisson_prec,
+                   "n_mag": info["n_mag"], "n_pot": info["n_pot"],
                    "nnz_K": info["nnz_K"], "pcg_waves_per_block": shape[0], "pcg_slices_per_wave": shape[1][0]},
         "counters": dict(tot, worst_status=worst),
         "roofline": {
             "bound": "hbm",
-            "kernel": ("scalar-potential CG iteration: k_pcg_iter"
-                       + ("<float>" if prec == binding.MM_FP32_BULK else "<double>")),
+            "kernel": cg_kernel_label(args.poisson_prec, prec == binding.MM_FP32_BULK),
             "achieved": None if achieved is None else round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.precision),
+            "traffic": (measured_traffic(args.precision, args.poisson_prec) if args.workload == "hard_cube"
+                        else None),
             "avg_iteration_us": round(1e6 * avg_iter, 3),
             "iterations": prof["iterations"],
             "bytes_per_iteration": prof["bytes_per_iteration"],
@@ -194,7 +228,7 @@ def main():
     }
 
     if not args.no_plain and prec != binding.MM_FP64:
-        o64 = binding.default_opts(jmax=w.jmax, precision=binding.MM_FP64)
+        o64 = binding.default_opts(jmax=w.jmax, precision=binding.MM_FP64, poisson_prec=pprec)
         ctx.set_opts(o64)
         if not args.no_tune:
             tune(ctx, binding, args)
@@ -211,6 +245,36 @@ def main():
                              "nli": int(sum(s["nli"] for s in rp["stats"])),
                              "max_rel_dE_vs_fp32": dE, "max_dmavg_vs_fp32": dmav}
         print(f"# plain fp64 curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
+
+    if args.poisson_prec == "amg" and not args.no_jacobi:
+        # the same curve with the Jacobi-preconditioned CG (one kernel per iteration)
+        oj = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=binding.MM_PREC_JACOBI)
+        ctx.set_opts(oj)
+        if not args.no_tune:
+            tune(ctx, binding, args)
+        torch.cuda.synchronize()
+        ctx.profile(-1)
+        ctx.profile(1)
+        ta = time.perf_counter()
+        rj = one_curve(oj)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        pj = ctx.profile(0)
+        ctx.set_opts(opts)
+        itj = pj["seconds"] / max(pj["iterations"], 1)
+        achj = pj["bytes_per_iteration"] / itj / 1e9 if pj["iterations"] else None
+        out["jacobi_cg"] = {
+            "seconds": round(tb - ta, 4), "cg_iterations": int(sum(s["mi"] for s in rj["stats"])),
+            "max_rel_dE_vs_amg": float(np.max(np.abs(rj["E"] - r["E"]) / np.maximum(np.abs(r["E"]), 1.0))),
+            "roofline": {"bound": "hbm", "kernel": cg_kernel_label("jacobi", prec == binding.MM_FP32_BULK),
+                         "achieved": None if achj is None else round(achj, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": None if achj is None else round(achj / HBM_PEAK_GBS, 4),
+                         "traffic": (measured_traffic(args.precision, "jacobi") if args.workload == "hard_cube"
+                                     else None),
+                         "avg_iteration_us": round(1e6 * itj, 3), "iterations": pj["iterations"],
+                         "bytes_per_iteration": pj["bytes_per_iteration"]},
+        }
+        print(f"# jacobi-preconditioned curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
 
     if not args.no_learned:
         out["learned_film"] = bench_learned(args, binding, inputs, np, torch)
@@ -306,9 +370,10 @@ def bench_film(args):
     net = learn.load_net(os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_large.npz"), ctx)
     legs = (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
             ("learned_fp32", 3, binding.MM_FP32_BULK))
+    pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     res, shapes, prof = {}, {}, None
     for name, mode, prec in legs:
-        o = binding.default_opts(jmax=w.jmax, precision=prec)
+        o = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=pprec)
         ctx.set_opts(o)
         if not args.no_tune:
             nw, spw = tune(ctx, binding, args)
@@ -350,12 +415,15 @@ def bench_film(args):
         "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, "
                                f"{len(fields)} fields +50..{1e3 * fields[-1][0]:.0f} mT along x, jmax 4, tol 1e-6, "
                                f"learned start + scaling, FP32 bulk",
-                   "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
+                   "poisson_preconditioner": args.poisson_prec, "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
                    "pcg_shapes": shapes},
         "forms": res,
         "speedup_learned_fp32_vs_plain_fp64": round(res["plain_fp64"]["seconds"] / sec, 3),
         "roofline": {
-            "bound": "hbm", "kernel": "scalar-potential CG iteration: k_pcg_iter<float> (learned_fp32 form)",
+            "bound": "hbm", "kernel": ("scalar-potential CG iteration: k_pcg_iter<float> (learned_fp32 form)"
+                                       if args.poisson_prec == "jacobi" else
+                                       "scalar-potential CG iteration with one multigrid cycle<float> "
+                                       "(learned_fp32 form)"),
             "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_iteration_us": round(1e6 * avg_iter, 3), "iterations": prof["iterations"],

@@ -254,7 +254,7 @@ std::vector<double> spd_inverse(const Csr &A) {
 }
 
 struct HostLevel {
-    Csr A, P, R;
+    Csr A, P, R, AP;
     std::vector<double> d;
     double rho = 0, omega = 0, theta = 0;
     std::vector<int> agg;
@@ -286,6 +286,14 @@ T *upload_v(mm_ctx *c, const std::vector<T> &v) {
 }
 
 std::vector<float> to32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+
+// lanes per row: the power of two at or above the mean row length, 4..64
+int lanes_for(const Csr &a) {
+    const double mean = a.n > 0 ? (double)a.nnz() / a.n : 1.0;
+    int g = 4;
+    while (g < 64 && g < mean) g *= 2;
+    return g;
+}
 
 std::vector<int> ptr32(const Csr &a) {
     if (a.nnz() > 0x7fffffffLL) throw ApiError{MM_ENOMEM, "multigrid: a level has more than 2^31 entries"};
@@ -341,7 +349,8 @@ AmgState *amg_get(mm_ctx *c) {
         }
         L.P = smoothed_prolongator(A, L.d, L.agg, na, L.omega);
         L.R = transpose(L.P);
-        Csr Ac = spmm(L.R, spmm(A, L.P));
+        L.AP = spmm(A, L.P);
+        Csr Ac = spmm(L.R, L.AP);
         L.A = std::move(A);
         S->lv.push_back(std::move(L));
         A = std::move(Ac);
@@ -349,9 +358,16 @@ AmgState *amg_get(mm_ctx *c) {
     }
     // device copies
     const int nl = (int)S->lv.size();
+    const int L = nl - 1;
     S->g64.nlev = S->g32.nlev = nl;
     const size_t RP = std::max(c->rows_p, 1);
     double b64 = 0, b32 = 0;
+    auto vec2 = [&](size_t n, double **d, float **f) {
+        *d = dalloc_n<double>(c, std::max<size_t>(n, 1));
+        *f = dalloc_n<float>(c, std::max<size_t>(n, 1));
+        HIPCHK(hipMemsetAsync(*d, 0, std::max<size_t>(n, 1) * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(*f, 0, std::max<size_t>(n, 1) * sizeof(float), c->stream));
+    };
     for (int l = 0; l < nl; ++l) {
         HostLevel &H = S->lv[l];
         AmgLevel<double> &D = S->g64.lv[l];
@@ -359,47 +375,106 @@ AmgState *amg_get(mm_ctx *c) {
         D.n = F.n = H.A.n;
         D.omega = H.omega;
         F.omega = (float)H.omega;
-        if (l > 0) up_csr(c, H.A, &D.Ap, &D.Aj, &D.Av, &F.Ap, &F.Aj, &F.Av);
-        std::vector<double> dinv(H.A.n);
-        for (int i = 0; i < H.A.n; ++i) dinv[i] = 1.0 / H.d[i];
+        const double n = (double)H.A.n, nA = (double)(l == 0 ? c->inst[0].nnz_K : H.A.nnz());
         if (l == 0) {
             D.dinv = c->invDK;
             F.dinv = c->invDK32;
-        } else {
-            D.dinv = upload_v(c, dinv);
-            F.dinv = upload_v(c, to32(dinv));
+            vec2(RP, &D.t, &F.t);
+            vec2(RP, &D.z, &F.z);
+            vec2(RP, &D.b, &F.b);  // staging of mm_amg_apply
+            vec2(RP, &D.y, &F.y);
+            if (l < L) {
+                up_csr(c, H.P, &D.Pp, &D.Pj, &D.Pv, &F.Pp, &F.Pj, &F.Pv);
+                up_csr(c, H.R, &D.Rp, &D.Rj, &D.Rv, &F.Rp, &F.Rj, &F.Rv);
+                D.gP = F.gP = lanes_for(H.P);
+                D.gR = F.gR = lanes_for(H.R);
+            }
+        } else if (l < L) {
+            // Q = P - omega D^-1 (A P); down = Q^T; up = [S | Q] with S =
+            // 2 omega D^-1 - omega^2 D^-1 A D^-1
+            const double w = H.omega;
+            Csr Q;
+            Q.n = H.P.n;
+            Q.ncols = H.P.ncols;
+            Q.p.assign(Q.n + 1, 0);
+            for (int i = 0; i < Q.n; ++i) {
+                int64_t e = H.P.p[i], f = H.AP.p[i];
+                const int64_t e1 = H.P.p[i + 1], f1 = H.AP.p[i + 1];
+                while (e < e1 || f < f1) {
+                    const int ce = e < e1 ? H.P.j[e] : 0x7fffffff, cf = f < f1 ? H.AP.j[f] : 0x7fffffff;
+                    const int col = std::min(ce, cf);
+                    double v = 0.0;
+                    if (ce == col) v += H.P.v[e++];
+                    if (cf == col) v -= w * H.AP.v[f++] / H.d[i];
+                    if (v != 0.0) {
+                        Q.j.push_back(col);
+                        Q.v.push_back(v);
+                    }
+                }
+                Q.p[i + 1] = (int64_t)Q.j.size();
+            }
+            const Csr Dn = transpose(Q);
+            Csr U;
+            U.n = H.A.n;
+            U.ncols = H.A.n + Q.ncols;
+            U.p.assign(U.n + 1, 0);
+            for (int i = 0; i < U.n; ++i) {
+                for (int64_t e = H.A.p[i]; e < H.A.p[i + 1]; ++e) {
+                    const int j = H.A.j[e];
+                    double v = -(w * w) * H.A.v[e] / (H.d[i] * H.d[j]);
+                    if (j == i) v += 2.0 * w / H.d[i];
+                    if (v != 0.0) {
+                        U.j.push_back(j);
+                        U.v.push_back(v);
+                    }
+                }
+                for (int64_t e = Q.p[i]; e < Q.p[i + 1]; ++e) {
+                    U.j.push_back(H.A.n + Q.j[e]);
+                    U.v.push_back(Q.v[e]);
+                }
+                U.p[i + 1] = (int64_t)U.j.size();
+            }
+            up_csr(c, Dn, &D.Dp, &D.Dj, &D.Dv, &F.Dp, &F.Dj, &F.Dv);
+            up_csr(c, U, &D.Up, &D.Uj, &D.Uv, &F.Up, &F.Uj, &F.Uv);
+            D.gD = F.gD = lanes_for(Dn);
+            D.gU = F.gU = lanes_for(U);
+            // [b_l; y_{l+1}] in one array
+            const size_t nb = (size_t)H.A.n + S->lv[l + 1].A.n;
+            double *d64;
+            float *d32;
+            vec2(nb, &d64, &d32);
+            D.b = d64;
+            F.b = d32;
+            S->g64.lv[l + 1].y = d64 + H.A.n;
+            S->g32.lv[l + 1].y = d32 + H.A.n;
+            if (l == 1) vec2((size_t)H.A.n, &D.y, &F.y);
+            for (int k = 0; k < 2; ++k) {
+                const double v = k ? 4.0 : 8.0;
+                (k ? b32 : b64) += (double)(Dn.nnz() + U.nnz()) * (v + 4) + 3.0 * n * v;
+            }
         }
-        if (!H.P.p.empty()) {
-            up_csr(c, H.P, &D.Pp, &D.Pj, &D.Pv, &F.Pp, &F.Pj, &F.Pv);
-            up_csr(c, H.R, &D.Rp, &D.Rj, &D.Rv, &F.Rp, &F.Rj, &F.Rv);
-        }
-        if (!H.Ainv.empty()) {
+        if (l == L) {
             D.Ainv = upload_v(c, H.Ainv);
             F.Ainv = upload_v(c, to32(H.Ainv));
+            if (l > 0) {
+                vec2((size_t)H.A.n, &D.b, &F.b);
+                if (l == 1) vec2((size_t)H.A.n, &D.y, &F.y);
+            }
+            for (int k = 0; k < 2; ++k) {
+                const double v = k ? 4.0 : 8.0;
+                (k ? b32 : b64) += n * n * v + 2.0 * n * v;
+            }
         }
-        const size_t nv = (l == 0) ? RP : (size_t)std::max(H.A.n, 1);
-        for (double **v : {&D.b, &D.t, &D.z, &D.y}) {
-            *v = dalloc_n<double>(c, nv);
-            HIPCHK(hipMemsetAsync(*v, 0, nv * sizeof(double), c->stream));
+        if (l == 0 && l < L) {
+            // fine level: K three times (the iteration, the post-smoothing,
+            // w = K u), R and P once each, and 17 vector passes
+            const double nP = (double)H.P.nnz();
+            for (int k = 0; k < 2; ++k) {
+                const double v = k ? 4.0 : 8.0;
+                (k ? b32 : b64) += 3.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 17.0 * n * v;
+            }
         }
-        for (float **v : {&F.b, &F.t, &F.z, &F.y}) {
-            *v = dalloc_n<float>(c, nv);
-            HIPCHK(hipMemsetAsync(*v, 0, nv * sizeof(float), c->stream));
-        }
-        // algorithmic bytes of one CG iteration, per level: the fine level
-        // reads K three times (iteration, post-smoothing, w = K u) and P
-        // twice; a coarse level reads A twice and P, R once each; vector
-        // passes as counted below; the coarsest reads its dense inverse
-        const double nA = (double)(l == 0 ? c->inst[0].nnz_K : H.A.nnz()), nP = (double)H.P.nnz();
-        const double n = (double)H.A.n;
-        for (int k = 0; k < 2; ++k) {
-            const double v = k ? 4.0 : 8.0;
-            double by;
-            if (!H.Ainv.empty() && l > 0) by = n * n * v + 2.0 * n * v;
-            else if (l == 0) by = 3.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 17.0 * n * v;
-            else by = 2.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 9.0 * n * v;
-            (k ? b32 : b64) += by;
-        }
+        H.AP = Csr();
     }
     S->g64.u = dalloc_n<double>(c, RP);
     S->g32.u = dalloc_n<float>(c, RP);

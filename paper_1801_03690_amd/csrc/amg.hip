@@ -13,10 +13,11 @@
 //                  the fine pre-smoothing t = r - omega K D^-1 r: K D^-1 r of
 //                  the new r is formed from the previous r, w, s records of
 //                  the neighbours as in the Jacobi path (no extra pass);
-//   per level l    restriction b_{l+1} = P_l^T t_l, coarse pre-smoothing
-//                  t = b - A omega D^-1 b, ..., dense solve on the coarsest
-//                  level, prolongation z = omega D^-1 b + P y and
-//                  post-smoothing y = z + omega D^-1 (b - A z) on the way up;
+//   coarse levels  restriction b_1 = P_0^T t_0; on each coarse level one
+//                  sparse product down (pre-smoothing and restriction
+//                  multiplied out) and one up (both smoothing sweeps and the
+//                  coarse correction); a dense solve on the coarsest level;
+//                  the prolongation z = omega D^-1 r + P_0 y_1;
 //   k_amg_post0    u = z + omega D^-1 (r - K z) on the fine level, partial
 //                  gamma;
 //   k_amg_w        w = K u, the whole record {r, w, s, D^-1} rewritten,
@@ -55,13 +56,15 @@ __device__ __forceinline__ VT csr_row(const int *__restrict__ p, const int *__re
                                       const VT *__restrict__ v, const VT *__restrict__ x, int row, int gl) {
     VT acc = 0;
     const int e1 = p[row + 1];
+#pragma unroll 2
     for (int e = p[row] + gl; e < e1; e += GL) acc += v[e] * x[j[e]];
     return group_sum<GL>(acc);
 }
 
-// y = R x (restriction; GL lanes per row of R)
+// y = A x for a CSR matrix (the fine restriction R, and the fused down and up
+// operators of the coarse levels; GL lanes per row)
 template <class VT, int GL>
-__global__ __launch_bounds__(kAB) void k_amg_restrict(int n, const int *__restrict__ p, const int *__restrict__ j,
+__global__ __launch_bounds__(kAB) void k_amg_spmv(int n, const int *__restrict__ p, const int *__restrict__ j,
                                                       const VT *__restrict__ v, const VT *__restrict__ x,
                                                       VT *__restrict__ y, const int *done) {
     if (skip(done)) return;
@@ -69,24 +72,6 @@ __global__ __launch_bounds__(kAB) void k_amg_restrict(int n, const int *__restri
     if (row >= n) return;
     const VT s = csr_row<GL>(p, j, v, x, row, gl);
     if (gl == 0) y[row] = s;
-}
-
-// t = b - A (omega D^-1 b) (pre-smoothing from zero, then its residual)
-template <class VT, int GL>
-__global__ __launch_bounds__(kAB) void k_amg_pre(int n, const int *__restrict__ p, const int *__restrict__ j,
-                                                 const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
-                                                 const VT *__restrict__ b, VT *__restrict__ t, const int *done) {
-    if (skip(done)) return;
-    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
-    if (row >= n) return;
-    VT acc = 0;
-    const int e1 = p[row + 1];
-    for (int e = p[row] + gl; e < e1; e += GL) {
-        const int c = j[e];
-        acc += v[e] * (dinv[c] * b[c]);
-    }
-    acc = group_sum<GL>(acc);
-    if (gl == 0) t[row] = b[row] - omega * acc;
 }
 
 // z = omega D^-1 b + P y (b at b[row * bs]: bs = 4 for the r field of the
@@ -103,19 +88,6 @@ __global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restric
     if (gl == 0) z[row] = omega * dinv[row] * b[(int64_t)row * bs] + s;
 }
 
-// y = z + omega D^-1 (b - A z) (post-smoothing)
-template <class VT, int GL>
-__global__ __launch_bounds__(kAB) void k_amg_post(int n, const int *__restrict__ p, const int *__restrict__ j,
-                                                  const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
-                                                  const VT *__restrict__ b, const VT *__restrict__ z,
-                                                  VT *__restrict__ y, const int *done) {
-    if (skip(done)) return;
-    const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
-    if (row >= n) return;
-    const VT s = csr_row<GL>(p, j, v, z, row, gl);
-    if (gl == 0) y[row] = z[row] + omega * dinv[row] * (b[row] - s);
-}
-
 // y = Ainv b on the coarsest level: one wave per row of the dense inverse
 template <class VT>
 __global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__ Ainv, const VT *__restrict__ b,
@@ -130,6 +102,37 @@ __global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__
     if (ln == 0) y[row] = acc;
 }
 
+// one SELL row of K times x (and optionally times y entrywise: sum K_ac y_c
+// x_c) with G column/value loads and gathers in flight per lane; entries past
+// the slice's width stand in as the slice's first row with value 0
+template <class MT, class VT, bool TWO>
+__device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const VT *__restrict__ x, int xs,
+                                         const VT *__restrict__ y) {
+    constexpr int G = sizeof(VT) == 4 ? 8 : 4;
+    const int64_t base = K.sptr[s];
+    const int wd = (int)((K.sptr[s + 1] - base) >> 6);
+    VT acc = 0;
+    for (int k0 = 0; k0 < wd; k0 += G) {
+        int cc[G];
+        VT vv[G], xv[G], yv[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const bool in = k0 + k < wd;
+            const int64_t e = base + 64 * (k0 + k) + ln;
+            cc[k] = in ? K.col[e] : s * 64;
+            vv[k] = in ? (VT)K.val[e] : (VT)0;
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            xv[k] = x[(int64_t)cc[k] * xs];
+            if (TWO) yv[k] = y[cc[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) acc += TWO ? vv[k] * (yv[k] * xv[k]) : vv[k] * xv[k];
+    }
+    return acc;
+}
+
 // fine level, start of a cycle from a residual that is not produced by
 // k_amg_iter (the CG start, or a plain vector): t = r - omega K D^-1 r with r
 // at r[row * rs]. With q given (the CG start), also sets w = s = 0 and d =
@@ -142,14 +145,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
     if (tl.inst < 0) return;
     const int rend = M.rend[tl.inst], ln = lane_id();
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const int64_t base = K.sptr[s];
-        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
-        VT acc = 0;
-        for (int k = 0; k < wd; ++k) {
-            const int64_t e = base + 64 * k + ln;
-            const int c = K.col[e];
-            acc += (VT)K.val[e] * (invD[c] * r[(int64_t)c * rs]);
-        }
+        const VT acc = row_gather<MT, VT, true>(K, s, ln, r, rs, invD);
         const int row = s * 64 + ln;
         if (row < rend) {
             t[row] = r[(int64_t)row * rs] - omega * acc;
@@ -175,13 +171,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[1] = {0};
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const int64_t base = K.sptr[s];
-        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
-        VT kz = 0;
-        for (int k = 0; k < wd; ++k) {
-            const int64_t e = base + 64 * k + ln;
-            kz += (VT)K.val[e] * z[K.col[e]];
-        }
+        const VT kz = row_gather<MT, VT, false>(K, s, ln, z, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
             const VT ri = r[(int64_t)row * rs];
@@ -205,13 +195,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[2] = {0, 0};
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const int64_t base = K.sptr[s];
-        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
-        VT ku = 0;
-        for (int k = 0; k < wd; ++k) {
-            const int64_t e = base + 64 * k + ln;
-            ku += (VT)K.val[e] * u[K.col[e]];
-        }
+        const VT ku = row_gather<MT, VT, false>(K, s, ln, u, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
             PcgNode<VT> me = q[row];
@@ -339,6 +323,31 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
         } break;                            \
     }
 
+// lanes per row of a CSR kernel: chosen per matrix from its mean row length
+#define MMNCG_GL_SWITCH(gl, ...)            \
+    switch (gl) {                           \
+        case 4: {                           \
+            constexpr int GL = 4;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 8: {                           \
+            constexpr int GL = 8;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 16: {                          \
+            constexpr int GL = 16;          \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 32: {                          \
+            constexpr int GL = 32;          \
+            __VA_ARGS__;                    \
+        } break;                            \
+        default: {                          \
+            constexpr int GL = 64;          \
+            __VA_ARGS__;                    \
+        } break;                            \
+    }
+
 namespace {
 
 template <int GL>
@@ -347,40 +356,31 @@ dim3 grid_rows(int n) {
     return dim3((unsigned)((th + kAB - 1) / kAB));
 }
 
-// the cycle below the fine level: restriction of t0, levels 1..L, and the
+// the cycle below the fine level: restriction of t0, the fused operators of
+// levels 1..L-1 down, the dense solve, the fused operators up, and the
 // prolongation back to z0 (r0 at r[row * rs])
 template <class VT>
 void coarse_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, hipStream_t s) {
     const int L = g.nlev - 1;
-    const AmgLevel<VT> &f = g.lv[0];
-    // down
-    for (int l = 0; l < L; ++l) {
+    const AmgLevel<VT> &f = g.lv[0], &c1 = g.lv[1];
+    MMNCG_GL_SWITCH(f.gR, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c1.n), dim3(kAB), 0, s, c1.n, f.Rp,
+                                             f.Rj, f.Rv, (const VT *)f.t, c1.b, done))
+    for (int l = 1; l < L; ++l) {
         const AmgLevel<VT> &a = g.lv[l], &c = g.lv[l + 1];
-        const VT *tl = a.t;
-        if (c.n > 0)
-            hipLaunchKernelGGL((k_amg_restrict<VT, 8>), grid_rows<8>(c.n), dim3(kAB), 0, s, c.n, a.Rp, a.Rj, a.Rv,
-                               tl, c.b, done);
-        if (l + 1 < L && c.n > 0)
-            hipLaunchKernelGGL((k_amg_pre<VT, 8>), grid_rows<8>(c.n), dim3(kAB), 0, s, c.n, c.Ap, c.Aj, c.Av,
-                               c.dinv, c.omega, (const VT *)c.b, c.t, done);
+        MMNCG_GL_SWITCH(a.gD, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c.n), dim3(kAB), 0, s, c.n,
+                                                 a.Dp, a.Dj, a.Dv, (const VT *)a.b, c.b, done))
     }
     const AmgLevel<VT> &cl = g.lv[L];
-    if (cl.n > 0)
-        hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
-                           cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
-    // up
-    for (int l = L - 1; l >= 0; --l) {
-        const AmgLevel<VT> &a = g.lv[l], &c = g.lv[l + 1];
-        if (l == 0) {
-            hipLaunchKernelGGL((k_amg_prolong<VT, 4>), grid_rows<4>(f.n), dim3(kAB), 0, s, f.n, f.Pp, f.Pj, f.Pv,
-                               f.dinv, f.omega, r, rs, (const VT *)c.y, f.z, done);
-        } else if (a.n > 0) {
-            hipLaunchKernelGGL((k_amg_prolong<VT, 4>), grid_rows<4>(a.n), dim3(kAB), 0, s, a.n, a.Pp, a.Pj, a.Pv,
-                               a.dinv, a.omega, (const VT *)a.b, 1, (const VT *)c.y, a.z, done);
-            hipLaunchKernelGGL((k_amg_post<VT, 8>), grid_rows<8>(a.n), dim3(kAB), 0, s, a.n, a.Ap, a.Aj, a.Av,
-                               a.dinv, a.omega, (const VT *)a.b, (const VT *)a.z, a.y, done);
-        }
+    hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
+                       cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
+    for (int l = L - 1; l >= 1; --l) {
+        const AmgLevel<VT> &a = g.lv[l];
+        // [b_l; y_{l+1}] is one array starting at b_l
+        MMNCG_GL_SWITCH(a.gU, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(a.n), dim3(kAB), 0, s, a.n,
+                                                 a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, done))
     }
+    MMNCG_GL_SWITCH(f.gP, hipLaunchKernelGGL((k_amg_prolong<VT, GL>), grid_rows<GL>(f.n), dim3(kAB), 0, s, f.n, f.Pp,
+                                             f.Pj, f.Pv, f.dinv, f.omega, r, rs, (const VT *)c1.y, f.z, done))
 }
 
 // everything between the fine pre-smoothing and the fine post-smoothing:

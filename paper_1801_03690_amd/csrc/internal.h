@@ -195,25 +195,32 @@ void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s);
 void launch_pcg_fin(const PcgLaunch &a, const int *act, double rtol2, int mode, hipStream_t s);
 
 // --- algebraic multigrid preconditioner of the scalar-potential CG (amg.hip) ---
-// Level l of the smoothed-aggregation hierarchy (device pointers). Level 0 is
-// the scalar-potential matrix itself (the SELL matrix K of the CG); levels
-// >= 1 hold their Galerkin operator A as CSR. P maps the next level's
-// vectors to this level's rows (CSR, rows of this level), R = P^T (rows of
-// the next level). The coarsest level holds its dense inverse (row-major).
+// Level l of the smoothed-aggregation hierarchy (device pointers). Level 0
+// is the scalar-potential matrix itself (the SELL matrix K of the CG), with
+// P (prolongation from level 1, CSR over the rows of level 0) and R = P^T.
+// A level 0 < l < L (L the coarsest) carries its cycle as two fused
+// operators: down, b_{l+1} = Dn b_l with Dn = P^T (I - omega A D^-1); up,
+// y_l = Up [b_l; y_{l+1}] with Up = [S | Q], S = 2 omega D^-1 - omega^2
+// D^-1 A D^-1, Q = (I - omega D^-1 A) P (the two damped-Jacobi sweeps and
+// the coarse correction of a V(1,1) cycle, multiplied out). b_l and y_{l+1}
+// are adjacent in memory. The coarsest level holds its dense inverse.
 constexpr int kAmgMaxLevels = 12;
 template <class VT>
 struct AmgLevel {
     int n = 0;
-    const int *Ap = nullptr, *Aj = nullptr;
-    const VT *Av = nullptr;
-    const VT *dinv = nullptr;  // 1 / a_ii
+    const VT *dinv = nullptr;  // 1 / a_ii (level 0)
     VT omega = 0;              // damped-Jacobi weight
-    const int *Pp = nullptr, *Pj = nullptr;
+    const int *Pp = nullptr, *Pj = nullptr;  // level 0
     const VT *Pv = nullptr;
     const int *Rp = nullptr, *Rj = nullptr;
     const VT *Rv = nullptr;
-    const VT *Ainv = nullptr;
+    const int *Dp = nullptr, *Dj = nullptr;  // 0 < l < L
+    const VT *Dv = nullptr;
+    const int *Up = nullptr, *Uj = nullptr;
+    const VT *Uv = nullptr;
+    const VT *Ainv = nullptr;  // l = L
     VT *b = nullptr, *t = nullptr, *z = nullptr, *y = nullptr;  // work vectors
+    int gP = 4, gR = 8, gD = 8, gU = 8;  // lanes per row of the CSR kernels (4..64)
 };
 template <class VT>
 struct AmgLaunch {
