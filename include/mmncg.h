@@ -83,7 +83,11 @@ typedef struct {
     double c1, c2;         /* sufficient-decrease and curvature constants */
     double poisson_rtol;   /* scalar-potential CG: stop at |r| <= rtol |b| */
     long max_nli;          /* nonlinear iteration cap per field value */
-    int precision;         /* MM_FP64 or MM_FP32_BULK */
+    int precision;         /* MM_FP64 or MM_FP32_BULK: FP32-stored operators; the
+                              scalar potential by FP32 CG inside FP64 defect
+                              correction (Jacobi), or by FP64 CG vectors on the
+                              FP32-stored matrix with an FP32 multigrid cycle
+                              (multigrid); FP64 reductions and master m */
     int terms;             /* energy terms, MM_T_* bitmask */
     int ls_max_halvings;   /* line-search backtracking cap */
     long poisson_maxit;    /* scalar-potential CG iteration cap per solve */
@@ -198,17 +202,19 @@ int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out);
 int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters);
 
 /* Measurement hook. enable = 1 times the scalar-potential CG iterations (the
-   dominant work of an evaluation: kernel A, q = K p with the direction update,
-   and kernel B, the solution/residual update) with HIP events on the
-   context's stream around every batch of iterations (the iterations run as
-   replays of a captured graph); enable = 0 stops; enable = -1 resets the
-   counters. out (may be NULL) receives {instance-iterations executed,
-   seconds, algorithmic bytes of those iterations, potential rows of all
-   instances}. Algorithmic bytes of one iteration of an instance: its stored
-   matrix (values + column indices, no padding) plus the vector traffic of the
-   two kernels (kernel A: read r, D^-1, old direction, write new direction and
-   K p; kernel B: read x, r, p, q, D^-1, write x and r), 8-byte values in the
-   FP64 mode and 4-byte values in the FP32 inner solves. */
+   dominant work of an evaluation) with HIP events on the context's stream
+   around every batch of iterations (the iterations run as replays of a
+   captured graph); enable = 0 stops; enable = -1 resets the counters. out
+   (may be NULL) receives {instance-iterations executed, seconds, algorithmic
+   bytes of those iterations, potential rows of all instances}. Algorithmic
+   bytes of one iteration: Jacobi CG (one kernel): the stored matrix (values +
+   column indices, no padding) once plus 11 vector passes (read r, w, s, D^-1,
+   p, x; write r, w, s, p, x); multigrid CG: the fine matrix three times, the
+   fine prolongator and restriction once each, 17 fine vector passes, each
+   coarse level's two fused operators and 3 vector passes, and the coarsest
+   dense inverse. Values are 8 bytes in the FP64 mode and 4 bytes in the FP32
+   inner solves and FP32-stored operators (the mixed multigrid form keeps its
+   fine CG vectors at 8 bytes). */
 int mm_profile(mm_ctx *c, int enable, double out[4]);
 
 /* Block shape of the scalar-potential kernels (the dominant work). Waves per

@@ -268,7 +268,7 @@ struct AmgState {
     AmgLaunch<double> g64;
     AmgLaunch<float> g32;
     double setup_seconds = 0;
-    double bytes64 = 0, bytes32 = 0;  // algorithmic bytes of one CG iteration
+    double bytes64 = 0, bytes32 = 0, bytesmix = 0;  // algorithmic bytes of one CG iteration
 };
 
 namespace {
@@ -483,6 +483,9 @@ AmgState *amg_get(mm_ctx *c) {
     sync(c);
     S->bytes64 = b64;
     S->bytes32 = b32;
+    // mixed form: FP32 matrices and cycle, FP64 CG vectors on the fine level
+    // (the 17 fine vector passes at 8 instead of 4 bytes)
+    S->bytesmix = b32 + (nl > 1 ? 17.0 * 4.0 * (double)S->lv[0].A.n : 0.0);
     S->setup_seconds = now_s() - t0;
     c->amg = S.release();
     return c->amg;
@@ -490,7 +493,7 @@ AmgState *amg_get(mm_ctx *c) {
 
 const AmgLaunch<double> &amg_launch64(AmgState *s) { return s->g64; }
 const AmgLaunch<float> &amg_launch32(AmgState *s) { return s->g32; }
-double amg_bytes(AmgState *s, bool fp32) { return fp32 ? s->bytes32 : s->bytes64; }
+double amg_bytes(AmgState *s, int form) { return form == 2 ? s->bytesmix : form == 1 ? s->bytes32 : s->bytes64; }
 
 }  // namespace mmncg
 

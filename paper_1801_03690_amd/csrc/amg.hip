@@ -74,30 +74,30 @@ __global__ __launch_bounds__(kAB) void k_amg_spmv(int n, const int *__restrict__
     if (gl == 0) y[row] = s;
 }
 
-// z = omega D^-1 b + P y (b at b[row * bs]: bs = 4 for the r field of the
-// fine-level records)
-template <class VT, int GL>
+// z = omega D^-1 b + P y on the fine level (b at b[row * bs]: bs = 4 for the
+// r field of the CG records, whose type RT may be wider than the cycle's VT)
+template <class VT, class RT, int GL>
 __global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restrict__ p, const int *__restrict__ j,
                                                      const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
-                                                     const VT *__restrict__ b, int bs, const VT *__restrict__ yc,
+                                                     const RT *__restrict__ b, int bs, const VT *__restrict__ yc,
                                                      VT *__restrict__ z, const int *done) {
     if (skip(done)) return;
     const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
     if (row >= n) return;
     const VT s = csr_row<GL>(p, j, v, yc, row, gl);
-    if (gl == 0) z[row] = omega * dinv[row] * b[(int64_t)row * bs] + s;
+    if (gl == 0) z[row] = omega * dinv[row] * (VT)b[(int64_t)row * bs] + s;
 }
 
 // y = Ainv b on the coarsest level: one wave per row of the dense inverse
-template <class VT>
-__global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__ Ainv, const VT *__restrict__ b,
+template <class VT, class BT>
+__global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__ Ainv, const BT *__restrict__ b,
                                                    int bs, VT *__restrict__ y, const int *done) {
     if (skip(done)) return;
     const int row = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
     if (row >= n) return;
     const VT *a = Ainv + (int64_t)row * n;
     VT acc = 0;
-    for (int c = ln; c < n; c += 64) acc += a[c] * b[(int64_t)c * bs];
+    for (int c = ln; c < n; c += 64) acc += a[c] * (VT)b[(int64_t)c * bs];
     acc = group_sum<64>(acc);
     if (ln == 0) y[row] = acc;
 }
@@ -137,9 +137,9 @@ __device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const V
 // k_amg_iter (the CG start, or a plain vector): t = r - omega K D^-1 r with r
 // at r[row * rs]. With q given (the CG start), also sets w = s = 0 and d =
 // D^-1 in the records q (the r fields are left alone: neighbours read them).
-template <class MT, class VT, int NW>
+template <class MT, class VT, class CT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
-                                                      const VT *__restrict__ invD, VT omega, VT *__restrict__ t,
+                                                      const VT *__restrict__ invD, VT omega, CT *__restrict__ t,
                                                       PcgNode<VT> *__restrict__ q) {
     Tile tl = tile_of(M);
     if (tl.inst < 0) return;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
         const VT acc = row_gather<MT, VT, true>(K, s, ln, r, rs, invD);
         const int row = s * 64 + ln;
         if (row < rend) {
-            t[row] = r[(int64_t)row * rs] - omega * acc;
+            t[row] = (CT)(r[(int64_t)row * rs] - omega * acc);
             if (q) {
                 q[row].w = (VT)0;
                 q[row].s = (VT)0;
@@ -158,12 +158,13 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
     }
 }
 
-// fine level: u = z + omega D^-1 (r - K z); partial gamma = r.u into slot
-// gslot (skipped when part is null)
-template <class MT, class VT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
+// fine level: u = z + omega D^-1 (r - K z) in the cycle's type VT, stored as
+// the CG's type RT; partial gamma = r.u of the stored values into slot gslot
+// (skipped when part is null)
+template <class MT, class VT, class RT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const RT *__restrict__ r, int rs,
                                                        const VT *__restrict__ invD, VT omega,
-                                                       const VT *__restrict__ z, VT *__restrict__ u,
+                                                       const VT *__restrict__ z, RT *__restrict__ u,
                                                        double *__restrict__ part, int gslot, const int *done) {
     Tile tl = tile_of(M);
     if (tl.inst < 0 || skip(done)) return;
@@ -174,8 +175,8 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
         const VT kz = row_gather<MT, VT, false>(K, s, ln, z, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
-            const VT ri = r[(int64_t)row * rs];
-            const VT ui = z[row] + omega * invD[row] * (ri - kz);
+            const RT ri = r[(int64_t)row * rs];
+            const RT ui = (RT)(z[row] + omega * invD[row] * ((VT)ri - kz));
             u[row] = ui;
             acc[0] += (double)ri * (double)ui;
         }
@@ -244,9 +245,9 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
 // partials P[par]; writes records q[par ^ 1] with w = 0, filled in by
 // k_amg_w) and t = r_new - omega K D^-1 r_new, where K D^-1 r_new = A -
 // alpha (B + beta C) with A, B, C the products of K D^-1 with the old r, w, s
-template <class MT, class VT, class XT, int NW>
+template <class MT, class VT, class XT, class CT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
-                                                      const VT *__restrict__ uu, VT *__restrict__ tt, VT omega,
+                                                      const VT *__restrict__ uu, CT *__restrict__ tt, VT omega,
                                                       PcgState *__restrict__ st, int par,
                                                       const double *__restrict__ part) {
     Tile tl = tile_of(M);
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
             x[row] = x[row] + (XT)(a * pn);
             p[row] = pn;
             q1[row] = PcgNode<VT>{rn, (VT)0, sn, me.d};
-            tt[row] = rn - omega * kdr;
+            tt[row] = (CT)(rn - omega * kdr);
         }
     }
 }
@@ -358,9 +359,9 @@ dim3 grid_rows(int n) {
 
 // the cycle below the fine level: restriction of t0, the fused operators of
 // levels 1..L-1 down, the dense solve, the fused operators up, and the
-// prolongation back to z0 (r0 at r[row * rs])
-template <class VT>
-void coarse_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, hipStream_t s) {
+// prolongation back to z0 (r0 at r[row * rs], of the CG's type RT)
+template <class VT, class RT>
+void coarse_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
     const int L = g.nlev - 1;
     const AmgLevel<VT> &f = g.lv[0], &c1 = g.lv[1];
     MMNCG_GL_SWITCH(f.gR, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c1.n), dim3(kAB), 0, s, c1.n, f.Rp,
@@ -371,29 +372,29 @@ void coarse_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, 
                                                  a.Dp, a.Dj, a.Dv, (const VT *)a.b, c.b, done))
     }
     const AmgLevel<VT> &cl = g.lv[L];
-    hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
-                       cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
+    hipLaunchKernelGGL((k_amg_dense<VT, VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0,
+                       s, cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
     for (int l = L - 1; l >= 1; --l) {
         const AmgLevel<VT> &a = g.lv[l];
         // [b_l; y_{l+1}] is one array starting at b_l
         MMNCG_GL_SWITCH(a.gU, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(a.n), dim3(kAB), 0, s, a.n,
                                                  a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, done))
     }
-    MMNCG_GL_SWITCH(f.gP, hipLaunchKernelGGL((k_amg_prolong<VT, GL>), grid_rows<GL>(f.n), dim3(kAB), 0, s, f.n, f.Pp,
-                                             f.Pj, f.Pv, f.dinv, f.omega, r, rs, (const VT *)c1.y, f.z, done))
+    MMNCG_GL_SWITCH(f.gP, hipLaunchKernelGGL((k_amg_prolong<VT, RT, GL>), grid_rows<GL>(f.n), dim3(kAB), 0, s, f.n,
+                                             f.Pp, f.Pj, f.Pv, f.dinv, f.omega, r, rs, (const VT *)c1.y, f.z, done))
 }
 
 // everything between the fine pre-smoothing and the fine post-smoothing:
 // z0 = omega D^-1 r + P V(P^T t0); with a single level, z0 = K^-1 r from the
 // dense inverse (and the post-smoothing weight is 0, see post_omega)
-template <class VT>
-void lower_cycle(const AmgLaunch<VT> &g, const VT *r, int rs, const int *done, hipStream_t s) {
+template <class VT, class RT>
+void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
     const AmgLevel<VT> &f = g.lv[0];
     if (g.nlev > 1) {
         coarse_cycle(g, r, rs, done, s);
     } else if (f.n > 0) {
-        hipLaunchKernelGGL((k_amg_dense<VT>), dim3((unsigned)((f.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0, s,
-                           f.n, f.Ainv, r, rs, f.z, done);
+        hipLaunchKernelGGL((k_amg_dense<VT, RT>), dim3((unsigned)((f.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB),
+                           0, s, f.n, f.Ainv, r, rs, f.z, done);
     }
 }
 
@@ -402,73 +403,97 @@ VT post_omega(const AmgLaunch<VT> &g) {
     return g.nlev > 1 ? g.lv[0].omega : (VT)0;
 }
 
-// one cycle on the fine level from the residual r (at r[row * rs]) into
-// g.u; with a CG, also the records' start fields (q) and the partials of
-// the start (gamma, then delta and r.r in P0)
-template <class VT>
-void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const VT *r, int rs, PcgNode<VT> *q, bool cg,
-                hipStream_t s) {
+// The fine-level vectors of the CG (records, direction, u) are of type RT;
+// the cycle and the stored fine matrix used inside it and by the CG are of
+// type VT (VT = RT in the FP64 and FP32 solves; VT = float, RT = double in
+// the mixed solve: FP32-stored operators and cycle, FP64 Krylov vectors).
+template <class VT, class RT>
+struct FineArgs {
+    const RT *invD;    // D^-1 of the records
+    RT omega;          // fine smoothing weight in RT
+    RT *u;             // preconditioned residual
+};
+
+// one cycle on the fine level from the residual r (at r[row * rs]) into u;
+// with a CG, also the records' start fields (q) and the partials of the
+// start (gamma, then delta and r.r in P0)
+template <class VT, class RT>
+void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const RT *r, int rs,
+                PcgNode<RT> *q, bool cg, hipStream_t s) {
     const RowMap &M = *a.M;
     const AmgLevel<VT> &f = g.lv[0];
     // t (unused with a single level) and the records' start fields
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, r, rs, f.dinv, f.omega, f.t, q))
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, RT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, r, rs, fa.invD, fa.omega, f.t, q))
     lower_cycle(g, r, rs, nullptr, s);
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, r, rs, f.dinv, post_omega(g), (const VT *)f.z, g.u,
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, r, rs, f.dinv, post_omega(g), (const VT *)f.z, fa.u,
                                              cg ? a.part : (double *)nullptr, kP0, (const int *)nullptr))
     if (cg)
-        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                                 view<VT>(*a.K), M, q, (const VT *)g.u, a.part, kP0 + 1,
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                                 view<VT>(*a.K), M, q, (const RT *)fa.u, a.part, kP0 + 1,
                                                  (const int *)nullptr))
 }
 
-template <class VT, class XT>
-void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const PcgVecs<VT> &v, XT *x, int par, hipStream_t s) {
+template <class VT, class RT, class XT>
+void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const PcgVecs<RT> &v, XT *x,
+              int par, hipStream_t s) {
     const RowMap &M = *a.M;
     const AmgLevel<VT> &f = g.lv[0];
     const int *done = &a.st[0].done;
-    PcgNode<VT> *q1 = v.q[par ^ 1];
+    PcgNode<RT> *q1 = v.q[par ^ 1];
     const int ws = par ? kP0 : kP1;  // this iteration's new partials
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, VT, XT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, v, x, (const VT *)g.u, f.t, f.omega, a.st,
-                                             par, (const double *)a.part))
-    lower_cycle(g, &q1->r, 4, done, s);
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, (const VT *)&q1->r, 4, f.dinv, post_omega(g),
-                                             (const VT *)f.z, g.u, a.part, ws, done);
-                    hipLaunchKernelGGL((k_amg_w<VT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<VT>(*a.K), M, q1, (const VT *)g.u, a.part, ws + 1, done))
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.omega, a.st, par,
+                                             (const double *)a.part))
+    lower_cycle(g, (const RT *)&q1->r, 4, done, s);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, f.dinv, post_omega(g),
+                                             (const VT *)f.z, fa.u, a.part, ws, done);
+                    hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1, done))
+}
+
+FineArgs<double, double> fine64(const PcgLaunch &a, const AmgLaunch<double> &g) {
+    return FineArgs<double, double>{a.invD, g.lv[0].omega, g.u};
+}
+FineArgs<float, float> fine32(const PcgLaunch &a, const AmgLaunch<float> &g) {
+    return FineArgs<float, float>{a.invD32, g.lv[0].omega, g.u};
+}
+FineArgs<float, double> finemix(const PcgLaunch &a, const AmgLaunch<double> &g64) {
+    return FineArgs<float, double>{a.invD, g64.lv[0].omega, g64.u};
 }
 
 }  // namespace
 
 void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s) {
-    launch_pcg_residual_q(a, act, s);
-    fine_cycle<double>(a, g, &a.v64.q[0]->r, 4, a.v64.q[0], true, s);
+    launch_pcg_residual_q(a, act, false, s);
+    fine_cycle<double, double>(a, g, fine64(a, g), &a.v64.q[0]->r, 4, a.v64.q[0], true, s);
     launch_pcg_fin(a, act, rtol2, 0, s);
 }
 
-void launch_amg_init32(const PcgLaunch &a, const AmgLaunch<float> &g, hipStream_t s) {
-    launch_pcg_start32_only(a, s);
-    fine_cycle<float>(a, g, &a.v32.q[0]->r, 4, a.v32.q[0], true, s);
-    launch_pcg_fin(a, nullptr, 0.0, 1, s);
+void launch_amg_initmix(const PcgLaunch &a, const AmgLaunch<float> &g, const AmgLaunch<double> &g64, const int *act,
+                        double rtol2, hipStream_t s) {
+    launch_pcg_residual_q(a, act, true, s);
+    fine_cycle<float, double>(a, g, finemix(a, g64), &a.v64.q[0]->r, 4, a.v64.q[0], true, s);
+    launch_pcg_fin(a, act, rtol2, 0, s);
 }
 
 void launch_amg_iter64(const PcgLaunch &a, const AmgLaunch<double> &g, int parity, hipStream_t s) {
-    amg_iter<double, double>(a, g, a.v64, a.u, parity, s);
+    amg_iter<double, double, double>(a, g, fine64(a, g), a.v64, a.u, parity, s);
 }
 
-void launch_amg_iter32(const PcgLaunch &a, const AmgLaunch<float> &g, int parity, hipStream_t s) {
-    amg_iter<float, float>(a, g, a.v32, a.x32, parity, s);
+void launch_amg_itermix(const PcgLaunch &a, const AmgLaunch<float> &g, const AmgLaunch<double> &g64, int parity,
+                        hipStream_t s) {
+    amg_iter<float, double, double>(a, g, finemix(a, g64), a.v64, a.u, parity, s);
 }
 
 void launch_amg_apply64(const PcgLaunch &a, const AmgLaunch<double> &g, const double *r, hipStream_t s) {
-    fine_cycle<double>(a, g, r, 1, nullptr, false, s);
+    fine_cycle<double, double>(a, g, fine64(a, g), r, 1, (PcgNode<double> *)nullptr, false, s);
 }
 
 void launch_amg_apply32(const PcgLaunch &a, const AmgLaunch<float> &g, const float *r, hipStream_t s) {
-    fine_cycle<float>(a, g, r, 1, nullptr, false, s);
+    fine_cycle<float, float>(a, g, fine32(a, g), r, 1, (PcgNode<float> *)nullptr, false, s);
 }
 
 }  // namespace mmncg

@@ -132,7 +132,7 @@ struct mm_ctx {
     // scalar-potential matrix, the hierarchy once built, its captured graphs
     HostCsr hostK;
     mmncg::AmgState *amg = nullptr;
-    hipGraphExec_t agraph64 = nullptr, agraph32 = nullptr;
+    hipGraphExec_t agraph64 = nullptr, mgraph = nullptr;
 
     // control block: ints {act, role, first, from, pact, plive} (host-written)
     // then {info, pflags x4} (device-written); doubles {alpha, h3 x3, pin x4}
@@ -195,7 +195,7 @@ AmgState *amg_get(mm_ctx *c);   // builds the hierarchy on first use
 void amg_release(mm_ctx *c);
 const AmgLaunch<double> &amg_launch64(AmgState *s);
 const AmgLaunch<float> &amg_launch32(AmgState *s);
-double amg_bytes(AmgState *s, bool fp32);
+double amg_bytes(AmgState *s, int form);  // algorithmic bytes of one CG iteration: 0 FP64, 1 FP32, 2 mixed
 void load_m(mm_ctx *c, const double *m);
 void reduce_field(const InstInfo &I, const double *BT, double h[3]);
 void eval_all(mm_ctx *c, const mm_opts &o, const std::vector<double> &h);

@@ -190,7 +190,7 @@ void launch_add_correction(const PcgLaunch &a, hipStream_t s);
 // the r fields of records 0 with the partials (b.b, r.r); the FP32 inner
 // start (x = 0, r = r64 * scale); the start partials into the CG state
 // (mode 0: CG start, 1: FP32 inner start, 2: residual only)
-void launch_pcg_residual_q(const PcgLaunch &a, const int *act, hipStream_t s);
+void launch_pcg_residual_q(const PcgLaunch &a, const int *act, bool fp32_matrix, hipStream_t s);
 void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s);
 void launch_pcg_fin(const PcgLaunch &a, const int *act, double rtol2, int mode, hipStream_t s);
 
@@ -230,10 +230,14 @@ struct AmgLaunch {
 };
 // CG start (single instance): residual, one cycle, w = K u, partials, state
 void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s);
-void launch_amg_init32(const PcgLaunch &a, const AmgLaunch<float> &g, hipStream_t s);
+// mixed solve (FP32-bulk mode): FP64 CG vectors and residual norms on the
+// FP32-stored matrix, the cycle in FP32; the solution goes straight to u
+void launch_amg_initmix(const PcgLaunch &a, const AmgLaunch<float> &g, const AmgLaunch<double> &g64, const int *act,
+                        double rtol2, hipStream_t s);
 // one CG iteration of parity `parity` (a chain of launches)
 void launch_amg_iter64(const PcgLaunch &a, const AmgLaunch<double> &g, int parity, hipStream_t s);
-void launch_amg_iter32(const PcgLaunch &a, const AmgLaunch<float> &g, int parity, hipStream_t s);
+void launch_amg_itermix(const PcgLaunch &a, const AmgLaunch<float> &g, const AmgLaunch<double> &g64, int parity,
+                        hipStream_t s);
 // one cycle applied to the plain vector r (n_pot rows) into g.u
 void launch_amg_apply64(const PcgLaunch &a, const AmgLaunch<double> &g, const double *r, hipStream_t s);
 void launch_amg_apply32(const PcgLaunch &a, const AmgLaunch<float> &g, const float *r, hipStream_t s);

@@ -377,10 +377,14 @@ void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s) {
                                              s, view<float>(*a.K), M, a.v32, a.x32, a.invD32, a.st, parity, a.part))
 }
 
-void launch_pcg_residual_q(const PcgLaunch &a, const int *act, hipStream_t s) {
+void launch_pcg_residual_q(const PcgLaunch &a, const int *act, bool fp32_matrix, hipStream_t s) {
     const RowMap &M = *a.M;
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<double>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part))
+    if (fp32_matrix)
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                                 view<float>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part))
+    else
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                                 view<double>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part))
 }
 
 void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s) {

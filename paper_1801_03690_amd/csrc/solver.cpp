@@ -80,7 +80,7 @@ void free_all(mm_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     amg_release(c);
     c->hostK = HostCsr();
-    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->agraph32}) {
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->mgraph}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
@@ -492,11 +492,16 @@ PcgLaunch pcg_args(mm_ctx *c) {
     return a;
 }
 
-void pcg_chunk(mm_ctx *c, bool fp32, bool amg) {
+// kinds of scalar-potential CG: Jacobi (one kernel per iteration), multigrid
+// in one precision, and multigrid in the mixed form of the FP32-bulk mode
+enum CgKind { CG_JACOBI = 0, CG_AMG = 1, CG_AMG_MIXED = 2 };
+
+void pcg_chunk(mm_ctx *c, bool fp32, int kind) {
     PcgLaunch a = pcg_args(c);
-    if (amg) {
+    if (kind != CG_JACOBI) {
         for (int j = 0; j < kAmgChunk; ++j) {
-            if (fp32) launch_amg_iter32(a, amg_launch32(c->amg), j & 1, c->stream);
+            if (kind == CG_AMG_MIXED)
+                launch_amg_itermix(a, amg_launch32(c->amg), amg_launch64(c->amg), j & 1, c->stream);
             else launch_amg_iter64(a, amg_launch64(c->amg), j & 1, c->stream);
         }
         return;
@@ -517,13 +522,15 @@ bool use_graphs() {
 
 // capture one chunk of iterations once per context, precision and
 // preconditioner
-hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32, bool amg) {
-    hipGraphExec_t &ge = amg ? (fp32 ? c->agraph32 : c->agraph64) : (fp32 ? c->graph32 : c->graph64);
+hipGraphExec_t pcg_graph(mm_ctx *c, bool fp32, int kind) {
+    hipGraphExec_t &ge = kind == CG_AMG_MIXED ? c->mgraph
+                         : kind == CG_AMG    ? c->agraph64
+                                             : (fp32 ? c->graph32 : c->graph64);
     if (ge) return ge;
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     try {
-        pcg_chunk(c, fp32, amg);
+        pcg_chunk(c, fp32, kind);
     } catch (...) {
         (void)hipStreamEndCapture(c->stream, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -546,21 +553,21 @@ void pull_pcg(mm_ctx *c) {
 // batch of replays and the executed iterations (and their algorithmic bytes)
 // are counted per instance; replays after an instance converged return at once
 // and their time stays in the measurement.
-void pcg_replay(mm_ctx *c, bool fp32, bool amg, long maxit, const std::vector<int> &on) {
-    hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32, amg) : nullptr;
-    const long chunk = amg ? kAmgChunk : kPcgChunk;
+void pcg_replay(mm_ctx *c, bool fp32, int kind, long maxit, const std::vector<int> &on) {
+    hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32, kind) : nullptr;
+    const long chunk = kind != CG_JACOBI ? kAmgChunk : kPcgChunk;
     long expect = chunk;
     for (int i : on) expect = std::max(expect, c->last_pcg[i]);
     long nrep = (expect + chunk - 1) / chunk;
     long launched = 0;
     std::vector<int> seen(c->ninst, 0);
     std::vector<double> bytes = fp32 ? c->pcg_bytes32 : c->pcg_bytes64;
-    if (amg) bytes.assign(c->ninst, amg_bytes(c->amg, fp32));
+    if (kind != CG_JACOBI) bytes.assign(c->ninst, amg_bytes(c->amg, kind == CG_AMG_MIXED ? 2 : 0));
     for (;;) {
         prof_mark(c);
         for (long k = 0; k < nrep; ++k) {
             if (ge) HIPCHK(hipGraphLaunch(ge, c->stream));
-            else pcg_chunk(c, fp32, amg);
+            else pcg_chunk(c, fp32, kind);
         }
         prof_mark(c);
         launched += nrep * chunk;
@@ -587,12 +594,18 @@ void zero_pot(mm_ctx *c, int i) {
 }
 
 // FP64 CG for the instances with act[i] set (uploaded); returns per-instance iterations
-std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, bool amg, const std::vector<int> &on) {
+// FP64 CG vectors and residual norms: the FP64 mode (Jacobi or multigrid),
+// and the mixed multigrid form of the FP32-bulk mode (FP32-stored matrix and
+// cycle), which needs no defect correction
+std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, int kind, const std::vector<int> &on) {
     std::vector<long> it(c->ninst, 0);
     PcgLaunch a = pcg_args(c);
-    if (amg) launch_amg_init64(a, amg_launch64(c->amg), c->d_(c->act()), rtol * rtol, c->stream);
-    else launch_pcg_init64(a, c->d_(c->act()), rtol * rtol, c->stream);
-    pcg_replay(c, false, amg, maxit, on);
+    const int *act = c->d_(c->act());
+    if (kind == CG_AMG_MIXED)
+        launch_amg_initmix(a, amg_launch32(c->amg), amg_launch64(c->amg), act, rtol * rtol, c->stream);
+    else if (kind == CG_AMG) launch_amg_init64(a, amg_launch64(c->amg), act, rtol * rtol, c->stream);
+    else launch_pcg_init64(a, act, rtol * rtol, c->stream);
+    pcg_replay(c, false, kind, maxit, on);
     for (int i : on) {
         if (c->hpst[i].zero_u) {
             zero_pot(c, i);
@@ -604,7 +617,7 @@ std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, bool amg, con
     return it;
 }
 
-std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, bool amg, const std::vector<int> &on) {
+std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::vector<int> &on) {
     std::vector<long> total(c->ninst, 0);
     PcgLaunch a = pcg_args(c);
     std::vector<int> live = on;
@@ -644,11 +657,10 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, bool amg, con
         live = inner;
         if (live.empty()) break;
         upload_ctl(c);
-        if (amg) launch_amg_init32(a, amg_launch32(c->amg), c->stream);
-        else launch_pcg_init32(a, c->stream);
+        launch_pcg_init32(a, c->stream);
         long cap = 0;
         for (int i : live) cap = std::max(cap, maxit - total[i]);
-        pcg_replay(c, true, amg, cap, live);
+        pcg_replay(c, true, CG_JACOBI, cap, live);
         for (int i : live) {
             total[i] += c->hpst[i].iters;
             c->last_pcg[i] = std::max<long>(4, c->hpst[i].iters);
@@ -666,7 +678,9 @@ void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std:
     if (on.empty() || c->rows_p == 0) return;
     if (amg) amg_get(c);  // first use: build the hierarchy (untimed, like the assembly)
     const double t0 = now_s();
-    std::vector<long> it = fp32 ? poisson_fp32(c, rtol, maxit, amg, on) : poisson_fp64(c, rtol, maxit, amg, on);
+    std::vector<long> it = (fp32 && amg)  ? poisson_fp64(c, rtol, maxit, CG_AMG_MIXED, on)
+                           : fp32         ? poisson_fp32(c, rtol, maxit, on)
+                                          : poisson_fp64(c, rtol, maxit, amg ? CG_AMG : CG_JACOBI, on);
     sync(c);
     const double dt = now_s() - t0;
     for (int i : on) {
@@ -682,7 +696,7 @@ void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std:
 // wave of instance i. Captured graphs hold the old map: they are dropped.
 void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
     sync(c);
-    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->agraph32}) {
+    for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->mgraph}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
