@@ -338,7 +338,7 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
        neighbour (weights within a relative 1e-12 are equal; lowest column);
      P = (I - omega D^-1 A) P0, P0 the aggregate indicator, omega = (4/3) /
        max_i sum_j |a_ij| / a_ii; next level P^T A P; coarsest level (at most
-       512 rows, or coarsening stalled, or 12 levels) solved by its dense
+       2048 rows, or coarsening stalled, or 12 levels) solved by its dense
        inverse;
      cycle: V(1,1) with damped Jacobi (weight omega) from zero.
    The hierarchy is built on the host on first use (a solve with

@@ -25,8 +25,8 @@ aggregation method:
               spectral radius of D^-1 A);
   coarse      A_c = P^T A P (Galerkin);
   levels      until a level has at most COARSE_MAX rows (solved with its
-              dense inverse), or coarsening stalls (n_c > 0.9 n), or
-              MAX_LEVELS;
+              dense inverse; a parameter of the hierarchy, 2048 by default),
+              or coarsening stalls (n_c > 0.9 n), or MAX_LEVELS;
   cycle       V(1,1) with damped Jacobi, the same omega: from zero,
               y = omega D^-1 b, t = b - A y, y += P V_{l+1}(P^T t),
               y += omega D^-1 (b - A y).
@@ -40,7 +40,7 @@ from __future__ import annotations
 import numpy as np
 
 THETA0 = 0.08
-COARSE_MAX = 512
+COARSE_MAX = 2048
 MAX_LEVELS = 12
 STALL = 0.9
 TIE = 1e-12
@@ -188,7 +188,7 @@ class Level:
         self.Ainv = None
 
 
-def hierarchy(A):
+def hierarchy(A, coarse_max=COARSE_MAX):
     """The levels, fine to coarse; the last holds a dense inverse. Stored
     zeros of A are dropped first (they are neither strong nor part of any
     product)."""
@@ -198,7 +198,7 @@ def hierarchy(A):
     while True:
         L = Level(A, theta)
         levels.append(L)
-        if A.n <= COARSE_MAX or len(levels) == MAX_LEVELS:
+        if A.n <= coarse_max or len(levels) == MAX_LEVELS:
             break
         agg, na = aggregate(A, theta)
         if na > STALL * A.n or na == 0:
@@ -251,8 +251,8 @@ def pcg(A, b, x0, precond, rtol, maxit=10000):
     return x, it
 
 
-def solve(A, b, x0=None, rtol=1e-10, levels=None):
+def solve(A, b, x0=None, rtol=1e-10, levels=None, coarse_max=COARSE_MAX):
     """AMG-preconditioned CG for A x = b."""
-    levels = hierarchy(A) if levels is None else levels
+    levels = hierarchy(A, coarse_max) if levels is None else levels
     x0 = np.zeros(A.n) if x0 is None else x0
     return pcg(A, b, x0, lambda r: vcycle(levels, r), rtol)

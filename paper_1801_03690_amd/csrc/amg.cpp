@@ -14,7 +14,7 @@
 //                1e-12 count as equal; the lowest column wins);
 //   prolongator  P = (I - omega D^-1 A) P0 with P0 the aggregate indicator,
 //                omega = (4/3) / rho, rho = max_i sum_j |a_ij| / a_ii;
-//   next level   A_c = P^T A P; stop at <= 512 rows (dense inverse), when
+//   next level   A_c = P^T A P; stop at <= 2048 rows (dense inverse), when
 //                coarsening stalls (more than 0.9 n aggregates) or at 12
 //                levels.
 // Entries that sum to exactly zero are dropped from every product.
@@ -32,10 +32,10 @@ namespace mmncg {
 namespace {
 
 constexpr double kTheta0 = 0.08;
-constexpr int kCoarseMax = 512;
+constexpr int kCoarseMax = 2048;
 constexpr double kStall = 0.9;
 constexpr double kTie = 1e-12;
-constexpr int kDenseLimit = 4096;  // largest coarsest level held as a dense inverse
+constexpr int kDenseLimit = 8192;  // largest coarsest level held as a dense inverse
 
 struct Csr {
     int n = 0, ncols = 0;
@@ -217,39 +217,59 @@ Csr smoothed_prolongator(const Csr &A, const std::vector<double> &d, const std::
     return P;
 }
 
-// inverse of a symmetric positive definite matrix through its Cholesky factor
+// inverse of a symmetric positive definite matrix through its Cholesky
+// factor: A = L L^T, then L^-1 row by row (row i = (e_i - sum_{m<i} l_im
+// row m) / l_ii) and A^-1 = L^-T L^-1 as a sum of outer products of the rows
+// of L^-1; every inner loop runs over contiguous memory
 std::vector<double> spd_inverse(const Csr &A) {
+    // the sums may be reassociated (vectorized): this is set-up, and the
+    // result is checked against the oracle's inverse to round-off
+#pragma clang fp reassociate(on)
     const int n = A.n;
     std::vector<double> L((size_t)n * n, 0.0);
     for (int r = 0; r < n; ++r)
         for (int64_t e = A.p[r]; e < A.p[r + 1]; ++e) L[(size_t)r * n + A.j[e]] = A.v[e];
     for (int k = 0; k < n; ++k) {
-        double s = L[(size_t)k * n + k];
-        for (int m = 0; m < k; ++m) s -= L[(size_t)k * n + m] * L[(size_t)k * n + m];
+        double *lk = &L[(size_t)k * n];
+        double s = lk[k];
+        for (int m = 0; m < k; ++m) s -= lk[m] * lk[m];
         if (!(s > 0.0)) throw ApiError{MM_EMESH, "multigrid: coarsest matrix is not positive definite"};
         const double lkk = std::sqrt(s);
-        L[(size_t)k * n + k] = lkk;
+        lk[k] = lkk;
         for (int i = k + 1; i < n; ++i) {
-            double t = L[(size_t)i * n + k];
-            for (int m = 0; m < k; ++m) t -= L[(size_t)i * n + m] * L[(size_t)k * n + m];
-            L[(size_t)i * n + k] = t / lkk;
+            double *li = &L[(size_t)i * n];
+            double t = li[k];
+            for (int m = 0; m < k; ++m) t -= li[m] * lk[m];
+            li[k] = t / lkk;
+        }
+        for (int m = k + 1; m < n; ++m) lk[m] = 0.0;
+    }
+    std::vector<double> Li((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double *ri = &Li[(size_t)i * n];
+        const double *li = &L[(size_t)i * n];
+        ri[i] = 1.0;
+        for (int m = 0; m < i; ++m) {
+            const double c = li[m];
+            if (c == 0.0) continue;
+            const double *rm = &Li[(size_t)m * n];
+            for (int j = 0; j <= m; ++j) ri[j] -= c * rm[j];
+        }
+        const double d = 1.0 / li[i];
+        for (int j = 0; j <= i; ++j) ri[j] *= d;
+    }
+    std::vector<double> inv((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const double *rk = &Li[(size_t)k * n];
+        for (int i = 0; i <= k; ++i) {
+            const double a = rk[i];
+            if (a == 0.0) continue;
+            double *oi = &inv[(size_t)i * n];
+            for (int j = i; j <= k; ++j) oi[j] += a * rk[j];
         }
     }
-    std::vector<double> inv((size_t)n * n, 0.0), x(n);
-    for (int c = 0; c < n; ++c) {
-        // L y = e_c, then L^T x = y
-        for (int i = 0; i < n; ++i) {
-            double t = (i == c) ? 1.0 : 0.0;
-            for (int m = 0; m < i; ++m) t -= L[(size_t)i * n + m] * x[m];
-            x[i] = t / L[(size_t)i * n + i];
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double t = x[i];
-            for (int m = i + 1; m < n; ++m) t -= L[(size_t)m * n + i] * x[m];
-            x[i] = t / L[(size_t)i * n + i];
-        }
-        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = x[i];
-    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) inv[(size_t)i * n + j] = inv[(size_t)j * n + i];
     return inv;
 }
 

@@ -106,7 +106,7 @@ def test_aggregates_partition_into_connected_sets():
 
 def test_galerkin_product_matches_dense():
     _, A = kuhn_K((4, 4, 4))
-    lv = M.hierarchy(A)
+    lv = M.hierarchy(A, coarse_max=64)
     assert len(lv) >= 2
     for l in range(len(lv) - 1):
         Ad, Pd = lv[l].A.dense(), lv[l].P.dense()
@@ -123,7 +123,8 @@ def test_vcycle_is_spd_with_spectrum_in_unit_interval():
     smoother is A-self-adjoint and positive semidefinite with norm < 1, so
     the cycle M is symmetric and eig(M A) lies in (0, 1]."""
     _, A = kuhn_K((4, 4, 4))
-    lv = M.hierarchy(A)
+    lv = M.hierarchy(A, coarse_max=64)
+    assert len(lv) >= 3
     n = A.n
     Md = np.stack([M.vcycle(lv, e) for e in np.eye(n)], axis=1)
     assert np.abs(Md - Md.T).max() <= 1e-12 * np.abs(Md).max()
@@ -151,7 +152,7 @@ def test_single_level_is_the_exact_inverse():
 def test_amg_pcg_matches_direct_and_beats_jacobi():
     o, A = kuhn_K((6, 6, 6))
     b = np.random.default_rng(4).standard_normal(A.n)
-    x, it = M.solve(A, b, rtol=1e-10)
+    x, it = M.solve(A, b, rtol=1e-10, coarse_max=128)
     xd = np.linalg.solve(A.dense(), b)
     assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
     _, itj = o.poisson(b, rtol=1e-10)

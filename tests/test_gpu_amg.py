@@ -6,7 +6,8 @@ level, the level operators and prolongators to round-off, one cycle in FP64
 to 1e-11 of its size (FP32 to 1e-5), and the multigrid-preconditioned solve
 to the solve tolerance, with iteration counts within one of the oracle's
 (the two CG forms differ only in rounding). Meshes span several SELL slices
-with a ragged last one; the 2x2x2 magnet has a single level.
+with a ragged last one, and two or three levels; the 2x2x2 magnet has a
+single level.
 """
 import numpy as np
 import pytest
@@ -43,37 +44,45 @@ def setup(B, ncell, **mat):
     return mesh, ctx, o, lv
 
 
-def dense_of(ptr, col, val, ncols):
-    n = ptr.size - 1
-    d = np.zeros((n, ncols))
-    np.add.at(d, (np.repeat(np.arange(n), np.diff(ptr)), col), val)
-    return d
+def sparse_diff(ptr, col, val, ref):
+    """Largest |entry difference| between a CSR (ptr, col, val) and an
+    oracle Csr with the same shape (entries missing on one side count as 0)."""
+    n, nc = ptr.size - 1, ref.ncols
+    ka = np.repeat(np.arange(n), np.diff(ptr)).astype(np.int64) * nc + col
+    kb = ref.rows().astype(np.int64) * nc + ref.j
+    keys = np.union1d(ka, kb)
+    va = np.zeros(keys.size)
+    vb = np.zeros(keys.size)
+    va[np.searchsorted(keys, ka)] = val
+    vb[np.searchsorted(keys, kb)] = ref.v
+    return np.abs(va - vb).max(), np.abs(vb).max()
 
 
-@pytest.mark.parametrize("ncell", [(6, 6, 6), (9, 8, 7)])
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (9, 8, 7), (14, 14, 14)])
 def test_hierarchy_matches_oracle(B, ncell):
     mesh, ctx, o, lv = setup(B, ncell)
     info = ctx.amg_info()
     print(ncell, info)
-    assert info["levels"] == len(lv) >= 3
+    assert info["levels"] == len(lv) >= 2
     assert info["rows"] == [L.A.n for L in lv]
-    for l in range(len(lv) - 1):
-        agg = ctx.amg_aggregates(l)
-        assert np.array_equal(agg, lv[l].agg), l
+    if ncell == (14, 14, 14):
+        assert len(lv) >= 3
+    for l in range(len(lv)):
         pa, ja, va = ctx.amg_level_matrix(l, 0)
-        Ad = dense_of(pa, ja, va, lv[l].A.n) if lv[l].A.n <= 6000 else None
-        if Ad is not None:
-            ref = lv[l].A.dense()
-            assert np.abs(Ad - ref).max() <= 1e-12 * np.abs(ref).max(), l
-        pp, jp, vp = ctx.amg_level_matrix(l, 1)
-        Pd = dense_of(pp, jp, vp, lv[l + 1].A.n)
-        ref = lv[l].P.dense()
-        assert np.abs(Pd - ref).max() <= 1e-12, l
+        d, sc = sparse_diff(pa, ja, va, lv[l].A)
+        assert d <= 1e-12 * sc, l
+        if l + 1 < len(lv):
+            agg = ctx.amg_aggregates(l)
+            assert np.array_equal(agg, lv[l].agg), l
+            pp, jp, vp = ctx.amg_level_matrix(l, 1)
+            d, sc = sparse_diff(pp, jp, vp, lv[l].P)
+            assert d <= 1e-12 * sc, l
     ctx.close()
 
 
-def test_cycle_matches_oracle(B):
-    mesh, ctx, o, lv = setup(B, (9, 8, 7))
+@pytest.mark.parametrize("ncell", [(9, 8, 7), (14, 14, 14)])
+def test_cycle_matches_oracle(B, ncell):
+    mesh, ctx, o, lv = setup(B, ncell)
     rng = np.random.default_rng(5)
     for k in range(2):
         r = rng.standard_normal(o.np)
