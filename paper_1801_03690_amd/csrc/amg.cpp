@@ -474,10 +474,18 @@ AmgState *amg_get(mm_ctx *c) {
             }
         }
         if (l == L) {
-            D.Ainv = upload_v(c, H.Ainv);
-            F.Ainv = upload_v(c, to32(H.Ainv));
+            // rows padded to a multiple of 4 values (16 bytes in FP32, 32 in FP64)
+            const int ld = (H.A.n + 3) / 4 * 4;
+            std::vector<double> pad((size_t)H.A.n * ld, 0.0);
+            for (int i = 0; i < H.A.n; ++i)
+                std::copy(H.Ainv.begin() + (size_t)i * H.A.n, H.Ainv.begin() + (size_t)(i + 1) * H.A.n,
+                          pad.begin() + (size_t)i * ld);
+            D.Ainv = upload_v(c, pad);
+            F.Ainv = upload_v(c, to32(pad));
+            D.ld = F.ld = ld;
             if (l > 0) {
-                vec2((size_t)H.A.n, &D.b, &F.b);
+                // the right-hand side is read 16 bytes at a time up to ld (zero padding)
+                vec2((size_t)ld, &D.b, &F.b);
                 if (l == 1) vec2((size_t)H.A.n, &D.y, &F.y);
             }
             for (int k = 0; k < 2; ++k) {

@@ -89,15 +89,31 @@ __global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restric
 }
 
 // y = Ainv b on the coarsest level: one wave per row of the dense inverse
+// (rows ld apart, ld a multiple of 16 bytes, padding zero). With a plain b
+// (bs = 1, also padded to ld with zeros) every lane loads 16 bytes of the row
+// and of b at a time; with b in the CG records (bs = 4), one value.
 template <class VT, class BT>
-__global__ __launch_bounds__(kAB) void k_amg_dense(int n, const VT *__restrict__ Ainv, const BT *__restrict__ b,
-                                                   int bs, VT *__restrict__ y, const int *done) {
+__global__ __launch_bounds__(kAB) void k_amg_dense(int n, int ld, const VT *__restrict__ Ainv,
+                                                   const BT *__restrict__ b, int bs, VT *__restrict__ y,
+                                                   const int *done) {
     if (skip(done)) return;
     const int row = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
     if (row >= n) return;
-    const VT *a = Ainv + (int64_t)row * n;
+    const VT *a = Ainv + (int64_t)row * ld;
     VT acc = 0;
-    for (int c = ln; c < n; c += 64) acc += a[c] * (VT)b[(int64_t)c * bs];
+    if (bs == 1) {
+        constexpr int V = 16 / sizeof(VT);
+        typedef VT vec __attribute__((ext_vector_type(V)));
+        const vec *av = (const vec *)a;
+        const vec *bv = (const vec *)b;
+        for (int k = ln; k < ld / V; k += 64) {
+            const vec x = av[k], z = bv[k];
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc += x[q] * z[q];
+        }
+    } else {
+        for (int c = ln; c < n; c += 64) acc += a[c] * (VT)b[(int64_t)c * bs];
+    }
     acc = group_sum<64>(acc);
     if (ln == 0) y[row] = acc;
 }
@@ -373,7 +389,7 @@ void coarse_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, 
     }
     const AmgLevel<VT> &cl = g.lv[L];
     hipLaunchKernelGGL((k_amg_dense<VT, VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0,
-                       s, cl.n, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
+                       s, cl.n, cl.ld, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
     for (int l = L - 1; l >= 1; --l) {
         const AmgLevel<VT> &a = g.lv[l];
         // [b_l; y_{l+1}] is one array starting at b_l
@@ -394,7 +410,7 @@ void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, h
         coarse_cycle(g, r, rs, done, s);
     } else if (f.n > 0) {
         hipLaunchKernelGGL((k_amg_dense<VT, RT>), dim3((unsigned)((f.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB),
-                           0, s, f.n, f.Ainv, r, rs, f.z, done);
+                           0, s, f.n, f.ld, f.Ainv, r, rs, f.z, done);
     }
 }
 

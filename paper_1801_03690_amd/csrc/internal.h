@@ -218,7 +218,8 @@ struct AmgLevel {
     const VT *Dv = nullptr;
     const int *Up = nullptr, *Uj = nullptr;
     const VT *Uv = nullptr;
-    const VT *Ainv = nullptr;  // l = L
+    const VT *Ainv = nullptr;  // l = L, rows ld apart (ld: a multiple of 16 bytes; padding zero)
+    int ld = 0;
     VT *b = nullptr, *t = nullptr, *z = nullptr, *y = nullptr;  // work vectors
     int gP = 4, gR = 8, gD = 8, gU = 8;  // lanes per row of the CSR kernels (4..64)
 };
