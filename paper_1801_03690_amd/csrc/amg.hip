@@ -20,8 +20,7 @@
 //                  the prolongation z = omega D^-1 r + P_0 y_1;
 //   k_amg_post0    u = z + omega D^-1 (r - K z) on the fine level, partial
 //                  gamma;
-//   k_amg_w        w = K u, the whole record {r, w, s, D^-1} rewritten,
-//                  partials delta and r.r.
+//   k_amg_w        w = K u into the records, partials delta and r.r.
 // Every kernel of an iteration returns at once when the instance's sticky
 // flag is up (the flag only changes inside k_amg_iter, which every later
 // launch follows in stream order). Vector type VT is double (FP64 mode) or
@@ -200,8 +199,9 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
     if (part) write_part<1, NW>(acc, 0u, part + (size_t)gslot * M.nblk, M.nblk, tl.b, sh);
 }
 
-// fine level: w = K u; the record {r, w, s, d} rewritten whole; partials
-// (delta = w.u, r.r) into slots wslot, wslot + 1
+// fine level: w = K u into the w field of the record (the other fields were
+// written by k_amg_iter, or by the start); partials (delta = w.u, r.r) into
+// slots wslot, wslot + 1
 template <class MT, class VT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
                                                    const VT *__restrict__ u, double *__restrict__ part, int wslot,
@@ -215,11 +215,10 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
         const VT ku = row_gather<MT, VT, false>(K, s, ln, u, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
-            PcgNode<VT> me = q[row];
-            me.w = ku;
-            q[row] = me;
+            const VT ri = q[row].r;
+            q[row].w = ku;
             acc[0] += (double)ku * (double)u[row];
-            acc[1] += (double)me.r * (double)me.r;
+            acc[1] += (double)ri * (double)ri;
         }
     }
     write_part<2, NW>(acc, 0u, part + (size_t)wslot * M.nblk, M.nblk, tl.b, sh);
