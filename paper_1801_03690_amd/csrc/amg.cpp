@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -281,14 +282,81 @@ struct HostLevel {
     std::vector<double> Ainv;
 };
 
+// the hierarchy of one matrix, fine to coarse (the rules at the top)
+std::vector<HostLevel> build_hierarchy(const HostCsr &K, int n) {
+    std::vector<HostLevel> lv;
+    Csr A = from_host(K, n);
+    double theta = kTheta0;
+    for (;;) {
+        HostLevel L;
+        L.d = diag(A);
+        for (double x : L.d)
+            if (!(x > 0.0)) throw ApiError{MM_EMESH, "multigrid: non-positive diagonal"};
+        L.rho = gershgorin_rho(A, L.d);
+        L.omega = (4.0 / 3.0) / L.rho;
+        L.theta = theta;
+        const bool last = A.n <= kCoarseMax || (int)lv.size() + 1 == kAmgMaxLevels;
+        int na = 0;
+        if (!last) {
+            na = aggregate(A, L.d, theta, L.agg);
+            if (na > kStall * A.n || na == 0) L.agg.clear();
+        }
+        if (L.agg.empty()) {
+            if (A.n > kDenseLimit) throw ApiError{MM_EMESH, "multigrid coarsening stalled"};
+            L.A = std::move(A);
+            L.Ainv = spd_inverse(L.A);
+            lv.push_back(std::move(L));
+            break;
+        }
+        L.P = smoothed_prolongator(A, L.d, L.agg, na, L.omega);
+        L.R = transpose(L.P);
+        L.AP = spmm(A, L.P);
+        Csr Ac = spmm(L.R, L.AP);
+        L.A = std::move(A);
+        lv.push_back(std::move(L));
+        A = std::move(Ac);
+        theta *= 0.5;
+    }
+    return lv;
+}
+
+int pad4(int n) { return (n + 3) / 4 * 4; }
+
+// global CSR of nrows rows from instance blocks placed at increasing first
+// rows; rows outside every block are empty
+struct GBlock {
+    int row0;
+    const Csr *m;
+    std::function<int(int)> col;
+};
+Csr concat(int nrows, int ncols, const std::vector<GBlock> &bl) {
+    Csr G;
+    G.n = nrows;
+    G.ncols = ncols;
+    G.p.assign(nrows + 1, 0);
+    int r = 0;
+    for (const GBlock &b : bl) {
+        for (; r < b.row0; ++r) G.p[r + 1] = (int64_t)G.j.size();
+        for (int i = 0; i < b.m->n; ++i, ++r) {
+            for (int64_t e = b.m->p[i]; e < b.m->p[i + 1]; ++e) {
+                G.j.push_back(b.col(b.m->j[e]));
+                G.v.push_back(b.m->v[e]);
+            }
+            G.p[r + 1] = (int64_t)G.j.size();
+        }
+    }
+    for (; r < nrows; ++r) G.p[r + 1] = (int64_t)G.j.size();
+    return G;
+}
+
 }  // namespace
 
 struct AmgState {
-    std::vector<HostLevel> lv;
+    std::vector<std::vector<HostLevel>> H;  // per instance, fine to coarse
     AmgLaunch<double> g64;
     AmgLaunch<float> g32;
     double setup_seconds = 0;
-    double bytes64 = 0, bytes32 = 0, bytesmix = 0;  // algorithmic bytes of one CG iteration
+    std::vector<double> bytes[3];  // per instance: algorithmic bytes of one CG iteration (FP64, FP32, mixed)
 };
 
 namespace {
@@ -330,6 +398,73 @@ void up_csr(mm_ctx *c, const Csr &a, const int **p, const int **j, const double 
     *v32 = upload_v(c, to32(a.v));
 }
 
+// Q = P - omega D^-1 (A P) of a level (rows of the level, columns of the next)
+Csr smoothed_transfer(const HostLevel &H) {
+    Csr Q;
+    Q.n = H.P.n;
+    Q.ncols = H.P.ncols;
+    Q.p.assign(Q.n + 1, 0);
+    for (int i = 0; i < Q.n; ++i) {
+        int64_t e = H.P.p[i], f = H.AP.p[i];
+        const int64_t e1 = H.P.p[i + 1], f1 = H.AP.p[i + 1];
+        while (e < e1 || f < f1) {
+            const int ce = e < e1 ? H.P.j[e] : 0x7fffffff, cf = f < f1 ? H.AP.j[f] : 0x7fffffff;
+            const int col = std::min(ce, cf);
+            double v = 0.0;
+            if (ce == col) v += H.P.v[e++];
+            if (cf == col) v -= H.omega * H.AP.v[f++] / H.d[i];
+            if (v != 0.0) {
+                Q.j.push_back(col);
+                Q.v.push_back(v);
+            }
+        }
+        Q.p[i + 1] = (int64_t)Q.j.size();
+    }
+    return Q;
+}
+
+// S = 2 omega D^-1 - omega^2 D^-1 A D^-1 of a level (the pattern of A)
+Csr smoother_pair(const HostLevel &H) {
+    const double w = H.omega;
+    Csr S;
+    S.n = H.A.n;
+    S.ncols = H.A.n;
+    S.p.assign(S.n + 1, 0);
+    for (int i = 0; i < S.n; ++i) {
+        for (int64_t e = H.A.p[i]; e < H.A.p[i + 1]; ++e) {
+            const int j = H.A.j[e];
+            double v = -(w * w) * H.A.v[e] / (H.d[i] * H.d[j]);
+            if (j == i) v += 2.0 * w / H.d[i];
+            if (v != 0.0) {
+                S.j.push_back(j);
+                S.v.push_back(v);
+            }
+        }
+        S.p[i + 1] = (int64_t)S.j.size();
+    }
+    return S;
+}
+
+// [S | Q] as one CSR over the columns [0, ncols_b) + [yoff, ...)
+Csr side_by_side(const Csr &S, const Csr &Q, int qoff) {
+    Csr U;
+    U.n = S.n;
+    U.ncols = qoff + Q.ncols;
+    U.p.assign(U.n + 1, 0);
+    for (int i = 0; i < U.n; ++i) {
+        for (int64_t e = S.p[i]; e < S.p[i + 1]; ++e) {
+            U.j.push_back(S.j[e]);
+            U.v.push_back(S.v[e]);
+        }
+        for (int64_t e = Q.p[i]; e < Q.p[i + 1]; ++e) {
+            U.j.push_back(qoff + Q.j[e]);
+            U.v.push_back(Q.v[e]);
+        }
+        U.p[i + 1] = (int64_t)U.j.size();
+    }
+    return U;
+}
+
 }  // namespace
 
 void amg_release(mm_ctx *c) {
@@ -337,183 +472,188 @@ void amg_release(mm_ctx *c) {
     c->amg = nullptr;
 }
 
-// builds the hierarchy of instance 0 (single-instance contexts) once per mesh
+// Builds the hierarchy of every instance once per mesh and lays the levels of
+// all instances side by side on the device (a batch shares every launch of
+// the cycle, as it shares those of the Jacobi CG).
 AmgState *amg_get(mm_ctx *c) {
     if (c->amg) return c->amg;
-    if (c->ninst != 1) throw ApiError{MM_ESTATE, "the multigrid preconditioner needs a single-instance context"};
-    if (c->hostK.nrows != c->inst[0].n_pot) throw ApiError{MM_ESTATE, "no host copy of the scalar-potential matrix"};
+    const int ni = c->ninst;
+    if (ni < 1 || (int)c->hostK.size() != ni) throw ApiError{MM_ESTATE, "no host copy of the scalar-potential matrix"};
     const double t0 = now_s();
     std::unique_ptr<AmgState> S(new AmgState());
-    Csr A = from_host(c->hostK, c->inst[0].n_pot);
-    double theta = kTheta0;
-    for (;;) {
-        HostLevel L;
-        L.d = diag(A);
-        for (double x : L.d)
-            if (!(x > 0.0)) throw ApiError{MM_EMESH, "multigrid: non-positive diagonal"};
-        L.rho = gershgorin_rho(A, L.d);
-        L.omega = (4.0 / 3.0) / L.rho;
-        L.theta = theta;
-        const bool last = A.n <= kCoarseMax || (int)S->lv.size() + 1 == kAmgMaxLevels;
-        int na = 0;
-        if (!last) {
-            na = aggregate(A, L.d, theta, L.agg);
-            if (na > kStall * A.n || na == 0) L.agg.clear();
-        }
-        if (L.agg.empty()) {
-            if (A.n > kDenseLimit) throw ApiError{MM_EMESH, "multigrid coarsening stalled"};
-            L.A = std::move(A);
-            L.Ainv = spd_inverse(L.A);
-            S->lv.push_back(std::move(L));
-            break;
-        }
-        L.P = smoothed_prolongator(A, L.d, L.agg, na, L.omega);
-        L.R = transpose(L.P);
-        L.AP = spmm(A, L.P);
-        Csr Ac = spmm(L.R, L.AP);
-        L.A = std::move(A);
-        S->lv.push_back(std::move(L));
-        A = std::move(Ac);
-        theta *= 0.5;
+    int nlev = 1;
+    for (int i = 0; i < ni; ++i) {
+        S->H.push_back(build_hierarchy(c->hostK[i], c->inst[i].n_pot));
+        nlev = std::max(nlev, (int)S->H[i].size());
     }
-    // device copies
-    const int nl = (int)S->lv.size();
-    const int L = nl - 1;
-    S->g64.nlev = S->g32.nlev = nl;
-    const size_t RP = std::max(c->rows_p, 1);
-    double b64 = 0, b32 = 0;
+    if (ni > 1)
+        for (int i = 0; i < ni; ++i)
+            if (S->H[i].size() < 2)
+                throw ApiError{MM_ESTATE, "multigrid batches need every instance above 2048 free potential nodes"};
+    // row offsets of every instance's block on every level
+    std::vector<std::vector<int>> off(nlev, std::vector<int>(ni, -1));
+    std::vector<int> N(nlev, 0);
+    N[0] = std::max(c->rows_p, 1);
+    for (int i = 0; i < ni; ++i) off[0][i] = c->inst[i].pot_off;
+    for (int l = 1; l < nlev; ++l)
+        for (int i = 0; i < ni; ++i)
+            if ((int)S->H[i].size() > l) {
+                off[l][i] = N[l];
+                N[l] += pad4(S->H[i][l].A.n);
+            }
+    auto L_of = [&](int i) { return (int)S->H[i].size() - 1; };
+    AmgLaunch<double> &D = S->g64;
+    AmgLaunch<float> &F = S->g32;
+    D.nlev = F.nlev = nlev;
+    D.batch = F.batch = ni > 1;
     auto vec2 = [&](size_t n, double **d, float **f) {
-        *d = dalloc_n<double>(c, std::max<size_t>(n, 1));
-        *f = dalloc_n<float>(c, std::max<size_t>(n, 1));
-        HIPCHK(hipMemsetAsync(*d, 0, std::max<size_t>(n, 1) * sizeof(double), c->stream));
-        HIPCHK(hipMemsetAsync(*f, 0, std::max<size_t>(n, 1) * sizeof(float), c->stream));
+        n = std::max<size_t>(n, 1);
+        *d = dalloc_n<double>(c, n);
+        *f = dalloc_n<float>(c, n);
+        HIPCHK(hipMemsetAsync(*d, 0, n * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(*f, 0, n * sizeof(float), c->stream));
     };
-    for (int l = 0; l < nl; ++l) {
-        HostLevel &H = S->lv[l];
-        AmgLevel<double> &D = S->g64.lv[l];
-        AmgLevel<float> &F = S->g32.lv[l];
-        D.n = F.n = H.A.n;
-        D.omega = H.omega;
-        F.omega = (float)H.omega;
-        const double n = (double)H.A.n, nA = (double)(l == 0 ? c->inst[0].nnz_K : H.A.nnz());
-        if (l == 0) {
-            D.dinv = c->invDK;
-            F.dinv = c->invDK32;
-            vec2(RP, &D.t, &F.t);
-            vec2(RP, &D.z, &F.z);
-            vec2(RP, &D.b, &F.b);  // staging of mm_amg_apply
-            vec2(RP, &D.y, &F.y);
-            if (l < L) {
-                up_csr(c, H.P, &D.Pp, &D.Pj, &D.Pv, &F.Pp, &F.Pj, &F.Pv);
-                up_csr(c, H.R, &D.Rp, &D.Rj, &D.Rv, &F.Rp, &F.Rj, &F.Rv);
-                D.gP = F.gP = lanes_for(H.P);
-                D.gR = F.gR = lanes_for(H.R);
-            }
-        } else if (l < L) {
-            // Q = P - omega D^-1 (A P); down = Q^T; up = [S | Q] with S =
-            // 2 omega D^-1 - omega^2 D^-1 A D^-1
-            const double w = H.omega;
-            Csr Q;
-            Q.n = H.P.n;
-            Q.ncols = H.P.ncols;
-            Q.p.assign(Q.n + 1, 0);
-            for (int i = 0; i < Q.n; ++i) {
-                int64_t e = H.P.p[i], f = H.AP.p[i];
-                const int64_t e1 = H.P.p[i + 1], f1 = H.AP.p[i + 1];
-                while (e < e1 || f < f1) {
-                    const int ce = e < e1 ? H.P.j[e] : 0x7fffffff, cf = f < f1 ? H.AP.j[f] : 0x7fffffff;
-                    const int col = std::min(ce, cf);
-                    double v = 0.0;
-                    if (ce == col) v += H.P.v[e++];
-                    if (cf == col) v -= w * H.AP.v[f++] / H.d[i];
-                    if (v != 0.0) {
-                        Q.j.push_back(col);
-                        Q.v.push_back(v);
-                    }
-                }
-                Q.p[i + 1] = (int64_t)Q.j.size();
-            }
-            const Csr Dn = transpose(Q);
-            Csr U;
-            U.n = H.A.n;
-            U.ncols = H.A.n + Q.ncols;
-            U.p.assign(U.n + 1, 0);
-            for (int i = 0; i < U.n; ++i) {
-                for (int64_t e = H.A.p[i]; e < H.A.p[i + 1]; ++e) {
-                    const int j = H.A.j[e];
-                    double v = -(w * w) * H.A.v[e] / (H.d[i] * H.d[j]);
-                    if (j == i) v += 2.0 * w / H.d[i];
-                    if (v != 0.0) {
-                        U.j.push_back(j);
-                        U.v.push_back(v);
-                    }
-                }
-                for (int64_t e = Q.p[i]; e < Q.p[i + 1]; ++e) {
-                    U.j.push_back(H.A.n + Q.j[e]);
-                    U.v.push_back(Q.v[e]);
-                }
-                U.p[i + 1] = (int64_t)U.j.size();
-            }
-            up_csr(c, Dn, &D.Dp, &D.Dj, &D.Dv, &F.Dp, &F.Dj, &F.Dv);
-            up_csr(c, U, &D.Up, &D.Uj, &D.Uv, &F.Up, &F.Uj, &F.Uv);
-            D.gD = F.gD = lanes_for(Dn);
-            D.gU = F.gU = lanes_for(U);
-            // [b_l; y_{l+1}] in one array
-            const size_t nb = (size_t)H.A.n + S->lv[l + 1].A.n;
-            double *d64;
-            float *d32;
-            vec2(nb, &d64, &d32);
-            D.b = d64;
-            F.b = d32;
-            S->g64.lv[l + 1].y = d64 + H.A.n;
-            S->g32.lv[l + 1].y = d32 + H.A.n;
-            if (l == 1) vec2((size_t)H.A.n, &D.y, &F.y);
-            for (int k = 0; k < 2; ++k) {
-                const double v = k ? 4.0 : 8.0;
-                (k ? b32 : b64) += (double)(Dn.nnz() + U.nnz()) * (v + 4) + 3.0 * n * v;
-            }
+    // per instance fine smoothing weight; level 0 work vectors
+    {
+        std::vector<double> om(ni), wd(N[0], 0.0);
+        for (int i = 0; i < ni; ++i) {
+            const HostLevel &H0 = S->H[i][0];
+            om[i] = H0.omega;
+            for (int r = 0; r < H0.A.n; ++r) wd[off[0][i] + r] = H0.omega / H0.d[r];
         }
-        if (l == L) {
-            // rows padded to a multiple of 4 values (16 bytes in FP32, 32 in FP64)
-            const int ld = (H.A.n + 3) / 4 * 4;
-            std::vector<double> pad((size_t)H.A.n * ld, 0.0);
-            for (int i = 0; i < H.A.n; ++i)
-                std::copy(H.Ainv.begin() + (size_t)i * H.A.n, H.Ainv.begin() + (size_t)(i + 1) * H.A.n,
-                          pad.begin() + (size_t)i * ld);
-            D.Ainv = upload_v(c, pad);
-            F.Ainv = upload_v(c, to32(pad));
-            D.ld = F.ld = ld;
-            if (l > 0) {
-                // the right-hand side is read 16 bytes at a time up to ld (zero padding)
-                vec2((size_t)ld, &D.b, &F.b);
-                if (l == 1) vec2((size_t)H.A.n, &D.y, &F.y);
-            }
-            for (int k = 0; k < 2; ++k) {
-                const double v = k ? 4.0 : 8.0;
-                (k ? b32 : b64) += n * n * v + 2.0 * n * v;
-            }
-        }
-        if (l == 0 && l < L) {
-            // fine level: K three times (the iteration, the post-smoothing,
-            // w = K u), R and P once each, and 17 vector passes
-            const double nP = (double)H.P.nnz();
-            for (int k = 0; k < 2; ++k) {
-                const double v = k ? 4.0 : 8.0;
-                (k ? b32 : b64) += 3.0 * nA * (v + 4) + 2.0 * nP * (v + 4) + 17.0 * n * v;
-            }
-        }
-        H.AP = Csr();
+        D.omega = upload_v(c, om);
+        F.omega = upload_v(c, to32(om));
+        D.lv[0].wd = upload_v(c, wd);
+        F.lv[0].wd = upload_v(c, to32(wd));
+        D.lv[0].n = F.lv[0].n = N[0];
+        vec2(N[0], &D.lv[0].t, &F.lv[0].t);
+        vec2(N[0], &D.lv[0].z, &F.lv[0].z);
+        vec2(N[0], &D.lv[0].b, &F.lv[0].b);  // staging of mm_amg_apply
+        vec2(N[0], &D.lv[0].y, &F.lv[0].y);
     }
-    S->g64.u = dalloc_n<double>(c, RP);
-    S->g32.u = dalloc_n<float>(c, RP);
-    HIPCHK(hipMemsetAsync(S->g64.u, 0, RP * sizeof(double), c->stream));
-    HIPCHK(hipMemsetAsync(S->g32.u, 0, RP * sizeof(float), c->stream));
+    // level 0 transfer
+    if (nlev > 1) {
+        std::vector<GBlock> bl;
+        for (int i = 0; i < ni; ++i) {
+            const int c0 = off[1][i];
+            bl.push_back(GBlock{off[0][i], &S->H[i][0].P, [c0](int j) { return c0 + j; }});
+        }
+        const Csr P = concat(N[0], N[1], bl);
+        const Csr R = transpose(P);
+        up_csr(c, P, &D.lv[0].Pp, &D.lv[0].Pj, &D.lv[0].Pv, &F.lv[0].Pp, &F.lv[0].Pj, &F.lv[0].Pv);
+        up_csr(c, R, &D.lv[0].Rp, &D.lv[0].Rj, &D.lv[0].Rv, &F.lv[0].Rp, &F.lv[0].Rj, &F.lv[0].Rv);
+        D.lv[0].gP = F.lv[0].gP = lanes_for(P);
+        D.lv[0].gR = F.lv[0].gR = lanes_for(R);
+    }
+    // coarse levels: right-hand sides and results, fused operators, dense solves
+    for (int l = 1; l < nlev; ++l) {
+        AmgLevel<double> &d = D.lv[l];
+        AmgLevel<float> &f = F.lv[l];
+        d.n = f.n = N[l];
+        double *b64;
+        float *b32;
+        const size_t nb = (size_t)N[l] + (l + 1 < nlev ? N[l + 1] : 0) + 4;
+        vec2(nb, &b64, &b32);
+        d.b = b64;
+        f.b = b32;
+        if (l + 1 < nlev) {
+            D.lv[l + 1].y = b64 + N[l];
+            F.lv[l + 1].y = b32 + N[l];
+        }
+        if (l == 1) vec2((size_t)N[1], &d.y, &f.y);
+        if (l + 1 < nlev) {
+            std::vector<Csr> Q(ni), Dn(ni), U(ni);
+            std::vector<GBlock> bd, bu;
+            for (int i = 0; i < ni; ++i) {
+                if (L_of(i) <= l) continue;  // this instance ends on this level or above
+                const HostLevel &H = S->H[i][l];
+                Q[i] = smoothed_transfer(H);
+                Dn[i] = transpose(Q[i]);
+                U[i] = side_by_side(smoother_pair(H), Q[i], H.A.n);
+                const int cb = off[l][i], cy = N[l] + off[l + 1][i], n_l = H.A.n;
+                bd.push_back(GBlock{off[l + 1][i], &Dn[i], [cb](int j) { return cb + j; }});
+                bu.push_back(GBlock{off[l][i], &U[i], [cb, cy, n_l](int j) { return j < n_l ? cb + j : cy + (j - n_l); }});
+            }
+            const Csr Dg = concat(N[l + 1], N[l], bd);
+            const Csr Ug = concat(N[l], N[l] + N[l + 1], bu);
+            up_csr(c, Dg, &d.Dp, &d.Dj, &d.Dv, &f.Dp, &f.Dj, &f.Dv);
+            up_csr(c, Ug, &d.Up, &d.Uj, &d.Uv, &f.Up, &f.Uj, &f.Uv);
+            d.gD = f.gD = lanes_for(Dg);
+            d.gU = f.gU = lanes_for(Ug);
+        }
+    }
+    // dense tables: the instances whose coarsest level is l
+    for (int l = 0; l < nlev; ++l) {
+        std::vector<int> dinst, drow0, dn, dld, dboff;
+        std::vector<int64_t> daoff;
+        std::vector<double> inv;
+        int rows = 0;
+        for (int i = 0; i < ni; ++i) {
+            if (L_of(i) != l) continue;
+            const HostLevel &H = S->H[i][l];
+            const int n = H.A.n, ld = pad4(n), k = (int)dn.size();
+            drow0.push_back(rows);
+            dn.push_back(n);
+            dld.push_back(ld);
+            daoff.push_back((int64_t)inv.size());
+            dboff.push_back(l == 0 ? 0 : off[l][i]);
+            for (int r = 0; r < n; ++r) {
+                dinst.push_back(k);
+                const size_t at = inv.size();
+                inv.resize(at + ld, 0.0);
+                std::copy(H.Ainv.begin() + (size_t)r * n, H.Ainv.begin() + (size_t)(r + 1) * n, inv.begin() + at);
+            }
+            rows += n;
+        }
+        if (rows == 0) continue;
+        const int *di = upload_v(c, dinst), *r0 = upload_v(c, drow0), *nn = upload_v(c, dn), *lds = upload_v(c, dld),
+                  *bo = upload_v(c, dboff);
+        const int64_t *ao = upload_v(c, daoff);
+        D.lv[l].ndense = F.lv[l].ndense = rows;
+        D.lv[l].dinst = F.lv[l].dinst = di;
+        D.lv[l].drow0 = F.lv[l].drow0 = r0;
+        D.lv[l].dn = F.lv[l].dn = nn;
+        D.lv[l].dld = F.lv[l].dld = lds;
+        D.lv[l].dboff = F.lv[l].dboff = bo;
+        D.lv[l].daoff = F.lv[l].daoff = ao;
+        D.lv[l].Ainv = upload_v(c, inv);
+        F.lv[l].Ainv = upload_v(c, to32(inv));
+    }
+    D.u = dalloc_n<double>(c, N[0]);
+    F.u = dalloc_n<float>(c, N[0]);
+    HIPCHK(hipMemsetAsync(D.u, 0, (size_t)N[0] * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(F.u, 0, (size_t)N[0] * sizeof(float), c->stream));
     sync(c);
-    S->bytes64 = b64;
-    S->bytes32 = b32;
-    // mixed form: FP32 matrices and cycle, FP64 CG vectors on the fine level
-    // (the 17 fine vector passes at 8 instead of 4 bytes)
-    S->bytesmix = b32 + (nl > 1 ? 17.0 * 4.0 * (double)S->lv[0].A.n : 0.0);
+    // algorithmic bytes of one CG iteration per instance: the fine matrix
+    // three times (the iteration, the post-smoothing, w = K u), P and R once
+    // each and 17 vector passes on the fine level; the two fused operators and
+    // 3 vector passes on each further level; the dense inverse of the coarsest
+    for (int k = 0; k < 3; ++k) S->bytes[k].assign(ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        const std::vector<HostLevel> &Hi = S->H[i];
+        const int L = L_of(i);
+        for (int k = 0; k < 2; ++k) {
+            const double v = k ? 4.0 : 8.0;
+            double by = 0;
+            for (int l = 0; l <= L; ++l) {
+                const HostLevel &H = Hi[l];
+                const double n = (double)H.A.n;
+                if (l == L) {
+                    by += n * n * v + 2.0 * n * v;
+                } else if (l == 0) {
+                    by += 3.0 * (double)c->inst[i].nnz_K * (v + 4) + 2.0 * (double)H.P.nnz() * (v + 4) + 17.0 * n * v;
+                } else {
+                    // the fused operators: Q^T (nnz of AP, P) and [S | Q]
+                    const double nq = (double)std::max(H.AP.nnz(), H.P.nnz());
+                    by += (2.0 * nq + (double)H.A.nnz()) * (v + 4) + 3.0 * n * v;
+                }
+            }
+            S->bytes[k][i] = by;
+        }
+        S->bytes[2][i] = S->bytes[1][i] + (L > 0 ? 17.0 * 4.0 * (double)Hi[0].A.n : 0.0);
+    }
+    for (auto &Hi : S->H)
+        for (auto &H : Hi) H.AP = Csr();
     S->setup_seconds = now_s() - t0;
     c->amg = S.release();
     return c->amg;
@@ -521,7 +661,7 @@ AmgState *amg_get(mm_ctx *c) {
 
 const AmgLaunch<double> &amg_launch64(AmgState *s) { return s->g64; }
 const AmgLaunch<float> &amg_launch32(AmgState *s) { return s->g32; }
-double amg_bytes(AmgState *s, int form) { return form == 2 ? s->bytesmix : form == 1 ? s->bytes32 : s->bytes64; }
+const std::vector<double> &amg_bytes(AmgState *s, int form) { return s->bytes[form]; }
 
 }  // namespace mmncg
 
@@ -534,13 +674,13 @@ int mm_amg_info(mm_ctx *c, int *n_levels, long *rows, long *nnz_A, long *nnz_P, 
         require_single(c);
         if (!n_levels) throw ApiError{MM_EINVAL, "null n_levels"};
         AmgState *S = amg_get(c);
-        const int nl = (int)S->lv.size();
+        const int nl = (int)S->H[0].size();
         *n_levels = nl;
         for (int l = 0; l < kAmgMaxLevels; ++l) {
             const bool in = l < nl;
-            if (rows) rows[l] = in ? S->lv[l].A.n : 0;
-            if (nnz_A) nnz_A[l] = in ? (long)S->lv[l].A.nnz() : 0;
-            if (nnz_P) nnz_P[l] = in ? (long)S->lv[l].P.nnz() : 0;
+            if (rows) rows[l] = in ? S->H[0][l].A.n : 0;
+            if (nnz_A) nnz_A[l] = in ? (long)S->H[0][l].A.nnz() : 0;
+            if (nnz_P) nnz_P[l] = in ? (long)S->H[0][l].P.nnz() : 0;
         }
         if (setup_seconds) *setup_seconds = S->setup_seconds;
         return MM_OK;
@@ -551,9 +691,9 @@ int mm_amg_aggregates(mm_ctx *c, int level, int *agg) {
     return guarded(c, [&] {
         require_single(c);
         AmgState *S = amg_get(c);
-        if (!agg || level < 0 || level + 1 >= (int)S->lv.size())
+        if (!agg || level < 0 || level + 1 >= (int)S->H[0].size())
             throw ApiError{MM_EINVAL, "level must have a coarser level below it"};
-        std::memcpy(agg, S->lv[level].agg.data(), S->lv[level].agg.size() * sizeof(int));
+        std::memcpy(agg, S->H[0][level].agg.data(), S->H[0][level].agg.size() * sizeof(int));
         return MM_OK;
     });
 }
@@ -562,8 +702,8 @@ int mm_amg_level_matrix(mm_ctx *c, int level, int which, long *ptr, int *col, do
     return guarded(c, [&] {
         require_single(c);
         AmgState *S = amg_get(c);
-        if (level < 0 || level >= (int)S->lv.size()) throw ApiError{MM_EINVAL, "no such level"};
-        const HostLevel &H = S->lv[level];
+        if (level < 0 || level >= (int)S->H[0].size()) throw ApiError{MM_EINVAL, "no such level"};
+        const HostLevel &H = S->H[0][level];
         const Csr *m = which == 0 ? &H.A : which == 1 ? &H.P : nullptr;
         if (!m || m->p.empty()) throw ApiError{MM_EINVAL, "which: 0 = level operator, 1 = prolongator (not on the coarsest level)"};
         if (ptr)

@@ -23,8 +23,11 @@
 //   k_amg_w        w = K u into the records, partials delta and r.r.
 // Every kernel of an iteration returns at once when the instance's sticky
 // flag is up (the flag only changes inside k_amg_iter, which every later
-// launch follows in stream order). Vector type VT is double (FP64 mode) or
-// float (inner solve of the FP32-bulk mode); reductions are FP64.
+// launch follows in stream order); in a batch the row-map kernels check their
+// instance's flag and the cycle's CSR and dense kernels run for every
+// instance (a converged instance's cycle is computed and not used). The
+// cycle runs in VT (double in the FP64 mode, float in the mixed form of the
+// FP32-bulk mode) and the CG vectors in RT (double); reductions are FP64.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -70,51 +73,61 @@ __global__ __launch_bounds__(kAB) void k_amg_spmv(int n, const int *__restrict__
     const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
     if (row >= n) return;
     const VT s = csr_row<GL>(p, j, v, x, row, gl);
-    if (gl == 0) y[row] = s;
+    // rows without entries (padding; instances solved densely on this level) are not written
+    if (gl == 0 && p[row + 1] > p[row]) y[row] = s;
 }
 
-// z = omega D^-1 b + P y on the fine level (b at b[row * bs]: bs = 4 for the
-// r field of the CG records, whose type RT may be wider than the cycle's VT)
+// z = omega D^-1 b + P y on the fine level, omega D^-1 per row in wd (b at
+// b[row * bs]: bs = 4 for the r field of the CG records, whose type RT may be
+// wider than the cycle's VT)
 template <class VT, class RT, int GL>
 __global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restrict__ p, const int *__restrict__ j,
-                                                     const VT *__restrict__ v, const VT *__restrict__ dinv, VT omega,
+                                                     const VT *__restrict__ v, const VT *__restrict__ wd,
                                                      const RT *__restrict__ b, int bs, const VT *__restrict__ yc,
                                                      VT *__restrict__ z, const int *done) {
     if (skip(done)) return;
     const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
     if (row >= n) return;
     const VT s = csr_row<GL>(p, j, v, yc, row, gl);
-    if (gl == 0) z[row] = omega * dinv[row] * (VT)b[(int64_t)row * bs] + s;
+    if (gl == 0) z[row] = wd[row] * (VT)b[(int64_t)row * bs] + s;
 }
 
-// y = Ainv b on the coarsest level: one wave per row of the dense inverse
-// (rows ld apart, ld a multiple of 16 bytes, padding zero). With a plain b
-// (bs = 1, also padded to ld with zeros) every lane loads 16 bytes of the row
-// and of b at a time; with b in the CG records (bs = 4), one value.
+// y = Ainv b for the instances whose coarsest level this is: one wave per
+// dense row; row r is row r - drow0[k] of table entry k = dinst[r], whose
+// inverse starts at daoff[k] (rows dld[k] apart, a multiple of 4 values,
+// padding zero) and whose b and y rows start at row dboff[k] of the level.
+// With a plain b (bs = 1; each instance's block padded to dld with zeros)
+// every lane loads 16 bytes of the row and of b at a time; with b in the CG
+// records (bs = 4), one value.
 template <class VT, class BT>
-__global__ __launch_bounds__(kAB) void k_amg_dense(int n, int ld, const VT *__restrict__ Ainv,
+__global__ __launch_bounds__(kAB) void k_amg_dense(int nrows, const int *__restrict__ dinst,
+                                                   const int *__restrict__ drow0, const int *__restrict__ dn,
+                                                   const int *__restrict__ dld, const int64_t *__restrict__ daoff,
+                                                   const int *__restrict__ dboff, const VT *__restrict__ Ainv,
                                                    const BT *__restrict__ b, int bs, VT *__restrict__ y,
                                                    const int *done) {
     if (skip(done)) return;
-    const int row = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
-    if (row >= n) return;
-    const VT *a = Ainv + (int64_t)row * ld;
+    const int r = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
+    if (r >= nrows) return;
+    const int k = dinst[r], row = r - drow0[k], n = dn[k], ld = dld[k], bo = dboff[k];
+    const VT *a = Ainv + daoff[k] + (int64_t)row * ld;
+    const BT *bb = b + (int64_t)bo * bs;
     VT acc = 0;
     if (bs == 1) {
         constexpr int V = 16 / sizeof(VT);
         typedef VT vec __attribute__((ext_vector_type(V)));
         const vec *av = (const vec *)a;
-        const vec *bv = (const vec *)b;
-        for (int k = ln; k < ld / V; k += 64) {
-            const vec x = av[k], z = bv[k];
+        const vec *bv = (const vec *)bb;
+        for (int q = ln; q < ld / V; q += 64) {
+            const vec x = av[q], w = bv[q];
 #pragma unroll
-            for (int q = 0; q < V; ++q) acc += x[q] * z[q];
+            for (int e = 0; e < V; ++e) acc += x[e] * w[e];
         }
     } else {
-        for (int c = ln; c < n; c += 64) acc += a[c] * (VT)b[(int64_t)c * bs];
+        for (int c = ln; c < n; c += 64) acc += a[c] * (VT)bb[(int64_t)c * bs];
     }
     acc = group_sum<64>(acc);
-    if (ln == 0) y[row] = acc;
+    if (ln == 0) y[bo + row] = acc;
 }
 
 // one SELL row of K times x (and optionally times y entrywise: sum K_ac y_c
@@ -150,14 +163,15 @@ __device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const V
 
 // fine level, start of a cycle from a residual that is not produced by
 // k_amg_iter (the CG start, or a plain vector): t = r - omega K D^-1 r with r
-// at r[row * rs]. With q given (the CG start), also sets w = s = 0 and d =
+// at r[row * rs] and the instance's omega. With q given (the CG start), also sets w = s = 0 and d =
 // D^-1 in the records q (the r fields are left alone: neighbours read them).
 template <class MT, class VT, class CT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
-                                                      const VT *__restrict__ invD, VT omega, CT *__restrict__ t,
-                                                      PcgNode<VT> *__restrict__ q) {
+                                                      const VT *__restrict__ invD, const VT *__restrict__ om,
+                                                      CT *__restrict__ t, PcgNode<VT> *__restrict__ q) {
     Tile tl = tile_of(M);
     if (tl.inst < 0) return;
+    const VT omega = om[tl.inst];
     const int rend = M.rend[tl.inst], ln = lane_id();
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
         const VT acc = row_gather<MT, VT, true>(K, s, ln, r, rs, invD);
@@ -173,16 +187,18 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
     }
 }
 
-// fine level: u = z + omega D^-1 (r - K z) in the cycle's type VT, stored as
-// the CG's type RT; partial gamma = r.u of the stored values into slot gslot
-// (skipped when part is null)
+// fine level: u = z + omega D^-1 (r - K z) (omega D^-1 per row in wd; with wd
+// null, u = z: a single dense level) in the cycle's type VT, stored as the
+// CG's type RT; partial gamma = r.u of the stored values into slot gslot
+// (skipped when part is null); instances whose flag is up are skipped when
+// st is given
 template <class MT, class VT, class RT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const RT *__restrict__ r, int rs,
-                                                       const VT *__restrict__ invD, VT omega,
-                                                       const VT *__restrict__ z, RT *__restrict__ u,
-                                                       double *__restrict__ part, int gslot, const int *done) {
+                                                       const VT *__restrict__ wd, const VT *__restrict__ z,
+                                                       RT *__restrict__ u, double *__restrict__ part, int gslot,
+                                                       const PcgState *st) {
     Tile tl = tile_of(M);
-    if (tl.inst < 0 || skip(done)) return;
+    if (tl.inst < 0 || (st && st[tl.inst].done)) return;
     __shared__ double sh[NW];
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[1] = {0};
@@ -191,7 +207,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
         const int row = s * 64 + ln;
         if (row < rend) {
             const RT ri = r[(int64_t)row * rs];
-            const RT ui = (RT)(z[row] + omega * invD[row] * ((VT)ri - kz));
+            const RT ui = wd ? (RT)(z[row] + wd[row] * ((VT)ri - kz)) : (RT)z[row];
             u[row] = ui;
             acc[0] += (double)ri * (double)ui;
         }
@@ -205,9 +221,9 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
 template <class MT, class VT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
                                                    const VT *__restrict__ u, double *__restrict__ part, int wslot,
-                                                   const int *done) {
+                                                   const PcgState *st) {
     Tile tl = tile_of(M);
-    if (tl.inst < 0 || skip(done)) return;
+    if (tl.inst < 0 || (st && st[tl.inst].done)) return;
     __shared__ double sh[NW * 2];
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[2] = {0, 0};
@@ -262,7 +278,8 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
 // alpha (B + beta C) with A, B, C the products of K D^-1 with the old r, w, s
 template <class MT, class VT, class XT, class CT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
-                                                      const VT *__restrict__ uu, CT *__restrict__ tt, VT omega,
+                                                      const VT *__restrict__ uu, CT *__restrict__ tt,
+                                                      const VT *__restrict__ om,
                                                       PcgState *__restrict__ st, int par,
                                                       const double *__restrict__ part) {
     Tile tl = tile_of(M);
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
         si->alpha[par] = alpha;
         si->iters += 1;
     }
-    const VT a = (VT)alpha, bt = (VT)beta;
+    const VT a = (VT)alpha, bt = (VT)beta, omega = om[tl.inst];
     for (int s = sf; s < tl.s1; s += NW) {
         if (s != sf) row_abc(K, s, ln, q0, pa, pb, pc);
         const int row = s * 64 + ln;
@@ -372,13 +389,29 @@ dim3 grid_rows(int n) {
     return dim3((unsigned)((th + kAB - 1) / kAB));
 }
 
-// the cycle below the fine level: restriction of t0, the fused operators of
-// levels 1..L-1 down, the dense solve, the fused operators up, and the
-// prolongation back to z0 (r0 at r[row * rs], of the CG's type RT)
+template <class VT, class BT>
+void dense(const AmgLevel<VT> &lv, const BT *b, int bs, VT *y, const int *done, hipStream_t s) {
+    if (lv.ndense > 0)
+        hipLaunchKernelGGL((k_amg_dense<VT, BT>), dim3((unsigned)((lv.ndense + kAB / 64 - 1) / (kAB / 64))),
+                           dim3(kAB), 0, s, lv.ndense, lv.dinst, lv.drow0, lv.dn, lv.dld, lv.daoff, lv.dboff,
+                           lv.Ainv, b, bs, y, done);
+}
+
+// everything between the fine pre-smoothing and the fine post-smoothing:
+// z0 = omega D^-1 r + P V(P^T t0) with r at r[row * rs] (of the CG's type RT):
+// the restriction, the fused operators of the coarse levels down, the dense
+// solves of the instances that end on each level, the fused operators up,
+// and the prolongation. With a single level (one instance, n_pot small),
+// z0 = K^-1 r from the dense inverse.
 template <class VT, class RT>
-void coarse_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
+void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
+    const AmgLevel<VT> &f = g.lv[0];
+    if (g.nlev == 1) {
+        dense(f, r, rs, f.z, done, s);
+        return;
+    }
     const int L = g.nlev - 1;
-    const AmgLevel<VT> &f = g.lv[0], &c1 = g.lv[1];
+    const AmgLevel<VT> &c1 = g.lv[1];
     MMNCG_GL_SWITCH(f.gR, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c1.n), dim3(kAB), 0, s, c1.n, f.Rp,
                                              f.Rj, f.Rv, (const VT *)f.t, c1.b, done))
     for (int l = 1; l < L; ++l) {
@@ -386,48 +419,33 @@ void coarse_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, 
         MMNCG_GL_SWITCH(a.gD, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c.n), dim3(kAB), 0, s, c.n,
                                                  a.Dp, a.Dj, a.Dv, (const VT *)a.b, c.b, done))
     }
-    const AmgLevel<VT> &cl = g.lv[L];
-    hipLaunchKernelGGL((k_amg_dense<VT, VT>), dim3((unsigned)((cl.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB), 0,
-                       s, cl.n, cl.ld, cl.Ainv, (const VT *)cl.b, 1, cl.y, done);
-    for (int l = L - 1; l >= 1; --l) {
+    for (int l = L; l >= 1; --l) {
         const AmgLevel<VT> &a = g.lv[l];
+        dense(a, (const VT *)a.b, 1, a.y, done, s);
         // [b_l; y_{l+1}] is one array starting at b_l
-        MMNCG_GL_SWITCH(a.gU, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(a.n), dim3(kAB), 0, s, a.n,
-                                                 a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, done))
+        if (l < L)
+            MMNCG_GL_SWITCH(a.gU, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(a.n), dim3(kAB), 0, s, a.n,
+                                                     a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, done))
     }
     MMNCG_GL_SWITCH(f.gP, hipLaunchKernelGGL((k_amg_prolong<VT, RT, GL>), grid_rows<GL>(f.n), dim3(kAB), 0, s, f.n,
-                                             f.Pp, f.Pj, f.Pv, f.dinv, f.omega, r, rs, (const VT *)c1.y, f.z, done))
-}
-
-// everything between the fine pre-smoothing and the fine post-smoothing:
-// z0 = omega D^-1 r + P V(P^T t0); with a single level, z0 = K^-1 r from the
-// dense inverse (and the post-smoothing weight is 0, see post_omega)
-template <class VT, class RT>
-void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
-    const AmgLevel<VT> &f = g.lv[0];
-    if (g.nlev > 1) {
-        coarse_cycle(g, r, rs, done, s);
-    } else if (f.n > 0) {
-        hipLaunchKernelGGL((k_amg_dense<VT, RT>), dim3((unsigned)((f.n + kAB / 64 - 1) / (kAB / 64))), dim3(kAB),
-                           0, s, f.n, f.ld, f.Ainv, r, rs, f.z, done);
-    }
-}
-
-template <class VT>
-VT post_omega(const AmgLaunch<VT> &g) {
-    return g.nlev > 1 ? g.lv[0].omega : (VT)0;
+                                             f.Pp, f.Pj, f.Pv, (const VT *)f.wd, r, rs, (const VT *)c1.y, f.z, done))
 }
 
 // The fine-level vectors of the CG (records, direction, u) are of type RT;
 // the cycle and the stored fine matrix used inside it and by the CG are of
-// type VT (VT = RT in the FP64 and FP32 solves; VT = float, RT = double in
+// type VT (VT = RT = double in the FP64 solve; VT = float, RT = double in
 // the mixed solve: FP32-stored operators and cycle, FP64 Krylov vectors).
 template <class VT, class RT>
 struct FineArgs {
     const RT *invD;    // D^-1 of the records
-    RT omega;          // fine smoothing weight in RT
+    const RT *omega;   // per instance, the fine smoothing weight in RT
     RT *u;             // preconditioned residual
 };
+
+template <class VT>
+const VT *post_wd(const AmgLaunch<VT> &g) {
+    return g.nlev > 1 ? g.lv[0].wd : nullptr;
+}
 
 // one cycle on the fine level from the residual r (at r[row * rs]) into u;
 // with a CG, also the records' start fields (q) and the partials of the
@@ -442,12 +460,12 @@ void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, R
                                              view<VT>(*a.K), M, r, rs, fa.invD, fa.omega, f.t, q))
     lower_cycle(g, r, rs, nullptr, s);
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, r, rs, f.dinv, post_omega(g), (const VT *)f.z, fa.u,
-                                             cg ? a.part : (double *)nullptr, kP0, (const int *)nullptr))
+                                             view<VT>(*a.K), M, r, rs, post_wd(g), (const VT *)f.z, fa.u,
+                                             cg ? a.part : (double *)nullptr, kP0, (const PcgState *)nullptr))
     if (cg)
         MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                                  view<VT>(*a.K), M, q, (const RT *)fa.u, a.part, kP0 + 1,
-                                                 (const int *)nullptr))
+                                                 (const PcgState *)nullptr))
 }
 
 template <class VT, class RT, class XT>
@@ -455,7 +473,9 @@ void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT>
               int par, hipStream_t s) {
     const RowMap &M = *a.M;
     const AmgLevel<VT> &f = g.lv[0];
-    const int *done = &a.st[0].done;
+    // one instance: every kernel of the chain reads its flag; a batch: the
+    // row-map kernels read their instance's
+    const int *done = g.batch ? nullptr : &a.st[0].done;
     PcgNode<RT> *q1 = v.q[par ^ 1];
     const int ws = par ? kP0 : kP1;  // this iteration's new partials
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
@@ -463,20 +483,21 @@ void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT>
                                              (const double *)a.part))
     lower_cycle(g, (const RT *)&q1->r, 4, done, s);
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, f.dinv, post_omega(g),
-                                             (const VT *)f.z, fa.u, a.part, ws, done);
+                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, post_wd(g), (const VT *)f.z,
+                                             fa.u, a.part, ws, (const PcgState *)a.st);
                     hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1, done))
+                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1,
+                                       (const PcgState *)a.st))
 }
 
 FineArgs<double, double> fine64(const PcgLaunch &a, const AmgLaunch<double> &g) {
-    return FineArgs<double, double>{a.invD, g.lv[0].omega, g.u};
+    return FineArgs<double, double>{a.invD, g.omega, g.u};
 }
 FineArgs<float, float> fine32(const PcgLaunch &a, const AmgLaunch<float> &g) {
-    return FineArgs<float, float>{a.invD32, g.lv[0].omega, g.u};
+    return FineArgs<float, float>{a.invD32, g.omega, g.u};
 }
 FineArgs<float, double> finemix(const PcgLaunch &a, const AmgLaunch<double> &g64) {
-    return FineArgs<float, double>{a.invD, g64.lv[0].omega, g64.u};
+    return FineArgs<float, double>{a.invD, g64.omega, g64.u};
 }
 
 }  // namespace

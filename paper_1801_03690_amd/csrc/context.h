@@ -128,9 +128,9 @@ struct mm_ctx {
     double *mpart = nullptr;    // magnet-row partials, MS_TOTAL slots
     double *ppart = nullptr;    // potential-row partials, kPcgSlots slots
     hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-    // multigrid preconditioner (single-instance contexts): host copy of the
-    // scalar-potential matrix, the hierarchy once built, its captured graphs
-    HostCsr hostK;
+    // multigrid preconditioner: host copies of the scalar-potential matrices,
+    // the hierarchies once built, their captured graphs
+    std::vector<HostCsr> hostK;  // per instance
     mmncg::AmgState *amg = nullptr;
     hipGraphExec_t agraph64 = nullptr, mgraph = nullptr;
 
@@ -195,7 +195,8 @@ AmgState *amg_get(mm_ctx *c);   // builds the hierarchy on first use
 void amg_release(mm_ctx *c);
 const AmgLaunch<double> &amg_launch64(AmgState *s);
 const AmgLaunch<float> &amg_launch32(AmgState *s);
-double amg_bytes(AmgState *s, int form);  // algorithmic bytes of one CG iteration: 0 FP64, 1 FP32, 2 mixed
+// algorithmic bytes of one CG iteration per instance: form 0 FP64, 1 FP32, 2 mixed
+const std::vector<double> &amg_bytes(AmgState *s, int form);
 void load_m(mm_ctx *c, const double *m);
 void reduce_field(const InstInfo &I, const double *BT, double h[3]);
 void eval_all(mm_ctx *c, const mm_opts &o, const std::vector<double> &h);

@@ -195,41 +195,53 @@ void launch_pcg_start32_only(const PcgLaunch &a, hipStream_t s);
 void launch_pcg_fin(const PcgLaunch &a, const int *act, double rtol2, int mode, hipStream_t s);
 
 // --- algebraic multigrid preconditioner of the scalar-potential CG (amg.hip) ---
-// Level l of the smoothed-aggregation hierarchy (device pointers). Level 0
-// is the scalar-potential matrix itself (the SELL matrix K of the CG), with
-// P (prolongation from level 1, CSR over the rows of level 0) and R = P^T.
-// A level 0 < l < L (L the coarsest) carries its cycle as two fused
-// operators: down, b_{l+1} = Dn b_l with Dn = P^T (I - omega A D^-1); up,
-// y_l = Up [b_l; y_{l+1}] with Up = [S | Q], S = 2 omega D^-1 - omega^2
-// D^-1 A D^-1, Q = (I - omega D^-1 A) P (the two damped-Jacobi sweeps and
-// the coarse correction of a V(1,1) cycle, multiplied out). b_l and y_{l+1}
-// are adjacent in memory. The coarsest level holds its dense inverse.
+// Level l of the smoothed-aggregation hierarchies of all instances (device
+// pointers). Every instance has its own hierarchy; level l of the launch is
+// the concatenation of the instances' level-l rows, each instance's block
+// padded to a multiple of 4 rows (level 0: the potential row space of the
+// row map). Level 0 is the scalar-potential matrix itself (the SELL matrix K
+// of the CG) with P (prolongation from level 1, CSR over the level-0 rows)
+// and R = P^T (rows of level 1). On a level 0 < l < L_i of instance i the
+// V(1,1) step is two fused operators: down, b_{l+1} = Dn b_l with Dn = P^T
+// (I - omega A D^-1); up, y_l = Up [b_l; y_{l+1}] with Up = [S | Q], S =
+// 2 omega D^-1 - omega^2 D^-1 A D^-1, Q = (I - omega D^-1 A) P (the two
+// damped-Jacobi sweeps and the coarse correction multiplied out). The b
+// part of level l and the y part of level l+1 are one array (b at its start,
+// y after the level's rows). Instances whose coarsest level is l solve it
+// with their dense inverse (rows ld apart, ld = rows padded to 4; padding
+// zero), listed in a table: dense row r belongs to entry dinst[r], whose
+// rows start at drow0, number dn, lie at row dboff of the level's b and y,
+// and whose inverse starts at daoff.
 constexpr int kAmgMaxLevels = 12;
 template <class VT>
 struct AmgLevel {
-    int n = 0;
-    const VT *dinv = nullptr;  // 1 / a_ii (level 0)
-    VT omega = 0;              // damped-Jacobi weight
+    int n = 0;                 // rows of the level (padded blocks)
+    const VT *wd = nullptr;    // level 0: omega_i / a_ii per row (0 on padding)
     const int *Pp = nullptr, *Pj = nullptr;  // level 0
     const VT *Pv = nullptr;
     const int *Rp = nullptr, *Rj = nullptr;
     const VT *Rv = nullptr;
-    const int *Dp = nullptr, *Dj = nullptr;  // 0 < l < L
+    const int *Dp = nullptr, *Dj = nullptr;  // levels 1 .. nlev - 2
     const VT *Dv = nullptr;
     const int *Up = nullptr, *Uj = nullptr;
     const VT *Uv = nullptr;
-    const VT *Ainv = nullptr;  // l = L, rows ld apart (ld: a multiple of 16 bytes; padding zero)
-    int ld = 0;
-    VT *b = nullptr, *t = nullptr, *z = nullptr, *y = nullptr;  // work vectors
+    int ndense = 0;            // dense rows on this level (0: none)
+    const int *dinst = nullptr, *drow0 = nullptr, *dn = nullptr, *dld = nullptr, *dboff = nullptr;
+    const int64_t *daoff = nullptr;
+    const VT *Ainv = nullptr;
+    VT *b = nullptr, *y = nullptr;  // right-hand side and result of the level
+    VT *t = nullptr, *z = nullptr;  // level 0: pre-smoothing residual, prolongated correction
     int gP = 4, gR = 8, gD = 8, gU = 8;  // lanes per row of the CSR kernels (4..64)
 };
 template <class VT>
 struct AmgLaunch {
-    int nlev = 0;
+    int nlev = 0;                  // levels of the deepest hierarchy
     AmgLevel<VT> lv[kAmgMaxLevels];
-    VT *u = nullptr;  // fine level: the preconditioned residual M r
+    VT *u = nullptr;               // level 0: the preconditioned residual M r
+    const VT *omega = nullptr;     // per instance: the fine smoothing weight
+    bool batch = false;            // several instances: the cycle's CSR and dense kernels do not read stop flags
 };
-// CG start (single instance): residual, one cycle, w = K u, partials, state
+// CG start: residual, one cycle, w = K u, partials, state (the instances of act)
 void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s);
 // mixed solve (FP32-bulk mode): FP64 CG vectors and residual norms on the
 // FP32-stored matrix, the cycle in FP32; the solution goes straight to u

@@ -79,7 +79,7 @@ void free_host_ctl(mm_ctx *c) {
 void free_all(mm_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     amg_release(c);
-    c->hostK = HostCsr();
+    c->hostK.clear();
     for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->mgraph}) {
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
@@ -352,7 +352,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
             append_csr(C, as[i].C, moff[i], moff[i], 0);
             append_csr(S, as[i].S, moff[i], moff[i], 0);
             append_csr(K, as[i].K, poff[i], poff[i], 0);
-            if (ni == 1) c->hostK = as[i].K;  // kept for the multigrid hierarchy
+            c->hostK.push_back(as[i].K);  // kept for the multigrid hierarchies
             append_csr(B, as[i].B, boff[i], moff[i], poff[i]);
             append_csr(Bt, as[i].Bt, moff[i], poff[i], 0);
             as[i].C = HostCsr();
@@ -562,7 +562,7 @@ void pcg_replay(mm_ctx *c, bool fp32, int kind, long maxit, const std::vector<in
     long launched = 0;
     std::vector<int> seen(c->ninst, 0);
     std::vector<double> bytes = fp32 ? c->pcg_bytes32 : c->pcg_bytes64;
-    if (kind != CG_JACOBI) bytes.assign(c->ninst, amg_bytes(c->amg, kind == CG_AMG_MIXED ? 2 : 0));
+    if (kind != CG_JACOBI) bytes = amg_bytes(c->amg, kind == CG_AMG_MIXED ? 2 : 0);
     for (;;) {
         prof_mark(c);
         for (long k = 0; k < nrep; ++k) {

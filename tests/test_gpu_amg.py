@@ -151,10 +151,53 @@ def test_amg_curve_matches_jacobi_curve(B, precision):
     ctx.close()
 
 
-def test_amg_needs_a_single_instance(B):
+def test_amg_batch_limits(B):
+    """The hierarchy queries are single-instance calls; a batch with an
+    instance small enough for a single dense level is refused."""
     ws = [inputs.small_box((3, 3, 3), 4.0), inputs.small_box((4, 3, 3), 4.0)]
     ctx = B.Context(0)
     ctx.upload_batch(ws)
     with pytest.raises(B.MMError):
         ctx.amg_info()
+    m0 = np.concatenate([inputs.random_unit(ctx.inst_info[i]["n_mag"], i) for i in range(2)])
+    with pytest.raises(B.MMError):
+        ctx.batch_curve(m0, np.zeros((2, 1, 3)), jmax=4, poisson_prec=B.MM_PREC_AMG)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_amg_matches_single_instances(B, precision):
+    """A batch whose instances have two- and three-level hierarchies (dense
+    solves on different levels in one launch) gives every instance the curve
+    of its own single-instance multigrid run, and of the Jacobi batch, to the
+    solve tolerance."""
+    ws = [inputs.hard_cube(n=6, step_T=0.5, stop_T=-2.0),
+          inputs.hard_cube(n=14, step_T=0.5, stop_T=-2.0, seed=3),
+          inputs.hard_cube(n=9, step_T=0.5, stop_T=-2.0, seed=4)]
+    prec = B.MM_FP64 if precision == "fp64" else B.MM_FP32_BULK
+    F = np.stack([w.fields for w in ws])
+    m0 = np.concatenate([w.m0 for w in ws])
+    levels = []
+    singles = []
+    for w in ws:
+        ctx = B.Context(0).upload(w.mesh)
+        levels.append(ctx.amg_info()["levels"])
+        singles.append(ctx.curve(w.m0, w.fields, opts=B.default_opts(jmax=10, precision=prec,
+                                                                         poisson_prec=B.MM_PREC_AMG)))
+        ctx.close()
+    assert len(set(levels)) >= 2, levels
+    ctx = B.Context(0).upload_batch([w.mesh for w in ws])
+    ra = ctx.batch_curve(m0, F, opts=B.default_opts(jmax=10, precision=prec, poisson_prec=B.MM_PREC_AMG))
+    ctx.reset_warm_start()
+    rj = ctx.batch_curve(m0, F, opts=B.default_opts(jmax=10, precision=prec))
+    ctx.close()
+    assert ra["rc"] == 0 and rj["rc"] == 0
+    for i, r1 in enumerate(singles):
+        dE = np.abs(ra["E"][i] - r1["E"]) / np.abs(r1["E"])
+        dJ = np.abs(ra["E"][i] - rj["E"][i]) / np.abs(rj["E"][i])
+        print(precision, i, levels[i], "max rel dE vs single", dE.max(), "vs jacobi batch", dJ.max(),
+              "CG iterations batch", sum(s["mi"] for s in ra["stats"][i]), "single",
+              sum(s["mi"] for s in r1["stats"]), "jacobi", sum(s["mi"] for s in rj["stats"][i]))
+        assert dE.max() <= 1e-9 and dJ.max() <= 1e-8
+        assert np.abs(ra["m_avg"][i] - r1["m_avg"]).max() <= 1e-6
+        assert sum(s["mi"] for s in ra["stats"][i]) < sum(s["mi"] for s in rj["stats"][i])
