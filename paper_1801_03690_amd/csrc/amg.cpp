@@ -505,7 +505,17 @@ AmgState *amg_get(mm_ctx *c) {
     AmgLaunch<double> &D = S->g64;
     AmgLaunch<float> &F = S->g32;
     D.nlev = F.nlev = nlev;
-    D.batch = F.batch = ni > 1;
+    D.single = F.single = ni == 1;
+    // instance of every row of every level (-1: padding)
+    for (int l = 0; l < nlev; ++l) {
+        std::vector<int> iof(N[l], -1);
+        for (int i = 0; i < ni; ++i) {
+            if (off[l][i] < 0) continue;
+            const int n = l == 0 ? c->inst[i].n_pot : S->H[i][l].A.n;
+            for (int r = 0; r < n; ++r) iof[off[l][i] + r] = i;
+        }
+        D.lv[l].iof = F.lv[l].iof = upload_v(c, iof);
+    }
     auto vec2 = [&](size_t n, double **d, float **f) {
         n = std::max<size_t>(n, 1);
         *d = dalloc_n<double>(c, n);
@@ -584,7 +594,7 @@ AmgState *amg_get(mm_ctx *c) {
     }
     // dense tables: the instances whose coarsest level is l
     for (int l = 0; l < nlev; ++l) {
-        std::vector<int> dinst, drow0, dn, dld, dboff;
+        std::vector<int> dinst, drow0, dn, dld, dboff, dwho;
         std::vector<int64_t> daoff;
         std::vector<double> inv;
         int rows = 0;
@@ -597,6 +607,7 @@ AmgState *amg_get(mm_ctx *c) {
             dld.push_back(ld);
             daoff.push_back((int64_t)inv.size());
             dboff.push_back(l == 0 ? 0 : off[l][i]);
+            dwho.push_back(i);
             for (int r = 0; r < n; ++r) {
                 dinst.push_back(k);
                 const size_t at = inv.size();
@@ -607,7 +618,7 @@ AmgState *amg_get(mm_ctx *c) {
         }
         if (rows == 0) continue;
         const int *di = upload_v(c, dinst), *r0 = upload_v(c, drow0), *nn = upload_v(c, dn), *lds = upload_v(c, dld),
-                  *bo = upload_v(c, dboff);
+                  *bo = upload_v(c, dboff), *wh = upload_v(c, dwho);
         const int64_t *ao = upload_v(c, daoff);
         D.lv[l].ndense = F.lv[l].ndense = rows;
         D.lv[l].dinst = F.lv[l].dinst = di;
@@ -615,6 +626,7 @@ AmgState *amg_get(mm_ctx *c) {
         D.lv[l].dn = F.lv[l].dn = nn;
         D.lv[l].dld = F.lv[l].dld = lds;
         D.lv[l].dboff = F.lv[l].dboff = bo;
+        D.lv[l].dwho = F.lv[l].dwho = wh;
         D.lv[l].daoff = F.lv[l].daoff = ao;
         D.lv[l].Ainv = upload_v(c, inv);
         F.lv[l].Ainv = upload_v(c, to32(inv));

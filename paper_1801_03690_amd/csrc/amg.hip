@@ -21,11 +21,11 @@
 //   k_amg_post0    u = z + omega D^-1 (r - K z) on the fine level, partial
 //                  gamma;
 //   k_amg_w        w = K u into the records, partials delta and r.r.
-// Every kernel of an iteration returns at once when the instance's sticky
+// Every kernel of an iteration skips the rows of an instance whose sticky
 // flag is up (the flag only changes inside k_amg_iter, which every later
-// launch follows in stream order); in a batch the row-map kernels check their
-// instance's flag and the cycle's CSR and dense kernels run for every
-// instance (a converged instance's cycle is computed and not used). The
+// launch follows in stream order): the row-map kernels by their blocks'
+// instance, the cycle's CSR and dense kernels through a per-row (per-entry)
+// instance table. The
 // cycle runs in VT (double in the FP64 mode, float in the mixed form of the
 // FP32-bulk mode) and the CG vectors in RT (double); reductions are FP64.
 #include <hip/hip_runtime.h>
@@ -42,7 +42,15 @@ namespace {
 constexpr int kAB = 256;  // threads per block of the coarse-level kernels
 constexpr int kP0 = 0, kP1 = 3;
 
-__device__ __forceinline__ bool skip(const int *done) { return done && *done; }
+// rows of an instance whose stop flag is up (and padding rows) are skipped
+// when st is given; iof[row] is the instance of the row (-1: padding), or
+// iof is null for a single instance (one flag, no table)
+__device__ __forceinline__ bool skip_row(const int *iof, const PcgState *st, int row) {
+    if (!st) return false;
+    if (!iof) return st[0].done;
+    const int i = iof[row];
+    return i < 0 || st[i].done;
+}
 
 // sum over the GL lanes of a row group (GL divides 64)
 template <int GL, class VT>
@@ -68,10 +76,10 @@ __device__ __forceinline__ VT csr_row(const int *__restrict__ p, const int *__re
 template <class VT, int GL>
 __global__ __launch_bounds__(kAB) void k_amg_spmv(int n, const int *__restrict__ p, const int *__restrict__ j,
                                                       const VT *__restrict__ v, const VT *__restrict__ x,
-                                                      VT *__restrict__ y, const int *done) {
-    if (skip(done)) return;
+                                                      VT *__restrict__ y, const int *__restrict__ iof,
+                                                      const PcgState *st) {
     const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
-    if (row >= n) return;
+    if (row >= n || skip_row(iof, st, row)) return;
     const VT s = csr_row<GL>(p, j, v, x, row, gl);
     // rows without entries (padding; instances solved densely on this level) are not written
     if (gl == 0 && p[row + 1] > p[row]) y[row] = s;
@@ -84,16 +92,18 @@ template <class VT, class RT, int GL>
 __global__ __launch_bounds__(kAB) void k_amg_prolong(int n, const int *__restrict__ p, const int *__restrict__ j,
                                                      const VT *__restrict__ v, const VT *__restrict__ wd,
                                                      const RT *__restrict__ b, int bs, const VT *__restrict__ yc,
-                                                     VT *__restrict__ z, const int *done) {
-    if (skip(done)) return;
+                                                     VT *__restrict__ z, const int *__restrict__ iof,
+                                                     const PcgState *st) {
     const int row = (int)((blockIdx.x * (unsigned)kAB + threadIdx.x) / GL), gl = threadIdx.x % GL;
-    if (row >= n) return;
+    if (row >= n || skip_row(iof, st, row)) return;
     const VT s = csr_row<GL>(p, j, v, yc, row, gl);
     if (gl == 0) z[row] = wd[row] * (VT)b[(int64_t)row * bs] + s;
 }
 
 // y = Ainv b for the instances whose coarsest level this is: one wave per
-// dense row; row r is row r - drow0[k] of table entry k = dinst[r], whose
+// dense row; row r is row r - drow0[k] of table entry k = dinst[r] (instance
+// dwho[k], or 0 when dwho is null; skipped once its flag is up when st is
+// given), whose
 // inverse starts at daoff[k] (rows dld[k] apart, a multiple of 4 values,
 // padding zero) and whose b and y rows start at row dboff[k] of the level.
 // With a plain b (bs = 1; each instance's block padded to dld with zeros)
@@ -103,13 +113,14 @@ template <class VT, class BT>
 __global__ __launch_bounds__(kAB) void k_amg_dense(int nrows, const int *__restrict__ dinst,
                                                    const int *__restrict__ drow0, const int *__restrict__ dn,
                                                    const int *__restrict__ dld, const int64_t *__restrict__ daoff,
-                                                   const int *__restrict__ dboff, const VT *__restrict__ Ainv,
-                                                   const BT *__restrict__ b, int bs, VT *__restrict__ y,
-                                                   const int *done) {
-    if (skip(done)) return;
+                                                   const int *__restrict__ dboff, const int *__restrict__ dwho,
+                                                   const VT *__restrict__ Ainv, const BT *__restrict__ b, int bs,
+                                                   VT *__restrict__ y, const PcgState *st) {
     const int r = (int)(blockIdx.x * (kAB / 64) + wave_id()), ln = lane_id();
-    if (r >= nrows) return;
-    const int k = dinst[r], row = r - drow0[k], n = dn[k], ld = dld[k], bo = dboff[k];
+    if (r >= nrows || (st && !dwho && st[0].done)) return;
+    const int k = dinst[r];
+    if (st && dwho && st[dwho[k]].done) return;
+    const int row = r - drow0[k], n = dn[k], ld = dld[k], bo = dboff[k];
     const VT *a = Ainv + daoff[k] + (int64_t)row * ld;
     const BT *bb = b + (int64_t)bo * bs;
     VT acc = 0;
@@ -389,12 +400,17 @@ dim3 grid_rows(int n) {
     return dim3((unsigned)((th + kAB - 1) / kAB));
 }
 
+template <class VT>
+const int *iof_of(const AmgLaunch<VT> &g, const AmgLevel<VT> &lv) {
+    return g.single ? nullptr : lv.iof;
+}
+
 template <class VT, class BT>
-void dense(const AmgLevel<VT> &lv, const BT *b, int bs, VT *y, const int *done, hipStream_t s) {
+void dense(const AmgLevel<VT> &lv, bool single, const BT *b, int bs, VT *y, const PcgState *st, hipStream_t s) {
     if (lv.ndense > 0)
         hipLaunchKernelGGL((k_amg_dense<VT, BT>), dim3((unsigned)((lv.ndense + kAB / 64 - 1) / (kAB / 64))),
                            dim3(kAB), 0, s, lv.ndense, lv.dinst, lv.drow0, lv.dn, lv.dld, lv.daoff, lv.dboff,
-                           lv.Ainv, b, bs, y, done);
+                           single ? (const int *)nullptr : lv.dwho, lv.Ainv, b, bs, y, st);
 }
 
 // everything between the fine pre-smoothing and the fine post-smoothing:
@@ -404,31 +420,32 @@ void dense(const AmgLevel<VT> &lv, const BT *b, int bs, VT *y, const int *done, 
 // and the prolongation. With a single level (one instance, n_pot small),
 // z0 = K^-1 r from the dense inverse.
 template <class VT, class RT>
-void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const int *done, hipStream_t s) {
+void lower_cycle(const AmgLaunch<VT> &g, const RT *r, int rs, const PcgState *st, hipStream_t s) {
     const AmgLevel<VT> &f = g.lv[0];
     if (g.nlev == 1) {
-        dense(f, r, rs, f.z, done, s);
+        dense(f, g.single, r, rs, f.z, st, s);
         return;
     }
     const int L = g.nlev - 1;
     const AmgLevel<VT> &c1 = g.lv[1];
     MMNCG_GL_SWITCH(f.gR, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c1.n), dim3(kAB), 0, s, c1.n, f.Rp,
-                                             f.Rj, f.Rv, (const VT *)f.t, c1.b, done))
+                                             f.Rj, f.Rv, (const VT *)f.t, c1.b, iof_of(g, c1), st))
     for (int l = 1; l < L; ++l) {
         const AmgLevel<VT> &a = g.lv[l], &c = g.lv[l + 1];
         MMNCG_GL_SWITCH(a.gD, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(c.n), dim3(kAB), 0, s, c.n,
-                                                 a.Dp, a.Dj, a.Dv, (const VT *)a.b, c.b, done))
+                                                 a.Dp, a.Dj, a.Dv, (const VT *)a.b, c.b, iof_of(g, c), st))
     }
     for (int l = L; l >= 1; --l) {
         const AmgLevel<VT> &a = g.lv[l];
-        dense(a, (const VT *)a.b, 1, a.y, done, s);
+        dense(a, g.single, (const VT *)a.b, 1, a.y, st, s);
         // [b_l; y_{l+1}] is one array starting at b_l
         if (l < L)
             MMNCG_GL_SWITCH(a.gU, hipLaunchKernelGGL((k_amg_spmv<VT, GL>), grid_rows<GL>(a.n), dim3(kAB), 0, s, a.n,
-                                                     a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, done))
+                                                     a.Up, a.Uj, a.Uv, (const VT *)a.b, a.y, iof_of(g, a), st))
     }
     MMNCG_GL_SWITCH(f.gP, hipLaunchKernelGGL((k_amg_prolong<VT, RT, GL>), grid_rows<GL>(f.n), dim3(kAB), 0, s, f.n,
-                                             f.Pp, f.Pj, f.Pv, (const VT *)f.wd, r, rs, (const VT *)c1.y, f.z, done))
+                                             f.Pp, f.Pj, f.Pv, (const VT *)f.wd, r, rs, (const VT *)c1.y, f.z, iof_of(g, f),
+                                             st))
 }
 
 // The fine-level vectors of the CG (records, direction, u) are of type RT;
@@ -458,7 +475,7 @@ void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, R
     // t (unused with a single level) and the records' start fields
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, RT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, r, rs, fa.invD, fa.omega, f.t, q))
-    lower_cycle(g, r, rs, nullptr, s);
+    lower_cycle(g, r, rs, (const PcgState *)nullptr, s);
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, r, rs, post_wd(g), (const VT *)f.z, fa.u,
                                              cg ? a.part : (double *)nullptr, kP0, (const PcgState *)nullptr))
@@ -473,15 +490,12 @@ void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT>
               int par, hipStream_t s) {
     const RowMap &M = *a.M;
     const AmgLevel<VT> &f = g.lv[0];
-    // one instance: every kernel of the chain reads its flag; a batch: the
-    // row-map kernels read their instance's
-    const int *done = g.batch ? nullptr : &a.st[0].done;
     PcgNode<RT> *q1 = v.q[par ^ 1];
     const int ws = par ? kP0 : kP1;  // this iteration's new partials
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.omega, a.st, par,
                                              (const double *)a.part))
-    lower_cycle(g, (const RT *)&q1->r, 4, done, s);
+    lower_cycle(g, (const RT *)&q1->r, 4, (const PcgState *)a.st, s);
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, (const RT *)&q1->r, 4, post_wd(g), (const VT *)f.z,
                                              fa.u, a.part, ws, (const PcgState *)a.st);

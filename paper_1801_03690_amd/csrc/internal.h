@@ -225,8 +225,9 @@ struct AmgLevel {
     const VT *Dv = nullptr;
     const int *Up = nullptr, *Uj = nullptr;
     const VT *Uv = nullptr;
+    const int *iof = nullptr;  // instance of every row of the level (-1: padding)
     int ndense = 0;            // dense rows on this level (0: none)
-    const int *dinst = nullptr, *drow0 = nullptr, *dn = nullptr, *dld = nullptr, *dboff = nullptr;
+    const int *dinst = nullptr, *drow0 = nullptr, *dn = nullptr, *dld = nullptr, *dboff = nullptr, *dwho = nullptr;
     const int64_t *daoff = nullptr;
     const VT *Ainv = nullptr;
     VT *b = nullptr, *y = nullptr;  // right-hand side and result of the level
@@ -239,7 +240,7 @@ struct AmgLaunch {
     AmgLevel<VT> lv[kAmgMaxLevels];
     VT *u = nullptr;               // level 0: the preconditioned residual M r
     const VT *omega = nullptr;     // per instance: the fine smoothing weight
-    bool batch = false;            // several instances: the cycle's CSR and dense kernels do not read stop flags
+    bool single = true;            // one instance: the cycle's kernels read its flag without the row tables
 };
 // CG start: residual, one cycle, w = K u, partials, state (the instances of act)
 void launch_amg_init64(const PcgLaunch &a, const AmgLaunch<double> &g, const int *act, double rtol2, hipStream_t s);
