@@ -262,8 +262,9 @@ void upload_vec(mm_ctx *c, double *dst, const std::vector<double> &v) {
 
 // Partition of one row space into logical blocks: instance i owns rows
 // [off[i], off[i] + n[i]) (off a multiple of 64); its ns = ceil(n/64) slices
-// are split evenly over min(kMaxBlocksPerInst, ceil(ns / slices_per_block))
-// blocks. The table is padded with empty blocks to a multiple of 8 (XCD
+// are split evenly over min(cap_i, ceil(ns / slices_per_block)) blocks, cap_i
+// = 256, or one block per 8192 rows up to kMaxBlocksPerInst for very large
+// instances. The table is padded with empty blocks to a multiple of 8 (XCD
 // renumbering).
 void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vector<int> &n,
               const std::vector<int> &slices_per_block) {
@@ -277,7 +278,11 @@ void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vec
         rend[i] = off[i] + n[i];
         if (ns == 0) continue;
         const int spb = std::max(1, slices_per_block[i]);
-        const int nb = std::min(kMaxBlocksPerInst, (ns + spb - 1) / spb);
+        // at most 256 blocks per instance, more only for very large instances
+        // (one per 8192 rows, up to kMaxBlocksPerInst): every block re-reduces
+        // the instance's partials, which costs more than it gains below that
+        const int cap = std::min(kMaxBlocksPerInst, std::max(256, (n[i] + 8191) / 8192));
+        const int nb = std::min(cap, (ns + spb - 1) / spb);
         for (int k = 0; k < nb; ++k) {
             tab.push_back(i);
             tab.push_back(sf + (int)((int64_t)k * ns / nb));
