@@ -97,6 +97,9 @@ def main():
                          "auto: the faster one for the workload)")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the Jacobi-preconditioned comparison curve of the multigrid headline")
+    ap.add_argument("--progress-every", type=int, default=0,
+                    help="run the curve in chunks of this many fields and report each (long curves); "
+                         "every chunk starts from the previous one's last minimum, as one curve would")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain copy kernel of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -164,7 +167,17 @@ def main():
     def one_curve(o):
         m.copy_(m0)
         ctx.reset_warm_start()
-        return ctx.curve(m, fields, opts=o)
+        if args.progress_every <= 0:
+            return ctx.curve(m, fields, opts=o)
+        parts = []
+        tc = time.perf_counter()
+        for k0 in range(0, len(fields), args.progress_every):
+            parts.append(ctx.curve(m, fields[k0:k0 + args.progress_every], opts=o))
+            print(f"# fields {k0}..{min(len(fields), k0 + args.progress_every) - 1} done, "
+                  f"{time.perf_counter() - tc:.1f}s", file=sys.stderr, flush=True)
+        return dict(m=m, m_avg=np.concatenate([p["m_avg"] for p in parts]),
+                    E=np.concatenate([p["E"] for p in parts]), stats=[x for p in parts for x in p["stats"]],
+                    rc=max(p["rc"] for p in parts))
 
     for i in range(args.warmup):
         r = one_curve(opts)

@@ -93,7 +93,8 @@ typedef struct {
     long poisson_maxit;    /* scalar-potential CG iteration cap per solve */
     int poisson_prec;      /* scalar-potential CG preconditioner: MM_PREC_JACOBI,
                               or MM_PREC_AMG (algebraic multigrid as in Sec. 3.1;
-                              single-instance contexts only) */
+                              in a batch every instance needs more than 2048
+                              free potential nodes, else MM_ESTATE) */
 } mm_opts;
 
 typedef struct {
@@ -341,9 +342,11 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
        2048 rows, or coarsening stalled, or 12 levels) solved by its dense
        inverse;
      cycle: V(1,1) with damped Jacobi (weight omega) from zero.
-   The hierarchy is built on the host on first use (a solve with
-   poisson_prec = MM_PREC_AMG or one of these calls) and kept until the mesh
-   changes. Single-instance contexts only (MM_ESTATE otherwise). */
+   Every instance has its own hierarchy, built on the host on first use (a
+   solve with poisson_prec = MM_PREC_AMG or one of the calls below) and kept
+   until the mesh changes; a batch runs all instances' cycles in shared
+   launches. The calls below inspect or apply the hierarchy of a
+   single-instance context (MM_ESTATE on a batch). */
 
 /* Number of levels and, per level l < 12 (arrays of 12, may be NULL): rows,
    stored entries of the level operator and of the prolongator from level
