@@ -595,6 +595,7 @@ typedef struct {
     long max_nli;
     int terms;
     int ls_max_halvings;
+    int beta;           /* 0: beta*ZA (Alg. 4), 1: beta*FR, 2: beta*PRP, 3: beta*HS (Sec. 2.1) */
 } or_opts;
 
 typedef struct {
@@ -740,9 +741,27 @@ static double inf_norm(const double *v, long n) {
 }
 
 /*
+ * beta* of the preconditioned NCG (Sec. 2.1, eqs. FR*, PRP*, HS*, and Alg. 4's
+ * ZA, the HS form restarted when y_{j+1}.g_{j+1} <= y_{j+1}.g_j), from
+ * num = <g_{j+1} - g_j, y_{j+1}>, den = <g_{j+1} - g_j, d_j>,
+ * gy1 = <g_{j+1}, y_{j+1}> and gy0 = <g_j, y_j> of the previous direction.
+ * A non-positive denominator gives 0 (reading S12).
+ */
+static double beta_star(int kind, double num, double den, double gy1, double gy0) {
+    switch (kind) {
+        case 1: return gy0 > 0.0 ? gy1 / gy0 : 0.0;
+        case 2: return gy0 > 0.0 ? num / gy0 : 0.0;
+        case 3: return den > 0.0 ? num / den : 0.0;
+        default: return (num > 0.0 && den > 0.0) ? num / den : 0.0;
+    }
+}
+
+/*
  * Alg. 4 for one reduced field h, starting from m (unit vectors), m updated in place.
  * Direction update: beta*ZA = <g+ - g, y+> / <g+ - g, d> if y+.g+ > y+.g else 0
- * (zero also when the denominator is not positive, reading S12).
+ * (zero also when the denominator is not positive, reading S12), or the
+ * beta* variant o->beta selects (beta_star); <g, y> of the direction taken is
+ * kept for the FR* and PRP* denominators (<g, g> when g stood in for y).
  * Descent safeguard (reading S7): if <g+, d+> >= 0 use y+ = g+ and recompute;
  * if still not descent, d+ = -g+.
  */
@@ -763,9 +782,11 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
     or_precond(c, s0.x, s0.lam, s0.g, o->jmax, NULL, y, o->terms);
     for (long i = 0; i < n3; i++) d[i] = -y[i];
     double dp0 = dot_n(s0.g, d, n3);
+    double gy_prev = -dp0;  /* <g, y> of the direction taken */
     if (!(dp0 < 0.0)) {
         for (long i = 0; i < n3; i++) d[i] = -s0.g[i];
         dp0 = dot_n(s0.g, d, n3);
+        gy_prev = -dp0;
         stats->fallbacks++;
     }
     int first = 1;
@@ -783,6 +804,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
             stats->restarts++;
             for (long i = 0; i < n3; i++) d[i] = -s0.g[i];
             dp0 = dot_n(s0.g, d, n3);
+            gy_prev = -dp0;
             dmax = max_norm3(d, nm);
             if (!(dp0 < 0.0) || !(dmax > 0.0)) { status = 2; break; }
             ok = line_search(c, o, h, &s0, d, dp0, o->theta_init / dmax, &s1, &tmp, &alpha, &dFacc, stats);
@@ -807,22 +829,28 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
         if (conv) { st_copy(&s0, &s1, nm); status = 0; break; }
         /* precondition at the new iterate */
         or_precond(c, s1.x, s1.lam, s1.g, o->jmax, NULL, y, o->terms);
-        ksum kn = {0, 0}, kd = {0, 0};
+        ksum kn = {0, 0}, kd = {0, 0}, ky = {0, 0};
         for (long i = 0; i < n3; i++) {
             double dg = s1.g[i] - s0.g[i];
             ks_add(&kn, dg * y[i]);
             ks_add(&kd, dg * d[i]);
+            ks_add(&ky, s1.g[i] * y[i]);
         }
-        double num = ks_val(&kn), den = ks_val(&kd);
-        double beta = (num > 0.0 && den > 0.0) ? num / den : 0.0;
+        double num = ks_val(&kn), den = ks_val(&kd), gy1 = ks_val(&ky);
+        double beta = beta_star(o->beta, num, den, gy1, gy_prev);
         for (long i = 0; i < n3; i++) dn[i] = -y[i] + beta * d[i];
         double dpn = dot_n(s1.g, dn, n3);
+        double gy_next = gy1;
         if (!(dpn < 0.0)) {
             stats->fallbacks++;
-            ksum k2 = {0, 0};
-            for (long i = 0; i < n3; i++) ks_add(&k2, (s1.g[i] - s0.g[i]) * s1.g[i]);
+            ksum k2 = {0, 0}, kg = {0, 0};
+            for (long i = 0; i < n3; i++) {
+                ks_add(&k2, (s1.g[i] - s0.g[i]) * s1.g[i]);
+                ks_add(&kg, s1.g[i] * s1.g[i]);
+            }
             double num2 = ks_val(&k2);
-            beta = (num2 > 0.0 && den > 0.0) ? num2 / den : 0.0;
+            gy_next = ks_val(&kg);
+            beta = beta_star(o->beta, num2, den, gy_next, gy_prev);
             for (long i = 0; i < n3; i++) dn[i] = -s1.g[i] + beta * d[i];
             dpn = dot_n(s1.g, dn, n3);
             if (!(dpn < 0.0)) {
@@ -830,6 +858,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
                 dpn = dot_n(s1.g, dn, n3);
             }
         }
+        gy_prev = gy_next;
         a_prev = alpha;
         dp_prev = dp0;
         first = 0;

@@ -543,3 +543,23 @@ def test_stoner_wohlfarth_switching_field(oracle_mod):
             assert abs(th - _sw_angle(psi, k_red, B / 1.61)) < 1e-6, B
     assert switched_at is not None
     assert switched_at - 0.01 < Hsw <= switched_at + 1e-12
+
+
+def test_beta_variants_reach_the_same_minimum(oracle_mod):
+    """beta*FR, beta*PRP and beta*HS (Sec. 2.1) in place of Alg. 4's beta*ZA:
+    the minimizer is a property of F, not of the direction rule, so every
+    variant ends at the same energy and unit-norm state; the rule does change
+    the path (iteration counts), which shows it takes effect."""
+    mesh = inputs.small_box((4, 4, 3), 4.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.1, 0.0, 0.995))
+    o = oracle_mod.Oracle(mesh)
+    m0 = inputs.tilted_state(o.nm, (0.3, 0.2, 0.93), 0.2, np.random.Generator(np.random.PCG64(7)))
+    res = {}
+    for kind in range(4):
+        m, E, st, rc = o.minimize(m0, [0.0, 0.0, -0.5], jmax=4, beta=kind, tol_torque=1e-8)
+        assert rc == 0, kind
+        assert np.abs(np.linalg.norm(m, axis=1) - 1.0).max() < 1e-12
+        res[kind] = (E[4], st["nli"], m)
+    for kind in (1, 2, 3):
+        assert abs(res[kind][0] - res[0][0]) <= 1e-11 * abs(res[0][0]), kind
+        assert np.abs(res[kind][2] - res[0][2]).max() < 1e-5, kind
+    assert len({res[k][1] for k in range(4)}) >= 2
