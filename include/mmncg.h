@@ -70,6 +70,7 @@ enum {
 
 enum { MM_FP64 = 0, MM_FP32_BULK = 1 };
 enum { MM_PREC_JACOBI = 0, MM_PREC_AMG = 1 };
+enum { MM_BETA_ZA = 0, MM_BETA_FR = 1, MM_BETA_PRP = 2, MM_BETA_HS = 3 };
 enum { MM_STOP_TORQUE = 0, MM_STOP_PAPER = 1 };
 enum { MM_T_EXCH = 1, MM_T_ANIS = 2, MM_T_ZEE = 4, MM_T_DEMAG = 8, MM_T_ALL = 15 };
 
@@ -95,6 +96,12 @@ typedef struct {
                               or MM_PREC_AMG (algebraic multigrid as in Sec. 3.1;
                               in a batch every instance needs more than 2048
                               free potential nodes, else MM_ESTATE) */
+    int beta;              /* beta* of the direction update: MM_BETA_ZA (Alg. 4, the
+                              default), or the preconditioned FR*, PRP* or HS*
+                              forms of Sec. 2.1 (FR*, PRP*: <g_{j+1}, y_{j+1}> and
+                              <g_{j+1} - g_j, y_{j+1}> over <g_j, y_j>; HS*: ZA
+                              without its restart); a non-positive denominator
+                              gives beta = 0 */
 } mm_opts;
 
 typedef struct {
@@ -120,7 +127,8 @@ typedef struct {
 /* Fill o with the defaults: jmax 4, tol_torque 1e-6, torque stopping,
    tau_F 1e-10, theta_max 0.2, theta_init 0.01, c1 1e-4, c2 0.1,
    poisson_rtol 1e-10, max_nli 20000, FP64, all terms, 20 halvings,
-   poisson_maxit 100000, Jacobi-preconditioned scalar-potential CG. */
+   poisson_maxit 100000, Jacobi-preconditioned scalar-potential CG,
+   beta*ZA. */
 int mm_opts_default(mm_opts *o);
 
 typedef void *(*mm_alloc_fn)(size_t bytes, void *user);

@@ -25,6 +25,7 @@ MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_EMESH, MM_ESTATE = 0, -1, -2, -3, -4
 MM_NOT_CONVERGED, MM_STALLED = 1, 2
 MM_FP64, MM_FP32_BULK = 0, 1
 MM_PREC_JACOBI, MM_PREC_AMG = 0, 1
+MM_BETA_ZA, MM_BETA_FR, MM_BETA_PRP, MM_BETA_HS = 0, 1, 2, 3
 MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
 MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
@@ -42,7 +43,8 @@ class Opts(C.Structure):
     _fields_ = [("jmax", C.c_int), ("tol_torque", C.c_double), ("stop_mode", C.c_int), ("tau_F", C.c_double),
                 ("theta_max", C.c_double), ("theta_init", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
                 ("poisson_rtol", C.c_double), ("max_nli", C.c_long), ("precision", C.c_int), ("terms", C.c_int),
-                ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long), ("poisson_prec", C.c_int)]
+                ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long), ("poisson_prec", C.c_int),
+                ("beta", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -80,6 +82,10 @@ def header_symbols():
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libmmncg.so not built ({path}); run __graft_entry__.build()")
+    # torch ships a HIP runtime of its own; it has to be in the process before
+    # the library pulls in the system one, so that both sit on the HSA runtime
+    # torch brought (the other order leaves hipGetDeviceCount failing)
+    import torch  # noqa: F401
     L = C.CDLL(path)
     L.mm_opts_default.argtypes = [C.POINTER(Opts)]
     L.mm_amg_info.argtypes = [_vp, C.POINTER(C.c_int), _vp, _vp, _vp, C.POINTER(C.c_double)]

@@ -117,6 +117,7 @@ struct mm_ctx {
     StateV st[3];  // current state, trial T, trial C
     double *gprev = nullptr, *d = nullptr, *y = nullptr, *pr = nullptr, *pp = nullptr, *pq = nullptr,
            *dscale = nullptr, *tmp3 = nullptr;
+    double *gy = nullptr;  // per instance <g, y> of the last direction, and its snapshot (2 x ninst)
     double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
     PcgNode<double> *q64[2] = {};  // CG node records by parity
     PcgNode<float> *q32[2] = {};

@@ -140,8 +140,11 @@ void launch_prec_init(const PrecLaunch &a, hipStream_t s);
 void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s);
 
 // --- direction (kernels.hip) ---
+// beta_kind: 0 beta*ZA, 1 beta*FR, 2 beta*PRP, 3 beta*HS; gy: 2 x ninst doubles
+// (<g, y> of the last direction per instance, and its snapshot)
 void launch_dir(const RowMap &M, const int *act, const int *first, const double *g1, const double *g0,
-                const double *y1, double *d, double *part_dots, double *part_out, int *info, hipStream_t s);
+                const double *y1, double *d, double *part_dots, double *part_out, int *info, int beta_kind,
+                double *gy, hipStream_t s);
 
 // --- misc (kernels.hip) ---
 void launch_energy_split(const Sell &S, const RowMap &M, const double *m, double *part, bool fp32, hipStream_t s);

@@ -414,8 +414,24 @@ __global__ __launch_bounds__(kBlock) void k_prec_pupdate(RowMap M, const int *__
     }
 }
 
+// beta* of the preconditioned NCG (Sec. 2.1, eqs. FR*, PRP*, HS*, and Alg. 4's
+// ZA, the HS form restarted when y_{j+1}.g_{j+1} <= y_{j+1}.g_j) from num =
+// <g1 - g0, y1>, den = <g1 - g0, d>, gy1 = <g1, y1> and gy0 = <g0, y0> of the
+// previous direction; a non-positive denominator gives 0
+__device__ __forceinline__ double beta_star(int kind, double num, double den, double gy1, double gy0) {
+    switch (kind) {
+        case 1: return gy0 > 0.0 ? gy1 / gy0 : 0.0;
+        case 2: return gy0 > 0.0 ? num / gy0 : 0.0;
+        case 3: return den > 0.0 ? num / den : 0.0;
+        default: return (num > 0.0 && den > 0.0) ? num / den : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// direction: dots, then beta*ZA with the descent safeguard. first[i] bits:
+// direction: dots, then beta* (ZA unless another kind is asked for) with the
+// descent safeguard; <g, y> of the direction taken is kept per instance in gy
+// (<g, g> when g stands in for y), and the dots kernel snapshots it into
+// gy_old for the update kernel, which overwrites gy. first[i] bits:
 // 1 = first direction of a field or a restart (no beta term), 2 = take g in
 // place of the preconditioned y (no preconditioner, or steepest descent)
 // dot slots: 0 <g1-g0,y1>, 1 <g1-g0,d>, 2 <g1,y1>, 3 <g1,d>, 4 <g1-g0,g1>, 5 <g1,g1>
@@ -423,9 +439,11 @@ __global__ __launch_bounds__(kBlock) void k_prec_pupdate(RowMap M, const int *__
 __global__ __launch_bounds__(kBlock) void k_dir_dots(RowMap M, const int *__restrict__ act,
                                                      const int *__restrict__ first, const double *__restrict__ g1,
                                                      const double *__restrict__ g0, const double *__restrict__ y1,
-                                                     const double *__restrict__ d, double *__restrict__ part) {
+                                                     const double *__restrict__ d, double *__restrict__ part,
+                                                     const double *__restrict__ gy, double *__restrict__ gy_old) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !act[t.inst]) return;
+    if (t.b == M.ipb[t.inst] && threadIdx.x == 0) gy_old[t.inst] = gy[t.inst];
     __shared__ double sh[NW * kDirParts];
     const int fm = first[t.inst];
     const bool fst = (fm & 1) != 0;
@@ -455,7 +473,9 @@ __global__ __launch_bounds__(kBlock) void k_dir_update(RowMap M, const int *__re
                                                        const int *__restrict__ first, const double *__restrict__ g1,
                                                        const double *__restrict__ y1, double *__restrict__ d,
                                                        const double *__restrict__ part_dots,
-                                                       double *__restrict__ part_out, int *__restrict__ info) {
+                                                       double *__restrict__ part_out, int *__restrict__ info,
+                                                       int kind, const double *__restrict__ gy_old,
+                                                       double *__restrict__ gy) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !act[t.inst]) return;
     __shared__ double sh[NW * kDirParts];
@@ -469,13 +489,12 @@ __global__ __launch_bounds__(kBlock) void k_dir_update(RowMap M, const int *__re
         if (-tt[2] < 0.0) { cy = -1; cd = 0; cg = 0; mode = 0; }
         else { cy = 0; cd = 0; cg = -1; mode = 2; }
     } else {
-        double num = tt[0], den = tt[1];
-        double beta = (num > 0.0 && den > 0.0) ? num / den : 0.0;
+        const double gy0 = gy_old[t.inst];
+        double beta = beta_star(kind, tt[0], tt[1], tt[2], gy0);
         double dpn = -tt[2] + beta * tt[3];
         if (dpn < 0.0) { cy = -1; cd = beta; cg = 0; mode = 0; }
         else {
-            double num2 = tt[4];
-            double beta2 = (num2 > 0.0 && den > 0.0) ? num2 / den : 0.0;
+            double beta2 = beta_star(kind, tt[4], tt[1], tt[5], gy0);
             double dpn2 = -tt[5] + beta2 * tt[3];
             if (dpn2 < 0.0) { cy = 0; cd = beta2; cg = -1; mode = 1; }
             else { cy = 0; cd = 0; cg = -1; mode = 2; }
@@ -498,7 +517,10 @@ __global__ __launch_bounds__(kBlock) void k_dir_update(RowMap M, const int *__re
         }
     }
     write_part<2, NW>(acc, 2u, part_out, M.nblk, t.b, sh);
-    if (t.b == M.ipb[t.inst] && threadIdx.x == 0) info[t.inst] = mode;
+    if (t.b == M.ipb[t.inst] && threadIdx.x == 0) {
+        info[t.inst] = mode;
+        gy[t.inst] = mode == 0 ? tt[2] : tt[5];
+    }
 }
 
 // exchange part of the energy: 1/2 m.(S m)
@@ -645,10 +667,12 @@ void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s) {
 }
 
 void launch_dir(const RowMap &M, const int *act, const int *first, const double *g1, const double *g0,
-                const double *y1, double *d, double *part_dots, double *part_out, int *info, hipStream_t s) {
-    hipLaunchKernelGGL(k_dir_dots, dim3(M.nblk), dim3(kBlock), 0, s, M, act, first, g1, g0, y1, d, part_dots);
+                const double *y1, double *d, double *part_dots, double *part_out, int *info, int beta_kind,
+                double *gy, hipStream_t s) {
+    hipLaunchKernelGGL(k_dir_dots, dim3(M.nblk), dim3(kBlock), 0, s, M, act, first, g1, g0, y1, d, part_dots,
+                       (const double *)gy, gy + M.ninst);
     hipLaunchKernelGGL(k_dir_update, dim3(M.nblk), dim3(kBlock), 0, s, M, act, first, g1, y1, d, part_dots, part_out,
-                       info);
+                       info, beta_kind, (const double *)(gy + M.ninst), gy);
 }
 
 void launch_energy_split(const Sell &S, const RowMap &M, const double *m, double *part, bool fp32, hipStream_t s) {

@@ -417,6 +417,8 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     }
     for (double **p : {&c->gprev, &c->d, &c->y, &c->pr, &c->pp, &c->pq, &c->tmp3}) *p = dalloc_n<double>(c, 3 * RM);
     c->dscale = dalloc_n<double>(c, RM);
+    c->gy = dalloc_n<double>(c, 2 * (size_t)ni);
+    HIPCHK(hipMemsetAsync(c->gy, 0, 2 * (size_t)ni * sizeof(double), c->stream));
     for (double **p : {&c->u, &c->b, &c->cr, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
     for (auto &q : c->q64) q = dalloc_n<PcgNode<double>>(c, RP);
     for (auto &q : c->q32) q = dalloc_n<PcgNode<float>>(c, RP);
@@ -1209,7 +1211,7 @@ public:
             }
             if (!dir.empty()) {
                 launch_dir(c_->Mm.map, c_->d_(c_->act()), c_->d_(c_->first()), c_->st[0].g, c_->gprev, c_->y, c_->d,
-                           mslot(c_, MS_DOTS), mslot(c_, MS_DOUT), c_->d_(c_->info()), s);
+                           mslot(c_, MS_DOTS), mslot(c_, MS_DOUT), c_->d_(c_->info()), o_.beta, c_->gy, s);
                 launch_finalize_inst(c_->Mm.map, mslot(c_, MS_DOUT), 2, 2u, dsc_at(c_, SC_DIR), s);
                 pull_sc(c_, SC_DIR, 2);
                 pull_flags(c_);
@@ -1480,6 +1482,7 @@ bool opts_valid(const mm_opts &o, std::string &why) {
     else if (o.poisson_maxit < 1) why = "poisson_maxit < 1";
     else if (o.ls_max_halvings < 0) why = "ls_max_halvings < 0";
     else if (o.poisson_prec != MM_PREC_JACOBI && o.poisson_prec != MM_PREC_AMG) why = "unknown poisson_prec";
+    else if (o.beta < MM_BETA_ZA || o.beta > MM_BETA_HS) why = "unknown beta";
     else return true;
     return false;
 }
@@ -1560,6 +1563,7 @@ int mm_opts_default(mm_opts *o) {
     o->ls_max_halvings = 20;
     o->poisson_maxit = 100000;
     o->poisson_prec = MM_PREC_JACOBI;
+    o->beta = MM_BETA_ZA;
     return MM_OK;
 }
 

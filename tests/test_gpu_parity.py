@@ -305,3 +305,24 @@ def test_fp32_bulk_error_is_small(B, oracle_mod):
     assert abs(Eg[4] - Eo[4]) <= 1e-6 * abs(Eo[4])
     assert np.abs(mg - mo).max() <= 1e-4
     ctx.close()
+
+
+@pytest.mark.parametrize("beta", [1, 2, 3])
+def test_beta_variants_match_oracle(B, oracle_mod, beta):
+    """beta*FR, beta*PRP and beta*HS (Sec. 2.1) in place of beta*ZA: the GPU
+    minimization reaches the oracle's minimum; with FR and PRP also in the
+    same number of nonlinear iterations. HS without Alg. 4's restart takes
+    over a thousand iterations here, along a path that rounding decides, so
+    only its end point is compared."""
+    mesh = inputs.small_box((4, 4, 3), 4.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.1, 0.0, 0.995))
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m0 = inputs.tilted_state(o.nm, (0.3, 0.2, 0.93), 0.2, np.random.Generator(np.random.PCG64(7)))
+    mg, Eg, sg, rcg = ctx.minimize(m0, [0.0, 0.0, -0.5], jmax=4, beta=beta)
+    mo, Eo, so, rco = o.minimize(m0, [0.0, 0.0, -0.5], jmax=4, beta=beta)
+    assert rcg == 0 and rco == 0
+    assert abs(Eg[4] - Eo[4]) <= e_tol(Eo)
+    assert np.abs(mg - mo).max() <= 1e-5
+    if beta != 3:
+        assert abs(sg["nli"] - so["nli"]) <= max(2, so["nli"] // 20), (sg["nli"], so["nli"])
+    ctx.close()
