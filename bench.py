@@ -5,7 +5,7 @@ One step = one whole demagnetization curve (every field value, each
 minimization run to max |m x h_eff| < 1e-6) of the hard-magnetic cube: edge
 80 nm, 20^3 cells x 6 tets, 3x air box for the scalar potential, mu0 Ms =
 1.61 T, K1 = 4.3 MJ/m^3, A = 7.7 pJ/m, easy axis z tilted 1 degree toward x,
-field along -z from 0 to -8 T in 0.05 T steps (161 values), jmax = 10, in the
+field along -z from 0 to -8 T in 0.05 T steps (161 values), jmax = 1, in the
 FP32-bulk mode (FP32 operators and Poisson CG, FP64 reductions, FP64
 magnetization), the scalar-potential CG preconditioned by algebraic multigrid
 (as in the paper; --poisson-prec jacobi for the Jacobi-preconditioned CG).
@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fields", type=int, default=0, help="truncate the schedule (0 = all 161)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--jmax", type=int, default=None,
+                    help="inner iteration cap of the preconditioner solve (default: the workload's)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison curve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
@@ -151,7 +153,8 @@ def main():
     m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
     m = torch.empty_like(m0)
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
-    opts = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=pprec)
+    jmax = w.jmax if args.jmax is None else args.jmax
+    opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
         amg = ctx.amg_info()
@@ -217,10 +220,10 @@ def main():
         "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
         "data": "synthetic (seeded Kuhn mesh, tilted +z start)",
         "config": {"workload": (f"hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {len(fields)} fields "
-                                f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6" if args.workload == "hard_cube" else
+                                f"0..{fields[-1][2]:.2f} T, jmax {jmax}, tol 1e-6" if args.workload == "hard_cube" else
                                 f"polycrystal 200 nm, 96^3 cells x6 tets + 3x air box, 27 Voronoi grains with a "
                                 f"2 nm boundary phase, first {len(fields)} of {len(w.fields)} fields "
-                                f"0..{fields[-1][2]:.2f} T, jmax 10, tol 1e-6"),
+                                f"0..{fields[-1][2]:.2f} T, jmax {jmax}, tol 1e-6"),
                    "precision": args.precision, "poisson_preconditioner": args.poisson_prec,
                    "n_mag": info["n_mag"], "n_pot": info["n_pot"],
                    "nnz_K": info["nnz_K"], "pcg_waves_per_block": shape[0], "pcg_slices_per_wave": shape[1][0]},
@@ -241,7 +244,7 @@ def main():
     }
 
     if not args.no_plain and prec != binding.MM_FP64:
-        o64 = binding.default_opts(jmax=w.jmax, precision=binding.MM_FP64, poisson_prec=pprec)
+        o64 = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec)
         ctx.set_opts(o64)
         if not args.no_tune:
             tune(ctx, binding, args)
@@ -261,7 +264,7 @@ def main():
 
     if args.poisson_prec == "amg" and not args.no_jacobi:
         # the same curve with the Jacobi-preconditioned CG (one kernel per iteration)
-        oj = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=binding.MM_PREC_JACOBI)
+        oj = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=binding.MM_PREC_JACOBI)
         ctx.set_opts(oj)
         if not args.no_tune:
             tune(ctx, binding, args)
@@ -297,7 +300,7 @@ def main():
         o = oracle.Oracle(w.mesh)
         ns = max(1, min(args.cpu_fields, len(fields)))
         ta = time.perf_counter()
-        ro = o.curve(w.m0, fields[:ns], jmax=w.jmax)
+        ro = o.curve(w.m0, fields[:ns], jmax=jmax)
         tb = time.perf_counter()
         t_sample = tb - ta
         # extrapolate with the GPU's own distribution of work over the fields
@@ -362,7 +365,7 @@ def bench_learned(args, binding, inputs, np, torch):
 def bench_film(args):
     """The 1000 x 1000 x 10 nm soft film (200 x 200 x 2 cells of 5 nm, 3x air
     box, 121,203 magnet nodes), field along x from +50 to -50 mT in 1 mT
-    steps, jmax 4, tol 1e-6: learned start + scaling in the FP32-bulk mode
+    steps, jmax 10, tol 1e-6: learned start + scaling in the FP32-bulk mode
     (the value) against the plain FP64 method and learned FP64, with the
     parameters trained on 400-1000 nm films (data/gnn_films_large.npz). Each
     form runs once after a shared warm-up of one field."""
@@ -373,6 +376,7 @@ def bench_film(args):
 
     w = inputs.film()
     fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
+    jmax = w.jmax if args.jmax is None else args.jmax
     ctx = binding.Context(0)
     t0 = time.time()
     ctx.upload(w.mesh)
@@ -386,7 +390,7 @@ def bench_film(args):
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     res, shapes, prof = {}, {}, None
     for name, mode, prec in legs:
-        o = binding.default_opts(jmax=w.jmax, precision=prec, poisson_prec=pprec)
+        o = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
         ctx.set_opts(o)
         if not args.no_tune:
             nw, spw = tune(ctx, binding, args)
@@ -426,7 +430,7 @@ def bench_film(args):
         "dtype": "f32 operators/f64 reductions (learned component bf16 MFMA)",
         "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
         "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, "
-                               f"{len(fields)} fields +50..{1e3 * fields[-1][0]:.0f} mT along x, jmax 4, tol 1e-6, "
+                               f"{len(fields)} fields +50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, tol 1e-6, "
                                f"learned start + scaling, FP32 bulk",
                    "poisson_preconditioner": args.poisson_prec, "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
                    "pcg_shapes": shapes},
@@ -473,7 +477,8 @@ def bench_batch(args):
     print(f"# setup {t_setup:.1f}s instances={len(ws)} n_mag={ctx.n_mag} n_pot={tot_pot} nnz_K={tot_nnz}",
           file=sys.stderr, flush=True)
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
-    opts = binding.default_opts(jmax=10, precision=prec, poisson_prec=pprec)
+    jmax = ws[0].jmax if args.jmax is None else args.jmax
+    opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
         # build the hierarchies (untimed, like the assembly) with one solve
@@ -520,7 +525,7 @@ def bench_batch(args):
         "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
         "data": "synthetic (seeded Kuhn meshes, tilted +z starts)",
         "config": {"workload": f"batch of 64 hard cubes 8^3..24^3 cells (4 nm), {nf} fields 0..{F[0, -1, 2]:.2f} T "
-                               f"each, jmax 10, tol 1e-6, one launch serves all instances",
+                               f"each, jmax {jmax}, tol 1e-6, one launch serves all instances",
                    "precision": args.precision, "poisson_preconditioner": args.poisson_prec, "instances": len(ws), "n_mag": ctx.n_mag, "n_pot": tot_pot,
                    "nnz_K": tot_nnz, "pcg_waves_per_block": shape[0],
                    "pcg_slices_per_wave": sorted(set(shape[1]))},
@@ -543,7 +548,7 @@ def bench_batch(args):
         k = int(np.argmin([d["n_pot"] for d in infos]))
         o = oracle.Oracle(ws[k].mesh)
         ta = time.perf_counter()
-        o.curve(ws[k].m0, ws[k].fields[:1], jmax=10)
+        o.curve(ws[k].m0, ws[k].fields[:1], jmax=jmax)
         t_sample = time.perf_counter() - ta
         w_all = sum(s["mi"] * infos[i]["nnz_K"] for i, row in enumerate(st) for s in row)
         w_smp = max(st[k][0]["mi"] * infos[k]["nnz_K"], 1)

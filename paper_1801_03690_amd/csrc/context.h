@@ -19,6 +19,7 @@ namespace mmncg {
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
 constexpr int kPcgChunk = 16;  // CG iterations per captured graph (even: the double buffers return to parity 0)
 constexpr int kAmgChunk = 2;   // the same for the multigrid-preconditioned CG (about 10 launches per iteration)
+constexpr int kPrecCheck = 16; // inner preconditioner iterations between host looks at its exit flags
 
 struct HipError {
     hipError_t e;

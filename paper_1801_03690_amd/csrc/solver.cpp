@@ -1043,7 +1043,22 @@ void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32) {
     a.flags = c->d_(c->pflags());
     a.fp32 = fp32;
     launch_prec_init(a, c->stream);
-    for (int j = 0; j < jmax; ++j) launch_prec_iter(a, j, j + 1 == jmax, c->stream);
+    // An instance that has left by (li2) or (li3) makes the later launches
+    // return at once, but each still costs a launch. Past kPrecCheck
+    // iterations the host reads the exit flags every kPrecCheck iterations
+    // and stops launching once every instance has left; below that no host
+    // round trip is added.
+    for (int j = 0; j < jmax; ++j) {
+        launch_prec_iter(a, j, j + 1 == jmax, c->stream);
+        if ((j + 1) % kPrecCheck == 0 && j + 1 < jmax) {
+            pull_flags(c);
+            sync(c);
+            bool running = false;
+            for (int i = 0; i < c->ninst && !running; ++i)
+                running = c->pact()[i] && c->pflags()[4 * i] == 0;
+            if (!running) break;
+        }
+    }
 }
 
 // load m (caller layout, host or device) into the current state and check

@@ -140,6 +140,27 @@ def test_precondition_matches_oracle(B, oracle_mod, jmax):
     ctx.close()
 
 
+@pytest.mark.parametrize("jmax", [16, 17, 40, 200])
+def test_precondition_long_inner_solve(B, oracle_mod, jmax):
+    """Inner solves longer than the host's 16-iteration look at the exit
+    flags: a fine soft box and a random tangent right-hand side take 29
+    iterations of Alg. 1 before (li3); j_max 16 and 17 stop on (li1) first."""
+    mesh = inputs.small_box((12, 12, 2), 1.0)
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13)
+    m = inputs.tilted_state(o.nm, (0, 0, 1), 0.01, np.random.Generator(np.random.PCG64(5)))
+    ro = o.eval_T(m, [0.0, 0.0, 0.02])
+    v = np.random.Generator(np.random.PCG64(9)).standard_normal(m.shape)
+    v -= (v * m).sum(1, keepdims=True) * m
+    g = 1e-4 * v / np.linalg.norm(v)
+    y, it = ctx.precondition(m, ro["G"], g, jmax)
+    yo, ito = o.precond(m, ro["lam"], g, jmax)
+    assert it == ito == min(jmax, 29)
+    assert rel(y, yo) < 1e-10
+    ctx.close()
+
+
 def test_precondition_negative_curvature_exit(B, oracle_mod):
     mesh = MESHES["hard_5x4x3"]()
     o = oracle_mod.Oracle(mesh)
