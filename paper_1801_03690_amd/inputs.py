@@ -232,6 +232,40 @@ def hard_cube(n=20, h=4.0, seed=1, step_T=0.05, stop_T=-8.0):
                     meta=dict(seed=seed, edge_nm=n * h))
 
 
+def lex_soft():
+    """Exchange length sqrt(A / Kd), Kd = mu0 Ms^2 / 2, of the soft material (nm)."""
+    kd = 0.5 * MU0 * SOFT["Ms"] ** 2
+    return math.sqrt(SOFT["A"] / kd) * 1e9
+
+
+def sp3_cube(size_lex=8.5, n=24, start="flower", seed=5, max_tilt=0.01, pad=None):
+    """Soft cube of edge size_lex exchange lengths for the single-domain limit
+    in the spirit of standard problem 3 (Sec. 3.3): the soft material's Ms and
+    A, uniaxial K1 = 0.1 Kd along z, n cells per edge (n = 24 gives the
+    paper's mesh size of 0.35 l_ex at 8.5 l_ex), an air box padded by `pad`
+    cells per side (default 3n: a 7x box, since the zero potential on a
+    closer boundary understates the flower's stray-field energy), zero field.
+    start='flower': saturated along +z; start='vortex': two domains, +z for
+    x <= 0 and -z for x > 0, with a sharp wall. Both carry per-node tilts of
+    at most max_tilt rad, which break the cube's symmetry."""
+    lex = lex_soft()
+    h = size_lex * lex / n
+    kd = 0.5 * MU0 * SOFT["Ms"] ** 2
+    p = 3 * n if pad is None else int(pad)
+    mesh = make_box_magnet((n, n, n), h, SOFT["Ms"], SOFT["A"], 0.1 * kd, (0.0, 0.0, 1.0), pad=(p, p, p))
+    nodes = mesh.magnet_nodes()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m0 = tilted_state(nodes.size, (0.0, 0.0, 1.0), max_tilt, rng)
+    if start == "vortex":
+        x = mesh.xyz[nodes, 0]
+        m0[x > 1e-9 * h] *= np.array([1.0, 1.0, -1.0])
+    elif start != "flower":
+        raise ValueError(start)
+    return Workload(f"sp3_{size_lex:g}lex_{start}", mesh, m0, np.zeros((1, 3)), jmax=12,
+                    meta=dict(size_lex=size_lex, lex_nm=lex, h_nm=h, volume_nm3=(n * h) ** 3, kd=kd,
+                              start=start, pad=p))
+
+
 def batch_cubes(n_inst=64, seed=2, nmin=8, nmax=24, h=4.0, step_T=0.1, stop_T=-8.0):
     """Independent hard cubes of uneven size for a parameter study."""
     rng = np.random.Generator(np.random.PCG64(seed))
