@@ -37,7 +37,7 @@ class Opts(C.Structure):
     _fields_ = [("jmax", C.c_int), ("tol_torque", C.c_double), ("stop_mode", C.c_int),
                 ("tau_F", C.c_double), ("theta_max", C.c_double), ("theta_init", C.c_double),
                 ("c1", C.c_double), ("c2", C.c_double), ("max_nli", C.c_long), ("terms", C.c_int),
-                ("ls_max_halvings", C.c_int), ("beta", C.c_int)]
+                ("ls_max_halvings", C.c_int), ("beta", C.c_int), ("pform", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -52,7 +52,7 @@ class Stats(C.Structure):
 
 def default_opts(jmax=4, **kw):
     o = Opts(jmax=jmax, tol_torque=1e-6, stop_mode=0, tau_F=1e-10, theta_max=0.2, theta_init=0.01,
-             c1=1e-4, c2=0.1, max_nli=20000, terms=T_ALL, ls_max_halvings=20, beta=0)
+             c1=1e-4, c2=0.1, max_nli=20000, terms=T_ALL, ls_max_halvings=20, beta=0, pform=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -98,9 +98,9 @@ def _load():
     L.or_poisson.argtypes = [vp, _dp, _dp, C.c_double, C.c_long]
     L.or_eval.restype = C.c_long
     L.or_eval.argtypes = [vp, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
-    L.or_apply_P.argtypes = [vp, _dp, _dp, _dp, _dp, C.c_int]
+    L.or_apply_P.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_int]
     L.or_precond_pub.restype = C.c_long
-    L.or_precond_pub.argtypes = [vp, _dp, _dp, _dp, C.c_int, _dp, _dp, C.c_int]
+    L.or_precond_pub.argtypes = [vp, _dp, _dp, _dp, C.c_int, _dp, _dp, C.c_int, C.c_int]
     L.or_minimize.restype = C.c_int
     L.or_minimize.argtypes = [vp, _dp, _dp, C.POINTER(Opts), C.POINTER(Stats), _dp]
     L.or_curve.restype = C.c_int
@@ -253,22 +253,28 @@ class Oracle:
     def eval_T(self, m, BT, terms=T_ALL):
         return self.eval(m, self.reduce_field(BT), terms)
 
-    def apply_P(self, m, lam, v, terms=T_EXCH | T_ANIS):
+    def apply_P(self, m, lam, v, terms=T_EXCH | T_ANIS, g=None, form=0):
+        """Preconditioner action of eq. (precond): form 0 without its last
+        term (the paper's choice), 1 with all terms (needs the projected
+        gradient g), 2 only the projected local part."""
         m = _f64(m, (self.nm, 3))
         lam = _f64(lam, (self.nm,))
         v = _f64(v, (self.nm, 3))
+        gv = np.zeros_like(v) if g is None else _f64(g, (self.nm, 3))
+        if form == 1 and g is None:
+            raise ValueError("form 1 needs the projected gradient g")
         out = np.zeros_like(v)
-        self._L.or_apply_P(self.h, _d(m), _d(lam), _d(v), _d(out), terms)
+        self._L.or_apply_P(self.h, _d(m), _d(lam), _d(gv), _d(v), _d(out), terms, int(form))
         return out
 
-    def precond(self, m, lam, g, jmax, dscale=None, terms=T_EXCH | T_ANIS):
+    def precond(self, m, lam, g, jmax, dscale=None, terms=T_EXCH | T_ANIS, form=0):
         m = _f64(m, (self.nm, 3))
         lam = _f64(lam, (self.nm,))
         g = _f64(g, (self.nm, 3))
         y = np.zeros_like(g)
         ds = None if dscale is None else _f64(dscale, (self.nm,))
         it = self._L.or_precond_pub(self.h, _d(m), _d(lam), _d(g), int(jmax),
-                                    None if ds is None else _d(ds), _d(y), terms)
+                                    None if ds is None else _d(ds), _d(y), terms, int(form))
         return y, int(it)
 
     def minimize(self, m, BT, opts=None, **kw):

@@ -19,6 +19,8 @@
  *   - the Lagrange multiplier lambda_i = m_i . grad F_i and the projected
  *     gradient Pi_{m-perp}(grad F)                       [eqs. (nablaLF), (proj), (optcond)]
  *   - the preconditioner action: eq. (precond) without its last term    [Sec. 2.2]
+ *     (the paper's choice), and for comparison the other candidates the
+ *     equation offers: all of it, or only its projected local part
  *   - preconditioned linear CG (Alg. 1) with the exits (li1)-(li3), Jacobi
  *     preconditioner = diagonal of the exchange matrix                  [Alg. 1, Sec. 3.1]
  *   - Alg. 4 with beta*ZA (restarted Hestenes-Stiefel), the descent
@@ -511,17 +513,28 @@ long or_eval(or_ctx *c, const double *m, const double *h, int terms, double *E, 
 }
 
 /*
- * Preconditioner action [eq. (precond) without its last term]:
- *   (P v)_a = (C v)_a - (m_a . (C v)_a) m_a - lambda_a v_a,
- * C = exchange + anisotropy only; lambda_a = m_a . grad F_a from the full gradient.
+ * Preconditioner action, eq. (precond) with C = exchange + anisotropy only
+ * and lambda_a = m_a . grad F_a from the full gradient:
+ *   form 0 (the paper's choice, without the last term):
+ *     (P v)_a = (C v)_a - (m_a . (C v)_a) m_a - lambda_a v_a
+ *   form 1 (all four terms): form 0 - (v_a . grad F_a) m_a, where
+ *     grad F_a = g_a + lambda_a m_a (g the projected gradient)
+ *   form 2 (the projected local part only): (C v)_a - (m_a . (C v)_a) m_a
  */
-void or_apply_P(const or_ctx *c, const double *m, const double *lam, const double *v, double *out, int terms) {
+void or_apply_P(const or_ctx *c, const double *m, const double *lam, const double *g, const double *v,
+                double *out, int terms, int form) {
     apply_local(c, v, out, terms & (T_EXCH | T_ANIS));
     for (long a = 0; a < c->nm; a++) {
-        const double *ma = m + 3 * a;
+        const double *ma = m + 3 * a, *va = v + 3 * a;
         double *o = out + 3 * a;
         double mc = ma[0] * o[0] + ma[1] * o[1] + ma[2] * o[2];
-        for (int d = 0; d < 3; d++) o[d] = o[d] - mc * ma[d] - lam[a] * v[3 * a + d];
+        double shift = form == 2 ? 0.0 : lam[a];
+        double vG = 0.0;
+        if (form == 1) {
+            const double *ga = g + 3 * a;
+            for (int d = 0; d < 3; d++) vG += va[d] * (ga[d] + lam[a] * ma[d]);
+        }
+        for (int d = 0; d < 3; d++) o[d] = o[d] - mc * ma[d] - shift * va[d] - vG * ma[d];
     }
 }
 
@@ -536,7 +549,7 @@ void or_apply_P(const or_ctx *c, const double *m, const double *lam, const doubl
  * Returns the number of inner iterations taken.
  */
 long or_precond(or_ctx *c, const double *m, const double *lam, const double *g, int jmax,
-                const double *dscale, double *y, int terms) {
+                const double *dscale, double *y, int terms, int form) {
     long n3 = 3 * c->nm;
     memset(y, 0, sizeof(double) * n3);
     if (jmax <= 0) { memcpy(y, g, sizeof(double) * n3); return 0; }
@@ -554,7 +567,7 @@ long or_precond(or_ctx *c, const double *m, const double *lam, const double *g, 
     double rz = dot_n(r, z, n3);
     long it = 0;
     for (int j = 0; j < jmax; j++) {
-        or_apply_P(c, m, lam, p, q, terms);
+        or_apply_P(c, m, lam, g, p, q, terms, form);
         double pq = dot_n(p, q, n3);
         if (!(pq > 0.0)) {
             if (j == 0) memcpy(y, g, sizeof(double) * n3);
@@ -579,8 +592,8 @@ long or_precond(or_ctx *c, const double *m, const double *lam, const double *g, 
     return it;
 }
 long or_precond_pub(or_ctx *c, const double *m, const double *lam, const double *g, int jmax,
-                    const double *dscale, double *y, int terms) {
-    return or_precond(c, m, lam, g, jmax, dscale, y, terms);
+                    const double *dscale, double *y, int terms, int form) {
+    return or_precond(c, m, lam, g, jmax, dscale, y, terms, form);
 }
 
 /* ------------------------------------------------------------------ */
@@ -596,6 +609,7 @@ typedef struct {
     int terms;
     int ls_max_halvings;
     int beta;           /* 0: beta*ZA (Alg. 4), 1: beta*FR, 2: beta*PRP, 3: beta*HS (Sec. 2.1) */
+    int pform;          /* preconditioner form of or_apply_P (0: the paper's) */
 } or_opts;
 
 typedef struct {
@@ -779,7 +793,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
     stats->evals++;
     int status = 1;
     if (o->stop_mode == 0 && s0.tmax < o->tol_torque) { status = 0; goto done; }
-    or_precond(c, s0.x, s0.lam, s0.g, o->jmax, NULL, y, o->terms);
+    or_precond(c, s0.x, s0.lam, s0.g, o->jmax, NULL, y, o->terms, o->pform);
     for (long i = 0; i < n3; i++) d[i] = -y[i];
     double dp0 = dot_n(s0.g, d, n3);
     double gy_prev = -dp0;  /* <g, y> of the direction taken */
@@ -828,7 +842,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
         }
         if (conv) { st_copy(&s0, &s1, nm); status = 0; break; }
         /* precondition at the new iterate */
-        or_precond(c, s1.x, s1.lam, s1.g, o->jmax, NULL, y, o->terms);
+        or_precond(c, s1.x, s1.lam, s1.g, o->jmax, NULL, y, o->terms, o->pform);
         ksum kn = {0, 0}, kd = {0, 0}, ky = {0, 0};
         for (long i = 0; i < n3; i++) {
             double dg = s1.g[i] - s0.g[i];

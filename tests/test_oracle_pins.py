@@ -328,7 +328,8 @@ def test_hessian_of_lagrangian_and_preconditioner(oracle_mod):
     """With the stray field off, the action of the Hessian of the Lagrangian
     (derivative of grad L = G - (m.G) m) equals
     C v - (v.G) m - (m.G) v - (m.(C v)) m; the preconditioner is that
-    expression without the term (v.G) m, and is symmetric on the tangent space."""
+    expression without the term (v.G) m, and is symmetric on the tangent space.
+    The other forms of eq. (precond): all terms, or without (m.G) v too."""
     terms = oracle_mod.T_EXCH | oracle_mod.T_ANIS | oracle_mod.T_ZEE
     mesh = _tiny_hard(with_air=False)
     o = oracle_mod.Oracle(mesh)
@@ -352,6 +353,13 @@ def test_hessian_of_lagrangian_and_preconditioner(oracle_mod):
     Pv = o.apply_P(m, r["lam"], v)
     np.testing.assert_allclose(Pv, hess + np.sum(v * G, 1, keepdims=True) * m,
                                atol=1e-12 * np.abs(hess).max())
+    # all four terms of eq. (precond) (form 1) are the Hessian itself; the
+    # projected local part (form 2) also drops (m.G) v
+    P1 = o.apply_P(m, r["lam"], v, g=r["g"], form=1)
+    np.testing.assert_allclose(P1, hess, atol=1e-12 * np.abs(hess).max())
+    P2 = o.apply_P(m, r["lam"], v, form=2)
+    np.testing.assert_allclose(P2, hess + np.sum(v * G, 1, keepdims=True) * m
+                               + np.sum(m * G, 1, keepdims=True) * v, atol=1e-12 * np.abs(hess).max())
     # symmetric on the tangent space
     t1 = inputs.random_vec(o.nm, 13)
     t2 = inputs.random_vec(o.nm, 14)
@@ -563,3 +571,22 @@ def test_beta_variants_reach_the_same_minimum(oracle_mod):
         assert abs(res[kind][0] - res[0][0]) <= 1e-11 * abs(res[0][0]), kind
         assert np.abs(res[kind][2] - res[0][2]).max() < 1e-5, kind
     assert len({res[k][1] for k in range(4)}) >= 2
+
+
+def test_preconditioner_forms_reach_the_same_minimum(oracle_mod):
+    """The candidates of eq. (precond) (all terms, or the projected local part
+    only) in place of the paper's choice: the preconditioner changes the path,
+    not the minimizer, so every form ends at the same energy and state."""
+    mesh = inputs.small_box((4, 4, 3), 4.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.1, 0.0, 0.995))
+    o = oracle_mod.Oracle(mesh)
+    m0 = inputs.tilted_state(o.nm, (0.3, 0.2, 0.93), 0.2, np.random.Generator(np.random.PCG64(7)))
+    res = {}
+    for form in range(3):
+        m, E, st, rc = o.minimize(m0, [0.0, 0.0, -0.5], jmax=4, pform=form, tol_torque=1e-8)
+        assert rc == 0, form
+        assert np.abs(np.linalg.norm(m, axis=1) - 1.0).max() < 1e-12
+        res[form] = (E[4], st["nli"], st["li"], m)
+    for form in (1, 2):
+        assert abs(res[form][0] - res[0][0]) <= 1e-11 * abs(res[0][0]), form
+        assert np.abs(res[form][3] - res[0][3]).max() < 1e-5, form
+    assert len({(res[k][1], res[k][2]) for k in range(3)}) == 3
