@@ -71,6 +71,7 @@ enum {
 enum { MM_FP64 = 0, MM_FP32_BULK = 1 };
 enum { MM_PREC_JACOBI = 0, MM_PREC_AMG = 1 };
 enum { MM_BETA_ZA = 0, MM_BETA_FR = 1, MM_BETA_PRP = 2, MM_BETA_HS = 3 };
+enum { MM_PFORM_PAPER = 0, MM_PFORM_FULL = 1, MM_PFORM_LOCAL = 2 };
 enum { MM_STOP_TORQUE = 0, MM_STOP_PAPER = 1 };
 enum { MM_T_EXCH = 1, MM_T_ANIS = 2, MM_T_ZEE = 4, MM_T_DEMAG = 8, MM_T_ALL = 15 };
 
@@ -102,6 +103,12 @@ typedef struct {
                               <g_{j+1} - g_j, y_{j+1}> over <g_j, y_j>; HS*: ZA
                               without its restart); a non-positive denominator
                               gives beta = 0 */
+    int prec_form;         /* preconditioner action, a form of eq. (precond) with
+                              C = exchange + anisotropy: MM_PFORM_PAPER (the
+                              default, without the last term, as Sec. 2.2 chooses),
+                              MM_PFORM_FULL (all four terms; not symmetric), or
+                              MM_PFORM_LOCAL (the projected local part
+                              C v - (m.Cv) m only) */
 } mm_opts;
 
 typedef struct {

@@ -8,7 +8,8 @@ measurements through the library: one demagnetization curve per setting, same
 stopping rule, and prints one row per setting (evals, nli, li, mi, seconds,
 and the time of the preconditioner and of the magnetostatics as the library
 counts them, and the largest end-of-field torque). Besides j_max and beta*,
-the (t1)-(t3) stopping rule of Sec. 3.1 can replace the torque tolerance.
+the (t1)-(t3) stopping rule of Sec. 3.1 can replace the torque tolerance, and
+the other forms of eq. (precond) the paper's preconditioner.
 Orchestration only: every step is a library call.
 
     python -m paper_1801_03690_amd.ablation --workload hard_cube --fields 41 \
@@ -24,6 +25,8 @@ from . import binding as B
 from . import inputs
 
 BETA_NAMES = {B.MM_BETA_ZA: "ZA", B.MM_BETA_FR: "FR", B.MM_BETA_PRP: "PRP", B.MM_BETA_HS: "HS"}
+FORM_NAMES = {B.MM_PFORM_PAPER: "without the last term", B.MM_PFORM_FULL: "all terms",
+              B.MM_PFORM_LOCAL: "projected local part"}
 
 
 WORKLOADS = {"soft_cube": inputs.soft_cube, "hard_cube": inputs.hard_cube, "film": inputs.film,
@@ -60,6 +63,8 @@ def main(argv=None):
     ap.add_argument("--fields", type=int, default=0, help="first fields of the schedule (0: all)")
     ap.add_argument("--jmax", default="0,1,2,4,10,20,100", help="comma-separated j_max values (beta*ZA)")
     ap.add_argument("--beta", default="0,1,2,3", help="beta* kinds at the workload's j_max (0 ZA, 1 FR, 2 PRP, 3 HS)")
+    ap.add_argument("--prec-form", default="", help="comma-separated forms of eq. (precond) at the workload's "
+                    "j_max (0 the paper's, 1 all terms, 2 the projected local part)")
     ap.add_argument("--tau-f", default="", help="comma-separated tau_F of the (t1)-(t3) stopping rule "
                     "(Sec. 3.1) at the workload's j_max and beta*ZA")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
@@ -92,6 +97,8 @@ def main(argv=None):
     settings = [(f"jmax={j}, beta*ZA", dict(jmax=j)) for j in [int(x) for x in args.jmax.split(",") if x != ""]]
     settings += [(f"jmax={w.jmax}, beta*{BETA_NAMES[b]}", dict(jmax=w.jmax, beta=b))
                  for b in [int(x) for x in args.beta.split(",") if x != ""]]
+    settings += [(f"jmax={w.jmax}, P {FORM_NAMES[int(f)]}", dict(jmax=w.jmax, prec_form=int(f)))
+                 for f in args.prec_form.split(",") if f != ""]
     settings += [(f"jmax={w.jmax}, (t1)-(t3) tau_F={t}", dict(jmax=w.jmax, stop_mode=B.MM_STOP_PAPER, tau_F=float(t)))
                  for t in args.tau_f.split(",") if t != ""]
     for label, kw in settings:

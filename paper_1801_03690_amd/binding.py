@@ -26,6 +26,7 @@ MM_NOT_CONVERGED, MM_STALLED = 1, 2
 MM_FP64, MM_FP32_BULK = 0, 1
 MM_PREC_JACOBI, MM_PREC_AMG = 0, 1
 MM_BETA_ZA, MM_BETA_FR, MM_BETA_PRP, MM_BETA_HS = 0, 1, 2, 3
+MM_PFORM_PAPER, MM_PFORM_FULL, MM_PFORM_LOCAL = 0, 1, 2
 MM_STOP_TORQUE, MM_STOP_PAPER = 0, 1
 MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
@@ -44,7 +45,7 @@ class Opts(C.Structure):
                 ("theta_max", C.c_double), ("theta_init", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
                 ("poisson_rtol", C.c_double), ("max_nli", C.c_long), ("precision", C.c_int), ("terms", C.c_int),
                 ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long), ("poisson_prec", C.c_int),
-                ("beta", C.c_int)]
+                ("beta", C.c_int), ("prec_form", C.c_int)]
 
 
 class Stats(C.Structure):

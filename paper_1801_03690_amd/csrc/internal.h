@@ -135,6 +135,7 @@ struct PrecLaunch {
     double *part;              // 7 slots: INIT(2), PQ(1), RZ0(2), RZ1(2)
     int *flags;                // per instance: {stop phase, iterations, exit reason, -}
     bool fp32;
+    int form = 0;              // MM_PFORM_*: terms of eq. (precond)
 };
 void launch_prec_init(const PrecLaunch &a, hipStream_t s);
 void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s);

@@ -293,12 +293,15 @@ __global__ __launch_bounds__(kBlock) void k_prec_init(RowMap M, const int *__res
     }
 }
 
-template <class V>
+// FORM selects the terms of eq. (precond): 0 all but the last, 1 all four
+// (the last, -(v . grad F) m, with grad F = g + lambda m), 2 without the
+// lambda v term as well
+template <class V, int FORM>
 __global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, RowMap M, const int *__restrict__ act,
                                                        const double *__restrict__ m, const double *__restrict__ lam,
-                                                       const double *__restrict__ p, double *__restrict__ q,
-                                                       double *__restrict__ part, const int *__restrict__ flags,
-                                                       int phase) {
+                                                       const double *__restrict__ g, const double *__restrict__ p,
+                                                       double *__restrict__ q, double *__restrict__ part,
+                                                       const int *__restrict__ flags, int phase) {
     Tile t = tile_of(M);
     if (t.inst < 0 || !act[t.inst] || stopped_before(flags + 4 * t.inst, phase)) return;
     __shared__ double sh[NW];
@@ -312,9 +315,16 @@ __global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, RowMap M, const 
             int64_t a3 = 3 * (int64_t)a;
             double m0 = m[a3], m1 = m[a3 + 1], m2 = m[a3 + 2];
             double mc = m0 * c0 + m1 * c1 + m2 * c2;
-            double l = lam[a];
+            double l = FORM == 2 ? 0.0 : lam[a];
             double p0 = p[a3], p1 = p[a3 + 1], p2 = p[a3 + 2];
             double q0 = c0 - mc * m0 - l * p0, q1 = c1 - mc * m1 - l * p1, q2 = c2 - mc * m2 - l * p2;
+            if (FORM == 1) {
+                const double la = lam[a];
+                const double vG = p0 * (g[a3] + la * m0) + p1 * (g[a3 + 1] + la * m1) + p2 * (g[a3 + 2] + la * m2);
+                q0 -= vG * m0;
+                q1 -= vG * m1;
+                q2 -= vG * m2;
+            }
             q[a3] = q0;
             q[a3 + 1] = q1;
             q[a3 + 2] = q2;
@@ -653,12 +663,19 @@ void launch_prec_init(const PrecLaunch &a, hipStream_t s) {
 void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s) {
     const RowMap &M = *a.M;
     const int ph = 3 * j;
-    if (a.fp32)
-        hipLaunchKernelGGL(k_prec_apply<float>, dim3(M.nblk), dim3(kBlock), 0, s, view<float>(*a.C), M, a.act, a.m,
-                           a.lam, a.p, a.q, a.part, a.flags, ph + 1);
-    else
-        hipLaunchKernelGGL(k_prec_apply<double>, dim3(M.nblk), dim3(kBlock), 0, s, view<double>(*a.C), M, a.act, a.m,
-                           a.lam, a.p, a.q, a.part, a.flags, ph + 1);
+#define MMNCG_PREC_APPLY(V, F)                                                                                     \
+    hipLaunchKernelGGL((k_prec_apply<V, F>), dim3(M.nblk), dim3(kBlock), 0, s, view<V>(*a.C), M, a.act, a.m, a.lam, \
+                       a.g, a.p, a.q, a.part, a.flags, ph + 1)
+    if (a.fp32) {
+        if (a.form == 1) MMNCG_PREC_APPLY(float, 1);
+        else if (a.form == 2) MMNCG_PREC_APPLY(float, 2);
+        else MMNCG_PREC_APPLY(float, 0);
+    } else {
+        if (a.form == 1) MMNCG_PREC_APPLY(double, 1);
+        else if (a.form == 2) MMNCG_PREC_APPLY(double, 2);
+        else MMNCG_PREC_APPLY(double, 0);
+    }
+#undef MMNCG_PREC_APPLY
     hipLaunchKernelGGL(k_prec_update, dim3(M.nblk), dim3(kBlock), 0, s, M, a.act, j, a.g, a.invDex, a.dscale, a.y,
                        a.r, a.p, a.q, a.part, a.flags, ph + 2);
     if (!last)

@@ -1025,7 +1025,7 @@ void energy_parts(mm_ctx *c, int i, const Sc &v, const mm_opts &o, double E[5]) 
 
 // preconditioner for the instances with pact[i]: at most jmax steps of Alg. 1
 // on P y = g at the current state (exits li1-li3)
-void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32) {
+void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32, int form) {
     PrecLaunch a;
     a.C = &c->C;
     a.M = &c->Mm.map;
@@ -1042,6 +1042,7 @@ void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32) {
     a.part = mslot(c, MS_PREC);
     a.flags = c->d_(c->pflags());
     a.fp32 = fp32;
+    a.form = form;
     launch_prec_init(a, c->stream);
     // An instance that has left by (li2) or (li3) makes the later launches
     // return at once, but each still costs a launch. Past kPrecCheck
@@ -1221,7 +1222,8 @@ public:
             if (any_prec) {
                 HIPCHK(hipEventRecord(c_->ev[2], s));
                 const bool scaled = (ln_.mode & 2) && r_[0].scaled;
-                precondition(c_, o_.jmax, scaled ? c_->dscale : nullptr, o_.precision == MM_FP32_BULK);
+                precondition(c_, o_.jmax, scaled ? c_->dscale : nullptr, o_.precision == MM_FP32_BULK,
+                             o_.prec_form);
                 HIPCHK(hipEventRecord(c_->ev[3], s));
             }
             if (!dir.empty()) {
@@ -1498,6 +1500,7 @@ bool opts_valid(const mm_opts &o, std::string &why) {
     else if (o.ls_max_halvings < 0) why = "ls_max_halvings < 0";
     else if (o.poisson_prec != MM_PREC_JACOBI && o.poisson_prec != MM_PREC_AMG) why = "unknown poisson_prec";
     else if (o.beta < MM_BETA_ZA || o.beta > MM_BETA_HS) why = "unknown beta";
+    else if (o.prec_form < MM_PFORM_PAPER || o.prec_form > MM_PFORM_LOCAL) why = "unknown prec_form";
     else return true;
     return false;
 }
@@ -1579,6 +1582,7 @@ int mm_opts_default(mm_opts *o) {
     o->poisson_maxit = 100000;
     o->poisson_prec = MM_PREC_JACOBI;
     o->beta = MM_BETA_ZA;
+    o->prec_form = MM_PFORM_PAPER;
     return MM_OK;
 }
 
@@ -1841,7 +1845,7 @@ int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double
             }
             c->pact()[0] = 1;
             upload_ctl(c);
-            precondition(c, jmax, ds, c->opts.precision == MM_FP32_BULK);
+            precondition(c, jmax, ds, c->opts.precision == MM_FP32_BULK, c->opts.prec_form);
             pull_flags(c);
         }
         copy_out(c, y, c->y, 3 * (size_t)nm);

@@ -27,6 +27,8 @@ def test_opts_defaults_without_gpu():
     o = binding.default_opts()
     assert o.jmax == 4 and o.tol_torque == 1e-6 and o.poisson_rtol == 1e-10
     assert o.theta_max == 0.2 and o.c1 == 1e-4 and o.c2 == 0.1 and o.max_nli == 20000
+    assert o.poisson_prec == binding.MM_PREC_JACOBI and o.beta == binding.MM_BETA_ZA
+    assert o.prec_form == binding.MM_PFORM_PAPER
 
 
 def test_create_without_gpu_fails_cleanly():

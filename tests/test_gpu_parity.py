@@ -347,3 +347,60 @@ def test_beta_variants_match_oracle(B, oracle_mod, beta):
     if beta != 3:
         assert abs(sg["nli"] - so["nli"]) <= max(2, so["nli"] // 20), (sg["nli"], so["nli"])
     ctx.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("jmax", [3, 10])
+def test_precondition_forms_match_oracle(B, oracle_mod, form, jmax):
+    """The other candidates of eq. (precond) (all four terms; the projected
+    local part only): the GPU inner solve takes the oracle's exits and
+    iterates."""
+    mesh = MESHES["hard_5x4x3"]()
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13, prec_form=form)
+    m = _near_state(o, 5)
+    ro = o.eval_T(m, [0.0, 0.0, 0.5])
+    y, it = ctx.precondition(m, ro["G"], ro["g"], jmax)
+    yo, ito = o.precond(m, ro["lam"], ro["g"], jmax, form=form)
+    assert it == ito
+    assert rel(y, yo) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_precondition_forms_minimize_match_oracle(B, oracle_mod, form):
+    """Alg. 4 with each candidate preconditioner follows the oracle to the
+    same minimum in the same number of nonlinear iterations."""
+    mesh = inputs.small_box((4, 4, 3), 4.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.1, 0.0, 0.995))
+    o = oracle_mod.Oracle(mesh)
+    ctx = _ctx(B, mesh)
+    m0 = inputs.tilted_state(o.nm, (0.3, 0.2, 0.93), 0.2, np.random.Generator(np.random.PCG64(7)))
+    mg, Eg, sg, rcg = ctx.minimize(m0, [0.0, 0.0, -0.5], jmax=4, prec_form=form)
+    mo, Eo, so, rco = o.minimize(m0, [0.0, 0.0, -0.5], jmax=4, pform=form)
+    assert rcg == 0 and rco == 0
+    assert abs(Eg[4] - Eo[4]) <= e_tol(Eo)
+    assert np.abs(mg - mo).max() <= 1e-5
+    assert abs(sg["nli"] - so["nli"]) <= max(2, so["nli"] // 20), (sg["nli"], so["nli"])
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_precondition_forms_long_inner_solve(B, oracle_mod, form):
+    """The candidates of eq. (precond) over a 29-40 iteration inner solve: the
+    last term gives y a normal part (3e-5 of |y| here), which the 1e-10
+    comparison resolves."""
+    mesh = inputs.small_box((12, 12, 2), 1.0)
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13, prec_form=form)
+    m = inputs.tilted_state(o.nm, (0, 0, 1), 0.01, np.random.Generator(np.random.PCG64(5)))
+    ro = o.eval_T(m, [0.0, 0.0, 0.02])
+    v = np.random.Generator(np.random.PCG64(9)).standard_normal(m.shape)
+    v -= (v * m).sum(1, keepdims=True) * m
+    g = 1e-4 * v / np.linalg.norm(v)
+    y, it = ctx.precondition(m, ro["G"], g, 40)
+    yo, ito = o.precond(m, ro["lam"], g, 40, form=form)
+    assert it == ito
+    assert rel(y, yo) < 1e-10
+    ctx.close()
