@@ -183,8 +183,10 @@ __global__ __launch_bounds__(kFinBlock) void k_pcg_init_fin(RowMap M, const doub
 // before any is used, so a wave keeps several gathers in flight. Entries past
 // the slice's width stand in as the slice's first row (a row of the same
 // instance) with value 0; the width is uniform over the wave, so those lanes
-// issue no loads of matrix storage.
-template <class MT, class VT>
+// issue no loads of matrix storage. With NT the matrix loads are marked
+// non-temporal: a matrix too large to stay in the Infinity Cache between
+// iterations then does not evict the records the gathers reuse.
+template <class MT, class VT, bool NT>
 __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0, VT &pa,
                                         VT &pb, VT &pc) {
     constexpr int G = sizeof(VT) == 4 ? 8 : 4;
@@ -198,8 +200,13 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
         for (int k = 0; k < G; ++k) {
             const bool in = k0 + k < wd;
             const int64_t e = base + 64 * (k0 + k) + ln;
-            cc[k] = in ? K.col[e] : s * 64;
-            vv[k] = in ? (VT)K.val[e] : (VT)0;
+            if (NT) {
+                cc[k] = in ? __builtin_nontemporal_load(K.col + e) : s * 64;
+                vv[k] = in ? (VT)__builtin_nontemporal_load(K.val + e) : (VT)0;
+            } else {
+                cc[k] = in ? K.col[e] : s * 64;
+                vv[k] = in ? (VT)K.val[e] : (VT)0;
+            }
         }
         PcgNode<VT> nq[G];
 #pragma unroll
@@ -220,7 +227,7 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
 // with A, B, C the products of K D^-1 with r, w and s: these do not depend on
 // the iteration's scalars, so the matrix gathers of a wave's first slice are
 // issued before the block has reduced the previous partials.
-template <class MT, class VT, class XT, int NW>
+template <class MT, class VT, class XT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
                                                       const VT *__restrict__ invD, PcgState *__restrict__ st, int par,
                                                       double *__restrict__ part) {
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
     const int sf = t.s0 + wave_id();
     const int rf = sf * 64 + ln;
     VT pa = 0, pb = 0, pc = 0;
-    if (sf < t.s1) row_abc(K, sf, ln, q0, pa, pb, pc);
+    if (sf < t.s1) row_abc<MT, VT, NT>(K, sf, ln, q0, pa, pb, pc);
     PcgNode<VT> me_f{0, 0, 0, 0};
     VT p_f = 0;
     XT x_f = 0;
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_iter(SV<MT> K, RowMap M, PcgVec
     const VT a = (VT)alpha, bt = (VT)beta;
     double acc[3] = {0, 0, 0};
     for (int s = sf; s < t.s1; s += NW) {
-        if (s != sf) row_abc(K, s, ln, q0, pa, pb, pc);
+        if (s != sf) row_abc<MT, VT, NT>(K, s, ln, q0, pa, pb, pc);
         int row = s * 64 + ln;
         if (row < rend) {
             const PcgNode<VT> me = (s == sf) ? me_f : q0[row];
@@ -365,16 +372,32 @@ void launch_pcg_init32(const PcgLaunch &a, hipStream_t s) {
                        (const int *)nullptr, a.pin, a.st);
 }
 
+// matrices whose stored entries (value + column index) exceed this stay out
+// of the Infinity Cache between iterations and are loaded non-temporally
+constexpr int64_t kStreamMatrixBytes = int64_t(128) << 20;
+
 void launch_pcg_iter64(const PcgLaunch &a, int parity, hipStream_t s) {
     const RowMap &M = *a.M;
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<double, double, double, NW>), dim3(M.nblk), dim3(NW * 64),
-                                             0, s, view<double>(*a.K), M, a.v64, a.u, a.invD, a.st, parity, a.part))
+    if (a.K->padded * int64_t(sizeof(double) + sizeof(int)) > kStreamMatrixBytes)
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<double, double, double, NW, true>), dim3(M.nblk),
+                                                 dim3(NW * 64), 0, s, view<double>(*a.K), M, a.v64, a.u, a.invD, a.st,
+                                                 parity, a.part))
+    else
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<double, double, double, NW, false>), dim3(M.nblk),
+                                                 dim3(NW * 64), 0, s, view<double>(*a.K), M, a.v64, a.u, a.invD, a.st,
+                                                 parity, a.part))
 }
 
 void launch_pcg_iter32(const PcgLaunch &a, int parity, hipStream_t s) {
     const RowMap &M = *a.M;
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<float, float, float, NW>), dim3(M.nblk), dim3(NW * 64), 0,
-                                             s, view<float>(*a.K), M, a.v32, a.x32, a.invD32, a.st, parity, a.part))
+    if (a.K->padded * int64_t(sizeof(float) + sizeof(int)) > kStreamMatrixBytes)
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<float, float, float, NW, true>), dim3(M.nblk),
+                                                 dim3(NW * 64), 0, s, view<float>(*a.K), M, a.v32, a.x32, a.invD32,
+                                                 a.st, parity, a.part))
+    else
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_iter<float, float, float, NW, false>), dim3(M.nblk),
+                                                 dim3(NW * 64), 0, s, view<float>(*a.K), M, a.v32, a.x32, a.invD32,
+                                                 a.st, parity, a.part))
 }
 
 void launch_pcg_residual_q(const PcgLaunch &a, const int *act, bool fp32_matrix, hipStream_t s) {

@@ -201,3 +201,25 @@ def test_batch_amg_matches_single_instances(B, precision):
         assert dE.max() <= 1e-9 and dJ.max() <= 1e-8
         assert np.abs(ra["m_avg"][i] - r1["m_avg"]).max() <= 1e-6
         assert sum(s["mi"] for s in ra["stats"][i]) < sum(s["mi"] for s in rj["stats"][i])
+
+
+def test_hard_cube_curve_is_run_to_run_identical(B):
+    """The headline configuration (20^3 hard cube, FP32 bulk, multigrid CG,
+    the workload's j_max) on its first 12 fields, twice in fresh contexts:
+    every reduction has a fixed order, so states, energies and iteration
+    counts agree bit for bit."""
+    w = inputs.hard_cube()
+    out = []
+    for _ in range(2):
+        ctx = B.Context(0).upload(w.mesh)
+        r = ctx.curve(np.array(w.m0), w.fields[:12], jmax=w.jmax, precision=B.MM_FP32_BULK,
+                      poisson_prec=B.MM_PREC_AMG)
+        assert r["rc"] == 0
+        out.append(r)
+        ctx.close()
+    np.testing.assert_array_equal(out[0]["m"], out[1]["m"])
+    np.testing.assert_array_equal(out[0]["E"], out[1]["E"])
+    np.testing.assert_array_equal(out[0]["m_avg"], out[1]["m_avg"])
+    for a, b in zip(out[0]["stats"], out[1]["stats"]):
+        for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks", "status"):
+            assert a[k] == b[k], k
