@@ -306,6 +306,28 @@ def test_hard_cube_full_size_eval(B, oracle_mod):
     ctx.close()
 
 
+def test_film_full_size_eval(B, oracle_mod):
+    """The 1000 nm film at full size (121,203 magnet nodes, 1.79M potential
+    nodes, 13M tets), with the row map and block counts the library picks for
+    it: energy terms, gradient and one j_max = 10 preconditioner solve against
+    the oracle, from a state tilted by up to 0.5 rad."""
+    w = inputs.film()
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_poisson(1e-12)
+    ctx = _ctx(B, w.mesh, poisson_rtol=1e-12)
+    assert ctx.n_mag == 121203
+    m = inputs.tilted_state(o.nm, (1.0, 0.0, 0.0), 0.5, np.random.Generator(np.random.PCG64(21)))
+    h = w.fields[10]
+    rg = ctx.energy_grad(m, h)
+    ro = o.eval_T(m, h)
+    assert np.abs(rg["E"] - ro["E"]).max() <= 1e-10 * np.abs(ro["E"]).sum()
+    assert rel(rg["G"], ro["G"]) < 1e-8
+    y, it = ctx.precondition(m, ro["G"], ro["g"], 10)
+    yo, ito = o.precond(m, ro["lam"], ro["g"], 10)
+    assert it == ito and rel(y, yo) < 1e-8
+    ctx.close()
+
+
 def test_fp32_bulk_error_is_small(B, oracle_mod):
     """FP32 operators with FP64 reductions: the error against the FP64 oracle
     is reported, and must stay near the FP32 rounding of the operators."""
