@@ -98,6 +98,29 @@ def test_batch_energy_grad_matches_oracle(B, oracle_mod):
     ctx.close()
 
 
+def test_batch64_full_size_energy_grad_sampled(B, oracle_mod):
+    """The 64-cube parameter study at full size (9.26M potential nodes in one
+    row map, multigrid CG with 64 hierarchies, the layout its benchmark runs):
+    one batched evaluation from states tilted by up to 0.5 rad, checked
+    against the oracle on the smallest, a middle and the largest instance."""
+    ws = inputs.batch_cubes()
+    ctx = B.Context(0).upload_batch([w.mesh for w in ws])
+    ctx.set_opts(poisson_rtol=1e-12, poisson_prec=B.MM_PREC_AMG)
+    ms = [inputs.tilted_state(w.mesh.magnet_nodes().size, (0.0, 0.0, 1.0), 0.5,
+                              np.random.Generator(np.random.PCG64(40 + i))) for i, w in enumerate(ws)]
+    h = np.array([w.fields[20] for w in ws])
+    r = ctx.batch_energy_grad(np.concatenate(ms), h)
+    Gs = ctx.split(r["G"])
+    order = np.argsort([m.shape[0] for m in ms], kind="stable")
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        o = oracle_mod.Oracle(ws[i].mesh)
+        o.set_poisson(1e-12)
+        ro = o.eval_T(ms[i], h[i])
+        assert abs(r["E"][i] - ro["E"][4]) <= 1e-10 * np.abs(ro["E"][:4]).sum(), i
+        assert np.abs(Gs[i] - ro["G"]).max() <= 1e-8 * np.abs(ro["G"]).max(), i
+    ctx.close()
+
+
 def test_batch_curve_matches_oracle(B, oracle_mod):
     meshes = batch_meshes()
     m0 = start_states(meshes)
