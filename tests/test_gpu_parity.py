@@ -328,6 +328,35 @@ def test_film_full_size_eval(B, oracle_mod):
     ctx.close()
 
 
+def test_polycrystal_full_size_uniform_state(B):
+    """The 200 nm polycrystal at full size (912,673 magnet nodes, 23.6M
+    potential nodes, 143M tets) is beyond an oracle run in seconds, so a
+    uniform state is checked against closed forms. Every Kuhn tet has volume
+    h^3/6, so the anisotropy energy is -sum_e K_e V_e (u_e.m)^2 and the Zeeman
+    energy -sum_e Ms_e V_e h.m (reduced units). The exchange energy vanishes,
+    and the stray-field energy density lies below the uniform cube's exact
+    Kd/3 (the air box only understates it)."""
+    w = inputs.polycrystal()
+    mesh = w.mesh
+    ctx = _ctx(B, mesh)
+    assert ctx.n_mag == 912673
+    mdir = np.array([0.3, 0.2, 0.93])
+    mdir /= np.linalg.norm(mdir)
+    BT = np.array([0.05, -0.02, -0.5])
+    r = ctx.energy_grad(np.tile(mdir, (ctx.n_mag, 1)), BT)
+    ms_ref = mesh.Ms.max()
+    mag = mesh.region > 0
+    vol = mesh.h ** 3 / 6.0
+    e_an = -np.sum(mesh.K1[mag] * (mesh.axis[mag] @ mdir) ** 2) * vol / (MU0 * ms_ref ** 2)
+    e_z = -np.sum(mesh.Ms[mag]) / ms_ref * vol * ((BT / (MU0 * ms_ref)) @ mdir)
+    assert abs(r["E"][0]) <= 1e-9 * abs(e_an)
+    assert abs(r["E"][1] - e_an) <= 1e-10 * abs(e_an)
+    assert abs(r["E"][2] - e_z) <= 1e-10 * abs(e_z)
+    e_d = 2.0 * r["E"][3] / (mag.sum() * vol)
+    assert 0.29 < e_d < 1.0 / 3.0, e_d
+    ctx.close()
+
+
 def test_fp32_bulk_error_is_small(B, oracle_mod):
     """FP32 operators with FP64 reductions: the error against the FP64 oracle
     is reported, and must stay near the FP32 rounding of the operators."""
