@@ -64,6 +64,23 @@ _ip = C.POINTER(C.c_int)
 _lp = C.POINTER(C.c_long)
 
 
+def direction(kind, g1, g0, y, d, gy_prev):
+    """The direction update of Alg. 4 alone (beta* of `kind` with the descent
+    safeguard) on plain vectors: returns (d_new, <g, y> for the next step,
+    whether the safeguard acted)."""
+    L = _load()
+    if not hasattr(L, "_dir_set"):
+        L.or_direction_pub.restype = C.c_double
+        L.or_direction_pub.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp, _dp, C.c_double, _dp, _ip]
+        L._dir_set = True
+    g1, g0, y, d = (np.ascontiguousarray(v, dtype=np.float64).ravel() for v in (g1, g0, y, d))
+    dn = np.zeros_like(g1)
+    fb = C.c_int(0)
+    gy = L.or_direction_pub(int(kind), g1.size, _d(g1), _d(g0), _d(y), _d(d), float(gy_prev), _d(dn),
+                            C.byref(fb))
+    return dn, float(gy), bool(fb.value)
+
+
 def _load():
     global _lib
     if _lib is not None:

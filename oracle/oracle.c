@@ -771,6 +771,58 @@ static double beta_star(int kind, double num, double den, double gy1, double gy0
 }
 
 /*
+ * The next direction of Alg. 4 from the gradients g1 (new iterate) and g0
+ * (previous), the preconditioned gradient y at g1 and the previous direction
+ * d: dn = -y + beta* d. With the descent safeguard (reading S7): if dn is
+ * not a descent direction, y is replaced by g1 and beta* recomputed, and if
+ * that fails too, dn = -g1. gy_prev is <g, y> of the previous step. Returns
+ * the <g, y> the next step divides by; *dpn = <g1, dn>; *fallback = 1 when
+ * the safeguard acted.
+ */
+static double direction(int kind, long n3, const double *g1, const double *g0, const double *y,
+                        const double *d, double gy_prev, double *dn, double *dpn, int *fallback) {
+    ksum kn = {0, 0}, kd = {0, 0}, ky = {0, 0};
+    for (long i = 0; i < n3; i++) {
+        double dg = g1[i] - g0[i];
+        ks_add(&kn, dg * y[i]);
+        ks_add(&kd, dg * d[i]);
+        ks_add(&ky, g1[i] * y[i]);
+    }
+    double num = ks_val(&kn), den = ks_val(&kd), gy1 = ks_val(&ky);
+    double beta = beta_star(kind, num, den, gy1, gy_prev);
+    for (long i = 0; i < n3; i++) dn[i] = -y[i] + beta * d[i];
+    double dp = dot_n(g1, dn, n3);
+    double gy_next = gy1;
+    *fallback = 0;
+    if (!(dp < 0.0)) {
+        *fallback = 1;
+        ksum k2 = {0, 0}, kg = {0, 0};
+        for (long i = 0; i < n3; i++) {
+            ks_add(&k2, (g1[i] - g0[i]) * g1[i]);
+            ks_add(&kg, g1[i] * g1[i]);
+        }
+        double num2 = ks_val(&k2);
+        gy_next = ks_val(&kg);
+        beta = beta_star(kind, num2, den, gy_next, gy_prev);
+        for (long i = 0; i < n3; i++) dn[i] = -g1[i] + beta * d[i];
+        dp = dot_n(g1, dn, n3);
+        if (!(dp < 0.0)) {
+            for (long i = 0; i < n3; i++) dn[i] = -g1[i];
+            dp = dot_n(g1, dn, n3);
+        }
+    }
+    *dpn = dp;
+    return gy_next;
+}
+
+/* the same, for tests */
+double or_direction_pub(int kind, long n3, const double *g1, const double *g0, const double *y, const double *d,
+                        double gy_prev, double *dn, int *fallback) {
+    double dp;
+    return direction(kind, n3, g1, g0, y, d, gy_prev, dn, &dp, fallback);
+}
+
+/*
  * Alg. 4 for one reduced field h, starting from m (unit vectors), m updated in place.
  * Direction update: beta*ZA = <g+ - g, y+> / <g+ - g, d> if y+.g+ > y+.g else 0
  * (zero also when the denominator is not positive, reading S12), or the
@@ -843,35 +895,10 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
         if (conv) { st_copy(&s0, &s1, nm); status = 0; break; }
         /* precondition at the new iterate */
         or_precond(c, s1.x, s1.lam, s1.g, o->jmax, NULL, y, o->terms, o->pform);
-        ksum kn = {0, 0}, kd = {0, 0}, ky = {0, 0};
-        for (long i = 0; i < n3; i++) {
-            double dg = s1.g[i] - s0.g[i];
-            ks_add(&kn, dg * y[i]);
-            ks_add(&kd, dg * d[i]);
-            ks_add(&ky, s1.g[i] * y[i]);
-        }
-        double num = ks_val(&kn), den = ks_val(&kd), gy1 = ks_val(&ky);
-        double beta = beta_star(o->beta, num, den, gy1, gy_prev);
-        for (long i = 0; i < n3; i++) dn[i] = -y[i] + beta * d[i];
-        double dpn = dot_n(s1.g, dn, n3);
-        double gy_next = gy1;
-        if (!(dpn < 0.0)) {
-            stats->fallbacks++;
-            ksum k2 = {0, 0}, kg = {0, 0};
-            for (long i = 0; i < n3; i++) {
-                ks_add(&k2, (s1.g[i] - s0.g[i]) * s1.g[i]);
-                ks_add(&kg, s1.g[i] * s1.g[i]);
-            }
-            double num2 = ks_val(&k2);
-            gy_next = ks_val(&kg);
-            beta = beta_star(o->beta, num2, den, gy_next, gy_prev);
-            for (long i = 0; i < n3; i++) dn[i] = -s1.g[i] + beta * d[i];
-            dpn = dot_n(s1.g, dn, n3);
-            if (!(dpn < 0.0)) {
-                for (long i = 0; i < n3; i++) dn[i] = -s1.g[i];
-                dpn = dot_n(s1.g, dn, n3);
-            }
-        }
+        int fallback;
+        double dpn;
+        double gy_next = direction(o->beta, n3, s1.g, s0.g, y, d, gy_prev, dn, &dpn, &fallback);
+        if (fallback) stats->fallbacks++;
         gy_prev = gy_next;
         a_prev = alpha;
         dp_prev = dp0;

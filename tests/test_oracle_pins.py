@@ -590,3 +590,75 @@ def test_preconditioner_forms_reach_the_same_minimum(oracle_mod):
         assert abs(res[form][0] - res[0][0]) <= 1e-11 * abs(res[0][0]), form
         assert np.abs(res[form][3] - res[0][3]).max() < 1e-5, form
     assert len({(res[k][1], res[k][2]) for k in range(3)}) == 3
+
+
+def test_direction_update_reduces_to_linear_cg(oracle_mod):
+    """On a strictly convex quadratic, with exact line searches and no
+    preconditioning (y = g), successive gradients are orthogonal and each is
+    orthogonal to the previous direction. So FR, PRP, HS and the restarted HS
+    (ZA) of Sec. 2.1 all reduce to the coefficient |g_k+1|^2 / |g_k|^2 of
+    linear CG: the direction update must reproduce the search directions of
+    textbook linear CG (residual form, Hestenes and Stiefel)."""
+    rng = np.random.default_rng(3)
+    n = 12
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x = np.zeros(n)
+    r = b - A @ x
+    p = r.copy()
+    gs, ps = [-r.copy()], [p.copy()]
+    for _ in range(n - 2):
+        Ap = A @ p
+        alpha = (r @ r) / (p @ Ap)
+        x = x + alpha * p
+        r_new = r - alpha * Ap
+        p = r_new + ((r_new @ r_new) / (r @ r)) * p
+        r = r_new
+        gs.append(-r.copy())
+        ps.append(p.copy())
+    for kind in range(4):
+        for k in range(len(gs) - 1):
+            g0, g1 = gs[k], gs[k + 1]
+            dn, gy, fb = oracle_mod.direction(kind, g1, g0, g1, ps[k], g0 @ g0)
+            assert not fb, (kind, k)
+            np.testing.assert_allclose(dn, ps[k + 1], rtol=0, atol=1e-9 * np.abs(ps[k + 1]).max())
+            assert abs(gy - g1 @ g1) <= 1e-12 * (g1 @ g1)
+
+
+def test_direction_safeguard_and_restart(oracle_mod):
+    """The descent safeguard of Alg. 4 and the restart of beta*ZA. A
+    preconditioned gradient pointing uphill (y = -g, previous direction 0)
+    gives -y, which is not a descent direction, so y is replaced by g and the
+    direction becomes -g. A new gradient that is half the old one
+    (<g1 - g0, y1> < 0) restarts beta*ZA (dn = -y), while beta*HS keeps the
+    negative coefficient."""
+    rng = np.random.default_rng(4)
+    g1 = rng.standard_normal(9)
+    g0 = rng.standard_normal(9)
+    dn, gy, fb = oracle_mod.direction(0, g1, g0, -g1, np.zeros(9), 1.0)
+    assert fb
+    np.testing.assert_array_equal(dn, -g1)
+    assert gy == pytest.approx(g1 @ g1)
+    g0 = 2.0 * g1
+    d0 = -g0 + 0.1 * rng.standard_normal(9)     # a descent direction at g0
+    dn, _, fb = oracle_mod.direction(0, g1, g0, g1, d0, g0 @ g0)
+    assert not fb
+    np.testing.assert_array_equal(dn, -g1)
+    dn3, _, _ = oracle_mod.direction(3, g1, g0, g1, d0, g0 @ g0)
+    beta3 = ((g1 - g0) @ g1) / ((g1 - g0) @ d0)
+    assert beta3 < 0.0
+    if (g1 @ (-g1 + beta3 * d0)) < 0.0:
+        np.testing.assert_allclose(dn3, -g1 + beta3 * d0, rtol=1e-14, atol=1e-14)
+
+
+def test_direction_without_gradient_change_restarts_prp_hs_za(oracle_mod):
+    """When the gradient does not change (g1 = g0), the numerator of PRP, HS
+    and ZA vanishes, so they restart along -y, while FR keeps the coefficient
+    |g1|^2 / |g0|^2 = 1: the property that separates FR from the others."""
+    g = np.random.default_rng(5).standard_normal(9)
+    d0 = -g
+    for kind in (1, 2, 3, 0):
+        dn, _, fb = oracle_mod.direction(kind, g, g, g, d0, g @ g)
+        assert not fb
+        np.testing.assert_allclose(dn, -2.0 * g if kind == 1 else -g, rtol=1e-14, atol=0)
