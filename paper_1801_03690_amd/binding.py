@@ -4,8 +4,9 @@ Argument marshalling only: every step of the method runs in the HIP library.
 Vectors may be numpy arrays (host) or torch tensors on the context's GPU
 (device pointers are passed straight through). PyTorch supplies device memory
 (its caching allocator, through the ABI's allocator callbacks) and the stream.
-If the shared library is missing this module raises at import time: there is
-no CPU fallback.
+The library is loaded on first use, after torch (whose HIP runtime must be in
+the process first). If it is missing, that first use raises ImportError: there
+is no CPU fallback.
 """
 from __future__ import annotations
 
