@@ -109,7 +109,7 @@ def main():
     if args.poisson_prec == "auto":
         args.poisson_prec = AUTO_PREC[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
