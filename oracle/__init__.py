@@ -44,7 +44,7 @@ class Stats(C.Structure):
     _fields_ = [("evals", C.c_long), ("nli", C.c_long), ("li", C.c_long), ("mi", C.c_long),
                 ("restarts", C.c_long), ("fallbacks", C.c_long), ("ls_fail", C.c_long),
                 ("F", C.c_double), ("tmax", C.c_double), ("status", C.c_long),
-                ("max_trap_err", C.c_double)]
+                ("max_trap_err", C.c_double), ("n_rise", C.c_long), ("max_rise", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +79,16 @@ def direction(kind, g1, g0, y, d, gy_prev):
     gy = L.or_direction_pub(int(kind), g1.size, _d(g1), _d(g0), _d(y), _d(d), float(gy_prev), _d(dn),
                             C.byref(fb))
     return dn, float(gy), bool(fb.value)
+
+
+def cubic_min(at, dFt, dp0, dpt):
+    """The line search's interpolation step alone: the minimizer of the cubic
+    through phi(0) = 0, phi'(0) = dp0, phi(at) = dFt, phi'(at) = dpt, or None
+    when that cubic has no local minimizer."""
+    L = _load()
+    ac = np.zeros(1)
+    ok = L.or_cubic_min_pub(float(at), float(dFt), float(dp0), float(dpt), _d(ac))
+    return float(ac[0]) if ok else None
 
 
 def _load():
@@ -122,6 +132,8 @@ def _load():
     L.or_minimize.argtypes = [vp, _dp, _dp, C.POINTER(Opts), C.POINTER(Stats), _dp]
     L.or_curve.restype = C.c_int
     L.or_curve.argtypes = [vp, _dp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats), _dp]
+    L.or_cubic_min_pub.restype = C.c_int
+    L.or_cubic_min_pub.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
     L.or_sizeof_opts.restype = C.c_long
     L.or_sizeof_stats.restype = C.c_long
     assert L.or_sizeof_opts() == C.sizeof(Opts), "oracle opts layout mismatch"

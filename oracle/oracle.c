@@ -495,7 +495,7 @@ long or_eval(or_ctx *c, const double *m, const double *h, int terms, double *E, 
         double l = ma[0] * Gt[0] + ma[1] * Gt[1] + ma[2] * Gt[2];
         double gp[3] = {Gt[0] - l * ma[0], Gt[1] - l * ma[1], Gt[2] - l * ma[2]};
         double t = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]) / c->L[a];
-        if (t > tm) tm = t;
+        if (t > tm || t != t) tm = t;   /* a NaN torque stays NaN */
         if (G) for (int d = 0; d < 3; d++) G[3 * a + d] = Gt[d];
         if (g) for (int d = 0; d < 3; d++) g[3 * a + d] = gp[d];
         if (lam) lam[a] = l;
@@ -616,8 +616,10 @@ typedef struct {
     long evals, nli, li, mi, restarts, fallbacks, ls_fail;
     double F;
     double tmax;
-    long status;        /* 0 ok, 1 not converged, 2 stalled */
+    long status;        /* 0 ok, 1 not converged, 2 stalled, 3 non-finite energy or gradient */
     double max_trap_err; /* max |(F+ - F) - dF_trapezoid| over accepted steps */
+    long n_rise;        /* accepted steps whose energy total F+ exceeds F */
+    double max_rise;    /* largest F+ - F over accepted steps (<= 0 when every step decreased F) */
 } or_stats;
 
 typedef struct {
@@ -679,6 +681,7 @@ static void ls_eval(or_ctx *c, const or_state *s0, const double *d, double alpha
 
 /* cubic Hermite minimizer through (0, 0, dp0) and (at, dFt, dpt)
    (Nocedal & Wright, interpolation step of the line search); returns 0 if none */
+int or_cubic_min_pub(double at, double dFt, double dp0, double dpt, double *ac);
 static int cubic_min(double at, double dFt, double dp0, double dpt, double *ac) {
     double d1 = dp0 + dpt - 3.0 * dFt / at;
     double disc = d1 * d1 - dp0 * dpt;
@@ -738,6 +741,10 @@ static int line_search(or_ctx *c, const or_opts *o, const double *h, const or_st
         if (dFa <= o->c1 * a * dp0) { *alpha = a; *dF_acc = dFa; return 1; }
     }
     return 0;
+}
+
+int or_cubic_min_pub(double at, double dFt, double dp0, double dpt, double *ac) {
+    return cubic_min(at, dFt, dp0, dpt, ac);
 }
 
 static double max_norm3(const double *v, long nm) {
@@ -843,7 +850,10 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
     memset(stats, 0, sizeof(*stats));
     or_eval(c, s0.x, h, o->terms, s0.E, s0.G, s0.g, s0.lam, &s0.tmax);
     stats->evals++;
+    stats->max_rise = -INFINITY;
     int status = 1;
+    /* a NaN or infinite energy or torque is reported, never taken for convergence */
+    if (!isfinite(s0.E[4]) || !isfinite(s0.tmax)) { status = 3; goto done; }
     if (o->stop_mode == 0 && s0.tmax < o->tol_torque) { status = 0; goto done; }
     or_precond(c, s0.x, s0.lam, s0.g, o->jmax, NULL, y, o->terms, o->pform);
     for (long i = 0; i < n3; i++) d[i] = -y[i];
@@ -858,7 +868,9 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
     int first = 1;
     double a_prev = 0.0, dp_prev = 0.0;
     for (long it = 0; it < o->max_nli; it++) {
-        if (!(dp0 < 0.0)) { status = 0; break; } /* zero projected gradient */
+        /* after the safeguard d = -g gives dp0 = -|g|^2: zero only at a zero
+           projected gradient; anything else that is not negative is NaN */
+        if (!(dp0 < 0.0)) { status = dp0 == 0.0 ? 0 : 3; break; }
         double dmax = max_norm3(d, nm);
         double a0;
         if (first) a0 = o->jmax > 0 ? 1.0 : o->theta_init / dmax;
@@ -876,8 +888,12 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
             ok = line_search(c, o, h, &s0, d, dp0, o->theta_init / dmax, &s1, &tmp, &alpha, &dFacc, stats);
             if (!ok) { stats->ls_fail++; status = 2; break; }
         }
-        double terr = fabs((s1.E[4] - s0.E[4]) - dFacc);
+        if (!isfinite(s1.E[4]) || !isfinite(s1.tmax)) { status = 3; break; }
+        double rise = s1.E[4] - s0.E[4];
+        double terr = fabs(rise - dFacc);
         if (terr > stats->max_trap_err) stats->max_trap_err = terr;
+        if (rise > 0.0) stats->n_rise++;
+        if (rise > stats->max_rise) stats->max_rise = rise;
         stats->nli++;
         /* convergence */
         int conv;

@@ -662,3 +662,99 @@ def test_direction_without_gradient_change_restarts_prp_hs_za(oracle_mod):
         dn, _, fb = oracle_mod.direction(kind, g, g, g, d0, g @ g)
         assert not fb
         np.testing.assert_allclose(dn, -2.0 * g if kind == 1 else -g, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# line-search pieces, the Jacobi diagonal, energy decrease per step
+# ---------------------------------------------------------------------------
+
+def _cubic_local_min(c3, c2, c1):
+    """Local minimizer of c3 a^3 + c2 a^2 + c1 a from the roots of its
+    derivative (numpy), or None."""
+    if c3 == 0.0:
+        return -c1 / (2 * c2) if c2 > 0 else None
+    best = None
+    for r in np.roots([3 * c3, 2 * c2, c1]):
+        if abs(r.imag) < 1e-12 and 6 * c3 * r.real + 2 * c2 > 0:
+            best = r.real
+    return best
+
+
+@pytest.mark.parametrize("c3,c2,c1,at", [
+    (1.0, 0.5, -2.0, 3.0),      # trial beyond the minimizer (overshoot)
+    (1.0, 0.5, -2.0, 0.3),      # trial short of it (undershoot)
+    (-1.0, 3.0, -2.0, 0.9),     # concave at large a, local minimum at 1 - 1/sqrt(3)
+    (0.0, 1.0, -2.0, 5.0),      # a parabola: minimizer 1
+    (2e-3, 4e2, -1e-3, 1e-7),   # scales of a late line search (tiny step, stiff curvature)
+    (-1.0, 1.0, -2.0, 0.5),     # phi' < 0 everywhere: no local minimizer
+])
+def test_cubic_step_recovers_the_minimizer_of_a_cubic(oracle_mod, c3, c2, c1, at):
+    """The line search's interpolation step (the cubic through the values and
+    slopes at 0 and at the trial) must give back the local minimizer of any
+    cubic it is fed samples of: four Hermite data fix a cubic, so on a cubic
+    the step is exact up to rounding."""
+    phi = c3 * at ** 3 + c2 * at ** 2 + c1 * at
+    dphi_t = 3 * c3 * at ** 2 + 2 * c2 * at + c1
+    ac = oracle_mod.cubic_min(at, phi, c1, dphi_t)
+    want = _cubic_local_min(c3, c2, c1)
+    if want is None:
+        assert ac is None
+    else:
+        assert ac is not None and abs(ac - want) <= 1e-10 * abs(want), (ac, want)
+
+
+def test_jacobi_diagonal_is_the_exchange_diagonal(oracle_mod):
+    """Sec. 2.2 takes the Jacobi preconditioner of Alg. 1 from the diagonal of
+    the exchange matrix: D_a = <e, C_A e> for the unit vector e of any
+    component of node a. On a Kuhn grid the P1 Laplacian is the 7-point stencil
+    (centre weight 6h), so an interior node has D = 2 a 6h."""
+    h, A = 2.5, 1.3e-11
+    mesh = inputs.small_box((4, 3, 3), h, air=False, A=A)
+    o = oracle_mod.Oracle(mesh)
+    D = o.jacobi_diag()
+    for comp in range(3):
+        for a in range(o.nm):
+            e = np.zeros((o.nm, 3))
+            e[a, comp] = 1.0
+            assert abs(o.apply_C(e, oracle_mod.T_EXCH)[a, comp] - D[a]) <= 1e-13 * D[a]
+    a_red = A / (MU0 * mesh.Ms.max() ** 2 * 1e-18)
+    x = mesh.xyz[o.magnet_nodes()]
+    lo, hi = x.min(0), x.max(0)
+    interior = np.all((x > lo + 1e-9) & (x < hi - 1e-9), axis=1)
+    assert interior.sum() == 3 * 2 * 2
+    np.testing.assert_allclose(D[interior], 2.0 * a_red * 6.0 * h, rtol=1e-13)
+    assert np.all(D[~interior] < 2.0 * a_red * 6.0 * h)
+
+
+@pytest.mark.parametrize("case", ["soft_relax", "hard_reversal"])
+def test_accepted_steps_lower_the_energy(oracle_mod, case):
+    """Alg. 4 with the sufficient-decrease line search lowers F at every
+    accepted step, and the energy difference the line search tests (the
+    exact one of the quadratic F, taken between unit vectors) equals F+ - F of
+    the evaluated totals up to rounding. The Poisson tolerance is tightened
+    so that rounding is the only error left in F."""
+    if case == "soft_relax":
+        w = inputs.soft_cube(n=4, h=4.0)
+        m0 = inputs.tilted_state(w.m0.shape[0], (0.3, 0.1, 0.95), 0.4, np.random.Generator(np.random.PCG64(3)))
+        field, jmax = w.fields[4], 4
+    else:
+        w = inputs.hard_cube(n=4, h=4.0)
+        m0, field, jmax = w.m0, np.array([0.0, 0.0, -7.0]), 10
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_poisson(1e-14)
+    m, E, st, rc = o.minimize(m0, field, jmax=jmax)
+    assert rc == 0 and st["nli"] >= 5
+    scale = np.abs(E[:4]).sum()
+    assert st["n_rise"] == 0, st
+    assert st["max_rise"] < 0.0
+    assert st["max_trap_err"] <= 1e-11 * scale, (st["max_trap_err"], scale)
+
+
+def test_nonfinite_field_is_reported_not_converged(oracle_mod):
+    """A NaN in the evaluation must not read as a zero torque: the status is
+    'non-finite' (3), never 'converged' (0)."""
+    w = inputs.soft_cube(n=3, h=4.0)
+    o = oracle_mod.Oracle(w.mesh)
+    m, E, st, rc = o.minimize(w.m0, [np.nan, 0.0, 1.0], jmax=4)
+    assert rc == 3 and st["status"] == 3
+    np.testing.assert_array_equal(m, w.m0)
