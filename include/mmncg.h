@@ -65,7 +65,9 @@ enum {
     MM_EMESH = -4,         /* degenerate tet, no magnet, inconsistent mesh */
     MM_ESTATE = -5,        /* call out of order (e.g. no mesh/material yet) */
     MM_NOT_CONVERGED = 1,  /* max_nli reached; outputs hold the last iterate */
-    MM_STALLED = 2         /* line search failed twice (also along -g) */
+    MM_STALLED = 2,        /* line search failed twice (also along -g) */
+    MM_NONFINITE = 3       /* an evaluation gave a NaN or infinite energy (e.g. a breakdown of a
+                              linear solve); outputs hold the last finite accepted iterate */
 };
 
 enum { MM_FP64 = 0, MM_FP32_BULK = 1 };
@@ -121,7 +123,7 @@ typedef struct {
     double t_nl, t_lin, t_mag; /* seconds: total, preconditioner, magnetostatics */
     double F;              /* final total energy (reduced units) */
     double torque_max;     /* final max |m x h_eff| */
-    int status;            /* MM_OK, MM_NOT_CONVERGED or MM_STALLED */
+    int status;            /* MM_OK, MM_NOT_CONVERGED, MM_STALLED or MM_NONFINITE */
 } mm_stats;
 
 typedef struct {
@@ -214,7 +216,10 @@ int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out);
 /* Scalar-potential solve K u = b by preconditioned CG (the preconditioner
    and precision of the context's options: Jacobi or multigrid, FP64 or
    FP32-bulk), warm-started from u_inout (n_pot), until |r| <= rtol |b|.
-   iters may be NULL. */
+   iters may be NULL. Returns MM_NOT_CONVERGED with the last iterate in
+   u_inout when poisson_maxit iterations do not reach rtol. The solve uses the
+   context's own potential buffers; on every exit, failures included, they are
+   reset so that later evaluations see the context as before the call. */
 int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, long *iters);
 
 /* Measurement hook. enable = 1 times the scalar-potential CG iterations (the
@@ -233,11 +238,27 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
    fine CG vectors at 8 bytes). */
 int mm_profile(mm_ctx *c, int enable, double out[4]);
 
+/* Per-launch timing of the field kernels of the energy evaluation (Sec. 2.2,
+   eq. (energy): C m + B^T u with the projection of eqs. (proj), (nablaLF)),
+   the divergence right-hand side B m (the scalar potential of Sec. 3.1), and
+   the preconditioner product P v of Alg. 1 (eq. (precond)). With enable = 1,
+   HIP events on the context's stream bracket every launch of the evaluation
+   epilogue and of B m, and the first P v of each inner solve (later ones may
+   return at once after an exit of Alg. 1); enable = 0 stops; -1 resets. out
+   (9 doubles, may be NULL) receives, for the epilogue, B m and P v in turn:
+   timed launches, seconds, algorithmic bytes of those launches. Algorithmic
+   bytes: every stored operator entry (values + column index, no padding) once
+   and every magnet-node vector the kernel reads or writes once (epilogue: C,
+   B^T, m, L, G, g, lambda, and for a line-search trial x, d, g, lambda of the
+   current state; B m: B, m, b; P v: C, m, lambda, v, P v, and g with all four
+   terms of eq. (precond)). */
+int mm_profile_kernels(mm_ctx *c, int enable, double out[9]);
+
 /* Block shape of the scalar-potential kernels (the dominant work). Waves per
    block NW in {4, 8, 16} is one choice for the whole launch; SELL slices per
    wave in {1, 2, 4} is chosen per instance size bucket (bucket =
    floor(log2(n_pot / 4096)) clamped to 0..7). A block of an instance covers NW
-   x slices-per-wave slices (at most 256 blocks per instance).
+   x slices-per-wave slices (up to the block cap below).
    MM_TUNE_DEFAULT: NW = 16, one slice per wave (the state after upload).
    MM_TUNE_MEASURE: times 32 CG iterations (best of 3, HIP events) of a
    synthetic solve of the whole batch (b = 1, u = 0, every instance active):
@@ -246,14 +267,18 @@ int mm_profile(mm_ctx *c, int enable, double out[4]);
    MM_TUNE_CACHE: as MEASURE, but a batch of the same composition (buckets and
    their instance counts) on the same device and precision (options of
    mm_set_opts) reuses the choice stored in the JSON file cache_path without
-   timing; otherwise the new choice is appended to the file.
+   timing; otherwise the new choice is appended to the file. Every choice is
+   timed at 1, 2 and 4 times the default cap on blocks per instance (256, or
+   one per 8192 rows for very large instances; at most 2048).
    The chosen shape stays fixed until the next mm_tune or upload, so a run is
    deterministic; another shape may change the rounding of the potential
    solves (another grouping of the reductions), never their tolerance. The
    warm start and the context's right-hand side are preserved. Outputs (may be
-   NULL): waves_per_block, slices_per_wave (n_inst ints). */
+   NULL): waves_per_block, slices_per_wave (n_inst ints), block_mult (the
+   multiplier of the block cap). */
 enum { MM_TUNE_DEFAULT = 0, MM_TUNE_MEASURE = 1, MM_TUNE_CACHE = 2 };
-int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave);
+int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave,
+            int *block_mult);
 
 /* ---------------------------------------------------------------------------
    Batches of independent instances (parameter studies, Sec. 3.1 curves of
@@ -395,6 +420,13 @@ const char *mm_gnn_last_error(const mm_gnn *g);
 /* Parameters as doubles (host or device), kept as FP32 masters; setting
    them also resets the optimizer state. */
 int mm_gnn_set_params(mm_gnn *g, const double *theta);
+
+/* Arithmetic of the network's dense layers: MM_GNN_BF16 (the default: BF16
+   operands on the matrix cores, FP32 accumulation) or MM_GNN_FP32 (a debug
+   mode: the same products with FP32 operands on the vector units, for checking
+   the forward and backward passes against an FP64 reference). */
+enum { MM_GNN_BF16 = 0, MM_GNN_FP32 = 1 };
+int mm_gnn_set_precision(mm_gnn *g, int precision);
 int mm_gnn_get_params(mm_gnn *g, double *theta);
 /* Input standardization applied in FP32 before the first layer: X_c <-
    (X_c - mu_c) / sd_c for the 32 feature columns (host arrays; sd > 0).
@@ -441,10 +473,13 @@ int mm_demag_diag(mm_ctx *c, const double *probes, int n_probe, double rtol, dou
    the candidate start when it lowers the energy, MM_LEARN_SCALE uses the
    Jacobi factors for that field step's preconditioner solves; mode 0 is the
    plain method. accepted (n ints, may be NULL) marks the fields whose
-   candidate start was taken. */
+   candidate start was taken. h_prev (3 doubles, Tesla, may be NULL) is the
+   field at which m_inout is a minimizer when the call continues a curve: the
+   first field then gets the proposal as well, so a curve run in several calls
+   takes the same steps as one call. */
 int mm_demag_curve_learned(mm_ctx *c, mm_gnn *net, mm_graph *graph, int mode, double *m_inout,
-                           const double *h_list, long n, const mm_opts *o, double *m_avg, double *E_tot,
-                           mm_stats *st, int *accepted);
+                           const double *h_prev, const double *h_list, long n, const mm_opts *o, double *m_avg,
+                           double *E_tot, mm_stats *st, int *accepted);
 
 #ifdef __cplusplus
 }

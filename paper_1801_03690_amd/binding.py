@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libmmncg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mmncg.h")
 
 MM_OK, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_EMESH, MM_ESTATE = 0, -1, -2, -3, -4, -5
-MM_NOT_CONVERGED, MM_STALLED = 1, 2
+MM_NOT_CONVERGED, MM_STALLED, MM_NONFINITE = 1, 2, 3
 MM_FP64, MM_FP32_BULK = 0, 1
 MM_PREC_JACOBI, MM_PREC_AMG = 0, 1
 MM_BETA_ZA, MM_BETA_FR, MM_BETA_PRP, MM_BETA_HS = 0, 1, 2, 3
@@ -33,6 +33,7 @@ MM_T_EXCH, MM_T_ANIS, MM_T_ZEE, MM_T_DEMAG, MM_T_ALL = 1, 2, 4, 8, 15
 MM_OP_C, MM_OP_B, MM_OP_BT, MM_OP_K = 0, 1, 2, 3
 MM_TUNE_DEFAULT, MM_TUNE_MEASURE, MM_TUNE_CACHE = 0, 1, 2
 MM_LEARN_START, MM_LEARN_SCALE = 1, 2
+MM_GNN_BF16, MM_GNN_FP32 = 0, 1
 
 
 class MMError(RuntimeError):
@@ -111,13 +112,14 @@ def load_library(path=LIB_PATH):
     L.mm_operator_apply.argtypes = [_vp, C.c_int, _vp, _vp]
     L.mm_poisson_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.POINTER(C.c_long)]
     L.mm_profile.argtypes = [_vp, C.c_int, _dp]
+    L.mm_profile_kernels.argtypes = [_vp, C.c_int, _dp]
     _lp = C.POINTER(C.c_long)
     L.mm_batch_upload.argtypes = [_vp, C.c_int, _lp, _lp, _dp, _ip, _ip, _dp, _dp, _dp, _dp]
     L.mm_batch_size.argtypes = [_vp, _ip]
     L.mm_batch_info.argtypes = [_vp, C.c_int, C.POINTER(Info)]
     L.mm_batch_magnet_nodes.argtypes = [_vp, C.c_int, _lp, _ip]
     L.mm_batch_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
-    L.mm_tune.argtypes = [_vp, C.c_int, C.c_char_p, _ip, _ip]
+    L.mm_tune.argtypes = [_vp, C.c_int, C.c_char_p, _ip, _ip, _ip]
     _fp = C.POINTER(C.c_float)
     L.mm_gnn_param_count.restype = C.c_long
     L.mm_gnn_param_count.argtypes = []
@@ -135,10 +137,11 @@ def load_library(path=LIB_PATH):
     L.mm_gnn_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.mm_gnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp]
     L.mm_gnn_adam.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.mm_gnn_set_precision.argtypes = [_vp, C.c_int]
     L.mm_demag_diag.argtypes = [_vp, _vp, C.c_int, C.c_double, _vp]
     L.mm_jacobi_diag.argtypes = [_vp, _vp]
-    L.mm_demag_curve_learned.argtypes = [_vp, _vp, _vp, C.c_int, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp,
-                                         C.POINTER(Stats), _ip]
+    L.mm_demag_curve_learned.argtypes = [_vp, _vp, _vp, C.c_int, _vp, _dp, _dp, C.c_long, C.POINTER(Opts), _dp,
+                                         _dp, C.POINTER(Stats), _ip]
     L.mm_batch_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats)]
     for name in header_symbols():
         if name not in ("mm_last_error", "mm_gnn_last_error", "mm_gnn_param_count"):
@@ -248,6 +251,7 @@ class Context:
         if rc != MM_OK:
             raise MMError(rc, "mm_create failed")
         self.h = h
+        self.last_rc = 0
         self.n_mag = 0
         self.n_pot = 0
         _LIVE.add(self)
@@ -371,20 +375,33 @@ class Context:
         return dict(iterations=it, seconds=float(out[1]), bytes=float(out[2]),
                     bytes_per_iteration=float(out[2]) / it if it else 0.0, rows=int(out[3]))
 
+    def profile_kernels(self, enable):
+        """Per-launch timers of the field kernels (mm_profile_kernels):
+        {name: dict(launches, seconds, bytes)} for the evaluation epilogue,
+        B m and the preconditioner product."""
+        out = np.zeros(9)
+        self._check(self._L.mm_profile_kernels(self.h, int(enable), out.ctypes.data_as(_dp)))
+        names = ("k_eval_epilogue", "k_bmul", "k_prec_apply")
+        return {n: dict(launches=int(out[3 * k]), seconds=float(out[3 * k + 1]), bytes=float(out[3 * k + 2]))
+                for k, n in enumerate(names)}
+
     def tune(self, mode=MM_TUNE_MEASURE, cache_path=None):
         """Pick the block shape of the scalar-potential kernels (mm_tune)."""
         ni = max(1, getattr(self, "n_inst", 1))
         nw = C.c_int()
         spw = np.zeros(ni, dtype=np.int32)
         path = None if cache_path is None else os.fsencode(cache_path)
-        self._check(self._L.mm_tune(self.h, int(mode), path, C.byref(nw), spw.ctypes.data_as(_ip)))
+        bm = C.c_int()
+        self._check(self._L.mm_tune(self.h, int(mode), path, C.byref(nw), spw.ctypes.data_as(_ip), C.byref(bm)))
+        self.block_mult = bm.value
         return nw.value, spw
 
     def poisson(self, b, u0=None, rtol=1e-10):
         bp, k1 = _vec_ptr(b)
         u = np.zeros(self.n_pot) if u0 is None else _host_f64(u0).copy()
         it = C.c_long()
-        self._check(self._L.mm_poisson_solve(self.h, bp, C.c_void_p(u.ctypes.data), rtol, C.byref(it)))
+        self.last_rc = self._check(self._L.mm_poisson_solve(self.h, bp, C.c_void_p(u.ctypes.data), rtol,
+                                                            C.byref(it)))
         return u, it.value
 
     # ----------------------------------------------------------------
@@ -523,7 +540,10 @@ class Context:
         self._check(self._L.mm_jacobi_diag(self.h, C.c_void_p(out.ctypes.data)))
         return out
 
-    def curve_learned(self, net, graph, mode, m, fields_T, opts=None, **kw):
+    def curve_learned(self, net, graph, mode, m, fields_T, opts=None, h_prev_T=None, **kw):
+        """h_prev_T: the field (Tesla) at which m is a minimizer, when the
+        call continues a curve; the first field then gets the learned
+        proposal too."""
         o = opts or default_opts(**kw)
         mp, keep = _vec_ptr(m)
         if isinstance(keep, np.ndarray):
@@ -535,8 +555,10 @@ class Context:
         Et = np.zeros(nf)
         st = (Stats * nf)()
         acc = np.zeros(nf, dtype=np.int32)
+        hp = None if h_prev_T is None else _host_f64(h_prev_T, (3,))
         rc = self._check(self._L.mm_demag_curve_learned(
-            self.h, net.h if net else None, graph.h if graph else None, int(mode), mp, F.ctypes.data_as(_dp), nf,
+            self.h, net.h if net else None, graph.h if graph else None, int(mode), mp,
+            None if hp is None else hp.ctypes.data_as(_dp), F.ctypes.data_as(_dp), nf,
             C.byref(o), mavg.ctypes.data_as(_dp), Et.ctypes.data_as(_dp), st, acc.ctypes.data_as(_ip)))
         return dict(m=keep, m_avg=mavg, E=Et, stats=[s.as_dict() for s in st], rc=rc, accepted=acc)
 
@@ -608,6 +630,10 @@ class Gnn:
         if rc < 0:
             raise MMError(rc, self._L.mm_gnn_last_error(self.h).decode())
         return rc
+
+    def set_precision(self, fp32):
+        """Dense layers in FP32 (debug mode) or BF16 on the matrix cores."""
+        self._chk(self._L.mm_gnn_set_precision(self.h, MM_GNN_FP32 if fp32 else MM_GNN_BF16))
 
     def set_params(self, theta):
         tp, keep = _vec_ptr(theta)

@@ -445,6 +445,23 @@ Csr smoother_pair(const HostLevel &H) {
     return S;
 }
 
+// rows of A in the order ord (row r of the result is row ord[r] of A)
+Csr permute_rows(const Csr &A, const std::vector<int> &ord) {
+    Csr P;
+    P.n = A.n;
+    P.ncols = A.ncols;
+    P.p.assign(A.n + 1, 0);
+    for (int r = 0; r < A.n; ++r) {
+        const int a = ord[r];
+        for (int64_t e = A.p[a]; e < A.p[a + 1]; ++e) {
+            P.j.push_back(A.j[e]);
+            P.v.push_back(A.v[e]);
+        }
+        P.p[r + 1] = (int64_t)P.j.size();
+    }
+    return P;
+}
+
 // [S | Q] as one CSR over the columns [0, ncols_b) + [yoff, ...)
 Csr side_by_side(const Csr &S, const Csr &Q, int qoff) {
     Csr U;
@@ -527,9 +544,12 @@ AmgState *amg_get(mm_ctx *c) {
     {
         std::vector<double> om(ni), wd(N[0], 0.0);
         for (int i = 0; i < ni; ++i) {
+            // level 0 lives on the device rows (the locality order of the
+            // potential rows); the hierarchy itself is in free-node numbering
             const HostLevel &H0 = S->H[i][0];
+            const std::vector<int> &ord = c->inst[i].pot_order;
             om[i] = H0.omega;
-            for (int r = 0; r < H0.A.n; ++r) wd[off[0][i] + r] = H0.omega / H0.d[r];
+            for (int r = 0; r < H0.A.n; ++r) wd[off[0][i] + r] = H0.omega / H0.d[ord[r]];
         }
         D.omega = upload_v(c, om);
         F.omega = upload_v(c, to32(om));
@@ -544,9 +564,11 @@ AmgState *amg_get(mm_ctx *c) {
     // level 0 transfer
     if (nlev > 1) {
         std::vector<GBlock> bl;
+        std::vector<Csr> Pd(ni);
         for (int i = 0; i < ni; ++i) {
             const int c0 = off[1][i];
-            bl.push_back(GBlock{off[0][i], &S->H[i][0].P, [c0](int j) { return c0 + j; }});
+            Pd[i] = permute_rows(S->H[i][0].P, c->inst[i].pot_order);
+            bl.push_back(GBlock{off[0][i], &Pd[i], [c0](int j) { return c0 + j; }});
         }
         const Csr P = concat(N[0], N[1], bl);
         const Csr R = transpose(P);
@@ -608,11 +630,15 @@ AmgState *amg_get(mm_ctx *c) {
             daoff.push_back((int64_t)inv.size());
             dboff.push_back(l == 0 ? 0 : off[l][i]);
             dwho.push_back(i);
+            // a single-level hierarchy works on the device rows of level 0
+            std::vector<int> ord(n);
+            for (int r = 0; r < n; ++r) ord[r] = l == 0 ? c->inst[i].pot_order[r] : r;
             for (int r = 0; r < n; ++r) {
                 dinst.push_back(k);
                 const size_t at = inv.size();
                 inv.resize(at + ld, 0.0);
-                std::copy(H.Ainv.begin() + (size_t)r * n, H.Ainv.begin() + (size_t)(r + 1) * n, inv.begin() + at);
+                const double *row = H.Ainv.data() + (size_t)ord[r] * n;
+                for (int q = 0; q < n; ++q) inv[at + q] = row[ord[q]];
             }
             rows += n;
         }
@@ -736,16 +762,16 @@ int mm_amg_apply(mm_ctx *c, const double *r, double *z, int precision) {
         const PcgLaunch a = pcg_args(c);
         // the fine level's b and y are not used by the cycle: input and output staging
         double *r64 = S->g64.lv[0].b, *z64 = S->g64.lv[0].y;
-        copy_in(c, r64, r, n);
+        pot_in(c, r64, r, z64);
         if (precision == MM_FP64) {
             launch_amg_apply64(a, S->g64, r64, c->stream);
-            copy_out(c, z, S->g64.u, n);
+            pot_out(c, z, S->g64.u, z64);
         } else {
             float *r32 = S->g32.lv[0].b;
             launch_to_f32(n, r64, r32, c->stream);
             launch_amg_apply32(a, S->g32, r32, c->stream);
             gnn_f32_to_f64(n, S->g32.u, z64, c->stream);
-            copy_out(c, z, z64, n);
+            pot_out(c, z, z64, r64);
         }
         sync(c);
         return MM_OK;

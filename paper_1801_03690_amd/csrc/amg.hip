@@ -143,8 +143,10 @@ __global__ __launch_bounds__(kAB) void k_amg_dense(int nrows, const int *__restr
 
 // one SELL row of K times x (and optionally times y entrywise: sum K_ac y_c
 // x_c) with G column/value loads and gathers in flight per lane; entries past
-// the slice's width stand in as the slice's first row with value 0
-template <class MT, class VT, bool TWO>
+// the slice's width stand in as the slice's first row with value 0. With NT
+// the matrix loads are non-temporal (a matrix larger than the Infinity Cache
+// then does not evict the vectors the gathers reuse).
+template <class MT, class VT, bool TWO, bool NT>
 __device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const VT *__restrict__ x, int xs,
                                          const VT *__restrict__ y) {
     constexpr int G = sizeof(VT) == 4 ? 8 : 4;
@@ -158,8 +160,8 @@ __device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const V
         for (int k = 0; k < G; ++k) {
             const bool in = k0 + k < wd;
             const int64_t e = base + 64 * (k0 + k) + ln;
-            cc[k] = in ? K.col[e] : s * 64;
-            vv[k] = in ? (VT)K.val[e] : (VT)0;
+            cc[k] = in ? (NT ? __builtin_nontemporal_load(K.col + e) : K.col[e]) : s * 64;
+            vv[k] = in ? (VT)(NT ? __builtin_nontemporal_load(K.val + e) : K.val[e]) : (VT)0;
         }
 #pragma unroll
         for (int k = 0; k < G; ++k) {
@@ -176,7 +178,7 @@ __device__ __forceinline__ VT row_gather(const SV<MT> &K, int s, int ln, const V
 // k_amg_iter (the CG start, or a plain vector): t = r - omega K D^-1 r with r
 // at r[row * rs] and the instance's omega. With q given (the CG start), also sets w = s = 0 and d =
 // D^-1 in the records q (the r fields are left alone: neighbours read them).
-template <class MT, class VT, class CT, int NW>
+template <class MT, class VT, class CT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const VT *__restrict__ r, int rs,
                                                       const VT *__restrict__ invD, const VT *__restrict__ om,
                                                       CT *__restrict__ t, PcgNode<VT> *__restrict__ q) {
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
     const VT omega = om[tl.inst];
     const int rend = M.rend[tl.inst], ln = lane_id();
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const VT acc = row_gather<MT, VT, true>(K, s, ln, r, rs, invD);
+        const VT acc = row_gather<MT, VT, true, NT>(K, s, ln, r, rs, invD);
         const int row = s * 64 + ln;
         if (row < rend) {
             t[row] = (CT)(r[(int64_t)row * rs] - omega * acc);
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_pre0(SV<MT> K, RowMap M, const 
 // CG's type RT; partial gamma = r.u of the stored values into slot gslot
 // (skipped when part is null); instances whose flag is up are skipped when
 // st is given
-template <class MT, class VT, class RT, int NW>
+template <class MT, class VT, class RT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const RT *__restrict__ r, int rs,
                                                        const VT *__restrict__ wd, const VT *__restrict__ z,
                                                        RT *__restrict__ u, double *__restrict__ part, int gslot,
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[1] = {0};
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const VT kz = row_gather<MT, VT, false>(K, s, ln, z, 1, (const VT *)nullptr);
+        const VT kz = row_gather<MT, VT, false, NT>(K, s, ln, z, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
             const RT ri = r[(int64_t)row * rs];
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
 // fine level: w = K u into the w field of the record (the other fields were
 // written by k_amg_iter, or by the start); partials (delta = w.u, r.r) into
 // slots wslot, wslot + 1
-template <class MT, class VT, int NW>
+template <class MT, class VT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
                                                    const VT *__restrict__ u, double *__restrict__ part, int wslot,
                                                    const PcgState *st) {
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
     const int rend = M.rend[tl.inst], ln = lane_id();
     double acc[2] = {0, 0};
     for (int s = tl.s0 + wave_id(); s < tl.s1; s += NW) {
-        const VT ku = row_gather<MT, VT, false>(K, s, ln, u, 1, (const VT *)nullptr);
+        const VT ku = row_gather<MT, VT, false, NT>(K, s, ln, u, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
             const VT ri = q[row].r;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
 
 // K D^-1 times the r, w and s fields of the neighbour records (one row of
 // the slice, this lane)
-template <class MT, class VT>
+template <class MT, class VT, bool NT>
 __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0, VT &pa,
                                         VT &pb, VT &pc) {
     constexpr int G = sizeof(VT) == 4 ? 8 : 4;
@@ -267,8 +269,8 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
         for (int k = 0; k < G; ++k) {
             const bool in = k0 + k < wd;
             const int64_t e = base + 64 * (k0 + k) + ln;
-            cc[k] = in ? K.col[e] : s * 64;
-            vv[k] = in ? (VT)K.val[e] : (VT)0;
+            cc[k] = in ? (NT ? __builtin_nontemporal_load(K.col + e) : K.col[e]) : s * 64;
+            vv[k] = in ? (VT)(NT ? __builtin_nontemporal_load(K.val + e) : K.val[e]) : (VT)0;
         }
         PcgNode<VT> nq[G];
 #pragma unroll
@@ -287,7 +289,7 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
 // partials P[par]; writes records q[par ^ 1] with w = 0, filled in by
 // k_amg_w) and t = r_new - omega K D^-1 r_new, where K D^-1 r_new = A -
 // alpha (B + beta C) with A, B, C the products of K D^-1 with the old r, w, s
-template <class MT, class VT, class XT, class CT, int NW>
+template <class MT, class VT, class XT, class CT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
                                                       const VT *__restrict__ uu, CT *__restrict__ tt,
                                                       const VT *__restrict__ om,
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
     const double tol2 = si->tol2, gprev = si->gamma[par ^ 1], aprev = si->alpha[par ^ 1];
     const int sf = tl.s0 + wave_id();
     VT pa = 0, pb = 0, pc = 0;
-    if (sf < tl.s1) row_abc(K, sf, ln, q0, pa, pb, pc);
+    if (sf < tl.s1) row_abc<MT, VT, NT>(K, sf, ln, q0, pa, pb, pc);
     block_reduce<3, NW>(g3, 0u, sh);
     const double gam = g3[0], del = g3[1], rr = g3[2];
     if (rr <= tol2) {
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
     }
     const VT a = (VT)alpha, bt = (VT)beta, omega = om[tl.inst];
     for (int s = sf; s < tl.s1; s += NW) {
-        if (s != sf) row_abc(K, s, ln, q0, pa, pb, pc);
+        if (s != sf) row_abc<MT, VT, NT>(K, s, ln, q0, pa, pb, pc);
         const int row = s * 64 + ln;
         if (row < rend) {
             const PcgNode<VT> me = q0[row];
@@ -467,41 +469,65 @@ const VT *post_wd(const AmgLaunch<VT> &g) {
 // one cycle on the fine level from the residual r (at r[row * rs]) into u;
 // with a CG, also the records' start fields (q) and the partials of the
 // start (gamma, then delta and r.r in P0)
-template <class VT, class RT>
-void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const RT *r, int rs,
-                PcgNode<RT> *q, bool cg, hipStream_t s) {
+// matrices whose stored entries (value + column index) exceed this stay out
+// of the Infinity Cache between passes and are loaded non-temporally
+constexpr int64_t kStreamMatrixBytes = int64_t(128) << 20;
+template <class VT>
+bool stream_matrix(const PcgLaunch &a) {
+    return a.K->padded * int64_t(sizeof(VT) + sizeof(int)) > kStreamMatrixBytes;
+}
+
+template <class VT, class RT, bool NT>
+void fine_cycle_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const RT *r, int rs,
+                   PcgNode<RT> *q, bool cg, hipStream_t s) {
     const RowMap &M = *a.M;
     const AmgLevel<VT> &f = g.lv[0];
-    // t (unused with a single level) and the records' start fields
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, RT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_pre0<VT, RT, VT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, r, rs, fa.invD, fa.omega, f.t, q))
     lower_cycle(g, r, rs, (const PcgState *)nullptr, s);
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<VT>(*a.K), M, r, rs, post_wd(g), (const VT *)f.z, fa.u,
                                              cg ? a.part : (double *)nullptr, kP0, (const PcgState *)nullptr))
     if (cg)
-        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
+        MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                                  view<VT>(*a.K), M, q, (const RT *)fa.u, a.part, kP0 + 1,
                                                  (const PcgState *)nullptr))
+}
+
+template <class VT, class RT>
+void fine_cycle(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const RT *r, int rs,
+                PcgNode<RT> *q, bool cg, hipStream_t s) {
+    // t (unused with a single level) and the records' start fields
+    if (stream_matrix<VT>(a))
+        fine_cycle_nt<VT, RT, true>(a, g, fa, r, rs, q, cg, s);
+    else
+        fine_cycle_nt<VT, RT, false>(a, g, fa, r, rs, q, cg, s);
+}
+
+template <class VT, class RT, class XT, bool NT>
+void amg_iter_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const PcgVecs<RT> &v, XT *x,
+                 int par, hipStream_t s) {
+    const RowMap &M = *a.M;
+    const AmgLevel<VT> &f = g.lv[0];
+    PcgNode<RT> *q1 = v.q[par ^ 1];
+    const int ws = par ? kP0 : kP1;  // this iteration's new partials
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0,
+                                             s, view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.omega, a.st, par,
+                                             (const double *)a.part))
+    lower_cycle(g, (const RT *)&q1->r, 4, (const PcgState *)a.st, s);
+    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, post_wd(g), (const VT *)f.z,
+                                             fa.u, a.part, ws, (const PcgState *)a.st);
+                    hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
+                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1,
+                                       (const PcgState *)a.st))
 }
 
 template <class VT, class RT, class XT>
 void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT> &fa, const PcgVecs<RT> &v, XT *x,
               int par, hipStream_t s) {
-    const RowMap &M = *a.M;
-    const AmgLevel<VT> &f = g.lv[0];
-    PcgNode<RT> *q1 = v.q[par ^ 1];
-    const int ws = par ? kP0 : kP1;  // this iteration's new partials
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.omega, a.st, par,
-                                             (const double *)a.part))
-    lower_cycle(g, (const RT *)&q1->r, 4, (const PcgState *)a.st, s);
-    MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, post_wd(g), (const VT *)f.z,
-                                             fa.u, a.part, ws, (const PcgState *)a.st);
-                    hipLaunchKernelGGL((k_amg_w<VT, RT, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1,
-                                       (const PcgState *)a.st))
+    if (stream_matrix<VT>(a)) amg_iter_nt<VT, RT, XT, true>(a, g, fa, v, x, par, s);
+    else amg_iter_nt<VT, RT, XT, false>(a, g, fa, v, x, par, s);
 }
 
 FineArgs<double, double> fine64(const PcgLaunch &a, const AmgLaunch<double> &g) {

@@ -46,15 +46,19 @@ enum MagSlot {
     MS_TOTAL = MS_MISC + 5
 };
 
+// field kernels with per-launch timers
+enum KernelTimer { KT_EVAL = 0, KT_BMUL = 1, KT_PREC_APPLY = 2, KT_N = 3 };
+
 // per-instance metadata kept on the host
 struct InstInfo {
     long n_nodes = 0, n_tets = 0;
     int n_mag = 0, n_pot = 0, n_brow = 0;
     int mag_off = 0, pot_off = 0, brow_off = 0;  // first global (padded) row
     long user_off = 0;                           // first magnet node in caller arrays
-    long nnz_C = 0, nnz_K = 0, nnz_B = 0;
+    long nnz_C = 0, nnz_K = 0, nnz_B = 0, nnz_S = 0;
     double Ms_ref = 0;
     std::vector<int> node_of_mag;
+    std::vector<int> pot_order;  // device row r (local) holds free node pot_order[r]
 };
 
 // device tables of one RowMap
@@ -110,9 +114,13 @@ struct mm_ctx {
     // block shape of the scalar-potential kernels: waves per block (launch
     // wide) and SELL slices per wave of each instance
     int pnw = kPoissonWaves;
+    int pbm = 1;  // multiplier of the default cap on blocks per instance (make_map)
     std::vector<int> pspw, poff, pn;
     bool tuned = false;
     double *L = nullptr, *invDex = nullptr, *invDK = nullptr;
+    // potential rows: free-node index of each device row and device row of
+    // each free node (global, instance offsets included)
+    int *pord = nullptr, *ppos = nullptr;
     float *invDK32 = nullptr;
 
     StateV st[3];  // current state, trial T, trial C
@@ -153,6 +161,13 @@ struct mm_ctx {
     std::vector<hipEvent_t> prof_ev;
     size_t prof_used = 0;
     double prof_seconds = 0, prof_units = 0, prof_bytes = 0;
+    // per-launch timing of the field kernels (mm_profile_kernels): event pairs
+    // around k_eval_epilogue, k_bmul and the first k_prec_apply of each inner
+    // solve, with the algorithmic bytes of each timed launch
+    bool kt_on = false;
+    std::vector<hipEvent_t> kt_ev[KT_N];
+    std::vector<double> kt_pend[KT_N];   // bytes of the pairs not yet harvested
+    double kt_sec[KT_N] = {0, 0, 0}, kt_calls[KT_N] = {0, 0, 0}, kt_bytes[KT_N] = {0, 0, 0};
 
     // control block accessors
     int *act() const { return hci; }
@@ -186,6 +201,10 @@ void dfree(mm_ctx *c, void *p);
 bool is_device_ptr(const void *p);
 void copy_in(mm_ctx *c, double *dst, const double *src, size_t n);
 void copy_out(mm_ctx *c, double *dst, const double *src, size_t n);
+// instance 0's potential vectors across the ABI (free-node numbering) and the
+// device (locality order); tmp: a scratch vector of n_pot doubles
+void pot_in(mm_ctx *c, double *dev, const double *abi, double *tmp);
+void pot_out(mm_ctx *c, double *abi, const double *dev, double *tmp);
 void sync(mm_ctx *c);
 void upload_ctl(mm_ctx *c);
 void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std::vector<int> &on);
@@ -212,6 +231,22 @@ void require_single(mm_ctx *c);
 // state, writes the network's tangent proposal into c->d and its Jacobi
 // factors into c->dscale (both on the magnet rows).
 void gnn_propose(mm_ctx *c, mm_gnn *g, mm_graph *gr, const double h_prev[3], const double h_next[3]);
+
+// scratch of the inner solve of Alg. 1 (the residual, direction and product
+// vectors, 3 x rows_m doubles each; the 7 partial-sum slots of the magnet-row
+// map, 7 x nblk doubles; the exit flags, 4 ints per instance); null members
+// mean the context's own buffers
+struct PrecScratch {
+    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+    int *flags = nullptr;
+};
+// bytes a PrecScratch for this context needs when carved out of one block
+// (each piece aligned to 256 bytes), and the carving itself
+size_t prec_scratch_bytes(const mm_ctx *c);
+PrecScratch prec_scratch_at(const mm_ctx *c, void *base);
+// mm_precondition's body; ext = nullptr uses the context's buffers
+int precondition_call(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax,
+                      const double *dscale, double *y, int *inner_iters, const PrecScratch *ext);
 
 template <class F>
 int guarded(mm_ctx *c, F &&f) {

@@ -126,6 +126,9 @@ __device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const 
                                            double &o1, double &o2) {
     int64_t base = A.sptr[s];
     int w = (int)((A.sptr[s + 1] - base) >> 6);
+    // difference form (see row_scalar3): the diagonal block holds the row sum
+    const int64_t row = (int64_t)s * 64 + ln;
+    const double xi0 = x[3 * row], xi1 = x[3 * row + 1], xi2 = x[3 * row + 2];
     o0 = o1 = o2 = 0.0;
     for (int k = 0; k < w; ++k) {
         int64_t e = base + 64 * k;
@@ -133,7 +136,9 @@ __device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const 
         const V *v = A.val + e * 6 + ln;
         double vxx = (double)v[0], vyy = (double)v[64], vzz = (double)v[128];
         double vxy = (double)v[192], vxz = (double)v[256], vyz = (double)v[320];
-        double x0 = x[3 * (int64_t)c], x1 = x[3 * (int64_t)c + 1], x2 = x[3 * (int64_t)c + 2];
+        const bool dg = c == row;
+        double x0 = dg ? xi0 : x[3 * (int64_t)c] - xi0, x1 = dg ? xi1 : x[3 * (int64_t)c + 1] - xi1,
+               x2 = dg ? xi2 : x[3 * (int64_t)c + 2] - xi2;
         o0 += vxx * x0 + vxy * x1 + vxz * x2;
         o1 += vxy * x0 + vyy * x1 + vyz * x2;
         o2 += vxz * x0 + vyz * x1 + vzz * x2;
@@ -153,20 +158,30 @@ __device__ __forceinline__ double row_scalar(const SV<V> &A, int s, int ln, cons
     return acc;
 }
 
-// scalar row applied to each component of node-major 3-vectors
+// scalar row applied to each component of node-major 3-vectors, for a
+// matrix stored in difference form (the local operators C and S): the
+// diagonal entry holds the row sum R_i and every other entry A_ij acts on
+// x_j - x_i, so (A x)_i = R_i x_i + sum_{j != i} A_ij (x_j - x_i), which is A x
+// in exact arithmetic. The exchange rows sum to zero, so a uniform x gives
+// exactly no exchange field whatever the precision of the stored values; in
+// the plain form FP32 rounding of the entries leaves row sums of about 6e-8
+// of the diagonal, a spurious radial field and an energy offset.
 template <class V>
 __device__ __forceinline__ void row_scalar3(const SV<V> &A, int s, int ln, const double *__restrict__ x, double &o0,
                                             double &o1, double &o2) {
     int64_t base = A.sptr[s];
     int w = (int)((A.sptr[s + 1] - base) >> 6);
+    const int64_t row = (int64_t)s * 64 + ln;
+    const double xi0 = x[3 * row], xi1 = x[3 * row + 1], xi2 = x[3 * row + 2];
     o0 = o1 = o2 = 0.0;
     for (int k = 0; k < w; ++k) {
         int64_t e = base + 64 * k + ln;
         double a = (double)A.val[e];
         int64_t c = A.col[e];
-        o0 += a * x[3 * c];
-        o1 += a * x[3 * c + 1];
-        o2 += a * x[3 * c + 2];
+        const bool dg = c == row;
+        o0 += a * (dg ? xi0 : x[3 * c] - xi0);
+        o1 += a * (dg ? xi1 : x[3 * c + 1] - xi1);
+        o2 += a * (dg ? xi2 : x[3 * c + 2] - xi2);
     }
 }
 

@@ -56,7 +56,18 @@ struct Assembly {
     HostCsr K;                     // Poisson matrix on free nodes
     HostCsr B;                     // rows: magnet nodes that are free (row_out = free index), cols magnet, vw 3
     HostCsr Bt;                    // rows: magnet nodes, cols free nodes, vw 3
+    // device order of the free nodes: device row r holds free node pot_order[r]
+    // (locality_order); every matrix above keeps the free-node numbering
+    std::vector<int> pot_order;
 };
+
+// Order of the free (potential) nodes on the device: the bounding box is cut
+// into cubic tiles of about 4096 nodes, the tiles are taken in x-fastest order
+// and the nodes keep their numbering order inside a tile. A matrix-vector
+// product then gathers its neighbours from rows close by in every direction,
+// not from whole grid planes away, so they stay in the L2 cache. Identity
+// below 8,192 nodes (one tile). order[r] = the free node on device row r.
+std::vector<int> locality_order(const double *xyz, const std::vector<int> &node_of_free);
 
 // Builds every operator from the mesh and per-tet SI materials. Returns an
 // error message (empty on success).
@@ -139,6 +150,9 @@ struct PrecLaunch {
 };
 void launch_prec_init(const PrecLaunch &a, hipStream_t s);
 void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s);
+// the two halves of launch_prec_iter: q = P p, then the update kernels
+void launch_prec_apply(const PrecLaunch &a, int j, hipStream_t s);
+void launch_prec_tail(const PrecLaunch &a, int j, bool last, hipStream_t s);
 
 // --- direction (kernels.hip) ---
 // beta_kind: 0 beta*ZA, 1 beta*FR, 2 beta*PRP, 3 beta*HS; gy: 2 x ninst doubles
@@ -153,6 +167,7 @@ void launch_mavg(const RowMap &M, const double *m, const double *L, double *part
 void launch_lambda(const RowMap &M, const double *m, const double *G, double *lam, hipStream_t s);
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
+void launch_gather(int64_t n, const int *idx, const double *in, double *out, hipStream_t s);
 
 // --- scalar-potential CG (poisson.hip) ---
 // per-node record of the single-reduction CG: residual r, w = K D^-1 r,
@@ -261,11 +276,13 @@ void launch_amg_apply64(const PcgLaunch &a, const AmgLaunch<double> &g, const do
 void launch_amg_apply32(const PcgLaunch &a, const AmgLaunch<float> &g, const float *r, hipStream_t s);
 
 // --- learned component (gnn.hip); widths fixed: 32 features, 64 channels ---
+// f32: FP32 operands on the vector units (debug mode) instead of BF16 MFMA
 void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float *W, int ldw, bool transW,
-            const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, hipStream_t s);
+            const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, bool f32,
+            hipStream_t s);
 int gnn_tn_blocks(int M);
 void gnn_mm_tn(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
-               bool accumulate, hipStream_t s);
+               bool accumulate, bool f32, hipStream_t s);
 void gnn_tn32(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
               hipStream_t s);
 void gnn_agg(int n, const int *ptr, const int *idx, const float *invdeg, const float *H, int ldh, float *out, int ldo,

@@ -602,6 +602,13 @@ __global__ void k_fill(int64_t n, double *__restrict__ x, double v) {
     if (i < n) x[i] = v;
 }
 
+// out[i] = in[idx[i]] (idx a permutation of [0, n))
+__global__ void k_gather(int64_t n, const int *__restrict__ idx, const double *__restrict__ in,
+                         double *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -661,6 +668,11 @@ void launch_prec_init(const PrecLaunch &a, hipStream_t s) {
                        a.p, a.part, a.flags);
 }
 void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s) {
+    launch_prec_apply(a, j, s);
+    launch_prec_tail(a, j, last, s);
+}
+
+void launch_prec_apply(const PrecLaunch &a, int j, hipStream_t s) {
     const RowMap &M = *a.M;
     const int ph = 3 * j;
 #define MMNCG_PREC_APPLY(V, F)                                                                                     \
@@ -676,6 +688,11 @@ void launch_prec_iter(const PrecLaunch &a, int j, bool last, hipStream_t s) {
         else MMNCG_PREC_APPLY(double, 0);
     }
 #undef MMNCG_PREC_APPLY
+}
+
+void launch_prec_tail(const PrecLaunch &a, int j, bool last, hipStream_t s) {
+    const RowMap &M = *a.M;
+    const int ph = 3 * j;
     hipLaunchKernelGGL(k_prec_update, dim3(M.nblk), dim3(kBlock), 0, s, M, a.act, j, a.g, a.invDex, a.dscale, a.y,
                        a.r, a.p, a.q, a.part, a.flags, ph + 2);
     if (!last)
@@ -711,6 +728,11 @@ void launch_fill(int64_t n, double *x, double v, hipStream_t s) {
     if (n <= 0) return;
     int64_t g = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(kBlock), 0, s, n, x, v);
+}
+void launch_gather(int64_t n, const int *idx, const double *in, double *out, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t g = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)g), dim3(kBlock), 0, s, n, idx, in, out);
 }
 
 }  // namespace mmncg

@@ -111,12 +111,26 @@ void copy_in(mm_ctx *c, double *dst, const double *src, size_t n) {
     HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
                           is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
 }
+void pot_in(mm_ctx *c, double *dev, const double *abi, double *tmp) {
+    const int n = c->inst[0].n_pot;
+    copy_in(c, tmp, abi, n);
+    launch_gather(n, c->pord, tmp, dev, c->stream);
+}
+void pot_out(mm_ctx *c, double *abi, const double *dev, double *tmp) {
+    const int n = c->inst[0].n_pot;
+    launch_gather(n, c->ppos, dev, tmp, c->stream);
+    copy_out(c, abi, tmp, n);
+}
 void copy_out(mm_ctx *c, double *dst, const double *src, size_t n) {
     if (n == 0) return;
     HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
                           is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
 }
-void sync(mm_ctx *c) { HIPCHK(hipStreamSynchronize(c->stream)); }
+void kt_harvest(mm_ctx *c);
+void sync(mm_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->kt_on) kt_harvest(c);
+}
 
 // The host writes the control block only after a synchronization that
 // follows the previous upload, so an upload never races with the host.
@@ -157,6 +171,38 @@ void prof_harvest(mm_ctx *c) {
         c->prof_seconds += ms * 1e-3;
     }
     c->prof_used = 0;
+}
+
+// field-kernel timers: an event before and after one launch (pair p of
+// kernel k uses events 2p and 2p + 1), harvested after the next
+// synchronization of the stream
+void kt_begin(mm_ctx *c, int k) {
+    if (!c->kt_on) return;
+    std::vector<hipEvent_t> &ev = c->kt_ev[k];
+    const size_t at = 2 * c->kt_pend[k].size();
+    while (ev.size() < at + 2) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(ev[at], c->stream));
+}
+void kt_end(mm_ctx *c, int k, double bytes) {
+    if (!c->kt_on) return;
+    HIPCHK(hipEventRecord(c->kt_ev[k][2 * c->kt_pend[k].size() + 1], c->stream));
+    c->kt_pend[k].push_back(bytes);
+}
+void kt_harvest(mm_ctx *c) {
+    for (int k = 0; k < KT_N; ++k) {
+        for (size_t p = 0; p < c->kt_pend[k].size(); ++p) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, c->kt_ev[k][2 * p], c->kt_ev[k][2 * p + 1]));
+            c->kt_sec[k] += ms * 1e-3;
+            c->kt_calls[k] += 1;
+            c->kt_bytes[k] += c->kt_pend[k][p];
+        }
+        c->kt_pend[k].clear();
+    }
 }
 
 double now_s() {
@@ -264,10 +310,13 @@ void upload_vec(mm_ctx *c, double *dst, const std::vector<double> &v) {
 // [off[i], off[i] + n[i]) (off a multiple of 64); its ns = ceil(n/64) slices
 // are split evenly over min(cap_i, ceil(ns / slices_per_block)) blocks, cap_i
 // = 256, or one block per 8192 rows up to kMaxBlocksPerInst for very large
-// instances. The table is padded with empty blocks to a multiple of 8 (XCD
-// renumbering).
+// instances, times cap_mult (the tuner's choice for the scalar-potential
+// rows). With `fill`, cap_i = kMaxBlocksPerInst: the magnet-row kernels
+// (4 waves per block, a few registers) need that many waves in flight to keep
+// HBM busy on large instances, and their partials are few. The table is padded
+// with empty blocks to a multiple of 8 (XCD renumbering).
 void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vector<int> &n,
-              const std::vector<int> &slices_per_block) {
+              const std::vector<int> &slices_per_block, bool fill = false, int cap_mult = 1) {
     const int ni = (int)off.size();
     std::vector<int> tab;
     std::vector<int> ipb(ni + 1, 0), rend(ni, 0);
@@ -281,7 +330,8 @@ void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vec
         // at most 256 blocks per instance, more only for very large instances
         // (one per 8192 rows, up to kMaxBlocksPerInst): every block re-reduces
         // the instance's partials, which costs more than it gains below that
-        const int cap = std::min(kMaxBlocksPerInst, std::max(256, (n[i] + 8191) / 8192));
+        const int cap = fill ? kMaxBlocksPerInst
+                             : std::min(kMaxBlocksPerInst, cap_mult * std::max(256, (n[i] + 8191) / 8192));
         const int nb = std::min(cap, (ns + spb - 1) / spb);
         for (int k = 0; k < nb; ++k) {
             tab.push_back(i);
@@ -314,6 +364,44 @@ void make_map(mm_ctx *c, DevMap &dm, const std::vector<int> &off, const std::vec
 
 int pad64(int n) { return (n + kSlice - 1) / kSlice * kSlice; }
 
+// The local operators C and S in difference form (the device applies them as
+// R_i x_i + sum_{j != i} A_ij (x_j - x_i)): the diagonal entry of every row
+// takes the row sum R_i (per block component for C). A row without a stored
+// diagonal is all zeros.
+void to_difference_form(HostCsr &A) {
+    const int vw = A.vw;
+    for (int r = 0; r < A.nrows; ++r) {
+        double sum[6] = {0, 0, 0, 0, 0, 0};
+        int64_t dg = -1;
+        for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
+            for (int q = 0; q < vw; ++q) sum[q] += A.val[e * vw + q];
+            if (A.col[e] == r) dg = e;
+        }
+        if (dg >= 0)
+            for (int q = 0; q < vw; ++q) A.val[dg * vw + q] = sum[q];
+    }
+}
+
+// A symmetric sparse matrix on renumbered rows: row r of the result is row
+// ord[r] of A, column j becomes pos[j] (pos the inverse of ord)
+HostCsr permute_sym(const HostCsr &A, const std::vector<int> &ord, const std::vector<int> &pos) {
+    HostCsr P;
+    P.nrows = A.nrows;
+    P.vw = A.vw;
+    P.ptr.assign(A.nrows + 1, 0);
+    P.col.reserve(A.col.size());
+    P.val.reserve(A.val.size());
+    for (int r = 0; r < A.nrows; ++r) {
+        const int a = ord[r];
+        for (int64_t e = A.ptr[a]; e < A.ptr[a + 1]; ++e) {
+            P.col.push_back(pos[A.col[e]]);
+            for (int q = 0; q < A.vw; ++q) P.val.push_back(A.val[e * A.vw + q]);
+        }
+        P.ptr[r + 1] = (int64_t)P.col.size();
+    }
+    return P;
+}
+
 // Builds every device structure of a batch from the per-instance assemblies.
 void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> &nn, const std::vector<long> &nt) {
     free_all(c);
@@ -337,6 +425,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
         I.nnz_C = as[i].C.ptr.empty() ? 0 : as[i].C.ptr[as[i].C.nrows];
         I.nnz_K = as[i].K.ptr.empty() ? 0 : as[i].K.ptr[as[i].K.nrows];
         I.nnz_B = as[i].B.ptr.empty() ? 0 : as[i].B.ptr[as[i].B.nrows];
+        I.nnz_S = as[i].S.ptr.empty() ? 0 : as[i].S.ptr[as[i].S.nrows];
         I.Ms_ref = as[i].Ms_ref;
         I.node_of_mag = as[i].node_of_mag;
         nm[i] = I.n_mag;
@@ -353,11 +442,29 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     c->tot_mag = uo;
     {
         HostCsr C, S, K, B, Bt;
+        std::vector<int> pord(std::max(rp, 1)), ppos(std::max(rp, 1));
+        for (int r = 0; r < (int)pord.size(); ++r) pord[r] = ppos[r] = r;  // padding rows map to themselves
         for (int i = 0; i < ni; ++i) {
+            // the potential rows in locality order: K's rows and columns, B's
+            // output rows and B^T's columns; the multigrid hierarchy is built
+            // on the free-node numbering and permuted when it is uploaded
+            const std::vector<int> &ord = as[i].pot_order;
+            std::vector<int> pos(np[i]);
+            for (int r = 0; r < np[i]; ++r) {
+                pos[ord[r]] = r;
+                pord[poff[i] + r] = poff[i] + ord[r];
+                ppos[poff[i] + ord[r]] = poff[i] + r;
+            }
+            c->inst[i].pot_order = ord;
+            c->hostK.push_back(as[i].K);  // kept for the multigrid hierarchies
+            as[i].K = permute_sym(as[i].K, ord, pos);
+            for (int &o : as[i].B.row_out) o = pos[o];
+            for (int &j : as[i].Bt.col) j = pos[j];
+            to_difference_form(as[i].C);
+            to_difference_form(as[i].S);
             append_csr(C, as[i].C, moff[i], moff[i], 0);
             append_csr(S, as[i].S, moff[i], moff[i], 0);
             append_csr(K, as[i].K, poff[i], poff[i], 0);
-            c->hostK.push_back(as[i].K);  // kept for the multigrid hierarchies
             append_csr(B, as[i].B, boff[i], moff[i], poff[i]);
             append_csr(Bt, as[i].Bt, moff[i], poff[i], 0);
             as[i].C = HostCsr();
@@ -381,9 +488,14 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
         upload_sell(c, K, c->K);
         upload_sell(c, B, c->B);
         upload_sell(c, Bt, c->Bt);
+        c->pord = dalloc_n<int>(c, pord.size());
+        c->ppos = dalloc_n<int>(c, ppos.size());
+        HIPCHK(hipMemcpyAsync(c->pord, pord.data(), pord.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->ppos, ppos.data(), ppos.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        sync(c);
     }
-    make_map(c, c->Mm, moff, nm, std::vector<int>(ni, kBlock / kSlice));
-    make_map(c, c->Mb, boff, nb, std::vector<int>(ni, kBlock / kSlice));
+    make_map(c, c->Mm, moff, nm, std::vector<int>(ni, kBlock / kSlice), true);
+    make_map(c, c->Mb, boff, nb, std::vector<int>(ni, kBlock / kSlice), true);
     c->pnw = kPoissonWaves;
     c->pspw.assign(ni, 1);
     c->poff = poff;
@@ -402,7 +514,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
                 L[moff[i] + a] = as[i].L[a];
                 iD[moff[i] + a] = 1.0 / as[i].Dex[a];
             }
-            for (int r = 0; r < np[i]; ++r) iK[poff[i] + r] = 1.0 / as[i].DK[r];
+            for (int r = 0; r < np[i]; ++r) iK[poff[i] + r] = 1.0 / as[i].DK[c->inst[i].pot_order[r]];
         }
         upload_vec(c, c->L, L);
         upload_vec(c, c->invDex, iD);
@@ -701,7 +813,7 @@ void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std:
 // ---------------------------------------------------------------------------
 // Rebuilds the potential-row map for nw waves per block and spw[i] slices per
 // wave of instance i. Captured graphs hold the old map: they are dropped.
-void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
+void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw, int bm = 1) {
     sync(c);
     for (hipGraphExec_t *g : {&c->graph64, &c->graph32, &c->agraph64, &c->mgraph}) {
         if (*g) (void)hipGraphExecDestroy(*g);
@@ -713,7 +825,7 @@ void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
     std::vector<int> spb(c->ninst);
     for (int i = 0; i < c->ninst; ++i) spb[i] = nw * spw[i];
     const int old = c->Mp.map.nblk;
-    make_map(c, c->Mp, c->poff, c->pn, spb);
+    make_map(c, c->Mp, c->poff, c->pn, spb, false, bm);
     if (c->Mp.map.nblk > old) {
         dfree(c, c->ppart);
         c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
@@ -722,6 +834,7 @@ void set_poisson_shape(mm_ctx *c, int nw, const std::vector<int> &spw) {
     }
     c->pnw = nw;
     c->pspw = spw;
+    c->pbm = bm;
 }
 
 // size bucket of an instance for the tuner: floor(log2(n_pot / 4096)), 0..7
@@ -779,7 +892,7 @@ double time_pcg(mm_ctx *c, const std::vector<int> &on, bool fp32) {
 // time per CG iteration of the whole batch.
 struct TuneEntry {
     std::string device, batch, spw;
-    int fp32, nw;
+    int fp32, nw, bm;
     double us;
 };
 
@@ -806,8 +919,8 @@ std::vector<TuneEntry> tune_read(const char *path) {
         TuneEntry e;
         if (std::sscanf(line,
                         " {\"device\": \"%511[^\"]\", \"fp32\": %d, \"batch\": \"%511[^\"]\", \"nw\": %d, "
-                        "\"spw\": \"%511[^\"]\", \"us\": %lf}",
-                        dev, &e.fp32, batch, &e.nw, spw, &e.us) == 6) {
+                        "\"bm\": %d, \"spw\": \"%511[^\"]\", \"us\": %lf}",
+                        dev, &e.fp32, batch, &e.nw, &e.bm, spw, &e.us) == 7) {
             e.device = dev;
             e.batch = batch;
             e.spw = spw;
@@ -822,12 +935,12 @@ void tune_write(const char *path, const std::vector<TuneEntry> &v) {
     std::string tmp = std::string(path) + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) throw ApiError{MM_EINVAL, std::string("cannot write tuning cache ") + path};
-    std::fprintf(f, "{\"mmncg_tune\": 2, \"entries\": [\n");
+    std::fprintf(f, "{\"mmncg_tune\": 3, \"entries\": [\n");
     for (size_t k = 0; k < v.size(); ++k)
         std::fprintf(f,
-                     "  {\"device\": \"%s\", \"fp32\": %d, \"batch\": \"%s\", \"nw\": %d, \"spw\": \"%s\", "
-                     "\"us\": %.4f}%s\n",
-                     v[k].device.c_str(), v[k].fp32, v[k].batch.c_str(), v[k].nw, v[k].spw.c_str(), v[k].us,
+                     "  {\"device\": \"%s\", \"fp32\": %d, \"batch\": \"%s\", \"nw\": %d, \"bm\": %d, "
+                     "\"spw\": \"%s\", \"us\": %.4f}%s\n",
+                     v[k].device.c_str(), v[k].fp32, v[k].batch.c_str(), v[k].nw, v[k].bm, v[k].spw.c_str(), v[k].us,
                      k + 1 < v.size() ? "," : "");
     std::fprintf(f, "]}\n");
     std::fclose(f);
@@ -836,6 +949,7 @@ void tune_write(const char *path, const std::vector<TuneEntry> &v) {
 
 constexpr int kTuneNw[3] = {4, 8, 16};
 constexpr int kTuneSpw[3] = {1, 2, 4};
+constexpr int kTuneBm[3] = {1, 2, 4};  // multipliers of the blocks-per-instance cap
 
 // Picks the block shape by timing CG iterations of the whole batch (every
 // instance active, synthetic right-hand side): for every waves-per-block
@@ -865,11 +979,11 @@ void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
         }
     const std::string dev = device_key(c);
     std::vector<TuneEntry> cache = use_cache ? tune_read(path) : std::vector<TuneEntry>();
-    auto apply = [&](int nw, const std::vector<int> &bspw) {
+    auto apply = [&](int nw, const std::vector<int> &bspw, int bm) {
         std::vector<int> spw(ni, 1);
         for (size_t k = 0; k < present.size(); ++k)
             for (int i : members[present[k]]) spw[i] = bspw[k];
-        set_poisson_shape(c, nw, spw);
+        set_poisson_shape(c, nw, spw, bm);
     };
     for (const TuneEntry &e : cache) {
         if (e.device != dev || e.fp32 != (fp32 ? 1 : 0) || e.batch != sig) continue;
@@ -881,10 +995,11 @@ void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
             if (nx == std::string::npos) break;
             pos = nx + 1;
         }
-        bool ok = bspw.size() == present.size() && (e.nw == 4 || e.nw == 8 || e.nw == 16);
+        bool ok = bspw.size() == present.size() && (e.nw == 4 || e.nw == 8 || e.nw == 16) &&
+                  (e.bm == 1 || e.bm == 2 || e.bm == 4);
         for (int v : bspw) ok = ok && (v == 1 || v == 2 || v == 4);
         if (!ok) continue;
-        apply(e.nw, bspw);
+        apply(e.nw, bspw, e.bm);
         c->tuned = true;
         return;
     }
@@ -892,40 +1007,42 @@ void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
     const size_t RP = std::max(c->rows_p, 1);
     HIPCHK(hipMemcpyAsync(c->usave, c->u, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     double best_t = 1e300;
-    int best_nw = kPoissonWaves;
+    int best_nw = kPoissonWaves, best_bm = 1;
     std::vector<int> best_b(present.size(), 1);
-    for (int nw : kTuneNw) {
-        std::vector<int> bspw(present.size(), 1);
-        double tcur = 1e300;
-        for (int cand : kTuneSpw) {
-            std::vector<int> trial(present.size(), cand);
-            apply(nw, trial);
-            const double t = time_pcg(c, all, fp32);
-            if (t < tcur) {
-                tcur = t;
-                bspw = trial;
+    for (int bm : kTuneBm)
+        for (int nw : kTuneNw) {
+            std::vector<int> bspw(present.size(), 1);
+            double tcur = 1e300;
+            for (int cand : kTuneSpw) {
+                std::vector<int> trial(present.size(), cand);
+                apply(nw, trial, bm);
+                const double t = time_pcg(c, all, fp32);
+                if (t < tcur) {
+                    tcur = t;
+                    bspw = trial;
+                }
+            }
+            if (present.size() > 1)
+                for (size_t k = 0; k < present.size(); ++k)
+                    for (int cand : kTuneSpw) {
+                        if (cand == bspw[k]) continue;
+                        std::vector<int> trial = bspw;
+                        trial[k] = cand;
+                        apply(nw, trial, bm);
+                        const double t = time_pcg(c, all, fp32);
+                        if (t < tcur) {
+                            tcur = t;
+                            bspw = trial;
+                        }
+                    }
+            if (tcur < best_t) {
+                best_t = tcur;
+                best_nw = nw;
+                best_b = bspw;
+                best_bm = bm;
             }
         }
-        if (present.size() > 1)
-            for (size_t k = 0; k < present.size(); ++k)
-                for (int cand : kTuneSpw) {
-                    if (cand == bspw[k]) continue;
-                    std::vector<int> trial = bspw;
-                    trial[k] = cand;
-                    apply(nw, trial);
-                    const double t = time_pcg(c, all, fp32);
-                    if (t < tcur) {
-                        tcur = t;
-                        bspw = trial;
-                    }
-                }
-        if (tcur < best_t) {
-            best_t = tcur;
-            best_nw = nw;
-            best_b = bspw;
-        }
-    }
-    apply(best_nw, best_b);
+    apply(best_nw, best_b, best_bm);
     launch_fill((int64_t)RP, c->b, 0.0, c->stream);
     HIPCHK(hipMemcpyAsync(c->u, c->usave, RP * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     upload_ctl(c);
@@ -933,7 +1050,7 @@ void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
     if (use_cache) {
         std::string spw;
         for (size_t k = 0; k < best_b.size(); ++k) spw += (k ? "," : "") + std::to_string(best_b[k]);
-        cache.push_back(TuneEntry{dev, sig, spw, fp32 ? 1 : 0, best_nw, best_t * 1e6});
+        cache.push_back(TuneEntry{dev, sig, spw, fp32 ? 1 : 0, best_nw, best_bm, best_t * 1e6});
         tune_write(path, cache);
     }
     c->tuned = true;
@@ -946,6 +1063,42 @@ void autotune(mm_ctx *c, bool use_cache, const char *path, bool fp32) {
 // ---------------------------------------------------------------------------
 int cmode_of(int terms) { return ((terms & MM_T_EXCH) ? 1 : 0) | ((terms & MM_T_ANIS) ? 2 : 0); }
 
+// Algorithmic bytes of the timed field kernels over the instances in `on`:
+// each stored operator entry (values and column index) once, each magnet-node
+// vector the kernel reads or writes once. v is the operator value size.
+double eval_bytes(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool demag, double v) {
+    const int cm = cmode_of(o.terms);
+    double b = 0;
+    for (int i : on) {
+        const InstInfo &I = c->inst[i];
+        if (cm & 2) b += I.nnz_C * (6 * v + 4);
+        if (cm == 1 || cm == 2) b += I.nnz_S * (v + 4);
+        if (demag) b += I.nnz_B * (3 * v + 4);  // B^T holds B's entries
+        // m (24), L (8) read; G (24), g (24), lambda (8) written; a line-search
+        // trial also reads x0 (24), d (24), g0 (24), lambda0 (8)
+        b += I.n_mag * (88.0 + (c->role()[i] != 0 ? 80.0 : 0.0));
+    }
+    return b;
+}
+double bmul_bytes(mm_ctx *c, const std::vector<int> &on, double v) {
+    double b = 0;
+    for (int i : on) {
+        const InstInfo &I = c->inst[i];
+        b += I.nnz_B * (3 * v + 4) + 24.0 * I.n_mag + 8.0 * I.n_brow;  // B, m read, b written
+    }
+    return b;
+}
+double prec_apply_bytes(mm_ctx *c, int form, double v) {
+    double b = 0;
+    for (int i = 0; i < c->ninst; ++i) {
+        if (!c->pact()[i]) continue;
+        const InstInfo &I = c->inst[i];
+        // C, then m (24), lambda (8), p (24) read and q (24) written (+ g with all four terms)
+        b += I.nnz_C * (6 * v + 4) + I.n_mag * (80.0 + (form == MM_PFORM_FULL ? 24.0 : 0.0));
+    }
+    return b;
+}
+
 void eval_round(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool any_trial) {
     hipStream_t s = c->stream;
     const bool fp32 = o.precision == MM_FP32_BULK;
@@ -955,8 +1108,11 @@ void eval_round(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool an
     const double *alpha = c->d_(c->alpha());
     if (any_trial) launch_trial(c->Mm.map, act, role, c->st, c->d, alpha, s);
     const bool demag = (o.terms & MM_T_DEMAG) && c->rows_p > 0 && c->B.nrows > 0;
+    const double v = fp32 ? 4.0 : 8.0;
     if (demag) {
+        kt_begin(c, KT_BMUL);
         launch_bmul(c->B, c->Mb.map, act, c->st, role, c->b, fp32, s);
+        if (c->kt_on) kt_end(c, KT_BMUL, bmul_bytes(c, on, v));
         poisson(c, o.poisson_rtol, o.poisson_maxit, fp32, o.poisson_prec == MM_PREC_AMG, on);
     }
     EvalLaunch e;
@@ -976,7 +1132,9 @@ void eval_round(mm_ctx *c, const mm_opts &o, const std::vector<int> &on, bool an
     e.alpha = alpha;
     e.part = mslot(c, MS_EVAL);
     e.fp32 = fp32;
+    kt_begin(c, KT_EVAL);
     launch_eval_epilogue(e, s);
+    if (c->kt_on) kt_end(c, KT_EVAL, eval_bytes(c, o, on, demag, v));
     launch_finalize_inst(c->Mm.map, mslot(c, MS_EVAL), kEvalParts, eval_max_mask(), dsc_at(c, SC_EVAL), s);
     pull_sc(c, SC_EVAL, kEvalParts);
     sync(c);
@@ -1025,7 +1183,32 @@ void energy_parts(mm_ctx *c, int i, const Sc &v, const mm_opts &o, double E[5]) 
 
 // preconditioner for the instances with pact[i]: at most jmax steps of Alg. 1
 // on P y = g at the current state (exits li1-li3)
-void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32, int form) {
+// the exit flags of the inner solve, device -> host (pflags of the control block)
+void pull_prec_flags(mm_ctx *c, const int *dflags) {
+    if (dflags == c->d_(c->pflags())) return pull_flags(c);
+    HIPCHK(hipMemcpyAsync(c->pflags(), dflags, 4 * (size_t)c->ninst * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+}
+
+size_t prec_scratch_bytes(const mm_ctx *c) {
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t v3 = al(3 * (size_t)std::max(c->rows_m, 1) * sizeof(double));
+    return 3 * v3 + al(7 * (size_t)c->Mm.map.nblk * sizeof(double)) + al(4 * (size_t)c->ninst * sizeof(int));
+}
+PrecScratch prec_scratch_at(const mm_ctx *c, void *base) {
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t v3 = al(3 * (size_t)std::max(c->rows_m, 1) * sizeof(double));
+    char *b = (char *)base;
+    PrecScratch s;
+    s.r = (double *)b;
+    s.p = (double *)(b + v3);
+    s.q = (double *)(b + 2 * v3);
+    s.part = (double *)(b + 3 * v3);
+    s.flags = (int *)(b + 3 * v3 + al(7 * (size_t)c->Mm.map.nblk * sizeof(double)));
+    return s;
+}
+
+void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32, int form, const PrecScratch *ext = nullptr) {
     PrecLaunch a;
     a.C = &c->C;
     a.M = &c->Mm.map;
@@ -1036,11 +1219,11 @@ void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32, int form
     a.invDex = c->invDex;
     a.dscale = dscale;
     a.y = c->y;
-    a.r = c->pr;
-    a.p = c->pp;
-    a.q = c->pq;
-    a.part = mslot(c, MS_PREC);
-    a.flags = c->d_(c->pflags());
+    a.r = ext ? ext->r : c->pr;
+    a.p = ext ? ext->p : c->pp;
+    a.q = ext ? ext->q : c->pq;
+    a.part = ext ? ext->part : mslot(c, MS_PREC);
+    a.flags = ext ? ext->flags : c->d_(c->pflags());
     a.fp32 = fp32;
     a.form = form;
     launch_prec_init(a, c->stream);
@@ -1050,9 +1233,14 @@ void precondition(mm_ctx *c, int jmax, const double *dscale, bool fp32, int form
     // and stops launching once every instance has left; below that no host
     // round trip is added.
     for (int j = 0; j < jmax; ++j) {
-        launch_prec_iter(a, j, j + 1 == jmax, c->stream);
+        // the first application always works on every active instance: it is
+        // the one timed (later ones may return at once after an exit)
+        if (j == 0) kt_begin(c, KT_PREC_APPLY);
+        launch_prec_apply(a, j, c->stream);
+        if (j == 0 && c->kt_on) kt_end(c, KT_PREC_APPLY, prec_apply_bytes(c, form, fp32 ? 4.0 : 8.0));
+        launch_prec_tail(a, j, j + 1 == jmax, c->stream);
         if ((j + 1) % kPrecCheck == 0 && j + 1 < jmax) {
-            pull_flags(c);
+            pull_prec_flags(c, a.flags);
             sync(c);
             bool running = false;
             for (int i = 0; i < c->ninst && !running; ++i)
@@ -1094,14 +1282,21 @@ void set_h3(mm_ctx *c, int i, const double h[3]) {
 // ---------------------------------------------------------------------------
 // the batched minimizer: Alg. 4 per instance over its list of field values
 // ---------------------------------------------------------------------------
+// Interpolation step of the line search: phi(a) = dp0 a + q a^2 + k a^3 is the
+// cubic with phi(0) = 0, phi'(0) = dp0 that also meets phi(at) = dFt and
+// phi'(at) = dpt. Its local minimizer is the root of phi'(a) = dp0 + 2 q a +
+// 3 k a^2 where phi'' = 2 sqrt(q^2 - 3 k dp0) > 0, written without the
+// cancellation of the textbook root: a = -dp0 / (q + sqrt(q^2 - 3 k dp0)).
+// k = 0 (a parabola) needs no special case. No local minimizer: false.
 bool cubic_step(double at, double dFt, double dp0, double dpt, double *ac) {
-    double d1 = dp0 + dpt - 3.0 * dFt / at;
-    double disc = d1 * d1 - dp0 * dpt;
+    const double slope = dFt / at;                        // secant slope over [0, at]
+    const double k = (dp0 + dpt - 2.0 * slope) / (at * at);
+    const double q = (3.0 * slope - 2.0 * dp0 - dpt) / at;
+    const double disc = q * q - 3.0 * k * dp0;
     if (!(disc >= 0.0) || !std::isfinite(disc)) return false;
-    double d2 = std::sqrt(disc);
-    double den = dpt - dp0 + 2.0 * d2;
-    if (!(den != 0.0) || !std::isfinite(den)) return false;
-    double a = at - at * (dpt + d2 - d1) / den;
+    const double den = q + std::sqrt(disc);
+    if (!(den > 0.0) || !std::isfinite(den)) return false;
+    const double a = -dp0 / den;
     if (!std::isfinite(a)) return false;
     *ac = a;
     return true;
@@ -1154,6 +1349,8 @@ struct Learned {
     mm_gnn *net = nullptr;
     mm_graph *graph = nullptr;
     int mode = 0;
+    bool has_prev = false;        // the curve continues from a minimizer at h_prev
+    double h_prev[3] = {0, 0, 0};  // reduced units
 };
 
 class Driver {
@@ -1298,15 +1495,18 @@ private:
 
     void after_eval(int i, const Sc &v) {
         Run &R = r_[i];
+        // a NaN or infinite energy (a breakdown somewhere in the evaluation)
+        // ends the field; the accepted state is left as it was
+        if (!std::isfinite(v.E)) return finish(i, MM_NONFINITE);
         switch (R.step) {
             case S_EVAL0:
                 R.cur = v;
                 if (o_.stop_mode == MM_STOP_TORQUE && v.tmax < o_.tol_torque) {
                     finish(i, MM_OK);
-                } else if (ln_.mode && R.field > 0) {
+                } else if (ln_.mode && (R.field > 0 || ln_.has_prev)) {
                     // proposal of the network for this field step: start
                     // N(m + dm) and Jacobi factors s
-                    const double *hp = &h_[(size_t)3 * (i * nf_ + R.field - 1)];
+                    const double *hp = R.field > 0 ? &h_[(size_t)3 * (i * nf_ + R.field - 1)] : ln_.h_prev;
                     gnn_propose(c_, ln_.net, ln_.graph, hp, R.h);
                     R.scaled = (ln_.mode & 2) != 0;
                     if (ln_.mode & 1) R.step = S_LEARN_T;
@@ -1445,7 +1645,9 @@ private:
         if (c_->info()[i] != 0) R.fallbacks++;
         // top of the nonlinear iteration
         if (R.nli >= o_.max_nli) return finish(i, MM_NOT_CONVERGED);
-        if (!(R.dp0 < 0.0)) return finish(i, MM_OK);
+        // after the descent safeguard d = -g, so dp0 = -|g|^2: zero means a
+        // zero projected gradient; a value that is not negative is NaN
+        if (!(R.dp0 < 0.0)) return finish(i, R.dp0 == 0.0 ? MM_OK : MM_NONFINITE);
         double a0;
         if (R.first) a0 = o_.jmax > 0 ? 1.0 : o_.theta_init / R.dmax;
         else a0 = R.a_prev * R.dp_prev / R.dp0;
@@ -1485,6 +1687,37 @@ private:
         start_field(i, k + 1);
     }
 };
+
+int precondition_call(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax,
+                      const double *dscale, double *y, int *inner_iters, const PrecScratch *ext) {
+    require_single(c);
+    if (!m || !grad || !gproj || !y || jmax < 0) throw ApiError{MM_EINVAL, "bad precondition arguments"};
+    const int nm = c->inst[0].n_mag;
+    load_m(c, m);
+    copy_in(c, c->st[0].G, grad, 3 * (size_t)nm);
+    copy_in(c, c->st[0].g, gproj, 3 * (size_t)nm);
+    launch_lambda(c->Mm.map, c->st[0].x, c->st[0].G, c->st[0].lam, c->stream);
+    int it = 0;
+    if (jmax == 0) {
+        HIPCHK(hipMemcpyAsync(c->y, c->st[0].g, 3 * (size_t)nm * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    } else {
+        const double *ds = nullptr;
+        if (dscale) {
+            copy_in(c, c->dscale, dscale, nm);
+            ds = c->dscale;
+        }
+        c->pact()[0] = 1;
+        upload_ctl(c);
+        precondition(c, jmax, ds, c->opts.precision == MM_FP32_BULK, c->opts.prec_form, ext);
+        pull_prec_flags(c, ext ? ext->flags : c->d_(c->pflags()));
+    }
+    copy_out(c, y, c->y, 3 * (size_t)nm);
+    sync(c);
+    if (jmax > 0) it = c->pflags()[1];
+    if (inner_iters) *inner_iters = it;
+    return MM_OK;
+}
 
 bool opts_valid(const mm_opts &o, std::string &why) {
     if (o.jmax < 0) why = "jmax < 0";
@@ -1628,6 +1861,8 @@ int mm_destroy(mm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
+    for (auto &v : c->kt_ev)
+        for (auto &e : v) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return MM_OK;
@@ -1825,35 +2060,7 @@ int mm_batch_energy_grad(mm_ctx *c, const double *m, const double *h_ext, double
 
 int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax, const double *dscale,
                     double *y, int *inner_iters) {
-    return guarded(c, [&] {
-        require_single(c);
-        if (!m || !grad || !gproj || !y || jmax < 0) throw ApiError{MM_EINVAL, "bad precondition arguments"};
-        const int nm = c->inst[0].n_mag;
-        load_m(c, m);
-        copy_in(c, c->st[0].G, grad, 3 * (size_t)nm);
-        copy_in(c, c->st[0].g, gproj, 3 * (size_t)nm);
-        launch_lambda(c->Mm.map, c->st[0].x, c->st[0].G, c->st[0].lam, c->stream);
-        int it = 0;
-        if (jmax == 0) {
-            HIPCHK(hipMemcpyAsync(c->y, c->st[0].g, 3 * (size_t)nm * sizeof(double), hipMemcpyDeviceToDevice,
-                                  c->stream));
-        } else {
-            const double *ds = nullptr;
-            if (dscale) {
-                copy_in(c, c->dscale, dscale, nm);
-                ds = c->dscale;
-            }
-            c->pact()[0] = 1;
-            upload_ctl(c);
-            precondition(c, jmax, ds, c->opts.precision == MM_FP32_BULK, c->opts.prec_form);
-            pull_flags(c);
-        }
-        copy_out(c, y, c->y, 3 * (size_t)nm);
-        sync(c);
-        if (jmax > 0) it = c->pflags()[1];
-        if (inner_iters) *inner_iters = it;
-        return MM_OK;
-    });
+    return guarded(c, [&] { return precondition_call(c, m, grad, gproj, jmax, dscale, y, inner_iters, nullptr); });
 }
 
 int mm_ncg_minimize(mm_ctx *c, double *m_inout, const double h_ext[3], const mm_opts *o, mm_stats *st,
@@ -1927,8 +2134,8 @@ int mm_batch_demag_curve(mm_ctx *c, double *m_inout, const double *h_list, long 
 }
 
 int mm_demag_curve_learned(mm_ctx *c, mm_gnn *net, mm_graph *graph, int mode, double *m_inout,
-                           const double *h_list, long n, const mm_opts *o, double *m_avg, double *E_tot,
-                           mm_stats *st, int *accepted) {
+                           const double *h_prev, const double *h_list, long n, const mm_opts *o, double *m_avg,
+                           double *E_tot, mm_stats *st, int *accepted) {
     return guarded(c, [&] {
         require_single(c);
         if (!m_inout || !h_list || n < 0) throw ApiError{MM_EINVAL, "bad curve arguments"};
@@ -1947,6 +2154,10 @@ int mm_demag_curve_learned(mm_ctx *c, mm_gnn *net, mm_graph *graph, int mode, do
         ln.net = net;
         ln.graph = graph;
         ln.mode = mode;
+        if (h_prev) {
+            ln.has_prev = true;
+            reduce_field(c->inst[0], h_prev, ln.h_prev);
+        }
         Driver drv(c, op, h, n, out, ln);
         int rc = drv.run();
         store_m(c, m_inout);
@@ -1974,18 +2185,18 @@ int mm_operator_apply(mm_ctx *c, int op, const double *in, double *out) {
                 StateV sv[3];
                 sv[0].x = c->tmp3;
                 launch_bmul(c->B, c->Mb.map, nullptr, sv, nullptr, c->cq, fp32, s);
-                copy_out(c, out, c->cq, np);
+                pot_out(c, out, c->cq, c->cr);
                 break;
             }
             case MM_OP_BT:
-                copy_in(c, c->cq, in, np);
+                pot_in(c, c->cq, in, c->cr);
                 launch_btmul(c->Bt, c->Mm.map, c->cq, c->pq, fp32, s);
                 copy_out(c, out, c->pq, 3 * (size_t)nm);
                 break;
             case MM_OP_K:
-                copy_in(c, c->cr, in, np);
+                pot_in(c, c->cr, in, c->cq);
                 launch_spmv_scalar(c->K, c->Mp.map, c->cr, c->cq, fp32, s);
-                copy_out(c, out, c->cq, np);
+                pot_out(c, out, c->cq, c->cr);
                 break;
             default:
                 throw ApiError{MM_EINVAL, "unknown operator"};
@@ -2002,25 +2213,41 @@ int mm_poisson_solve(mm_ctx *c, const double *b, double *u_inout, double rtol, l
         const int np = c->inst[0].n_pot;
         // the solve runs on the context's b and u: keep the warm start aside
         HIPCHK(hipMemcpyAsync(c->usave, c->u, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        copy_in(c, c->b, b, np);
-        copy_in(c, c->u, u_inout, np);
-        c->act()[0] = 1;
-        upload_ctl(c);
-        const long mi0 = c->cnt[0].mi;
-        poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK,
-                c->opts.poisson_prec == MM_PREC_AMG, {0});
-        const long it = c->cnt[0].mi - mi0;
-        copy_out(c, u_inout, c->u, np);
-        // evaluations write only the magnet rows of b: clear it; restore u
-        launch_fill(np, c->b, 0.0, c->stream);
-        HIPCHK(hipMemcpyAsync(c->u, c->usave, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        sync(c);
+        // evaluations write only the magnet rows of b, so b is cleared and the
+        // warm start restored on every exit, failed solves included
+        auto restore = [&] {
+            launch_fill(np, c->b, 0.0, c->stream);
+            HIPCHK(hipMemcpyAsync(c->u, c->usave, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            sync(c);
+        };
+        long it = 0;
+        try {
+            pot_in(c, c->b, b, c->cq);
+            pot_in(c, c->u, u_inout, c->cq);
+            c->act()[0] = 1;
+            upload_ctl(c);
+            const long mi0 = c->cnt[0].mi;
+            poisson(c, rtol, c->opts.poisson_maxit, c->opts.precision == MM_FP32_BULK,
+                    c->opts.poisson_prec == MM_PREC_AMG, {0});
+            it = c->cnt[0].mi - mi0;
+            pot_out(c, u_inout, c->u, c->cq);
+        } catch (const ApiError &e) {
+            // not converged within poisson_maxit: the last iterate is the result
+            if (e.code == MM_NOT_CONVERGED) pot_out(c, u_inout, c->u, c->cq);
+            restore();
+            throw;
+        } catch (...) {
+            restore();
+            throw;
+        }
+        restore();
         if (iters) *iters = it;
         return MM_OK;
     });
 }
 
-int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave) {
+int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, int *slices_per_wave,
+            int *block_mult) {
     return guarded(c, [&] {
         require_ready(c);
         const bool fp32 = c->opts.precision == MM_FP32_BULK;
@@ -2040,8 +2267,28 @@ int mm_tune(mm_ctx *c, int mode, const char *cache_path, int *waves_per_block, i
                 throw ApiError{MM_EINVAL, "unknown tuning mode"};
         }
         if (waves_per_block) *waves_per_block = c->pnw;
+        if (block_mult) *block_mult = c->pbm;
         if (slices_per_wave)
             for (int i = 0; i < c->ninst; ++i) slices_per_wave[i] = c->pspw[i];
+        return MM_OK;
+    });
+}
+
+int mm_profile_kernels(mm_ctx *c, int enable, double out[9]) {
+    return guarded(c, [&] {
+        if (c->stream) sync(c);
+        kt_harvest(c);
+        if (enable < 0) {
+            for (int k = 0; k < KT_N; ++k) c->kt_sec[k] = c->kt_calls[k] = c->kt_bytes[k] = 0;
+        } else {
+            c->kt_on = enable != 0;
+        }
+        if (out)
+            for (int k = 0; k < KT_N; ++k) {
+                out[3 * k] = c->kt_calls[k];
+                out[3 * k + 1] = c->kt_sec[k];
+                out[3 * k + 2] = c->kt_bytes[k];
+            }
         return MM_OK;
     });
 }

@@ -206,7 +206,7 @@ def test_tuner_cache_and_forced_shape(B, oracle_mod, tmp_path):
     nw, spw = ctx.tune(B.MM_TUNE_CACHE, str(cache))
     assert nw in (4, 8, 16) and set(spw.tolist()) <= {1, 2, 4}
     text = cache.read_text()
-    assert '"mmncg_tune": 2' in text
+    assert '"mmncg_tune": 3' in text and '"bm": ' in text
     # a second call is served from the cache alone (the file is not rewritten)
     mtime = cache.stat().st_mtime_ns
     nw2, spw2 = ctx.tune(B.MM_TUNE_CACHE, str(cache))

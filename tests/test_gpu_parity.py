@@ -255,19 +255,64 @@ def test_device_pointers(B, oracle_mod):
     ctx.close()
 
 
+def _curve_energy_tols(o, ro, fields):
+    """Relative energy tolerance 1e-8 of each field's energy scale: the
+    larger of |E| and the sum of the magnitudes of its parts (the total
+    passes through zero where the Zeeman energy balances the rest)."""
+    tols = []
+    for k in range(len(fields)):
+        parts = o.eval_T(ro["hist"][k], fields[k])["E"]
+        tols.append(1e-8 * max(abs(ro["E"][k]), float(np.abs(parts[:4]).sum())))
+    return np.array(tols)
+
+
 def test_curve_matches_oracle_small(B, oracle_mod):
     """Whole demagnetization curve of a small soft cube (21 fields)."""
     w = inputs.soft_cube(n=4, h=4.0)
     o = oracle_mod.Oracle(w.mesh)
     ctx = _ctx(B, w.mesh)
     rg = ctx.curve(w.m0, w.fields, jmax=4)
-    ro = o.curve(w.m0, w.fields, jmax=4)
+    ro = o.curve(w.m0, w.fields, jmax=4, keep_hist=True)
     assert rg["rc"] == 0 and ro["rc"] == 0
-    for k in range(len(w.fields)):
-        tol = 1e-8 * max(abs(ro["E"][k]), 1.0)
-        assert abs(rg["E"][k] - ro["E"][k]) <= tol * 10, k
+    tol = _curve_energy_tols(o, ro, w.fields)
+    dE = np.abs(rg["E"] - ro["E"])
+    assert np.all(dE <= tol), (dE / tol).max()
     assert np.abs(rg["m_avg"] - ro["m_avg"]).max() < 1e-5
     assert np.abs(rg["m"] - ro["m"]).max() <= 1e-5
+    ctx.close()
+
+
+def test_failed_poisson_solve_leaves_the_context_clean(B, oracle_mod):
+    """A scalar-potential solve stopped by its iteration cap reports
+    MM_NOT_CONVERGED and must leave the context as it was: a later
+    evaluation matches the oracle."""
+    mesh = MESHES["hard_5x4x3"]()
+    o = oracle_mod.Oracle(mesh)
+    o.set_poisson(1e-13)
+    ctx = _ctx(B, mesh, poisson_rtol=1e-13, poisson_maxit=1)
+    b = o.bmul(inputs.random_unit(o.nm, 3))
+    u, it = ctx.poisson(b, u0=np.full(o.np, 0.5), rtol=1e-12)
+    assert ctx.last_rc == B.MM_NOT_CONVERGED
+    assert np.abs(u - 0.5).max() > 0.0       # the last iterate was written
+    ctx.set_opts(poisson_rtol=1e-13)
+    m = inputs.random_unit(o.nm, 4)
+    hT = np.array([0.1, 0.2, 0.5])
+    rg = ctx.energy_grad(m, hT)
+    ro = o.eval_T(m, hT)
+    assert np.abs(rg["E"] - ro["E"]).max() < 1e-11 * np.abs(ro["E"]).max()
+    assert rel(rg["G"], ro["G"]) < 1e-10
+    ctx.close()
+
+
+def test_nonfinite_field_is_reported_not_converged(B):
+    """A NaN in an evaluation ends the field with MM_NONFINITE and the
+    input state, never with MM_OK."""
+    mesh = MESHES["soft_3x2x2"]()
+    ctx = _ctx(B, mesh)
+    m0 = inputs.tilted_state(ctx.n_mag, (0, 0, 1), 0.01, np.random.Generator(np.random.PCG64(2)))
+    mg, Eg, sg, rc = ctx.minimize(m0, [np.nan, 0.0, 0.2], jmax=4)
+    assert rc == B.MM_NONFINITE and sg["status"] == B.MM_NONFINITE
+    np.testing.assert_array_equal(mg, m0)
     ctx.close()
 
 
