@@ -37,6 +37,7 @@ struct mm_gnn {
     float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
     float *mu = nullptr, *sd = nullptr;   // input standardization (32 each)
     long t = 0;
+    bool f32 = false;  // debug mode: FP32 operands in the dense layers (mm_gnn_set_precision)
     int cap = 0;  // workspace rows
     std::vector<void *> ws;
     float *X = nullptr, *Xn = nullptr, *y0 = nullptr, *h3 = nullptr, *zm = nullptr, *zs = nullptr, *dh = nullptr, *dt = nullptr,
@@ -185,17 +186,17 @@ void forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, double *d
     hipStream_t s = g->stream;
     const float *th = g->theta;
     gnn_norm_features(n, X, g->mu, g->sd, g->Xn, s);
-    gnn_mm(n, kF, kW, 1, g->Xn, kF, th + oWin, kW, false, th + oBin, g->z[0], 2 * kW, g->y0, kW, nullptr, 0, s);
+    gnn_mm(n, kF, kW, 1, g->Xn, kF, th + oWin, kW, false, th + oBin, g->z[0], 2 * kW, g->y0, kW, nullptr, 0, g->f32, s);
     for (int l = 0; l < kLayers; ++l) {
         float *z = g->z[l];
         gnn_agg(n, gr->ptr, gr->idx, gr->invdeg, z, 2 * kW, g->a[l], kW, s);
-        gnn_mm(n, kW, kW, 0, g->a[l], kW, th + oWe1(l), kW, false, nullptr, z + kW, 2 * kW, nullptr, 0, nullptr, 0, s);
+        gnn_mm(n, kW, kW, 0, g->a[l], kW, th + oWe1(l), kW, false, nullptr, z + kW, 2 * kW, nullptr, 0, nullptr, 0, g->f32, s);
         gnn_edge_add(n, gr->ebar, th + oWe2(l), z + kW, 2 * kW, s);
         gnn_mm(n, 2 * kW, kW, 1, z, 2 * kW, th + oW1(l), kW, false, th + ob1(l), g->tt[l], kW, g->y1[l], kW, nullptr,
-               0, s);
+               0, g->f32, s);
         float *hn = (l + 1 < kLayers) ? g->z[l + 1] : g->h3;
         const int ldh = (l + 1 < kLayers) ? 2 * kW : kW;
-        gnn_mm(n, kW, kW, 2, g->tt[l], kW, th + oW2(l), kW, false, th + ob2(l), hn, ldh, nullptr, 0, z, 2 * kW, s);
+        gnn_mm(n, kW, kW, 2, g->tt[l], kW, th + oW2(l), kW, false, th + ob2(l), hn, ldh, nullptr, 0, z, 2 * kW, g->f32, s);
     }
     gnn_heads(n, g->h3, th + oWm, th + obm, th + oWs, th + obs, m, g->zm, g->zs, dm, sv, s);
 }
@@ -214,21 +215,21 @@ void backward(mm_gnn *g, mm_graph *gr) {
     gnn_heads_dh(n, g->d_zm, g->d_zs, th + oWm, th + oWs, g->dh, s);
     for (int l = kLayers - 1; l >= 0; --l) {
         float *z = g->z[l];
-        gnn_mm_tn(n, kW, kW, g->tt[l], kW, g->dh, kW, part, gr_ + oW2(l), false, s);
+        gnn_mm_tn(n, kW, kW, g->tt[l], kW, g->dh, kW, part, gr_ + oW2(l), false, g->f32, s);
         gnn_tn32(n, 1, kW, nullptr, 0, g->dh, kW, part, gr_ + ob2(l), s);
-        gnn_mm(n, kW, kW, 0, g->dh, kW, th + oW2(l), kW, true, nullptr, g->dt, kW, nullptr, 0, nullptr, 0, s);
+        gnn_mm(n, kW, kW, 0, g->dh, kW, th + oW2(l), kW, true, nullptr, g->dt, kW, nullptr, 0, nullptr, 0, g->f32, s);
         gnn_silu_bwd((int64_t)n * kW, g->dt, g->y1[l], g->dy, s);
-        gnn_mm_tn(n, 2 * kW, kW, z, 2 * kW, g->dy, kW, part, gr_ + oW1(l), false, s);
+        gnn_mm_tn(n, 2 * kW, kW, z, 2 * kW, g->dy, kW, part, gr_ + oW1(l), false, g->f32, s);
         gnn_tn32(n, 1, kW, nullptr, 0, g->dy, kW, part, gr_ + ob1(l), s);
-        gnn_mm(n, kW, 2 * kW, 0, g->dy, kW, th + oW1(l), kW, true, nullptr, g->dz, 2 * kW, nullptr, 0, nullptr, 0, s);
+        gnn_mm(n, kW, 2 * kW, 0, g->dy, kW, th + oW1(l), kW, true, nullptr, g->dz, 2 * kW, nullptr, 0, nullptr, 0, g->f32, s);
         gnn_add64(n, g->dz, 2 * kW, g->dh, kW, s);
-        gnn_mm_tn(n, kW, kW, g->a[l], kW, g->dz + kW, 2 * kW, part, gr_ + oWe1(l), false, s);
+        gnn_mm_tn(n, kW, kW, g->a[l], kW, g->dz + kW, 2 * kW, part, gr_ + oWe1(l), false, g->f32, s);
         gnn_tn32(n, 4, kW, gr->ebar, 4, g->dz + kW, 2 * kW, part, gr_ + oWe2(l), s);
-        gnn_mm(n, kW, kW, 0, g->dz + kW, 2 * kW, th + oWe1(l), kW, true, nullptr, g->da, kW, nullptr, 0, nullptr, 0, s);
+        gnn_mm(n, kW, kW, 0, g->dz + kW, 2 * kW, th + oWe1(l), kW, true, nullptr, g->da, kW, nullptr, 0, nullptr, 0, g->f32, s);
         gnn_agg_t_add(n, gr->ptr, gr->idx, gr->invdeg, g->da, kW, g->dh, kW, s);
     }
     gnn_silu_bwd((int64_t)n * kW, g->dh, g->y0, g->dy, s);
-    gnn_mm_tn(n, kF, kW, g->Xn, kF, g->dy, kW, part, gr_ + oWin, false, s);
+    gnn_mm_tn(n, kF, kW, g->Xn, kF, g->dy, kW, part, gr_ + oWin, false, g->f32, s);
     gnn_tn32(n, 1, kW, nullptr, 0, g->dy, kW, part, gr_ + oBin, s);
 }
 
@@ -311,6 +312,17 @@ int mm_gnn_destroy(mm_gnn *g) {
 }
 
 const char *mm_gnn_last_error(const mm_gnn *g) { return g ? g->err.c_str() : "null network"; }
+
+int mm_gnn_set_precision(mm_gnn *g, int precision) {
+    if (!g) return MM_EINVAL;
+    if (precision != MM_GNN_BF16 && precision != MM_GNN_FP32) {
+        g->err = "precision must be MM_GNN_BF16 or MM_GNN_FP32";
+        return MM_EINVAL;
+    }
+    g->f32 = precision == MM_GNN_FP32;
+    g->err.clear();
+    return MM_OK;
+}
 
 int mm_gnn_set_params(mm_gnn *g, const double *theta) {
     return gguard(g, [&] {

@@ -3,9 +3,10 @@
 // scaling of the preconditioner's Jacobi diagonal (not part of the paper's
 // method; the method's own minimizer always runs to the same tolerance).
 //
-// Dense layers run on the matrix cores: v_mfma_f32_16x16x16_bf16 with BF16
-// operands (FP32 activations and FP32 master weights rounded to nearest even
-// when loaded) and FP32 accumulation. Neighbour means, heads, losses and the
+// Dense layers run on the matrix cores: gfx950's v_mfma_f32_16x16x32_bf16
+// with BF16 operands (FP32 activations and FP32 master weights rounded to
+// nearest even when loaded) and FP32 accumulation; a debug mode runs the same
+// products with FP32 operands on the vector units. Neighbour means, heads, losses and the
 // optimizer run in FP32 on the vector units. Every reduction over nodes is a
 // fixed-order two-stage sum (per-block partials, then one pass over the
 // blocks): no floating-point atomics, so training is deterministic.
@@ -17,8 +18,17 @@ namespace mmncg {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D += A B on one 16 x 16 tile, k = 32: lane l supplies A(l % 16, 8 (l / 16) + j)
+// and B(8 (l / 16) + j, l % 16), j = 0..7 (BF16 bit patterns), and holds
+// D(4 (l / 16) + j, l % 16), j = 0..3
+__device__ __forceinline__ f32x4 mfma32(const s16x8 &a, const s16x8 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                    0, 0);
+}
 
 constexpr int kGB = 256;   // threads per block
 constexpr int kRowsPerBlock = 64;   // rows of the row-GEMM per block (16 per wave)
@@ -37,13 +47,29 @@ __device__ __forceinline__ float dsilu_f(float x) {
     return s * (1.0f + x * (1.0f - s));
 }
 
+// epilogue of the row products: Y = v (0), Ypre = v and Y = silu(v) (1),
+// Y = R + v (2), Y += v (3)
+template <int EPI>
+__device__ __forceinline__ void mm_store(int row, int col, float v, float *__restrict__ Y, int ldy,
+                                         float *__restrict__ Ypre, int ldp, const float *__restrict__ R, int ldr) {
+    if (EPI == 0) {
+        Y[(size_t)row * ldy + col] = v;
+    } else if (EPI == 1) {
+        Ypre[(size_t)row * ldp + col] = v;
+        Y[(size_t)row * ldy + col] = silu_f(v);
+    } else if (EPI == 2) {
+        Y[(size_t)row * ldy + col] = R[(size_t)row * ldr + col] + v;
+    } else {
+        Y[(size_t)row * ldy + col] += v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Y[M x NC] = A[M x K] B[K x NC] (+ bias) with an epilogue.
 // A(i, k) = A[i * lda + k]; B(k, j) = W[k * ldw + j], or W[j * ldw + k] when
 // transposed. A block stages B in LDS as BF16 and computes 64 rows; wave w
-// owns rows 16w..16w+15 and all NC columns (NC / 16 MFMA tiles). Operand
-// layout of the 16x16x16 MFMA: lane l supplies A(l % 16, 4 (l / 16) + j) and
-// B(4 (l / 16) + j, l % 16), j = 0..3, and receives D(4 (l / 16) + j, l % 16).
+// owns rows 16w..16w+15 and all NC columns (NC / 16 MFMA tiles of mfma32).
+// K is a multiple of 32.
 // ---------------------------------------------------------------------------
 template <int NC, int EPI>
 __global__ __launch_bounds__(kGB) void k_mm(int M, int K, const float *__restrict__ A, int lda,
@@ -58,24 +84,27 @@ __global__ __launch_bounds__(kGB) void k_mm(int M, int K, const float *__restric
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = blockIdx.x * kRowsPerBlock + 16 * w;
-    const int li = lane & 15, lk = 4 * (lane >> 4);
+    const int li = lane & 15, lk = 8 * (lane >> 4), lo = 4 * (lane >> 4);
     f32x4 acc[NC / 16];
 #pragma unroll
     for (int t = 0; t < NC / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = r0 + li;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 a;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        s16x8 a;
         if (arow < M) {
             const float *ap = A + (size_t)arow * lda + k0 + lk;
-            a = bf16x4{to_bf16(ap[0]), to_bf16(ap[1]), to_bf16(ap[2]), to_bf16(ap[3])};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = to_bf16(ap[j]);
         } else {
-            a = bf16x4{0, 0, 0, 0};
+            a = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
         }
 #pragma unroll
         for (int t = 0; t < NC / 16; ++t) {
             const short *bp = Bs + (size_t)(k0 + lk) * NC + 16 * t + li;
-            bf16x4 b = bf16x4{bp[0], bp[NC], bp[2 * NC], bp[3 * NC]};
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            s16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = bp[j * NC];
+            acc[t] = mfma32(a, b, acc[t]);
         }
     }
 #pragma unroll
@@ -84,54 +113,59 @@ __global__ __launch_bounds__(kGB) void k_mm(int M, int K, const float *__restric
         const float bv = bias ? bias[col] : 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int row = r0 + lk + j;
-            if (row >= M) continue;
-            float v = acc[t][j] + bv;
-            if (EPI == 0) {
-                Y[(size_t)row * ldy + col] = v;
-            } else if (EPI == 1) {
-                Ypre[(size_t)row * ldp + col] = v;
-                Y[(size_t)row * ldy + col] = silu_f(v);
-            } else if (EPI == 2) {
-                Y[(size_t)row * ldy + col] = R[(size_t)row * ldr + col] + v;
-            } else {
-                Y[(size_t)row * ldy + col] += v;
-            }
+            const int row = r0 + lo + j;
+            if (row < M) mm_store<EPI>(row, col, acc[t][j] + bv, Y, ldy, Ypre, ldp, R, ldr);
         }
     }
 }
 
+// the same product with FP32 operands on the vector units (the debug mode):
+// one thread per output, k summed in order
+template <int NC, int EPI>
+__global__ __launch_bounds__(kGB) void k_mm32(int M, int K, const float *__restrict__ A, int lda,
+                                              const float *__restrict__ W, int ldw, int transW,
+                                              const float *__restrict__ bias, float *__restrict__ Y, int ldy,
+                                              float *__restrict__ Ypre, int ldp, const float *__restrict__ R,
+                                              int ldr) {
+    const int64_t e = (int64_t)blockIdx.x * kGB + threadIdx.x;
+    if (e >= (int64_t)M * NC) return;
+    const int row = (int)(e / NC), col = (int)(e % NC);
+    float acc = 0.0f;
+    for (int k = 0; k < K; ++k)
+        acc = fmaf(A[(size_t)row * lda + k], transW ? W[(size_t)col * ldw + k] : W[(size_t)k * ldw + col], acc);
+    mm_store<EPI>(row, col, acc + (bias ? bias[col] : 0.0f), Y, ldy, Ypre, ldp, R, ldr);
+}
+
 // ---------------------------------------------------------------------------
 // weight gradients: part[blk][KI x NC] = sum over the block's rows r of
-// A[r][i] B[r][j] (MFMA with the rows as the reduction dimension); the
-// partials are summed over blocks by k_reduce_blocks
+// A[r][i] B[r][j] (MFMA with the rows as the reduction dimension, 32 rows per
+// step: lane l supplies rows r0 + 8 (l / 16) + j); the partials are summed
+// over blocks by k_reduce_blocks
 // ---------------------------------------------------------------------------
 template <int KI, int NC>
 __global__ __launch_bounds__(kGB) void k_mm_tn(int M, const float *__restrict__ A, int lda,
                                                const float *__restrict__ B, int ldb, float *__restrict__ part) {
     constexpr int TI = KI / 16, TJ = NC / 16, NT = TI * TJ, TPW = (NT + 3) / 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int li = lane & 15, lk = 4 * (lane >> 4);
+    const int li = lane & 15, lk = 8 * (lane >> 4), lo = 4 * (lane >> 4);
     const int rbeg = blockIdx.x * kTnRows;
     f32x4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int r0 = rbeg; r0 < rbeg + kTnRows && r0 < M; r0 += 16) {
+    for (int r0 = rbeg; r0 < rbeg + kTnRows && r0 < M; r0 += 32) {
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = w + 4 * q;
             if (tile >= NT) continue;
             const int it = tile / TJ, jt = tile % TJ;
-            short av[4], bv[4];
+            s16x8 a, b;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 const int r = r0 + lk + j;
-                av[j] = r < M ? to_bf16(A[(size_t)r * lda + 16 * it + li]) : (short)0;
-                bv[j] = r < M ? to_bf16(B[(size_t)r * ldb + 16 * jt + li]) : (short)0;
+                a[j] = r < M ? to_bf16(A[(size_t)r * lda + 16 * it + li]) : (short)0;
+                b[j] = r < M ? to_bf16(B[(size_t)r * ldb + 16 * jt + li]) : (short)0;
             }
-            bf16x4 a = bf16x4{av[0], av[1], av[2], av[3]};
-            bf16x4 b = bf16x4{bv[0], bv[1], bv[2], bv[3]};
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+            acc[q] = mfma32(a, b, acc[q]);
         }
     }
     float *out = part + (size_t)blockIdx.x * KI * NC;
@@ -141,15 +175,16 @@ __global__ __launch_bounds__(kGB) void k_mm_tn(int M, const float *__restrict__ 
         if (tile >= NT) continue;
         const int it = tile / TJ, jt = tile % TJ;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out[(16 * it + lk + j) * NC + 16 * jt + li] = acc[q][j];
+        for (int j = 0; j < 4; ++j) out[(16 * it + lo + j) * NC + 16 * jt + li] = acc[q][j];
     }
 }
 
-// FP32 version for small products (KI * NC <= 256): thread t owns output
-// (t / NC, t % NC); A == null means a column of ones (column sums of B)
+// FP32 version (small products, and every weight gradient in the debug
+// mode): thread t of block row y owns output t + 256 y = (i, j), i = . / NC;
+// A == null means a column of ones (column sums of B)
 __global__ __launch_bounds__(kGB) void k_tn32(int M, int KI, int NC, const float *__restrict__ A, int lda,
                                               const float *__restrict__ B, int ldb, float *__restrict__ part) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x + kGB * blockIdx.y;
     if (t >= KI * NC) return;
     const int i = t / NC, j = t % NC;
     const int rbeg = blockIdx.x * kTnRows;
@@ -389,12 +424,17 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 // launchers
 // ===========================================================================
 void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float *W, int ldw, bool transW,
-            const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, hipStream_t s) {
+            const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, bool f32,
+            hipStream_t s) {
     if (M <= 0) return;
-    const dim3 g(blocks_for(M, kRowsPerBlock)), b(kGB);
-#define MMNCG_MM(NCV, E)                                                                                           \
-    hipLaunchKernelGGL((k_mm<NCV, E>), g, b, 0, s, M, K, A, lda, W, ldw, transW ? 1 : 0, bias, Y, ldy, Ypre, ldp, R, \
-                       ldr)
+    const dim3 g(f32 ? blocks_for((int64_t)M * NC, kGB) : blocks_for(M, kRowsPerBlock)), b(kGB);
+#define MMNCG_MM(NCV, E)                                                                                             \
+    if (f32)                                                                                                         \
+        hipLaunchKernelGGL((k_mm32<NCV, E>), g, b, 0, s, M, K, A, lda, W, ldw, transW ? 1 : 0, bias, Y, ldy, Ypre, ldp, \
+                           R, ldr);                                                                                  \
+    else                                                                                                             \
+        hipLaunchKernelGGL((k_mm<NCV, E>), g, b, 0, s, M, K, A, lda, W, ldw, transW ? 1 : 0, bias, Y, ldy, Ypre, ldp, \
+                           R, ldr)
 #define MMNCG_MM_E(NCV)          \
     switch (epi) {               \
         case 0: MMNCG_MM(NCV, 0); break; \
@@ -416,10 +456,11 @@ void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float 
 int gnn_tn_blocks(int M) { return (int)blocks_for(M, kTnRows); }
 
 void gnn_mm_tn(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
-               bool accumulate, hipStream_t s) {
+               bool accumulate, bool f32, hipStream_t s) {
     const int nb = gnn_tn_blocks(M);
     if (M <= 0) return;
-    if (KI == 32) hipLaunchKernelGGL((k_mm_tn<32, 64>), dim3(nb), dim3(kGB), 0, s, M, A, lda, B, ldb, part);
+    if (f32) hipLaunchKernelGGL(k_tn32, dim3(nb, blocks_for(KI * 64, kGB)), dim3(kGB), 0, s, M, KI, 64, A, lda, B, ldb, part);
+    else if (KI == 32) hipLaunchKernelGGL((k_mm_tn<32, 64>), dim3(nb), dim3(kGB), 0, s, M, A, lda, B, ldb, part);
     else if (KI == 64) hipLaunchKernelGGL((k_mm_tn<64, 64>), dim3(nb), dim3(kGB), 0, s, M, A, lda, B, ldb, part);
     else hipLaunchKernelGGL((k_mm_tn<128, 64>), dim3(nb), dim3(kGB), 0, s, M, A, lda, B, ldb, part);
     (void)NC;

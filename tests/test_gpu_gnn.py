@@ -11,6 +11,7 @@ through BF16. Features and the Hutchinson probe are FP64/FP32 arithmetic
 checked to round-off.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -22,6 +23,7 @@ from paper_1801_03690_amd import inputs
 pytestmark = pytest.mark.gpu
 
 MU0 = 4e-7 * math.pi
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _gpu_available():
@@ -164,6 +166,36 @@ def test_loss_and_gradient_match_oracle(B):
     ctx.close()
 
 
+def test_fp32_debug_mode_matches_the_fp64_oracle(B):
+    """With FP32 operands in the dense layers (the debug mode), the forward
+    pass, the loss and every parameter gradient agree with the unrounded FP64
+    oracle to 1e-5 of their scale: what is left is FP32 rounding, which pins
+    the backward kernels independently of the BF16 rounding of the default
+    mode."""
+    ctx, gr, net, o, og = setup(B, mesh_small())
+    net.set_precision(True)
+    theta = inputs.gnn_init(12, head_scale=1.0) + 0.02 * np.random.default_rng(3).standard_normal(G.n_params())
+    net.set_params(theta)
+    th32 = net.get_params()
+    X, m, dmt, st = rand_inputs(gr.n, 4)
+    L = o.lumped()
+    dm, s = net.forward(gr, X, m)
+    dmo, so, cache = G.forward(th32, X.astype(np.float64), og, m, emulate_bf16=False)
+    assert np.abs(dm - dmo).max() <= 1e-5 * np.abs(dmo).max()
+    assert np.abs(s - so).max() <= 1e-5 * np.abs(so).max()
+    loss, grad = net.loss_grad(gr, X, m, dmt, st, inv_dm2=2.0, w_s=0.5)
+    lo, go = G.backward(th32, cache, og, dmt, st, L, 2.0, 0.5, emulate_bf16=False)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    gb, ob = blocks(grad), blocks(go)
+    for name, _ in G.param_shapes():
+        sc = np.abs(ob[name]).max()
+        assert np.abs(gb[name] - ob[name]).max() <= 1e-5 * sc + 1e-12, name
+    net.set_precision(False)
+    net.close()
+    gr.close()
+    ctx.close()
+
+
 def test_adam_step_matches_oracle(B):
     ctx, gr, net, o, og = setup(B, mesh_small())
     theta = inputs.gnn_init(13, head_scale=1.0)
@@ -228,8 +260,10 @@ def test_learned_curve_keeps_the_method(B):
 def test_training_lowers_the_loss_and_keeps_the_minima(B):
     """Short training on the solver's own trajectories of three small films:
     the held-out relative step error falls well below that of the untrained
-    network, the learned curve takes the proposed start at many fields, stays
-    in the plain curve's minima, and its iteration counts are reported."""
+    network, the learned curve takes the proposed start at many fields and
+    stays in the plain curve's minima. (Six epochs on three 60-100 nm films
+    are too few to promise a gain; the shipped network's gain is asserted
+    by test_trained_network_saves_work_on_held_out_films.)"""
     from paper_1801_03690_amd import learn
     films = [learn.Film(inputs.small_film(100 + i, lo=60.0, hi=100.0), n_probe=8, probe_seed=500 + i)
              for i in range(3)]
@@ -253,3 +287,26 @@ def test_training_lowers_the_loss_and_keeps_the_minima(B):
     assert res[3]["accepted"] >= 0.2 * (len(val[0].work.fields) - 1)
     for f in films + val:
         f.close()
+
+
+@pytest.mark.parametrize("seed", [900, 901])
+def test_trained_network_saves_work_on_held_out_films(B, seed):
+    """The shipped network (paper_1801_03690_amd/data/gnn_films.npz, trained
+    by learn.py with the library's kernels on films 100-115 of 120-280 nm) on
+    films it never saw: the learned curve (warm start + Jacobi scaling) meets
+    the same torque tolerance in the plain curve's minima with at least 10%
+    fewer evaluations, nonlinear iterations and scalar-potential CG
+    iterations than the plain method (measured when it was trained: 24-27%)."""
+    from paper_1801_03690_amd import learn
+    w = inputs.small_film(seed)
+    ctx = B.Context(0).upload(w.mesh)
+    net = learn.load_net(os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films.npz"), ctx)
+    res = learn.compare(w, net, jmax=4, modes=(0, 3), ctx=ctx)
+    print(f"held-out film {w.name}: plain {res[0]}, learned {res[3]}")
+    plain, lrn = res[0], res[3]
+    assert plain["rc"] == 0 and lrn["rc"] == 0
+    assert lrn["basin_mismatches"] == 0 and lrn["max_rel_dE_vs_plain"] < 1e-7
+    for k in ("evals", "nli", "mi"):
+        assert lrn[k] <= 0.9 * plain[k], (k, lrn[k], plain[k])
+    net.close()
+    ctx.close()
