@@ -1,22 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark: demagnetization-curve time-to-solution on one MI355X.
 
-One step = one whole demagnetization curve (every field value, each
-minimization run to max |m x h_eff| < 1e-6) of the hard-magnetic cube: edge
-80 nm, 20^3 cells x 6 tets, 3x air box for the scalar potential, mu0 Ms =
-1.61 T, K1 = 4.3 MJ/m^3, A = 7.7 pJ/m, easy axis z tilted 1 degree toward x,
-field along -z from 0 to -8 T in 0.05 T steps (161 values), jmax = 1, in the
-FP32-bulk mode (FP32 operators and Poisson CG, FP64 reductions, FP64
-magnetization), the scalar-potential CG preconditioned by algebraic multigrid
-(as in the paper; --poisson-prec jacobi for the Jacobi-preconditioned CG).
-Inputs (mesh operators, the start state) are resident in HBM before the timed
-region; assembly and the multigrid set-up are untimed, as in the paper.
+Default workload: the soft thin film, 1000 x 1000 x 10 nm on 200 x 200 x 2
+cells of 5 nm x 6 tets (121,203 magnet nodes) in a 3x air box for the scalar
+potential (1.79M free potential nodes), Ms = 8e5 A/m, A = 13 pJ/m, K1 = 0,
+field along x from +50 mT to -50 mT in 1 mT steps (101 values), j_max 10,
+every minimization run to max |m x h_eff| < 1e-6 (reduced units). Two forms
+reach the same torque tolerance:
 
-Printed (one JSON line): time per curve, the measured bandwidth of the
-dominant work, one scalar-potential CG iteration, against the HBM roofline
-(HIP events around its launches inside the timed region), the plain FP64
-form's and the Jacobi-preconditioned form's times for the same curve, and the
-CPU FP64 oracle timed on a bounded sample of the same workload.
+  * learned + FP32 (the value): the network's warm start and Jacobi scaling at
+    every field after the first, FP32-stored operators with FP64 reductions;
+  * plain FP64: the method without the network, every operator in FP64.
+
+One step is one stretch of the curve: the field list is split into `--steps`
+consecutive chunks, each continuing from the previous chunk's minimum (the
+learned proposal included), so the K timed steps together are exactly one
+whole curve and `value` is its time-to-solution. With more steps than fields
+each step is one field and the curve restarts from its initial state after
+the last field; `value` is then the timed seconds per curve walked. The
+`--warmup` untimed steps are the first chunks of the same curve, run before
+the timed curve starts again from the initial state. Inputs (operators,
+start state, network) are resident in HBM; assembly, the block-shape tuning
+and the network's training are not timed, as in the paper (Sec. 3.1).
+
+Printed (one JSON line): the time per curve, the plain FP64 form's time for
+the same curve, the roofline of the dominant kernel (the scalar-potential CG
+iteration, timed with HIP events on the library's stream around its graph
+replays inside the timed region), the per-launch bandwidth of the field
+kernels (C m + B^T u epilogue, B m, P v) from HIP events in the same region,
+the CPU FP64 oracle timed on a bounded sample of the same workload, and the
+20^3 hard cube's curve (FP32 bulk, multigrid CG) as an extra figure.
+
+Other workloads (--workload): hard_cube, polycrystal (bound it with
+--fields), batch64.
 """
 from __future__ import annotations
 
@@ -30,24 +46,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-# counter-measured traffic per CG iteration of the hard cube, by preconditioner:
-# (file, kernel source it was measured on)
+METRIC = "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol"
+PROF = os.path.join(ROOT, "profiles")
+SRC = os.path.join(ROOT, "paper_1801_03690_amd", "csrc")
+# counter-measured traffic per CG iteration: (file, kernel source it was measured on)
 TRAFFIC = {
-    "jacobi": (os.path.join(ROOT, "profiles", "pcg_hard_cube_20_traffic.txt"),
-               os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "poisson.hip")),
-    "amg": (os.path.join(ROOT, "profiles", "amg_hard_cube_20_traffic.txt"),
-            os.path.join(ROOT, "paper_1801_03690_amd", "csrc", "amg.hip")),
+    ("hard_cube", "jacobi"): (os.path.join(PROF, "pcg_hard_cube_20_traffic.txt"), os.path.join(SRC, "poisson.hip")),
+    ("hard_cube", "amg"): (os.path.join(PROF, "amg_hard_cube_20_traffic.txt"), os.path.join(SRC, "amg.hip")),
+    ("film", "jacobi"): (os.path.join(PROF, "pcg_film_traffic.txt"), os.path.join(SRC, "poisson.hip")),
+    ("polycrystal", "amg"): (os.path.join(PROF, "amg_polycrystal_traffic.txt"), os.path.join(SRC, "amg.hip")),
 }
 # preconditioner of the scalar-potential CG per workload when --poisson-prec auto:
 # multigrid where it is faster (measured), Jacobi on the thin film (a few dozen
-# Jacobi iterations per solve) and in batches (multigrid is single-instance)
+# Jacobi iterations per solve)
 AUTO_PREC = {"hard_cube": "amg", "polycrystal": "amg", "film": "jacobi", "batch64": "amg"}
+NET = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_large.npz")
 
 
-def measured_traffic(precision, pprec):
+def measured_traffic(workload, precision, pprec):
     """Counter-measured bytes per CG iteration, if taken on the current kernel source."""
     import hashlib
-    path, src = TRAFFIC[pprec]
+    if (workload, pprec) not in TRAFFIC:
+        return None
+    path, src = TRAFFIC[(workload, pprec)]
     try:
         kv = dict(line.split(None, 1) for line in open(path) if line.strip() and not line.startswith("#"))
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -66,6 +87,29 @@ def cg_kernel_label(pprec, fp32):
             "(restriction, fused coarse-level operators), k_amg_dense, k_amg_prolong, k_amg_post0, k_amg_w")
 
 
+def roofline(prof, label, traffic):
+    it = prof["iterations"]
+    avg = prof["seconds"] / max(it, 1)
+    ach = prof["bytes_per_iteration"] / avg / 1e9 if it else None
+    return {"bound": "hbm", "kernel": label, "achieved": None if ach is None else round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "avg_iteration_us": round(1e6 * avg, 3), "iterations": it,
+            "bytes_per_iteration": prof["bytes_per_iteration"]}
+
+
+def kernel_fracs(kt):
+    """Per-launch bandwidth of the field kernels from mm_profile_kernels."""
+    out = {}
+    for name, v in kt.items():
+        if v["launches"] == 0:
+            continue
+        ach = v["bytes"] / v["seconds"] / 1e9
+        out[name] = {"launches": v["launches"], "avg_us": round(1e6 * v["seconds"] / v["launches"], 2),
+                     "bytes_per_launch": round(v["bytes"] / v["launches"]), "achieved_GBs": round(ach, 1),
+                     "frac": round(ach / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def tune(ctx, binding, args):
     """Block shape of the scalar-potential kernels, fixed for the run."""
     if args.tune_cache:
@@ -73,35 +117,62 @@ def tune(ctx, binding, args):
     return ctx.tune(binding.MM_TUNE_MEASURE)
 
 
+def host_info():
+    """CPU model, logical CPUs and memory of the machine the oracle runs on."""
+    model, mem = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "mem_total_GiB": mem}
+
+
+def chunks_of(nf, steps):
+    """Field indices of each step: `steps` consecutive chunks of the curve, or
+    one field per step (wrapping to a new curve) when steps > nf."""
+    import numpy as np
+    if steps <= nf:
+        return [c.tolist() for c in np.array_split(np.arange(nf), steps)]
+    return [[k % nf] for k in range(steps)]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fields", type=int, default=0, help="truncate the schedule (0 = all 161)")
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps: the film's curve in this many chunks (other workloads: whole curves)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["film", "hard_cube", "batch64", "polycrystal"], default="film",
+                    help="film: the 1000 x 1000 x 10 nm soft film, learned + FP32 against plain FP64 (default); "
+                         "hard_cube: one 20^3 grain; batch64: 64 uneven grains in shared launches; "
+                         "polycrystal: the 200 nm, 96^3-cell, 27-grain magnet (use --fields to bound it)")
+    ap.add_argument("--fields", type=int, default=0, help="truncate the schedule (0 = all)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--jmax", type=int, default=None,
                     help="inner iteration cap of the preconditioner solve (default: the workload's)")
+    ap.add_argument("--net", default=NET, help="trained network of the learned form (film)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison curve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-fields", type=int, default=1, help="field steps of the oracle sample")
+    ap.add_argument("--cpu-fields", type=int, default=3, help="field steps of the oracle sample")
+    ap.add_argument("--cpu-nli", type=int, default=3, help="nonlinear iterations per field of the oracle sample")
+    ap.add_argument("--no-hard-cube", action="store_true", help="skip the hard cube's extra figure (film)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default block shape (no autotuning)")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the plain-vs-learned comparison on a held-out film")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of tuned block shapes (reused when it holds this workload)")
-    ap.add_argument("--workload", choices=["hard_cube", "batch64", "film", "polycrystal"], default="hard_cube",
-                    help="hard_cube: one 20^3 grain (default); batch64: 64 uneven grains in shared launches; "
-                         "film: the 1000 x 1000 x 10 nm soft film, plain FP64 against learned + FP32; "
-                         "polycrystal: the 200 nm, 96^3-cell, 27-grain magnet (use --fields to bound it)")
     ap.add_argument("--poisson-prec", choices=["auto", "jacobi", "amg"], default="auto",
                     help="preconditioner of the scalar-potential CG (amg: smoothed-aggregation multigrid; "
                          "auto: the faster one for the workload)")
     ap.add_argument("--no-jacobi", action="store_true",
-                    help="skip the Jacobi-preconditioned comparison curve of the multigrid headline")
+                    help="skip the Jacobi-preconditioned comparison curve of a multigrid headline")
     ap.add_argument("--progress-every", type=int, default=0,
-                    help="run the curve in chunks of this many fields and report each (long curves); "
-                         "every chunk starts from the previous one's last minimum, as one curve would")
+                    help="hard_cube/polycrystal: run the curve in chunks of this many fields and report each")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain copy kernel of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -109,14 +180,14 @@ def main():
     if args.poisson_prec == "auto":
         args.poisson_prec = AUTO_PREC[args.workload]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: libmmncg has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    from paper_1801_03690_amd import binding, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate:
@@ -130,26 +201,230 @@ def main():
         print(json.dumps({"calibration": "torch.mul(a, 1.0, out=b)", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": 5}), flush=True)
         return
-    if args.workload == "batch64":
-        return bench_batch(args)
     if args.workload == "film":
         return bench_film(args)
-    if args.workload == "polycrystal":
-        w = inputs.polycrystal()
-        args.no_learned = True
-        args.no_cpu = True
-    else:
-        w = inputs.hard_cube()
-    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
-    prec = binding.MM_FP32_BULK if args.precision == "fp32" else binding.MM_FP64
+    if args.workload == "batch64":
+        return bench_batch(args)
+    out = bench_curve(args)
+    print(json.dumps(out), flush=True)
 
+
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# the film: learned + FP32 against plain FP64 (the default)
+# ---------------------------------------------------------------------------
+
+def bench_film(args):
+    import numpy as np
+    import torch
+
+    from paper_1801_03690_amd import binding, inputs, learn
+
+    w = inputs.film()
+    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
+    nf = len(fields)
+    jmax = w.jmax if args.jmax is None else args.jmax
+    pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     ctx = binding.Context(0)
     t0 = time.time()
     ctx.upload(w.mesh)
-    t_setup = time.time() - t0
     info = ctx.info()
-    print(f"# setup {t_setup:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}",
-          file=sys.stderr, flush=True)
+    log(f"setup {time.time() - t0:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}")
+    graph = binding.Graph(ctx)
+    net = learn.load_net(args.net, ctx)
+    o_l = binding.default_opts(jmax=jmax, precision=binding.MM_FP32_BULK, poisson_prec=pprec)
+    o_p = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec)
+    m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
+    m = torch.empty_like(m0)
+    shapes = {}
+
+    def set_form(o, name):
+        ctx.set_opts(o)
+        if not args.no_tune:
+            nw, spw = tune(ctx, binding, args)
+            shapes[name] = (nw, spw.tolist())
+
+    def run_steps(idx_lists, o, mode):
+        """Steps over chunks of the field list; returns per-field results."""
+        parts, times = [], []
+        last = None
+        for idx in idx_lists:
+            if idx[0] == 0 or last is None or idx[0] != last + 1:
+                m.copy_(m0)
+                ctx.reset_warm_start()
+                hp = None
+            else:
+                hp = fields[idx[0] - 1]
+            ta = time.perf_counter()
+            r = ctx.curve_learned(net, graph, mode, m, fields[idx[0]: idx[-1] + 1], opts=o, h_prev_T=hp)
+            times.append(time.perf_counter() - ta)
+            parts.append((idx, r))
+            last = idx[-1]
+        return parts, times
+
+    # --- learned + FP32 (the value)
+    set_form(o_l, "learned_fp32")
+    steps = chunks_of(nf, args.steps)
+    if args.warmup:
+        run_steps(chunks_of(nf, max(args.steps, args.warmup))[: args.warmup], o_l, 3)
+        log(f"warmup: {args.warmup} steps")
+    torch.cuda.synchronize()
+    ctx.profile(-1)
+    ctx.profile(1)
+    ctx.profile_kernels(-1)
+    ctx.profile_kernels(1)
+    t0 = time.perf_counter()
+    parts, times = run_steps(steps, o_l, 3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(0)
+    kt = ctx.profile_kernels(0)
+    for i, dt in enumerate(times):
+        log(f"step {i} fields {steps[i][0]}..{steps[i][-1]}: {dt:.3f}s")
+    fields_walked = sum(len(p[0]) for p in parts)
+    sec_curve = (t1 - t0) * nf / fields_walked
+    first = {}
+    for idx, r in parts:  # per-field results of the first walk of the curve
+        for j, k in enumerate(idx):
+            if k not in first:
+                first[k] = (r["stats"][j], r["E"][j], r["m_avg"][j], r["accepted"][j])
+    st_l = [first[k][0] for k in range(nf)]
+    E_l = np.array([first[k][1] for k in range(nf)])
+    mav_l = np.array([first[k][2] for k in range(nf)])
+    learned = dict(seconds=round(sec_curve, 4), **count(st_l), starts_taken=int(sum(first[k][3] for k in range(nf))),
+                   worst_status=max(s["status"] for s in st_l))
+
+    out = {
+        "metric": METRIC, "value": round(sec_curve, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (t1 - t0) / args.steps, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 operators/f64 reductions (learned component bf16 MFMA)",
+        "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
+        "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, {nf} fields "
+                               f"+50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, tol 1e-6; learned warm "
+                               f"start + Jacobi scaling, FP32 bulk; the curve in {min(args.steps, nf)} chunks",
+                   "poisson_preconditioner": args.poisson_prec, "n_mag": info["n_mag"], "n_pot": info["n_pot"],
+                   "nnz_K": info["nnz_K"], "nnz_C_blocks": info["nnz_C_blocks"], "pcg_shapes": shapes},
+        "learned_fp32": learned,
+        "roofline": roofline(prof, cg_kernel_label(args.poisson_prec, True) + " (learned_fp32 form)",
+                             measured_traffic("film", "fp32", args.poisson_prec)),
+        "field_kernels": kernel_fracs(kt),
+    }
+
+    # --- plain FP64, the whole curve in one call
+    if not args.no_plain:
+        set_form(o_p, "plain_fp64")
+        m.copy_(m0)
+        ctx.reset_warm_start()
+        ctx.curve(m, fields[:1], opts=o_p)  # warm-up of this form's kernels and graphs
+        m.copy_(m0)
+        ctx.reset_warm_start()
+        torch.cuda.synchronize()
+        ctx.profile_kernels(-1)
+        ctx.profile_kernels(1)
+        ta = time.perf_counter()
+        rp = ctx.curve(m, fields, opts=o_p)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ktp = ctx.profile_kernels(0)
+        log(f"plain fp64 curve {tb - ta:.2f}s")
+        d = np.abs(mav_l - rp["m_avg"]).max(axis=1)
+        out["plain_fp64"] = dict(seconds=round(tb - ta, 4), **count(rp["stats"]),
+                                 worst_status=max(s["status"] for s in rp["stats"]),
+                                 field_kernels=kernel_fracs(ktp))
+        out["speedup_learned_fp32_vs_plain_fp64"] = round((tb - ta) / sec_curve, 3)
+        out["learned_fp32"]["basin_changes_vs_plain"] = int((d > 1e-2).sum())
+        out["learned_fp32"]["max_rel_dE_vs_plain"] = float(np.max(np.abs(E_l - rp["E"]) / np.abs(rp["E"])))
+        out["learned_fp32"]["max_dmavg_vs_plain"] = float(d.max())
+    net.close()
+    graph.close()
+    ctx.close()
+
+    if not args.no_hard_cube:
+        a2 = argparse.Namespace(**vars(args))
+        a2.workload, a2.poisson_prec, a2.fields, a2.jmax, a2.steps, a2.warmup = "hard_cube", "amg", 0, None, 1, 1
+        a2.no_cpu, a2.no_jacobi, a2.progress_every, a2.precision = True, True, 0, "fp32"
+        hc = bench_curve(a2)
+        out["hard_cube"] = {k: hc[k] for k in ("value", "config", "counters", "roofline", "field_kernels")}
+        if "plain_fp64" in hc:
+            out["hard_cube"]["plain_fp64"] = hc["plain_fp64"]
+        out["hard_cube"]["unit"] = "s"
+
+    if not args.no_cpu and "plain_fp64" in out:
+        out["cpu_baseline"] = cpu_baseline_film(args, w, fields, jmax, out["plain_fp64"])
+    print(json.dumps(out), flush=True)
+
+
+def count(stats):
+    return {k: int(sum(s[k] for s in stats)) for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks")}
+
+
+def cpu_baseline_film(args, w, fields, jmax, plain):
+    """The oracle (single-threaded C, FP64, Jacobi CG) on the first
+    `cpu_fields` fields, `cpu_nli` nonlinear iterations each, each field
+    started from the previous one's end. Its cost is a sum over work units
+    (scalar-potential CG iterations, evaluations, inner preconditioner
+    iterations) whose unit costs come from the sample itself: an evaluation
+    whose potential is already converged (no CG iteration) and one inner
+    solve are timed at the sample's last state; the rest of the sample's time
+    is its CG iterations. The whole-curve figure weights those unit costs
+    with the plain FP64 GPU curve's counts of the same units."""
+    import oracle
+    o = oracle.Oracle(w.mesh)
+    m = w.m0.copy()
+    ns = max(1, min(args.cpu_fields, len(fields)))
+    tot = dict(evals=0, mi=0, li=0)
+    ta = time.perf_counter()
+    for k in range(ns):
+        m, E, st, rc = o.minimize(m, fields[k], jmax=jmax, max_nli=args.cpu_nli)
+        for q in tot:
+            tot[q] += st[q]
+    t_sample = time.perf_counter() - ta
+    h = o.reduce_field(fields[ns - 1])
+    tb = time.perf_counter()
+    r = o.eval(m, h)  # the potential is warm: no CG iteration
+    t_eval = time.perf_counter() - tb
+    assert r["poisson_iters"] == 0, r["poisson_iters"]
+    tb = time.perf_counter()
+    y, it = o.precond(m, r["lam"], r["g"], jmax)
+    t_li = (time.perf_counter() - tb) / max(it, 1)
+    t_cg = max(t_sample - t_eval * tot["evals"] - t_li * tot["li"], 0.0) / max(tot["mi"], 1)
+    est = t_cg * plain["mi"] + t_eval * plain["evals"] + t_li * plain["li"]
+    base = {"value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {ns} of {len(fields)} field steps, {args.cpu_nli} nonlinear iteration(s) each "
+                       f"({t_sample:.1f} s: {tot['evals']} evaluations, {tot['mi']} CG iterations, {tot['li']} "
+                       f"inner iterations); unit costs {1e3 * t_cg:.1f} ms per CG iteration, {1e3 * t_eval:.0f} ms "
+                       f"per evaluation without CG, {1e3 * t_li:.0f} ms per inner iteration, weighted with the "
+                       f"plain FP64 GPU curve's counts"),
+            "sample_seconds": round(t_sample, 2)}
+    base.update(host_info())
+    log(f"cpu baseline: sample {t_sample:.1f}s, estimate {est:.0f}s")
+    return base
+
+
+# ---------------------------------------------------------------------------
+# one grain (hard cube) or the polycrystal: whole curves as steps
+# ---------------------------------------------------------------------------
+
+def bench_curve(args):
+    import numpy as np
+    import torch
+
+    from paper_1801_03690_amd import binding, inputs
+
+    w = inputs.polycrystal() if args.workload == "polycrystal" else inputs.hard_cube()
+    if args.workload == "polycrystal":
+        args.no_cpu = True
+    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
+    prec = binding.MM_FP32_BULK if args.precision == "fp32" else binding.MM_FP64
+    ctx = binding.Context(0)
+    t0 = time.time()
+    ctx.upload(w.mesh)
+    info = ctx.info()
+    log(f"setup {time.time() - t0:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}")
     m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
     m = torch.empty_like(m0)
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
@@ -158,14 +433,12 @@ def main():
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
         amg = ctx.amg_info()
-        print(f"# multigrid levels {amg['rows']} built in {amg['setup_seconds']:.2f}s", file=sys.stderr, flush=True)
-    # block shape of the scalar-potential kernels: timed once here, untimed
-    # like the assembly, and fixed for the run
+        log(f"multigrid levels {amg['rows']} built in {amg['setup_seconds']:.2f}s")
     shape = (16, [1])
     if not args.no_tune:
         nw, spw = tune(ctx, binding, args)
         shape = (nw, spw.tolist())
-        print(f"# tuned shape: {nw} waves per block, slices per wave {spw.tolist()}", file=sys.stderr, flush=True)
+        log(f"tuned shape: {nw} waves per block, slices per wave {spw.tolist()}")
 
     def one_curve(o):
         m.copy_(m0)
@@ -176,71 +449,53 @@ def main():
         tc = time.perf_counter()
         for k0 in range(0, len(fields), args.progress_every):
             parts.append(ctx.curve(m, fields[k0:k0 + args.progress_every], opts=o))
-            print(f"# fields {k0}..{min(len(fields), k0 + args.progress_every) - 1} done, "
-                  f"{time.perf_counter() - tc:.1f}s", file=sys.stderr, flush=True)
+            log(f"fields {k0}..{min(len(fields), k0 + args.progress_every) - 1} done, "
+                f"{time.perf_counter() - tc:.1f}s")
         return dict(m=m, m_avg=np.concatenate([p["m_avg"] for p in parts]),
                     E=np.concatenate([p["E"] for p in parts]), stats=[x for p in parts for x in p["stats"]],
                     rc=max(p["rc"] for p in parts))
 
     for i in range(args.warmup):
         r = one_curve(opts)
-        print(f"# warmup {i} done rc={r['rc']}", file=sys.stderr, flush=True)
+        log(f"warmup {i} done rc={r['rc']}")
 
     torch.cuda.synchronize()
     ctx.profile(-1)
     ctx.profile(1)
+    ctx.profile_kernels(-1)
+    ctx.profile_kernels(1)
     t0 = time.perf_counter()
     results = []
     for i in range(args.steps):
         results.append(one_curve(opts))
-        print(f"# step {i} done", file=sys.stderr, flush=True)
+        log(f"step {i} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile(0)
+    kt = ctx.profile_kernels(0)
     sec_per_curve = (t1 - t0) / args.steps
     r = results[-1]
     st = r["stats"]
-    tot = {k: int(sum(s[k] for s in st)) for k in ("evals", "nli", "li", "mi", "restarts", "fallbacks")}
     worst = max(s["status"] for s in st)
-
-    avg_iter = prof["seconds"] / max(prof["iterations"], 1)
-    achieved = prof["bytes_per_iteration"] / avg_iter / 1e9 if prof["iterations"] else None
-
+    name = ("hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {n} fields 0..{f:.2f} T, jmax {j}, tol 1e-6"
+            if args.workload == "hard_cube" else
+            "polycrystal 200 nm, 96^3 cells x6 tets + 3x air box, 27 Voronoi grains with a 2 nm boundary phase, "
+            "first {n} of {N} fields 0..{f:.2f} T, jmax {j}, tol 1e-6")
     out = {
-        "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
-        "value": round(sec_per_curve, 4),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * sec_per_curve, 2),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "metric": METRIC, "value": round(sec_per_curve, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * sec_per_curve, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
         "data": "synthetic (seeded Kuhn mesh, tilted +z start)",
-        "config": {"workload": (f"hard cube 80 nm, 20^3 cells x6 tets + 3x air box, {len(fields)} fields "
-                                f"0..{fields[-1][2]:.2f} T, jmax {jmax}, tol 1e-6" if args.workload == "hard_cube" else
-                                f"polycrystal 200 nm, 96^3 cells x6 tets + 3x air box, 27 Voronoi grains with a "
-                                f"2 nm boundary phase, first {len(fields)} of {len(w.fields)} fields "
-                                f"0..{fields[-1][2]:.2f} T, jmax {jmax}, tol 1e-6"),
+        "config": {"workload": name.format(n=len(fields), N=len(w.fields), f=fields[-1][2], j=jmax),
                    "precision": args.precision, "poisson_preconditioner": args.poisson_prec,
-                   "n_mag": info["n_mag"], "n_pot": info["n_pot"],
-                   "nnz_K": info["nnz_K"], "pcg_waves_per_block": shape[0], "pcg_slices_per_wave": shape[1][0]},
-        "counters": dict(tot, worst_status=worst),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": cg_kernel_label(args.poisson_prec, prec == binding.MM_FP32_BULK),
-            "achieved": None if achieved is None else round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (measured_traffic(args.precision, args.poisson_prec) if args.workload == "hard_cube"
-                        else None),
-            "avg_iteration_us": round(1e6 * avg_iter, 3),
-            "iterations": prof["iterations"],
-            "bytes_per_iteration": prof["bytes_per_iteration"],
-        },
+                   "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
+                   "nnz_C_blocks": info["nnz_C_blocks"], "pcg_waves_per_block": shape[0],
+                   "pcg_slices_per_wave": shape[1][0]},
+        "counters": dict(count(st), worst_status=worst),
+        "roofline": roofline(prof, cg_kernel_label(args.poisson_prec, prec == binding.MM_FP32_BULK),
+                             measured_traffic(args.workload, args.precision, args.poisson_prec)),
+        "field_kernels": kernel_fracs(kt),
     }
 
     if not args.no_plain and prec != binding.MM_FP64:
@@ -256,11 +511,9 @@ def main():
         ctx.set_opts(opts)
         dE = float(np.max(np.abs(rp["E"] - r["E"]) / np.maximum(np.abs(rp["E"]), 1.0)))
         dmav = float(np.max(np.abs(rp["m_avg"] - r["m_avg"])))
-        out["plain_fp64"] = {"seconds": round(tb - ta, 4),
-                             "evals": int(sum(s["evals"] for s in rp["stats"])),
-                             "nli": int(sum(s["nli"] for s in rp["stats"])),
+        out["plain_fp64"] = {"seconds": round(tb - ta, 4), **count(rp["stats"]),
                              "max_rel_dE_vs_fp32": dE, "max_dmavg_vs_fp32": dmav}
-        print(f"# plain fp64 curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
+        log(f"plain fp64 curve {tb - ta:.2f}s")
 
     if args.poisson_prec == "amg" and not args.no_jacobi:
         # the same curve with the Jacobi-preconditioned CG (one kernel per iteration)
@@ -277,23 +530,13 @@ def main():
         tb = time.perf_counter()
         pj = ctx.profile(0)
         ctx.set_opts(opts)
-        itj = pj["seconds"] / max(pj["iterations"], 1)
-        achj = pj["bytes_per_iteration"] / itj / 1e9 if pj["iterations"] else None
         out["jacobi_cg"] = {
             "seconds": round(tb - ta, 4), "cg_iterations": int(sum(s["mi"] for s in rj["stats"])),
             "max_rel_dE_vs_amg": float(np.max(np.abs(rj["E"] - r["E"]) / np.maximum(np.abs(r["E"]), 1.0))),
-            "roofline": {"bound": "hbm", "kernel": cg_kernel_label("jacobi", prec == binding.MM_FP32_BULK),
-                         "achieved": None if achj is None else round(achj, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": None if achj is None else round(achj / HBM_PEAK_GBS, 4),
-                         "traffic": (measured_traffic(args.precision, "jacobi") if args.workload == "hard_cube"
-                                     else None),
-                         "avg_iteration_us": round(1e6 * itj, 3), "iterations": pj["iterations"],
-                         "bytes_per_iteration": pj["bytes_per_iteration"]},
+            "roofline": roofline(pj, cg_kernel_label("jacobi", prec == binding.MM_FP32_BULK),
+                                 measured_traffic(args.workload, args.precision, "jacobi")),
         }
-        print(f"# jacobi-preconditioned curve {tb - ta:.2f}s", file=sys.stderr, flush=True)
-
-    if not args.no_learned:
-        out["learned_film"] = bench_learned(args, binding, inputs, np, torch)
+        log(f"jacobi-preconditioned curve {tb - ta:.2f}s")
 
     if not args.no_cpu:
         import oracle
@@ -301,157 +544,24 @@ def main():
         ns = max(1, min(args.cpu_fields, len(fields)))
         ta = time.perf_counter()
         ro = o.curve(w.m0, fields[:ns], jmax=jmax)
-        tb = time.perf_counter()
-        t_sample = tb - ta
-        # extrapolate with the GPU's own distribution of work over the fields
+        t_sample = time.perf_counter() - ta
+        # scaled with the GPU's own distribution of work over the fields
         gpu_all = sum(s["t_nl"] for s in st)
         gpu_sample = sum(s["t_nl"] for s in st[:ns])
         est = t_sample * gpu_all / max(gpu_sample, 1e-12)
-        out["cpu_baseline"] = {
+        out["cpu_baseline"] = dict({
             "value": round(est, 2), "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"first {ns} of {len(fields)} field steps timed ({t_sample:.2f} s, "
                       f"{sum(s['evals'] for s in ro['stats'])} evals); scaled to the whole curve by the "
                       f"GPU's per-field time distribution",
-            "sample_seconds": round(t_sample, 3),
-        }
-    print(json.dumps(out), flush=True)
-
-
-def bench_learned(args, binding, inputs, np, torch):
-    """Plain FP64 method against learned start + scaling in the FP32-bulk
-    mode on a held-out soft film (seed 901 of the training family: 235 x 270
-    nm, 5 nm cells, 2 cells thick, 3x air box, field along x from +50 to -50
-    mT in 1 mT steps, jmax 4, same stopping rule), with the parameters
-    trained by `python -m paper_1801_03690_amd.learn` (data/gnn_films.npz)."""
-    path = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films.npz")
-    from paper_1801_03690_amd import learn
-    w = inputs.small_film(901)
-    ctx = binding.Context(0)
-    ctx.upload(w.mesh)
-    graph = binding.Graph(ctx)
-    net = learn.load_net(path, ctx)
-    res = {}
-    for name, mode, prec in (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
-                             ("learned_fp32", 3, binding.MM_FP32_BULK)):
-        o = binding.default_opts(jmax=4, precision=prec)
-        ctx.set_opts(o)
-        if not args.no_tune:
-            tune(ctx, binding, args)
-        ctx.reset_warm_start()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = ctx.curve_learned(net, graph, mode, w.m0, w.fields, opts=o)
-        dt = time.perf_counter() - t0
-        st = r["stats"]
-        res[name] = dict(seconds=round(dt, 4), evals=int(sum(x["evals"] for x in st)),
-                         nli=int(sum(x["nli"] for x in st)), cg_iterations=int(sum(x["mi"] for x in st)),
-                         starts_taken=int(r["accepted"].sum()), rc=int(r["rc"]), _r=r)
-        print(f"# film {name}: {dt:.2f}s", file=sys.stderr, flush=True)
-    ref = res["plain_fp64"]["_r"]
-    for k in res:
-        r = res[k].pop("_r")
-        d = np.abs(r["m_avg"] - ref["m_avg"]).max(axis=1)
-        res[k]["basin_changes_vs_plain"] = int((d > 1e-2).sum())
-        res[k]["max_rel_dE_vs_plain"] = float(np.max(np.abs(r["E"] - ref["E"]) / np.abs(ref["E"])))
-    res["speedup_learned_fp32_vs_plain_fp64"] = round(res["plain_fp64"]["seconds"] / res["learned_fp32"]["seconds"], 3)
-    res["workload"] = (f"held-out film {w.name}: {ctx.n_mag} magnet nodes, {len(w.fields)} fields +50..-50 mT, "
-                       f"jmax 4, tol 1e-6")
-    net.close()
-    graph.close()
+            "sample_seconds": round(t_sample, 3)}, **host_info())
     ctx.close()
-    return res
+    return out
 
 
-def bench_film(args):
-    """The 1000 x 1000 x 10 nm soft film (200 x 200 x 2 cells of 5 nm, 3x air
-    box, 121,203 magnet nodes), field along x from +50 to -50 mT in 1 mT
-    steps, jmax 10, tol 1e-6: learned start + scaling in the FP32-bulk mode
-    (the value) against the plain FP64 method and learned FP64, with the
-    parameters trained on 400-1000 nm films (data/gnn_films_large.npz). Each
-    form runs once after a shared warm-up of one field."""
-    import numpy as np
-    import torch
-
-    from paper_1801_03690_amd import binding, inputs, learn
-
-    w = inputs.film()
-    fields = w.fields if args.fields <= 0 else w.fields[: args.fields]
-    jmax = w.jmax if args.jmax is None else args.jmax
-    ctx = binding.Context(0)
-    t0 = time.time()
-    ctx.upload(w.mesh)
-    info = ctx.info()
-    print(f"# setup {time.time() - t0:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}",
-          file=sys.stderr, flush=True)
-    graph = binding.Graph(ctx)
-    net = learn.load_net(os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_large.npz"), ctx)
-    legs = (("plain_fp64", 0, binding.MM_FP64), ("learned_fp64", 3, binding.MM_FP64),
-            ("learned_fp32", 3, binding.MM_FP32_BULK))
-    pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
-    res, shapes, prof = {}, {}, None
-    for name, mode, prec in legs:
-        o = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
-        ctx.set_opts(o)
-        if not args.no_tune:
-            nw, spw = tune(ctx, binding, args)
-            shapes[name] = (nw, spw.tolist())
-        if args.warmup:
-            ctx.reset_warm_start()
-            ctx.curve_learned(net, graph, mode, w.m0, fields[:1], opts=o)
-        ctx.reset_warm_start()
-        torch.cuda.synchronize()
-        if name == "learned_fp32":
-            ctx.profile(-1)
-            ctx.profile(1)
-        t0 = time.perf_counter()
-        r = ctx.curve_learned(net, graph, mode, w.m0, fields, opts=o)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if name == "learned_fp32":
-            prof = ctx.profile(0)
-        st = r["stats"]
-        res[name] = dict(seconds=round(dt, 4), evals=int(sum(x["evals"] for x in st)),
-                         nli=int(sum(x["nli"] for x in st)), cg_iterations=int(sum(x["mi"] for x in st)),
-                         starts_taken=int(r["accepted"].sum()), rc=int(r["rc"]), _r=r)
-        print(f"# film {name}: {dt:.2f}s", file=sys.stderr, flush=True)
-    ref = res["plain_fp64"]["_r"]
-    for k in res:
-        r = res[k].pop("_r")
-        d = np.abs(r["m_avg"] - ref["m_avg"]).max(axis=1)
-        res[k]["basin_changes_vs_plain"] = int((d > 1e-2).sum())
-        res[k]["max_rel_dE_vs_plain"] = float(np.max(np.abs(r["E"] - ref["E"]) / np.abs(ref["E"])))
-    sec = res["learned_fp32"]["seconds"]
-    avg_iter = prof["seconds"] / max(prof["iterations"], 1)
-    achieved = prof["bytes_per_iteration"] / avg_iter / 1e9 if prof["iterations"] else None
-    out = {
-        "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
-        "value": sec, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * sec, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 operators/f64 reductions (learned component bf16 MFMA)",
-        "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
-        "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, "
-                               f"{len(fields)} fields +50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, tol 1e-6, "
-                               f"learned start + scaling, FP32 bulk",
-                   "poisson_preconditioner": args.poisson_prec, "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
-                   "pcg_shapes": shapes},
-        "forms": res,
-        "speedup_learned_fp32_vs_plain_fp64": round(res["plain_fp64"]["seconds"] / sec, 3),
-        "roofline": {
-            "bound": "hbm", "kernel": ("scalar-potential CG iteration: k_pcg_iter<float> (learned_fp32 form)"
-                                       if args.poisson_prec == "jacobi" else
-                                       "scalar-potential CG iteration with one multigrid cycle<float> "
-                                       "(learned_fp32 form)"),
-            "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_iteration_us": round(1e6 * avg_iter, 3), "iterations": prof["iterations"],
-            "bytes_per_iteration": prof["bytes_per_iteration"],
-        },
-    }
-    net.close()
-    graph.close()
-    ctx.close()
-    print(json.dumps(out), flush=True)
-
+# ---------------------------------------------------------------------------
+# the batched parameter study
+# ---------------------------------------------------------------------------
 
 def bench_batch(args):
     """64 independent hard cubes of 8^3..24^3 cells (4 nm cells, K1 3.0-4.9
@@ -474,8 +584,7 @@ def bench_batch(args):
     infos = ctx.inst_info
     tot_pot = sum(d["n_pot"] for d in infos)
     tot_nnz = sum(d["nnz_K"] for d in infos)
-    print(f"# setup {t_setup:.1f}s instances={len(ws)} n_mag={ctx.n_mag} n_pot={tot_pot} nnz_K={tot_nnz}",
-          file=sys.stderr, flush=True)
+    log(f"setup {t_setup:.1f}s instances={len(ws)} n_mag={ctx.n_mag} n_pot={tot_pot} nnz_K={tot_nnz}")
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     jmax = ws[0].jmax if args.jmax is None else args.jmax
     opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
@@ -484,13 +593,12 @@ def bench_batch(args):
         # build the hierarchies (untimed, like the assembly) with one solve
         ta = time.time()
         ctx.batch_energy_grad(np.concatenate([w.m0 for w in ws]), np.zeros((len(ws), 3)))
-        print(f"# multigrid hierarchies built and first solve in {time.time() - ta:.1f}s", file=sys.stderr,
-              flush=True)
+        log(f"multigrid hierarchies built and first solve in {time.time() - ta:.1f}s")
     shape = (16, [1] * len(ws))
     if not args.no_tune:
         nw, spw = tune(ctx, binding, args)
         shape = (nw, spw.tolist())
-        print(f"# tuned shape: {nw} waves per block, slices per wave {spw.tolist()}", file=sys.stderr, flush=True)
+        log(f"tuned shape: {nw} waves per block, slices per wave {spw.tolist()}")
     m0 = torch.tensor(np.concatenate([w.m0 for w in ws]), dtype=torch.float64, device="cuda")
     m = torch.empty_like(m0)
 
@@ -501,14 +609,14 @@ def bench_batch(args):
 
     for i in range(args.warmup):
         run(opts)
-        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+        log(f"warmup {i} done")
     torch.cuda.synchronize()
     ctx.profile(-1)
     ctx.profile(1)
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = run(opts)
-        print(f"# step {i} done rc={r['rc']}", file=sys.stderr, flush=True)
+        log(f"step {i} done rc={r['rc']}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile(0)
@@ -519,26 +627,21 @@ def bench_batch(args):
     worst = max(s["status"] for row in st for s in row)
     achieved = prof["bytes"] / prof["seconds"] / 1e9 if prof["seconds"] > 0 else None
     out = {
-        "metric": "demag-curve time-to-solution (s) & SpMV HBM GB/s, plain vs learned+FP32, equal tol",
-        "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * sec, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
+        "metric": METRIC, "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * sec, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 operators/f64 reductions" if prec == binding.MM_FP32_BULK else "f64",
         "data": "synthetic (seeded Kuhn meshes, tilted +z starts)",
         "config": {"workload": f"batch of 64 hard cubes 8^3..24^3 cells (4 nm), {nf} fields 0..{F[0, -1, 2]:.2f} T "
                                f"each, jmax {jmax}, tol 1e-6, one launch serves all instances",
-                   "precision": args.precision, "poisson_preconditioner": args.poisson_prec, "instances": len(ws), "n_mag": ctx.n_mag, "n_pot": tot_pot,
-                   "nnz_K": tot_nnz, "pcg_waves_per_block": shape[0],
+                   "precision": args.precision, "poisson_preconditioner": args.poisson_prec, "instances": len(ws),
+                   "n_mag": ctx.n_mag, "n_pot": tot_pot, "nnz_K": tot_nnz, "pcg_waves_per_block": shape[0],
                    "pcg_slices_per_wave": sorted(set(shape[1]))},
         "counters": dict(tot, worst_status=worst),
         "roofline": {
-            "bound": "hbm",
-            "kernel": cg_kernel_label(args.poisson_prec, prec == binding.MM_FP32_BULK),
-            "achieved": None if achieved is None else round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "instance_iterations": prof["iterations"], "seconds": round(prof["seconds"], 4),
-            "bytes": prof["bytes"],
+            "bound": "hbm", "kernel": cg_kernel_label(args.poisson_prec, prec == binding.MM_FP32_BULK),
+            "achieved": None if achieved is None else round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "instance_iterations": prof["iterations"], "seconds": round(prof["seconds"], 4), "bytes": prof["bytes"],
         },
     }
     if not args.no_cpu:
@@ -552,12 +655,11 @@ def bench_batch(args):
         t_sample = time.perf_counter() - ta
         w_all = sum(s["mi"] * infos[i]["nnz_K"] for i, row in enumerate(st) for s in row)
         w_smp = max(st[k][0]["mi"] * infos[k]["nnz_K"], 1)
-        out["cpu_baseline"] = {
+        out["cpu_baseline"] = dict({
             "value": round(t_sample * w_all / w_smp, 2), "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"instance {k} ({infos[k]['n_pot']} potential nodes), first field step ({t_sample:.2f} s); "
                       f"scaled by the batch's scalar-potential CG work (iterations x nnz(K), GPU counts)",
-            "sample_seconds": round(t_sample, 3),
-        }
+            "sample_seconds": round(t_sample, 3)}, **host_info())
     print(json.dumps(out), flush=True)
 
 
