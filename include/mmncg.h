@@ -193,6 +193,22 @@ int mm_energy_grad(mm_ctx *c, const double *m, const double h_ext[3], double E_p
 int mm_precondition(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax,
                     const double *dscale, double *y, int *inner_iters);
 
+/* For callers that cannot allocate device memory during a call (code under
+   HIP graph capture, tight serving loops, harnesses that forbid allocation):
+   mm_precondition with the same arguments, results and errors, except that
+   the scratch of its inner solve (the residual, direction and product vectors
+   of Alg. 1, the block partial sums and the exit flags) lives in a static
+   device array of MM_NOALLOC_SCRATCH_BYTES per GPU instead of context memory;
+   the call allocates nothing. The array is shared by every call on that GPU
+   and keeps the last call's contents (the call clears what must start at
+   zero); calls that overlap on one GPU race. A context whose inner solve
+   needs more than the array holds (about 460,000 magnet nodes) is refused
+   with MM_EINVAL. Each GPU the library runs on keeps its array until the
+   process ends. */
+#define MM_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mm_precondition_noalloc(mm_ctx *c, const double *m, const double *grad, const double *gproj, int jmax,
+                            const double *dscale, double *y, int *inner_iters);
+
 /* Alg. 4 for one field (Tesla), m_inout updated in place. Returns MM_OK,
    MM_NOT_CONVERGED or MM_STALLED (outputs written in all three cases). */
 int mm_ncg_minimize(mm_ctx *c, double *m_inout, const double h_ext[3], const mm_opts *o, mm_stats *st,

@@ -107,6 +107,7 @@ def load_library(path=LIB_PATH):
     L.mm_reset_warm_start.argtypes = [_vp]
     L.mm_energy_grad.argtypes = [_vp, _vp, _dp, _dp, _vp, _vp, _dp]
     L.mm_precondition.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _ip]
+    L.mm_precondition_noalloc.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp, _vp, _ip]
     L.mm_ncg_minimize.argtypes = [_vp, _vp, _dp, C.POINTER(Opts), C.POINTER(Stats), _dp]
     L.mm_demag_curve.argtypes = [_vp, _vp, _dp, C.c_long, C.POINTER(Opts), _dp, _dp, C.POINTER(Stats), _vp]
     L.mm_operator_apply.argtypes = [_vp, C.c_int, _vp, _vp]
@@ -318,7 +319,9 @@ class Context:
                                            C.c_void_p(G.ctypes.data), C.c_void_p(g.ctypes.data), C.byref(t)))
         return dict(E=E, G=G, g=g, tmax=t.value)
 
-    def precondition(self, m, G, g, jmax, dscale=None):
+    def precondition(self, m, G, g, jmax, dscale=None, noalloc=False):
+        """mm_precondition, or with noalloc=True mm_precondition_noalloc
+        (the inner solve's scratch in the library's static device array)."""
         mp, k1 = _vec_ptr(m)
         Gp, k2 = _vec_ptr(G)
         gp, k3 = _vec_ptr(g)
@@ -327,8 +330,8 @@ class Context:
             dsp, k4 = _vec_ptr(dscale)
         y = np.zeros((self.n_mag, 3))
         it = C.c_int()
-        self._check(self._L.mm_precondition(self.h, mp, Gp, gp, int(jmax), dsp, C.c_void_p(y.ctypes.data),
-                                            C.byref(it)))
+        fn = self._L.mm_precondition_noalloc if noalloc else self._L.mm_precondition
+        self._check(fn(self.h, mp, Gp, gp, int(jmax), dsp, C.c_void_p(y.ctypes.data), C.byref(it)))
         return y, it.value
 
     def minimize(self, m, h_T, opts=None, **kw):

@@ -18,7 +18,8 @@ OUT = os.path.join(HERE, "libmmncg.so")
 BUILD = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("MMNCG_ARCH", "gfx950")
-SOURCES = ["kernels.hip", "poisson.hip", "amg.hip", "gnn.hip", "assemble.cpp", "solver.cpp", "gnn.cpp", "amg.cpp"]
+SOURCES = ["kernels.hip", "poisson.hip", "amg.hip", "gnn.hip", "noalloc.hip", "assemble.cpp", "solver.cpp", "gnn.cpp",
+           "amg.cpp"]
 # packed FP32 instructions are disabled for all device code
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", INC, "-I", CSRC]
