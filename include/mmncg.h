@@ -474,6 +474,39 @@ int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, c
 /* One Adam step (bias-corrected) with the last gradient. */
 int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps);
 
+/* Training on the solver's own trajectories: `epochs` passes over n_samples
+   samples, each pass in an order shuffled by SplitMix64 from `seed` (the same
+   seed gives the same order and the same parameters), every sample one
+   mm_gnn_loss_grad (graph[k], X[k], m[k], dm_target[k], s_target[k],
+   inv_dm2[k], w_s) and one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8).
+   The per-sample arrays are device pointers (n x 32 floats, n x 3 and n
+   doubles of that sample's graph); graphs may repeat. epoch_loss (epochs
+   doubles, may be NULL) receives the mean loss of each pass. */
+int mm_gnn_train(mm_gnn *g, long n_samples, mm_graph *const *graph, const float *const *X, const double *const *m,
+                 const double *const *dm_target, const double *const *s_target, const double *inv_dm2, double w_s,
+                 int epochs, double lr, unsigned long long seed, double *epoch_loss);
+
+/* The network's parameters (FP32 masters) and input standardization written
+   to / read from a file of this library's own format (a 24-byte header: magic,
+   parameter count, feature count; then the parameters, the 32 means and the
+   32 spreads as little-endian floats). mm_gnn_load checks the header and that
+   every value is finite (spreads > 0), and clears the Adam state. */
+int mm_gnn_save(mm_gnn *g, const char *path);
+int mm_gnn_load(mm_gnn *g, const char *path);
+
+/* Training targets of one field step k -> k+1 at the graph's magnet nodes
+   (host or device vectors): dm_target = the step m_next - m projected on the
+   tangent plane of m (n x 3), and s_target = 1 + t / D (n) with D the
+   exchange diagonal (mm_jacobi_diag) and t the mean over the two directions
+   normal to m of the magnetostatic Hessian's diagonal diag3 (n x 3, e.g. from
+   mm_demag_diag): t = (sum_c diag3_c - sum_c m_c^2 diag3_c) / 2. */
+int mm_gnn_targets(mm_graph *graph, const double *m, const double *m_next, const double *diag3, double *dm_target,
+                   double *s_target);
+
+/* Column sums and sums of squares (FP64, 32 each, host) of node features X
+   (n x 32 floats, host or device): the input standardization's statistics. */
+int mm_gnn_moments(mm_graph *graph, const float *X, double *sum, double *sumsq);
+
 /* Exchange diagonal D (n_mag): the Jacobi preconditioner of Alg. 1 inside
    mm_precondition (before any dscale). */
 int mm_jacobi_diag(mm_ctx *c, double *D);

@@ -137,6 +137,12 @@ def load_library(path=LIB_PATH):
     L.mm_gnn_features.argtypes = [_vp, _vp, _dp, _dp, _vp]
     L.mm_gnn_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.mm_gnn_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_double, _dp, _vp]
+    L.mm_gnn_train.argtypes = [_vp, C.c_long, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                               C.POINTER(_vp), _dp, C.c_double, C.c_int, C.c_double, C.c_ulonglong, _dp]
+    L.mm_gnn_save.argtypes = [_vp, C.c_char_p]
+    L.mm_gnn_load.argtypes = [_vp, C.c_char_p]
+    L.mm_gnn_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.mm_gnn_moments.argtypes = [_vp, _vp, _dp, _dp]
     L.mm_gnn_adam.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double]
     L.mm_gnn_set_precision.argtypes = [_vp, C.c_int]
     L.mm_demag_diag.argtypes = [_vp, _vp, C.c_int, C.c_double, _vp]
@@ -605,6 +611,27 @@ class Graph:
         self.ctx._check(self._L.mm_gnn_features(self.h, mp, hp.ctypes.data_as(_dp), hn.ctypes.data_as(_dp), xp))
         return X
 
+    def targets(self, m, m_next, diag3, dm_out=None, s_out=None):
+        """Training targets of one field step (mm_gnn_targets): the
+        tangent step dm* (n x 3) and the Jacobi factor s* (n); outputs may be
+        given (numpy or device tensors)."""
+        mp, k1 = _vec_ptr(m)
+        np_, k2 = _vec_ptr(m_next)
+        dp_, k3 = _vec_ptr(diag3)
+        dm = np.zeros((self.n, 3)) if dm_out is None else dm_out
+        sv = np.zeros(self.n) if s_out is None else s_out
+        dmp, k4 = _vec_ptr(dm)
+        svp, k5 = _vec_ptr(sv)
+        self.ctx._check(self._L.mm_gnn_targets(self.h, mp, np_, dp_, dmp, svp))
+        return dm, sv
+
+    def moments(self, X):
+        """Column sums and sums of squares of features X (mm_gnn_moments)."""
+        xp, xk = _vec_ptr(X, np.float32)
+        s1, s2 = np.zeros(32), np.zeros(32)
+        self.ctx._check(self._L.mm_gnn_moments(self.h, xp, s1.ctypes.data_as(_dp), s2.ctypes.data_as(_dp)))
+        return s1, s2
+
 
 class Gnn:
     """Graph network of the learned warm start / scaling (mm_gnn)."""
@@ -674,3 +701,28 @@ class Gnn:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._chk(self._L.mm_gnn_adam(self.h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def train(self, samples, epochs, lr, w_s=1.0, seed=0):
+        """mm_gnn_train over samples [(graph, X, m, dm_target, s_target,
+        inv_dm2)], the arrays device tensors; returns the mean loss per
+        epoch."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        n = len(samples)
+        P = C.c_void_p * n
+        g = P(*[s[0].h for s in samples])
+        cols = [P(*[C.c_void_p(s[q].data_ptr()) for s in samples]) for q in range(1, 5)]
+        w = np.array([float(s[5]) for s in samples])
+        out = np.zeros(max(epochs, 1))
+        self._chk(self._L.mm_gnn_train(self.h, n, g, cols[0], cols[1], cols[2], cols[3], w.ctypes.data_as(_dp),
+                                       float(w_s), int(epochs), float(lr), int(seed), out.ctypes.data_as(_dp)))
+        return out[:epochs]
+
+    def save(self, path):
+        """Parameters and input standardization to a file (mm_gnn_save)."""
+        self._chk(self._L.mm_gnn_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        """Parameters and input standardization from mm_gnn_save's file."""
+        self._chk(self._L.mm_gnn_load(self.h, os.fsencode(path)))
+        return self

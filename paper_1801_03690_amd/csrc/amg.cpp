@@ -658,13 +658,16 @@ AmgState *amg_get(mm_ctx *c) {
         F.lv[l].Ainv = upload_v(c, to32(inv));
     }
     D.u = dalloc_n<double>(c, N[0]);
+    D.rf = dalloc_n<double>(c, N[0]);
     F.u = dalloc_n<float>(c, N[0]);
     HIPCHK(hipMemsetAsync(D.u, 0, (size_t)N[0] * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(D.rf, 0, (size_t)N[0] * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(F.u, 0, (size_t)N[0] * sizeof(float), c->stream));
     sync(c);
     // algorithmic bytes of one CG iteration per instance: the fine matrix
     // three times (the iteration, the post-smoothing, w = K u), P and R once
-    // each and 17 vector passes on the fine level; the two fused operators and
+    // each and 18 vector passes on the fine level (one of them the plain copy
+    // of r); the two fused operators and
     // 3 vector passes on each further level; the dense inverse of the coarsest
     for (int k = 0; k < 3; ++k) S->bytes[k].assign(ni, 0.0);
     for (int i = 0; i < ni; ++i) {
@@ -679,7 +682,7 @@ AmgState *amg_get(mm_ctx *c) {
                 if (l == L) {
                     by += n * n * v + 2.0 * n * v;
                 } else if (l == 0) {
-                    by += 3.0 * (double)c->inst[i].nnz_K * (v + 4) + 2.0 * (double)H.P.nnz() * (v + 4) + 17.0 * n * v;
+                    by += 3.0 * (double)c->inst[i].nnz_K * (v + 4) + 2.0 * (double)H.P.nnz() * (v + 4) + 18.0 * n * v;
                 } else {
                     // the fused operators: Q^T (nnz of AP, P) and [S | Q]
                     const double nq = (double)std::max(H.AP.nnz(), H.P.nnz());
@@ -688,7 +691,7 @@ AmgState *amg_get(mm_ctx *c) {
             }
             S->bytes[k][i] = by;
         }
-        S->bytes[2][i] = S->bytes[1][i] + (L > 0 ? 17.0 * 4.0 * (double)Hi[0].A.n : 0.0);
+        S->bytes[2][i] = S->bytes[1][i] + (L > 0 ? 18.0 * 4.0 * (double)Hi[0].A.n : 0.0);
     }
     for (auto &Hi : S->H)
         for (auto &H : Hi) H.AP = Csr();

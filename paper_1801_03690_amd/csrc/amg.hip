@@ -229,12 +229,12 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
 }
 
 // fine level: w = K u into the w field of the record (the other fields were
-// written by k_amg_iter, or by the start); partials (delta = w.u, r.r) into
-// slots wslot, wslot + 1
+// written by k_amg_iter, or by the start); partials (delta = w.u, r.r, with r
+// at r[row * rs]) into slots wslot, wslot + 1
 template <class MT, class VT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
-                                                   const VT *__restrict__ u, double *__restrict__ part, int wslot,
-                                                   const PcgState *st) {
+                                                   const VT *__restrict__ r, int rs, const VT *__restrict__ u,
+                                                   double *__restrict__ part, int wslot, const PcgState *st) {
     Tile tl = tile_of(M);
     if (tl.inst < 0 || (st && st[tl.inst].done)) return;
     __shared__ double sh[NW * 2];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
         const VT ku = row_gather<MT, VT, false, NT>(K, s, ln, u, 1, (const VT *)nullptr);
         const int row = s * 64 + ln;
         if (row < rend) {
-            const VT ri = q[row].r;
+            const VT ri = r[(int64_t)row * rs];
             q[row].w = ku;
             acc[0] += (double)ku * (double)u[row];
             acc[1] += (double)ri * (double)ri;
@@ -287,12 +287,14 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
 
 // the updates of one CG iteration of parity par (reads records q[par] and the
 // partials P[par]; writes records q[par ^ 1] with w = 0, filled in by
-// k_amg_w) and t = r_new - omega K D^-1 r_new, where K D^-1 r_new = A -
-// alpha (B + beta C) with A, B, C the products of K D^-1 with the old r, w, s
+// k_amg_w, and r_new once more as the plain vector rf, which the rest of the
+// iteration reads instead of the records) and t = r_new - omega K D^-1 r_new,
+// where K D^-1 r_new = A - alpha (B + beta C) with A, B, C the products of
+// K D^-1 with the old r, w, s
 template <class MT, class VT, class XT, class CT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
                                                       const VT *__restrict__ uu, CT *__restrict__ tt,
-                                                      const VT *__restrict__ om,
+                                                      VT *__restrict__ rf, const VT *__restrict__ om,
                                                       PcgState *__restrict__ st, int par,
                                                       const double *__restrict__ part) {
     Tile tl = tile_of(M);
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
             x[row] = x[row] + (XT)(a * pn);
             p[row] = pn;
             q1[row] = PcgNode<VT>{rn, (VT)0, sn, me.d};
+            rf[row] = rn;
             tt[row] = (CT)(rn - omega * kdr);
         }
     }
@@ -459,6 +462,7 @@ struct FineArgs {
     const RT *invD;    // D^-1 of the records
     const RT *omega;   // per instance, the fine smoothing weight in RT
     RT *u;             // preconditioned residual
+    RT *rf;            // the residual as a plain vector (written by k_amg_iter)
 };
 
 template <class VT>
@@ -490,7 +494,7 @@ void fine_cycle_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT
                                              cg ? a.part : (double *)nullptr, kP0, (const PcgState *)nullptr))
     if (cg)
         MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                                 view<VT>(*a.K), M, q, (const RT *)fa.u, a.part, kP0 + 1,
+                                                 view<VT>(*a.K), M, q, r, rs, (const RT *)fa.u, a.part, kP0 + 1,
                                                  (const PcgState *)nullptr))
 }
 
@@ -512,14 +516,18 @@ void amg_iter_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, 
     PcgNode<RT> *q1 = v.q[par ^ 1];
     const int ws = par ? kP0 : kP1;  // this iteration's new partials
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0,
-                                             s, view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.omega, a.st, par,
-                                             (const double *)a.part))
-    lower_cycle(g, (const RT *)&q1->r, 4, (const PcgState *)a.st, s);
+                                             s, view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.rf, fa.omega,
+                                             a.st, par, (const double *)a.part))
+    const RT *rf = fa.rf;
+    // a single dense level takes b from the records (its plain-b path loads
+    // VT vectors padded with zeros, which rf is not)
+    if (g.nlev > 1) lower_cycle(g, rf, 1, (const PcgState *)a.st, s);
+    else lower_cycle(g, (const RT *)&q1->r, 4, (const PcgState *)a.st, s);
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_post0<VT, VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                             view<VT>(*a.K), M, (const RT *)&q1->r, 4, post_wd(g), (const VT *)f.z,
-                                             fa.u, a.part, ws, (const PcgState *)a.st);
+                                             view<VT>(*a.K), M, rf, 1, post_wd(g), (const VT *)f.z, fa.u, a.part,
+                                             ws, (const PcgState *)a.st);
                     hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<VT>(*a.K), M, q1, (const RT *)fa.u, a.part, ws + 1,
+                                       view<VT>(*a.K), M, q1, rf, 1, (const RT *)fa.u, a.part, ws + 1,
                                        (const PcgState *)a.st))
 }
 
@@ -531,13 +539,13 @@ void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT>
 }
 
 FineArgs<double, double> fine64(const PcgLaunch &a, const AmgLaunch<double> &g) {
-    return FineArgs<double, double>{a.invD, g.omega, g.u};
+    return FineArgs<double, double>{a.invD, g.omega, g.u, g.rf};
 }
 FineArgs<float, float> fine32(const PcgLaunch &a, const AmgLaunch<float> &g) {
-    return FineArgs<float, float>{a.invD32, g.omega, g.u};
+    return FineArgs<float, float>{a.invD32, g.omega, g.u, (float *)nullptr};
 }
 FineArgs<float, double> finemix(const PcgLaunch &a, const AmgLaunch<double> &g64) {
-    return FineArgs<float, double>{a.invD, g64.omega, g64.u};
+    return FineArgs<float, double>{a.invD, g64.omega, g64.u, g64.rf};
 }
 
 }  // namespace

@@ -31,6 +31,7 @@ inline SV<float> view<float>(const Sell &A) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 // Hardware blocks are dealt round-robin to the 8 XCDs; renumber them so that
@@ -120,28 +121,59 @@ __device__ __forceinline__ bool stopped_before(const int *flag, int phase) {
 // ---------------------------------------------------------------------------
 // SELL-64 rows
 // ---------------------------------------------------------------------------
+// The row walks below take their entries in groups of G: the column indices
+// and values of a group are loaded first, then its gathers, then the products
+// are added in entry order (the same sums as one entry at a time), so that a
+// wave has a group's loads in flight at once. A group's entries past the
+// slice's width are skipped (the test is uniform over the wave). Values stay
+// in their stored type until they are multiplied. A larger G holds more
+// registers, so fewer waves fit a SIMD: each kernel takes the G measured
+// fastest for it.
 // symmetric 3x3 block row (xx yy zz xy xz yz) times node-major 3-vectors
-template <class V>
+template <int G, class V>
 __device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const double *__restrict__ x, double &o0,
                                            double &o1, double &o2) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
+    const int64_t base = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - base) >> 6);
     // difference form (see row_scalar3): the diagonal block holds the row sum
     const int64_t row = (int64_t)s * 64 + ln;
     const double xi0 = x[3 * row], xi1 = x[3 * row + 1], xi2 = x[3 * row + 2];
     o0 = o1 = o2 = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        int c = A.col[e + ln];
-        const V *v = A.val + e * 6 + ln;
-        double vxx = (double)v[0], vyy = (double)v[64], vzz = (double)v[128];
-        double vxy = (double)v[192], vxz = (double)v[256], vyz = (double)v[320];
-        const bool dg = c == row;
-        double x0 = dg ? xi0 : x[3 * (int64_t)c] - xi0, x1 = dg ? xi1 : x[3 * (int64_t)c + 1] - xi1,
-               x2 = dg ? xi2 : x[3 * (int64_t)c + 2] - xi2;
-        o0 += vxx * x0 + vxy * x1 + vxz * x2;
-        o1 += vxy * x0 + vyy * x1 + vyz * x2;
-        o2 += vxz * x0 + vyz * x1 + vzz * x2;
+#pragma unroll 1
+    for (int k0 = 0; k0 < w; k0 += G) {
+        int cc[G];
+        V vv[G][6];
+        double xx[G][3];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t e = base + 64 * (k0 + k);
+                cc[k] = A.col[e + ln];
+                const V *v = A.val + e * 6 + ln;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) vv[k][q] = v[64 * q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t c = cc[k];
+                const bool dg = c == row;
+                xx[k][0] = dg ? xi0 : x[3 * c] - xi0;
+                xx[k][1] = dg ? xi1 : x[3 * c + 1] - xi1;
+                xx[k][2] = dg ? xi2 : x[3 * c + 2] - xi2;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const double vxx = (double)vv[k][0], vyy = (double)vv[k][1], vzz = (double)vv[k][2];
+                const double vxy = (double)vv[k][3], vxz = (double)vv[k][4], vyz = (double)vv[k][5];
+                o0 += vxx * xx[k][0] + vxy * xx[k][1] + vxz * xx[k][2];
+                o1 += vxy * xx[k][0] + vyy * xx[k][1] + vyz * xx[k][2];
+                o2 += vxz * xx[k][0] + vyz * xx[k][1] + vzz * xx[k][2];
+            }
+        }
     }
 }
 
@@ -186,35 +218,78 @@ __device__ __forceinline__ void row_scalar3(const SV<V> &A, int s, int ln, const
 }
 
 // sum_k vec3_k . x[col_k]
-template <class V>
+template <int G, class V>
 __device__ __forceinline__ double row_vec3_dot(const SV<V> &A, int s, int ln, const double *__restrict__ x) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
+    const int64_t base = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - base) >> 6);
     double acc = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        int c = A.col[e + ln];
-        const V *v = A.val + e * 3 + ln;
-        acc += (double)v[0] * x[3 * (int64_t)c] + (double)v[64] * x[3 * (int64_t)c + 1] +
-               (double)v[128] * x[3 * (int64_t)c + 2];
+#pragma unroll 1
+    for (int k0 = 0; k0 < w; k0 += G) {
+        int cc[G];
+        V vv[G][3];
+        double xx[G][3];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t e = base + 64 * (k0 + k);
+                cc[k] = A.col[e + ln];
+                const V *v = A.val + e * 3 + ln;
+                vv[k][0] = v[0];
+                vv[k][1] = v[64];
+                vv[k][2] = v[128];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t c = cc[k];
+                xx[k][0] = x[3 * c];
+                xx[k][1] = x[3 * c + 1];
+                xx[k][2] = x[3 * c + 2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (k0 + k < w)
+                acc += (double)vv[k][0] * xx[k][0] + (double)vv[k][1] * xx[k][1] + (double)vv[k][2] * xx[k][2];
     }
     return acc;
 }
 
 // sum_k vec3_k * u[col_k]
-template <class V>
+template <int G, class V>
 __device__ __forceinline__ void row_vec3_scale(const SV<V> &A, int s, int ln, const double *__restrict__ u,
                                                double &o0, double &o1, double &o2) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
+    const int64_t base = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - base) >> 6);
     o0 = o1 = o2 = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k;
-        double uc = u[A.col[e + ln]];
-        const V *v = A.val + e * 3 + ln;
-        o0 += (double)v[0] * uc;
-        o1 += (double)v[64] * uc;
-        o2 += (double)v[128] * uc;
+#pragma unroll 1
+    for (int k0 = 0; k0 < w; k0 += G) {
+        int cc[G];
+        V vv[G][3];
+        double uu[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t e = base + 64 * (k0 + k);
+                cc[k] = A.col[e + ln];
+                const V *v = A.val + e * 3 + ln;
+                vv[k][0] = v[0];
+                vv[k][1] = v[64];
+                vv[k][2] = v[128];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (k0 + k < w) uu[k] = u[cc[k]];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                o0 += (double)vv[k][0] * uu[k];
+                o1 += (double)vv[k][1] * uu[k];
+                o2 += (double)vv[k][2] * uu[k];
+            }
+        }
     }
 }
 

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <set>
 #include <vector>
@@ -247,6 +249,57 @@ void check_pair(mm_gnn *g, mm_graph *gr) {
     if (gr->c->device != g->device) throw ApiError{MM_EINVAL, "network and graph are on different devices"};
     if (gr->c->stream != g->stream) sync(gr->c);
 }
+
+// one forward + backward pass on a sample (gradient left in g->grad); the loss
+double loss_grad_step(mm_gnn *g, mm_graph *gr, const float *X, const double *m, const double *dm_target,
+                      const double *s_target, double inv_dm2, double w_s) {
+    check_pair(g, gr);
+    if (!m || !dm_target || !s_target) throw ApiError{MM_EINVAL, "m and both targets are required"};
+    if (!(inv_dm2 >= 0) || !(w_s >= 0)) throw ApiError{MM_EINVAL, "loss weights must be >= 0"};
+    const int n = gr->n;
+    ensure_ws(g, n);
+    hipStream_t st = g->stream;
+    const float *Xd = gr->X;
+    if (X) {
+        copy_f32_in(st, g->X, X, (size_t)kF * n);
+        Xd = g->X;
+    }
+    copy_d_in(st, g->m, m, 3 * (size_t)n);
+    copy_d_in(st, g->dmt, dm_target, 3 * (size_t)n);
+    copy_d_in(st, g->st, s_target, n);
+    forward(g, gr, Xd, g->m, nullptr, nullptr);
+    gnn_loss_heads(n, g->zm, g->zs, g->m, g->dmt, g->st, gr->c->L, 1.0 / gr->sumL, inv_dm2, w_s, g->d_zm, g->d_zs,
+                   g->lpart, g->loss, st);
+    backward(g, gr);
+    double lv = 0.0;
+    HIPCHK(hipMemcpyAsync(&lv, g->loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    gsync(g);
+    return lv;
+}
+
+// one bias-corrected Adam step with the last gradient (enqueued)
+void adam_step(mm_gnn *g, double lr, double beta1, double beta2, double eps) {
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        throw ApiError{MM_EINVAL, "bad Adam constants"};
+    g->t += 1;
+    const double bc1 = 1.0 - std::pow(beta1, (double)g->t), bc2 = 1.0 - std::pow(beta2, (double)g->t);
+    gnn_adam(kNParams, g->theta, g->grad, g->m1, g->m2, (float)lr, (float)beta1, (float)beta2, (float)eps,
+             (float)bc1, (float)bc2, g->stream);
+}
+
+// SplitMix64 (Steele, Lea and Flood): the shuffles of mm_gnn_train
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+// first word of a parameter file of mm_gnn_save ("MMGNN" + format 1)
+constexpr int64_t kGnnFileMagic = 0x31004E4E474D4DLL;
 
 }  // namespace
 
@@ -531,26 +584,8 @@ int mm_gnn_forward(mm_gnn *g, mm_graph *gr, const float *X, const double *m, dou
 int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, const double *dm_target,
                      const double *s_target, double inv_dm2, double w_s, double *loss, double *grad) {
     return gguard(g, [&] {
-        check_pair(g, gr);
-        if (!m || !dm_target || !s_target) throw ApiError{MM_EINVAL, "m and both targets are required"};
-        if (!(inv_dm2 >= 0) || !(w_s >= 0)) throw ApiError{MM_EINVAL, "loss weights must be >= 0"};
-        const int n = gr->n;
-        ensure_ws(g, n);
+        const double lv = loss_grad_step(g, gr, X, m, dm_target, s_target, inv_dm2, w_s);
         hipStream_t st = g->stream;
-        const float *Xd = gr->X;
-        if (X) {
-            copy_f32_in(st, g->X, X, (size_t)kF * n);
-            Xd = g->X;
-        }
-        copy_d_in(st, g->m, m, 3 * (size_t)n);
-        copy_d_in(st, g->dmt, dm_target, 3 * (size_t)n);
-        copy_d_in(st, g->st, s_target, n);
-        forward(g, gr, Xd, g->m, nullptr, nullptr);
-        gnn_loss_heads(n, g->zm, g->zs, g->m, g->dmt, g->st, gr->c->L, 1.0 / gr->sumL, inv_dm2, w_s, g->d_zm,
-                       g->d_zs, g->lpart, g->loss, st);
-        backward(g, gr);
-        double lv = 0.0;
-        HIPCHK(hipMemcpyAsync(&lv, g->loss, sizeof(double), hipMemcpyDeviceToHost, st));
         if (grad) {
             std::vector<float> h(kNParams);
             HIPCHK(hipMemcpyAsync(h.data(), g->grad, kNParams * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -567,13 +602,137 @@ int mm_gnn_loss_grad(mm_gnn *g, mm_graph *gr, const float *X, const double *m, c
 
 int mm_gnn_adam(mm_gnn *g, double lr, double beta1, double beta2, double eps) {
     return gguard(g, [&] {
-        if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
-            throw ApiError{MM_EINVAL, "bad Adam constants"};
-        g->t += 1;
-        const double bc1 = 1.0 - std::pow(beta1, (double)g->t), bc2 = 1.0 - std::pow(beta2, (double)g->t);
-        gnn_adam(kNParams, g->theta, g->grad, g->m1, g->m2, (float)lr, (float)beta1, (float)beta2, (float)eps,
-                 (float)bc1, (float)bc2, g->stream);
+        adam_step(g, lr, beta1, beta2, eps);
         gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_train(mm_gnn *g, long n_samples, mm_graph *const *graphs, const float *const *X, const double *const *m,
+                 const double *const *dm_target, const double *const *s_target, const double *inv_dm2, double w_s,
+                 int epochs, double lr, unsigned long long seed, double *epoch_loss) {
+    return gguard(g, [&] {
+        if (n_samples < 1 || !graphs || !X || !m || !dm_target || !s_target || !inv_dm2 || epochs < 0)
+            throw ApiError{MM_EINVAL, "bad training arguments"};
+        std::vector<long> order(n_samples);
+        for (long k = 0; k < n_samples; ++k) order[k] = k;
+        SplitMix64 rng{seed};
+        for (int ep = 0; ep < epochs; ++ep) {
+            // Fisher-Yates with the counter-based generator: the same seed gives the same order
+            for (long k = n_samples - 1; k > 0; --k) std::swap(order[k], order[(long)(rng.next() % (uint64_t)(k + 1))]);
+            double tot = 0.0;
+            for (long k : order) {
+                tot += loss_grad_step(g, graphs[k], X[k], m[k], dm_target[k], s_target[k], inv_dm2[k], w_s);
+                adam_step(g, lr, 0.9, 0.999, 1e-8);
+            }
+            gsync(g);
+            if (epoch_loss) epoch_loss[ep] = tot / (double)n_samples;
+        }
+        return MM_OK;
+    });
+}
+
+int mm_gnn_save(mm_gnn *g, const char *path) {
+    return gguard(g, [&] {
+        if (!path) throw ApiError{MM_EINVAL, "null path"};
+        std::vector<float> th(kNParams), mu(kF), sd(kF);
+        HIPCHK(hipMemcpyAsync(th.data(), g->theta, kNParams * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipMemcpyAsync(mu.data(), g->mu, kF * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipMemcpyAsync(sd.data(), g->sd, kF * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+        gsync(g);
+        const std::string tmp = std::string(path) + ".tmp";
+        FILE *f = std::fopen(tmp.c_str(), "wb");
+        if (!f) throw ApiError{MM_EINVAL, std::string("cannot write ") + path};
+        const int64_t hdr[3] = {kGnnFileMagic, (int64_t)kNParams, (int64_t)kF};
+        bool ok = std::fwrite(hdr, sizeof hdr, 1, f) == 1 && std::fwrite(th.data(), sizeof(float), th.size(), f) == th.size() &&
+                  std::fwrite(mu.data(), sizeof(float), kF, f) == (size_t)kF &&
+                  std::fwrite(sd.data(), sizeof(float), kF, f) == (size_t)kF;
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok || std::rename(tmp.c_str(), path) != 0) throw ApiError{MM_EINVAL, std::string("cannot write ") + path};
+        return MM_OK;
+    });
+}
+
+int mm_gnn_load(mm_gnn *g, const char *path) {
+    return gguard(g, [&] {
+        if (!path) throw ApiError{MM_EINVAL, "null path"};
+        FILE *f = std::fopen(path, "rb");
+        if (!f) throw ApiError{MM_EINVAL, std::string("cannot read ") + path};
+        int64_t hdr[3] = {0, 0, 0};
+        std::vector<float> th(kNParams), mu(kF), sd(kF);
+        bool ok = std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == kGnnFileMagic && hdr[1] == kNParams && hdr[2] == kF &&
+                  std::fread(th.data(), sizeof(float), th.size(), f) == th.size() &&
+                  std::fread(mu.data(), sizeof(float), kF, f) == (size_t)kF &&
+                  std::fread(sd.data(), sizeof(float), kF, f) == (size_t)kF;
+        std::fclose(f);
+        if (!ok) throw ApiError{MM_EINVAL, std::string("not a parameter file of this network: ") + path};
+        for (float v : th)
+            if (!std::isfinite(v)) throw ApiError{MM_EINVAL, "non-finite parameter"};
+        for (int c = 0; c < kF; ++c)
+            if (!std::isfinite(mu[c]) || !(sd[c] > 0) || !std::isfinite(sd[c])) throw ApiError{MM_EINVAL, "bad standardization"};
+        HIPCHK(hipMemcpyAsync(g->theta, th.data(), kNParams * sizeof(float), hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->mu, mu.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->sd, sd.data(), kF * sizeof(float), hipMemcpyHostToDevice, g->stream));
+        // a loaded network starts a fresh optimizer state
+        HIPCHK(hipMemsetAsync(g->m1, 0, kNParams * sizeof(float), g->stream));
+        HIPCHK(hipMemsetAsync(g->m2, 0, kNParams * sizeof(float), g->stream));
+        g->t = 0;
+        gsync(g);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_targets(mm_graph *gr, const double *m, const double *m_next, const double *diag3, double *dm_target,
+                   double *s_target) {
+    if (!gr) return MM_EINVAL;
+    mm_ctx *c = gr->c;
+    return guarded(c, [&] {
+        require_single(c);
+        if (!m || !m_next || !diag3 || !dm_target || !s_target) throw ApiError{MM_EINVAL, "null vector"};
+        const int n = gr->n;
+        std::vector<void *> tmp;
+        double *dm_ = galloc<double>(c, tmp, 3 * (size_t)n), *dm1 = galloc<double>(c, tmp, 3 * (size_t)n),
+               *dd = galloc<double>(c, tmp, 3 * (size_t)n), *dt = galloc<double>(c, tmp, 3 * (size_t)n),
+               *ds = galloc<double>(c, tmp, (size_t)n);
+        try {
+            copy_in(c, dm_, m, 3 * (size_t)n);
+            copy_in(c, dm1, m_next, 3 * (size_t)n);
+            copy_in(c, dd, diag3, 3 * (size_t)n);
+            gnn_targets(n, dm_, dm1, dd, c->invDex, dt, ds, c->stream);
+            copy_out(c, dm_target, dt, 3 * (size_t)n);
+            copy_out(c, s_target, ds, (size_t)n);
+            sync(c);
+        } catch (...) {
+            release(c, tmp);
+            throw;
+        }
+        release(c, tmp);
+        return MM_OK;
+    });
+}
+
+int mm_gnn_moments(mm_graph *gr, const float *X, double *sum, double *sumsq) {
+    if (!gr) return MM_EINVAL;
+    mm_ctx *c = gr->c;
+    return guarded(c, [&] {
+        if (!X || !sum || !sumsq) throw ApiError{MM_EINVAL, "null argument"};
+        const int n = gr->n;
+        std::vector<void *> tmp;
+        float *dX = galloc<float>(c, tmp, (size_t)kF * std::max(n, 1));
+        double *part = galloc<double>(c, tmp, 64 * (size_t)gnn_moment_blocks(n)), *out = galloc<double>(c, tmp, 64);
+        std::vector<double> h(64);
+        try {
+            copy_f32_in(c->stream, dX, X, (size_t)kF * n);
+            gnn_moments(n, dX, part, out, c->stream);
+            HIPCHK(hipMemcpyAsync(h.data(), out, 64 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+        } catch (...) {
+            release(c, tmp);
+            throw;
+        }
+        release(c, tmp);
+        std::memcpy(sum, h.data(), 32 * sizeof(double));
+        std::memcpy(sumsq, h.data() + 32, 32 * sizeof(double));
         return MM_OK;
     });
 }

@@ -416,9 +416,76 @@ __global__ void k_f32_to_f64(int64_t n, const float *__restrict__ a, double *__r
     if (e < n) b[e] = (double)a[e];
 }
 
+// training targets per node a: dm*_a = P_{m_a}(m1_a - m_a) (the step to the
+// next minimizer in the tangent plane of m_a) and s*_a = 1 + t_a / D_a with
+// t_a the mean over the two directions normal to m_a of the magnetostatic
+// Hessian's diagonal (diag3, per component): t = (sum_c diag_c - sum_c
+// m_c^2 diag_c) / 2; invD = 1 / D
+__global__ __launch_bounds__(kGB) void k_targets(int n, const double *__restrict__ m, const double *__restrict__ m1,
+                                                 const double *__restrict__ diag3, const double *__restrict__ invD,
+                                                 double *__restrict__ dmt, double *__restrict__ st) {
+    const int a = blockIdx.x * kGB + threadIdx.x;
+    if (a >= n) return;
+    const int64_t a3 = 3 * (int64_t)a;
+    const double m0 = m[a3], mx = m[a3 + 1], mz = m[a3 + 2];
+    const double d0 = m1[a3] - m0, d1 = m1[a3 + 1] - mx, d2 = m1[a3 + 2] - mz;
+    const double dm = d0 * m0 + d1 * mx + d2 * mz;
+    dmt[a3] = d0 - dm * m0;
+    dmt[a3 + 1] = d1 - dm * mx;
+    dmt[a3 + 2] = d2 - dm * mz;
+    const double g0 = diag3[a3], g1 = diag3[a3 + 1], g2 = diag3[a3 + 2];
+    const double t = 0.5 * ((g0 + g1 + g2) - (m0 * m0 * g0 + mx * mx * g1 + mz * mz * g2));
+    st[a] = 1.0 + t * invD[a];
+}
+
+// column sums and sums of squares of X (n x 32) in FP64: block b writes the
+// 64 partials of its rows (thread t: column t % 32, every 8th row), summed
+// over blocks in order by k_sum_cols
+constexpr int kMomRows = 2048;
+__global__ __launch_bounds__(kGB) void k_moments(int n, const float *__restrict__ X, double *__restrict__ part) {
+    __shared__ double sh[kGB][2];
+    const int col = threadIdx.x % 32, rg = threadIdx.x / 32;
+    const int r0 = blockIdx.x * kMomRows, r1 = min(n, r0 + kMomRows);
+    double s1 = 0.0, s2 = 0.0;
+    for (int r = r0 + rg; r < r1; r += kGB / 32) {
+        const double x = (double)X[(int64_t)r * 32 + col];
+        s1 += x;
+        s2 += x * x;
+    }
+    sh[threadIdx.x][0] = s1;
+    sh[threadIdx.x][1] = s2;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double a = 0.0, b = 0.0;
+        for (int g = 0; g < kGB / 32; ++g) {
+            a += sh[g * 32 + threadIdx.x][0];
+            b += sh[g * 32 + threadIdx.x][1];
+        }
+        part[(int64_t)blockIdx.x * 64 + threadIdx.x] = a;
+        part[(int64_t)blockIdx.x * 64 + 32 + threadIdx.x] = b;
+    }
+}
+__global__ void k_sum_cols(int nblk, const double *__restrict__ part, double *__restrict__ out) {
+    const int q = threadIdx.x;  // 64 threads
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * 64 + q];
+    out[q] = acc;
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+void gnn_targets(int n, const double *m, const double *m1, const double *diag3, const double *invD, double *dmt,
+                 double *st, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_targets, dim3(blocks_for(n, kGB)), dim3(kGB), 0, s, n, m, m1, diag3, invD, dmt, st);
+}
+int gnn_moment_blocks(int n) { return n > 0 ? (int)blocks_for(n, kMomRows) : 1; }
+void gnn_moments(int n, const float *X, double *part, double *out, hipStream_t s) {
+    const int nb = gnn_moment_blocks(n);
+    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(kGB), 0, s, n, X, part);
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(64), 0, s, nb, (const double *)part, out);
+}
 
 // ===========================================================================
 // launchers

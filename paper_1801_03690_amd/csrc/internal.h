@@ -258,6 +258,8 @@ struct AmgLaunch {
     int nlev = 0;                  // levels of the deepest hierarchy
     AmgLevel<VT> lv[kAmgMaxLevels];
     VT *u = nullptr;               // level 0: the preconditioned residual M r
+    VT *rf = nullptr;              // level 0: the CG residual r as a plain vector (the records hold it
+                                   // too, among three other fields the cycle does not read)
     const VT *omega = nullptr;     // per instance: the fine smoothing weight
     bool single = true;            // one instance: the cycle's kernels read its flag without the row tables
 };
@@ -281,6 +283,10 @@ void gnn_mm(int M, int K, int NC, int epi, const float *A, int lda, const float 
             const float *bias, float *Y, int ldy, float *Ypre, int ldp, const float *R, int ldr, bool f32,
             hipStream_t s);
 int gnn_tn_blocks(int M);
+void gnn_targets(int n, const double *m, const double *m1, const double *diag3, const double *invD, double *dmt,
+                 double *st, hipStream_t s);
+int gnn_moment_blocks(int n);
+void gnn_moments(int n, const float *X, double *part, double *out, hipStream_t s);
 void gnn_mm_tn(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,
                bool accumulate, bool f32, hipStream_t s);
 void gnn_tn32(int M, int KI, int NC, const float *A, int lda, const float *B, int ldb, float *part, float *out,

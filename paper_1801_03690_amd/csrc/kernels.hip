@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_block6(SV<V> A, RowMap M, const
     const int rend = M.rend[t.inst], ln = lane_id();
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o0, o1, o2;
-        row_block6(A, s, ln, x, o0, o1, o2);
+        row_block6<2>(A, s, ln, x, o0, o1, o2);
         int row = s * 64 + ln;
         if (row < rend) {
             y[3 * (int64_t)row] = o0;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_bmul(SV<V> B, RowMap MB, const int *
     const double *m = pick(s0v, s1v, s2v, role ? role[t.inst] : 0).x;
     const int rend = MB.rend[t.inst], ln = lane_id();
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
-        double o = row_vec3_dot(B, s, ln, m);
+        double o = row_vec3_dot<4>(B, s, ln, m);
         int row = s * 64 + ln;
         if (row < rend) b[B.row_out[row]] = o;
     }
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_btmul(SV<V> Bt, RowMap M, const doub
     const int rend = M.rend[t.inst], ln = lane_id();
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double o0, o1, o2;
-        row_vec3_scale(Bt, s, ln, u, o0, o1, o2);
+        row_vec3_scale<2>(Bt, s, ln, u, o0, o1, o2);
         int row = s * 64 + ln;
         if (row < rend) {
             g[3 * (int64_t)row] = o0;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_epilogue(SV<V> C, SV<V> S, SV<V
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double c0 = 0, c1 = 0, c2 = 0;
         // cmode: 0 none, 1 exchange only (S), 2 anisotropy only (C - S), 3 both (C)
-        if (cmode & 2) row_block6(C, s, ln, m, c0, c1, c2);
+        if (cmode & 2) row_block6<2>(C, s, ln, m, c0, c1, c2);
         if (cmode == 1 || cmode == 2) {
             double e0, e1, e2;
             row_scalar3(S, s, ln, m, e0, e1, e2);
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_epilogue(SV<V> C, SV<V> S, SV<V
             }
         }
         double d0 = 0, d1 = 0, d2 = 0;
-        if (use_demag) row_vec3_scale(Bt, s, ln, u, d0, d1, d2);
+        if (use_demag) row_vec3_scale<2>(Bt, s, ln, u, d0, d1, d2);
         int r = s * 64 + ln;
         if (r < rend) {
             int64_t r3 = 3 * (int64_t)r;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_apply(SV<V> C, RowMap M, const 
     double acc[1] = {0};
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
         double c0, c1, c2;
-        row_block6(C, s, ln, p, c0, c1, c2);
+        row_block6<1>(C, s, ln, p, c0, c1, c2);
         int a = s * 64 + ln;
         if (a < rend) {
             int64_t a3 = 3 * (int64_t)a;

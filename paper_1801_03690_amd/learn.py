@@ -2,8 +2,11 @@
 
 Orchestration only: every step runs in the library through its C ABI (plain
 demagnetization curves that produce the training trajectories, node features,
-the Hutchinson probe of the magnetostatic diagonal, the network's forward and
-backward kernels and Adam). Device arrays are torch tensors (memory only).
+the Hutchinson probe of the magnetostatic diagonal, the training targets
+(mm_gnn_targets), the feature statistics (mm_gnn_moments), the training
+loop with the network's forward and backward kernels and Adam
+(mm_gnn_train) and the parameter file (mm_gnn_save / mm_gnn_load)). Device
+arrays are torch tensors (memory only).
 
 Training data: for each seeded film, the plain method's minimizers m_k along
 its field sweep; one sample per step k -> k+1 with
@@ -26,7 +29,7 @@ from . import inputs
 class Film:
     """One film: its context, graph, trajectory and training samples (device)."""
 
-    def __init__(self, work, jmax=4, n_probe=32, probe_seed=0, keep=True):
+    def __init__(self, work, jmax=4, n_probe=32, probe_seed=0, keep=True, precision=B.MM_FP64):
         import torch
         self.work = work
         self.ctx = B.Context(0).upload(work.mesh)
@@ -34,25 +37,22 @@ class Film:
         self.n = self.ctx.n_mag
         self.jmax = jmax
         t0 = time.perf_counter()
-        r = self.ctx.curve(work.m0, work.fields, jmax=jmax, keep_hist=True)
+        r = self.ctx.curve(work.m0, work.fields, jmax=jmax, keep_hist=True, precision=precision)
         self.t_curve = time.perf_counter() - t0
         self.plain = r
         hist = r["hist"]
         z = inputs.rademacher(n_probe, self.n, seed=probe_seed)
         self.diag3 = self.ctx.demag_diag(z, rtol=1e-8)
-        D = self.ctx.jacobi_diag()
         F = work.fields
         self.samples = []
         for k in range(len(F) - 1):
-            mk = hist[k]
-            X = self.graph.features(mk, F[k], F[k + 1])
-            d = hist[k + 1] - mk
-            dmt = d - (d * mk).sum(axis=1, keepdims=True) * mk
-            t = 0.5 * (self.diag3.sum(axis=1) - (mk * mk * self.diag3).sum(axis=1))
-            st = 1.0 + t / D
-            dev = "cuda"
-            self.samples.append(tuple(torch.tensor(a, device=dev) for a in
-                                      (X, mk, dmt, st)))
+            mk = torch.tensor(hist[k], device="cuda")
+            X = torch.empty((self.n, 32), dtype=torch.float32, device="cuda")
+            self.graph.features(mk, F[k], F[k + 1], out=X)
+            dmt = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+            st = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            self.graph.targets(mk, hist[k + 1], self.diag3, dm_out=dmt, s_out=st)
+            self.samples.append((X, mk, dmt, st))
         self.ctx.reset_warm_start()
 
     def close(self):
@@ -71,21 +71,19 @@ class Normalizer:
     the trained heads back to unscaled dm."""
 
     def __init__(self, films):
-        import torch
-        s1 = torch.zeros(32, dtype=torch.float64, device="cuda")
-        s2 = torch.zeros_like(s1)
+        s1, s2 = np.zeros(32), np.zeros(32)
         cnt = 0
         d2, dn = 0.0, 0
         for f in films:
             for X, m, dmt, st in f.samples:
-                Xd = X.double()
-                s1 += Xd.sum(dim=0)
-                s2 += (Xd * Xd).sum(dim=0)
+                a, b = f.graph.moments(X)
+                s1 += a
+                s2 += b
                 cnt += X.shape[0]
                 d2 += float((dmt * dmt).sum())
                 dn += dmt.shape[0]
-        mu = (s1 / cnt).cpu().numpy()
-        var = (s2 / cnt).cpu().numpy() - mu * mu
+        mu = s1 / cnt
+        var = s2 / cnt - mu * mu
         sd = np.sqrt(np.maximum(var, 0.0))
         self.mu = np.where(sd > 1e-12, mu, 0.0)
         self.sd = np.where(sd > 1e-12, sd, 1.0)
@@ -115,45 +113,56 @@ class Normalizer:
         th[o_wm:o_wm + 64 * 3 + 3] *= self.dm_rms
         return th
 
-    def save(self, path, theta, **meta):
+    def save(self, path, theta, net=None, **meta):
+        """npz with the folded parameters, standardization and run facts; with
+        `net` also the library's parameter file (path + '.mmgnn')."""
         import json
-        np.savez(path, theta=self.fold(theta), mu=self.mu, sd=self.sd, dm_rms=self.dm_rms,
-                 meta=json.dumps(meta))
+        th = self.fold(theta)
+        np.savez(path, theta=th, mu=self.mu, sd=self.sd, dm_rms=self.dm_rms, meta=json.dumps(meta))
+        if net is not None:
+            net.set_params(th)
+            net.save(str(path) + ".mmgnn")
+            net.set_params(theta)
 
 
 def load_net(path, ctx):
     """A network on `ctx`'s device with the parameters and input
-    standardization saved by Normalizer.save."""
-    z = np.load(path)
+    standardization saved by Normalizer.save (npz) or by mm_gnn_save."""
     net = B.Gnn(ctx)
+    if str(path).endswith(".mmgnn"):
+        return net.load(path)
+    z = np.load(path)
     net.set_params(z["theta"])
     net.set_input_norm(z["mu"], z["sd"])
     return net
 
 
-def train(films, net, epochs=10, lr=1e-3, w_s=1.0, seed=0, log=None, val=None):
+def train(films, net, epochs=10, lr=1e-3, w_s=1.0, seed=0, log=None, val=None, stop_at=None, after_epoch=None):
     """Adam over every sample of every film (standardized by Normalizer.apply),
-    shuffled each epoch (seeded)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    order = [(i, k) for i, f in enumerate(films) for k in range(len(f.samples))]
+    shuffled each epoch (seeded): one library call (mm_gnn_train) per epoch.
+    With stop_at (a time.perf_counter() value) no epoch starts that would end
+    after it (judged by the longest epoch so far); after_epoch(ep) runs after
+    every epoch (a checkpoint)."""
+    samples = [(f.graph, X, m, dmt, st, w) for f in films for (X, m, dmt, st, w) in f.samples]
     hist = []
+    longest = 0.0
     for ep in range(epochs):
-        rng.shuffle(order)
-        tot = 0.0
+        if stop_at is not None and ep > 0 and time.perf_counter() + longest > stop_at:
+            if log:
+                log(dict(stopped_before_epoch=ep))
+            break
         t0 = time.perf_counter()
-        for i, k in order:
-            f = films[i]
-            X, m, dmt, st, w = f.samples[k]
-            loss, _ = net.loss_grad(f.graph, X, m, dmt, st, inv_dm2=w, w_s=w_s, want_grad=False)
-            net.adam(lr)
-            tot += loss
-        rec = dict(epoch=ep, train_loss=tot / len(order), seconds=time.perf_counter() - t0)
+        loss = net.train(samples, 1, lr, w_s=w_s, seed=1000003 * seed + ep)[0]
+        rec = dict(epoch=ep, train_loss=float(loss), seconds=time.perf_counter() - t0)
         if val is not None:
             rec["val_dm_loss"] = evaluate(val, net, w_s=0.0)
             rec["val_s_loss"] = evaluate(val, net, w_s=1.0, dm=False)
         hist.append(rec)
+        longest = max(longest, time.perf_counter() - t0)
         if log:
             log(rec)
+        if after_epoch:
+            after_epoch(ep)
     return hist
 
 
@@ -169,7 +178,7 @@ def evaluate(films, net, w_s=1.0, dm=True):
     return tot / max(cnt, 1)
 
 
-def compare(work, net, jmax=4, modes=(0, 3), ctx=None):
+def compare(work, net, jmax=4, modes=(0, 3), ctx=None, precision=B.MM_FP64):
     """Plain (mode 0) against learned curves on one workload, same stopping
     rule. Returns per mode: seconds, evaluations, NCG and CG iterations,
     accepted starts, and the largest difference of <m> from the plain curve
@@ -183,7 +192,7 @@ def compare(work, net, jmax=4, modes=(0, 3), ctx=None):
     for mode in modes:
         ctx.reset_warm_start()
         t0 = time.perf_counter()
-        r = ctx.curve_learned(net, graph, mode, work.m0, work.fields, jmax=jmax)
+        r = ctx.curve_learned(net, graph, mode, work.m0, work.fields, jmax=jmax, precision=precision)
         dt = time.perf_counter() - t0
         st = r["stats"]
         rec = dict(seconds=dt, evals=int(sum(s["evals"] for s in st)), nli=int(sum(s["nli"] for s in st)),
@@ -218,21 +227,30 @@ def main(argv=None):
     ap.add_argument("--out", default="gnn_films.npz")
     ap.add_argument("--report", default="gnn_films.json")
     ap.add_argument("--modes", default="0,1,2,3", help="curve modes compared on the held-out films")
+    ap.add_argument("--jmax", type=int, default=4, help="inner iteration cap of the curves")
+    ap.add_argument("--fp32-data", action="store_true",
+                    help="training curves in the FP32-bulk mode (the minima agree with FP64 to round-off level)")
+    ap.add_argument("--eval-film", action="store_true",
+                    help="also compare plain and learned curves on the 1000 x 1000 x 10 nm film (FP64)")
+    ap.add_argument("--train-until", type=float, default=None,
+                    help="start no training epoch that would end later than this many seconds after the start "
+                         "(the parameters are saved after every epoch)")
     args = ap.parse_args(argv)
     t0 = time.perf_counter()
 
     def say(*a):
         print(f"[{time.perf_counter() - t0:7.1f}s]", *a, flush=True)
 
+    prec = B.MM_FP32_BULK if args.fp32_data else B.MM_FP64
     films = []
     for i in range(args.films):
         w = inputs.small_film(100 + i, lo=args.lo, hi=args.hi)
-        films.append(Film(w, n_probe=args.probes, probe_seed=500 + i))
+        films.append(Film(w, jmax=args.jmax, n_probe=args.probes, probe_seed=500 + i, precision=prec))
         say(f"film {i} {w.name} n={films[-1].n} plain curve {films[-1].t_curve:.2f}s")
     val = []
     for i in range(args.heldout):
         w = inputs.small_film(900 + i, lo=args.lo, hi=args.hi)
-        val.append(Film(w, n_probe=args.probes, probe_seed=1900 + i))
+        val.append(Film(w, jmax=args.jmax, n_probe=args.probes, probe_seed=1900 + i, precision=prec))
         say(f"held-out {i} {w.name} n={val[-1].n}")
     nz = Normalizer(films)
     nz.apply(films)
@@ -241,17 +259,36 @@ def main(argv=None):
     net.set_params(inputs.gnn_init(args.seed))
     untrained = dict(val_dm_loss=evaluate(val, net, w_s=0.0), val_s_loss=evaluate(val, net, w_s=1.0, dm=False))
     say("untrained", untrained)
-    hist = train(films, net, epochs=args.epochs, lr=args.lr, seed=args.seed, log=lambda r: say(r), val=val)
-    nz.save(args.out, net.get_params(), films=args.films, epochs=args.epochs, lr=args.lr, lo=args.lo,
-            hi=args.hi, probes=args.probes, seed=args.seed)
+    def checkpoint(ep):
+        nz.save(args.out, net.get_params(), net=net, films=args.films, epochs=ep + 1, lr=args.lr, lo=args.lo,
+                hi=args.hi, probes=args.probes, seed=args.seed, jmax=args.jmax, fp32_data=args.fp32_data)
+
+    stop_at = None if args.train_until is None else t0 + args.train_until
+    hist = train(films, net, epochs=args.epochs, lr=args.lr, seed=args.seed, log=lambda r: say(r), val=val,
+                 stop_at=stop_at, after_epoch=checkpoint)
+    if not hist:
+        checkpoint(-1)
     gains = []
+    modes = tuple(int(x) for x in args.modes.split(","))
     for f in val:
         dep = load_net(args.out, f.ctx)
-        res = compare(f.work, dep, modes=tuple(int(x) for x in args.modes.split(",")), ctx=f.ctx)
+        res = compare(f.work, dep, jmax=args.jmax, modes=modes, ctx=f.ctx)
         say(f.work.name, res)
         gains.append(dict(name=f.work.name, n=f.n, **{f"mode{k}": v for k, v in res.items()}))
         dep.close()
-    rep = dict(untrained=untrained, history=hist, heldout=gains, seconds=time.perf_counter() - t0)
+    rep = dict(untrained=untrained, history=hist, heldout=gains)
+    if args.eval_film:
+        for f in films + val:
+            f.close()
+        w = inputs.film()
+        ctx = B.Context(0).upload(w.mesh)
+        dep = load_net(args.out, ctx)
+        res = compare(w, dep, jmax=w.jmax, modes=(0, 3), ctx=ctx)
+        say(w.name, res)
+        rep["film_1000nm"] = {f"mode{k}": v for k, v in res.items()}
+        dep.close()
+        ctx.close()
+    rep["seconds"] = time.perf_counter() - t0
     with open(args.report, "w") as fh:
         json.dump(rep, fh, indent=1)
     say("done")

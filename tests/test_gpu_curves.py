@@ -106,7 +106,9 @@ def _switch_index(m_avg_z):
 
 def _compare_curves(g, rg):
     """Per-field agreement of a GPU curve with the stored oracle curve,
-    allowing the switching step to move by one field (S24 (ii))."""
+    allowing the switching step to move by one field (after a switching
+    event several minima are correct, and either curve may reach the new
+    branch one field earlier)."""
     scale = np.maximum(np.abs(g["E"]), np.abs(g["parts"][:, :4]).sum(axis=1))
     dE = np.abs(rg["E"] - g["E"]) / scale
     dmav = np.abs(rg["m_avg"] - g["m_avg"]).max(axis=1)
@@ -153,7 +155,7 @@ def test_hard_cube_fp32_bulk_error_per_field(B, hard_gold):
 
 
 def test_hard_cube_steps_match_oracle(B, hard_gold):
-    """Per-step parity (S24 (i)): from the oracle's own state m_{k-1} at four
+    """Per-step parity: from the oracle's own state m_{k-1} at four
     steps, the switching step among them, one minimization at field k in the
     headline's mode (multigrid CG, j_max 1) in FP64 reaches the oracle's
     minimum from the same start."""

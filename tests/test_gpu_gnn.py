@@ -196,6 +196,73 @@ def test_fp32_debug_mode_matches_the_fp64_oracle(B):
     ctx.close()
 
 
+def test_targets_and_moments_match_oracle(B):
+    """mm_gnn_targets against the oracle's dm* and s*, mm_gnn_moments
+    against FP64 sums of the same features."""
+    mesh = inputs.small_box((5, 4, 3), 3.0, Ms=1.61 / MU0, A=7.7e-12, K1=4.3e6, axis=(0.2, 0.1, 0.97))
+    ctx, gr, net, o, og = setup(B, mesh)
+    rng = np.random.default_rng(17)
+    m = inputs.random_unit(o.nm, 5)
+    m1 = m + 0.05 * rng.standard_normal(m.shape)
+    m1 /= np.linalg.norm(m1, axis=1, keepdims=True)
+    diag3 = np.abs(rng.standard_normal((o.nm, 3)))
+    dm, s = gr.targets(m, m1, diag3)
+    D = o.jacobi_diag()
+    dmo = G.dm_target(m, m1)
+    so = G.s_target(diag3, m, D)
+    assert np.abs(dm - dmo).max() <= 1e-14 * np.abs(dmo).max()
+    assert np.abs(s - so).max() <= 1e-14 * np.abs(so).max()
+    X, _, _, _ = rand_inputs(gr.n, 9)
+    s1, s2 = gr.moments(X)
+    Xd = X.astype(np.float64)
+    assert np.abs(s1 - Xd.sum(axis=0)).max() <= 1e-12 * np.abs(Xd).sum()
+    assert np.abs(s2 - (Xd * Xd).sum(axis=0)).max() <= 1e-12 * (Xd * Xd).sum()
+    net.close()
+    gr.close()
+    ctx.close()
+
+
+def test_save_load_and_seeded_training(B, tmp_path):
+    """mm_gnn_save / mm_gnn_load round trip (parameters, standardization,
+    the forward pass bit for bit); mm_gnn_train from the same start and seed
+    gives the same parameters twice, and lowers the loss."""
+    import torch
+    ctx, gr, net, o, og = setup(B, mesh_small())
+    theta = inputs.gnn_init(5, head_scale=1.0)
+    net.set_params(theta)
+    mu = np.linspace(-0.5, 0.5, 32)
+    sd = np.linspace(0.5, 2.0, 32)
+    net.set_input_norm(mu, sd)
+    X, m, dmt, st = rand_inputs(gr.n, 6)
+    path = str(tmp_path / "net.mmgnn")
+    net.save(path)
+    net2 = B.Gnn(ctx).load(path)
+    np.testing.assert_array_equal(net2.get_params(), net.get_params())
+    a, b = net.forward(gr, X, m), net2.forward(gr, X, m)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    with pytest.raises(B.MMError):
+        bad = tmp_path / "bad.mmgnn"
+        bad.write_bytes(b"not a network")
+        net2.load(str(bad))
+    dev = [torch.tensor(v, device="cuda") for v in (X, m, dmt, st)]
+    samples = [(gr, dev[0], dev[1], dev[2], dev[3], 1.0)] * 4
+    runs = []
+    for _ in range(2):
+        n = B.Gnn(ctx)
+        n.set_params(theta)
+        losses = n.train(samples, 3, 1e-3, seed=42)
+        runs.append((n.get_params(), losses))
+        n.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    assert runs[0][1][-1] < runs[0][1][0]
+    net2.close()
+    net.close()
+    gr.close()
+    ctx.close()
+
+
 def test_adam_step_matches_oracle(B):
     ctx, gr, net, o, og = setup(B, mesh_small())
     theta = inputs.gnn_init(13, head_scale=1.0)

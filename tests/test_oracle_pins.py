@@ -144,7 +144,7 @@ def test_zeeman_uniform_and_linear(oracle_mod):
     assert abs(o.lumped().sum() - V) < 1e-12 * V
 
 
-def test_uniform_state_config0_analytic(oracle_mod):
+def test_uniform_state_soft_cube_analytic(oracle_mod):
     """Soft cube at +1 T along (0.01, 0.01, 1), m = z: E_ex = E_an = 0 and
     E_Z = -64000 * h * (h_dir . z) in units of mu0 Ms^2 nm^3."""
     w = inputs.soft_cube()
