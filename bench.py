@@ -8,8 +8,9 @@ field along x from +50 mT to -50 mT in 1 mT steps (101 values), j_max 10,
 every minimization run to max |m x h_eff| < 1e-6 (reduced units). Two forms
 reach the same torque tolerance:
 
-  * learned + FP32 (the value): the network's warm start and Jacobi scaling at
-    every field after the first, FP32-stored operators with FP64 reductions;
+  * learned + FP32 (the value): the network's warm start at every field after
+    the first (with --learn-mode start+scale also its Jacobi scaling),
+    FP32-stored operators with FP64 reductions;
   * plain FP64: the method without the network, every operator in FP64.
 
 One step is one stretch of the curve: the field list is split into `--steps`
@@ -60,7 +61,7 @@ TRAFFIC = {
 # multigrid where it is faster (measured), Jacobi on the thin film (a few dozen
 # Jacobi iterations per solve)
 AUTO_PREC = {"hard_cube": "amg", "polycrystal": "amg", "film": "jacobi", "batch64": "amg"}
-NET = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_large.npz")
+NET = os.path.join(ROOT, "paper_1801_03690_amd", "data", "gnn_films_600_1400.npz")
 
 
 def measured_traffic(workload, precision, pprec):
@@ -158,6 +159,8 @@ def main():
     ap.add_argument("--jmax", type=int, default=None,
                     help="inner iteration cap of the preconditioner solve (default: the workload's)")
     ap.add_argument("--net", default=NET, help="trained network of the learned form (film)")
+    ap.add_argument("--learn-mode", choices=["start", "start+scale"], default="start",
+                    help="learned form: the warm start alone, or with the learned Jacobi scaling")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison curve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-fields", type=int, default=3, help="field steps of the oracle sample")
@@ -266,10 +269,11 @@ def bench_film(args):
         return parts, times
 
     # --- learned + FP32 (the value)
+    lmode = binding.MM_LEARN_START | (binding.MM_LEARN_SCALE if args.learn_mode == "start+scale" else 0)
     set_form(o_l, "learned_fp32")
     steps = chunks_of(nf, args.steps)
     if args.warmup:
-        run_steps(chunks_of(nf, max(args.steps, args.warmup))[: args.warmup], o_l, 3)
+        run_steps(chunks_of(nf, max(args.steps, args.warmup))[: args.warmup], o_l, lmode)
         log(f"warmup: {args.warmup} steps")
     torch.cuda.synchronize()
     ctx.profile(-1)
@@ -277,7 +281,7 @@ def bench_film(args):
     ctx.profile_kernels(-1)
     ctx.profile_kernels(1)
     t0 = time.perf_counter()
-    parts, times = run_steps(steps, o_l, 3)
+    parts, times = run_steps(steps, o_l, lmode)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile(0)
@@ -305,7 +309,9 @@ def bench_film(args):
         "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
         "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, {nf} fields "
                                f"+50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, tol 1e-6; learned warm "
-                               f"start + Jacobi scaling, FP32 bulk; the curve in {min(args.steps, nf)} chunks",
+                               f"start{' + Jacobi scaling' if args.learn_mode == 'start+scale' else ''}, FP32 bulk; "
+                               f"the curve in {min(args.steps, nf)} chunks",
+                   "network": os.path.basename(args.net),
                    "poisson_preconditioner": args.poisson_prec, "n_mag": info["n_mag"], "n_pot": info["n_pot"],
                    "nnz_K": info["nnz_K"], "nnz_C_blocks": info["nnz_C_blocks"], "pcg_shapes": shapes},
         "learned_fp32": learned,
@@ -433,7 +439,8 @@ def bench_curve(args):
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
         amg = ctx.amg_info()
-        log(f"multigrid levels {amg['rows']} built in {amg['setup_seconds']:.2f}s")
+        log(f"multigrid levels {amg['rows']} (operator entries {amg['nnz_A']}, prolongator entries "
+            f"{amg['nnz_P']}) built in {amg['setup_seconds']:.2f}s")
     shape = (16, [1])
     if not args.no_tune:
         nw, spw = tune(ctx, binding, args)
