@@ -375,6 +375,14 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
 // lanes per row of a CSR kernel: chosen per matrix from its mean row length
 #define MMNCG_GL_SWITCH(gl, ...)            \
     switch (gl) {                           \
+        case 1: {                           \
+            constexpr int GL = 1;           \
+            __VA_ARGS__;                    \
+        } break;                            \
+        case 2: {                           \
+            constexpr int GL = 2;           \
+            __VA_ARGS__;                    \
+        } break;                            \
         case 4: {                           \
             constexpr int GL = 4;           \
             __VA_ARGS__;                    \
