@@ -664,9 +664,11 @@ AmgState *amg_get(mm_ctx *c) {
     }
     D.u = dalloc_n<double>(c, N[0]);
     D.rf = dalloc_n<double>(c, N[0]);
+    D.wf = dalloc_n<double>(c, N[0]);
     F.u = dalloc_n<float>(c, N[0]);
     HIPCHK(hipMemsetAsync(D.u, 0, (size_t)N[0] * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(D.rf, 0, (size_t)N[0] * sizeof(double), c->stream));
+    HIPCHK(hipMemsetAsync(D.wf, 0, (size_t)N[0] * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(F.u, 0, (size_t)N[0] * sizeof(float), c->stream));
     sync(c);
     // algorithmic bytes of one CG iteration per instance: the fine matrix

@@ -20,7 +20,7 @@
 //                  the prolongation z = omega D^-1 r + P_0 y_1;
 //   k_amg_post0    u = z + omega D^-1 (r - K z) on the fine level, partial
 //                  gamma;
-//   k_amg_w        w = K u into the records, partials delta and r.r.
+//   k_amg_w        w = K u into a plain vector, partials delta and r.r.
 // Every kernel of an iteration skips the rows of an instance whose sticky
 // flag is up (the flag only changes inside k_amg_iter, which every later
 // launch follows in stream order): the row-map kernels by their blocks'
@@ -228,11 +228,12 @@ __global__ __launch_bounds__(NW * 64) void k_amg_post0(SV<MT> K, RowMap M, const
     if (part) write_part<1, NW>(acc, 0u, part + (size_t)gslot * M.nblk, M.nblk, tl.b, sh);
 }
 
-// fine level: w = K u into the w field of the record (the other fields were
-// written by k_amg_iter, or by the start); partials (delta = w.u, r.r, with r
-// at r[row * rs]) into slots wslot, wslot + 1
+// fine level: w = K u into the plain vector wf (the records' w field is not
+// used by the multigrid CG: a store of one 8-byte field into 32-byte records
+// writes whole records back); partials (delta = w.u, r.r, with r at
+// r[row * rs]) into slots wslot, wslot + 1
 template <class MT, class VT, int NW, bool NT>
-__global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<VT> *__restrict__ q,
+__global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, VT *__restrict__ wf,
                                                    const VT *__restrict__ r, int rs, const VT *__restrict__ u,
                                                    double *__restrict__ part, int wslot, const PcgState *st) {
     Tile tl = tile_of(M);
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
         const int row = s * 64 + ln;
         if (row < rend) {
             const VT ri = r[(int64_t)row * rs];
-            q[row].w = ku;
+            wf[row] = ku;
             acc[0] += (double)ku * (double)u[row];
             acc[1] += (double)ri * (double)ri;
         }
@@ -253,11 +254,11 @@ __global__ __launch_bounds__(NW * 64) void k_amg_w(SV<MT> K, RowMap M, PcgNode<V
     write_part<2, NW>(acc, 0u, part + (size_t)wslot * M.nblk, M.nblk, tl.b, sh);
 }
 
-// K D^-1 times the r, w and s fields of the neighbour records (one row of
-// the slice, this lane)
+// K D^-1 times r, w and s of the neighbours (r, s and D^-1 from the records,
+// w from the plain vector wf; one row of the slice, this lane)
 template <class MT, class VT, bool NT>
-__device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0, VT &pa,
-                                        VT &pb, VT &pc) {
+__device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const PcgNode<VT> *__restrict__ q0,
+                                        const VT *__restrict__ wf, VT &pa, VT &pb, VT &pc) {
     constexpr int G = sizeof(VT) == 4 ? 8 : 4;
     const int64_t base = K.sptr[s];
     const int wd = (int)((K.sptr[s + 1] - base) >> 6);
@@ -273,28 +274,34 @@ __device__ __forceinline__ void row_abc(const SV<MT> &K, int s, int ln, const Pc
             vv[k] = in ? (VT)(NT ? __builtin_nontemporal_load(K.val + e) : K.val[e]) : (VT)0;
         }
         PcgNode<VT> nq[G];
+        VT nw[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) nq[k] = q0[cc[k]];
+        for (int k = 0; k < G; ++k) {
+            nq[k] = q0[cc[k]];
+            nw[k] = wf[cc[k]];
+        }
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             const VT kd = vv[k] * nq[k].d;
             pa += kd * nq[k].r;
-            pb += kd * nq[k].w;
+            pb += kd * nw[k];
             pc += kd * nq[k].s;
         }
     }
 }
 
-// the updates of one CG iteration of parity par (reads records q[par] and the
-// partials P[par]; writes records q[par ^ 1] with w = 0, filled in by
-// k_amg_w, and r_new once more as the plain vector rf, which the rest of the
-// iteration reads instead of the records) and t = r_new - omega K D^-1 r_new,
+// the updates of one CG iteration of parity par (reads records q[par], w in
+// wf and the partials P[par]; writes records q[par ^ 1] (their w field unused:
+// k_amg_w writes the new w to wf), and r_new once more as the plain vector rf,
+// which the rest of the iteration reads instead of the records) and
+// t = r_new - omega K D^-1 r_new,
 // where K D^-1 r_new = A - alpha (B + beta C) with A, B, C the products of
 // K D^-1 with the old r, w, s
 template <class MT, class VT, class XT, class CT, int NW, bool NT>
 __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVecs<VT> v, XT *__restrict__ x,
                                                       const VT *__restrict__ uu, CT *__restrict__ tt,
-                                                      VT *__restrict__ rf, const VT *__restrict__ om,
+                                                      VT *__restrict__ rf, const VT *__restrict__ wf,
+                                                      const VT *__restrict__ om,
                                                       PcgState *__restrict__ st, int par,
                                                       const double *__restrict__ part) {
     Tile tl = tile_of(M);
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
     const double tol2 = si->tol2, gprev = si->gamma[par ^ 1], aprev = si->alpha[par ^ 1];
     const int sf = tl.s0 + wave_id();
     VT pa = 0, pb = 0, pc = 0;
-    if (sf < tl.s1) row_abc<MT, VT, NT>(K, sf, ln, q0, pa, pb, pc);
+    if (sf < tl.s1) row_abc<MT, VT, NT>(K, sf, ln, q0, wf, pa, pb, pc);
     block_reduce<3, NW>(g3, 0u, sh);
     const double gam = g3[0], del = g3[1], rr = g3[2];
     if (rr <= tol2) {
@@ -336,12 +343,13 @@ __global__ __launch_bounds__(NW * 64) void k_amg_iter(SV<MT> K, RowMap M, PcgVec
     }
     const VT a = (VT)alpha, bt = (VT)beta, omega = om[tl.inst];
     for (int s = sf; s < tl.s1; s += NW) {
-        if (s != sf) row_abc<MT, VT, NT>(K, s, ln, q0, pa, pb, pc);
+        if (s != sf) row_abc<MT, VT, NT>(K, s, ln, q0, wf, pa, pb, pc);
         const int row = s * 64 + ln;
         if (row < rend) {
             const PcgNode<VT> me = q0[row];
             const VT ui = uu[row];
-            const VT sn = bt != (VT)0 ? me.w + bt * me.s : me.w;
+            const VT wi = wf[row];
+            const VT sn = bt != (VT)0 ? wi + bt * me.s : wi;
             const VT pn = bt != (VT)0 ? ui + bt * p[row] : ui;
             const VT rn = me.r - a * sn;
             const VT kdr = bt != (VT)0 ? pa - a * (pb + bt * pc) : pa - a * pb;
@@ -471,6 +479,7 @@ struct FineArgs {
     const RT *omega;   // per instance, the fine smoothing weight in RT
     RT *u;             // preconditioned residual
     RT *rf;            // the residual as a plain vector (written by k_amg_iter)
+    RT *wf;            // w = K u as a plain vector (written by k_amg_w)
 };
 
 template <class VT>
@@ -502,7 +511,7 @@ void fine_cycle_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT
                                              cg ? a.part : (double *)nullptr, kP0, (const PcgState *)nullptr))
     if (cg)
         MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                                 view<VT>(*a.K), M, q, r, rs, (const RT *)fa.u, a.part, kP0 + 1,
+                                                 view<VT>(*a.K), M, fa.wf, r, rs, (const RT *)fa.u, a.part, kP0 + 1,
                                                  (const PcgState *)nullptr))
 }
 
@@ -524,8 +533,8 @@ void amg_iter_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, 
     PcgNode<RT> *q1 = v.q[par ^ 1];
     const int ws = par ? kP0 : kP1;  // this iteration's new partials
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_amg_iter<VT, RT, XT, VT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0,
-                                             s, view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.rf, fa.omega,
-                                             a.st, par, (const double *)a.part))
+                                             s, view<VT>(*a.K), M, v, x, (const RT *)fa.u, f.t, fa.rf,
+                                             (const RT *)fa.wf, fa.omega, a.st, par, (const double *)a.part))
     const RT *rf = fa.rf;
     // a single dense level takes b from the records (its plain-b path loads
     // VT vectors padded with zeros, which rf is not)
@@ -535,7 +544,7 @@ void amg_iter_nt(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, 
                                              view<VT>(*a.K), M, rf, 1, post_wd(g), (const VT *)f.z, fa.u, a.part,
                                              ws, (const PcgState *)a.st);
                     hipLaunchKernelGGL((k_amg_w<VT, RT, NW, NT>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<VT>(*a.K), M, q1, rf, 1, (const RT *)fa.u, a.part, ws + 1,
+                                       view<VT>(*a.K), M, fa.wf, rf, 1, (const RT *)fa.u, a.part, ws + 1,
                                        (const PcgState *)a.st))
 }
 
@@ -547,13 +556,13 @@ void amg_iter(const PcgLaunch &a, const AmgLaunch<VT> &g, const FineArgs<VT, RT>
 }
 
 FineArgs<double, double> fine64(const PcgLaunch &a, const AmgLaunch<double> &g) {
-    return FineArgs<double, double>{a.invD, g.omega, g.u, g.rf};
+    return FineArgs<double, double>{a.invD, g.omega, g.u, g.rf, g.wf};
 }
 FineArgs<float, float> fine32(const PcgLaunch &a, const AmgLaunch<float> &g) {
-    return FineArgs<float, float>{a.invD32, g.omega, g.u, (float *)nullptr};
+    return FineArgs<float, float>{a.invD32, g.omega, g.u, (float *)nullptr, (float *)nullptr};
 }
 FineArgs<float, double> finemix(const PcgLaunch &a, const AmgLaunch<double> &g64) {
-    return FineArgs<float, double>{a.invD, g64.omega, g64.u, g64.rf};
+    return FineArgs<float, double>{a.invD, g64.omega, g64.u, g64.rf, g64.wf};
 }
 
 }  // namespace

@@ -260,6 +260,7 @@ struct AmgLaunch {
     VT *u = nullptr;               // level 0: the preconditioned residual M r
     VT *rf = nullptr;              // level 0: the CG residual r as a plain vector (the records hold it
                                    // too, among three other fields the cycle does not read)
+    VT *wf = nullptr;              // level 0: w = K u of the CG as a plain vector
     const VT *omega = nullptr;     // per instance: the fine smoothing weight
     bool single = true;            // one instance: the cycle's kernels read its flag without the row tables
 };
