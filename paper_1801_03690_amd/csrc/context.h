@@ -128,6 +128,13 @@ struct mm_ctx {
            *dscale = nullptr, *tmp3 = nullptr;
     double *gy = nullptr;  // per instance <g, y> of the last direction, and its snapshot (2 x ninst)
     double *u = nullptr, *b = nullptr, *cr = nullptr, *cq = nullptr, *usave = nullptr;
+    // the line search's potentials: ux at the accepted state, ut at the last
+    // trial of role 1 (the start of a role-2 trial's solve is interpolated
+    // between them); per-instance operations staged in pinned memory, two
+    // slots (before and after an evaluation round) of ninst each
+    double *ux = nullptr, *ut = nullptr;
+    int *hpo = nullptr, *dpo = nullptr;
+    double *hpr = nullptr, *dpr = nullptr;
     PcgNode<double> *q64[2] = {};  // CG node records by parity
     PcgNode<float> *q32[2] = {};
     double *p64 = nullptr;         // CG directions

@@ -177,15 +177,31 @@ __device__ __forceinline__ void row_block6(const SV<V> &A, int s, int ln, const 
     }
 }
 
-// scalar row times a plain vector
-template <class V, class X>
+// scalar row times a plain vector, entries in groups of G as above
+template <int G, class V, class X>
 __device__ __forceinline__ double row_scalar(const SV<V> &A, int s, int ln, const X *__restrict__ x) {
-    int64_t base = A.sptr[s];
-    int w = (int)((A.sptr[s + 1] - base) >> 6);
+    const int64_t base = A.sptr[s];
+    const int w = (int)((A.sptr[s + 1] - base) >> 6);
     double acc = 0.0;
-    for (int k = 0; k < w; ++k) {
-        int64_t e = base + 64 * k + ln;
-        acc += (double)A.val[e] * (double)x[A.col[e]];
+#pragma unroll 1
+    for (int k0 = 0; k0 < w; k0 += G) {
+        int cc[G];
+        V vv[G];
+        double xx[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k0 + k < w) {
+                const int64_t e = base + 64 * (k0 + k) + ln;
+                cc[k] = A.col[e];
+                vv[k] = A.val[e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (k0 + k < w) xx[k] = (double)x[cc[k]];
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (k0 + k < w) acc += (double)vv[k] * xx[k];
     }
     return acc;
 }

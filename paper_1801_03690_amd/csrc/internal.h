@@ -167,6 +167,12 @@ void launch_mavg(const RowMap &M, const double *m, const double *L, double *part
 void launch_lambda(const RowMap &M, const double *m, const double *G, double *lam, hipStream_t s);
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 void launch_fill(int64_t n, double *x, double v, hipStream_t s);
+// per-instance operations on the scalar potential over the potential rows M:
+// op[i] = 0 none, 1 ux <- u, 2 ut <- u, 3 ux <- ut, 4 u <- ux + rho[i] (ut - ux),
+// 5 ux <- u and ut <- u
+enum { POT_NONE = 0, POT_UX_U = 1, POT_UT_U = 2, POT_UX_UT = 3, POT_INTERP = 4, POT_BOTH_U = 5 };
+void launch_pot_op(const RowMap &M, const int *op, const double *rho, double *u, double *ux, double *ut,
+                   hipStream_t s);
 void launch_gather(int64_t n, const int *idx, const double *in, double *out, hipStream_t s);
 
 // --- scalar-potential CG (poisson.hip) ---

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scalar(SV<V> A, RowMap M, const
     if (t.inst < 0) return;
     const int rend = M.rend[t.inst], ln = lane_id();
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
-        double o = row_scalar(A, s, ln, x);
+        double o = row_scalar<4>(A, s, ln, x);
         int row = s * 64 + ln;
         if (row < rend) y[row] = o;
     }
@@ -597,6 +597,33 @@ __global__ void k_to_f32(int64_t n, const double *__restrict__ x, float *__restr
     if (i < n) y[i] = (float)x[i];
 }
 
+// per-instance operations on the scalar potential (see launch_pot_op)
+__global__ __launch_bounds__(kBlock) void k_pot_op(RowMap M, const int *__restrict__ op,
+                                                   const double *__restrict__ rho, double *__restrict__ u,
+                                                   double *__restrict__ ux, double *__restrict__ ut) {
+    Tile t = tile_of(M);
+    if (t.inst < 0) return;
+    const int o = op[t.inst];
+    if (o == POT_NONE) return;
+    const double q = rho[t.inst];
+    const int rend = M.rend[t.inst];
+    for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
+        const int i = s * 64 + lane_id();
+        if (i >= rend) continue;
+        switch (o) {
+            case POT_UX_U: ux[i] = u[i]; break;
+            case POT_UT_U: ut[i] = u[i]; break;
+            case POT_UX_UT: ux[i] = ut[i]; break;
+            case POT_INTERP: u[i] = ux[i] + q * (ut[i] - ux[i]); break;
+            default: {
+                const double v = u[i];
+                ux[i] = v;
+                ut[i] = v;
+            } break;
+        }
+    }
+}
+
 __global__ void k_fill(int64_t n, double *__restrict__ x, double v) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] = v;
@@ -728,6 +755,11 @@ void launch_fill(int64_t n, double *x, double v, hipStream_t s) {
     if (n <= 0) return;
     int64_t g = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(kBlock), 0, s, n, x, v);
+}
+
+void launch_pot_op(const RowMap &M, const int *op, const double *rho, double *u, double *ux, double *ut,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_pot_op, dim3(M.nblk), dim3(kBlock), 0, s, M, op, rho, u, ux, ut);
 }
 void launch_gather(int64_t n, const int *idx, const double *in, double *out, hipStream_t s) {
     if (n <= 0) return;

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_residual(SV<MT> K, RowMap M, co
     const int rend = M.rend[t.inst], ln = lane_id();
     double acc[2] = {0, 0};
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
-        double ku = row_scalar(K, s, ln, u);
+        double ku = row_scalar<sizeof(MT) == 4 ? 8 : 4>(K, s, ln, u);
         int row = s * 64 + ln;
         if (row < rend) {
             double bi = b[row];
@@ -99,39 +99,56 @@ __global__ __launch_bounds__(NW * 64) void k_pcg_start32(RowMap M, const double 
     }
 }
 
-// w = K D^-1 r for the start residual (r in the records of buffer 0); sets
-// w, s = 0 and d = D^-1 in buffer 0 and d in buffer 1; partials (gamma,
-// delta, r.r) into P0. Only the r fields of neighbours are read, and no r
-// field is written. Active instances: act[i] when act is given, else those
-// with an inner solve.
+// w = K D^-1 r for the start residual (r in the records of buffer 0); writes
+// whole records {r, w, 0, D^-1} of buffer 0 (a store of single fields would
+// write the whole record back anyway; the first iteration writes whole
+// records of buffer 1). Neighbours read only the r field, which the store
+// rewrites with the value it already holds. Partials (gamma, delta, r.r)
+// into P0. Entries go in groups as in row_abc. Active instances: act[i] when
+// act is given, else those with an inner solve.
 template <class MT, class VT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_pcg_start_w(SV<MT> K, RowMap M, const int *__restrict__ act,
                                                      const double *__restrict__ pin, PcgNode<VT> *__restrict__ q0,
-                                                     PcgNode<VT> *__restrict__ q1, const VT *__restrict__ invD,
-                                                     double *__restrict__ part) {
+                                                     const VT *__restrict__ invD, double *__restrict__ part) {
     Tile t = tile_of(M);
     if (t.inst < 0) return;
     if (act ? !act[t.inst] : !(pin[4 * t.inst + 1] > 0.0)) return;
     __shared__ double sh[NW * 3];
     const int rend = M.rend[t.inst], ln = lane_id();
     double acc[3] = {0, 0, 0};
+    constexpr int G = sizeof(VT) == 4 ? 8 : 4;
     for (int s = t.s0 + wave_id(); s < t.s1; s += NW) {
-        int64_t base = K.sptr[s];
-        int wd = (int)((K.sptr[s + 1] - base) >> 6);
+        const int64_t base = K.sptr[s];
+        const int wd = (int)((K.sptr[s + 1] - base) >> 6);
         VT wv = 0;
-        for (int k = 0; k < wd; ++k) {
-            int64_t e = base + 64 * k + ln;
-            int c = K.col[e];
-            wv += (VT)K.val[e] * (invD[c] * q0[c].r);
+#pragma unroll 1
+        for (int k0 = 0; k0 < wd; k0 += G) {
+            int cc[G];
+            VT vv[G], dd[G], rn[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k0 + k < wd) {
+                    const int64_t e = base + 64 * (k0 + k) + ln;
+                    cc[k] = K.col[e];
+                    vv[k] = (VT)K.val[e];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k0 + k < wd) {
+                    dd[k] = invD[cc[k]];
+                    rn[k] = q0[cc[k]].r;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                if (k0 + k < wd) wv += vv[k] * (dd[k] * rn[k]);
         }
         int row = s * 64 + ln;
         if (row < rend) {
             const VT ri = q0[row].r, di = invD[row];
             const VT ui = di * ri;
-            q0[row].w = wv;
-            q0[row].s = (VT)0;
-            q0[row].d = di;
-            q1[row].d = di;
+            q0[row] = PcgNode<VT>{ri, wv, (VT)0, di};
             acc[0] += (double)ri * (double)ui;
             acc[1] += (double)wv * (double)ui;
             acc[2] += (double)ri * (double)ri;
@@ -348,7 +365,7 @@ void launch_pcg_init64(const PcgLaunch &a, const int *act, double rtol2, hipStre
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_residual<double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
                                              view<double>(*a.K), M, act, a.b, a.u, &a.v64.q[0]->r, 4, a.part);
                     hipLaunchKernelGGL((k_pcg_start_w<double, double, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<double>(*a.K), M, act, a.pin, a.v64.q[0], a.v64.q[1], a.invD, a.part))
+                                       view<double>(*a.K), M, act, a.pin, a.v64.q[0], a.invD, a.part))
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, rtol2, 0, act,
                        a.pin, a.st);
 }
@@ -366,8 +383,8 @@ void launch_pcg_init32(const PcgLaunch &a, hipStream_t s) {
     MMNCG_NW_SWITCH(a.nw, hipLaunchKernelGGL((k_pcg_start32<NW>), dim3(M.nblk), dim3(NW * 64), 0, s, M, a.pin,
                                              (const double *)a.r64, a.x32, a.v32.q[0]);
                     hipLaunchKernelGGL((k_pcg_start_w<float, float, NW>), dim3(M.nblk), dim3(NW * 64), 0, s,
-                                       view<float>(*a.K), M, (const int *)nullptr, a.pin, a.v32.q[0], a.v32.q[1],
-                                       a.invD32, a.part))
+                                       view<float>(*a.K), M, (const int *)nullptr, a.pin, a.v32.q[0], a.invD32,
+                                       a.part))
     hipLaunchKernelGGL(k_pcg_init_fin, dim3(M.ninst), dim3(kFinBlock), 0, s, M, (const double *)a.part, 0.0, 1,
                        (const int *)nullptr, a.pin, a.st);
 }

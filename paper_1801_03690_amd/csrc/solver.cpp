@@ -70,7 +70,8 @@ void dfree(mm_ctx *c, void *p) {
 }
 
 void free_host_ctl(mm_ctx *c) {
-    for (void **p : {(void **)&c->hci, (void **)&c->hcd, (void **)&c->hsc, (void **)&c->hpst}) {
+    for (void **p : {(void **)&c->hci, (void **)&c->hcd, (void **)&c->hsc, (void **)&c->hpst, (void **)&c->hpo,
+                     (void **)&c->hpr}) {
         if (*p) (void)hipHostFree(*p);
         *p = nullptr;
     }
@@ -531,7 +532,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     c->dscale = dalloc_n<double>(c, RM);
     c->gy = dalloc_n<double>(c, 2 * (size_t)ni);
     HIPCHK(hipMemsetAsync(c->gy, 0, 2 * (size_t)ni * sizeof(double), c->stream));
-    for (double **p : {&c->u, &c->b, &c->cr, &c->cq, &c->usave}) *p = dalloc_n<double>(c, RP);
+    for (double **p : {&c->u, &c->b, &c->cr, &c->cq, &c->usave, &c->ux, &c->ut}) *p = dalloc_n<double>(c, RP);
     for (auto &q : c->q64) q = dalloc_n<PcgNode<double>>(c, RP);
     for (auto &q : c->q32) q = dalloc_n<PcgNode<float>>(c, RP);
     c->p64 = dalloc_n<double>(c, RP);
@@ -542,11 +543,15 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
     c->dci = dalloc_n<int>(c, 11 * (size_t)ni);
     c->dcd = dalloc_n<double>(c, 8 * (size_t)ni);
+    c->dpo = dalloc_n<int>(c, 2 * (size_t)ni);
+    c->dpr = dalloc_n<double>(c, 2 * (size_t)ni);
     c->dsc = dalloc_n<double>(c, (size_t)SC_PER * ni);
     HIPCHK(hipHostMalloc((void **)&c->hci, 11 * (size_t)ni * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->hcd, 8 * (size_t)ni * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->hsc, (size_t)SC_PER * ni * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->hpst, (size_t)ni * sizeof(PcgState), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hpo, 2 * (size_t)ni * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hpr, 2 * (size_t)ni * sizeof(double), hipHostMallocDefault));
     std::memset(c->hci, 0, 11 * (size_t)ni * sizeof(int));
     std::memset(c->hcd, 0, 8 * (size_t)ni * sizeof(double));
     std::memset(c->hsc, 0, (size_t)SC_PER * ni * sizeof(double));
@@ -561,7 +566,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     for (double *p : {c->gprev, c->d, c->y, c->pr, c->pp, c->pq, c->tmp3})
         HIPCHK(hipMemsetAsync(p, 0, 3 * RM * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->dscale, 0, RM * sizeof(double), c->stream));
-    for (double *p : {c->u, c->b, c->cr, c->cq, c->usave})
+    for (double *p : {c->u, c->b, c->cr, c->cq, c->usave, c->ux, c->ut})
         HIPCHK(hipMemsetAsync(p, 0, RP * sizeof(double), c->stream));
     for (auto *q : c->q64) HIPCHK(hipMemsetAsync(q, 0, RP * sizeof(PcgNode<double>), c->stream));
     for (auto *q : c->q32) HIPCHK(hipMemsetAsync(q, 0, RP * sizeof(PcgNode<float>), c->stream));
@@ -1353,6 +1358,27 @@ struct Learned {
     double h_prev[3] = {0, 0, 0};  // reduced units
 };
 
+// Per-instance operations on the scalar potential (launch_pot_op) staged in
+// slot `slot` (0 before an evaluation round, 1 after it) of the pinned
+// arrays: the driver synchronizes at least once between two uses of a slot.
+void pot_ops(mm_ctx *c, int slot, const std::vector<int> &op, const std::vector<double> &rho) {
+    const int n = c->ninst;
+    bool any = false;
+    for (int i = 0; i < n; ++i) any = any || op[i] != POT_NONE;
+    if (!any) return;
+    int *ho = c->hpo + (size_t)slot * n;
+    double *hr = c->hpr + (size_t)slot * n;
+    for (int i = 0; i < n; ++i) {
+        ho[i] = op[i];
+        hr[i] = rho[i];
+    }
+    int *dop = c->dpo + (size_t)slot * n;
+    double *drho = c->dpr + (size_t)slot * n;
+    HIPCHK(hipMemcpyAsync(dop, ho, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(drho, hr, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_pot_op(c->Mp.map, dop, drho, c->u, c->ux, c->ut, c->stream);
+}
+
 class Driver {
 public:
     Driver(mm_ctx *c, const mm_opts &o, const std::vector<double> &hred, long nfield, const CurveOut &out,
@@ -1392,8 +1418,34 @@ public:
             for (int i = 0; i < n; ++i) busy = busy || r_[i].step == S_NEED_DIR || r_[i].step == S_FIELD_DONE;
             if (!busy) break;
             if (!on.empty()) {
+                // the scalar potential's start: a trial of role 2 (the line
+                // search's second point on the same direction) starts from the
+                // potentials at the accepted state and at the first trial,
+                // interpolated linearly in alpha (the potential is linear in m,
+                // and N(x + alpha d) departs from the line by O(alpha^2));
+                // every other evaluation starts from the last potential
+                std::vector<int> op(n, POT_NONE);
+                std::vector<double> rho(n, 0.0);
+                for (int i : on)
+                    if (r_[i].step == S_TRIAL_C && r_[i].at > 0.0) {
+                        op[i] = POT_INTERP;
+                        rho[i] = r_[i].ac / r_[i].at;
+                    }
+                pot_ops(c_, 0, op, rho);
+                std::vector<int> role_of(n, 0);
+                for (int i : on) role_of[i] = c_->role()[i];
                 eval_round(c_, o_, on, any_trial);
                 for (int i : on) after_eval(i, eval_result(c_, i));
+                // keep the potentials of the accepted state (ux) and of the
+                // last role-1 trial (ut)
+                std::fill(op.begin(), op.end(), POT_NONE);
+                for (int i : on) {
+                    const int from = c_->from()[i];
+                    if (role_of[i] == 0) op[i] = POT_UX_U;
+                    else if (role_of[i] == 1) op[i] = from == 1 ? POT_BOTH_U : POT_UT_U;
+                    else op[i] = from == 2 ? POT_UX_U : (from == 1 ? POT_UX_UT : POT_NONE);
+                }
+                pot_ops(c_, 1, op, rho);
             }
             // ---- 2. copy accepted trials, precondition and direction
             std::vector<int> dir, fin;
