@@ -379,7 +379,8 @@ std::vector<float> to32(const std::vector<double> &v) { return std::vector<float
 // mean row length over kEntriesPerLane. Several entries per lane beat one: a
 // wave then serves more rows, with fewer shuffle steps per row (measured on
 // the 23.6M-row polycrystal's hierarchy: one CG iteration took 4,471 us with
-// one entry per lane, 4,099 with two and 3,829 with four)
+// one entry per lane and at least 4 lanes per row, 3,872 with two entries,
+// 3,522 with four and 3,605 with eight)
 constexpr int kEntriesPerLane = 4;
 int lanes_for(const Csr &a) {
     const double mean = a.n > 0 ? (double)a.nnz() / a.n : 1.0;
