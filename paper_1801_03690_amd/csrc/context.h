@@ -160,7 +160,12 @@ struct mm_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
     mm_opts opts;
+    // iterations of the last scalar-potential solve of each kind, per instance
+    // (kPcgKinds slots: the evaluation's role 0..2, first or later pass of the
+    // defect correction): the next solve of that kind replays as many before
+    // it first asks the device whether it has converged
     std::vector<long> last_pcg;
+    int pcg_pass = 0;  // defect-correction pass of the solve being replayed
     std::vector<double> pcg_bytes64, pcg_bytes32;
     std::vector<Cnt> cnt;
     // kernel timing (mm_profile)

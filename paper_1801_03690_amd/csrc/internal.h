@@ -12,6 +12,7 @@ namespace mmncg {
 
 constexpr int kSlice = 64;      // rows per SELL slice = one wavefront
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
+constexpr int kPcgKinds = 6;    // kinds of scalar-potential solve per instance (3 roles x 2 passes)
 constexpr int kMaxBlocksPerInst = 2048;  // per instance and row space (256 below 2M rows)
 constexpr int kPoissonWaves = 16;       // default waves per block of the scalar-potential kernels
 

@@ -580,7 +580,7 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     HIPCHK(hipMemsetAsync(c->dcd, 0, 8 * (size_t)ni * sizeof(double), c->stream));
     HIPCHK(hipMemsetAsync(c->dsc, 0, (size_t)SC_PER * ni * sizeof(double), c->stream));
     sync(c);
-    c->last_pcg.assign(ni, 16);
+    c->last_pcg.assign((size_t)kPcgKinds * ni, 16);
     c->cnt.assign(ni, Cnt());
     c->pcg_bytes64.assign(ni, 0.0);
     c->pcg_bytes32.assign(ni, 0.0);
@@ -677,11 +677,20 @@ void pull_pcg(mm_ctx *c) {
 // batch of replays and the executed iterations (and their algorithmic bytes)
 // are counted per instance; replays after an instance converged return at once
 // and their time stays in the measurement.
+// slot of last_pcg for instance i's current solve: the role of its evaluation
+// (the accepted state, the line search's first or second trial: their starts
+// differ in quality) and the defect-correction pass (the first pass does
+// nearly all the work)
+long &last_pcg_of(mm_ctx *c, int i) {
+    const int rl = std::min(std::max(c->role()[i], 0), 2);
+    return c->last_pcg[(size_t)kPcgKinds * i + 2 * rl + (c->pcg_pass > 0 ? 1 : 0)];
+}
+
 void pcg_replay(mm_ctx *c, bool fp32, int kind, long maxit, const std::vector<int> &on) {
     hipGraphExec_t ge = use_graphs() ? pcg_graph(c, fp32, kind) : nullptr;
     const long chunk = kind != CG_JACOBI ? kAmgChunk : kPcgChunk;
     long expect = chunk;
-    for (int i : on) expect = std::max(expect, c->last_pcg[i]);
+    for (int i : on) expect = std::max(expect, last_pcg_of(c, i));
     long nrep = (expect + chunk - 1) / chunk;
     long launched = 0;
     std::vector<int> seen(c->ninst, 0);
@@ -736,7 +745,7 @@ std::vector<long> poisson_fp64(mm_ctx *c, double rtol, long maxit, int kind, con
             continue;
         }
         it[i] = c->hpst[i].iters;
-        c->last_pcg[i] = std::max<long>(4, it[i]);
+        last_pcg_of(c, i) = std::max<long>(4, it[i]);
     }
     return it;
 }
@@ -784,14 +793,16 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::ve
         launch_pcg_init32(a, c->stream);
         long cap = 0;
         for (int i : live) cap = std::max(cap, maxit - total[i]);
+        c->pcg_pass = outer;
         pcg_replay(c, true, CG_JACOBI, cap, live);
         for (int i : live) {
             total[i] += c->hpst[i].iters;
-            c->last_pcg[i] = std::max<long>(4, c->hpst[i].iters);
+            last_pcg_of(c, i) = std::max<long>(4, c->hpst[i].iters);
             if (total[i] >= maxit) throw ApiError{MM_NOT_CONVERGED, "scalar-potential CG did not converge"};
         }
         launch_add_correction(a, c->stream);
     }
+    c->pcg_pass = 0;
     if (!live.empty()) throw ApiError{MM_NOT_CONVERGED, "scalar-potential defect correction did not converge"};
     for (int k = 0; k < c->ninst; ++k) pin[4 * k + 1] = 0.0;
     return total;
@@ -800,6 +811,7 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::ve
 // solve for the instances in `on` (act[] uploaded with exactly these set)
 void poisson(mm_ctx *c, double rtol, long maxit, bool fp32, bool amg, const std::vector<int> &on) {
     if (on.empty() || c->rows_p == 0) return;
+    c->pcg_pass = 0;
     if (amg) amg_get(c);  // first use: build the hierarchy (untimed, like the assembly)
     const double t0 = now_s();
     std::vector<long> it = (fp32 && amg)  ? poisson_fp64(c, rtol, maxit, CG_AMG_MIXED, on)
@@ -2062,7 +2074,7 @@ int mm_reset_warm_start(mm_ctx *c) {
         require_ready(c);
         launch_fill(c->rows_p, c->u, 0.0, c->stream);
         sync(c);
-        c->last_pcg.assign(c->ninst, 16);
+        c->last_pcg.assign((size_t)kPcgKinds * c->ninst, 16);
         return MM_OK;
     });
 }
