@@ -131,9 +131,9 @@ struct mm_ctx {
     // the line search's potentials: ux at the accepted state, ut at the last
     // trial of role 1 (the start of a role-2 trial's solve is interpolated
     // between them); per-instance operations staged in pinned memory, two
-    // slots (before and after an evaluation round) of ninst each
+    // slots (before and after an evaluation round) of ninst doubles and ninst
+    // ints each
     double *ux = nullptr, *ut = nullptr;
-    int *hpo = nullptr, *dpo = nullptr;
     double *hpr = nullptr, *dpr = nullptr;
     PcgNode<double> *q64[2] = {};  // CG node records by parity
     PcgNode<float> *q32[2] = {};

@@ -70,8 +70,9 @@ void dfree(mm_ctx *c, void *p) {
 }
 
 void free_host_ctl(mm_ctx *c) {
-    for (void **p : {(void **)&c->hci, (void **)&c->hcd, (void **)&c->hsc, (void **)&c->hpst, (void **)&c->hpo,
-                     (void **)&c->hpr}) {
+    // hci lives in hcd's allocation (one copy uploads both)
+    c->hci = nullptr;
+    for (void **p : {(void **)&c->hcd, (void **)&c->hsc, (void **)&c->hpst, (void **)&c->hpr}) {
         if (*p) (void)hipHostFree(*p);
         *p = nullptr;
     }
@@ -137,8 +138,9 @@ void sync(mm_ctx *c) {
 // follows the previous upload, so an upload never races with the host.
 void upload_ctl(mm_ctx *c) {
     const int n = c->ninst;
-    HIPCHK(hipMemcpyAsync(c->dci, c->hci, 6 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->dcd, c->hcd, 8 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // the doubles and the first six int arrays are contiguous (see setup)
+    HIPCHK(hipMemcpyAsync(c->dcd, c->hcd, 8 * (size_t)n * sizeof(double) + 6 * (size_t)n * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
 }
 void pull_flags(mm_ctx *c) {
     const int n = c->ninst;
@@ -541,17 +543,21 @@ void setup_device(mm_ctx *c, std::vector<Assembly> &as, const std::vector<long> 
     c->pst = dalloc_n<PcgState>(c, ni);
     c->mpart = dalloc_n<double>(c, (size_t)MS_TOTAL * c->Mm.map.nblk);
     c->ppart = dalloc_n<double>(c, (size_t)kPcgSlots * c->Mp.map.nblk);
-    c->dci = dalloc_n<int>(c, 11 * (size_t)ni);
-    c->dcd = dalloc_n<double>(c, 8 * (size_t)ni);
-    c->dpo = dalloc_n<int>(c, 2 * (size_t)ni);
-    c->dpr = dalloc_n<double>(c, 2 * (size_t)ni);
+    // control block: 8 double arrays then 11 int arrays in one allocation, so
+    // that one copy uploads the doubles and the first six int arrays; the
+    // staged potential operations likewise: per slot, ninst doubles then
+    // ninst ints
+    const size_t ctl_bytes = 8 * (size_t)ni * sizeof(double) + 11 * (size_t)ni * sizeof(int);
+    const size_t po_bytes = 2 * (size_t)ni * (sizeof(double) + sizeof(int));
+    c->dcd = (double *)dalloc(c, ctl_bytes);
+    c->dci = (int *)(c->dcd + 8 * (size_t)ni);
+    c->dpr = (double *)dalloc(c, po_bytes);
     c->dsc = dalloc_n<double>(c, (size_t)SC_PER * ni);
-    HIPCHK(hipHostMalloc((void **)&c->hci, 11 * (size_t)ni * sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->hcd, 8 * (size_t)ni * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hcd, ctl_bytes, hipHostMallocDefault));
+    c->hci = (int *)(c->hcd + 8 * (size_t)ni);
     HIPCHK(hipHostMalloc((void **)&c->hsc, (size_t)SC_PER * ni * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&c->hpst, (size_t)ni * sizeof(PcgState), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->hpo, 2 * (size_t)ni * sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&c->hpr, 2 * (size_t)ni * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&c->hpr, po_bytes, hipHostMallocDefault));
     std::memset(c->hci, 0, 11 * (size_t)ni * sizeof(int));
     std::memset(c->hcd, 0, 8 * (size_t)ni * sizeof(double));
     std::memset(c->hsc, 0, (size_t)SC_PER * ni * sizeof(double));
@@ -1378,17 +1384,18 @@ void pot_ops(mm_ctx *c, int slot, const std::vector<int> &op, const std::vector<
     bool any = false;
     for (int i = 0; i < n; ++i) any = any || op[i] != POT_NONE;
     if (!any) return;
-    int *ho = c->hpo + (size_t)slot * n;
-    double *hr = c->hpr + (size_t)slot * n;
+    // slot layout: n doubles (rho), then n ints (op); one copy per call
+    const size_t stride = (size_t)n * (sizeof(double) + sizeof(int));
+    char *hb = (char *)c->hpr + slot * stride, *db = (char *)c->dpr + slot * stride;
+    double *hr = (double *)hb;
+    int *ho = (int *)(hb + (size_t)n * sizeof(double));
     for (int i = 0; i < n; ++i) {
-        ho[i] = op[i];
         hr[i] = rho[i];
+        ho[i] = op[i];
     }
-    int *dop = c->dpo + (size_t)slot * n;
-    double *drho = c->dpr + (size_t)slot * n;
-    HIPCHK(hipMemcpyAsync(dop, ho, n * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(drho, hr, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    launch_pot_op(c->Mp.map, dop, drho, c->u, c->ux, c->ut, c->stream);
+    HIPCHK(hipMemcpyAsync(db, hb, stride, hipMemcpyHostToDevice, c->stream));
+    launch_pot_op(c->Mp.map, (const int *)(db + (size_t)n * sizeof(double)), (const double *)db, c->u, c->ux, c->ut,
+                  c->stream);
 }
 
 class Driver {
