@@ -785,8 +785,10 @@ std::vector<long> poisson_fp32(mm_ctx *c, double rtol, long maxit, const std::ve
             }
             if (rr <= rtol * rtol * bb) continue;
             const double rn = std::sqrt(rr);
-            // relative target of the inner FP32 solve: not beyond what the last correction needs
-            double tol = std::max(1e-5, 0.5 * rtol * std::sqrt(bb) / rn);
+            // relative target of the inner FP32 solve: what the outer FP64 test
+            // needs and no more (the CG stops below it; a pass that ends short
+            // is followed by one more), floored at 1e-5 where FP32 runs out
+            double tol = std::max(1e-5, rtol * std::sqrt(bb) / rn);
             tol = std::min(tol, 1e-1);
             pin[4 * i] = 1.0 / rn;
             pin[4 * i + 1] = tol * tol;
