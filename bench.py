@@ -174,6 +174,12 @@ def main():
                          "auto: the faster one for the workload)")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the Jacobi-preconditioned comparison curve of a multigrid headline")
+    ap.add_argument("--state", default=None,
+                    help="hard_cube/polycrystal: run the curve in pieces, resuming from this .npz when it exists "
+                         "and saving the state to it after every --progress-every fields (a curve longer than one "
+                         "run is timed over several)")
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="with --state: stop after the piece that passes this many seconds of curve time")
     ap.add_argument("--progress-every", type=int, default=0,
                     help="hard_cube/polycrystal: run the curve in chunks of this many fields and report each")
     ap.add_argument("--calibrate", action="store_true",
@@ -415,6 +421,66 @@ def cpu_baseline_film(args, w, fields, jmax, plain):
 # one grain (hard cube) or the polycrystal: whole curves as steps
 # ---------------------------------------------------------------------------
 
+def curve_in_pieces(args, ctx, w, fields, opts, m, m0, info, jmax, shape):
+    """One curve in pieces of --progress-every fields: the state (m, the next
+    field, the curve time so far and the per-field counters) is saved after
+    every piece, and a later run resumes from it. The curve time is the sum
+    of the pieces' wall times; a resumed run starts its first solve from a
+    zero potential (the warm start is not saved)."""
+    import numpy as np
+    import torch
+
+    keys = ("evals", "nli", "li", "mi", "restarts", "fallbacks", "status")
+    if os.path.exists(args.state):
+        st = np.load(args.state)
+        k0, elapsed, runs = int(st["next_field"]), float(st["elapsed"]), int(st["runs"]) + 1
+        m.copy_(torch.from_numpy(st["m"]).to(m.device))
+        rows, E, mav = [list(x) for x in st["stats"]], list(st["E"]), [list(x) for x in st["m_avg"]]
+        log(f"resumed at field {k0} after {elapsed:.1f}s of curve time ({runs - 1} earlier runs)")
+    else:
+        k0, elapsed, runs, rows, E, mav = 0, 0.0, 1, [], [], []
+        m.copy_(m0)
+    ctx.reset_warm_start()
+    pe = max(1, args.progress_every)
+    t_run = 0.0
+    while k0 < len(fields):
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        r = ctx.curve(m, fields[k0:k0 + pe], opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tc
+        elapsed += dt
+        t_run += dt
+        rows += [[s[k] for k in keys] for s in r["stats"]]
+        E += list(r["E"])
+        mav += [list(x) for x in r["m_avg"]]
+        k0 = min(len(fields), k0 + pe)
+        tmp = args.state + ".tmp.npz"
+        np.savez(tmp, m=m.cpu().numpy(), next_field=k0, elapsed=elapsed, runs=runs, stats=np.array(rows),
+                 E=np.array(E), m_avg=np.array(mav))
+        os.replace(tmp, args.state)
+        log(f"fields ..{k0 - 1} done: {dt:.1f}s, curve time so far {elapsed:.1f}s")
+        if args.time_limit and t_run > args.time_limit and k0 < len(fields):
+            log(f"time limit reached: state saved at field {k0}")
+            return
+    tot = {k: int(sum(row[i] for row in rows)) for i, k in enumerate(keys[:-1])}
+    out = {
+        "metric": METRIC, "value": round(elapsed, 2), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * elapsed, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 operators/f64 reductions" if args.precision == "fp32" else "f64",
+        "data": "synthetic (seeded Kuhn mesh, tilted +z start)",
+        "config": {"workload": f"{args.workload}: whole curve of {len(fields)} fields, jmax {jmax}, tol 1e-6, "
+                               f"timed in {runs} runs resumed from the saved state",
+                   "precision": args.precision, "poisson_preconditioner": args.poisson_prec,
+                   "n_mag": info["n_mag"], "n_pot": info["n_pot"], "nnz_K": info["nnz_K"],
+                   "pcg_waves_per_block": shape[0]},
+        "counters": dict(tot, worst_status=int(max(row[-1] for row in rows))),
+        "per_field": {"nli": [int(row[1]) for row in rows], "E": [float(x) for x in E],
+                      "m_avg_z": [float(x[2]) for x in mav]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_curve(args):
     import numpy as np
     import torch
@@ -446,6 +512,9 @@ def bench_curve(args):
         nw, spw = tune(ctx, binding, args)
         shape = (nw, spw.tolist())
         log(f"tuned shape: {nw} waves per block, slices per wave {spw.tolist()}")
+
+    if args.state:
+        return curve_in_pieces(args, ctx, w, fields, opts, m, m0, info, jmax, shape)
 
     def one_curve(o):
         m.copy_(m0)
