@@ -244,8 +244,8 @@ def bench_film(args):
     log(f"setup {time.time() - t0:.1f}s n_mag={info['n_mag']} n_pot={info['n_pot']} nnz_K={info['nnz_K']}")
     graph = binding.Graph(ctx)
     net = learn.load_net(args.net, ctx)
-    o_l = binding.default_opts(jmax=jmax, precision=binding.MM_FP32_BULK, poisson_prec=pprec)
-    o_p = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec)
+    o_l = binding.default_opts(jmax=jmax, precision=binding.MM_FP32_BULK, poisson_prec=pprec, theta_max=w.theta_max)
+    o_p = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec, theta_max=w.theta_max)
     m0 = torch.tensor(w.m0, dtype=torch.float64, device="cuda")
     m = torch.empty_like(m0)
     shapes = {}
@@ -314,7 +314,8 @@ def bench_film(args):
         "dtype": "f32 operators/f64 reductions (learned component bf16 MFMA)",
         "data": "synthetic (seeded Kuhn mesh, tilted +x start)",
         "config": {"workload": f"soft film 1000x1000x10 nm, 200x200x2 cells x6 tets + 3x air box, {nf} fields "
-                               f"+50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, tol 1e-6; learned warm "
+                               f"+50..{1e3 * fields[-1][0]:.0f} mT along x, jmax {jmax}, rotation cap "
+                               f"{w.theta_max} rad, tol 1e-6; learned warm "
                                f"start{' + Jacobi scaling' if args.learn_mode == 'start+scale' else ''}, FP32 bulk; "
                                f"the curve in {min(args.steps, nf)} chunks",
                    "network": os.path.basename(args.net),
@@ -391,7 +392,7 @@ def cpu_baseline_film(args, w, fields, jmax, plain):
     tot = dict(evals=0, mi=0, li=0)
     ta = time.perf_counter()
     for k in range(ns):
-        m, E, st, rc = o.minimize(m, fields[k], jmax=jmax, max_nli=args.cpu_nli)
+        m, E, st, rc = o.minimize(m, fields[k], jmax=jmax, max_nli=args.cpu_nli, theta_max=w.theta_max)
         for q in tot:
             tot[q] += st[q]
     t_sample = time.perf_counter() - ta

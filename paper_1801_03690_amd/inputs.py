@@ -202,6 +202,7 @@ class Workload:
     fields: np.ndarray      # (n_fields, 3) Tesla
     jmax: int
     meta: dict = field(default_factory=dict)
+    theta_max: float = 0.2  # the line search's rotation cap (rad)
 
 
 def soft_cube(n=10, h=4.0, seed=0, n_fields=21):
@@ -285,16 +286,19 @@ def batch_cubes(n_inst=64, seed=2, nmin=8, nmax=24, h=4.0, step_T=0.1, stop_T=-8
     return out
 
 
+FILM_THETA_MAX = 0.5  # the film's rotation cap: the fastest of 0.2, 0.5 and 1.0 on the whole curve
+
+
 def film(nx=200, ny=200, nz=2, h=5.0, seed=3, step_T=0.001, start_T=0.05):
     """Soft thin film, field along x from +start_T to -start_T. j_max = 10: the
     fastest of 1, 10, 20 on the whole curve (and of 0, 1, 4, 10 on its first
-    10 fields)."""
+    10 fields). Rotation cap FILM_THETA_MAX."""
     mesh = make_box_magnet((nx, ny, nz), h, axis=(1.0, 0.0, 0.0), **SOFT)
     rng = np.random.Generator(np.random.PCG64(seed))
     m0 = tilted_state(mesh.magnet_nodes().size, (1.0, 0.0, 0.0), 0.01, rng)
     fields = field_schedule(start_T, -start_T, step_T, (1.0, 0.0, 0.0))
     return Workload(f"film_{nx}x{ny}x{nz}", mesh, m0, fields, jmax=10,
-                    meta=dict(seed=seed))
+                    meta=dict(seed=seed), theta_max=FILM_THETA_MAX)
 
 
 def training_film(seed, h=5.0, lo=600.0, hi=1400.0, nz=2):

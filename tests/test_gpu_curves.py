@@ -58,6 +58,28 @@ def soft_oracle(oracle_mod):
     return w, ro, scale
 
 
+def test_soft_cube_full_curve_matches_oracle_at_the_film_rotation_cap(B, oracle_mod):
+    """The same bar with the line search's rotation cap of the film's workload
+    (0.5 rad instead of 0.2) on both sides."""
+    w = inputs.soft_cube()
+    th = inputs.FILM_THETA_MAX
+    o = oracle_mod.Oracle(w.mesh)
+    ro = o.curve(w.m0, w.fields, jmax=w.jmax, keep_hist=True, theta_max=th)
+    assert ro["rc"] == 0
+    scale = np.array([max(abs(ro["E"][k]), float(np.abs(o.eval_T(ro["hist"][k], w.fields[k])["E"][:4]).sum()))
+                      for k in range(len(w.fields))])
+    ctx = B.Context(0)
+    ctx.upload(w.mesh)
+    rg = ctx.curve(w.m0, w.fields, jmax=w.jmax, theta_max=th, keep_hist=True)
+    ctx.close()
+    assert rg["rc"] == 0
+    dE = np.abs(rg["E"] - ro["E"]) / scale
+    dm = np.abs(rg["hist"] - ro["hist"]).max(axis=(1, 2))
+    print(f"soft cube (rotation cap {th}): max rel dE {dE.max():.2e}, max |dm| {dm.max():.2e}")
+    assert dE.max() <= 1e-8, dE
+    assert dm.max() <= 1e-5, dm
+
+
 @pytest.mark.parametrize("pprec", ["jacobi", "amg"])
 def test_soft_cube_full_curve_matches_oracle(B, soft_oracle, pprec):
     w, ro, scale = soft_oracle
