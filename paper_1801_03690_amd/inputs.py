@@ -286,7 +286,7 @@ def batch_cubes(n_inst=64, seed=2, nmin=8, nmax=24, h=4.0, step_T=0.1, stop_T=-8
     return out
 
 
-FILM_THETA_MAX = 0.5  # the film's rotation cap: the fastest of 0.2, 0.5 and 1.0 on the whole curve
+FILM_THETA_MAX = 0.5  # the film's rotation cap: the fastest of 0.2, 0.35, 0.5, 0.7 and 1.0 on the whole curve
 
 
 def film(nx=200, ny=200, nz=2, h=5.0, seed=3, step_T=0.001, start_T=0.05):
