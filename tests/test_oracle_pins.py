@@ -573,6 +573,27 @@ def test_beta_variants_reach_the_same_minimum(oracle_mod):
     assert len({res[k][1] for k in range(4)}) >= 2
 
 
+def test_rotation_caps_reach_the_same_minimum(oracle_mod):
+    """The line search's rotation cap (0.2 rad by default, 0.5 for the film's
+    workload, 1.0) bounds each step, not the minimizer: every cap ends at the
+    same energy and state; the cap changes the path (iteration counts)."""
+    mesh = inputs.small_box((4, 4, 3), 4.0, **inputs.SOFT)
+    o = oracle_mod.Oracle(mesh)
+    # a soft magnet along x turned by a 1 T field along z: the first steps
+    # rotate by more than the smallest cap allows
+    m0 = inputs.tilted_state(o.nm, (1.0, 0.0, 0.0), 0.2, np.random.Generator(np.random.PCG64(7)))
+    res = {}
+    for th in (0.2, inputs.FILM_THETA_MAX, 1.0):
+        m, E, st, rc = o.minimize(m0, [0.0, 0.0, 1.0], jmax=4, theta_max=th, tol_torque=1e-8)
+        assert rc == 0, th
+        assert np.abs(np.linalg.norm(m, axis=1) - 1.0).max() < 1e-12
+        res[th] = (E[4], st["nli"], m)
+    for th in (inputs.FILM_THETA_MAX, 1.0):
+        assert abs(res[th][0] - res[0.2][0]) <= 1e-11 * abs(res[0.2][0]), th
+        assert np.abs(res[th][2] - res[0.2][2]).max() < 1e-5, th
+    assert len({r[1] for r in res.values()}) >= 2
+
+
 def test_preconditioner_forms_reach_the_same_minimum(oracle_mod):
     """The candidates of eq. (precond) (all terms, or the projected local part
     only) in place of the paper's choice: the preconditioner changes the path,
