@@ -178,6 +178,10 @@ def main():
                     help="hard_cube/polycrystal: run the curve in pieces, resuming from this .npz when it exists "
                          "and saving the state to it after every --progress-every fields (a curve longer than one "
                          "run is timed over several)")
+    ap.add_argument("--theta-max", type=float, default=None,
+                    help="hard_cube/polycrystal: the line search's rotation cap (default: the library's, 0.2 rad)")
+    ap.add_argument("--max-nli", type=int, default=None,
+                    help="hard_cube/polycrystal: nonlinear iterations per field before a field ends unconverged")
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="with --state: stop after the piece that passes this many seconds of curve time")
     ap.add_argument("--progress-every", type=int, default=0,
@@ -502,7 +506,8 @@ def bench_curve(args):
     m = torch.empty_like(m0)
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     jmax = w.jmax if args.jmax is None else args.jmax
-    opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec)
+    extra = {k: v for k, v in (("theta_max", args.theta_max), ("max_nli", args.max_nli)) if v is not None}
+    opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec, **extra)
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
         amg = ctx.amg_info()
@@ -576,7 +581,7 @@ def bench_curve(args):
     }
 
     if not args.no_plain and prec != binding.MM_FP64:
-        o64 = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec)
+        o64 = binding.default_opts(jmax=jmax, precision=binding.MM_FP64, poisson_prec=pprec, **extra)
         ctx.set_opts(o64)
         if not args.no_tune:
             tune(ctx, binding, args)
@@ -594,7 +599,7 @@ def bench_curve(args):
 
     if args.poisson_prec == "amg" and not args.no_jacobi:
         # the same curve with the Jacobi-preconditioned CG (one kernel per iteration)
-        oj = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=binding.MM_PREC_JACOBI)
+        oj = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=binding.MM_PREC_JACOBI, **extra)
         ctx.set_opts(oj)
         if not args.no_tune:
             tune(ctx, binding, args)
