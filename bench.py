@@ -364,6 +364,7 @@ def bench_film(args):
         a2 = argparse.Namespace(**vars(args))
         a2.workload, a2.poisson_prec, a2.fields, a2.jmax, a2.steps, a2.warmup = "hard_cube", "amg", 0, None, 1, 1
         a2.no_cpu, a2.no_jacobi, a2.progress_every, a2.precision = True, True, 0, "fp32"
+        a2.state, a2.theta_max, a2.max_nli = None, None, None
         hc = bench_curve(a2)
         out["hard_cube"] = {k: hc[k] for k in ("value", "config", "counters", "roofline", "field_kernels")}
         if "plain_fp64" in hc:
