@@ -74,3 +74,43 @@ def test_curve_in_pieces_resumes_where_it_stopped(tmp_path, monkeypatch):
     out = json.loads(capsys_out[-1])
     assert out["counters"]["nli"] == 10 and out["counters"]["mi"] == 100
     assert "2 runs" in out["config"]["workload"]
+
+
+def test_counter_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
+    """roofline.traffic comes from a committed counter summary only while the
+    kernel source still hashes to the one profiled; a changed source, another
+    precision or a missing summary gives null."""
+    import hashlib
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    src = tmp_path / "kernel.hip"
+    src.write_text("// a kernel\n")
+    h = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+    summ = tmp_path / "traffic.txt"
+    summ.write_text(f"# counters\nsource_sha256_prefix {h}\nprecision fp32\ntraffic_bytes_per_iteration 1234.5\n")
+    monkeypatch.setitem(bench.TRAFFIC, ("film", "jacobi"), (str(summ), str(src)))
+    assert bench.measured_traffic("film", "fp32", "jacobi") == 1234.5
+    assert bench.measured_traffic("film", "fp64", "jacobi") is None
+    src.write_text("// a kernel, changed\n")
+    assert bench.measured_traffic("film", "fp32", "jacobi") is None
+    monkeypatch.setitem(bench.TRAFFIC, ("film", "jacobi"), (str(tmp_path / "missing.txt"), str(src)))
+    assert bench.measured_traffic("film", "fp32", "jacobi") is None
+    assert bench.measured_traffic("batch64", "fp32", "jacobi") is None
+
+
+def test_headline_traffic_summary_matches_the_current_kernel():
+    """Every committed counter summary names the sha256 prefix of the kernel
+    source it was taken on, and the bench line reports its traffic only while
+    they agree. The headline's (the film's Jacobi CG in FP32 bulk) must be
+    current; the others may be older and then give null."""
+    import hashlib
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    for key, (path, src) in bench.TRAFFIC.items():
+        kv = dict(line.split(None, 1) for line in open(path) if line.strip() and not line.startswith("#"))
+        assert len(kv["source_sha256_prefix"].strip()) == 16 and float(kv["traffic_bytes_per_iteration"]) > 0, key
+    assert bench.measured_traffic("film", "fp32", "jacobi") is not None
