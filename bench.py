@@ -5,8 +5,9 @@ Default workload: the soft thin film, 1000 x 1000 x 10 nm on 200 x 200 x 2
 cells of 5 nm x 6 tets (121,203 magnet nodes) in a 3x air box for the scalar
 potential (1.79M free potential nodes), Ms = 8e5 A/m, A = 13 pJ/m, K1 = 0,
 field along x from +50 mT to -50 mT in 1 mT steps (101 values), j_max 10,
-every minimization run to max |m x h_eff| < 1e-6 (reduced units). Two forms
-reach the same torque tolerance:
+line-search rotation cap 0.5 rad, every minimization run to
+max |m x h_eff| < 1e-6 (reduced units). Two forms reach the same torque
+tolerance:
 
   * learned + FP32 (the value): the network's warm start at every field after
     the first (with --learn-mode start+scale also its Jacobi scaling),
@@ -33,7 +34,7 @@ the CPU FP64 oracle timed on a bounded sample of the same workload, and the
 20^3 hard cube's curve (FP32 bulk, multigrid CG) as an extra figure.
 
 Other workloads (--workload): hard_cube, polycrystal (bound it with
---fields), batch64.
+--fields, or time it in pieces with --state), batch64.
 """
 from __future__ import annotations
 
