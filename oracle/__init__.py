@@ -8,6 +8,7 @@ does. The oracle is a plain C file (`oracle.c`) built with gcc into
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -37,7 +38,8 @@ class Opts(C.Structure):
     _fields_ = [("jmax", C.c_int), ("tol_torque", C.c_double), ("stop_mode", C.c_int),
                 ("tau_F", C.c_double), ("theta_max", C.c_double), ("theta_init", C.c_double),
                 ("c1", C.c_double), ("c2", C.c_double), ("max_nli", C.c_long), ("terms", C.c_int),
-                ("ls_max_halvings", C.c_int), ("beta", C.c_int), ("pform", C.c_int)]
+                ("ls_max_halvings", C.c_int), ("beta", C.c_int), ("pform", C.c_int),
+                ("theta_adapt", C.c_int), ("theta_hi", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -52,7 +54,8 @@ class Stats(C.Structure):
 
 def default_opts(jmax=4, **kw):
     o = Opts(jmax=jmax, tol_torque=1e-6, stop_mode=0, tau_F=1e-10, theta_max=0.2, theta_init=0.01,
-             c1=1e-4, c2=0.1, max_nli=20000, terms=T_ALL, ls_max_halvings=20, beta=0, pform=0)
+             c1=1e-4, c2=0.1, max_nli=20000, terms=T_ALL, ls_max_halvings=20, beta=0, pform=0,
+             theta_adapt=0, theta_hi=math.pi / 2)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -610,6 +610,8 @@ typedef struct {
     int ls_max_halvings;
     int beta;           /* 0: beta*ZA (Alg. 4), 1: beta*FR, 2: beta*PRP, 3: beta*HS (Sec. 2.1) */
     int pform;          /* preconditioner form of or_apply_P (0: the paper's) */
+    int theta_adapt;    /* 1: the rotation cap follows the accepted steps (reading S6's cap) */
+    double theta_hi;    /* its upper bound (rad) */
 } or_opts;
 
 typedef struct {
@@ -697,12 +699,13 @@ static int cubic_min(double at, double dFt, double dp0, double dpt, double *ac) 
 
 /*
  * Line search on phi(alpha) = F(N(x + alpha d)) (reading S6, "LS-2P").
- * alpha_max caps the largest nodal rotation at theta_max. On success st1
- * holds the accepted state and the function returns 1; *alpha the step.
+ * alpha_max caps the largest nodal rotation at theta (theta_max, or the
+ * adapted cap). On success st1 holds the accepted state and the function
+ * returns 1; *alpha the step and *amax_out the alpha_max it used.
  */
-static int line_search(or_ctx *c, const or_opts *o, const double *h, const or_state *s0,
+static int line_search(or_ctx *c, const or_opts *o, double theta, const double *h, const or_state *s0,
                        const double *d, double dp0, double a0, or_state *st1, or_state *tmp,
-                       double *alpha, double *dF_acc, or_stats *stats) {
+                       double *alpha, double *dF_acc, or_stats *stats, double *amax_out) {
     long nm = c->nm;
     double dmax = 0.0;
     for (long a = 0; a < nm; a++) {
@@ -710,7 +713,8 @@ static int line_search(or_ctx *c, const or_opts *o, const double *h, const or_st
         if (n > dmax) dmax = n;
     }
     if (!(dmax > 0.0)) return 0;
-    double amax = o->theta_max / dmax;
+    double amax = theta / dmax;
+    *amax_out = amax;
     double at = a0 < amax ? a0 : amax;
     double dFt, dpt;
     ls_eval(c, s0, d, at, h, o->terms, st1, &dFt, &dpt, stats);
@@ -741,6 +745,17 @@ static int line_search(or_ctx *c, const or_opts *o, const double *h, const or_st
         if (dFa <= o->c1 * a * dp0) { *alpha = a; *dF_acc = dFa; return 1; }
     }
     return 0;
+}
+
+/*
+ * The adapted rotation cap (reading S6): a step the cap stopped doubles it,
+ * up to theta_hi; a step shorter than a quarter of the cap halves it, down
+ * to theta_max; any other step leaves it. Each field starts at theta_max.
+ */
+static double adapt_cap(const or_opts *o, double theta, double alpha, double amax) {
+    if (alpha >= amax * (1.0 - 1e-12)) return 2.0 * theta < o->theta_hi ? 2.0 * theta : o->theta_hi;
+    if (alpha < 0.25 * amax) return 0.5 * theta > o->theta_max ? 0.5 * theta : o->theta_max;
+    return theta;
 }
 
 int or_cubic_min_pub(double at, double dFt, double dp0, double dpt, double *ac) {
@@ -867,6 +882,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
     }
     int first = 1;
     double a_prev = 0.0, dp_prev = 0.0;
+    double theta = o->theta_max, amax_used = 0.0;
     for (long it = 0; it < o->max_nli; it++) {
         /* after the safeguard d = -g gives dp0 = -|g|^2: zero only at a zero
            projected gradient; anything else that is not negative is NaN */
@@ -876,7 +892,7 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
         if (first) a0 = o->jmax > 0 ? 1.0 : o->theta_init / dmax;
         else a0 = a_prev * dp_prev / dp0;
         double alpha, dFacc;
-        int ok = line_search(c, o, h, &s0, d, dp0, a0, &s1, &tmp, &alpha, &dFacc, stats);
+        int ok = line_search(c, o, theta, h, &s0, d, dp0, a0, &s1, &tmp, &alpha, &dFacc, stats, &amax_used);
         if (!ok) {
             /* restart along the steepest descent direction */
             stats->restarts++;
@@ -885,9 +901,11 @@ int or_minimize(or_ctx *c, double *m, const double *h, const or_opts *o, or_stat
             gy_prev = -dp0;
             dmax = max_norm3(d, nm);
             if (!(dp0 < 0.0) || !(dmax > 0.0)) { status = 2; break; }
-            ok = line_search(c, o, h, &s0, d, dp0, o->theta_init / dmax, &s1, &tmp, &alpha, &dFacc, stats);
+            ok = line_search(c, o, theta, h, &s0, d, dp0, o->theta_init / dmax, &s1, &tmp, &alpha, &dFacc, stats,
+                             &amax_used);
             if (!ok) { stats->ls_fail++; status = 2; break; }
         }
+        if (o->theta_adapt) theta = adapt_cap(o, theta, alpha, amax_used);
         if (!isfinite(s1.E[4]) || !isfinite(s1.tmax)) { status = 3; break; }
         double rise = s1.E[4] - s0.E[4];
         double terr = fabs(rise - dFacc);
