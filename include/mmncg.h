@@ -111,6 +111,12 @@ typedef struct {
                               MM_PFORM_FULL (all four terms; not symmetric), or
                               MM_PFORM_LOCAL (the projected local part
                               C v - (m.Cv) m only) */
+    int theta_adapt;       /* 1: the rotation cap follows the accepted steps: a
+                              step the cap stopped doubles it (up to theta_hi), a
+                              step below a quarter of it halves it (down to
+                              theta_max); each field starts at theta_max.
+                              0 (the default): the cap stays theta_max */
+    double theta_hi;       /* upper bound of the adapted cap (rad), >= theta_max */
 } mm_opts;
 
 typedef struct {

@@ -47,7 +47,7 @@ class Opts(C.Structure):
                 ("theta_max", C.c_double), ("theta_init", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
                 ("poisson_rtol", C.c_double), ("max_nli", C.c_long), ("precision", C.c_int), ("terms", C.c_int),
                 ("ls_max_halvings", C.c_int), ("poisson_maxit", C.c_long), ("poisson_prec", C.c_int),
-                ("beta", C.c_int), ("prec_form", C.c_int)]
+                ("beta", C.c_int), ("prec_form", C.c_int), ("theta_adapt", C.c_int), ("theta_hi", C.c_double)]
 
 
 class Stats(C.Structure):

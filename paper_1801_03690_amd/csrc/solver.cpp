@@ -1347,6 +1347,7 @@ struct Run {
     bool restarting = false;  // the next direction is the steepest-descent restart
     bool first = true;
     double dp0 = 0, dmax = 0, a_prev = 0, dp_prev = 0;
+    double theta = 0;        // the line search's rotation cap of this field
     // line search
     bool restart_ls = false, arm_t = false;
     double amax = 0, a0 = 0, at = 0, ac = 0, a = 0, dFt = 0;
@@ -1546,6 +1547,7 @@ private:
         R.first = true;
         R.restarting = false;
         R.a_prev = R.dp_prev = 0.0;
+        R.theta = o_.theta_max;
         R.nli = R.restarts = R.fallbacks = 0;
         R.c0 = c_->cnt[i];
         R.t0 = now_s();
@@ -1608,7 +1610,8 @@ private:
         }
     }
 
-    // line search on phi(alpha) = F(N(x + alpha d)): capped rotation,
+    // line search on phi(alpha) = F(N(x + alpha d)): capped rotation (the cap
+    // theta_max, or with theta_adapt the cap that follows the accepted steps),
     // sufficient decrease on the exact energy difference, one cubic
     // interpolation, then halving
     void start_ls(int i, double a0, bool restart) {
@@ -1619,7 +1622,7 @@ private:
             return;
         }
         R.a0 = a0;
-        R.amax = o_.theta_max / R.dmax;
+        R.amax = R.theta / R.dmax;
         R.at = std::min(a0, R.amax);
         R.step = S_TRIAL_T;
     }
@@ -1697,6 +1700,12 @@ private:
                          "tmax %.4e E %.12e\n",
                          i, R.field, R.nli, alpha, R.amax, R.a0, R.dp0, v.dF, v.E - s0.E, v.tmax, v.E);
         R.cur = v;
+        if (o_.theta_adapt) {
+            // a step the cap stopped doubles it, a step below a quarter of it
+            // halves it, within [theta_max, theta_hi]
+            if (alpha >= R.amax * (1.0 - 1e-12)) R.theta = std::min(2.0 * R.theta, o_.theta_hi);
+            else if (alpha < 0.25 * R.amax) R.theta = std::max(0.5 * R.theta, o_.theta_max);
+        }
         if (conv) return finish(i, MM_OK);
         R.a_prev = alpha;
         R.dp_prev = R.dp0;
@@ -1796,6 +1805,8 @@ bool opts_valid(const mm_opts &o, std::string &why) {
     if (o.jmax < 0) why = "jmax < 0";
     else if (!(o.tol_torque > 0)) why = "tol_torque <= 0";
     else if (!(o.theta_max > 0) || !(o.theta_init > 0)) why = "theta_max/theta_init <= 0";
+    else if (o.theta_adapt != 0 && o.theta_adapt != 1) why = "theta_adapt not 0 or 1";
+    else if (o.theta_adapt && !(o.theta_hi >= o.theta_max)) why = "theta_hi < theta_max";
     else if (!(o.c1 > 0 && o.c1 < 1) || !(o.c2 > o.c1 && o.c2 < 1)) why = "need 0 < c1 < c2 < 1";
     else if (!(o.poisson_rtol > 0)) why = "poisson_rtol <= 0";
     else if (o.max_nli < 1) why = "max_nli < 1";
@@ -1889,6 +1900,8 @@ int mm_opts_default(mm_opts *o) {
     o->poisson_prec = MM_PREC_JACOBI;
     o->beta = MM_BETA_ZA;
     o->prec_form = MM_PFORM_PAPER;
+    o->theta_adapt = 0;
+    o->theta_hi = 1.5707963267948966;
     return MM_OK;
 }
 

@@ -29,6 +29,8 @@ def test_opts_defaults_without_gpu():
     assert o.theta_max == 0.2 and o.c1 == 1e-4 and o.c2 == 0.1 and o.max_nli == 20000
     assert o.poisson_prec == binding.MM_PREC_JACOBI and o.beta == binding.MM_BETA_ZA
     assert o.prec_form == binding.MM_PFORM_PAPER
+    # the last fields: their values also check that the ctypes layout matches the C struct
+    assert o.theta_adapt == 0 and o.theta_hi == 1.5707963267948966
 
 
 def test_create_without_gpu_fails_cleanly():
