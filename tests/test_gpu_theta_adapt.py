@@ -1,9 +1,8 @@
 """The adapted rotation cap (mm_opts.theta_adapt) on the GPU against the
-oracle's, through the C ABI. Not collected (the file name does not start
-with test_) until it has run on a GPU: the soft cube's whole curve and a full
-reversal of a soft magnet, each to the bar of the FP64 curve tests (energy
-within 1e-8 of its scale, every nodal m within 1e-5), and fewer nonlinear
-iterations than the fixed cap on the reversal."""
+oracle's, through the C ABI: the soft cube's whole curve and a full reversal
+of a soft magnet, each to the bar of the FP64 curve tests (energy within 1e-8
+of its scale, every nodal m within 1e-5), and fewer nonlinear iterations than
+the fixed cap on the reversal."""
 import numpy as np
 import pytest
 
