@@ -181,6 +181,10 @@ def main():
                          "run is timed over several)")
     ap.add_argument("--theta-max", type=float, default=None,
                     help="hard_cube/polycrystal: the line search's rotation cap (default: the library's, 0.2 rad)")
+    ap.add_argument("--theta-adapt", type=int, choices=[0, 1], default=None,
+                    help="hard_cube/polycrystal: 1 = the rotation cap follows the accepted steps (mm_opts.theta_adapt)")
+    ap.add_argument("--theta-hi", type=float, default=None,
+                    help="hard_cube/polycrystal: upper bound of the adapted rotation cap (rad)")
     ap.add_argument("--max-nli", type=int, default=None,
                     help="hard_cube/polycrystal: nonlinear iterations per field before a field ends unconverged")
     ap.add_argument("--time-limit", type=float, default=0.0,
@@ -365,7 +369,7 @@ def bench_film(args):
         a2 = argparse.Namespace(**vars(args))
         a2.workload, a2.poisson_prec, a2.fields, a2.jmax, a2.steps, a2.warmup = "hard_cube", "amg", 0, None, 1, 1
         a2.no_cpu, a2.no_jacobi, a2.progress_every, a2.precision = True, True, 0, "fp32"
-        a2.state, a2.theta_max, a2.max_nli = None, None, None
+        a2.state, a2.theta_max, a2.max_nli, a2.theta_adapt, a2.theta_hi = None, None, None, None, None
         hc = bench_curve(a2)
         out["hard_cube"] = {k: hc[k] for k in ("value", "config", "counters", "roofline", "field_kernels")}
         if "plain_fp64" in hc:
@@ -508,7 +512,8 @@ def bench_curve(args):
     m = torch.empty_like(m0)
     pprec = binding.MM_PREC_AMG if args.poisson_prec == "amg" else binding.MM_PREC_JACOBI
     jmax = w.jmax if args.jmax is None else args.jmax
-    extra = {k: v for k, v in (("theta_max", args.theta_max), ("max_nli", args.max_nli)) if v is not None}
+    extra = {k: v for k, v in (("theta_max", args.theta_max), ("max_nli", args.max_nli),
+                               ("theta_adapt", args.theta_adapt), ("theta_hi", args.theta_hi)) if v is not None}
     opts = binding.default_opts(jmax=jmax, precision=prec, poisson_prec=pprec, **extra)
     ctx.set_opts(opts)
     if pprec == binding.MM_PREC_AMG:
